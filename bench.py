@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Benchmark of the hierarchical kernel solver on one MI355X.
+
+Workload (the paper's N log N scaling shape, m = 512, s = 256, on a synthetic
+Gaussian mixture in place of its datasets): N = 1,048,576 points in 16-D, 32
+clusters with centres ~ U[-10,10]^16 and sigma ~ U[0.5,2]; h = 2, lambda = 0.01,
+64 right-hand sides ~ N(0,1).
+
+One step = skeletonize (sampled ID, FP64 QRCP) + factorize (mixed precision:
+FP32 kernel blocks and level products, FP64 LUs) + solve of the 64 right-hand
+sides with iterative refinement against the FP64 operator.  Inputs are resident
+in HBM before the timed region; the tree is built once, outside it.
+
+Printed: one JSON line.  value = factor time (skeletonize + factorize) of the
+mixed path in seconds; solves/s, the plain FP64 path (timed once after the
+steps), the mixed-vs-FP64 relative error, the roofline of the dominant kernel
+(per-kernel HIP-event timings) and the oracle CPU baseline are included.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "N=1M d=16 s=256: factor time (s), solves/s; mixed vs FP64 at rel err≤1e-6"
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_counts(N, d, m, s, D, nsamp, nrhs):
+    """Per-kernel algorithmic flops and bytes of one step (FP64 element = 8 B)."""
+    n_c = lambda l: N / 2 ** (l + 1)  # noqa: E731  child size at level l
+    # QRCP of nsamp x 2s (or m) blocks, s steps, one read + one write of the
+    # trailing block per step (norms fused into the update)
+    qr_bytes = qr_flops = 0.0
+    for lvl in range(1, D + 1):
+        cols = m if lvl == D else 2 * s
+        rows = min(nsamp, N - N / 2 ** lvl)
+        nodes = 2 ** lvl
+        for j in range(min(s, cols)):
+            area = (rows - j) * (cols - j - 1)
+            qr_bytes += nodes * 16.0 * area
+            qr_flops += nodes * 6.0 * area
+    z_flops = sum(2.0 * s * s * N for _ in range(D))                     # Z blocks, eq. (8)
+    tele_flops = sum(2.0 * s * s * N for l in range(1, D))               # telescoping, eq. (10)
+    return dict(qr_bytes=qr_bytes, qr_flops=qr_flops, z_flops=z_flops, tele_flops=tele_flops)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--N", type=int, default=1 << 20)
+    ap.add_argument("--nrhs", type=int, default=64)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-sample", type=int, default=8192, help="points in the oracle's sample problem")
+    ap.add_argument("--max-refine", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1701_02324_amd as ak
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    c = synth.config(3, N=args.N, nrhs=args.nrhs)
+    N, d = c["X"].shape
+    m, s, h, lam, nsamp = c["m"], c["s"], c["h"], c["lam"], c["nsamp"]
+    log(f"[bench] workload N={N} d={d} m={m} s={s} h={h} lambda={lam} nrhs={args.nrhs}")
+    X = torch.as_tensor(c["X"], device=dev)
+    B = torch.as_tensor(c["B"], device=dev)
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    tree = ak.Tree(X, m, s, h, n_samples=nsamp, seed=c["seed"])
+    torch.cuda.synchronize()
+    t_tree = time.perf_counter() - t0
+    log(f"[bench] tree built in {t_tree:.3f} s (depth {tree.D})")
+
+    def step(prec, keep=False):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        tree.skeletonize()
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        f = tree.factorize(lam, prec)
+        if prec == ak.ASKIT_MIXED:
+            f.set_refinement(args.max_refine, 1e-10)
+        torch.cuda.synchronize()
+        cc = time.perf_counter()
+        x = f.solve(B)
+        torch.cuda.synchronize()
+        e = time.perf_counter()
+        info = f.info() if prec == ak.ASKIT_MIXED else None
+        out = dict(skel=b - a, factor=cc - b, solve=e - cc, info=info)
+        if keep:
+            return out, f, x
+        f.close()
+        del x
+        return out, None, None
+
+    for w in range(args.warmup):
+        r, _, _ = step(ak.ASKIT_MIXED)
+        log(f"[bench] warmup {w}: skel {r['skel']:.3f} s factor {r['factor']:.3f} s solve {r['solve']:.3f} s")
+
+    ak.askit_profile_enable(True)
+    torch.cuda.synchronize()
+    T0 = time.perf_counter()
+    runs = []
+    fmx = xmx = None
+    for k in range(args.steps):
+        r, f, x = step(ak.ASKIT_MIXED, keep=(k == args.steps - 1))
+        runs.append(r)
+        if f is not None:
+            fmx, xmx = f, x
+        log(f"[bench] step {k}: skel {r['skel']:.3f} s factor {r['factor']:.3f} s solve {r['solve']:.3f} s "
+            f"refine {r['info']}")
+    torch.cuda.synchronize()
+    T1 = time.perf_counter()
+    prof = ak.askit_profile_report()
+    ak.askit_profile_enable(False)
+    ms_step = 1e3 * (T1 - T0) / args.steps
+    t_skel = float(np.mean([r["skel"] for r in runs]))
+    t_fac = float(np.mean([r["factor"] for r in runs]))
+    t_sol = float(np.mean([r["solve"] for r in runs]))
+    info = runs[-1]["info"]
+
+    res = {}
+    if not args.no_fp64:
+        a = time.perf_counter()
+        f64 = tree.factorize(lam, ak.ASKIT_FP64)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        x64 = f64.solve(B)
+        torch.cuda.synchronize()
+        e = time.perf_counter()
+        err = float(((xmx - x64).norm(dim=0) / x64.norm(dim=0)).max())
+        r64 = B - f64.matvec(x64)
+        eps64 = float((r64.norm(dim=0) / B.norm(dim=0)).max())
+        res = dict(fp64_factor_s=t_skel + (b - a), fp64_factorize_only_s=b - a, fp64_solve_s=e - b,
+                   fp64_solves_per_s=args.nrhs / (e - b), mixed_vs_fp64_rel_err=err, fp64_residual=eps64,
+                   speedup_factor_mixed_over_fp64=(t_skel + (b - a)) / (t_skel + t_fac),
+                   speedup_factorize_only=(b - a) / t_fac)
+        log(f"[bench] fp64: factorize {b - a:.3f} s solve {e - b:.3f} s; mixed vs fp64 {err:.2e}; "
+            f"fp64 residual {eps64:.2e}")
+        f64.close()
+        del x64, r64
+
+    # roofline of the dominant kernel (largest total time in the timed steps)
+    D = tree.D
+    cnt = algorithmic_counts(N, d, m, s, D, nsamp, args.nrhs)
+    top = sorted(prof.items(), key=lambda kv: -kv[1][0])
+    dom, (dom_ms, dom_n) = top[0]
+    per_launch_ms = dom_ms / dom_n
+    roof = None
+    if dom.endswith("k_qrcp"):
+        bytes_per_launch = cnt["qr_bytes"] / D  # launches: one per level
+        achieved = bytes_per_launch / (per_launch_ms * 1e-3) / 1e9
+        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                    traffic=None, kernel=dom, algorithmic="16 B per trailing element per pivot step",
+                    avg_launch_ms=per_launch_ms)
+    elif dom.endswith("k_kmm") and dom.startswith("factor"):
+        fl = cnt["z_flops"] / D
+        achieved = fl / (per_launch_ms * 1e-3) / 1e12
+        roof = dict(bound="mfma", achieved=achieved, peak=PEAK_TFLOPS["fp32"], unit="TFLOP/s",
+                    frac=achieved / PEAK_TFLOPS["fp32"], traffic=None, kernel=dom,
+                    algorithmic="2 s^2 N flop per level", avg_launch_ms=per_launch_ms)
+    else:
+        roof = dict(bound="unknown", achieved=None, peak=None, unit=None, frac=None, traffic=None, kernel=dom,
+                    avg_launch_ms=per_launch_ms)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(c, args.cpu_sample, args.nrhs)
+
+    out = {
+        "metric": METRIC, "value": t_skel + t_fac, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"gaussian-mixture N={N} d={d} m={m} s={s} h={h} lambda={lam} nrhs={args.nrhs}",
+                   "N": N, "d": d, "leaf_size": m, "rank": s, "n_samples": nsamp, "nrhs": args.nrhs,
+                   "precision": "mixed"},
+        "skeletonize_s": t_skel, "factorize_s": t_fac, "solve_s": t_sol, "solves_per_s": args.nrhs / t_sol,
+        "refinement": info, "tree_s": t_tree,
+        **res,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernels_ms": {k: [round(v[0] / args.steps, 3), v[1] // args.steps] for k, v in top[:12]},
+    }
+    print(json.dumps(out))
+
+
+def cpu_baseline(c, n_sample, nrhs):
+    """The oracle (plain C, OpenMP) on a bounded sample of the same workload:
+    the first n_sample points of the mixture with the same d, m, s, h, lambda;
+    factor time (skeletonize + factorize) scaled to N by the N log(N/m) work
+    model of the method (Sec. 3, "Work")."""
+    import oracle
+    X = c["X"][:n_sample]
+    Bs = c["B"][:n_sample]
+    m, s = c["m"], c["s"]
+    o = oracle.Oracle(X, m, s, c["h"], nsamp=c["nsamp"], seed=c["seed"])
+    o.build_tree()
+    log(f"[bench] cpu baseline: oracle on {n_sample} points, {oracle.num_threads()} threads")
+    a = time.perf_counter()
+    o.skeletonize()
+    b = time.perf_counter()
+    o.factorize(c["lam"])
+    e = time.perf_counter()
+    o.solve(Bs)
+    g = time.perf_counter()
+    N = c["X"].shape[0]
+    Dn = max(1, int(np.ceil(np.log2(n_sample / m))))
+    DN = max(1, int(np.ceil(np.log2(N / m))))
+    scale = (N * DN) / (n_sample * Dn)
+    t_fac = (e - a) * scale
+    log(f"[bench] cpu baseline: skel {b - a:.2f} s factor {e - b:.2f} s solve {g - e:.2f} s (sample)")
+    return {"value": t_fac, "unit": "s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"first {n_sample} points of the workload (depth {Dn}); skeletonize+factorize "
+                      f"{e - a:.2f} s measured, scaled by N log(N/m) to N={N} (depth {DN})",
+            "sample_solve_s": g - e}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,165 @@
+/*
+ * askit.h -- C ABI of libaskit, a gfx950 (MI355X) implementation of the
+ * hierarchical direct solver for regularized kernel systems of
+ *   Yu, March & Biros, "An N log N Parallel Fast Direct Solver for Kernel
+ *   Matrices", arXiv:1701.02324.
+ *
+ * Problem (Sec. 1): given N points x_i in R^d, the Gaussian kernel of eq. (1)
+ * K_ij = exp(-|x_i - x_j|^2 / (2 h^2)) and lambda >= 0, solve
+ * (lambda I + Ktilde) x = b, where Ktilde is the hierarchical (ASKIT)
+ * approximation of K built from a binary tree and skeletons (Sec. 2.1).
+ * The pipeline is build_tree -> skeletonize (Alg. 1) -> factorize (Alg. 2)
+ * -> solve (Alg. 3).
+ *
+ * Conventions for every entry point:
+ *  - All array arguments are DEVICE pointers (memory of the current HIP
+ *    device), owned by the caller; the library never frees them and never
+ *    keeps them after the call returns (inputs are copied when retained).
+ *  - Points are N x d row-major (point-major; the paper's d x N matrix X).
+ *  - Right-hand sides and solutions are N x nrhs column-major with leading
+ *    dimension ld >= N, in the caller's original point order.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream)
+ *    and runs asynchronously unless stated otherwise.  Argument validation is
+ *    synchronous.  Calls on one handle must not overlap.
+ *  - Every call returns an askit_status; askit_last_error() gives the
+ *    message of the last failure on the calling thread.
+ *  - Handles own all device workspace and are released only by *_destroy.
+ *    A factor keeps a reference to its tree: destroy factors first.
+ */
+#ifndef ASKIT_H
+#define ASKIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ASKIT_OK = 0,
+    ASKIT_ERR_ARG = 1,       /* invalid argument; nothing was enqueued        */
+    ASKIT_ERR_ALLOC = 2,     /* device allocation failed                       */
+    ASKIT_ERR_HIP = 3,       /* a HIP runtime call failed                      */
+    ASKIT_ERR_STATE = 4,     /* call out of order (e.g. solve before factor)   */
+    ASKIT_ERR_SINGULAR = 5,  /* an exactly zero pivot was met                  */
+    ASKIT_WARN_ILLCOND = 6   /* result written, but a block's pivot ratio fell
+                                below 1e-12 (instability of Sec. 3 detected)   */
+} askit_status;
+
+typedef enum { ASKIT_FP64 = 0, ASKIT_MIXED = 1 } askit_precision;
+
+typedef struct askit_tree_s *askit_tree;
+typedef struct askit_factor_s *askit_factor;
+
+/* Method parameters.  leaf_size = m (>= 2), rank = s (>= 1; fixed rank,
+ * clamped per node to the number of candidates), n_samples = rows sampled
+ * per node for the ID (0 -> 4 s), seed = sampling seed, problem = index
+ * folded into the sampling streams, h = kernel bandwidth (> 0). */
+typedef struct {
+    int32_t leaf_size;
+    int32_t rank;
+    int32_t n_samples;
+    int32_t reserved;
+    uint64_t seed;
+    int64_t problem;
+    double h;
+} askit_options;
+
+/* Tree build (Sec. 2.1, "Partitioning the matrix"): complete binary tree of
+ * depth D = ceil(log2(N / m)); each node's points are split in two halves
+ * (floor(n/2) to the left) by the hyperplane through their median along
+ * their principal axis.  X: device, N x d row-major FP64, copied.  Blocks
+ * until the tree is built.  Errors: ASKIT_ERR_ARG for N < 1, d < 1 or
+ * d > 64, m < 2, s < 1, h <= 0, non-finite coordinates. */
+askit_status askit_build_tree(const double *X, int64_t N, int32_t d, const askit_options *opt, void *stream,
+                              askit_tree *out);
+
+/* Tree depth D and the permutation (perm[position] = original index). */
+askit_status askit_tree_depth(askit_tree t, int32_t *D);
+askit_status askit_tree_perm(askit_tree t, int64_t *perm /* device, N */);
+
+/* Skeletonize (Alg. 1; ID of eq. (4)): bottom-up over all non-root nodes,
+ * sample min(n_samples, N - n_alpha) rows outside the node, form the kernel
+ * block against the candidates (the node's points for a leaf, [l~ r~] for an
+ * internal node) and select s columns by column-pivoted QR in FP64.
+ * Blocks until done. */
+askit_status askit_skeletonize(askit_tree t, void *stream);
+
+/* Skeleton exchange (positions in the tree order; P = P_{alpha~ C}, row-major
+ * s_alpha x |C|).  sizes[2*i] = s_alpha, sizes[2*i+1] = |C| for heap node i
+ * (i = 1 .. 2^(D+1)-2; entry 0 is the root and stays 0).  ids holds
+ * nnodes * rank int32 and P nnodes * rank * cmax doubles with
+ * cmax = max(leaf_size, 2 rank), node i at offset i * rank (ids) and
+ * i * rank * cmax (P).  All three are HOST pointers.  Import replaces the
+ * skeletons of a built tree (used to factor on a given set of skeletons). */
+askit_status askit_skeletons_export(askit_tree t, int32_t *ids, double *P, int32_t *sizes);
+askit_status askit_skeletons_import(askit_tree t, const int32_t *ids, const double *P, const int32_t *sizes);
+
+/* Factorize (Alg. 2, eqs. (7)-(10)): leaf LU of lambda I + K_aa; for every
+ * internal node the reduced system Z = I + V W of eq. (8) formed from fused
+ * kernel-block x Phat products and LU-factored in FP64; Phat telescoped by
+ * eq. (10).  precision: ASKIT_FP64, or ASKIT_MIXED (FP32 kernel blocks, Phat
+ * and level products; FP64 LUs).  Blocks until done.  Returns
+ * ASKIT_WARN_ILLCOND (with a valid factor) when a pivot ratio min|U_ii| /
+ * max|U_ii| of some block is below 1e-12. */
+askit_status askit_factorize(askit_tree t, double lambda, int32_t precision, void *stream, askit_factor *out);
+
+/* X = (lambda I + Ktilde)^{-1} B (Alg. 3).  B, X: device, N x nrhs
+ * column-major (ldb, ldx >= N); B and X may alias.  With refinement enabled
+ * (the default for a MIXED factor, see askit_set_refinement) the result is
+ * refined against the FP64 operator of askit_matvec until the update is below
+ * refine_tol relative or max_refine steps; see askit_last_solve_info.  Without
+ * refinement the call is asynchronous on `stream`; with it, `stream` is
+ * synchronized once per refinement step. */
+askit_status askit_solve(askit_factor f, const double *B, int64_t ldb, int32_t nrhs, double *X, int64_t ldx,
+                         void *stream);
+
+/* X = (lambda I + Ktilde)^{-T} B: the transpose of the same factorization
+ * (Ktilde is not symmetric in the form of eq. (6)), applied from the root
+ * down: Ktilde_aa^{-T} = D^{-T} (I - V^T Z^{-T} W^T).  Same conventions. */
+askit_status askit_solve_transpose(askit_factor f, const double *B, int64_t ldb, int32_t nrhs, double *X,
+                                   int64_t ldx, void *stream);
+
+/* Y = (lambda I + Ktilde) X (which = 0) or Y = dKtilde/dh X (which = 1,
+ * skeletons held fixed), the hierarchical matvec of Sec. 2.1 in the form of
+ * eq. (6), FP64, kernel blocks recomputed.  Same layout conventions. */
+askit_status askit_matvec(askit_factor f, int32_t which, const double *X, int64_t ldx, int32_t nrhs, double *Y,
+                          int64_t ldy, void *stream);
+
+/* Iterative refinement controls (defaults: MIXED 10 steps, FP64 0 steps =
+ * plain direct solve; tolerance 1e-10 on the relative update). */
+askit_status askit_set_refinement(askit_factor f, int32_t max_refine, double refine_tol);
+
+typedef struct {
+    int32_t iterations;      /* refinement steps taken                       */
+    int32_t converged;       /* 1 if the update fell below refine_tol        */
+    double last_update;      /* max over columns of |dx| / |x| at the end   */
+    double residual;         /* max over columns of |b - A x| / |b|          */
+} askit_solve_info;
+
+askit_status askit_last_solve_info(askit_factor f, askit_solve_info *info);
+
+/* Factor diagnostics: the smallest pivot ratio min|U_ii|/max|U_ii| over all
+ * leaf and reduced-system LUs, and its node. */
+askit_status askit_factor_pivot_ratio(askit_factor f, double *ratio, int32_t *node);
+
+/* Per-phase timings (ms) and sizes of the last calls on a handle, as JSON. */
+askit_status askit_get_stats(askit_tree t, askit_factor f, char *json, size_t cap);
+
+/* Per-kernel timing: with profiling on, every launch of the library is
+ * bracketed by HIP events on its stream; askit_profile_report writes
+ * {"phase:kernel": [total_ms, launches], ...} (it synchronizes on the pending
+ * events).  Enabling resets the totals. */
+askit_status askit_profile_enable(int32_t on);
+askit_status askit_profile_report(char *json, size_t cap);
+
+const char *askit_last_error(void);
+void askit_tree_destroy(askit_tree t);
+void askit_factor_destroy(askit_factor f);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ASKIT_H */

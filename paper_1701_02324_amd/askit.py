@@ -1,0 +1,320 @@
+"""ctypes binding of libaskit (include/askit.h): argument marshalling only.
+
+Every arithmetic step runs in the HIP kernels of the library; this module
+passes device pointers of torch tensors and the current HIP stream.  The
+function names match the C entry points.  Importing it without a built
+library, or calling it without a GPU, raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loads the HIP runtime first, so the library binds to the same one
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaskit.so")
+
+ASKIT_OK, ASKIT_ERR_ARG, ASKIT_ERR_ALLOC, ASKIT_ERR_HIP, ASKIT_ERR_STATE, ASKIT_ERR_SINGULAR, ASKIT_WARN_ILLCOND = range(7)
+ASKIT_FP64, ASKIT_MIXED = 0, 1
+
+EXPORTED = [
+    "askit_build_tree", "askit_tree_depth", "askit_tree_perm", "askit_skeletonize", "askit_skeletons_export",
+    "askit_skeletons_import", "askit_factorize", "askit_solve", "askit_solve_transpose", "askit_matvec",
+    "askit_set_refinement", "askit_last_solve_info", "askit_factor_pivot_ratio", "askit_get_stats",
+    "askit_last_error", "askit_tree_destroy", "askit_factor_destroy", "askit_profile_enable",
+    "askit_profile_report",
+]
+
+
+class AskitError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"askit status {status}: {msg}")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("leaf_size", ctypes.c_int32), ("rank", ctypes.c_int32), ("n_samples", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64), ("problem", ctypes.c_int64),
+                ("h", ctypes.c_double)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("last_update", ctypes.c_double),
+                ("residual", ctypes.c_double)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+
+
+def load(path: str = LIB_PATH):
+    """Load libaskit.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1701_02324_amd.build`")
+    L = ctypes.CDLL(path)
+    L.askit_last_error.restype = ctypes.c_char_p
+    L.askit_build_tree.argtypes = [_vp, _i64, _i32, ctypes.POINTER(Options), _vp, ctypes.POINTER(_vp)]
+    L.askit_tree_depth.argtypes = [_vp, ctypes.POINTER(_i32)]
+    L.askit_tree_perm.argtypes = [_vp, _vp]
+    L.askit_skeletonize.argtypes = [_vp, _vp]
+    L.askit_skeletons_export.argtypes = [_vp, _vp, _vp, _vp]
+    L.askit_skeletons_import.argtypes = [_vp, _vp, _vp, _vp]
+    L.askit_factorize.argtypes = [_vp, ctypes.c_double, _i32, _vp, ctypes.POINTER(_vp)]
+    for f in ("askit_solve", "askit_solve_transpose"):
+        getattr(L, f).argtypes = [_vp, _vp, _i64, _i32, _vp, _i64, _vp]
+    L.askit_matvec.argtypes = [_vp, _i32, _vp, _i64, _i32, _vp, _i64, _vp]
+    L.askit_set_refinement.argtypes = [_vp, _i32, ctypes.c_double]
+    L.askit_last_solve_info.argtypes = [_vp, ctypes.POINTER(SolveInfo)]
+    L.askit_factor_pivot_ratio.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32)]
+    L.askit_get_stats.argtypes = [_vp, _vp, ctypes.c_char_p, ctypes.c_size_t]
+    L.askit_profile_enable.argtypes = [_i32]
+    L.askit_profile_report.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+    L.askit_tree_destroy.argtypes = [_vp]
+    L.askit_factor_destroy.argtypes = [_vp]
+    for name in EXPORTED:
+        if name not in ("askit_last_error", "askit_tree_destroy", "askit_factor_destroy"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(st, allow_warn=False):
+    if st == ASKIT_OK or (allow_warn and st == ASKIT_WARN_ILLCOND):
+        return st
+    raise AskitError(st, load().askit_last_error().decode())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev64(x, name):
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    return x.to(torch.float64)
+
+
+def _colmajor(B):
+    """N x nrhs (or N) tensor -> (column-major storage tensor of shape nrhs x N, was_vector)."""
+    vec = B.dim() == 1
+    B2 = B[:, None] if vec else B
+    return B2.t().contiguous(), vec
+
+
+# ---------------------------------------------------------------------------
+# thin wrappers with the C names
+# ---------------------------------------------------------------------------
+
+def askit_build_tree(X, leaf_size, rank, h, n_samples=0, seed=0, problem=0, stream=None):
+    X = _dev64(X, "X").contiguous()
+    N, d = X.shape
+    opt = Options(int(leaf_size), int(rank), int(n_samples), 0, int(seed) & 0xFFFFFFFFFFFFFFFF, int(problem), float(h))
+    out = _vp()
+    _check(load().askit_build_tree(_vp(X.data_ptr()), N, d, ctypes.byref(opt), _stream(stream), ctypes.byref(out)))
+    return out
+
+
+def askit_tree_depth(tree):
+    D = _i32()
+    _check(load().askit_tree_depth(tree, ctypes.byref(D)))
+    return D.value
+
+
+def askit_tree_perm(tree, N, device="cuda"):
+    p = torch.empty(N, dtype=torch.int64, device=device)
+    _check(load().askit_tree_perm(tree, _vp(p.data_ptr())))
+    return p
+
+
+def askit_skeletonize(tree, stream=None):
+    _check(load().askit_skeletonize(tree, _stream(stream)))
+
+
+def askit_skeletons_export(tree, nnodes, rank, cmax):
+    import numpy as np
+    ids = np.zeros(nnodes * rank, dtype=np.int32)
+    P = np.zeros(nnodes * rank * cmax, dtype=np.float64)
+    sizes = np.zeros(2 * nnodes, dtype=np.int32)
+    _check(load().askit_skeletons_export(tree, ids.ctypes.data, P.ctypes.data, sizes.ctypes.data))
+    return ids, P, sizes
+
+
+def askit_skeletons_import(tree, ids, P, sizes):
+    import numpy as np
+    ids = np.ascontiguousarray(ids, dtype=np.int32)
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    sizes = np.ascontiguousarray(sizes, dtype=np.int32)
+    _check(load().askit_skeletons_import(tree, ids.ctypes.data, P.ctypes.data, sizes.ctypes.data))
+
+
+def askit_factorize(tree, lam, precision=ASKIT_FP64, stream=None):
+    out = _vp()
+    st = load().askit_factorize(tree, float(lam), int(precision), _stream(stream), ctypes.byref(out))
+    _check(st, allow_warn=True)
+    return out, st
+
+
+def _apply(fn, factor, B, stream, *pre):
+    B = _dev64(B, "B")
+    Bc, vec = _colmajor(B)
+    nrhs, N = Bc.shape
+    Xc = torch.empty_like(Bc)
+    _check(fn(factor, *pre, _vp(Bc.data_ptr()), N, nrhs, _vp(Xc.data_ptr()), N, _stream(stream)))
+    X = Xc.t()
+    return X[:, 0] if vec else X
+
+
+def askit_solve(factor, B, stream=None):
+    return _apply(load().askit_solve, factor, B, stream)
+
+
+def askit_solve_transpose(factor, B, stream=None):
+    return _apply(load().askit_solve_transpose, factor, B, stream)
+
+
+def askit_matvec(factor, X, which=0, stream=None):
+    return _apply(load().askit_matvec, factor, X, stream, int(which))
+
+
+def askit_set_refinement(factor, max_refine, refine_tol):
+    _check(load().askit_set_refinement(factor, int(max_refine), float(refine_tol)))
+
+
+def askit_last_solve_info(factor):
+    info = SolveInfo()
+    _check(load().askit_last_solve_info(factor, ctypes.byref(info)))
+    return dict(iterations=info.iterations, converged=bool(info.converged), last_update=info.last_update,
+                residual=info.residual)
+
+
+def askit_factor_pivot_ratio(factor):
+    r = ctypes.c_double()
+    n = _i32()
+    _check(load().askit_factor_pivot_ratio(factor, ctypes.byref(r), ctypes.byref(n)))
+    return r.value, n.value
+
+
+def askit_get_stats(tree=None, factor=None):
+    import json
+    buf = ctypes.create_string_buffer(2048)
+    _check(load().askit_get_stats(tree, factor, buf, 2048))
+    return json.loads(buf.value.decode())
+
+
+def askit_profile_enable(on=True):
+    _check(load().askit_profile_enable(1 if on else 0))
+
+
+def askit_profile_report():
+    """{"phase:kernel": (total_ms, launches)} since profiling was enabled."""
+    import json
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(load().askit_profile_report(buf, 1 << 16))
+    return {k: tuple(v) for k, v in json.loads(buf.value.decode()).items()}
+
+
+def askit_tree_destroy(tree):
+    if tree:
+        load().askit_tree_destroy(tree)
+
+
+def askit_factor_destroy(factor):
+    if factor:
+        load().askit_factor_destroy(factor)
+
+
+# ---------------------------------------------------------------------------
+# convenience objects (own their handles)
+# ---------------------------------------------------------------------------
+
+class Tree:
+    """Tree + skeletons of one problem (points X on the GPU, FP64)."""
+
+    def __init__(self, X, leaf_size, rank, h, n_samples=0, seed=0, problem=0, stream=None):
+        self.N, self.d = X.shape
+        self.m, self.s, self.h = int(leaf_size), int(rank), float(h)
+        self.nsamp = int(n_samples) or 4 * self.s
+        self.handle = askit_build_tree(X, leaf_size, rank, h, n_samples, seed, problem, stream)
+        self.D = askit_tree_depth(self.handle)
+        self.nnodes = (2 << self.D) - 1
+        self.mmax = -(-self.N // (1 << self.D))
+        self.cmax = max(self.mmax, 2 * self.s)
+        self.device = X.device
+
+    def perm(self):
+        return askit_tree_perm(self.handle, self.N, self.device)
+
+    def skeletonize(self, stream=None):
+        askit_skeletonize(self.handle, stream)
+        return self
+
+    def export_skeletons(self):
+        return askit_skeletons_export(self.handle, self.nnodes, self.s, self.cmax)
+
+    def import_skeletons(self, ids, P, sizes):
+        askit_skeletons_import(self.handle, ids, P, sizes)
+
+    def factorize(self, lam, precision=ASKIT_FP64, stream=None):
+        return Factor(self, lam, precision, stream)
+
+    def stats(self):
+        return askit_get_stats(self.handle, None)
+
+    def close(self):
+        askit_tree_destroy(getattr(self, "handle", None))
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Factor:
+    """Factorization of lambda I + Ktilde on a skeletonized tree."""
+
+    def __init__(self, tree, lam, precision=ASKIT_FP64, stream=None):
+        self.tree = tree
+        self.lam = float(lam)
+        self.precision = precision
+        self.handle, self.status = askit_factorize(tree.handle, lam, precision, stream)
+
+    def solve(self, B, stream=None):
+        return askit_solve(self.handle, B, stream)
+
+    def solve_transpose(self, B, stream=None):
+        return askit_solve_transpose(self.handle, B, stream)
+
+    def matvec(self, X, which=0, stream=None):
+        return askit_matvec(self.handle, X, which, stream)
+
+    def set_refinement(self, max_refine, tol):
+        askit_set_refinement(self.handle, max_refine, tol)
+
+    def info(self):
+        return askit_last_solve_info(self.handle)
+
+    def pivot_ratio(self):
+        return askit_factor_pivot_ratio(self.handle)
+
+    def stats(self):
+        return askit_get_stats(self.tree.handle, self.handle)
+
+    def close(self):
+        askit_factor_destroy(getattr(self, "handle", None))
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,1540 @@
+// api.hip -- host orchestration and C ABI of libaskit (see include/askit.h).
+//
+// The host only sequences launches: every arithmetic step of the tree build,
+// the skeletonization, the factorization and the solves runs in the kernels
+// of the k_*.hip files.  Each phase is expressed as a "plan": a list of
+// launches whose task descriptors (one per tree node and product chunk) are
+// built once on the host, uploaded once, and replayed level by level.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "askit.h"
+#include "askit_kernels.h"
+
+using namespace askit;
+
+namespace {
+
+thread_local std::string g_err;
+
+askit_status fail(askit_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+#define HIP_TRY(x)                                                                              \
+    do {                                                                                        \
+        hipError_t e_ = (x);                                                                    \
+        if (e_ != hipSuccess) return fail(ASKIT_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define ST_TRY(x)                          \
+    do {                                   \
+        askit_status s_ = (x);             \
+        if (s_ != ASKIT_OK) return s_;     \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device memory
+// ---------------------------------------------------------------------------
+struct DBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    ~DBuf() { release(); }
+    void release() {
+        if (p) hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    askit_status alloc(size_t n) {
+        release();
+        if (n == 0) n = 8;
+        if (hipMalloc(&p, n) != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            return fail(ASKIT_ERR_ALLOC, "device allocation of " + std::to_string(n) + " bytes failed");
+        }
+        bytes = n;
+        return ASKIT_OK;
+    }
+    template <class T> T *as() const { return (T *)p; }
+};
+
+template <class T> askit_status upload(DBuf &b, const std::vector<T> &v) {
+    ST_TRY(b.alloc(sizeof(T) * std::max<size_t>(v.size(), 1)));
+    if (!v.empty()) HIP_TRY(hipMemcpy(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    return ASKIT_OK;
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline unsigned grid1(int64_t n, int bs = 256) { return (unsigned)std::max<int64_t>(1, cdiv(n, bs)); }
+
+// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014), used to seed the per-node
+// sampling streams: node state = output number k = id + 1 + problem 2^32 of
+// the generator started at `seed`.
+uint64_t splitmix_out(uint64_t st) {
+    uint64_t z = st;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+uint64_t node_state(uint64_t seed, int64_t problem, int64_t id) {
+    uint64_t k = (uint64_t)id + 1ULL + ((uint64_t)problem << 32);
+    return splitmix_out(seed + k * 0x9E3779B97F4A7C15ULL);
+}
+
+// ---------------------------------------------------------------------------
+// plans: a list of enqueue closures plus the device buffers they reference
+// ---------------------------------------------------------------------------
+typedef std::function<hipError_t(hipStream_t, int)> Launch;
+
+// Optional per-kernel timing with HIP events recorded on the launch stream
+// (askit_profile_enable); totals per kernel name are read back by
+// askit_profile_report.
+struct ProfRec {
+    std::string name;
+    hipEvent_t a, b;
+};
+struct Prof {
+    bool on = false;
+    std::vector<ProfRec> pend;
+    std::map<std::string, std::pair<double, int64_t>> acc;
+};
+Prof g_prof;
+
+template <class F> hipError_t timed(const std::string &name, hipStream_t st, F &&f) {
+    if (!g_prof.on) return f();
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return hipErrorOutOfMemory;
+    hipEventRecord(a, st);
+    hipError_t e = f();
+    hipEventRecord(b, st);
+    g_prof.pend.push_back({name, a, b});
+    return e;
+}
+
+hipError_t prof_flush() {
+    for (auto &r : g_prof.pend) {
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e != hipSuccess) return e;
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, r.a, r.b);
+        auto &v = g_prof.acc[r.name];
+        v.first += ms;
+        v.second += 1;
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    g_prof.pend.clear();
+    return hipSuccess;
+}
+
+struct Plan {
+    std::string tag;
+    std::vector<std::pair<std::string, Launch>> steps;
+    std::vector<std::unique_ptr<DBuf>> bufs;
+    DBuf *own() {
+        bufs.emplace_back(new DBuf());
+        return bufs.back().get();
+    }
+    void add(const char *name, Launch f) { steps.emplace_back(tag + ":" + name, std::move(f)); }
+    hipError_t run(hipStream_t st, int ncol) const {
+        for (const auto &s : steps) {
+            hipError_t e = timed(s.first, st, [&] { return s.second(st, ncol); });
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+};
+
+enum Prec { P64 = 0, P32 = 1 };
+
+// a launch of the fused kernel-matrix product with optional split of the
+// contraction into chunks (partials in a workspace, reduced in index order)
+struct KmmBuild {
+    std::vector<KmmTask> tasks;
+    std::vector<TileItem> items;
+    std::vector<RedTask> reds;
+    int tc = 64;
+    int64_t ws_elems = 0;  // partial elements needed (output type)
+    int out_size = 8;
+};
+
+void kmm_add(KmmBuild &kb, KmmTask t, int kcap, int ncap, int64_t KC, int b_elem, char *ws) {
+    const int nrt = (int)cdiv(t.rcap, 64), nct = (int)cdiv(ncap, kb.tc);
+    const int64_t nch = std::max<int64_t>(1, cdiv(kcap, KC));
+    if (nch == 1) {
+        t.k0 = 0;
+        t.k1 = kcap;
+        int ti = (int)kb.tasks.size();
+        kb.tasks.push_back(t);
+        for (int r = 0; r < nrt; r++)
+            for (int c = 0; c < nct; c++) kb.items.push_back({ti, r, c, 0});
+        return;
+    }
+    const int64_t per = (int64_t)t.rcap * ncap;
+    RedTask rd{};
+    rd.src = ws + kb.ws_elems * kb.out_size;
+    rd.pstride = per;
+    rd.prs = ncap;
+    rd.np = (int32_t)nch;
+    rd.rows = t.rcap;
+    rd.dst = t.C;
+    rd.drs = t.crs;
+    rd.dcs = t.ccs;
+    rd.op = t.op;
+    for (int64_t c = 0; c < nch; c++) {
+        KmmTask u = t;
+        u.k0 = (int32_t)(c * KC);
+        u.k1 = (int32_t)std::min<int64_t>(kcap, (c + 1) * KC);
+        u.B = (const char *)t.B + (int64_t)u.k0 * t.ldb * b_elem;
+        u.C = ws + (kb.ws_elems + c * per) * kb.out_size;
+        u.crs = ncap;
+        u.ccs = 1;
+        u.op = OP_STORE;
+        int ti = (int)kb.tasks.size();
+        kb.tasks.push_back(u);
+        for (int r = 0; r < nrt; r++)
+            for (int cc = 0; cc < nct; cc++) kb.items.push_back({ti, r, cc, 0});
+    }
+    kb.reds.push_back(rd);
+    kb.ws_elems += nch * per;
+}
+
+struct GmmBuild {
+    std::vector<GmmTask> tasks;
+    std::vector<TileItem> items;
+    std::vector<RedTask> reds;
+    int tc = 64;
+    int64_t ws_elems = 0;
+    int elem = 8;
+};
+
+// C(r, c) op= sum_k A(r, k) B(k, c); split of k into chunks of KC if kdim > KC
+void gmm_add(GmmBuild &gb, GmmTask t, int ncap, int64_t KC, char *ws) {
+    const int nrt = (int)cdiv(t.rows, 64), nct = (int)cdiv(ncap, gb.tc);
+    const int64_t nch = std::max<int64_t>(1, cdiv(t.kdim, KC));
+    if (nch == 1) {
+        int ti = (int)gb.tasks.size();
+        gb.tasks.push_back(t);
+        for (int r = 0; r < nrt; r++)
+            for (int c = 0; c < nct; c++) gb.items.push_back({ti, r, c, 0});
+        return;
+    }
+    const int64_t per = (int64_t)t.rows * ncap;
+    RedTask rd{};
+    rd.src = ws + gb.ws_elems * gb.elem;
+    rd.pstride = per;
+    rd.prs = ncap;
+    rd.np = (int32_t)nch;
+    rd.rows = t.rows;
+    rd.dst = t.C;
+    rd.drs = t.crs;
+    rd.dcs = t.ccs;
+    rd.op = t.op;
+    for (int64_t c = 0; c < nch; c++) {
+        GmmTask u = t;
+        int64_t k0 = c * KC;
+        u.kdim = (int32_t)std::min<int64_t>(t.kdim - k0, KC);
+        u.A = (const char *)t.A + k0 * t.acs * gb.elem;
+        u.B = (const char *)t.B + k0 * t.brs * gb.elem;
+        u.C = ws + (gb.ws_elems + c * per) * gb.elem;
+        u.crs = ncap;
+        u.ccs = 1;
+        u.op = OP_STORE;
+        int ti = (int)gb.tasks.size();
+        gb.tasks.push_back(u);
+        for (int r = 0; r < nrt; r++)
+            for (int cc = 0; cc < nct; cc++) gb.items.push_back({ti, r, cc, 0});
+    }
+    gb.reds.push_back(rd);
+    gb.ws_elems += nch * per;
+}
+
+template <typename T, typename TO, int TC>
+hipError_t launch_kmm(const KmmTask *tasks, const TileItem *items, int nitems, int ncol, int d, hipStream_t st) {
+    hipLaunchKernelGGL((k_kmm<T, TO, TC>), dim3(nitems), dim3(256), 0, st, tasks, items, ncol, d);
+    return hipGetLastError();
+}
+
+template <typename T, int TC>
+hipError_t launch_gmm(const GmmTask *tasks, const TileItem *items, int nitems, int ncol, hipStream_t st) {
+    hipLaunchKernelGGL((k_gmm<T, TC>), dim3(nitems), dim3(256), 0, st, tasks, items, ncol, 1 << 30);
+    return hipGetLastError();
+}
+
+// finalize a kmm build into plan steps; tin/tout = element precisions
+askit_status kmm_commit(Plan &P, KmmBuild &kb, Prec tin, Prec tout, int d, int rows_red_max) {
+    if (kb.tasks.empty()) return ASKIT_OK;
+    DBuf *bt = P.own(), *bi = P.own();
+    ST_TRY(upload(*bt, kb.tasks));
+    ST_TRY(upload(*bi, kb.items));
+    const KmmTask *tp = bt->as<KmmTask>();
+    const TileItem *ip = bi->as<TileItem>();
+    const int nitems = (int)kb.items.size(), tc = kb.tc;
+    P.add("k_kmm", [=](hipStream_t st, int ncol) -> hipError_t {
+        if (tin == P64) {
+            if (tc == 128) return launch_kmm<double, double, 128>(tp, ip, nitems, ncol, d, st);
+            if (tc == 64) return launch_kmm<double, double, 64>(tp, ip, nitems, ncol, d, st);
+            return launch_kmm<double, double, 16>(tp, ip, nitems, ncol, d, st);
+        }
+        if (tout == P64) {
+            if (tc == 128) return launch_kmm<float, double, 128>(tp, ip, nitems, ncol, d, st);
+            if (tc == 64) return launch_kmm<float, double, 64>(tp, ip, nitems, ncol, d, st);
+            return launch_kmm<float, double, 16>(tp, ip, nitems, ncol, d, st);
+        }
+        if (tc == 128) return launch_kmm<float, float, 128>(tp, ip, nitems, ncol, d, st);
+        if (tc == 64) return launch_kmm<float, float, 64>(tp, ip, nitems, ncol, d, st);
+        return launch_kmm<float, float, 16>(tp, ip, nitems, ncol, d, st);
+    });
+    if (!kb.reds.empty()) {
+        DBuf *br = P.own();
+        ST_TRY(upload(*br, kb.reds));
+        const RedTask *rp = br->as<RedTask>();
+        const int nred = (int)kb.reds.size();
+        P.add("k_reduce", [=](hipStream_t st, int ncol) -> hipError_t {
+            int bpt = (int)cdiv((int64_t)rows_red_max * ncol, 256);
+            if (tout == P64) hipLaunchKernelGGL((k_reduce<double, double>), dim3(nred * bpt), dim3(256), 0, st, rp, ncol, bpt);
+            else hipLaunchKernelGGL((k_reduce<float, float>), dim3(nred * bpt), dim3(256), 0, st, rp, ncol, bpt);
+            return hipGetLastError();
+        });
+    }
+    return ASKIT_OK;
+}
+
+askit_status gmm_commit(Plan &P, GmmBuild &gb, Prec t, int rows_red_max) {
+    if (gb.tasks.empty()) return ASKIT_OK;
+    DBuf *bt = P.own(), *bi = P.own();
+    ST_TRY(upload(*bt, gb.tasks));
+    ST_TRY(upload(*bi, gb.items));
+    const GmmTask *tp = bt->as<GmmTask>();
+    const TileItem *ip = bi->as<TileItem>();
+    const int nitems = (int)gb.items.size(), tc = gb.tc;
+    P.add("k_gmm", [=](hipStream_t st, int ncol) -> hipError_t {
+        if (t == P64) {
+            if (tc == 128) return launch_gmm<double, 128>(tp, ip, nitems, ncol, st);
+            if (tc == 64) return launch_gmm<double, 64>(tp, ip, nitems, ncol, st);
+            return launch_gmm<double, 16>(tp, ip, nitems, ncol, st);
+        }
+        if (tc == 128) return launch_gmm<float, 128>(tp, ip, nitems, ncol, st);
+        if (tc == 64) return launch_gmm<float, 64>(tp, ip, nitems, ncol, st);
+        return launch_gmm<float, 16>(tp, ip, nitems, ncol, st);
+    });
+    if (!gb.reds.empty()) {
+        DBuf *br = P.own();
+        ST_TRY(upload(*br, gb.reds));
+        const RedTask *rp = br->as<RedTask>();
+        const int nred = (int)gb.reds.size();
+        P.add("k_reduce", [=](hipStream_t st, int ncol) -> hipError_t {
+            int bpt = (int)cdiv((int64_t)rows_red_max * ncol, 256);
+            if (t == P64) hipLaunchKernelGGL((k_reduce<double, double>), dim3(nred * bpt), dim3(256), 0, st, rp, ncol, bpt);
+            else hipLaunchKernelGGL((k_reduce<float, float>), dim3(nred * bpt), dim3(256), 0, st, rp, ncol, bpt);
+            return hipGetLastError();
+        });
+    }
+    return ASKIT_OK;
+}
+
+askit_status lu_commit(Plan &P, const std::vector<LuTask> &v) {
+    if (v.empty()) return ASKIT_OK;
+    DBuf *b = P.own();
+    ST_TRY(upload(*b, v));
+    const LuTask *tp = b->as<LuTask>();
+    const int n = (int)v.size();
+    P.add("k_lu", [=](hipStream_t st, int) -> hipError_t {
+        hipLaunchKernelGGL(k_lu, dim3(n), dim3(256), 0, st, tp);
+        return hipGetLastError();
+    });
+    P.add("k_lu_diaginv", [=](hipStream_t st, int) -> hipError_t {
+        hipLaunchKernelGGL(k_lu_diaginv, dim3(n), dim3(256), 0, st, tp);
+        return hipGetLastError();
+    });
+    return ASKIT_OK;
+}
+
+// LU solves with nrhs = fixed (>0) or the run-time column count (fixed = 0)
+template <typename T, bool TR>
+hipError_t launch_lusolve(const LuTask *tp, int n, int nrhs, hipStream_t st) {
+    if (nrhs > 16) {
+        const int panels = (int)cdiv(nrhs, 32);
+        hipLaunchKernelGGL((k_lusolve<T, 32, TR>), dim3(n * panels), dim3(256), 0, st, tp, nrhs, panels);
+    } else {
+        hipLaunchKernelGGL((k_lusolve<T, 16, TR>), dim3(n), dim3(256), 0, st, tp, nrhs, 1);
+    }
+    return hipGetLastError();
+}
+
+askit_status getrs_commit(Plan &P, const std::vector<LuTask> &v, Prec t, bool trans, int fixed) {
+    if (v.empty()) return ASKIT_OK;
+    DBuf *b = P.own();
+    ST_TRY(upload(*b, v));
+    const LuTask *tp = b->as<LuTask>();
+    const int n = (int)v.size();
+    P.add(trans ? "k_lusolve_t" : "k_lusolve", [=](hipStream_t st, int ncol) -> hipError_t {
+        const int nrhs = fixed ? fixed : ncol;
+        if (t == P64) return trans ? launch_lusolve<double, true>(tp, n, nrhs, st) : launch_lusolve<double, false>(tp, n, nrhs, st);
+        return trans ? launch_lusolve<float, true>(tp, n, nrhs, st) : launch_lusolve<float, false>(tp, n, nrhs, st);
+    });
+    return ASKIT_OK;
+}
+
+askit_status copy_commit(Plan &P, const std::vector<CopyTask> &v, Prec from, Prec to, int rows_max, int cols_max) {
+    if (v.empty()) return ASKIT_OK;
+    DBuf *b = P.own();
+    ST_TRY(upload(*b, v));
+    const CopyTask *tp = b->as<CopyTask>();
+    const int n = (int)v.size();
+    const int rb = (int)cdiv((int64_t)rows_max * cols_max, 256);
+    P.add("k_copy", [=](hipStream_t st, int) -> hipError_t {
+        if (from == P64 && to == P64) hipLaunchKernelGGL((k_copy<double, double>), dim3(n * rb), dim3(256), 0, st, tp, rb);
+        else if (from == P64) hipLaunchKernelGGL((k_copy<double, float>), dim3(n * rb), dim3(256), 0, st, tp, rb);
+        else hipLaunchKernelGGL((k_copy<float, double>), dim3(n * rb), dim3(256), 0, st, tp, rb);
+        return hipGetLastError();
+    });
+    return ASKIT_OK;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+struct askit_tree_s {
+    int64_t N = 0;
+    int d = 0, m = 0, s = 0, nsamp = 0, D = 0, cmax = 0, mmax = 0;
+    int64_t nnodes = 0, problem = 0;
+    uint64_t seed = 0;
+    double h = 1.0;
+    std::vector<int64_t> nb, ne;  // host node ranges
+    DBuf X, Xp, perm, dnb, dne;
+    DBuf srank, trunc, skel, Pt, samp;
+    bool skel_ok = false;
+    int refs = 0;
+    double t_tree = 0, t_skel = 0;
+    int64_t first(int l) const { return ((int64_t)1 << l) - 1; }
+};
+
+struct askit_factor_s {
+    askit_tree t = nullptr;
+    double lambda = 0;
+    Prec prec = P64;
+    DBuf LU, piv, ratio, Xc, Xcf, ws, dinv;
+    std::vector<std::unique_ptr<DBuf>> PH;  // levels 1..D
+    int64_t leafLU = 0, zLU = 0;            // element offsets of the arenas
+    // solve state
+    int cap = 0;
+    DBuf W, TB, WX, WY, CB, wsS, R, Dx, nrm;
+    std::unique_ptr<Plan> solve_plan, solvet_plan, mv_plan[2];
+    int max_refine = 10;
+    double refine_tol = 1e-10;
+    askit_solve_info info{};
+    double min_ratio = 1.0;
+    int min_node = -1;
+    double t_factor = 0, t_solve = 0;
+    void *ph(int level) const { return PH[level - 1]->p; }
+    size_t elem() const { return prec == P64 ? 8 : 4; }
+    double *lu_of(int64_t id) const {
+        int64_t leaf0 = t->first(t->D);
+        if (id >= leaf0) return LU.as<double>() + leafLU + (id - leaf0) * (int64_t)t->mmax * t->mmax;
+        return LU.as<double>() + zLU + id * (int64_t)(2 * t->s) * (2 * t->s);
+    }
+    double *dinv_of(int64_t id) const {
+        int64_t leaf0 = t->first(t->D), lb = (t->mmax + 15) / 16, zb = (2 * t->s + 15) / 16;
+        if (id >= leaf0) return dinv.as<double>() + (id - leaf0) * lb * 512;
+        return dinv.as<double>() + (leaf0 + 1) * lb * 512 + id * zb * 512;
+    }
+    int32_t *piv_of(int64_t id) const {
+        int64_t leaf0 = t->first(t->D);
+        if (id >= leaf0) return piv.as<int32_t>() + (id - leaf0) * (int64_t)t->mmax;
+        return piv.as<int32_t>() + (leaf0 + 1) * t->mmax + id * (int64_t)(2 * t->s);
+    }
+};
+
+extern "C" {
+
+const char *askit_last_error(void) { return g_err.c_str(); }
+
+askit_status askit_profile_enable(int32_t on) {
+    HIP_TRY(prof_flush());
+    g_prof.acc.clear();
+    g_prof.on = on != 0;
+    return ASKIT_OK;
+}
+
+askit_status askit_profile_report(char *json, size_t cap) {
+    if (!json || cap == 0) return fail(ASKIT_ERR_ARG, "NULL buffer");
+    HIP_TRY(prof_flush());
+    std::string o = "{";
+    bool first = true;
+    for (auto &kv : g_prof.acc) {
+        char b[256];
+        snprintf(b, sizeof b, "%s\"%s\": [%.6f, %lld]", first ? "" : ", ", kv.first.c_str(), kv.second.first,
+                 (long long)kv.second.second);
+        o += b;
+        first = false;
+    }
+    o += "}";
+    if (o.size() + 1 > cap) return fail(ASKIT_ERR_ARG, "buffer too small");
+    memcpy(json, o.c_str(), o.size() + 1);
+    return ASKIT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tree
+// ---------------------------------------------------------------------------
+askit_status askit_build_tree(const double *X, int64_t N, int32_t d, const askit_options *opt, void *stream,
+                              askit_tree *out) {
+    if (!out) return fail(ASKIT_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!X || !opt) return fail(ASKIT_ERR_ARG, "X or options is NULL");
+    if (N < 1 || N >= (int64_t)1 << 31) return fail(ASKIT_ERR_ARG, "N must be in [1, 2^31)");
+    if (d < 1 || d > kMaxDim) return fail(ASKIT_ERR_ARG, "d must be in [1, 64]");
+    if (opt->leaf_size < 2) return fail(ASKIT_ERR_ARG, "leaf_size must be >= 2");
+    if (opt->rank < 1) return fail(ASKIT_ERR_ARG, "rank must be >= 1");
+    if (!(opt->h > 0.0) || !std::isfinite(opt->h)) return fail(ASKIT_ERR_ARG, "h must be positive and finite");
+    if (opt->n_samples < 0) return fail(ASKIT_ERR_ARG, "n_samples must be >= 0");
+    hipStream_t st = (hipStream_t)stream;
+    std::unique_ptr<askit_tree_s> t(new askit_tree_s());
+    t->N = N;
+    t->d = d;
+    t->m = opt->leaf_size;
+    t->s = opt->rank;
+    t->nsamp = opt->n_samples ? opt->n_samples : 4 * opt->rank;
+    t->seed = opt->seed;
+    t->problem = opt->problem;
+    t->h = opt->h;
+    while ((int64_t)t->m * ((int64_t)1 << t->D) < N) t->D++;
+    t->nnodes = ((int64_t)2 << t->D) - 1;
+    t->mmax = (int)cdiv(N, (int64_t)1 << t->D);
+    t->cmax = std::max(t->mmax, 2 * t->s);
+    if (t->mmax > 512 || 2 * t->s > 512)
+        return fail(ASKIT_ERR_ARG, "leaf size and 2 * rank must not exceed 512");
+    if (t->nsamp > 4096 || t->cmax > 2048) return fail(ASKIT_ERR_ARG, "n_samples must be <= 4096");
+    t->nb.assign(t->nnodes, 0);
+    t->ne.assign(t->nnodes, 0);
+    t->ne[0] = N;
+    for (int64_t id = 0; id < t->first(t->D); id++) {
+        int64_t b = t->nb[id], n = t->ne[id] - b;
+        t->nb[2 * id + 1] = b;
+        t->ne[2 * id + 1] = b + n / 2;
+        t->nb[2 * id + 2] = b + n / 2;
+        t->ne[2 * id + 2] = t->ne[id];
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    ST_TRY(t->X.alloc(sizeof(double) * N * d));
+    ST_TRY(t->Xp.alloc(sizeof(double) * N * d));
+    ST_TRY(t->perm.alloc(sizeof(int64_t) * N));
+    ST_TRY(upload(t->dnb, t->nb));
+    ST_TRY(upload(t->dne, t->ne));
+    HIP_TRY(hipMemcpyAsync(t->X.p, X, sizeof(double) * N * d, hipMemcpyDeviceToDevice, st));
+    // scratch for the level reductions and the sort
+    const int npair = d * (d + 1) / 2;
+    std::vector<int16_t> pa, pc;
+    for (int a = 0; a < d; a++)
+        for (int c = a; c < d; c++) {
+            pa.push_back((int16_t)a);
+            pc.push_back((int16_t)c);
+        }
+    DBuf dpa, dpc, part, mu, S, axis, key, kid, key2, kid2, bad;
+    ST_TRY(upload(dpa, pa));
+    ST_TRY(upload(dpc, pc));
+    int64_t part_max = 0;
+    for (int l = 0; l < t->D; l++) {
+        int64_t cnt = (int64_t)1 << l, nmax = cdiv(N, cnt), maxch = cdiv(nmax, kTreeChunk);
+        part_max = std::max(part_max, cnt * maxch * std::max(d, npair));
+    }
+    int64_t cnt_max = t->D > 0 ? ((int64_t)1 << (t->D - 1)) : 1;
+    ST_TRY(part.alloc(sizeof(double) * std::max<int64_t>(part_max, 1)));
+    ST_TRY(mu.alloc(sizeof(double) * cnt_max * d));
+    ST_TRY(S.alloc(sizeof(double) * cnt_max * d * d));
+    ST_TRY(axis.alloc(sizeof(double) * cnt_max * d));
+    ST_TRY(key.alloc(sizeof(double) * N));
+    ST_TRY(kid.alloc(sizeof(int64_t) * N));
+    ST_TRY(key2.alloc(sizeof(double) * N));
+    ST_TRY(kid2.alloc(sizeof(int64_t) * N));
+    ST_TRY(bad.alloc(sizeof(int32_t)));
+    HIP_TRY(hipMemsetAsync(bad.p, 0, sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_check_finite, dim3(grid1(N * d)), dim3(256), 0, st, t->X.as<double>(), N * d, bad.as<int32_t>());
+    hipLaunchKernelGGL(k_iota, dim3(grid1(N)), dim3(256), 0, st, t->perm.as<int64_t>(), N);
+    const int64_t *nb = t->dnb.as<int64_t>(), *ne = t->dne.as<int64_t>();
+    for (int l = 0; l < t->D; l++) {
+        const int cnt = 1 << l;
+        const int64_t first = t->first(l), nmax = cdiv(N, cnt);
+        const int maxch = (int)cdiv(nmax, kTreeChunk);
+        hipLaunchKernelGGL(k_tree_chunk_mean, dim3(grid1((int64_t)cnt * maxch * d)), dim3(256), 0, st,
+                           t->X.as<double>(), t->perm.as<int64_t>(), d, nb, ne, first, cnt, maxch, part.as<double>());
+        hipLaunchKernelGGL(k_tree_mean, dim3(grid1((int64_t)cnt * d)), dim3(256), 0, st, nb, ne, first, cnt, maxch, d,
+                           part.as<double>(), mu.as<double>());
+        hipLaunchKernelGGL(k_tree_chunk_scatter, dim3(grid1((int64_t)cnt * maxch * npair)), dim3(256), 0, st,
+                           t->X.as<double>(), t->perm.as<int64_t>(), d, nb, ne, first, cnt, maxch, mu.as<double>(),
+                           dpa.as<int16_t>(), dpc.as<int16_t>(), npair, part.as<double>());
+        hipLaunchKernelGGL(k_tree_axis, dim3(grid1(cnt, 64)), dim3(64), 0, st, nb, ne, first, cnt, maxch, d,
+                           dpa.as<int16_t>(), dpc.as<int16_t>(), npair, part.as<double>(), S.as<double>(),
+                           axis.as<double>());
+        const int bpn = (int)cdiv(nmax, 256);
+        hipLaunchKernelGGL(k_tree_keys, dim3(cnt * bpn), dim3(256), 0, st, t->X.as<double>(), t->perm.as<int64_t>(), d,
+                           nb, ne, first, bpn, mu.as<double>(), axis.as<double>(), key.as<double>(), kid.as<int64_t>());
+        const int tpn = (int)cdiv(nmax, 1024);
+        hipLaunchKernelGGL(k_tree_sort_tiles, dim3(cnt * tpn), dim3(512), 0, st, nb, ne, first, tpn, key.as<double>(),
+                           kid.as<int64_t>());
+        double *ka = key.as<double>(), *kb2 = key2.as<double>();
+        int64_t *ia = kid.as<int64_t>(), *ib = kid2.as<int64_t>();
+        for (int64_t w = 1024; w < nmax; w *= 2) {
+            hipLaunchKernelGGL(k_tree_merge, dim3(cnt * bpn), dim3(256), 0, st, nb, ne, first, bpn, w, ka, ia, kb2, ib);
+            std::swap(ka, kb2);
+            std::swap(ia, ib);
+        }
+        hipLaunchKernelGGL(k_copy_ids, dim3(grid1(N)), dim3(256), 0, st, ia, t->perm.as<int64_t>(), N);
+        HIP_TRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_gather_points, dim3(grid1(N * d)), dim3(256), 0, st, t->X.as<double>(),
+                       t->perm.as<int64_t>(), d, N, t->Xp.as<double>());
+    HIP_TRY(hipGetLastError());
+    int32_t hbad = 0;
+    HIP_TRY(hipMemcpyAsync(&hbad, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (hbad) return fail(ASKIT_ERR_ARG, "X has non-finite coordinates");
+    // skeleton arrays
+    ST_TRY(t->srank.alloc(sizeof(int32_t) * t->nnodes));
+    ST_TRY(t->trunc.alloc(sizeof(int32_t) * t->nnodes));
+    ST_TRY(t->skel.alloc(sizeof(int32_t) * t->nnodes * t->s));
+    ST_TRY(t->Pt.alloc(sizeof(double) * t->nnodes * t->cmax * t->s));
+    HIP_TRY(hipMemsetAsync(t->srank.p, 0, sizeof(int32_t) * t->nnodes, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    t->t_tree = ms_since(t0);
+    *out = t.release();
+    return ASKIT_OK;
+}
+
+askit_status askit_tree_depth(askit_tree t, int32_t *D) {
+    if (!t || !D) return fail(ASKIT_ERR_ARG, "NULL argument");
+    *D = t->D;
+    return ASKIT_OK;
+}
+
+askit_status askit_tree_perm(askit_tree t, int64_t *perm) {
+    if (!t || !perm) return fail(ASKIT_ERR_ARG, "NULL argument");
+    HIP_TRY(hipMemcpy(perm, t->perm.p, sizeof(int64_t) * t->N, hipMemcpyDeviceToDevice));
+    return ASKIT_OK;
+}
+
+void askit_tree_destroy(askit_tree t) { delete t; }
+
+// ---------------------------------------------------------------------------
+// skeletonization (Alg. 1), level by level from the leaves up
+// ---------------------------------------------------------------------------
+static askit_status skeletonize_impl(askit_tree *trees, int count, hipStream_t st) {
+    // heights from the leaves: all trees' nodes of one height in one launch
+    int Hmax = 0;
+    for (int i = 0; i < count; i++) Hmax = std::max(Hmax, trees[i]->D);
+    int nsamp_max = 0, cmax = 0, s = trees[0]->s, d = trees[0]->d;
+    for (int i = 0; i < count; i++) {
+        nsamp_max = std::max(nsamp_max, trees[i]->nsamp);
+        cmax = std::max(cmax, trees[i]->cmax);
+        if (trees[i]->s != s || trees[i]->d != d)
+            return fail(ASKIT_ERR_ARG, "batched trees must share rank and dimension");
+        if (!trees[i]->samp.p) ST_TRY(trees[i]->samp.alloc(sizeof(int32_t) * trees[i]->nnodes * trees[i]->nsamp));
+    }
+    // per height: task lists
+    std::vector<std::vector<SampTask>> samp(Hmax);
+    std::vector<std::vector<SkelTask>> sk(Hmax);
+    int64_t maxnodes = 0;
+    for (int hgt = 0; hgt < Hmax; hgt++) {
+        for (int i = 0; i < count; i++) {
+            askit_tree t = trees[i];
+            int l = t->D - hgt;
+            if (l < 1) continue;
+            for (int64_t id = t->first(l); id < t->first(l + 1); id++) {
+                SampTask a{};
+                a.b = t->nb[id];
+                a.e = t->ne[id];
+                a.N = t->N;
+                a.state = node_state(t->seed, t->problem, id);
+                a.out = t->samp.as<int32_t>() + id * t->nsamp;
+                samp[hgt].push_back(a);
+                SkelTask k{};
+                k.X = t->Xp.as<double>();
+                k.q = a.out;
+                k.nq = (int32_t)std::min<int64_t>(t->nsamp, t->N - (a.e - a.b));
+                k.leaf = (l == t->D);
+                k.b = a.b;
+                k.n = (int32_t)(a.e - a.b);
+                if (!k.leaf) {
+                    k.skl = t->skel.as<int32_t>() + (2 * id + 1) * t->s;
+                    k.skr = t->skel.as<int32_t>() + (2 * id + 2) * t->s;
+                    k.srl = t->srank.as<int32_t>() + 2 * id + 1;
+                    k.srr = t->srank.as<int32_t>() + 2 * id + 2;
+                }
+                k.skel = t->skel.as<int32_t>() + id * t->s;
+                k.sr = t->srank.as<int32_t>() + id;
+                k.trunc = t->trunc.as<int32_t>() + id;
+                k.Pt = t->Pt.as<double>() + id * (int64_t)t->cmax * t->s;
+                k.scale = -1.0 / (2.0 * t->h * t->h);
+                sk[hgt].push_back(k);
+            }
+        }
+        maxnodes = std::max<int64_t>(maxnodes, (int64_t)sk[hgt].size());
+    }
+    DBuf M, err, dsamp, dsk;
+    ST_TRY(M.alloc(sizeof(double) * std::max<int64_t>(1, maxnodes) * nsamp_max * cmax));
+    ST_TRY(err.alloc(sizeof(int32_t)));
+    HIP_TRY(hipMemsetAsync(err.p, 0, sizeof(int32_t), st));
+    for (int hgt = 0; hgt < Hmax; hgt++) {
+        if (sk[hgt].empty()) continue;
+        for (size_t j = 0; j < sk[hgt].size(); j++) sk[hgt][j].M = M.as<double>() + (int64_t)j * nsamp_max * cmax;
+        HIP_TRY(hipStreamSynchronize(st));
+        ST_TRY(upload(dsamp, samp[hgt]));
+        ST_TRY(upload(dsk, sk[hgt]));
+        const int n = (int)sk[hgt].size();
+        // all trees of a batch share nsamp (checked by the batched entry point)
+        HIP_TRY(timed("skel:k_sample", st, [&] {
+            hipLaunchKernelGGL(k_sample, dim3(n), dim3(64), 0, st, dsamp.as<SampTask>(), nsamp_max, err.as<int32_t>());
+            return hipGetLastError();
+        }));
+        const int rt = (int)cdiv(nsamp_max, 64);
+        HIP_TRY(timed("skel:k_sample_block", st, [&] {
+            hipLaunchKernelGGL(k_sample_block, dim3(n * rt), dim3(256), 0, st, dsk.as<SkelTask>(), rt, nsamp_max, d);
+            return hipGetLastError();
+        }));
+        HIP_TRY(timed("skel:k_qrcp", st, [&] {
+            hipLaunchKernelGGL(k_qrcp, dim3(n), dim3(512), 0, st, dsk.as<SkelTask>(), s, cmax, nsamp_max);
+            return hipGetLastError();
+        }));
+    }
+    int32_t herr = 0;
+    HIP_TRY(hipMemcpyAsync(&herr, err.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (herr) return fail(ASKIT_ERR_HIP, "row sampling did not terminate");
+    for (int i = 0; i < count; i++) trees[i]->skel_ok = true;
+    return ASKIT_OK;
+}
+
+askit_status askit_skeletonize(askit_tree t, void *stream) {
+    if (!t) return fail(ASKIT_ERR_ARG, "NULL tree");
+    if (t->refs) return fail(ASKIT_ERR_STATE, "destroy the factors of this tree before re-skeletonizing");
+    auto t0 = std::chrono::steady_clock::now();
+    ST_TRY(skeletonize_impl(&t, 1, (hipStream_t)stream));
+    t->t_skel = ms_since(t0);
+    return ASKIT_OK;
+}
+
+askit_status askit_skeletons_export(askit_tree t, int32_t *ids, double *P, int32_t *sizes) {
+    if (!t || !ids || !P || !sizes) return fail(ASKIT_ERR_ARG, "NULL argument");
+    if (!t->skel_ok) return fail(ASKIT_ERR_STATE, "tree not skeletonized");
+    std::vector<int32_t> sr(t->nnodes);
+    HIP_TRY(hipMemcpy(ids, t->skel.p, sizeof(int32_t) * t->nnodes * t->s, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(sr.data(), t->srank.p, sizeof(int32_t) * t->nnodes, hipMemcpyDeviceToHost));
+    std::vector<double> Pt((size_t)t->nnodes * t->cmax * t->s);
+    HIP_TRY(hipMemcpy(Pt.data(), t->Pt.p, sizeof(double) * Pt.size(), hipMemcpyDeviceToHost));
+    // P_{alpha~ C} (s_alpha x |C|, compact columns) from the padded transposed rows
+    for (int64_t id = 0; id < t->nnodes; id++) {
+        sizes[2 * id] = id ? sr[id] : 0;
+        int nc = 0;
+        int lvl = 0;
+        while (((int64_t)2 << lvl) - 1 <= id) lvl++;
+        if (id == 0) {
+            sizes[1] = 0;
+            continue;
+        }
+        bool leaf = (lvl == t->D);
+        int sl = leaf ? 0 : sr[2 * id + 1];
+        nc = leaf ? (int)(t->ne[id] - t->nb[id]) : sl + sr[2 * id + 2];
+        sizes[2 * id + 1] = nc;
+        double *dst = P + id * (int64_t)t->s * t->cmax;
+        for (int k = 0; k < sr[id]; k++)
+            for (int c = 0; c < nc; c++) {
+                int row = leaf ? c : (c < sl ? c : t->s + (c - sl));
+                dst[(int64_t)k * nc + c] = Pt[(size_t)id * t->cmax * t->s + (size_t)row * t->s + k];
+            }
+    }
+    return ASKIT_OK;
+}
+
+askit_status askit_skeletons_import(askit_tree t, const int32_t *ids, const double *P, const int32_t *sizes) {
+    if (!t || !ids || !P || !sizes) return fail(ASKIT_ERR_ARG, "NULL argument");
+    if (t->refs) return fail(ASKIT_ERR_STATE, "destroy the factors of this tree first");
+    std::vector<int32_t> sr(t->nnodes, 0), sk((size_t)t->nnodes * t->s, -1), tr(t->nnodes, 0);
+    std::vector<double> Pt((size_t)t->nnodes * t->cmax * t->s, 0.0);
+    for (int64_t id = 1; id < t->nnodes; id++) {
+        int lvl = 0;
+        while (((int64_t)2 << lvl) - 1 <= id) lvl++;
+        bool leaf = (lvl == t->D);
+        int r = sizes[2 * id], nc = sizes[2 * id + 1];
+        int want_nc = leaf ? (int)(t->ne[id] - t->nb[id]) : sizes[2 * (2 * id + 1)] + sizes[2 * (2 * id + 2)];
+        if (r < 1 || r > t->s || nc != want_nc) return fail(ASKIT_ERR_ARG, "inconsistent skeleton sizes");
+        sr[id] = r;
+        int sl = leaf ? 0 : sizes[2 * (2 * id + 1)];
+        for (int k = 0; k < r; k++) {
+            int32_t p = ids[id * t->s + k];
+            if (p < t->nb[id] || p >= t->ne[id]) return fail(ASKIT_ERR_ARG, "skeleton point outside its node");
+            sk[(size_t)id * t->s + k] = p;
+        }
+        const double *src = P + id * (int64_t)t->s * t->cmax;
+        for (int k = 0; k < r; k++)
+            for (int c = 0; c < nc; c++) {
+                int row = leaf ? c : (c < sl ? c : t->s + (c - sl));
+                Pt[(size_t)id * t->cmax * t->s + (size_t)row * t->s + k] = src[(int64_t)k * nc + c];
+            }
+    }
+    HIP_TRY(hipMemcpy(t->srank.p, sr.data(), sizeof(int32_t) * t->nnodes, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(t->trunc.p, tr.data(), sizeof(int32_t) * t->nnodes, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(t->skel.p, sk.data(), sizeof(int32_t) * sk.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(t->Pt.p, Pt.data(), sizeof(double) * Pt.size(), hipMemcpyHostToDevice));
+    t->skel_ok = true;
+    return ASKIT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// factorization (Alg. 2)
+// ---------------------------------------------------------------------------
+static const int64_t kChunk = 4096;  // contraction chunk of the split products
+
+static askit_status factor_plan(askit_factor f, Plan &P) {
+    askit_tree t = f->t;
+    const int s = t->s, D = t->D, d = t->d, s2 = 2 * s;
+    const Prec pr = f->prec;
+    const int el = (int)f->elem();
+    const int64_t leaf0 = t->first(D);
+    // leaves: lambda I + K_aa, LU, Phat = A^{-1} P_{alpha alpha~}
+    {
+        std::vector<LeafTask> lt;
+        std::vector<LuTask> lu, rs;
+        std::vector<CopyTask> cp;
+        for (int64_t id = leaf0; id < t->nnodes; id++) {
+            LeafTask a{};
+            a.X = t->Xp.as<double>();
+            a.b = t->nb[id];
+            a.n = (int32_t)(t->ne[id] - t->nb[id]);
+            a.lda = t->mmax;
+            a.A = f->lu_of(id);
+            a.scale = -1.0 / (2.0 * t->h * t->h);
+            a.lambda = f->lambda;
+            lt.push_back(a);
+            LuTask u{};
+            u.A = a.A;
+            u.piv = f->piv_of(id);
+            u.dinv = f->dinv_of(id);
+            u.n = a.n;
+            u.lda = t->mmax;
+            u.ratio = f->ratio.as<double>() + id;
+            lu.push_back(u);
+            if (D > 0) {
+                CopyTask c{};
+                c.src = t->Pt.as<double>() + id * (int64_t)t->cmax * s;
+                c.dst = (char *)f->ph(D) + t->nb[id] * s * el;
+                c.sld = s;
+                c.dld = s;
+                c.rows = a.n;
+                c.cols = s;
+                cp.push_back(c);
+                u.B = c.dst;
+                u.ldb = s;
+                rs.push_back(u);
+            }
+        }
+        DBuf *b = P.own();
+        ST_TRY(upload(*b, lt));
+        const LeafTask *lp = b->as<LeafTask>();
+        const int nl = (int)lt.size(), mm = t->mmax;
+        P.add("k_leaf_block", [=](hipStream_t st, int) -> hipError_t {
+            hipLaunchKernelGGL(k_leaf_block, dim3(nl * mm), dim3(256), 0, st, lp, mm, d);
+            return hipGetLastError();
+        });
+        ST_TRY(lu_commit(P, lu));
+        ST_TRY(copy_commit(P, cp, P64, pr, t->mmax, s));
+        ST_TRY(getrs_commit(P, rs, pr, false, s));
+    }
+    // internal levels, bottom-up
+    for (int l = D - 1; l >= 0; l--) {
+        const int64_t f0 = t->first(l), cnt = (int64_t)1 << l;
+        double *Z0 = f->lu_of(f0);
+        P.add("k_identity", [=](hipStream_t st, int) -> hipError_t {
+            hipLaunchKernelGGL(k_identity, dim3(grid1((int64_t)s2 * s2 * cnt)), dim3(256), 0, st, Z0, s2,
+                               (int64_t)s2 * s2, (int)cnt);
+            return hipGetLastError();
+        });
+        KmmBuild kb;
+        kb.tc = s >= 128 ? 128 : (s >= 64 ? 64 : 16);
+        kb.out_size = 8;
+        std::vector<LuTask> lu, rs;
+        std::vector<CopyTask> cp, cp32;
+        GmmBuild gb;
+        gb.tc = kb.tc;
+        gb.elem = el;
+        for (int64_t id = f0; id < f0 + cnt; id++) {
+            const int64_t lc = 2 * id + 1, rc = 2 * id + 2;
+            double *Z = f->lu_of(id);
+            for (int side = 0; side < 2; side++) {
+                const int64_t a = side ? rc : lc, o = side ? lc : rc;  // skeleton of a vs points of o
+                KmmTask k{};
+                k.X = t->Xp.as<double>();
+                k.R.idx = t->skel.as<int32_t>() + a * s;
+                k.R.cnt = t->srank.as<int32_t>() + a;
+                k.R.n = s;
+                k.S.base = t->nb[o];
+                k.S.n = (int32_t)(t->ne[o] - t->nb[o]);
+                k.B = (const char *)f->ph(l + 1) + t->nb[o] * s * el;
+                k.ldb = s;
+                k.C = side ? Z + s : Z + (int64_t)s * s2;
+                k.crs = 1;
+                k.ccs = s2;
+                k.scale = -1.0 / (2.0 * t->h * t->h);
+                k.op = OP_STORE;
+                k.rcap = s;
+                kmm_add(kb, k, k.S.n, s, kChunk, el, f->ws.as<char>());
+            }
+            LuTask u{};
+            u.A = Z;
+            u.piv = f->piv_of(id);
+            u.dinv = f->dinv_of(id);
+            u.n = s2;
+            u.lda = s2;
+            u.ratio = f->ratio.as<double>() + id;
+            lu.push_back(u);
+            if (l >= 1) {
+                double *xc = f->Xc.as<double>() + (id - f0) * (int64_t)s2 * s;
+                CopyTask c{};
+                c.src = t->Pt.as<double>() + id * (int64_t)t->cmax * s;
+                c.dst = xc;
+                c.sld = s;
+                c.dld = s;
+                c.rows = s2;
+                c.cols = s;
+                cp.push_back(c);
+                u.B = xc;
+                u.ldb = s;
+                rs.push_back(u);
+                const void *xb = xc;
+                if (pr == P32) {
+                    float *xf = f->Xcf.as<float>() + (id - f0) * (int64_t)s2 * s;
+                    CopyTask c2 = c;
+                    c2.src = xc;
+                    c2.dst = xf;
+                    cp32.push_back(c2);
+                    xb = xf;
+                }
+                for (int side = 0; side < 2; side++) {
+                    const int64_t ch = side ? rc : lc;
+                    GmmTask g{};
+                    g.A = (const char *)f->ph(l + 1) + t->nb[ch] * s * el;
+                    g.ars = s;
+                    g.acs = 1;
+                    g.B = (const char *)xb + (int64_t)side * s * s * el;
+                    g.brs = s;
+                    g.bcs = 1;
+                    g.C = (char *)f->ph(l) + t->nb[ch] * s * el;
+                    g.crs = s;
+                    g.ccs = 1;
+                    g.rows = (int32_t)(t->ne[ch] - t->nb[ch]);
+                    g.kdim = s;
+                    g.op = OP_STORE;
+                    gmm_add(gb, g, s, 1 << 30, nullptr);
+                }
+            }
+        }
+        if (kb.ws_elems * 8 > (int64_t)f->ws.bytes) return fail(ASKIT_ERR_STATE, "internal: workspace too small");
+        ST_TRY(kmm_commit(P, kb, pr, P64, d, s));
+        ST_TRY(lu_commit(P, lu));
+        ST_TRY(copy_commit(P, cp, P64, P64, s2, s));
+        ST_TRY(getrs_commit(P, rs, P64, false, s));
+        if (pr == P32) ST_TRY(copy_commit(P, cp32, P64, P32, s2, s));
+        ST_TRY(gmm_commit(P, gb, pr, 0));
+    }
+    return ASKIT_OK;
+}
+
+// partial-sum workspace needed by the split products of one level
+static int64_t split_ws_elems(askit_tree t, int ncol, int64_t KC) {
+    int64_t worst = 0;
+    for (int l = 0; l < t->D; l++) {
+        int64_t tot = 0;
+        for (int64_t id = t->first(l); id < t->first(l + 1); id++)
+            for (int side = 0; side < 2; side++) {
+                int64_t o = 2 * id + 1 + (side ? 0 : 1);
+                int64_t n = t->ne[o] - t->nb[o];
+                int64_t nch = cdiv(n, KC);
+                if (nch > 1) tot += nch * (int64_t)t->s * ncol;
+            }
+        worst = std::max(worst, tot);
+    }
+    return worst;
+}
+
+static askit_status factorize_impl(askit_tree t, double lambda, int precision, hipStream_t st, askit_factor *out) {
+    std::unique_ptr<askit_factor_s> f(new askit_factor_s());
+    f->t = t;
+    f->lambda = lambda;
+    f->prec = precision == ASKIT_MIXED ? P32 : P64;
+    f->max_refine = f->prec == P32 ? 10 : 0;
+    const int s = t->s, D = t->D, s2 = 2 * s;
+    const int64_t leaf0 = t->first(D), nleaf = (int64_t)1 << D;
+    f->leafLU = 0;
+    f->zLU = nleaf * (int64_t)t->mmax * t->mmax;
+    ST_TRY(f->LU.alloc(sizeof(double) * (f->zLU + leaf0 * (int64_t)s2 * s2)));
+    ST_TRY(f->piv.alloc(sizeof(int32_t) * (nleaf * t->mmax + leaf0 * s2)));
+    ST_TRY(f->ratio.alloc(sizeof(double) * t->nnodes));
+    ST_TRY(f->dinv.alloc(sizeof(double) * 512 * (nleaf * ((t->mmax + 15) / 16) + leaf0 * ((s2 + 15) / 16))));
+    for (int l = 1; l <= D; l++) {
+        f->PH.emplace_back(new DBuf());
+        ST_TRY(f->PH.back()->alloc(f->elem() * t->N * s));
+    }
+    const int64_t lvl_max = D >= 2 ? ((int64_t)1 << (D - 1)) : 1;  // nodes of the widest level with a telescoping step
+    ST_TRY(f->Xc.alloc(sizeof(double) * lvl_max * s2 * s));
+    if (f->prec == P32) ST_TRY(f->Xcf.alloc(sizeof(float) * lvl_max * s2 * s));
+    ST_TRY(f->ws.alloc(sizeof(double) * std::max<int64_t>(1, split_ws_elems(t, s, kChunk))));
+    Plan P;
+    P.tag = "factor";
+    ST_TRY(factor_plan(f.get(), P));
+    HIP_TRY(P.run(st, s));
+    std::vector<double> ratio(t->nnodes);
+    HIP_TRY(hipMemcpyAsync(ratio.data(), f->ratio.p, sizeof(double) * t->nnodes, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    f->min_ratio = 1.0;
+    for (int64_t id = 0; id < t->nnodes; id++) {
+        if (ratio[id] < f->min_ratio) {
+            f->min_ratio = ratio[id];
+            f->min_node = (int)id;
+        }
+    }
+    t->refs++;
+    *out = f.release();
+    if ((*out)->min_ratio == 0.0) return fail(ASKIT_ERR_SINGULAR, "exactly singular pivot in a leaf or reduced system");
+    if ((*out)->min_ratio < 1e-12) return fail(ASKIT_WARN_ILLCOND, "pivot ratio below 1e-12: factorization unstable");
+    return ASKIT_OK;
+}
+
+askit_status askit_factorize(askit_tree t, double lambda, int32_t precision, void *stream, askit_factor *out) {
+    if (!t || !out) return fail(ASKIT_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    if (!t->skel_ok) return fail(ASKIT_ERR_STATE, "skeletonize the tree first");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(ASKIT_ERR_ARG, "lambda must be >= 0 and finite");
+    if (precision != ASKIT_FP64 && precision != ASKIT_MIXED) return fail(ASKIT_ERR_ARG, "unknown precision");
+    auto t0 = std::chrono::steady_clock::now();
+    askit_status st = factorize_impl(t, lambda, precision, (hipStream_t)stream, out);
+    if (*out) (*out)->t_factor = ms_since(t0);
+    return st;
+}
+
+void askit_factor_destroy(askit_factor f) {
+    if (!f) return;
+    f->t->refs--;
+    delete f;
+}
+
+askit_status askit_factor_pivot_ratio(askit_factor f, double *ratio, int32_t *node) {
+    if (!f || !ratio || !node) return fail(ASKIT_ERR_ARG, "NULL argument");
+    *ratio = f->min_ratio;
+    *node = f->min_node;
+    return ASKIT_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// solves and matvec: plans per right-hand-side capacity
+// ---------------------------------------------------------------------------
+static askit_status ensure_cap(askit_factor f, int nrhs) {
+    if (nrhs <= f->cap) return ASKIT_OK;
+    askit_tree t = f->t;
+    int cap = std::max(nrhs, 1);
+    cap = ((cap + 15) / 16) * 16;
+    const int s = t->s;
+    const size_t el = f->elem();
+    ST_TRY(f->W.alloc(el * t->N * cap));
+    ST_TRY(f->TB.alloc(el * std::max<int64_t>(1, t->first(t->D)) * 2 * s * cap));
+    ST_TRY(f->WX.alloc(sizeof(double) * t->N * cap));
+    ST_TRY(f->WY.alloc(sizeof(double) * t->N * cap));
+    ST_TRY(f->CB.alloc(sizeof(double) * t->nnodes * s * cap));
+    // split-product partials: the larger of the solve (rows s) and transpose
+    // solve (rows s) needs, in doubles
+    ST_TRY(f->wsS.alloc(sizeof(double) * std::max<int64_t>(1, split_ws_elems(t, cap, kChunk))));
+    f->cap = cap;
+    f->solve_plan.reset();
+    f->solvet_plan.reset();
+    f->mv_plan[0].reset();
+    f->mv_plan[1].reset();
+    return ASKIT_OK;
+}
+
+static askit_status solve_plan(askit_factor f, Plan &P) {
+    askit_tree t = f->t;
+    const int s = t->s, D = t->D, d = t->d, cap = f->cap, s2 = 2 * s;
+    const Prec pr = f->prec;
+    const int el = (int)f->elem();
+    char *W = f->W.as<char>();
+    std::vector<LuTask> leaves;
+    for (int64_t id = t->first(D); id < t->nnodes; id++) {
+        LuTask u{};
+        u.A = f->lu_of(id);
+        u.piv = f->piv_of(id);
+        u.dinv = f->dinv_of(id);
+        u.n = (int32_t)(t->ne[id] - t->nb[id]);
+        u.lda = t->mmax;
+        u.B = W + t->nb[id] * cap * el;
+        u.ldb = cap;
+        leaves.push_back(u);
+    }
+    ST_TRY(getrs_commit(P, leaves, pr, false, 0));
+    for (int l = D - 1; l >= 0; l--) {
+        KmmBuild kb;
+        kb.tc = cap >= 128 ? 128 : (cap >= 64 ? 64 : 16);
+        kb.out_size = el;
+        GmmBuild gb;
+        gb.tc = kb.tc;
+        gb.elem = el;
+        std::vector<LuTask> zs;
+        for (int64_t id = t->first(l); id < t->first(l + 1); id++) {
+            const int64_t lc = 2 * id + 1, rc = 2 * id + 2;
+            char *tb = f->TB.as<char>() + id * (int64_t)s2 * cap * el;
+            for (int side = 0; side < 2; side++) {
+                const int64_t a = side ? rc : lc, o = side ? lc : rc;
+                KmmTask k{};
+                k.X = t->Xp.as<double>();
+                k.R.idx = t->skel.as<int32_t>() + a * s;
+                k.R.cnt = t->srank.as<int32_t>() + a;
+                k.R.n = s;
+                k.S.base = t->nb[o];
+                k.S.n = (int32_t)(t->ne[o] - t->nb[o]);
+                k.B = W + t->nb[o] * cap * el;
+                k.ldb = cap;
+                k.C = tb + (int64_t)side * s * cap * el;
+                k.crs = cap;
+                k.ccs = 1;
+                k.scale = -1.0 / (2.0 * t->h * t->h);
+                k.op = OP_STORE;
+                k.rcap = s;
+                kmm_add(kb, k, k.S.n, cap, kChunk, el, f->wsS.as<char>());
+            }
+            LuTask u{};
+            u.A = f->lu_of(id);
+            u.piv = f->piv_of(id);
+            u.dinv = f->dinv_of(id);
+            u.n = s2;
+            u.lda = s2;
+            u.B = tb;
+            u.ldb = cap;
+            zs.push_back(u);
+            for (int side = 0; side < 2; side++) {
+                const int64_t ch = side ? rc : lc;
+                GmmTask g{};
+                g.A = (const char *)f->ph(l + 1) + t->nb[ch] * s * el;
+                g.ars = s;
+                g.acs = 1;
+                g.B = tb + (int64_t)side * s * cap * el;
+                g.brs = cap;
+                g.bcs = 1;
+                g.C = W + t->nb[ch] * cap * el;
+                g.crs = cap;
+                g.ccs = 1;
+                g.rows = (int32_t)(t->ne[ch] - t->nb[ch]);
+                g.kdim = s;
+                g.op = OP_SUB;
+                gmm_add(gb, g, cap, 1 << 30, nullptr);
+            }
+        }
+        ST_TRY(kmm_commit(P, kb, pr, pr, d, s));
+        ST_TRY(getrs_commit(P, zs, pr, false, 0));
+        ST_TRY(gmm_commit(P, gb, pr, 0));
+    }
+    return ASKIT_OK;
+}
+
+static askit_status solvet_plan(askit_factor f, Plan &P) {
+    askit_tree t = f->t;
+    const int s = t->s, D = t->D, d = t->d, cap = f->cap, s2 = 2 * s;
+    const Prec pr = f->prec;
+    const int el = (int)f->elem();
+    char *W = f->W.as<char>();
+    for (int l = 0; l < D; l++) {
+        GmmBuild gb;
+        gb.tc = cap >= 128 ? 128 : (cap >= 64 ? 64 : 16);
+        gb.elem = el;
+        KmmBuild kb;
+        kb.tc = gb.tc;
+        kb.out_size = el;
+        std::vector<LuTask> zs;
+        for (int64_t id = t->first(l); id < t->first(l + 1); id++) {
+            const int64_t lc = 2 * id + 1, rc = 2 * id + 2;
+            char *tb = f->TB.as<char>() + id * (int64_t)s2 * cap * el;
+            for (int side = 0; side < 2; side++) {  // gt = [Phat_l^T w_l ; Phat_r^T w_r]
+                const int64_t ch = side ? rc : lc;
+                GmmTask g{};
+                g.A = (const char *)f->ph(l + 1) + t->nb[ch] * s * el;
+                g.ars = 1;
+                g.acs = s;
+                g.B = W + t->nb[ch] * cap * el;
+                g.brs = cap;
+                g.bcs = 1;
+                g.C = tb + (int64_t)side * s * cap * el;
+                g.crs = cap;
+                g.ccs = 1;
+                g.rows = s;
+                g.kdim = (int32_t)(t->ne[ch] - t->nb[ch]);
+                g.op = OP_STORE;
+                gmm_add(gb, g, cap, kChunk, f->wsS.as<char>());
+            }
+            LuTask u{};
+            u.A = f->lu_of(id);
+            u.piv = f->piv_of(id);
+            u.dinv = f->dinv_of(id);
+            u.n = s2;
+            u.lda = s2;
+            u.B = tb;
+            u.ldb = cap;
+            zs.push_back(u);
+            for (int side = 0; side < 2; side++) {  // w_l -= K_{r~ l}^T y_bot, w_r -= K_{l~ r}^T y_top
+                const int64_t ch = side ? rc : lc, a = side ? lc : rc;
+                KmmTask k{};
+                k.X = t->Xp.as<double>();
+                k.R.base = t->nb[ch];
+                k.R.n = (int32_t)(t->ne[ch] - t->nb[ch]);
+                k.S.idx = t->skel.as<int32_t>() + a * s;
+                k.S.cnt = t->srank.as<int32_t>() + a;
+                k.S.n = s;
+                k.B = tb + (int64_t)(side ? 0 : s) * cap * el;
+                k.ldb = cap;
+                k.C = W + t->nb[ch] * cap * el;
+                k.crs = cap;
+                k.ccs = 1;
+                k.scale = -1.0 / (2.0 * t->h * t->h);
+                k.op = OP_SUB;
+                k.rcap = k.R.n;
+                kmm_add(kb, k, s, cap, 1 << 30, el, nullptr);
+            }
+        }
+        ST_TRY(gmm_commit(P, gb, pr, s));
+        ST_TRY(getrs_commit(P, zs, pr, true, 0));
+        ST_TRY(kmm_commit(P, kb, pr, pr, d, 0));
+    }
+    std::vector<LuTask> leaves;
+    for (int64_t id = t->first(D); id < t->nnodes; id++) {
+        LuTask u{};
+        u.A = f->lu_of(id);
+        u.piv = f->piv_of(id);
+        u.dinv = f->dinv_of(id);
+        u.n = (int32_t)(t->ne[id] - t->nb[id]);
+        u.lda = t->mmax;
+        u.B = W + t->nb[id] * cap * el;
+        u.ldb = cap;
+        leaves.push_back(u);
+    }
+    ST_TRY(getrs_commit(P, leaves, pr, true, 0));
+    return ASKIT_OK;
+}
+
+// (lambda I + Ktilde) x or dKtilde/dh x in FP64 (WX -> WY)
+static askit_status matvec_plan(askit_factor f, int which, Plan &P) {
+    askit_tree t = f->t;
+    const int s = t->s, D = t->D, d = t->d, cap = f->cap;
+    double *WX = f->WX.as<double>(), *WY = f->WY.as<double>(), *CB = f->CB.as<double>();
+    const double scale = -1.0 / (2.0 * t->h * t->h);
+    {  // leaves: exact diagonal blocks
+        KmmBuild kb;
+        kb.tc = cap >= 128 ? 128 : (cap >= 64 ? 64 : 16);
+        for (int64_t id = t->first(D); id < t->nnodes; id++) {
+            KmmTask k{};
+            k.X = t->Xp.as<double>();
+            k.R.base = t->nb[id];
+            k.R.n = (int32_t)(t->ne[id] - t->nb[id]);
+            k.S = k.R;
+            k.B = WX + t->nb[id] * cap;
+            k.ldb = cap;
+            k.C = WY + t->nb[id] * cap;
+            k.crs = cap;
+            k.ccs = 1;
+            k.scale = scale;
+            k.hinv = 1.0 / t->h;
+            k.which = which;
+            k.op = OP_STORE;
+            k.rcap = k.R.n;
+            kmm_add(kb, k, k.S.n, cap, 1 << 30, 8, nullptr);
+        }
+        ST_TRY(kmm_commit(P, kb, P64, P64, d, 0));
+        if (!which) {
+            const double lam = f->lambda;
+            const int64_t N = t->N;
+            P.add("k_axpy", [=](hipStream_t st, int ncol) -> hipError_t {
+                hipLaunchKernelGGL(k_axpy<double>, dim3(grid1(N * ncol)), dim3(256), 0, st, WY, WX, (int64_t)cap, N,
+                                   ncol, lam);
+                return hipGetLastError();
+            });
+        }
+    }
+    if (D == 0) return ASKIT_OK;
+    // skeleton potentials c_l = K_{l~ r} x_r, c_r = K_{r~ l} x_l, one launch per level
+    for (int l = 0; l < D; l++) {
+        KmmBuild kl;
+        kl.tc = cap >= 128 ? 128 : (cap >= 64 ? 64 : 16);
+        for (int64_t id = t->first(l); id < t->first(l + 1); id++) {
+            const int64_t lc = 2 * id + 1, rc = 2 * id + 2;
+            for (int side = 0; side < 2; side++) {
+                const int64_t a = side ? rc : lc, o = side ? lc : rc;
+                KmmTask k{};
+                k.X = t->Xp.as<double>();
+                k.R.idx = t->skel.as<int32_t>() + a * s;
+                k.R.cnt = t->srank.as<int32_t>() + a;
+                k.R.n = s;
+                k.S.base = t->nb[o];
+                k.S.n = (int32_t)(t->ne[o] - t->nb[o]);
+                k.B = WX + t->nb[o] * cap;
+                k.ldb = cap;
+                k.C = CB + a * (int64_t)s * cap;
+                k.crs = cap;
+                k.ccs = 1;
+                k.scale = scale;
+                k.hinv = 1.0 / t->h;
+                k.which = which;
+                k.op = OP_STORE;
+                k.rcap = s;
+                kmm_add(kl, k, k.S.n, cap, kChunk, 8, f->wsS.as<char>());
+            }
+        }
+        ST_TRY(kmm_commit(P, kl, P64, P64, d, s));
+    }
+    // push down: [c_l; c_r] += P_c c_beta, levels 1 .. D-1 in order
+    for (int l = 1; l < D; l++) {
+        GmmBuild gb;
+        gb.tc = cap >= 128 ? 128 : (cap >= 64 ? 64 : 16);
+        for (int64_t id = t->first(l); id < t->first(l + 1); id++) {
+            for (int side = 0; side < 2; side++) {
+                GmmTask g{};
+                g.A = t->Pt.as<double>() + id * (int64_t)t->cmax * s + (int64_t)side * s * s;
+                g.ars = s;
+                g.acs = 1;
+                g.B = CB + id * (int64_t)s * cap;
+                g.brs = cap;
+                g.bcs = 1;
+                g.C = CB + (2 * id + 1 + side) * (int64_t)s * cap;
+                g.crs = cap;
+                g.ccs = 1;
+                g.rows = s;
+                g.kdim = s;
+                g.op = OP_ADD;
+                gmm_add(gb, g, cap, 1 << 30, nullptr);
+            }
+        }
+        ST_TRY(gmm_commit(P, gb, P64, 0));
+    }
+    {  // leaves: y_a += P_{alpha alpha~} c_a
+        GmmBuild gb;
+        gb.tc = cap >= 128 ? 128 : (cap >= 64 ? 64 : 16);
+        for (int64_t id = t->first(D); id < t->nnodes; id++) {
+            GmmTask g{};
+            g.A = t->Pt.as<double>() + id * (int64_t)t->cmax * s;
+            g.ars = s;
+            g.acs = 1;
+            g.B = CB + id * (int64_t)s * cap;
+            g.brs = cap;
+            g.bcs = 1;
+            g.C = WY + t->nb[id] * cap;
+            g.crs = cap;
+            g.ccs = 1;
+            g.rows = (int32_t)(t->ne[id] - t->nb[id]);
+            g.kdim = s;
+            g.op = OP_ADD;
+            gmm_add(gb, g, cap, 1 << 30, nullptr);
+        }
+        ST_TRY(gmm_commit(P, gb, P64, 0));
+    }
+    return ASKIT_OK;
+}
+
+static askit_status check_solve_args(askit_factor f, const double *B, int64_t ldb, int32_t nrhs, double *X,
+                                     int64_t ldx) {
+    if (!f) return fail(ASKIT_ERR_ARG, "NULL factor");
+    if (!B || !X) return fail(ASKIT_ERR_ARG, "NULL array");
+    if (nrhs < 1) return fail(ASKIT_ERR_ARG, "nrhs must be >= 1");
+    if (ldb < f->t->N || ldx < f->t->N) return fail(ASKIT_ERR_ARG, "leading dimension smaller than N");
+    return ASKIT_OK;
+}
+
+// one application of the stored factors: X = A^{-1} B (or A^{-T} B)
+static askit_status apply_inverse(askit_factor f, const double *B, int64_t ldb, int nrhs, double *X, int64_t ldx,
+                                  bool trans, hipStream_t st) {
+    askit_tree t = f->t;
+    ST_TRY(ensure_cap(f, nrhs));
+    std::unique_ptr<Plan> &pl = trans ? f->solvet_plan : f->solve_plan;
+    if (!pl) {
+        pl.reset(new Plan());
+        pl->tag = trans ? "solve_t" : "solve";
+        ST_TRY(trans ? solvet_plan(f, *pl) : solve_plan(f, *pl));
+    }
+    const int64_t N = t->N;
+    if (f->prec == P64)
+        hipLaunchKernelGGL(k_gather_rhs<double>, dim3(grid1(N * nrhs)), dim3(256), 0, st, B, ldb,
+                           t->perm.as<int64_t>(), N, nrhs, f->W.as<double>(), (int64_t)f->cap);
+    else
+        hipLaunchKernelGGL(k_gather_rhs<float>, dim3(grid1(N * nrhs)), dim3(256), 0, st, B, ldb,
+                           t->perm.as<int64_t>(), N, nrhs, f->W.as<float>(), (int64_t)f->cap);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(pl->run(st, nrhs));
+    if (f->prec == P64)
+        hipLaunchKernelGGL(k_scatter_rhs<double>, dim3(grid1(N * nrhs)), dim3(256), 0, st, f->W.as<double>(),
+                           (int64_t)f->cap, t->perm.as<int64_t>(), N, nrhs, X, ldx, 0);
+    else
+        hipLaunchKernelGGL(k_scatter_rhs<float>, dim3(grid1(N * nrhs)), dim3(256), 0, st, f->W.as<float>(),
+                           (int64_t)f->cap, t->perm.as<int64_t>(), N, nrhs, X, ldx, 0);
+    HIP_TRY(hipGetLastError());
+    return ASKIT_OK;
+}
+
+static askit_status matvec_impl(askit_factor f, int which, const double *Xin, int64_t ldx, int nrhs, double *Y,
+                                int64_t ldy, hipStream_t st) {
+    askit_tree t = f->t;
+    ST_TRY(ensure_cap(f, nrhs));
+    if (!f->mv_plan[which]) {
+        f->mv_plan[which].reset(new Plan());
+        f->mv_plan[which]->tag = which ? "matvec_dh" : "matvec";
+        ST_TRY(matvec_plan(f, which, *f->mv_plan[which]));
+    }
+    const int64_t N = t->N;
+    hipLaunchKernelGGL(k_gather_rhs<double>, dim3(grid1(N * nrhs)), dim3(256), 0, st, Xin, ldx,
+                       t->perm.as<int64_t>(), N, nrhs, f->WX.as<double>(), (int64_t)f->cap);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(f->mv_plan[which]->run(st, nrhs));
+    hipLaunchKernelGGL(k_scatter_rhs<double>, dim3(grid1(N * nrhs)), dim3(256), 0, st, f->WY.as<double>(),
+                       (int64_t)f->cap, t->perm.as<int64_t>(), N, nrhs, Y, ldy, 0);
+    HIP_TRY(hipGetLastError());
+    return ASKIT_OK;
+}
+
+// max over columns of |U_c| / |V_c| (two-norms)
+static askit_status colratio(askit_factor f, const double *U, int64_t ldu, const double *V, int64_t ldv, int nrhs,
+                             hipStream_t st, double *out) {
+    const int64_t N = f->t->N;
+    if (f->nrm.bytes < sizeof(double) * 2 * nrhs) ST_TRY(f->nrm.alloc(sizeof(double) * 2 * nrhs));
+    hipLaunchKernelGGL(k_zero, dim3(grid1(2 * nrhs)), dim3(256), 0, st, f->nrm.as<double>(), (int64_t)2 * nrhs);
+    int gx = (int)std::min<int64_t>(1024, cdiv(N, 256));
+    hipLaunchKernelGGL(k_colnorms, dim3(gx, nrhs), dim3(256), 0, st, U, ldu, V, ldv, N, nrhs, f->nrm.as<double>());
+    HIP_TRY(hipGetLastError());
+    std::vector<double> h(2 * nrhs);
+    HIP_TRY(hipMemcpyAsync(h.data(), f->nrm.p, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    double worst = 0.0;
+    for (int c = 0; c < nrhs; c++) {
+        double r = h[nrhs + c] > 0 ? std::sqrt(h[c] / h[nrhs + c]) : (h[c] > 0 ? INFINITY : 0.0);
+        worst = std::max(worst, r);
+    }
+    *out = worst;
+    return ASKIT_OK;
+}
+
+extern "C" {
+
+askit_status askit_solve(askit_factor f, const double *B, int64_t ldb, int32_t nrhs, double *X, int64_t ldx,
+                         void *stream) {
+    ST_TRY(check_solve_args(f, B, ldb, nrhs, X, ldx));
+    hipStream_t st = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    f->info = askit_solve_info{};
+    if (f->max_refine == 0) {
+        ST_TRY(apply_inverse(f, B, ldb, nrhs, X, ldx, false, st));
+        f->t_solve = ms_since(t0);
+        return ASKIT_OK;
+    }
+    // refinement: x0 = Ahat^{-1} b, then x += Ahat^{-1} (b - A x) with the FP64 operator
+    const int64_t N = f->t->N;
+    if (f->R.bytes < sizeof(double) * N * nrhs) {
+        ST_TRY(f->R.alloc(sizeof(double) * N * nrhs));
+        ST_TRY(f->Dx.alloc(sizeof(double) * N * nrhs));
+    }
+    double *R = f->R.as<double>(), *Dx = f->Dx.as<double>();
+    ST_TRY(apply_inverse(f, B, ldb, nrhs, Dx, N, false, st));
+    // copy the first iterate into X (B and X may alias: B is not read again
+    // before the residual, which needs it -- so refine against a saved copy)
+    DBuf Bsave;
+    const double *Bref = B;
+    if (B == X) {
+        ST_TRY(Bsave.alloc(sizeof(double) * N * nrhs));
+        HIP_TRY(hipMemcpy2DAsync(Bsave.p, sizeof(double) * N, B, sizeof(double) * ldb, sizeof(double) * N, nrhs,
+                                 hipMemcpyDeviceToDevice, st));
+        Bref = Bsave.as<double>();
+        ldb = N;
+    }
+    HIP_TRY(hipMemcpy2DAsync(X, sizeof(double) * ldx, Dx, sizeof(double) * N, sizeof(double) * N, nrhs,
+                             hipMemcpyDeviceToDevice, st));
+    int it = 0;
+    double upd = INFINITY, res = INFINITY;
+    for (; it < f->max_refine; it++) {
+        ST_TRY(matvec_impl(f, 0, X, ldx, nrhs, R, N, st));
+        hipLaunchKernelGGL(k_residual, dim3(grid1(N * nrhs)), dim3(256), 0, st, Bref, ldb, R, N, N, nrhs);
+        HIP_TRY(hipGetLastError());
+        ST_TRY(colratio(f, R, N, Bref, ldb, nrhs, st, &res));
+        ST_TRY(apply_inverse(f, R, N, nrhs, Dx, N, false, st));
+        hipLaunchKernelGGL(k_update, dim3(grid1(N * nrhs)), dim3(256), 0, st, X, ldx, Dx, N, N, nrhs);
+        HIP_TRY(hipGetLastError());
+        ST_TRY(colratio(f, Dx, N, X, ldx, nrhs, st, &upd));
+        if (upd <= f->refine_tol) {
+            it++;
+            break;
+        }
+    }
+    f->info.iterations = it;
+    f->info.converged = upd <= f->refine_tol;
+    f->info.last_update = upd;
+    f->info.residual = res;
+    HIP_TRY(hipStreamSynchronize(st));
+    f->t_solve = ms_since(t0);
+    return ASKIT_OK;
+}
+
+askit_status askit_solve_transpose(askit_factor f, const double *B, int64_t ldb, int32_t nrhs, double *X,
+                                   int64_t ldx, void *stream) {
+    ST_TRY(check_solve_args(f, B, ldb, nrhs, X, ldx));
+    return apply_inverse(f, B, ldb, nrhs, X, ldx, true, (hipStream_t)stream);
+}
+
+askit_status askit_matvec(askit_factor f, int32_t which, const double *Xin, int64_t ldx, int32_t nrhs, double *Y,
+                          int64_t ldy, void *stream) {
+    ST_TRY(check_solve_args(f, Xin, ldx, nrhs, Y, ldy));
+    if (which != 0 && which != 1) return fail(ASKIT_ERR_ARG, "which must be 0 or 1");
+    return matvec_impl(f, which, Xin, ldx, nrhs, Y, ldy, (hipStream_t)stream);
+}
+
+askit_status askit_set_refinement(askit_factor f, int32_t max_refine, double refine_tol) {
+    if (!f || max_refine < 0 || !(refine_tol > 0.0)) return fail(ASKIT_ERR_ARG, "bad refinement controls");
+    f->max_refine = max_refine;
+    f->refine_tol = refine_tol;
+    return ASKIT_OK;
+}
+
+askit_status askit_last_solve_info(askit_factor f, askit_solve_info *info) {
+    if (!f || !info) return fail(ASKIT_ERR_ARG, "NULL argument");
+    *info = f->info;
+    return ASKIT_OK;
+}
+
+askit_status askit_get_stats(askit_tree t, askit_factor f, char *json, size_t cap) {
+    if (!json || cap == 0) return fail(ASKIT_ERR_ARG, "NULL buffer");
+    char buf[1024];
+    int n = snprintf(buf, sizeof buf,
+                     "{\"N\": %lld, \"d\": %d, \"depth\": %d, \"leaf_size\": %d, \"rank\": %d, "
+                     "\"tree_ms\": %.3f, \"skeletonize_ms\": %.3f, \"factorize_ms\": %.3f, \"solve_ms\": %.3f, "
+                     "\"precision\": \"%s\", \"min_pivot_ratio\": %.3e, \"refine_iterations\": %d}",
+                     t ? (long long)t->N : 0LL, t ? t->d : 0, t ? t->D : 0, t ? t->m : 0, t ? t->s : 0,
+                     t ? t->t_tree : 0.0, t ? t->t_skel : 0.0, f ? f->t_factor : 0.0, f ? f->t_solve : 0.0,
+                     f ? (f->prec == P64 ? "fp64" : "mixed") : "none", f ? f->min_ratio : 0.0,
+                     f ? f->info.iterations : 0);
+    if (n < 0 || (size_t)n >= cap) return fail(ASKIT_ERR_ARG, "buffer too small");
+    memcpy(json, buf, n + 1);
+    return ASKIT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,133 @@
+// askit_dev.h -- device-side types shared by the HIP translation units of
+// libaskit (gfx950).  Internal to the library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace askit {
+
+constexpr int kWave = 64;
+constexpr int kMaxDim = 64;      // largest point dimension d accepted
+constexpr int kTreeChunk = 256;  // positions per chunk of the tree reductions
+constexpr int kPowerIters = 50;  // power iterations for the principal axis
+constexpr double kRankGuard = 1e-14;
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Point sources: a contiguous range of tree positions, or a list of positions
+// (skeletons) whose length lives in device memory (ranks are decided on the
+// device).  Positions index the permuted point array.
+// ---------------------------------------------------------------------------
+struct PtSrc {
+    const int32_t *idx;    // list of positions, or nullptr for a range
+    const int32_t *cnt;    // device count for a list (nullptr -> n)
+    int64_t base;          // first position of a range
+    int32_t n;             // range length / list capacity
+    int32_t pad;
+};
+
+// One product task of the fused kernel-matrix kernel:
+//   C(r, c) op= sum_k K(R_r, S_k) B(k, c)   (r < rows, c < ncol, k in chunk)
+// R and S are point sources of the same problem (points X, bandwidth).
+struct KmmTask {
+    const double *X;       // permuted points of the problem, d per point
+    PtSrc R, S;
+    int32_t k0, k1;        // contraction sub-range [k0, k1) of S
+    const void *B;         // B(k, c) = B[(k - k0) * ldb + c]
+    int64_t ldb;
+    void *C;               // C(r, c) = C[r * crs + c * ccs]
+    int64_t crs, ccs;
+    double scale;          // -1 / (2 h^2)
+    double hinv;           // 1 / h (for dK/dh = K r^2 / h^3)
+    int32_t which;         // 0: K, 1: dK/dh
+    int32_t op;            // OutOp
+    int32_t rcap;          // rows written: r < count gets the product, count <= r < rcap
+    int32_t pad;           // gets 0 when op == OP_STORE (padded skeleton slots)
+};
+
+// One plain product task:  C(r, c) op= sum_k A(r, k) B(k, c)
+struct GmmTask {
+    const void *A;  int64_t ars, acs;
+    const void *B;  int64_t brs, bcs;
+    void *C;        int64_t crs, ccs;
+    int32_t rows, kdim;
+    int32_t op, pad;
+};
+
+// Work item of a tiled launch: task index, row tile, column tile.
+struct TileItem {
+    int32_t task, rt, ct, pad;
+};
+
+// Partial-sum reduction: dst(r, c) op= sum_{p < np} src[p](r, c), partials
+// contiguous with stride pstride, each partial rows x ncol row-major.
+struct RedTask {
+    const void *src;
+    int64_t pstride;       // elements between partials
+    int64_t prs;           // row stride inside a partial
+    int32_t np, rows;
+    void *dst;
+    int64_t drs, dcs;
+    int32_t op, pad;
+};
+
+// Strided block copy / cast: dst(r, c) = src(r, c), r < rows, c < cols.
+struct CopyTask {
+    const void *src;
+    void *dst;
+    int64_t sld, dld;
+    int32_t rows, cols;
+};
+
+// Leaf block lambda I + K_aa (column-major, lda) of the points [b, b+n).
+struct LeafTask {
+    const double *X;
+    int64_t b;
+    int32_t n, lda;
+    double *A;
+    double scale, lambda;
+};
+
+// Batched LU / LU-solve task (column-major matrix).
+struct LuTask {
+    double *A;
+    int32_t *piv;
+    int32_t n, lda;
+    void *B;              // right-hand sides, row-major n x nrhs, row stride ldb
+    int64_t ldb;
+    double *ratio;        // pivot ratio output (factor)
+    double *dinv;         // inverses of the 16 x 16 diagonal blocks of L and U
+};
+
+// Sampling task (uniform rows outside a node, SplitMix64 stream).
+struct SampTask {
+    int64_t b, e, N;
+    uint64_t state;
+    int32_t *out;
+};
+
+// Sampled kernel block + QRCP task for one non-root node.
+struct SkelTask {
+    const double *X;
+    const int32_t *q;      // sampled positions (nsamp capacity)
+    int32_t nq;            // number of sampled rows
+    int32_t leaf;          // 1: candidates = [b, b+n); 0: [skl[:sl], skr[:sr]]
+    int64_t b;
+    int32_t n;
+    int32_t pad;
+    const int32_t *skl, *skr, *srl, *srr;
+    double *M;             // nsamp_cap x cmax column-major
+    int32_t *skel;         // out: s positions (-1 padded)
+    int32_t *sr;           // out: rank
+    int32_t *trunc;        // out: rank-guard flag
+    double *Pt;            // out: cmax x s row-major P_{C alpha~} (rows padded)
+    double scale;          // -1 / (2 h^2)
+};
+
+// Output operations of the product kernels.
+enum OutOp : int { OP_STORE = 0, OP_ADD = 1, OP_SUB = 2 };
+
+}  // namespace askit

@@ -1,0 +1,315 @@
+// k_lu.hip -- batched FP64 LU with partial pivoting (the GETRF of Sec. 2.2:
+// leaf blocks lambda I + K_aa and reduced systems Z of eq. (8)) and the
+// matching batched solves (GETRS), plain and transposed.
+//
+// One workgroup per matrix.  Column-major matrices; pivot = row of largest
+// |a| in the column, lowest row on ties; piv[k] = row exchanged with row k.
+// The factor works blocked: a panel of kPanel columns is factored with
+// rank-1 updates restricted to the panel, the row exchanges are applied to
+// the rest of the matrix, the block row of U is solved with the unit lower
+// panel triangle, and the trailing matrix receives one rank-kPanel update
+// computed with FP64 MFMA (v_mfma_f64_16x16x4f64) from LDS-staged panels.
+#include "askit_dev.h"
+
+namespace askit {
+
+constexpr int kLuThreads = 256;
+constexpr int kPanel = 16;
+constexpr int kLuMaxN = 512;
+
+__device__ inline void argmax_abs(double v, int i, double &bv, int &bi) {
+    double a = fabs(v);
+    if (a > bv || (a == bv && i < bi)) {
+        bv = a;
+        bi = i;
+    }
+}
+
+__global__ __launch_bounds__(kLuThreads) void k_lu(const LuTask *__restrict__ tasks) {
+    __shared__ double Lp[kLuMaxN * kPanel];   // panel columns below the diagonal block (col-major, ld = n)
+    __shared__ double Up[kPanel * kLuMaxN];   // U block row (row-major, ld = n)
+    __shared__ double redv[kLuThreads / kWave];
+    __shared__ int redi[kLuThreads / kWave];
+    __shared__ double s_min, s_max;
+    const LuTask t = tasks[blockIdx.x];
+    const int n = t.n, lda = t.lda, tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    double *A = t.A;
+    if (tid == 0) {
+        s_min = INFINITY;
+        s_max = 0.0;
+    }
+    for (int kb = 0; kb < n; kb += kPanel) {
+        const int nb = n - kb < kPanel ? n - kb : kPanel;
+        // ---- panel factorization (columns kb .. kb+nb-1, rows kb .. n-1)
+        for (int k = kb; k < kb + nb; k++) {
+            double bv = -1.0;
+            int bi = 0x7fffffff;
+            for (int i = k + tid; i < n; i += kLuThreads) argmax_abs(A[i + (int64_t)k * lda], i, bv, bi);
+            for (int o = kWave / 2; o > 0; o >>= 1) {
+                double ov = __shfl_xor(bv, o);
+                int oi = __shfl_xor(bi, o);
+                if (ov > bv || (ov == bv && oi < bi)) {
+                    bv = ov;
+                    bi = oi;
+                }
+            }
+            if (lane == 0) {
+                redv[wave] = bv;
+                redi[wave] = bi;
+            }
+            __syncthreads();
+            int p = redi[0];
+            double pv = redv[0];
+            for (int w = 1; w < kLuThreads / kWave; w++)
+                if (redv[w] > pv || (redv[w] == pv && redi[w] < p)) {
+                    pv = redv[w];
+                    p = redi[w];
+                }
+            // exchange rows k and p inside the panel only
+            if (p != k && tid < nb) {
+                int j = kb + tid;
+                double a = A[k + (int64_t)j * lda];
+                A[k + (int64_t)j * lda] = A[p + (int64_t)j * lda];
+                A[p + (int64_t)j * lda] = a;
+            }
+            if (tid == 0) t.piv[k] = p;
+            __syncthreads();
+            const double ukk = A[k + (int64_t)k * lda];
+            if (tid == 0) {
+                double au = fabs(ukk);
+                s_min = fmin(s_min, au);
+                s_max = fmax(s_max, au);
+            }
+            // scale the column and update the rest of the panel
+            if (ukk != 0.0) {
+                for (int i = k + 1 + tid; i < n; i += kLuThreads) A[i + (int64_t)k * lda] /= ukk;
+            }
+            __syncthreads();
+            const int rem = kb + nb - k - 1;
+            if (ukk != 0.0 && rem > 0) {
+                const int rows = n - k - 1;
+                for (int idx = tid; idx < rows * rem; idx += kLuThreads) {
+                    int i = k + 1 + idx % rows, j = k + 1 + idx / rows;
+                    A[i + (int64_t)j * lda] -= A[i + (int64_t)k * lda] * A[k + (int64_t)j * lda];
+                }
+            }
+            __syncthreads();
+        }
+        // ---- row exchanges of this panel applied to the other columns
+        for (int j = tid; j < n; j += kLuThreads) {
+            if (j >= kb && j < kb + nb) continue;
+            for (int k = kb; k < kb + nb; k++) {
+                int p = t.piv[k];
+                if (p != k) {
+                    double a = A[k + (int64_t)j * lda];
+                    A[k + (int64_t)j * lda] = A[p + (int64_t)j * lda];
+                    A[p + (int64_t)j * lda] = a;
+                }
+            }
+        }
+        __syncthreads();
+        const int j0 = kb + nb, nt = n - j0;
+        if (nt <= 0) break;
+        // ---- U block row: A[kb:kb+nb, j0:n] = L11^{-1} A[kb:kb+nb, j0:n]
+        for (int j = j0 + tid; j < n; j += kLuThreads) {
+            double u[kPanel];
+            for (int r = 0; r < nb; r++) {
+                double acc = A[kb + r + (int64_t)j * lda];
+                for (int c = 0; c < r; c++) acc = fma(-A[kb + r + (int64_t)(kb + c) * lda], u[c], acc);
+                u[r] = acc;
+            }
+            for (int r = 0; r < nb; r++) {
+                A[kb + r + (int64_t)j * lda] = u[r];
+                Up[r * n + (j - j0)] = u[r];
+            }
+        }
+        for (int idx = tid; idx < nt * kPanel; idx += kLuThreads) {
+            int i = idx % nt, c = idx / nt;
+            Lp[c * nt + i] = c < nb ? A[j0 + i + (int64_t)(kb + c) * lda] : 0.0;
+        }
+        if (nb < kPanel)
+            for (int idx = tid; idx < (kPanel - nb) * nt; idx += kLuThreads) Up[(nb + idx / nt) * n + idx % nt] = 0.0;
+        __syncthreads();
+        // ---- trailing update A22 -= L21 U12 with 16x16 MFMA tiles; each
+        // wave owns whole 16x16 output blocks
+        const int bt = (nt + 15) / 16;
+        for (int blk = wave; blk < bt * bt; blk += kLuThreads / kWave) {
+            const int bi0 = (blk % bt) * 16, bj0 = (blk / bt) * 16;
+            const int row = lane % 16, kq = lane / 16;
+            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+            for (int k4 = 0; k4 < kPanel; k4 += 4) {
+                int ai = bi0 + row, bj = bj0 + row;
+                double a = ai < nt ? Lp[(k4 + kq) * nt + ai] : 0.0;
+                double b = bj < nt ? Up[(k4 + kq) * n + bj] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+            }
+            // acc[r] -> (row 4r + lane/16, col lane % 16) of the block (FP64 layout)
+            const int cj = bj0 + lane % 16;
+            if (cj < nt) {
+                for (int r = 0; r < 4; r++) {
+                    int ci = bi0 + 4 * r + kq;
+                    if (ci < nt) A[j0 + ci + (int64_t)(j0 + cj) * lda] -= acc[r];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && t.ratio) *t.ratio = n ? (s_max > 0.0 ? s_min / s_max : 0.0) : 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// Inverses of the 16 x 16 diagonal blocks of L (unit lower) and U, used by the
+// blocked triangular solves: Dinv[2b] = L_bb^{-1}, Dinv[2b+1] = U_bb^{-1}
+// (column-major 16 x 16; a partial last block is completed by the identity).
+// One workgroup per matrix, one lane per block column.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_lu_diaginv(const LuTask *__restrict__ tasks) {
+    const LuTask t = tasks[blockIdx.x];
+    const int n = t.n, lda = t.lda, nb = (n + 15) / 16;
+    for (int job = threadIdx.x; job < nb * 32; job += blockDim.x) {
+        const int b = job / 32, j = job % 16, upper = (job % 32) / 16, b0 = b * 16;
+        double x[16];
+        double *out = t.dinv + ((int64_t)(2 * b + upper)) * 256;
+        auto a = [&](int r, int c) -> double {
+            int gr = b0 + r, gc = b0 + c;
+            if (gr >= n || gc >= n) return r == c ? 1.0 : 0.0;
+            return t.A[gr + (int64_t)gc * lda];
+        };
+        if (!upper) {  // x = L^{-1} e_j, unit diagonal
+            for (int i = 0; i < 16; i++) {
+                double acc = (i == j) ? 1.0 : 0.0;
+                for (int k = 0; k < i; k++) acc = fma(-a(i, k), x[k], acc);
+                x[i] = acc;
+            }
+        } else {  // x = U^{-1} e_j
+            for (int i = 15; i >= 0; i--) {
+                double acc = (i == j) ? 1.0 : 0.0;
+                for (int k = i + 1; k < 16; k++) acc = fma(-a(i, k), x[k], acc);
+                x[i] = acc / a(i, i);
+            }
+        }
+        for (int i = 0; i < 16; i++) out[i + 16 * j] = x[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched LU solves (GETRS) A X = B or A^T X = B for right-hand sides stored
+// row-major (n x nrhs, row stride ldb), FP32 or FP64 storage, FP64
+// arithmetic.  One workgroup per (matrix, panel of NR columns); the panel is
+// held in LDS.  Each triangular sweep goes over 16-row blocks: the block is
+// finished with its precomputed diagonal inverse, then the remaining blocks
+// receive a rank-16 update, both on the FP64 matrix cores.
+// ---------------------------------------------------------------------------
+template <int NR>
+__device__ inline void diag_apply(double (*S)[NR + 1], int r0, const double *D, bool transD, int lane, int wave) {
+    // S[r0:r0+16, :] = D' S[r0:r0+16, :] with D' = D or D^T (16 x 16, column-major)
+    constexpr int CB = NR / 16;
+    dbl4 acc = {0, 0, 0, 0};
+    const int cb = wave;
+    if (cb < CB) {
+#pragma unroll
+        for (int k4 = 0; k4 < 16; k4 += 4) {
+            const int row = lane % 16, kk = k4 + lane / 16;
+            double a = transD ? D[kk + 16 * row] : D[row + 16 * kk];
+            double b = S[r0 + kk][cb * 16 + lane % 16];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+    }
+    __syncthreads();
+    if (cb < CB)
+        for (int q = 0; q < 4; q++) S[r0 + 4 * q + lane / 16][cb * 16 + lane % 16] = acc[q];
+    __syncthreads();
+}
+
+// S[J block] -= M(J, I) S[I block] for the blocks J in [jb0, jb1); element
+// (r, c) of the 16 x 16 coupling block is read through get(row, col) with
+// global row/column indices
+template <int NR, typename G>
+__device__ inline void block_update(double (*S)[NR + 1], int i0, int jb0, int jb1, G get, int lane, int wave) {
+    constexpr int CB = NR / 16;
+    const int nw = kLuThreads / kWave;
+    for (int job = wave; job < (jb1 - jb0) * CB; job += nw) {
+        const int J = jb0 + job / CB, cb = job % CB;
+        dbl4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int k4 = 0; k4 < 16; k4 += 4) {
+            const int kk = k4 + lane / 16;
+            double a = get(J * 16 + lane % 16, i0 + kk);
+            double b = S[i0 + kk][cb * 16 + lane % 16];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+        for (int q = 0; q < 4; q++) S[J * 16 + 4 * q + lane / 16][cb * 16 + lane % 16] -= acc[q];
+    }
+    __syncthreads();
+}
+
+template <typename T, int NR, bool TRANS>
+__global__ __launch_bounds__(kLuThreads) void k_lusolve(const LuTask *__restrict__ tasks, int nrhs, int panels) {
+    __shared__ double S[kLuMaxN][NR + 1];
+    const LuTask t = tasks[blockIdx.x / panels];
+    const int c0 = (blockIdx.x % panels) * NR;
+    if (c0 >= nrhs) return;
+    const int ncols = min(NR, nrhs - c0);
+    const int n = t.n, lda = t.lda, nb = (n + 15) / 16, tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    const double *A = t.A;
+    T *B = (T *)t.B;
+    for (int i = tid; i < nb * 16 * NR; i += kLuThreads) {
+        const int r = i / NR, c = i % NR;
+        S[r][c] = (r < n && c < ncols) ? (double)B[(int64_t)r * t.ldb + c0 + c] : 0.0;
+    }
+    __syncthreads();
+    auto Lget = [&](int r, int c) -> double { return (r < n && c < n && r > c) ? A[r + (int64_t)c * lda] : 0.0; };
+    auto Uget = [&](int r, int c) -> double { return (r < n && c < n && r <= c) ? A[r + (int64_t)c * lda] : 0.0; };
+    if (!TRANS) {
+        if (tid < NR)
+            for (int k = 0; k < n; k++) {
+                const int p = t.piv[k];
+                if (p != k) {
+                    double a = S[k][tid];
+                    S[k][tid] = S[p][tid];
+                    S[p][tid] = a;
+                }
+            }
+        __syncthreads();
+        for (int ib = 0; ib < nb; ib++) {  // L y = P b
+            diag_apply<NR>(S, ib * 16, t.dinv + (int64_t)(2 * ib) * 256, false, lane, wave);
+            block_update<NR>(S, ib * 16, ib + 1, nb, Lget, lane, wave);
+        }
+        for (int ib = nb - 1; ib >= 0; ib--) {  // U x = y
+            diag_apply<NR>(S, ib * 16, t.dinv + (int64_t)(2 * ib + 1) * 256, false, lane, wave);
+            block_update<NR>(S, ib * 16, 0, ib, Uget, lane, wave);
+        }
+    } else {
+        auto UTget = [&](int r, int c) -> double { return Uget(c, r); };
+        auto LTget = [&](int r, int c) -> double { return Lget(c, r); };
+        for (int ib = 0; ib < nb; ib++) {  // U^T z = b
+            diag_apply<NR>(S, ib * 16, t.dinv + (int64_t)(2 * ib + 1) * 256, true, lane, wave);
+            block_update<NR>(S, ib * 16, ib + 1, nb, UTget, lane, wave);
+        }
+        for (int ib = nb - 1; ib >= 0; ib--) {  // L^T w = z
+            diag_apply<NR>(S, ib * 16, t.dinv + (int64_t)(2 * ib) * 256, true, lane, wave);
+            block_update<NR>(S, ib * 16, 0, ib, LTget, lane, wave);
+        }
+        if (tid < NR)
+            for (int k = n - 1; k >= 0; k--) {
+                const int p = t.piv[k];
+                if (p != k) {
+                    double a = S[k][tid];
+                    S[k][tid] = S[p][tid];
+                    S[p][tid] = a;
+                }
+            }
+        __syncthreads();
+    }
+    for (int i = tid; i < n * NR; i += kLuThreads) {
+        const int r = i / NR, c = i % NR;
+        if (c < ncols) B[(int64_t)r * t.ldb + c0 + c] = (T)S[r][c];
+    }
+}
+
+#define LUS_INST(T, NR)                                                              \
+    template __global__ void k_lusolve<T, NR, false>(const LuTask *, int, int);      \
+    template __global__ void k_lusolve<T, NR, true>(const LuTask *, int, int);
+LUS_INST(double, 16) LUS_INST(double, 32) LUS_INST(float, 16) LUS_INST(float, 32)
+
+}  // namespace askit

@@ -1,0 +1,218 @@
+// k_prod.hip -- tiled MFMA products of the factorization and the solves.
+//
+// k_kmm: the fused kernel-block product C op= K(R, S) B of Sec. 2.4 (kernel
+// summation without storing the block): a 64 x 16 tile of Gaussian kernel
+// entries (eq. (1)) is generated from LDS-staged coordinates and fed straight
+// to the matrix cores together with a 16 x TC tile of B.  It forms the
+// reduced-system blocks K_{l~ r} Phat_r and K_{r~ l} Phat_l of eq. (8), the
+// products V v of Alg. 3 and their transposes, and the matvec of eq. (6).
+//
+// k_gmm: the plain products with the hat factors (telescoping of eq. (10),
+// W y of Alg. 3, W^T g of the transpose solve) with arbitrary strides.
+//
+// Both use v_mfma_f64_16x16x4f64 (FP64 path) or v_mfma_f32_16x16x4f32
+// (mixed path): a 256-thread workgroup owns a 64 x TC output tile, wave w
+// owns rows 16w..16w+15 and TC/16 accumulator blocks.  MFMA operand layout
+// (16x16x4, both types): lane l holds A[l%16][l/16] and B[l/16][l%16].
+// Accumulator register r of lane l holds C[i][l%16] with i = 4(l/16) + r for
+// FP32 and i = 4r + l/16 for FP64 (measured on gfx950).
+#include "askit_dev.h"
+
+namespace askit {
+
+template <typename T> struct Acc;
+template <> struct Acc<double> {
+    typedef dbl4 type;
+    static __device__ inline dbl4 mma(double a, double b, dbl4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int lane, int r) { return 4 * r + lane / 16; }
+};
+template <> struct Acc<float> {
+    typedef flt4 type;
+    static __device__ inline flt4 mma(float a, float b, flt4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int lane, int r) { return 4 * (lane / 16) + r; }
+};
+
+__device__ inline double kexp(double x) { return exp(x); }
+__device__ inline float kexp(float x) { return expf(x); }
+
+constexpr int kTR = 64;   // tile rows
+constexpr int kKS = 16;   // contraction per stage
+
+template <typename T>
+__device__ inline void store_out(T *C, int64_t off, T v, int op) {
+    if (op == OP_STORE) C[off] = v;
+    else if (op == OP_ADD) C[off] += v;
+    else C[off] -= v;
+}
+
+__device__ inline int src_count(const PtSrc &s) { return s.cnt ? *s.cnt : s.n; }
+__device__ inline int64_t src_pos(const PtSrc &s, int i) { return s.idx ? (int64_t)s.idx[i] : s.base + i; }
+
+template <typename T, typename TO, int TC>
+__global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, const TileItem *__restrict__ items,
+                                             int ncol, int d) {
+    constexpr int NB = TC / 16;
+    __shared__ T sA[kTR][kKS + 1];
+    __shared__ T sB[kKS][TC + 1];
+    __shared__ T sR[kTR * kMaxDim];
+    __shared__ T sS[kKS * kMaxDim];
+    const TileItem it = items[blockIdx.x];
+    const KmmTask t = tasks[it.task];
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    const int nrow = src_count(t.R);
+    const int r0 = it.rt * kTR, c0 = it.ct * TC;
+    TO *C = (TO *)t.C;
+    if (r0 >= nrow) {  // tile of padded rows: zero-fill on store
+        if (t.op == OP_STORE)
+            for (int i = tid; i < kTR * TC; i += 256) {
+                int r = r0 + i / TC, c = c0 + i % TC;
+                if (r < t.rcap && c < ncol) C[(int64_t)r * t.crs + (int64_t)c * t.ccs] = (TO)0;
+            }
+        return;
+    }
+    int k1 = t.k1;
+    if (t.S.cnt) k1 = min(k1, *t.S.cnt);
+    const T scale = (T)t.scale, hinv = (T)t.hinv;
+    // stage the row points (fixed for the whole contraction)
+    for (int i = tid; i < kTR * d; i += 256) {
+        int r = i / d, k = i % d;
+        sR[i] = r0 + r < nrow ? (T)t.X[src_pos(t.R, r0 + r) * d + k] : (T)0;
+    }
+    typename Acc<T>::type acc[NB];
+    for (int b = 0; b < NB; b++) acc[b] = typename Acc<T>::type{0, 0, 0, 0};
+    const T *B = (const T *)t.B;
+    for (int ks = t.k0; ks < k1; ks += kKS) {
+        const int kn = min(kKS, k1 - ks);
+        __syncthreads();
+        for (int i = tid; i < kKS * d; i += 256) {
+            int r = i / d, k = i % d;
+            sS[i] = r < kn ? (T)t.X[src_pos(t.S, ks + r) * d + k] : (T)0;
+        }
+        for (int i = tid; i < kKS * TC; i += 256) {
+            int k = i / TC, c = i % TC;
+            sB[k][c] = (k < kn && c0 + c < ncol) ? B[(int64_t)(ks - t.k0 + k) * t.ldb + c0 + c] : (T)0;
+        }
+        __syncthreads();
+        // generate the kernel tile: 64 x 16 entries, 4 per thread
+        for (int i = tid; i < kTR * kKS; i += 256) {
+            int r = i % kTR, k = i / kTR;
+            T v = (T)0;
+            if (k < kn && r0 + r < nrow) {
+                const T *x = sR + r * d, *y = sS + k * d;
+                T r2 = 0;
+                for (int q = 0; q < d; q++) {
+                    T df = x[q] - y[q];
+                    r2 = fma(df, df, r2);
+                }
+                v = kexp(r2 * scale);
+                if (t.which) v = v * r2 * hinv * hinv * hinv;
+            }
+            sA[r][k] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k4 = 0; k4 < kKS; k4 += 4) {
+            T a = sA[wave * 16 + lane % 16][k4 + lane / 16];
+#pragma unroll
+            for (int b = 0; b < NB; b++) {
+                T bb = sB[k4 + lane / 16][b * 16 + lane % 16];
+                acc[b] = Acc<T>::mma(a, bb, acc[b]);
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        const int c = c0 + b * 16 + lane % 16;
+        if (c >= ncol) continue;
+        for (int q = 0; q < 4; q++) {
+            const int r = r0 + wave * 16 + Acc<T>::row(lane, q);
+            if (r < nrow) store_out(C, (int64_t)r * t.crs + (int64_t)c * t.ccs, (TO)acc[b][q], t.op);
+            else if (r < t.rcap && t.op == OP_STORE) C[(int64_t)r * t.crs + (int64_t)c * t.ccs] = (TO)0;
+        }
+    }
+}
+
+template <typename T, int TC>
+__global__ __launch_bounds__(256) void k_gmm(const GmmTask *__restrict__ tasks, const TileItem *__restrict__ items,
+                                             int ncol, int kchunk) {
+    constexpr int NB = TC / 16;
+    __shared__ T sA[kTR][kKS + 1];
+    __shared__ T sB[kKS][TC + 1];
+    const TileItem it = items[blockIdx.x];
+    const GmmTask t = tasks[it.task];
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    const int r0 = it.rt * kTR, c0 = it.ct * TC;
+    if (r0 >= t.rows) return;
+    // optional split of the contraction: item.pad = chunk index
+    const int kb = it.pad * kchunk, ke = min(t.kdim, kb + kchunk);
+    const T *A = (const T *)t.A, *B = (const T *)t.B;
+    const bool a_kfast = (t.acs == 1), b_cfast = (t.bcs == 1);
+    typename Acc<T>::type acc[NB];
+    for (int b = 0; b < NB; b++) acc[b] = typename Acc<T>::type{0, 0, 0, 0};
+    for (int ks = kb; ks < ke; ks += kKS) {
+        const int kn = min(kKS, ke - ks);
+        __syncthreads();
+        for (int i = tid; i < kTR * kKS; i += 256) {
+            int r, k;
+            if (a_kfast) { r = i / kKS; k = i % kKS; }
+            else { r = i % kTR; k = i / kTR; }
+            sA[r][k] = (k < kn && r0 + r < t.rows) ? A[(int64_t)(r0 + r) * t.ars + (int64_t)(ks + k) * t.acs] : (T)0;
+        }
+        for (int i = tid; i < kKS * TC; i += 256) {
+            int k, c;
+            if (b_cfast) { k = i / TC; c = i % TC; }
+            else { k = i % kKS; c = i / kKS; }
+            sB[k][c] = (k < kn && c0 + c < ncol) ? B[(int64_t)(ks + k) * t.brs + (int64_t)(c0 + c) * t.bcs] : (T)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k4 = 0; k4 < kKS; k4 += 4) {
+            T a = sA[wave * 16 + lane % 16][k4 + lane / 16];
+#pragma unroll
+            for (int b = 0; b < NB; b++) {
+                T bb = sB[k4 + lane / 16][b * 16 + lane % 16];
+                acc[b] = Acc<T>::mma(a, bb, acc[b]);
+            }
+        }
+    }
+    T *C = (T *)t.C;
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        const int c = c0 + b * 16 + lane % 16;
+        if (c >= ncol) continue;
+        for (int q = 0; q < 4; q++) {
+            const int r = r0 + wave * 16 + Acc<T>::row(lane, q);
+            if (r < t.rows) store_out(C, (int64_t)r * t.crs + (int64_t)c * t.ccs, (T)acc[b][q], t.op);
+        }
+    }
+}
+
+// dst(r, c) op= sum_p src_p(r, c), partials summed in index order
+template <typename T, typename TO>
+__global__ void k_reduce(const RedTask *__restrict__ tasks, int ncol, int blocks_per_task) {
+    const RedTask t = tasks[blockIdx.x / blocks_per_task];
+    const int64_t e = (int64_t)(blockIdx.x % blocks_per_task) * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)t.rows * ncol) return;
+    const int r = (int)(e / ncol), c = (int)(e % ncol);
+    const T *src = (const T *)t.src;
+    double acc = 0.0;
+    for (int p = 0; p < t.np; p++) acc += (double)src[p * t.pstride + (int64_t)r * t.prs + c];
+    store_out((TO *)t.dst, (int64_t)r * t.drs + (int64_t)c * t.dcs, (TO)acc, t.op);
+}
+
+#define KMM_INST(T, TO, TC) template __global__ void k_kmm<T, TO, TC>(const KmmTask *, const TileItem *, int, int);
+KMM_INST(double, double, 16) KMM_INST(double, double, 64) KMM_INST(double, double, 128)
+KMM_INST(float, float, 16) KMM_INST(float, float, 64) KMM_INST(float, float, 128)
+KMM_INST(float, double, 16) KMM_INST(float, double, 64) KMM_INST(float, double, 128)
+#define GMM_INST(T, TC) template __global__ void k_gmm<T, TC>(const GmmTask *, const TileItem *, int, int);
+GMM_INST(double, 16) GMM_INST(double, 64) GMM_INST(double, 128)
+GMM_INST(float, 16) GMM_INST(float, 64) GMM_INST(float, 128)
+template __global__ void k_reduce<double, double>(const RedTask *, int, int);
+template __global__ void k_reduce<float, float>(const RedTask *, int, int);
+template __global__ void k_reduce<float, double>(const RedTask *, int, int);
+
+}  // namespace askit

@@ -1,0 +1,313 @@
+// k_skel.hip -- skeletonization kernels (Sec. 2.1, "Computing low rank
+// approximations"; Alg. 1; the ID of eq. (4)).
+//
+//  * k_sample: the sampled rows S' of a node: min(nsamp, N - n) distinct
+//    positions outside the node, drawn uniformly with SplitMix64 (Steele, Lea
+//    & Flood 2014) from the node's own stream, duplicates rejected; when the
+//    complement has at most nsamp positions it is taken whole, in order.
+//  * k_sample_block: the kernel block K(X_S', X_C) in FP64, column-major.
+//  * k_qrcp: column-pivoted Householder QR of that block, truncated at the
+//    rank s (trailing column norms recomputed at every step, largest norm
+//    first, lowest column on ties), the rank guard |R_jj| <= 1e-14 |R_00|,
+//    T = R11^{-1} R12 and the projection P = [I T] Pi^T, written transposed.
+#include "askit_dev.h"
+
+namespace askit {
+
+// ---------------------------------------------------------------------------
+// sampling: one wave per node; lane 0 runs the sequential rejection loop with
+// an open-addressing set in LDS
+// ---------------------------------------------------------------------------
+constexpr int kSampHashBits = 13;  // 8192 slots: nsamp <= 4096
+
+__device__ inline uint64_t splitmix_next(uint64_t &st) {
+    uint64_t z = (st += 0x9E3779B97F4A7C15ULL);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(64) void k_sample(const SampTask *__restrict__ tasks, int nsamp, int32_t *__restrict__ err) {
+    __shared__ int32_t table[1 << kSampHashBits];
+    const SampTask t = tasks[blockIdx.x];
+    const int64_t n = t.e - t.b, c = t.N - n;
+    if (c <= nsamp) {
+        for (int64_t i = threadIdx.x; i < c; i += kWave) t.out[i] = (int32_t)(i < t.b ? i : i + n);
+        return;
+    }
+    for (int i = threadIdx.x; i < (1 << kSampHashBits); i += kWave) table[i] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t st = t.state;
+        const uint64_t cap = 64ULL * (uint64_t)(c + nsamp);
+        int k = 0;
+        uint64_t draws = 0;
+        while (k < nsamp) {
+            if (++draws > cap) {
+                atomicOr(err, 1);
+                break;
+            }
+            uint64_t r = __umul64hi(splitmix_next(st), (uint64_t)c);
+            int64_t pos = (int64_t)r < t.b ? (int64_t)r : (int64_t)r + n;
+            uint32_t key = (uint32_t)pos + 1u;
+            uint32_t slot = (uint32_t)(((uint64_t)pos * 0x9E3779B97F4A7C15ULL) >> (64 - kSampHashBits));
+            bool dup = false;
+            while (true) {
+                int32_t v = table[slot];
+                if (v == 0) {
+                    table[slot] = (int32_t)key;
+                    break;
+                }
+                if ((uint32_t)v == key) {
+                    dup = true;
+                    break;
+                }
+                slot = (slot + 1) & ((1u << kSampHashBits) - 1);
+            }
+            if (!dup) t.out[k++] = (int32_t)pos;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// sampled kernel block M = K(X_S', X_C), column-major (ldm rows)
+// ---------------------------------------------------------------------------
+__device__ inline int32_t cand_pos(const SkelTask &t, int c, int sl) {
+    if (t.leaf) return (int32_t)(t.b + c);
+    return c < sl ? t.skl[c] : t.skr[c - sl];
+}
+
+__device__ inline double sqdist(const double *x, const double *y, int d) {
+    double r2 = 0.0;
+    for (int k = 0; k < d; k++) {
+        double df = x[k] - y[k];
+        r2 = fma(df, df, r2);
+    }
+    return r2;
+}
+
+// block: 256 threads = 64 sampled rows x 4 column lanes; the 64 sampled
+// points are staged in LDS, every candidate point is read once per block
+__global__ __launch_bounds__(256) void k_sample_block(const SkelTask *__restrict__ tasks, int rowtiles, int ldm, int d) {
+    __shared__ double ys[64 * kMaxDim];
+    const int task = blockIdx.x / rowtiles, r0 = (blockIdx.x % rowtiles) * 64;
+    const SkelTask t = tasks[task];
+    if (r0 >= t.nq) return;
+    const int sl = t.leaf ? 0 : *t.srl;
+    const int ncand = t.leaf ? t.n : sl + *t.srr;
+    const int nr = t.nq - r0 < 64 ? t.nq - r0 : 64;
+    for (int i = threadIdx.x; i < nr * d; i += blockDim.x) ys[i] = t.X[(int64_t)t.q[r0 + i / d] * d + i % d];
+    __syncthreads();
+    const int r = threadIdx.x % 64;
+    if (r >= nr) return;
+    const double *y = ys + r * d;
+    for (int c = threadIdx.x / 64; c < ncand; c += 4) {
+        const double *x = t.X + (int64_t)cand_pos(t, c, sl) * d;
+        t.M[(int64_t)c * ldm + r0 + r] = exp(sqdist(x, y, d) * t.scale);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// QRCP + interpolative decomposition, one workgroup per node
+// ---------------------------------------------------------------------------
+constexpr int kQrThreads = 512;
+constexpr int kQrWaves = kQrThreads / kWave;
+
+__device__ inline double wave_sum(double v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// block-wide sum (all threads get the result); red: kQrWaves doubles of LDS
+__device__ double block_sum(double v, double *red) {
+    v = wave_sum(v);
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    __syncthreads();
+    if (l == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < kQrWaves; i++) s += red[i];
+    return s;
+}
+
+// LDS budget: norms and pivots per candidate column, Householder vector
+constexpr int kQrMaxCols = 2048;
+constexpr int kQrMaxRows = 4096;
+
+__global__ __launch_bounds__(kQrThreads) void k_qrcp(const SkelTask *__restrict__ tasks, int s, int cmax, int ldm) {
+    __shared__ double nrm[kQrMaxCols];
+    __shared__ int32_t piv[kQrMaxCols];
+    __shared__ double vh[kQrMaxRows];
+    __shared__ double red[kQrWaves];
+    __shared__ double redv[kQrThreads / kWave];
+    __shared__ int32_t redi[kQrThreads / kWave];
+    __shared__ int32_t s_rank, s_zero;
+
+    const SkelTask t = tasks[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    const int sl = t.leaf ? 0 : *t.srl;
+    const int ncand = t.leaf ? t.n : sl + *t.srr;
+    const int rows = t.nq;
+    double *M = t.M;
+    // padded row of candidate c in P_{C alpha~}: internal nodes keep the two
+    // children's skeletons in the halves [0, s) and [s, 2s)
+    auto prow = [&](int c) { return t.leaf ? c : (c < sl ? c : s + (c - sl)); };
+
+    for (int64_t i = tid; i < (int64_t)cmax * s; i += kQrThreads) t.Pt[i] = 0.0;
+    if (ncand <= s) {  // no compression: skeleton = candidates, P = I
+        __syncthreads();
+        for (int k = tid; k < s; k += kQrThreads) t.skel[k] = k < ncand ? cand_pos(t, k, sl) : -1;
+        for (int c = tid; c < ncand; c += kQrThreads) t.Pt[(int64_t)prow(c) * s + c] = 1.0;
+        if (tid == 0) {
+            *t.sr = ncand;
+            *t.trunc = 0;
+        }
+        return;
+    }
+    int steps = s < rows ? s : rows;
+    for (int c = tid; c < ncand; c += kQrThreads) piv[c] = c;
+    // initial squared column norms (one wave per column)
+    for (int c = wave; c < ncand; c += kQrWaves) {
+        double acc = 0.0;
+        for (int i = lane; i < rows; i += kWave) {
+            double v = M[(int64_t)c * ldm + i];
+            acc = fma(v, v, acc);
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) nrm[c] = acc;
+    }
+    if (tid == 0) {
+        s_rank = steps;
+        s_zero = 0;
+    }
+    __syncthreads();
+    double r00 = 0.0;
+    for (int j = 0; j < steps; j++) {
+        // pivot: largest norm, lowest column on ties
+        double bv = -1.0;
+        int bi = 0x7fffffff;
+        for (int c = j + tid; c < ncand; c += kQrThreads) {
+            double v = nrm[c];
+            if (v > bv || (v == bv && c < bi)) {
+                bv = v;
+                bi = c;
+            }
+        }
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            double ov = __shfl_xor(bv, o);
+            int oi = __shfl_xor(bi, o);
+            if (ov > bv || (ov == bv && oi < bi)) {
+                bv = ov;
+                bi = oi;
+            }
+        }
+        if (lane == 0) {
+            redv[wave] = bv;
+            redi[wave] = bi;
+        }
+        __syncthreads();
+        int p = redi[0];
+        double pv = redv[0];
+        for (int w = 1; w < kQrWaves; w++)
+            if (redv[w] > pv || (redv[w] == pv && redi[w] < p)) {
+                pv = redv[w];
+                p = redi[w];
+            }
+        if (p != j) {
+            for (int i = tid; i < rows; i += kQrThreads) {
+                double a = M[(int64_t)j * ldm + i];
+                M[(int64_t)j * ldm + i] = M[(int64_t)p * ldm + i];
+                M[(int64_t)p * ldm + i] = a;
+            }
+        }
+        __syncthreads();
+        if (tid == 0 && p != j) {
+            int ti = piv[j]; piv[j] = piv[p]; piv[p] = ti;
+            double tv = nrm[j]; nrm[j] = nrm[p]; nrm[p] = tv;
+        }
+        // Householder reflector of column j, rows j..rows-1
+        double *col = M + (int64_t)j * ldm;
+        const double alpha = col[j];  // read before the barriers of block_sum
+        double part = 0.0;
+        for (int i = j + 1 + tid; i < rows; i += kQrThreads) part = fma(col[i], col[i], part);
+        double xn = block_sum(part, red);
+        double beta, tau, sc;
+        if (xn == 0.0) {
+            beta = alpha; tau = 0.0; sc = 0.0;
+        } else {
+            beta = -copysign(sqrt(alpha * alpha + xn), alpha);
+            tau = (beta - alpha) / beta;
+            sc = 1.0 / (alpha - beta);
+        }
+        if (j == 0) r00 = fabs(beta);
+        bool stop = (j > 0 && fabs(beta) <= kRankGuard * r00) || (j == 0 && r00 == 0.0);
+        if (stop) {
+            if (tid == 0) {
+                s_rank = j == 0 ? 1 : j;
+                s_zero = (j == 0);
+            }
+            __syncthreads();
+            break;
+        }
+        for (int i = j + 1 + tid; i < rows; i += kQrThreads) {
+            double v = col[i] * sc;
+            vh[i] = v;
+            col[i] = v;
+        }
+        if (tid == 0) {
+            vh[j] = 1.0;
+            col[j] = beta;
+        }
+        __syncthreads();
+        // apply H to the columns right of j; new norms over rows j+1..
+        for (int c = j + 1 + wave; c < ncand; c += kQrWaves) {
+            double *ck = M + (int64_t)c * ldm;
+            double w = 0.0;
+            for (int i = j + lane; i < rows; i += kWave) w = fma(vh[i], ck[i], w);
+            w = wave_sum(w) * tau;
+            double acc = 0.0;
+            for (int i = j + lane; i < rows; i += kWave) {
+                double v = fma(-vh[i], w, ck[i]);
+                ck[i] = v;
+                if (i > j) acc = fma(v, v, acc);
+            }
+            acc = wave_sum(acc);
+            if (lane == 0) nrm[c] = acc;
+        }
+        __syncthreads();
+    }
+    const int rank = s_rank;
+    const bool zero = s_zero != 0;
+    // T = R11^{-1} R12 in place of R12 (one thread per column)
+    const int nr = ncand - rank;
+    for (int c = tid; c < nr; c += kQrThreads) {
+        double *tc = M + (int64_t)(rank + c) * ldm;
+        for (int i = rank - 1; i >= 0; i--) {
+            if (zero) {
+                tc[i] = 0.0;
+                continue;
+            }
+            double acc = tc[i];
+            for (int k = i + 1; k < rank; k++) acc = fma(-M[(int64_t)k * ldm + i], tc[k], acc);
+            tc[i] = acc / M[(int64_t)i * ldm + i];
+        }
+    }
+    __syncthreads();
+    // outputs: skeleton positions, rank, P_{C alpha~} rows
+    for (int k = tid; k < s; k += kQrThreads) t.skel[k] = k < rank ? cand_pos(t, piv[k], sl) : -1;
+    if (tid == 0) {
+        *t.sr = rank;
+        *t.trunc = (rank < (s < ncand ? s : ncand)) ? 1 : 0;
+    }
+    for (int jc = tid; jc < ncand; jc += kQrThreads) {
+        double *row = t.Pt + (int64_t)prow(piv[jc]) * s;
+        if (jc < rank) {
+            row[jc] = 1.0;
+        } else {
+            const double *tc = M + (int64_t)jc * ldm;
+            for (int k = 0; k < rank; k++) row[k] = tc[k];
+        }
+    }
+}
+
+}  // namespace askit
