@@ -67,7 +67,12 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-sample", type=int, default=8192, help="points in the oracle's sample problem")
-    ap.add_argument("--max-refine", type=int, default=10)
+    ap.add_argument("--max-refine", type=int, default=10, help="GMRES-IR operator applications (mixed path)")
+    ap.add_argument("--no-stable-check", action="store_true",
+                    help="skip the mixed-vs-FP64 check on the N=65536 d=8 mixture (lambda=0.1)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB elementwise copy (reference for the HBM byte counters)")
+    ap.add_argument("--tol", type=float, default=1e-11, help="target relative residual of the refined solves")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built",
@@ -102,13 +107,15 @@ def main():
         b = time.perf_counter()
         f = tree.factorize(lam, prec)
         if prec == ak.ASKIT_MIXED:
-            f.set_refinement(args.max_refine, 1e-10)
+            f.set_refinement(args.max_refine, args.tol)
         torch.cuda.synchronize()
         cc = time.perf_counter()
         x = f.solve(B)
         torch.cuda.synchronize()
         e = time.perf_counter()
         info = f.info() if prec == ak.ASKIT_MIXED else None
+        if info is not None:
+            info["min_pivot_ratio"] = f.pivot_ratio()[0]
         out = dict(skel=b - a, factor=cc - b, solve=e - cc, info=info)
         if keep:
             return out, f, x
@@ -151,17 +158,29 @@ def main():
         x64 = f64.solve(B)
         torch.cuda.synchronize()
         e = time.perf_counter()
-        err = float(((xmx - x64).norm(dim=0) / x64.norm(dim=0)).max())
         r64 = B - f64.matvec(x64)
         eps64 = float((r64.norm(dim=0) / B.norm(dim=0)).max())
+        # the FP64 path refined against the same FP64 operator (GMRES-IR with
+        # the FP64 factors) is the reference the mixed result is compared with
+        f64.set_refinement(50, args.tol)
+        g0 = time.perf_counter()
+        xref = f64.solve(B)
+        torch.cuda.synchronize()
+        g1 = time.perf_counter()
+        info64 = f64.info()
+        info64["min_pivot_ratio"] = f64.pivot_ratio()[0]
+        err = float(((xmx - xref).norm(dim=0) / xref.norm(dim=0)).max())
+        err_direct = float(((xmx - x64).norm(dim=0) / x64.norm(dim=0)).max())
         res = dict(fp64_factor_s=t_skel + (b - a), fp64_factorize_only_s=b - a, fp64_solve_s=e - b,
-                   fp64_solves_per_s=args.nrhs / (e - b), mixed_vs_fp64_rel_err=err, fp64_residual=eps64,
+                   fp64_solves_per_s=args.nrhs / (e - b), fp64_residual=eps64,
+                   fp64_refined_solve_s=g1 - g0, fp64_refinement=info64,
+                   mixed_vs_fp64_rel_err=err, mixed_vs_fp64_direct_rel_err=err_direct,
                    speedup_factor_mixed_over_fp64=(t_skel + (b - a)) / (t_skel + t_fac),
                    speedup_factorize_only=(b - a) / t_fac)
-        log(f"[bench] fp64: factorize {b - a:.3f} s solve {e - b:.3f} s; mixed vs fp64 {err:.2e}; "
-            f"fp64 residual {eps64:.2e}")
+        log(f"[bench] fp64: factorize {b - a:.3f} s solve {e - b:.3f} s (residual {eps64:.2e}); refined "
+            f"{g1 - g0:.3f} s {info64}; mixed vs fp64 refined {err:.2e}, vs fp64 direct {err_direct:.2e}")
         f64.close()
-        del x64, r64
+        del x64, r64, xref
 
     # roofline of the dominant kernel (largest total time in the timed steps)
     D = tree.D
@@ -186,6 +205,18 @@ def main():
         roof = dict(bound="unknown", achieved=None, peak=None, unit=None, frac=None, traffic=None, kernel=dom,
                     avg_launch_ms=per_launch_ms)
 
+    stable = None
+    if not args.no_stable_check:
+        stable = stable_config_check(ak, torch, dev, args.tol)
+    if args.calibrate_copy:
+        x = torch.empty(1 << 27, dtype=torch.float64, device=dev).uniform_()
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy: 3 x (1 GiB read + 1 GiB write), torch.neg")
+        del x, y
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(c, args.cpu_sample, args.nrhs)
@@ -201,10 +232,46 @@ def main():
         "refinement": info, "tree_s": t_tree,
         **res,
         "roofline": roof,
+        "mixed_on_stable_config": stable,
         "cpu_baseline": cpu,
         "kernels_ms": {k: [round(v[0] / args.steps, 3), v[1] // args.steps] for k, v in top[:12]},
     }
     print(json.dumps(out))
+
+
+def stable_config_check(ak, torch, dev, tol):
+    """Mixed vs FP64 where the recursion is stable: N = 65,536 points of an
+    8-cluster mixture in 8-D (centres ~ U[-5,5]^8, sigma = 1), h = 1, lambda = 0.1,
+    m = 256, s = 128, 16 right-hand sides."""
+    import synth
+    c = synth.config(2)
+    X = torch.as_tensor(c["X"], device=dev)
+    B = torch.as_tensor(c["B"], device=dev)
+    t = ak.Tree(X, c["m"], c["s"], c["h"], n_samples=c["nsamp"], seed=c["seed"])
+    t.skeletonize()
+    out = {"workload": "gaussian-mixture N=65536 d=8 m=256 s=128 h=1 lambda=0.1 nrhs=16"}
+    res = {}
+    for name, prec in (("fp64", ak.ASKIT_FP64), ("mixed", ak.ASKIT_MIXED)):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        f = t.factorize(c["lam"], prec)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        f.set_refinement(50, tol)
+        x = f.solve(B)
+        torch.cuda.synchronize()
+        e = time.perf_counter()
+        res[name] = (x, f.info())
+        out[f"{name}_factorize_s"] = b - a
+        out[f"{name}_refined_solve_s"] = e - b
+        out[f"{name}_refinement"] = f.info()
+        f.close()
+    x64, xm = res["fp64"][0], res["mixed"][0]
+    out["mixed_vs_fp64_rel_err"] = float(((xm - x64).norm(dim=0) / x64.norm(dim=0)).max())
+    log(f"[bench] stable config: mixed vs fp64 {out['mixed_vs_fp64_rel_err']:.2e}, "
+        f"mixed refinement {out['mixed_refinement']}")
+    t.close()
+    return out
 
 
 def cpu_baseline(c, n_sample, nrhs):

@@ -108,10 +108,12 @@ askit_status askit_factorize(askit_tree t, double lambda, int32_t precision, voi
 /* X = (lambda I + Ktilde)^{-1} B (Alg. 3).  B, X: device, N x nrhs
  * column-major (ldb, ldx >= N); B and X may alias.  With refinement enabled
  * (the default for a MIXED factor, see askit_set_refinement) the result is
- * refined against the FP64 operator of askit_matvec until the update is below
- * refine_tol relative or max_refine steps; see askit_last_solve_info.  Without
- * refinement the call is asynchronous on `stream`; with it, `stream` is
- * synchronized once per refinement step. */
+ * refined against the FP64 operator of askit_matvec by restarted GMRES
+ * preconditioned with the stored factorization, until the relative residual
+ * |b - A x| / |b| of every column is below refine_tol or max_refine operator
+ * applications; see askit_last_solve_info.  Without refinement the call is
+ * asynchronous on `stream`; with it, `stream` is synchronized at every
+ * iteration. */
 askit_status askit_solve(askit_factor f, const double *B, int64_t ldb, int32_t nrhs, double *X, int64_t ldx,
                          void *stream);
 
@@ -127,22 +129,66 @@ askit_status askit_solve_transpose(askit_factor f, const double *B, int64_t ldb,
 askit_status askit_matvec(askit_factor f, int32_t which, const double *X, int64_t ldx, int32_t nrhs, double *Y,
                           int64_t ldy, void *stream);
 
-/* Iterative refinement controls (defaults: MIXED 10 steps, FP64 0 steps =
- * plain direct solve; tolerance 1e-10 on the relative update). */
+/* Refinement controls: max_refine = largest number of preconditioned
+ * operator applications (0 = plain direct solve; defaults: MIXED 100, FP64 0),
+ * refine_tol = target relative residual (default 1e-11). */
 askit_status askit_set_refinement(askit_factor f, int32_t max_refine, double refine_tol);
 
 typedef struct {
-    int32_t iterations;      /* refinement steps taken                       */
-    int32_t converged;       /* 1 if the update fell below refine_tol        */
-    double last_update;      /* max over columns of |dx| / |x| at the end   */
-    double residual;         /* max over columns of |b - A x| / |b|          */
+    int32_t iterations;        /* preconditioned operator applications       */
+    int32_t converged;         /* 1 if the residual reached refine_tol       */
+    double initial_residual;   /* max over columns of |b - A x0| / |b|, x0 =
+                                  the direct solve with the stored factors   */
+    double residual;           /* same for the returned x                    */
 } askit_solve_info;
 
 askit_status askit_last_solve_info(askit_factor f, askit_solve_info *info);
 
+/* Bandwidth of the factorizations made after this call, with the tree's
+ * skeletons and projections held fixed (the ID is not differentiated).  Used
+ * for derivatives in h and finite differences; a tree starts with options.h. */
+askit_status askit_tree_set_bandwidth(askit_tree t, double h);
+
+/* Adjoint scalars of the differentiation of x = A^{-1} b, A = lambda I +
+ * Ktilde(h): given x and z = A^{-T} g (both N x nrhs column-major, leading
+ * dimension ld, device), returns
+ *   dlambda = -sum_j z_j . x_j                   (dA/dlambda = I)
+ *   dh      = -sum_j z_j . (dKtilde/dh x_j)     (kernel blocks recomputed
+ *                                                 with dk/dh = k r^2 / h^3)
+ * so that dL/dlambda and dL/dh follow for a loss L with dL/dx = g.
+ * Synchronizes `stream`; outputs are HOST scalars. */
+askit_status askit_adjoint_scalars(askit_factor f, const double *X, const double *Z, int64_t ld, int32_t nrhs,
+                                   double *dlambda, double *dh, void *stream);
+
 /* Factor diagnostics: the smallest pivot ratio min|U_ii|/max|U_ii| over all
  * leaf and reduced-system LUs, and its node. */
 askit_status askit_factor_pivot_ratio(askit_factor f, double *ratio, int32_t *node);
+
+/* Batches of independent problems (level-batched execution).  Trees of a
+ * batch share rank, dimension and sample count; sizes, leaf sizes, depths,
+ * bandwidths and lambdas may differ.
+ *  - askit_skeletonize_batched: Alg. 1 on all trees, one launch per kernel
+ *    and tree height (distance from the leaves) over the nodes of all trees.
+ *  - askit_batch_create: allocates one factor per tree, builds the
+ *    factorization and solve plans over all trees (one launch per kernel and
+ *    height) and captures each in a hipGraph; nothing is computed yet.
+ *    lambdas: HOST array of count values; nrhs = right-hand sides per solve.
+ *  - askit_batch_factorize: replays the factorization graph on `stream`.
+ *  - askit_batch_check: pivot ratios of all factors (synchronizes).
+ *  - askit_batch_solve: B[i], X[i] (HOST arrays of count DEVICE pointers, each
+ *    N_i x nrhs column-major with ld = N_i) -> X[i] = A_i^{-1} B[i]; replays
+ *    the solve graph and synchronizes `stream` before returning.
+ *  - askit_batch_factor: borrowed handle of problem i (for matvec, transpose
+ *    solve, refinement); it is released by askit_batch_destroy. */
+typedef struct askit_batch_s *askit_batch;
+askit_status askit_skeletonize_batched(askit_tree *trees, int32_t count, void *stream);
+askit_status askit_batch_create(askit_tree *trees, int32_t count, const double *lambdas, int32_t precision,
+                                int32_t nrhs, askit_batch *out);
+askit_status askit_batch_factorize(askit_batch b, void *stream);
+askit_status askit_batch_check(askit_batch b, double *min_ratio, int32_t *problem, void *stream);
+askit_status askit_batch_solve(askit_batch b, const double *const *B, double *const *X, void *stream);
+askit_status askit_batch_factor(askit_batch b, int32_t i, askit_factor *f);
+void askit_batch_destroy(askit_batch b);
 
 /* Per-phase timings (ms) and sizes of the last calls on a handle, as JSON. */
 askit_status askit_get_stats(askit_tree t, askit_factor f, char *json, size_t cap);

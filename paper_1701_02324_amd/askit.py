@@ -23,7 +23,9 @@ EXPORTED = [
     "askit_skeletons_import", "askit_factorize", "askit_solve", "askit_solve_transpose", "askit_matvec",
     "askit_set_refinement", "askit_last_solve_info", "askit_factor_pivot_ratio", "askit_get_stats",
     "askit_last_error", "askit_tree_destroy", "askit_factor_destroy", "askit_profile_enable",
-    "askit_profile_report",
+    "askit_profile_report", "askit_tree_set_bandwidth", "askit_adjoint_scalars", "askit_skeletonize_batched",
+    "askit_batch_create", "askit_batch_factorize", "askit_batch_check", "askit_batch_solve", "askit_batch_factor",
+    "askit_batch_destroy",
 ]
 
 
@@ -40,8 +42,8 @@ class Options(ctypes.Structure):
 
 
 class SolveInfo(ctypes.Structure):
-    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("last_update", ctypes.c_double),
-                ("residual", ctypes.c_double)]
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("initial_residual", ctypes.c_double), ("residual", ctypes.c_double)]
 
 
 _lib = None
@@ -73,12 +75,23 @@ def load(path: str = LIB_PATH):
     L.askit_last_solve_info.argtypes = [_vp, ctypes.POINTER(SolveInfo)]
     L.askit_factor_pivot_ratio.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32)]
     L.askit_get_stats.argtypes = [_vp, _vp, ctypes.c_char_p, ctypes.c_size_t]
+    L.askit_tree_set_bandwidth.argtypes = [_vp, ctypes.c_double]
+    L.askit_adjoint_scalars.argtypes = [_vp, _vp, _vp, _i64, _i32, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double), _vp]
+    L.askit_skeletonize_batched.argtypes = [ctypes.POINTER(_vp), _i32, _vp]
+    L.askit_batch_create.argtypes = [ctypes.POINTER(_vp), _i32, ctypes.POINTER(ctypes.c_double), _i32, _i32,
+                                     ctypes.POINTER(_vp)]
+    L.askit_batch_factorize.argtypes = [_vp, _vp]
+    L.askit_batch_check.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32), _vp]
+    L.askit_batch_solve.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]
+    L.askit_batch_factor.argtypes = [_vp, _i32, ctypes.POINTER(_vp)]
+    L.askit_batch_destroy.argtypes = [_vp]
     L.askit_profile_enable.argtypes = [_i32]
     L.askit_profile_report.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
     L.askit_tree_destroy.argtypes = [_vp]
     L.askit_factor_destroy.argtypes = [_vp]
     for name in EXPORTED:
-        if name not in ("askit_last_error", "askit_tree_destroy", "askit_factor_destroy"):
+        if name not in ("askit_last_error", "askit_tree_destroy", "askit_factor_destroy", "askit_batch_destroy"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -184,6 +197,22 @@ def askit_matvec(factor, X, which=0, stream=None):
     return _apply(load().askit_matvec, factor, X, stream, int(which))
 
 
+def askit_tree_set_bandwidth(tree, h):
+    _check(load().askit_tree_set_bandwidth(tree, float(h)))
+
+
+def askit_adjoint_scalars(factor, X, Z, stream=None):
+    """(dlambda, dh) = (-sum z.x, -sum z.(dKtilde/dh x)) for N x nrhs tensors X, Z."""
+    Xc, _ = _colmajor(_dev64(X, "X"))
+    Zc, _ = _colmajor(_dev64(Z, "Z"))
+    nrhs, N = Xc.shape
+    a = ctypes.c_double()
+    b = ctypes.c_double()
+    _check(load().askit_adjoint_scalars(factor, _vp(Xc.data_ptr()), _vp(Zc.data_ptr()), N, nrhs, ctypes.byref(a),
+                                        ctypes.byref(b), _stream(stream)))
+    return a.value, b.value
+
+
 def askit_set_refinement(factor, max_refine, refine_tol):
     _check(load().askit_set_refinement(factor, int(max_refine), float(refine_tol)))
 
@@ -191,8 +220,8 @@ def askit_set_refinement(factor, max_refine, refine_tol):
 def askit_last_solve_info(factor):
     info = SolveInfo()
     _check(load().askit_last_solve_info(factor, ctypes.byref(info)))
-    return dict(iterations=info.iterations, converged=bool(info.converged), last_update=info.last_update,
-                residual=info.residual)
+    return dict(iterations=info.iterations, converged=bool(info.converged),
+                initial_residual=info.initial_residual, residual=info.residual)
 
 
 def askit_factor_pivot_ratio(factor):
@@ -265,6 +294,11 @@ class Tree:
     def factorize(self, lam, precision=ASKIT_FP64, stream=None):
         return Factor(self, lam, precision, stream)
 
+    def set_bandwidth(self, h):
+        """Bandwidth of subsequent factorizations (skeletons frozen)."""
+        askit_tree_set_bandwidth(self.handle, h)
+        self.hfac = float(h)
+
     def stats(self):
         return askit_get_stats(self.handle, None)
 
@@ -300,6 +334,9 @@ class Factor:
     def set_refinement(self, max_refine, tol):
         askit_set_refinement(self.handle, max_refine, tol)
 
+    def adjoint_scalars(self, X, Z, stream=None):
+        return askit_adjoint_scalars(self.handle, X, Z, stream)
+
     def info(self):
         return askit_last_solve_info(self.handle)
 
@@ -311,6 +348,87 @@ class Factor:
 
     def close(self):
         askit_factor_destroy(getattr(self, "handle", None))
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# batches of independent problems
+# ---------------------------------------------------------------------------
+
+def askit_skeletonize_batched(trees, stream=None):
+    arr = (_vp * len(trees))(*[t.handle for t in trees])
+    _check(load().askit_skeletonize_batched(arr, len(trees), _stream(stream)))
+
+
+def askit_batch_create(trees, lambdas, precision=ASKIT_FP64, nrhs=1):
+    arr = (_vp * len(trees))(*[t.handle for t in trees])
+    lam = (ctypes.c_double * len(trees))(*[float(x) for x in lambdas])
+    out = _vp()
+    _check(load().askit_batch_create(arr, len(trees), lam, int(precision), int(nrhs), ctypes.byref(out)))
+    return out
+
+
+def askit_batch_factorize(batch, stream=None):
+    _check(load().askit_batch_factorize(batch, _stream(stream)))
+
+
+def askit_batch_check(batch, stream=None):
+    r = ctypes.c_double()
+    p = _i32()
+    _check(load().askit_batch_check(batch, ctypes.byref(r), ctypes.byref(p), _stream(stream)))
+    return r.value, p.value
+
+
+def askit_batch_solve(batch, Bs, stream=None):
+    """Bs: list of N_i x nrhs CUDA tensors -> list of solutions."""
+    cols = [_colmajor(_dev64(B, "B"))[0] for B in Bs]
+    outs = [torch.empty_like(c) for c in cols]
+    pb = (_vp * len(cols))(*[c.data_ptr() for c in cols])
+    px = (_vp * len(cols))(*[o.data_ptr() for o in outs])
+    _check(load().askit_batch_solve(batch, pb, px, _stream(stream)))
+    return [o.t() for o in outs]
+
+
+def askit_batch_factor(batch, i):
+    f = _vp()
+    _check(load().askit_batch_factor(batch, int(i), ctypes.byref(f)))
+    return f
+
+
+def askit_batch_destroy(batch):
+    if batch:
+        load().askit_batch_destroy(batch)
+
+
+class Batch:
+    """Independent problems factorized and solved together (one launch per
+    kernel and tree height, replayed from hipGraphs)."""
+
+    def __init__(self, trees, lambdas, precision=ASKIT_FP64, nrhs=1):
+        self.trees = list(trees)
+        self.handle = askit_batch_create(self.trees, lambdas, precision, nrhs)
+        self.nrhs = nrhs
+
+    def factorize(self, stream=None):
+        askit_batch_factorize(self.handle, stream)
+
+    def check(self, stream=None):
+        return askit_batch_check(self.handle, stream)
+
+    def solve(self, Bs, stream=None):
+        return askit_batch_solve(self.handle, Bs, stream)
+
+    def factor_handle(self, i):
+        return askit_batch_factor(self.handle, i)
+
+    def close(self):
+        askit_batch_destroy(getattr(self, "handle", None))
         self.handle = None
 
     def __del__(self):

@@ -173,7 +173,9 @@ struct KmmBuild {
     int out_size = 8;
 };
 
-void kmm_add(KmmBuild &kb, KmmTask t, int kcap, int ncap, int64_t KC, int b_elem, char *ws) {
+// `off` counts the partial elements already handed out in the workspace `ws`
+// (one counter per workspace; the total is recorded in kb.ws_elems)
+void kmm_add(KmmBuild &kb, KmmTask t, int kcap, int ncap, int64_t KC, int b_elem, char *ws, int64_t &off) {
     const int nrt = (int)cdiv(t.rcap, 64), nct = (int)cdiv(ncap, kb.tc);
     const int64_t nch = std::max<int64_t>(1, cdiv(kcap, KC));
     if (nch == 1) {
@@ -187,7 +189,7 @@ void kmm_add(KmmBuild &kb, KmmTask t, int kcap, int ncap, int64_t KC, int b_elem
     }
     const int64_t per = (int64_t)t.rcap * ncap;
     RedTask rd{};
-    rd.src = ws + kb.ws_elems * kb.out_size;
+    rd.src = ws + off * kb.out_size;
     rd.pstride = per;
     rd.prs = ncap;
     rd.np = (int32_t)nch;
@@ -201,7 +203,7 @@ void kmm_add(KmmBuild &kb, KmmTask t, int kcap, int ncap, int64_t KC, int b_elem
         u.k0 = (int32_t)(c * KC);
         u.k1 = (int32_t)std::min<int64_t>(kcap, (c + 1) * KC);
         u.B = (const char *)t.B + (int64_t)u.k0 * t.ldb * b_elem;
-        u.C = ws + (kb.ws_elems + c * per) * kb.out_size;
+        u.C = ws + (off + c * per) * kb.out_size;
         u.crs = ncap;
         u.ccs = 1;
         u.op = OP_STORE;
@@ -211,7 +213,8 @@ void kmm_add(KmmBuild &kb, KmmTask t, int kcap, int ncap, int64_t KC, int b_elem
             for (int cc = 0; cc < nct; cc++) kb.items.push_back({ti, r, cc, 0});
     }
     kb.reds.push_back(rd);
-    kb.ws_elems += nch * per;
+    off += nch * per;
+    kb.ws_elems = std::max(kb.ws_elems, off);
 }
 
 struct GmmBuild {
@@ -224,7 +227,7 @@ struct GmmBuild {
 };
 
 // C(r, c) op= sum_k A(r, k) B(k, c); split of k into chunks of KC if kdim > KC
-void gmm_add(GmmBuild &gb, GmmTask t, int ncap, int64_t KC, char *ws) {
+void gmm_add(GmmBuild &gb, GmmTask t, int ncap, int64_t KC, char *ws, int64_t &off) {
     const int nrt = (int)cdiv(t.rows, 64), nct = (int)cdiv(ncap, gb.tc);
     const int64_t nch = std::max<int64_t>(1, cdiv(t.kdim, KC));
     if (nch == 1) {
@@ -236,7 +239,7 @@ void gmm_add(GmmBuild &gb, GmmTask t, int ncap, int64_t KC, char *ws) {
     }
     const int64_t per = (int64_t)t.rows * ncap;
     RedTask rd{};
-    rd.src = ws + gb.ws_elems * gb.elem;
+    rd.src = ws + off * gb.elem;
     rd.pstride = per;
     rd.prs = ncap;
     rd.np = (int32_t)nch;
@@ -251,7 +254,7 @@ void gmm_add(GmmBuild &gb, GmmTask t, int ncap, int64_t KC, char *ws) {
         u.kdim = (int32_t)std::min<int64_t>(t.kdim - k0, KC);
         u.A = (const char *)t.A + k0 * t.acs * gb.elem;
         u.B = (const char *)t.B + k0 * t.brs * gb.elem;
-        u.C = ws + (gb.ws_elems + c * per) * gb.elem;
+        u.C = ws + (off + c * per) * gb.elem;
         u.crs = ncap;
         u.ccs = 1;
         u.op = OP_STORE;
@@ -261,12 +264,16 @@ void gmm_add(GmmBuild &gb, GmmTask t, int ncap, int64_t KC, char *ws) {
             for (int cc = 0; cc < nct; cc++) gb.items.push_back({ti, r, cc, 0});
     }
     gb.reds.push_back(rd);
-    gb.ws_elems += nch * per;
+    off += nch * per;
+    gb.ws_elems = std::max(gb.ws_elems, off);
 }
 
-template <typename T, typename TO, int TC>
-hipError_t launch_kmm(const KmmTask *tasks, const TileItem *items, int nitems, int ncol, int d, hipStream_t st) {
-    hipLaunchKernelGGL((k_kmm<T, TO, TC>), dim3(nitems), dim3(256), 0, st, tasks, items, ncol, d);
+template <typename T, typename TB, typename TO>
+hipError_t launch_kmm(const KmmTask *tasks, const TileItem *items, int nitems, int ncol, int d, int tc,
+                      hipStream_t st) {
+    if (tc == 128) hipLaunchKernelGGL((k_kmm<T, TB, TO, 128>), dim3(nitems), dim3(256), 0, st, tasks, items, ncol, d);
+    else if (tc == 64) hipLaunchKernelGGL((k_kmm<T, TB, TO, 64>), dim3(nitems), dim3(256), 0, st, tasks, items, ncol, d);
+    else hipLaunchKernelGGL((k_kmm<T, TB, TO, 16>), dim3(nitems), dim3(256), 0, st, tasks, items, ncol, d);
     return hipGetLastError();
 }
 
@@ -276,9 +283,11 @@ hipError_t launch_gmm(const GmmTask *tasks, const TileItem *items, int nitems, i
     return hipGetLastError();
 }
 
-// finalize a kmm build into plan steps; tin/tout = element precisions
-askit_status kmm_commit(Plan &P, KmmBuild &kb, Prec tin, Prec tout, int d, int rows_red_max) {
+// finalize a kmm build into plan steps: tc = compute precision, tb = storage
+// of B, tout = output precision
+askit_status kmm_commit(Plan &P, KmmBuild &kb, Prec tin, Prec tout, int d, int rows_red_max, int tbin = -1) {
     if (kb.tasks.empty()) return ASKIT_OK;
+    const Prec tb = tbin < 0 ? tin : (Prec)tbin;
     DBuf *bt = P.own(), *bi = P.own();
     ST_TRY(upload(*bt, kb.tasks));
     ST_TRY(upload(*bi, kb.items));
@@ -286,19 +295,10 @@ askit_status kmm_commit(Plan &P, KmmBuild &kb, Prec tin, Prec tout, int d, int r
     const TileItem *ip = bi->as<TileItem>();
     const int nitems = (int)kb.items.size(), tc = kb.tc;
     P.add("k_kmm", [=](hipStream_t st, int ncol) -> hipError_t {
-        if (tin == P64) {
-            if (tc == 128) return launch_kmm<double, double, 128>(tp, ip, nitems, ncol, d, st);
-            if (tc == 64) return launch_kmm<double, double, 64>(tp, ip, nitems, ncol, d, st);
-            return launch_kmm<double, double, 16>(tp, ip, nitems, ncol, d, st);
-        }
-        if (tout == P64) {
-            if (tc == 128) return launch_kmm<float, double, 128>(tp, ip, nitems, ncol, d, st);
-            if (tc == 64) return launch_kmm<float, double, 64>(tp, ip, nitems, ncol, d, st);
-            return launch_kmm<float, double, 16>(tp, ip, nitems, ncol, d, st);
-        }
-        if (tc == 128) return launch_kmm<float, float, 128>(tp, ip, nitems, ncol, d, st);
-        if (tc == 64) return launch_kmm<float, float, 64>(tp, ip, nitems, ncol, d, st);
-        return launch_kmm<float, float, 16>(tp, ip, nitems, ncol, d, st);
+        if (tin == P64 && tb == P64) return launch_kmm<double, double, double>(tp, ip, nitems, ncol, d, tc, st);
+        if (tin == P64) return launch_kmm<double, float, double>(tp, ip, nitems, ncol, d, tc, st);
+        if (tout == P64) return launch_kmm<float, float, double>(tp, ip, nitems, ncol, d, tc, st);
+        return launch_kmm<float, float, float>(tp, ip, nitems, ncol, d, tc, st);
     });
     if (!kb.reds.empty()) {
         DBuf *br = P.own();
@@ -407,6 +407,20 @@ askit_status copy_commit(Plan &P, const std::vector<CopyTask> &v, Prec from, Pre
     return ASKIT_OK;
 }
 
+askit_status ident_commit(Plan &P, const std::vector<IdTask> &v, int n) {
+    if (v.empty()) return ASKIT_OK;
+    DBuf *b = P.own();
+    ST_TRY(upload(*b, v));
+    const IdTask *tp = b->as<IdTask>();
+    const int cnt = (int)v.size();
+    const int bpm = (int)cdiv((int64_t)n * n, 256);
+    P.add("k_identity", [=](hipStream_t st, int) -> hipError_t {
+        hipLaunchKernelGGL(k_identity, dim3(cnt * bpm), dim3(256), 0, st, tp, bpm);
+        return hipGetLastError();
+    });
+    return ASKIT_OK;
+}
+
 double ms_since(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -421,7 +435,8 @@ struct askit_tree_s {
     int d = 0, m = 0, s = 0, nsamp = 0, D = 0, cmax = 0, mmax = 0;
     int64_t nnodes = 0, problem = 0;
     uint64_t seed = 0;
-    double h = 1.0;
+    double h = 1.0;      // bandwidth of the skeletonization
+    double hfac = 1.0;   // bandwidth of the next factorization (skeletons frozen)
     std::vector<int64_t> nb, ne;  // host node ranges
     DBuf X, Xp, perm, dnb, dne;
     DBuf srank, trunc, skel, Pt, samp;
@@ -434,16 +449,17 @@ struct askit_tree_s {
 struct askit_factor_s {
     askit_tree t = nullptr;
     double lambda = 0;
+    double h = 1.0;
     Prec prec = P64;
     DBuf LU, piv, ratio, Xc, Xcf, ws, dinv;
     std::vector<std::unique_ptr<DBuf>> PH;  // levels 1..D
     int64_t leafLU = 0, zLU = 0;            // element offsets of the arenas
     // solve state
     int cap = 0;
-    DBuf W, TB, WX, WY, CB, wsS, R, Dx, nrm;
+    DBuf W, TB, WX, WY, CB, wsS, R, Dx, nrm, Vk, kpart, ksmall;
     std::unique_ptr<Plan> solve_plan, solvet_plan, mv_plan[2];
     int max_refine = 10;
-    double refine_tol = 1e-10;
+    double refine_tol = 1e-11;
     askit_solve_info info{};
     double min_ratio = 1.0;
     int min_node = -1;
@@ -520,6 +536,7 @@ askit_status askit_build_tree(const double *X, int64_t N, int32_t d, const askit
     t->seed = opt->seed;
     t->problem = opt->problem;
     t->h = opt->h;
+    t->hfac = opt->h;
     while ((int64_t)t->m * ((int64_t)1 << t->D) < N) t->D++;
     t->nnodes = ((int64_t)2 << t->D) - 1;
     t->mmax = (int)cdiv(N, (int64_t)1 << t->D);
@@ -585,8 +602,9 @@ askit_status askit_build_tree(const double *X, int64_t N, int32_t d, const askit
         hipLaunchKernelGGL(k_tree_chunk_scatter, dim3(grid1((int64_t)cnt * maxch * npair)), dim3(256), 0, st,
                            t->X.as<double>(), t->perm.as<int64_t>(), d, nb, ne, first, cnt, maxch, mu.as<double>(),
                            dpa.as<int16_t>(), dpc.as<int16_t>(), npair, part.as<double>());
-        hipLaunchKernelGGL(k_tree_axis, dim3(grid1(cnt, 64)), dim3(64), 0, st, nb, ne, first, cnt, maxch, d,
-                           dpa.as<int16_t>(), dpc.as<int16_t>(), npair, part.as<double>(), S.as<double>(),
+        hipLaunchKernelGGL(k_tree_scatter, dim3(grid1((int64_t)cnt * npair)), dim3(256), 0, st, nb, ne, first, cnt,
+                           maxch, d, dpa.as<int16_t>(), dpc.as<int16_t>(), npair, part.as<double>(), S.as<double>());
+        hipLaunchKernelGGL(k_tree_axis, dim3(grid1(cnt, 64)), dim3(64), 0, st, cnt, d, S.as<double>(),
                            axis.as<double>());
         const int bpn = (int)cdiv(nmax, 256);
         hipLaunchKernelGGL(k_tree_keys, dim3(cnt * bpn), dim3(256), 0, st, t->X.as<double>(), t->perm.as<int64_t>(), d,
@@ -617,6 +635,8 @@ askit_status askit_build_tree(const double *X, int64_t N, int32_t d, const askit
     ST_TRY(t->skel.alloc(sizeof(int32_t) * t->nnodes * t->s));
     ST_TRY(t->Pt.alloc(sizeof(double) * t->nnodes * t->cmax * t->s));
     HIP_TRY(hipMemsetAsync(t->srank.p, 0, sizeof(int32_t) * t->nnodes, st));
+    HIP_TRY(hipMemsetAsync(t->skel.p, 0xff, sizeof(int32_t) * t->nnodes * t->s, st));  // -1: no skeleton yet
+    HIP_TRY(hipMemsetAsync(t->trunc.p, 0, sizeof(int32_t) * t->nnodes, st));
     HIP_TRY(hipStreamSynchronize(st));
     t->t_tree = ms_since(t0);
     *out = t.release();
@@ -676,6 +696,7 @@ static askit_status skeletonize_impl(askit_tree *trees, int count, hipStream_t s
                 k.leaf = (l == t->D);
                 k.b = a.b;
                 k.n = (int32_t)(a.e - a.b);
+                k.cmax = t->cmax;
                 if (!k.leaf) {
                     k.skl = t->skel.as<int32_t>() + (2 * id + 1) * t->s;
                     k.skr = t->skel.as<int32_t>() + (2 * id + 2) * t->s;
@@ -714,7 +735,7 @@ static askit_status skeletonize_impl(askit_tree *trees, int count, hipStream_t s
             return hipGetLastError();
         }));
         HIP_TRY(timed("skel:k_qrcp", st, [&] {
-            hipLaunchKernelGGL(k_qrcp, dim3(n), dim3(512), 0, st, dsk.as<SkelTask>(), s, cmax, nsamp_max);
+            hipLaunchKernelGGL(k_qrcp, dim3(n), dim3(512), 0, st, dsk.as<SkelTask>(), s, nsamp_max);
             return hipGetLastError();
         }));
     }
@@ -806,70 +827,75 @@ askit_status askit_skeletons_import(askit_tree t, const int32_t *ids, const doub
 // ---------------------------------------------------------------------------
 static const int64_t kChunk = 4096;  // contraction chunk of the split products
 
-static askit_status factor_plan(askit_factor f, Plan &P) {
-    askit_tree t = f->t;
-    const int s = t->s, D = t->D, d = t->d, s2 = 2 * s;
-    const Prec pr = f->prec;
-    const int el = (int)f->elem();
-    const int64_t leaf0 = t->first(D);
-    // leaves: lambda I + K_aa, LU, Phat = A^{-1} P_{alpha alpha~}
+// Factorization plan for one or several factors of equal rank, dimension and
+// precision: one launch per kernel and tree height (distance from the
+// leaves), covering the nodes of every tree at that height.
+static askit_status factor_plan(const std::vector<askit_factor> &fs, Plan &P) {
+    askit_tree t0 = fs[0]->t;
+    const int s = t0->s, d = t0->d, s2 = 2 * s;
+    const Prec pr = fs[0]->prec;
+    const int el = (int)fs[0]->elem();
+    int Hmax = 0, mmax = 0;
+    for (auto f : fs) {
+        Hmax = std::max(Hmax, f->t->D);
+        mmax = std::max(mmax, f->t->mmax);
+    }
+    // height 0: leaves -- lambda I + K_aa, LU, Phat = A^{-1} P_{alpha alpha~}
     {
         std::vector<LeafTask> lt;
         std::vector<LuTask> lu, rs;
         std::vector<CopyTask> cp;
-        for (int64_t id = leaf0; id < t->nnodes; id++) {
-            LeafTask a{};
-            a.X = t->Xp.as<double>();
-            a.b = t->nb[id];
-            a.n = (int32_t)(t->ne[id] - t->nb[id]);
-            a.lda = t->mmax;
-            a.A = f->lu_of(id);
-            a.scale = -1.0 / (2.0 * t->h * t->h);
-            a.lambda = f->lambda;
-            lt.push_back(a);
-            LuTask u{};
-            u.A = a.A;
-            u.piv = f->piv_of(id);
-            u.dinv = f->dinv_of(id);
-            u.n = a.n;
-            u.lda = t->mmax;
-            u.ratio = f->ratio.as<double>() + id;
-            lu.push_back(u);
-            if (D > 0) {
-                CopyTask c{};
-                c.src = t->Pt.as<double>() + id * (int64_t)t->cmax * s;
-                c.dst = (char *)f->ph(D) + t->nb[id] * s * el;
-                c.sld = s;
-                c.dld = s;
-                c.rows = a.n;
-                c.cols = s;
-                cp.push_back(c);
-                u.B = c.dst;
-                u.ldb = s;
-                rs.push_back(u);
+        for (auto f : fs) {
+            askit_tree t = f->t;
+            const int D = t->D;
+            for (int64_t id = t->first(D); id < t->nnodes; id++) {
+                LeafTask a{};
+                a.X = t->Xp.as<double>();
+                a.b = t->nb[id];
+                a.n = (int32_t)(t->ne[id] - t->nb[id]);
+                a.lda = t->mmax;
+                a.A = f->lu_of(id);
+                a.scale = -1.0 / (2.0 * f->h * f->h);
+                a.lambda = f->lambda;
+                lt.push_back(a);
+                LuTask u{};
+                u.A = a.A;
+                u.piv = f->piv_of(id);
+                u.dinv = f->dinv_of(id);
+                u.n = a.n;
+                u.lda = t->mmax;
+                u.ratio = f->ratio.as<double>() + id;
+                lu.push_back(u);
+                if (D > 0) {
+                    CopyTask c{};
+                    c.src = t->Pt.as<double>() + id * (int64_t)t->cmax * s;
+                    c.dst = (char *)f->ph(D) + t->nb[id] * s * el;
+                    c.sld = s;
+                    c.dld = s;
+                    c.rows = a.n;
+                    c.cols = s;
+                    cp.push_back(c);
+                    u.B = c.dst;
+                    u.ldb = s;
+                    rs.push_back(u);
+                }
             }
         }
         DBuf *b = P.own();
         ST_TRY(upload(*b, lt));
         const LeafTask *lp = b->as<LeafTask>();
-        const int nl = (int)lt.size(), mm = t->mmax;
+        const int nl = (int)lt.size(), mm = mmax;
         P.add("k_leaf_block", [=](hipStream_t st, int) -> hipError_t {
             hipLaunchKernelGGL(k_leaf_block, dim3(nl * mm), dim3(256), 0, st, lp, mm, d);
             return hipGetLastError();
         });
         ST_TRY(lu_commit(P, lu));
-        ST_TRY(copy_commit(P, cp, P64, pr, t->mmax, s));
+        ST_TRY(copy_commit(P, cp, P64, pr, mmax, s));
         ST_TRY(getrs_commit(P, rs, pr, false, s));
     }
-    // internal levels, bottom-up
-    for (int l = D - 1; l >= 0; l--) {
-        const int64_t f0 = t->first(l), cnt = (int64_t)1 << l;
-        double *Z0 = f->lu_of(f0);
-        P.add("k_identity", [=](hipStream_t st, int) -> hipError_t {
-            hipLaunchKernelGGL(k_identity, dim3(grid1((int64_t)s2 * s2 * cnt)), dim3(256), 0, st, Z0, s2,
-                               (int64_t)s2 * s2, (int)cnt);
-            return hipGetLastError();
-        });
+    // heights 1 .. Hmax: internal nodes, bottom-up
+    for (int hgt = 1; hgt <= Hmax; hgt++) {
+        std::vector<IdTask> ident;
         KmmBuild kb;
         kb.tc = s >= 128 ? 128 : (s >= 64 ? 64 : 16);
         kb.out_size = 8;
@@ -878,78 +904,88 @@ static askit_status factor_plan(askit_factor f, Plan &P) {
         GmmBuild gb;
         gb.tc = kb.tc;
         gb.elem = el;
-        for (int64_t id = f0; id < f0 + cnt; id++) {
-            const int64_t lc = 2 * id + 1, rc = 2 * id + 2;
-            double *Z = f->lu_of(id);
-            for (int side = 0; side < 2; side++) {
-                const int64_t a = side ? rc : lc, o = side ? lc : rc;  // skeleton of a vs points of o
-                KmmTask k{};
-                k.X = t->Xp.as<double>();
-                k.R.idx = t->skel.as<int32_t>() + a * s;
-                k.R.cnt = t->srank.as<int32_t>() + a;
-                k.R.n = s;
-                k.S.base = t->nb[o];
-                k.S.n = (int32_t)(t->ne[o] - t->nb[o]);
-                k.B = (const char *)f->ph(l + 1) + t->nb[o] * s * el;
-                k.ldb = s;
-                k.C = side ? Z + s : Z + (int64_t)s * s2;
-                k.crs = 1;
-                k.ccs = s2;
-                k.scale = -1.0 / (2.0 * t->h * t->h);
-                k.op = OP_STORE;
-                k.rcap = s;
-                kmm_add(kb, k, k.S.n, s, kChunk, el, f->ws.as<char>());
-            }
-            LuTask u{};
-            u.A = Z;
-            u.piv = f->piv_of(id);
-            u.dinv = f->dinv_of(id);
-            u.n = s2;
-            u.lda = s2;
-            u.ratio = f->ratio.as<double>() + id;
-            lu.push_back(u);
-            if (l >= 1) {
-                double *xc = f->Xc.as<double>() + (id - f0) * (int64_t)s2 * s;
-                CopyTask c{};
-                c.src = t->Pt.as<double>() + id * (int64_t)t->cmax * s;
-                c.dst = xc;
-                c.sld = s;
-                c.dld = s;
-                c.rows = s2;
-                c.cols = s;
-                cp.push_back(c);
-                u.B = xc;
-                u.ldb = s;
-                rs.push_back(u);
-                const void *xb = xc;
-                if (pr == P32) {
-                    float *xf = f->Xcf.as<float>() + (id - f0) * (int64_t)s2 * s;
-                    CopyTask c2 = c;
-                    c2.src = xc;
-                    c2.dst = xf;
-                    cp32.push_back(c2);
-                    xb = xf;
-                }
+        for (auto f : fs) {
+            askit_tree t = f->t;
+            const int l = t->D - hgt;
+            if (l < 0) continue;
+            const int64_t f0 = t->first(l), cnt = (int64_t)1 << l;
+            int64_t wsoff = 0;
+            for (int64_t id = f0; id < f0 + cnt; id++) {
+                const int64_t lc = 2 * id + 1, rc = 2 * id + 2;
+                double *Z = f->lu_of(id);
+                ident.push_back({Z, s2, 0});
                 for (int side = 0; side < 2; side++) {
-                    const int64_t ch = side ? rc : lc;
-                    GmmTask g{};
-                    g.A = (const char *)f->ph(l + 1) + t->nb[ch] * s * el;
-                    g.ars = s;
-                    g.acs = 1;
-                    g.B = (const char *)xb + (int64_t)side * s * s * el;
-                    g.brs = s;
-                    g.bcs = 1;
-                    g.C = (char *)f->ph(l) + t->nb[ch] * s * el;
-                    g.crs = s;
-                    g.ccs = 1;
-                    g.rows = (int32_t)(t->ne[ch] - t->nb[ch]);
-                    g.kdim = s;
-                    g.op = OP_STORE;
-                    gmm_add(gb, g, s, 1 << 30, nullptr);
+                    const int64_t a = side ? rc : lc, o = side ? lc : rc;  // skeleton of a vs points of o
+                    KmmTask k{};
+                    k.X = t->Xp.as<double>();
+                    k.R.idx = t->skel.as<int32_t>() + a * s;
+                    k.R.cnt = t->srank.as<int32_t>() + a;
+                    k.R.n = s;
+                    k.S.base = t->nb[o];
+                    k.S.n = (int32_t)(t->ne[o] - t->nb[o]);
+                    k.B = (const char *)f->ph(l + 1) + t->nb[o] * s * el;
+                    k.ldb = s;
+                    k.C = side ? Z + s : Z + (int64_t)s * s2;
+                    k.crs = 1;
+                    k.ccs = s2;
+                    k.scale = -1.0 / (2.0 * f->h * f->h);
+                    k.op = OP_STORE;
+                    k.rcap = s;
+                    kmm_add(kb, k, k.S.n, s, kChunk, el, f->ws.as<char>(), wsoff);
+                }
+                LuTask u{};
+                u.A = Z;
+                u.piv = f->piv_of(id);
+                u.dinv = f->dinv_of(id);
+                u.n = s2;
+                u.lda = s2;
+                u.ratio = f->ratio.as<double>() + id;
+                lu.push_back(u);
+                if (l >= 1) {
+                    double *xc = f->Xc.as<double>() + (id - f0) * (int64_t)s2 * s;
+                    CopyTask c{};
+                    c.src = t->Pt.as<double>() + id * (int64_t)t->cmax * s;
+                    c.dst = xc;
+                    c.sld = s;
+                    c.dld = s;
+                    c.rows = s2;
+                    c.cols = s;
+                    cp.push_back(c);
+                    u.B = xc;
+                    u.ldb = s;
+                    rs.push_back(u);
+                    const void *xb = xc;
+                    if (pr == P32) {
+                        float *xf = f->Xcf.as<float>() + (id - f0) * (int64_t)s2 * s;
+                        CopyTask c2 = c;
+                        c2.src = xc;
+                        c2.dst = xf;
+                        cp32.push_back(c2);
+                        xb = xf;
+                    }
+                    for (int side = 0; side < 2; side++) {
+                        const int64_t ch = side ? rc : lc;
+                        GmmTask g{};
+                        g.A = (const char *)f->ph(l + 1) + t->nb[ch] * s * el;
+                        g.ars = s;
+                        g.acs = 1;
+                        g.B = (const char *)xb + (int64_t)side * s * s * el;
+                        g.brs = s;
+                        g.bcs = 1;
+                        g.C = (char *)f->ph(l) + t->nb[ch] * s * el;
+                        g.crs = s;
+                        g.ccs = 1;
+                        g.rows = (int32_t)(t->ne[ch] - t->nb[ch]);
+                        g.kdim = s;
+                        g.op = OP_STORE;
+                        int64_t none = 0;
+                        gmm_add(gb, g, s, 1 << 30, nullptr, none);
+                    }
                 }
             }
+            if (wsoff * 8 > (int64_t)f->ws.bytes) return fail(ASKIT_ERR_STATE, "internal: workspace too small");
         }
-        if (kb.ws_elems * 8 > (int64_t)f->ws.bytes) return fail(ASKIT_ERR_STATE, "internal: workspace too small");
+        ST_TRY(ident_commit(P, ident, s2));
         ST_TRY(kmm_commit(P, kb, pr, P64, d, s));
         ST_TRY(lu_commit(P, lu));
         ST_TRY(copy_commit(P, cp, P64, P64, s2, s));
@@ -977,12 +1013,14 @@ static int64_t split_ws_elems(askit_tree t, int ncol, int64_t KC) {
     return worst;
 }
 
-static askit_status factorize_impl(askit_tree t, double lambda, int precision, hipStream_t st, askit_factor *out) {
-    std::unique_ptr<askit_factor_s> f(new askit_factor_s());
+// allocation of a factor's arenas (no work enqueued)
+static askit_status factor_alloc(askit_tree t, double lambda, int precision, std::unique_ptr<askit_factor_s> &f) {
+    f.reset(new askit_factor_s());
     f->t = t;
     f->lambda = lambda;
+    f->h = t->hfac;
     f->prec = precision == ASKIT_MIXED ? P32 : P64;
-    f->max_refine = f->prec == P32 ? 10 : 0;
+    f->max_refine = f->prec == P32 ? 100 : 0;
     const int s = t->s, D = t->D, s2 = 2 * s;
     const int64_t leaf0 = t->first(D), nleaf = (int64_t)1 << D;
     f->leafLU = 0;
@@ -999,25 +1037,43 @@ static askit_status factorize_impl(askit_tree t, double lambda, int precision, h
     ST_TRY(f->Xc.alloc(sizeof(double) * lvl_max * s2 * s));
     if (f->prec == P32) ST_TRY(f->Xcf.alloc(sizeof(float) * lvl_max * s2 * s));
     ST_TRY(f->ws.alloc(sizeof(double) * std::max<int64_t>(1, split_ws_elems(t, s, kChunk))));
-    Plan P;
-    P.tag = "factor";
-    ST_TRY(factor_plan(f.get(), P));
-    HIP_TRY(P.run(st, s));
+    return ASKIT_OK;
+}
+
+// smallest pivot ratio of a finished factorization (synchronizes `st`)
+static askit_status factor_ratio(askit_factor f, hipStream_t st) {
+    askit_tree t = f->t;
     std::vector<double> ratio(t->nnodes);
     HIP_TRY(hipMemcpyAsync(ratio.data(), f->ratio.p, sizeof(double) * t->nnodes, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     f->min_ratio = 1.0;
+    f->min_node = -1;
     for (int64_t id = 0; id < t->nnodes; id++) {
         if (ratio[id] < f->min_ratio) {
             f->min_ratio = ratio[id];
             f->min_node = (int)id;
         }
     }
+    return ASKIT_OK;
+}
+
+static askit_status ratio_status(askit_factor f) {
+    if (f->min_ratio == 0.0) return fail(ASKIT_ERR_SINGULAR, "exactly singular pivot in a leaf or reduced system");
+    if (f->min_ratio < 1e-12) return fail(ASKIT_WARN_ILLCOND, "pivot ratio below 1e-12: factorization unstable");
+    return ASKIT_OK;
+}
+
+static askit_status factorize_impl(askit_tree t, double lambda, int precision, hipStream_t st, askit_factor *out) {
+    std::unique_ptr<askit_factor_s> f;
+    ST_TRY(factor_alloc(t, lambda, precision, f));
+    Plan P;
+    P.tag = "factor";
+    ST_TRY(factor_plan({f.get()}, P));
+    HIP_TRY(P.run(st, t->s));
+    ST_TRY(factor_ratio(f.get(), st));
     t->refs++;
     *out = f.release();
-    if ((*out)->min_ratio == 0.0) return fail(ASKIT_ERR_SINGULAR, "exactly singular pivot in a leaf or reduced system");
-    if ((*out)->min_ratio < 1e-12) return fail(ASKIT_WARN_ILLCOND, "pivot ratio below 1e-12: factorization unstable");
-    return ASKIT_OK;
+    return ratio_status(*out);
 }
 
 askit_status askit_factorize(askit_tree t, double lambda, int32_t precision, void *stream, askit_factor *out) {
@@ -1073,26 +1129,34 @@ static askit_status ensure_cap(askit_factor f, int nrhs) {
     return ASKIT_OK;
 }
 
-static askit_status solve_plan(askit_factor f, Plan &P) {
-    askit_tree t = f->t;
-    const int s = t->s, D = t->D, d = t->d, cap = f->cap, s2 = 2 * s;
-    const Prec pr = f->prec;
-    const int el = (int)f->elem();
-    char *W = f->W.as<char>();
+// Solve plan (Alg. 3) for one or several factors sharing rank, dimension,
+// precision and right-hand-side capacity: leaf LU solves of every tree in one
+// launch, then per height the node steps of every tree.
+static askit_status solve_plan(const std::vector<askit_factor> &fs, Plan &P) {
+    askit_tree t0 = fs[0]->t;
+    const int s = t0->s, d = t0->d, cap = fs[0]->cap, s2 = 2 * s;
+    const Prec pr = fs[0]->prec;
+    const int el = (int)fs[0]->elem();
+    int Hmax = 0;
+    for (auto f : fs) Hmax = std::max(Hmax, f->t->D);
     std::vector<LuTask> leaves;
-    for (int64_t id = t->first(D); id < t->nnodes; id++) {
-        LuTask u{};
-        u.A = f->lu_of(id);
-        u.piv = f->piv_of(id);
-        u.dinv = f->dinv_of(id);
-        u.n = (int32_t)(t->ne[id] - t->nb[id]);
-        u.lda = t->mmax;
-        u.B = W + t->nb[id] * cap * el;
-        u.ldb = cap;
-        leaves.push_back(u);
+    for (auto f : fs) {
+        askit_tree t = f->t;
+        char *W = f->W.as<char>();
+        for (int64_t id = t->first(t->D); id < t->nnodes; id++) {
+            LuTask u{};
+            u.A = f->lu_of(id);
+            u.piv = f->piv_of(id);
+            u.dinv = f->dinv_of(id);
+            u.n = (int32_t)(t->ne[id] - t->nb[id]);
+            u.lda = t->mmax;
+            u.B = W + t->nb[id] * cap * el;
+            u.ldb = cap;
+            leaves.push_back(u);
+        }
     }
     ST_TRY(getrs_commit(P, leaves, pr, false, 0));
-    for (int l = D - 1; l >= 0; l--) {
+    for (int hgt = 1; hgt <= Hmax; hgt++) {
         KmmBuild kb;
         kb.tc = cap >= 128 ? 128 : (cap >= 64 ? 64 : 16);
         kb.out_size = el;
@@ -1100,53 +1164,61 @@ static askit_status solve_plan(askit_factor f, Plan &P) {
         gb.tc = kb.tc;
         gb.elem = el;
         std::vector<LuTask> zs;
-        for (int64_t id = t->first(l); id < t->first(l + 1); id++) {
-            const int64_t lc = 2 * id + 1, rc = 2 * id + 2;
-            char *tb = f->TB.as<char>() + id * (int64_t)s2 * cap * el;
-            for (int side = 0; side < 2; side++) {
-                const int64_t a = side ? rc : lc, o = side ? lc : rc;
-                KmmTask k{};
-                k.X = t->Xp.as<double>();
-                k.R.idx = t->skel.as<int32_t>() + a * s;
-                k.R.cnt = t->srank.as<int32_t>() + a;
-                k.R.n = s;
-                k.S.base = t->nb[o];
-                k.S.n = (int32_t)(t->ne[o] - t->nb[o]);
-                k.B = W + t->nb[o] * cap * el;
-                k.ldb = cap;
-                k.C = tb + (int64_t)side * s * cap * el;
-                k.crs = cap;
-                k.ccs = 1;
-                k.scale = -1.0 / (2.0 * t->h * t->h);
-                k.op = OP_STORE;
-                k.rcap = s;
-                kmm_add(kb, k, k.S.n, cap, kChunk, el, f->wsS.as<char>());
-            }
-            LuTask u{};
-            u.A = f->lu_of(id);
-            u.piv = f->piv_of(id);
-            u.dinv = f->dinv_of(id);
-            u.n = s2;
-            u.lda = s2;
-            u.B = tb;
-            u.ldb = cap;
-            zs.push_back(u);
-            for (int side = 0; side < 2; side++) {
-                const int64_t ch = side ? rc : lc;
-                GmmTask g{};
-                g.A = (const char *)f->ph(l + 1) + t->nb[ch] * s * el;
-                g.ars = s;
-                g.acs = 1;
-                g.B = tb + (int64_t)side * s * cap * el;
-                g.brs = cap;
-                g.bcs = 1;
-                g.C = W + t->nb[ch] * cap * el;
-                g.crs = cap;
-                g.ccs = 1;
-                g.rows = (int32_t)(t->ne[ch] - t->nb[ch]);
-                g.kdim = s;
-                g.op = OP_SUB;
-                gmm_add(gb, g, cap, 1 << 30, nullptr);
+        for (auto f : fs) {
+            askit_tree t = f->t;
+            const int l = t->D - hgt;
+            if (l < 0) continue;
+            char *W = f->W.as<char>();
+            int64_t wsoff = 0;
+            for (int64_t id = t->first(l); id < t->first(l + 1); id++) {
+                const int64_t lc = 2 * id + 1, rc = 2 * id + 2;
+                char *tb = f->TB.as<char>() + id * (int64_t)s2 * cap * el;
+                for (int side = 0; side < 2; side++) {
+                    const int64_t a = side ? rc : lc, o = side ? lc : rc;
+                    KmmTask k{};
+                    k.X = t->Xp.as<double>();
+                    k.R.idx = t->skel.as<int32_t>() + a * s;
+                    k.R.cnt = t->srank.as<int32_t>() + a;
+                    k.R.n = s;
+                    k.S.base = t->nb[o];
+                    k.S.n = (int32_t)(t->ne[o] - t->nb[o]);
+                    k.B = W + t->nb[o] * cap * el;
+                    k.ldb = cap;
+                    k.C = tb + (int64_t)side * s * cap * el;
+                    k.crs = cap;
+                    k.ccs = 1;
+                    k.scale = -1.0 / (2.0 * f->h * f->h);
+                    k.op = OP_STORE;
+                    k.rcap = s;
+                    kmm_add(kb, k, k.S.n, cap, kChunk, el, f->wsS.as<char>(), wsoff);
+                }
+                LuTask u{};
+                u.A = f->lu_of(id);
+                u.piv = f->piv_of(id);
+                u.dinv = f->dinv_of(id);
+                u.n = s2;
+                u.lda = s2;
+                u.B = tb;
+                u.ldb = cap;
+                zs.push_back(u);
+                for (int side = 0; side < 2; side++) {
+                    const int64_t ch = side ? rc : lc;
+                    GmmTask g{};
+                    g.A = (const char *)f->ph(l + 1) + t->nb[ch] * s * el;
+                    g.ars = s;
+                    g.acs = 1;
+                    g.B = tb + (int64_t)side * s * cap * el;
+                    g.brs = cap;
+                    g.bcs = 1;
+                    g.C = W + t->nb[ch] * cap * el;
+                    g.crs = cap;
+                    g.ccs = 1;
+                    g.rows = (int32_t)(t->ne[ch] - t->nb[ch]);
+                    g.kdim = s;
+                    g.op = OP_SUB;
+                    int64_t none = 0;
+                    gmm_add(gb, g, cap, 1 << 30, nullptr, none);
+                }
             }
         }
         ST_TRY(kmm_commit(P, kb, pr, pr, d, s));
@@ -1170,6 +1242,7 @@ static askit_status solvet_plan(askit_factor f, Plan &P) {
         kb.tc = gb.tc;
         kb.out_size = el;
         std::vector<LuTask> zs;
+        int64_t wsoff = 0, none = 0;
         for (int64_t id = t->first(l); id < t->first(l + 1); id++) {
             const int64_t lc = 2 * id + 1, rc = 2 * id + 2;
             char *tb = f->TB.as<char>() + id * (int64_t)s2 * cap * el;
@@ -1188,7 +1261,7 @@ static askit_status solvet_plan(askit_factor f, Plan &P) {
                 g.rows = s;
                 g.kdim = (int32_t)(t->ne[ch] - t->nb[ch]);
                 g.op = OP_STORE;
-                gmm_add(gb, g, cap, kChunk, f->wsS.as<char>());
+                gmm_add(gb, g, cap, kChunk, f->wsS.as<char>(), wsoff);
             }
             LuTask u{};
             u.A = f->lu_of(id);
@@ -1213,10 +1286,10 @@ static askit_status solvet_plan(askit_factor f, Plan &P) {
                 k.C = W + t->nb[ch] * cap * el;
                 k.crs = cap;
                 k.ccs = 1;
-                k.scale = -1.0 / (2.0 * t->h * t->h);
+                k.scale = -1.0 / (2.0 * f->h * f->h);
                 k.op = OP_SUB;
                 k.rcap = k.R.n;
-                kmm_add(kb, k, s, cap, 1 << 30, el, nullptr);
+                kmm_add(kb, k, s, cap, 1 << 30, el, nullptr, none);
             }
         }
         ST_TRY(gmm_commit(P, gb, pr, s));
@@ -1244,10 +1317,11 @@ static askit_status matvec_plan(askit_factor f, int which, Plan &P) {
     askit_tree t = f->t;
     const int s = t->s, D = t->D, d = t->d, cap = f->cap;
     double *WX = f->WX.as<double>(), *WY = f->WY.as<double>(), *CB = f->CB.as<double>();
-    const double scale = -1.0 / (2.0 * t->h * t->h);
+    const double scale = -1.0 / (2.0 * f->h * f->h);
     {  // leaves: exact diagonal blocks
         KmmBuild kb;
         kb.tc = cap >= 128 ? 128 : (cap >= 64 ? 64 : 16);
+        int64_t wsoff = 0;
         for (int64_t id = t->first(D); id < t->nnodes; id++) {
             KmmTask k{};
             k.X = t->Xp.as<double>();
@@ -1260,11 +1334,11 @@ static askit_status matvec_plan(askit_factor f, int which, Plan &P) {
             k.crs = cap;
             k.ccs = 1;
             k.scale = scale;
-            k.hinv = 1.0 / t->h;
+            k.hinv = 1.0 / f->h;
             k.which = which;
             k.op = OP_STORE;
             k.rcap = k.R.n;
-            kmm_add(kb, k, k.S.n, cap, 1 << 30, 8, nullptr);
+            kmm_add(kb, k, k.S.n, cap, 1 << 30, 8, nullptr, wsoff);
         }
         ST_TRY(kmm_commit(P, kb, P64, P64, d, 0));
         if (!which) {
@@ -1282,6 +1356,7 @@ static askit_status matvec_plan(askit_factor f, int which, Plan &P) {
     for (int l = 0; l < D; l++) {
         KmmBuild kl;
         kl.tc = cap >= 128 ? 128 : (cap >= 64 ? 64 : 16);
+        int64_t wsoff = 0;
         for (int64_t id = t->first(l); id < t->first(l + 1); id++) {
             const int64_t lc = 2 * id + 1, rc = 2 * id + 2;
             for (int side = 0; side < 2; side++) {
@@ -1299,11 +1374,11 @@ static askit_status matvec_plan(askit_factor f, int which, Plan &P) {
                 k.crs = cap;
                 k.ccs = 1;
                 k.scale = scale;
-                k.hinv = 1.0 / t->h;
+                k.hinv = 1.0 / f->h;
                 k.which = which;
                 k.op = OP_STORE;
                 k.rcap = s;
-                kmm_add(kl, k, k.S.n, cap, kChunk, 8, f->wsS.as<char>());
+                kmm_add(kl, k, k.S.n, cap, kChunk, 8, f->wsS.as<char>(), wsoff);
             }
         }
         ST_TRY(kmm_commit(P, kl, P64, P64, d, s));
@@ -1312,6 +1387,7 @@ static askit_status matvec_plan(askit_factor f, int which, Plan &P) {
     for (int l = 1; l < D; l++) {
         GmmBuild gb;
         gb.tc = cap >= 128 ? 128 : (cap >= 64 ? 64 : 16);
+        int64_t wsoff = 0;
         for (int64_t id = t->first(l); id < t->first(l + 1); id++) {
             for (int side = 0; side < 2; side++) {
                 GmmTask g{};
@@ -1327,7 +1403,7 @@ static askit_status matvec_plan(askit_factor f, int which, Plan &P) {
                 g.rows = s;
                 g.kdim = s;
                 g.op = OP_ADD;
-                gmm_add(gb, g, cap, 1 << 30, nullptr);
+                gmm_add(gb, g, cap, 1 << 30, nullptr, wsoff);
             }
         }
         ST_TRY(gmm_commit(P, gb, P64, 0));
@@ -1335,6 +1411,7 @@ static askit_status matvec_plan(askit_factor f, int which, Plan &P) {
     {  // leaves: y_a += P_{alpha alpha~} c_a
         GmmBuild gb;
         gb.tc = cap >= 128 ? 128 : (cap >= 64 ? 64 : 16);
+        int64_t wsoff = 0;
         for (int64_t id = t->first(D); id < t->nnodes; id++) {
             GmmTask g{};
             g.A = t->Pt.as<double>() + id * (int64_t)t->cmax * s;
@@ -1349,7 +1426,7 @@ static askit_status matvec_plan(askit_factor f, int which, Plan &P) {
             g.rows = (int32_t)(t->ne[id] - t->nb[id]);
             g.kdim = s;
             g.op = OP_ADD;
-            gmm_add(gb, g, cap, 1 << 30, nullptr);
+            gmm_add(gb, g, cap, 1 << 30, nullptr, wsoff);
         }
         ST_TRY(gmm_commit(P, gb, P64, 0));
     }
@@ -1374,7 +1451,7 @@ static askit_status apply_inverse(askit_factor f, const double *B, int64_t ldb, 
     if (!pl) {
         pl.reset(new Plan());
         pl->tag = trans ? "solve_t" : "solve";
-        ST_TRY(trans ? solvet_plan(f, *pl) : solve_plan(f, *pl));
+        ST_TRY(trans ? solvet_plan(f, *pl) : solve_plan({f}, *pl));
     }
     const int64_t N = t->N;
     if (f->prec == P64)
@@ -1436,6 +1513,168 @@ static askit_status colratio(askit_factor f, const double *U, int64_t ldu, const
     return ASKIT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Refinement against the FP64 operator: restarted GMRES on (lambda I +
+// Ktilde) x = b, right-preconditioned with the stored factorization (GMRES-IR,
+// Carson & Higham 2018).  Plain refinement x += Ahat^{-1}(b - A x) diverges
+// once the factorization error times the growth of the recursion exceeds one;
+// the Krylov form keeps converging as long as the preconditioned spectrum is
+// clustered.  All columns iterate in lockstep; the small Hessenberg systems
+// are solved on the host.
+// ---------------------------------------------------------------------------
+static const int kRestart = 30;
+
+// out[j * nrhs + c] = <V_j(:, c), W(:, c)>, j < nv (device -> host)
+static askit_status mdot(askit_factor f, const double *V, const double *W, int nv, int nrhs, hipStream_t st,
+                         std::vector<double> &out) {
+    const int64_t N = f->t->N;
+    const int64_t chunk = std::max<int64_t>(4096, cdiv(N, 256));
+    const int nchunk = (int)cdiv(N, chunk);
+    const int njc = nv * nrhs;
+    if (f->kpart.bytes < sizeof(double) * ((size_t)njc * nchunk + njc)) {
+        HIP_TRY(hipStreamSynchronize(st));
+        ST_TRY(f->kpart.alloc(sizeof(double) * ((size_t)njc * nchunk + njc) * 2));
+    }
+    double *part = f->kpart.as<double>(), *res = part + (size_t)njc * nchunk;
+    hipLaunchKernelGGL(k_mdot_part, dim3(njc, nchunk), dim3(256), 0, st, V, W, N, nrhs, chunk, part);
+    hipLaunchKernelGGL(k_mdot_finish, dim3(grid1(njc)), dim3(256), 0, st, part, nchunk, njc, res);
+    HIP_TRY(hipGetLastError());
+    out.resize(njc);
+    HIP_TRY(hipMemcpyAsync(out.data(), res, sizeof(double) * njc, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return ASKIT_OK;
+}
+
+static askit_status put_small(askit_factor f, const std::vector<double> &v, hipStream_t st) {
+    if (f->ksmall.bytes < sizeof(double) * v.size()) {
+        HIP_TRY(hipStreamSynchronize(st));
+        ST_TRY(f->ksmall.alloc(sizeof(double) * v.size() * 2));
+    }
+    HIP_TRY(hipMemcpyAsync(f->ksmall.p, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice, st));
+    return ASKIT_OK;
+}
+
+static askit_status gmres_refine(askit_factor f, const double *B, int64_t ldb, int nrhs, double *X, int64_t ldx,
+                                 hipStream_t st) {
+    const int64_t N = f->t->N, NR = N * (int64_t)nrhs;
+    const int m = kRestart;
+    const size_t need = sizeof(double) * (size_t)NR;
+    if (f->Vk.bytes < need * (m + 1) || f->R.bytes < need || f->Dx.bytes < need) {
+        HIP_TRY(hipStreamSynchronize(st));
+        ST_TRY(f->Vk.alloc(need * (m + 1)));
+        ST_TRY(f->R.alloc(need));
+        ST_TRY(f->Dx.alloc(need));
+    }
+    double *V = f->Vk.as<double>(), *R = f->R.as<double>(), *Z = f->Dx.as<double>();
+    // |b| per column
+    HIP_TRY(hipMemcpy2DAsync(R, sizeof(double) * N, B, sizeof(double) * ldb, sizeof(double) * N, nrhs,
+                             hipMemcpyDeviceToDevice, st));
+    std::vector<double> bn, h1, h2, hn;
+    ST_TRY(mdot(f, R, R, 1, nrhs, st, bn));
+    for (auto &v : bn) v = v > 0 ? std::sqrt(v) : 1.0;
+    // x0 = Ahat^{-1} b  (B may alias X: it is not read again after the copy in R
+    // ... except for the residuals, so keep b in the last Krylov slot)
+    double *Bc = V + (size_t)m * NR;
+    HIP_TRY(hipMemcpyAsync(Bc, R, need, hipMemcpyDeviceToDevice, st));
+    ST_TRY(apply_inverse(f, B, ldb, nrhs, X, ldx, false, st));
+    int it = 0;
+    double res = INFINITY, res0 = -1.0;
+    std::vector<double> H((size_t)nrhs * (m + 1) * m), g((size_t)nrhs * (m + 1)), cs((size_t)nrhs * m),
+        sn((size_t)nrhs * m), sc(nrhs), y;
+    while (true) {
+        // r = b - A x
+        ST_TRY(matvec_impl(f, 0, X, ldx, nrhs, R, N, st));
+        hipLaunchKernelGGL(k_sub_from, dim3(grid1(NR)), dim3(256), 0, st, Bc, N, R, N, nrhs);
+        HIP_TRY(hipGetLastError());
+        std::vector<double> rn;
+        ST_TRY(mdot(f, R, R, 1, nrhs, st, rn));
+        res = 0.0;
+        for (int c = 0; c < nrhs; c++) {
+            rn[c] = std::sqrt(std::max(rn[c], 0.0));
+            res = std::max(res, rn[c] / bn[c]);
+        }
+        if (res0 < 0) res0 = res;
+        if (res <= f->refine_tol || it >= f->max_refine) break;
+        // Arnoldi with the last Krylov slot kept for b: at most m - 1 steps
+        const int mm = m - 1;
+        for (int c = 0; c < nrhs; c++) sc[c] = rn[c] > 0 ? 1.0 / rn[c] : 0.0;
+        ST_TRY(put_small(f, sc, st));
+        hipLaunchKernelGGL(k_scale_cols, dim3(grid1(NR)), dim3(256), 0, st, V, R, f->ksmall.as<double>(), N, nrhs);
+        std::fill(g.begin(), g.end(), 0.0);
+        for (int c = 0; c < nrhs; c++) g[(size_t)c * (m + 1)] = rn[c];
+        int used = 0;
+        for (int j = 0; j < mm && it < f->max_refine; j++) {
+            double *Vj = V + (size_t)j * NR, *W = R;
+            ST_TRY(apply_inverse(f, Vj, N, nrhs, Z, N, false, st));
+            ST_TRY(matvec_impl(f, 0, Z, N, nrhs, W, N, st));
+            // classical Gram-Schmidt, twice
+            ST_TRY(mdot(f, V, W, j + 1, nrhs, st, h1));
+            ST_TRY(put_small(f, h1, st));
+            hipLaunchKernelGGL(k_maxpy, dim3(grid1(NR)), dim3(256), 0, st, W, V, f->ksmall.as<double>(), j + 1, N, nrhs);
+            ST_TRY(mdot(f, V, W, j + 1, nrhs, st, h2));
+            ST_TRY(put_small(f, h2, st));
+            hipLaunchKernelGGL(k_maxpy, dim3(grid1(NR)), dim3(256), 0, st, W, V, f->ksmall.as<double>(), j + 1, N, nrhs);
+            ST_TRY(mdot(f, W, W, 1, nrhs, st, hn));
+            for (int c = 0; c < nrhs; c++) {
+                hn[c] = std::sqrt(std::max(hn[c], 0.0));
+                sc[c] = hn[c] > 0 ? 1.0 / hn[c] : 0.0;
+            }
+            ST_TRY(put_small(f, sc, st));
+            hipLaunchKernelGGL(k_scale_cols, dim3(grid1(NR)), dim3(256), 0, st, V + (size_t)(j + 1) * NR, W,
+                               f->ksmall.as<double>(), N, nrhs);
+            HIP_TRY(hipGetLastError());
+            it++;
+            used = j + 1;
+            double worst = 0.0;
+            for (int c = 0; c < nrhs; c++) {
+                double *Hc = H.data() + (size_t)c * (m + 1) * m, *gc = g.data() + (size_t)c * (m + 1);
+                double *csc = cs.data() + (size_t)c * m, *snc = sn.data() + (size_t)c * m;
+                auto Hat = [&](int r, int k) -> double & { return Hc[(size_t)r * m + k]; };
+                for (int r = 0; r <= j; r++) Hat(r, j) = h1[(size_t)r * nrhs + c] + h2[(size_t)r * nrhs + c];
+                Hat(j + 1, j) = hn[c];
+                for (int r = 0; r < j; r++) {
+                    double a = Hat(r, j), b = Hat(r + 1, j);
+                    Hat(r, j) = csc[r] * a + snc[r] * b;
+                    Hat(r + 1, j) = -snc[r] * a + csc[r] * b;
+                }
+                double a = Hat(j, j), b = Hat(j + 1, j), rr = std::hypot(a, b);
+                csc[j] = rr > 0 ? a / rr : 1.0;
+                snc[j] = rr > 0 ? b / rr : 0.0;
+                Hat(j, j) = rr;
+                Hat(j + 1, j) = 0.0;
+                gc[j + 1] = -snc[j] * gc[j];
+                gc[j] = csc[j] * gc[j];
+                worst = std::max(worst, std::fabs(gc[j + 1]) / bn[c]);
+            }
+            if (worst <= 0.5 * f->refine_tol) break;
+        }
+        if (used == 0) break;
+        // x += Ahat^{-1} V y
+        y.assign((size_t)used * nrhs, 0.0);
+        for (int c = 0; c < nrhs; c++) {
+            double *Hc = H.data() + (size_t)c * (m + 1) * m, *gc = g.data() + (size_t)c * (m + 1);
+            for (int r = used - 1; r >= 0; r--) {
+                double acc = gc[r];
+                for (int k = r + 1; k < used; k++) acc -= Hc[(size_t)r * m + k] * y[(size_t)k * nrhs + c];
+                double d = Hc[(size_t)r * m + r];
+                y[(size_t)r * nrhs + c] = d != 0.0 ? acc / d : 0.0;
+            }
+        }
+        ST_TRY(put_small(f, y, st));
+        hipLaunchKernelGGL(k_lincomb, dim3(grid1(NR)), dim3(256), 0, st, R, V, f->ksmall.as<double>(), used, N, nrhs);
+        HIP_TRY(hipGetLastError());
+        ST_TRY(apply_inverse(f, R, N, nrhs, Z, N, false, st));
+        hipLaunchKernelGGL(k_update, dim3(grid1(NR)), dim3(256), 0, st, X, ldx, Z, N, N, nrhs);
+        HIP_TRY(hipGetLastError());
+    }
+    f->info.iterations = it;
+    f->info.converged = res <= f->refine_tol;
+    f->info.initial_residual = res0;
+    f->info.residual = res;
+    HIP_TRY(hipStreamSynchronize(st));
+    return ASKIT_OK;
+}
+
 extern "C" {
 
 askit_status askit_solve(askit_factor f, const double *B, int64_t ldb, int32_t nrhs, double *X, int64_t ldx,
@@ -1449,48 +1688,7 @@ askit_status askit_solve(askit_factor f, const double *B, int64_t ldb, int32_t n
         f->t_solve = ms_since(t0);
         return ASKIT_OK;
     }
-    // refinement: x0 = Ahat^{-1} b, then x += Ahat^{-1} (b - A x) with the FP64 operator
-    const int64_t N = f->t->N;
-    if (f->R.bytes < sizeof(double) * N * nrhs) {
-        ST_TRY(f->R.alloc(sizeof(double) * N * nrhs));
-        ST_TRY(f->Dx.alloc(sizeof(double) * N * nrhs));
-    }
-    double *R = f->R.as<double>(), *Dx = f->Dx.as<double>();
-    ST_TRY(apply_inverse(f, B, ldb, nrhs, Dx, N, false, st));
-    // copy the first iterate into X (B and X may alias: B is not read again
-    // before the residual, which needs it -- so refine against a saved copy)
-    DBuf Bsave;
-    const double *Bref = B;
-    if (B == X) {
-        ST_TRY(Bsave.alloc(sizeof(double) * N * nrhs));
-        HIP_TRY(hipMemcpy2DAsync(Bsave.p, sizeof(double) * N, B, sizeof(double) * ldb, sizeof(double) * N, nrhs,
-                                 hipMemcpyDeviceToDevice, st));
-        Bref = Bsave.as<double>();
-        ldb = N;
-    }
-    HIP_TRY(hipMemcpy2DAsync(X, sizeof(double) * ldx, Dx, sizeof(double) * N, sizeof(double) * N, nrhs,
-                             hipMemcpyDeviceToDevice, st));
-    int it = 0;
-    double upd = INFINITY, res = INFINITY;
-    for (; it < f->max_refine; it++) {
-        ST_TRY(matvec_impl(f, 0, X, ldx, nrhs, R, N, st));
-        hipLaunchKernelGGL(k_residual, dim3(grid1(N * nrhs)), dim3(256), 0, st, Bref, ldb, R, N, N, nrhs);
-        HIP_TRY(hipGetLastError());
-        ST_TRY(colratio(f, R, N, Bref, ldb, nrhs, st, &res));
-        ST_TRY(apply_inverse(f, R, N, nrhs, Dx, N, false, st));
-        hipLaunchKernelGGL(k_update, dim3(grid1(N * nrhs)), dim3(256), 0, st, X, ldx, Dx, N, N, nrhs);
-        HIP_TRY(hipGetLastError());
-        ST_TRY(colratio(f, Dx, N, X, ldx, nrhs, st, &upd));
-        if (upd <= f->refine_tol) {
-            it++;
-            break;
-        }
-    }
-    f->info.iterations = it;
-    f->info.converged = upd <= f->refine_tol;
-    f->info.last_update = upd;
-    f->info.residual = res;
-    HIP_TRY(hipStreamSynchronize(st));
+    ST_TRY(gmres_refine(f, B, ldb, nrhs, X, ldx, st));
     f->t_solve = ms_since(t0);
     return ASKIT_OK;
 }
@@ -1520,6 +1718,215 @@ askit_status askit_last_solve_info(askit_factor f, askit_solve_info *info) {
     *info = f->info;
     return ASKIT_OK;
 }
+
+askit_status askit_tree_set_bandwidth(askit_tree t, double h) {
+    if (!t) return fail(ASKIT_ERR_ARG, "NULL tree");
+    if (!(h > 0.0) || !std::isfinite(h)) return fail(ASKIT_ERR_ARG, "h must be positive and finite");
+    t->hfac = h;
+    return ASKIT_OK;
+}
+
+askit_status askit_adjoint_scalars(askit_factor f, const double *Xs, const double *Zs, int64_t ld, int32_t nrhs,
+                                   double *dlambda, double *dh, void *stream) {
+    ST_TRY(check_solve_args(f, Xs, ld, nrhs, (double *)Zs, ld));
+    if (!dlambda || !dh) return fail(ASKIT_ERR_ARG, "NULL output");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t N = f->t->N, NR = N * (int64_t)nrhs;
+    if (f->R.bytes < sizeof(double) * NR || f->Dx.bytes < sizeof(double) * NR) {
+        HIP_TRY(hipStreamSynchronize(st));
+        ST_TRY(f->R.alloc(sizeof(double) * NR));
+        ST_TRY(f->Dx.alloc(sizeof(double) * NR));
+    }
+    double *Xc = f->Dx.as<double>(), *Y = f->R.as<double>();
+    HIP_TRY(hipMemcpy2DAsync(Xc, sizeof(double) * N, Xs, sizeof(double) * ld, sizeof(double) * N, nrhs,
+                             hipMemcpyDeviceToDevice, st));
+    ST_TRY(matvec_impl(f, 1, Xc, N, nrhs, Y, N, st));
+    // Zs may have a leading dimension above N: the dots read it through a
+    // compact copy in the first Krylov slot
+    if (f->Vk.bytes < sizeof(double) * NR) {
+        HIP_TRY(hipStreamSynchronize(st));
+        ST_TRY(f->Vk.alloc(sizeof(double) * NR));
+    }
+    double *Zc = f->Vk.as<double>();
+    HIP_TRY(hipMemcpy2DAsync(Zc, sizeof(double) * N, Zs, sizeof(double) * ld, sizeof(double) * N, nrhs,
+                             hipMemcpyDeviceToDevice, st));
+    std::vector<double> zx, zy;
+    ST_TRY(mdot(f, Zc, Xc, 1, nrhs, st, zx));
+    ST_TRY(mdot(f, Zc, Y, 1, nrhs, st, zy));
+    double a = 0.0, b = 0.0;
+    for (int c = 0; c < nrhs; c++) {
+        a += zx[c];
+        b += zy[c];
+    }
+    *dlambda = -a;
+    *dh = -b;
+    return ASKIT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches of independent problems: one launch per kernel and tree height for
+// all problems, the factorization and the solve each captured in a hipGraph
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct askit_batch_s {
+    std::vector<askit_factor> fs;
+    int nrhs = 0;
+    Plan fplan, splan;
+    hipGraphExec_t fexec = nullptr, sexec = nullptr;
+    hipGraph_t fgraph = nullptr, sgraph = nullptr;
+    DBuf ptrs, gtasks;
+    ~askit_batch_s() {
+        if (fexec) hipGraphExecDestroy(fexec);
+        if (sexec) hipGraphExecDestroy(sexec);
+        if (fgraph) hipGraphDestroy(fgraph);
+        if (sgraph) hipGraphDestroy(sgraph);
+        for (auto f : fs) askit_factor_destroy(f);
+    }
+};
+
+// record a plan into a graph on a private capture stream
+static askit_status capture(const Plan &P, int ncol, hipGraph_t *g, hipGraphExec_t *ex,
+                            const std::function<hipError_t(hipStream_t)> &pre = nullptr,
+                            const std::function<hipError_t(hipStream_t)> &post = nullptr) {
+    hipStream_t cs;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    const bool prof = g_prof.on;
+    g_prof.on = false;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess && pre) e = pre(cs);
+    if (e == hipSuccess) e = P.run(cs, ncol);
+    if (e == hipSuccess && post) e = post(cs);
+    hipError_t e2 = hipStreamEndCapture(cs, g);
+    g_prof.on = prof;
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(ex, *g, nullptr, nullptr, 0);
+    hipStreamDestroy(cs);
+    HIP_TRY(e);
+    return ASKIT_OK;
+}
+
+extern "C" {
+
+askit_status askit_skeletonize_batched(askit_tree *trees, int32_t count, void *stream) {
+    if (!trees || count < 1) return fail(ASKIT_ERR_ARG, "no trees");
+    for (int i = 0; i < count; i++) {
+        if (!trees[i]) return fail(ASKIT_ERR_ARG, "NULL tree");
+        if (trees[i]->refs) return fail(ASKIT_ERR_STATE, "destroy the factors of the trees first");
+        if (trees[i]->nsamp != trees[0]->nsamp || trees[i]->s != trees[0]->s || trees[i]->d != trees[0]->d)
+            return fail(ASKIT_ERR_ARG, "batched trees must share rank, sample count and dimension");
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    ST_TRY(skeletonize_impl(trees, count, (hipStream_t)stream));
+    double ms = ms_since(t0);
+    for (int i = 0; i < count; i++) trees[i]->t_skel = ms;
+    return ASKIT_OK;
+}
+
+askit_status askit_batch_create(askit_tree *trees, int32_t count, const double *lambdas, int32_t precision,
+                                int32_t nrhs, askit_batch *out) {
+    if (!out) return fail(ASKIT_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!trees || !lambdas || count < 1 || nrhs < 1) return fail(ASKIT_ERR_ARG, "bad batch arguments");
+    if (precision != ASKIT_FP64 && precision != ASKIT_MIXED) return fail(ASKIT_ERR_ARG, "unknown precision");
+    for (int i = 0; i < count; i++) {
+        if (!trees[i] || !trees[i]->skel_ok) return fail(ASKIT_ERR_STATE, "every tree must be skeletonized");
+        if (trees[i]->s != trees[0]->s || trees[i]->d != trees[0]->d)
+            return fail(ASKIT_ERR_ARG, "batched trees must share rank and dimension");
+        if (!(lambdas[i] >= 0.0) || !std::isfinite(lambdas[i])) return fail(ASKIT_ERR_ARG, "bad lambda");
+    }
+    std::unique_ptr<askit_batch_s> b(new askit_batch_s());
+    b->nrhs = nrhs;
+    for (int i = 0; i < count; i++) {
+        std::unique_ptr<askit_factor_s> f;
+        ST_TRY(factor_alloc(trees[i], lambdas[i], precision, f));
+        trees[i]->refs++;
+        b->fs.push_back(f.release());
+        ST_TRY(ensure_cap(b->fs.back(), nrhs));
+    }
+    b->fplan.tag = "batch_factor";
+    ST_TRY(factor_plan(b->fs, b->fplan));
+    b->splan.tag = "batch_solve";
+    ST_TRY(solve_plan(b->fs, b->splan));
+    // gather / scatter descriptors: one per problem; user pointers come from a
+    // device table (B[0..count), X[0..count)) refreshed by every solve call
+    std::vector<GatherTask> gt;
+    int64_t nmax = 0;
+    for (auto f : b->fs) {
+        GatherTask g{};
+        g.perm = f->t->perm.as<int64_t>();
+        g.N = f->t->N;
+        g.W = f->W.p;
+        g.ldw = f->cap;
+        gt.push_back(g);
+        nmax = std::max(nmax, f->t->N);
+    }
+    ST_TRY(upload(b->gtasks, gt));
+    ST_TRY(b->ptrs.alloc(sizeof(double *) * 2 * count));
+    const GatherTask *gp = b->gtasks.as<GatherTask>();
+    const double *const *pB = b->ptrs.as<const double *>();
+    double *const *pX = b->ptrs.as<double *>() + count;
+    const Prec pr = b->fs[0]->prec;
+    const int bpt = (int)cdiv(nmax * nrhs, 256);
+    auto gather = [=](hipStream_t st) -> hipError_t {
+        if (pr == P64) hipLaunchKernelGGL(k_gather_multi<double>, dim3(count * bpt), dim3(256), 0, st, gp, pB, nrhs, bpt);
+        else hipLaunchKernelGGL(k_gather_multi<float>, dim3(count * bpt), dim3(256), 0, st, gp, pB, nrhs, bpt);
+        return hipGetLastError();
+    };
+    auto scatter = [=](hipStream_t st) -> hipError_t {
+        if (pr == P64) hipLaunchKernelGGL(k_scatter_multi<double>, dim3(count * bpt), dim3(256), 0, st, gp, pX, nrhs, bpt);
+        else hipLaunchKernelGGL(k_scatter_multi<float>, dim3(count * bpt), dim3(256), 0, st, gp, pX, nrhs, bpt);
+        return hipGetLastError();
+    };
+    ST_TRY(capture(b->fplan, trees[0]->s, &b->fgraph, &b->fexec));
+    ST_TRY(capture(b->splan, nrhs, &b->sgraph, &b->sexec, gather, scatter));
+    *out = b.release();
+    return ASKIT_OK;
+}
+
+askit_status askit_batch_factorize(askit_batch b, void *stream) {
+    if (!b) return fail(ASKIT_ERR_ARG, "NULL batch");
+    HIP_TRY(hipGraphLaunch(b->fexec, (hipStream_t)stream));
+    return ASKIT_OK;
+}
+
+askit_status askit_batch_check(askit_batch b, double *min_ratio, int32_t *problem, void *stream) {
+    if (!b || !min_ratio || !problem) return fail(ASKIT_ERR_ARG, "NULL argument");
+    *min_ratio = 1.0;
+    *problem = -1;
+    for (size_t i = 0; i < b->fs.size(); i++) {
+        ST_TRY(factor_ratio(b->fs[i], (hipStream_t)stream));
+        if (b->fs[i]->min_ratio < *min_ratio) {
+            *min_ratio = b->fs[i]->min_ratio;
+            *problem = (int32_t)i;
+        }
+    }
+    return ASKIT_OK;
+}
+
+askit_status askit_batch_solve(askit_batch b, const double *const *B, double *const *X, void *stream) {
+    if (!b || !B || !X) return fail(ASKIT_ERR_ARG, "NULL argument");
+    const int count = (int)b->fs.size();
+    std::vector<const void *> tab(2 * count);
+    for (int i = 0; i < count; i++) {
+        if (!B[i] || !X[i]) return fail(ASKIT_ERR_ARG, "NULL right-hand side");
+        tab[i] = B[i];
+        tab[count + i] = X[i];
+    }
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(b->ptrs.p, tab.data(), sizeof(void *) * 2 * count, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipGraphLaunch(b->sexec, st));
+    HIP_TRY(hipStreamSynchronize(st));  // the pointer table is host memory of this call
+    return ASKIT_OK;
+}
+
+askit_status askit_batch_factor(askit_batch b, int32_t i, askit_factor *f) {
+    if (!b || !f || i < 0 || i >= (int32_t)b->fs.size()) return fail(ASKIT_ERR_ARG, "bad batch index");
+    *f = b->fs[i];
+    return ASKIT_OK;
+}
+
+void askit_batch_destroy(askit_batch b) { delete b; }
 
 askit_status askit_get_stats(askit_tree t, askit_factor f, char *json, size_t cap) {
     if (!json || cap == 0) return fail(ASKIT_ERR_ARG, "NULL buffer");

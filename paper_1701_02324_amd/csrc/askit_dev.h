@@ -91,6 +91,21 @@ struct LeafTask {
     double scale, lambda;
 };
 
+// Permutation of one problem's right-hand sides into tree order (batched
+// solves): W(pos, c) = B_i[perm[pos] + c N] and back.
+struct GatherTask {
+    const int64_t *perm;
+    int64_t N;
+    void *W;
+    int64_t ldw;
+};
+
+// n x n identity block (column-major, ld = n) for a reduced system.
+struct IdTask {
+    double *Z;
+    int32_t n, pad;
+};
+
 // Batched LU / LU-solve task (column-major matrix).
 struct LuTask {
     double *A;
@@ -117,7 +132,7 @@ struct SkelTask {
     int32_t leaf;          // 1: candidates = [b, b+n); 0: [skl[:sl], skr[:sr]]
     int64_t b;
     int32_t n;
-    int32_t pad;
+    int32_t cmax;          // rows of this tree's P slots (max(leaf size, 2s))
     const int32_t *skl, *skr, *srl, *srr;
     double *M;             // nsamp_cap x cmax column-major
     int32_t *skel;         // out: s positions (-1 padded)

@@ -13,8 +13,9 @@ __global__ void k_tree_mean(const int64_t *nb, const int64_t *ne, int64_t first,
 __global__ void k_tree_chunk_scatter(const double *X, const int64_t *perm, int d, const int64_t *nb,
                                      const int64_t *ne, int64_t first, int cnt, int maxch, const double *mu,
                                      const int16_t *pa, const int16_t *pc, int npair, double *part);
-__global__ void k_tree_axis(const int64_t *nb, const int64_t *ne, int64_t first, int cnt, int maxch, int d,
-                            const int16_t *pa, const int16_t *pc, int npair, double *part, double *S, double *axis);
+__global__ void k_tree_scatter(const int64_t *nb, const int64_t *ne, int64_t first, int cnt, int maxch, int d,
+                               const int16_t *pa, const int16_t *pc, int npair, double *part, double *S);
+__global__ void k_tree_axis(int cnt, int d, const double *S, double *axis);
 __global__ void k_tree_keys(const double *X, const int64_t *perm, int d, const int64_t *nb, const int64_t *ne,
                             int64_t first, int blocks_per_node, const double *mu, const double *axis, double *key,
                             int64_t *kid);
@@ -30,7 +31,7 @@ __global__ void k_check_finite(const double *X, int64_t n, int32_t *bad);
 // skeletons (k_skel.hip)
 __global__ void k_sample(const SampTask *tasks, int nsamp, int32_t *err);
 __global__ void k_sample_block(const SkelTask *tasks, int rowtiles, int ldm, int d);
-__global__ void k_qrcp(const SkelTask *tasks, int s, int cmax, int ldm);
+__global__ void k_qrcp(const SkelTask *tasks, int s, int ldm);
 
 // LU (k_lu.hip)
 __global__ void k_lu(const LuTask *tasks);
@@ -38,7 +39,7 @@ __global__ void k_lu_diaginv(const LuTask *tasks);
 template <typename T, int NR, bool TRANS> __global__ void k_lusolve(const LuTask *tasks, int nrhs, int panels);
 
 // products (k_prod.hip)
-template <typename T, typename TO, int TC>
+template <typename T, typename TB, typename TO, int TC>
 __global__ void k_kmm(const KmmTask *tasks, const TileItem *items, int ncol, int d);
 template <typename T, int TC> __global__ void k_gmm(const GmmTask *tasks, const TileItem *items, int ncol, int kchunk);
 template <typename T, typename TO> __global__ void k_reduce(const RedTask *tasks, int ncol, int blocks_per_task);
@@ -51,7 +52,11 @@ template <typename T>
 __global__ void k_scatter_rhs(const T *W, int64_t ldw, const int64_t *perm, int64_t N, int nrhs, double *X,
                               int64_t ldx, int add);
 __global__ void k_leaf_block(const LeafTask *tasks, int nmax, int d);
-__global__ void k_identity(double *Z, int n, int64_t stride, int count);
+template <typename T>
+__global__ void k_gather_multi(const GatherTask *tasks, const double *const *B, int nrhs, int bpt);
+template <typename T>
+__global__ void k_scatter_multi(const GatherTask *tasks, double *const *X, int nrhs, int bpt);
+__global__ void k_identity(const IdTask *tasks, int bpm);
 template <typename TS, typename TD> __global__ void k_copy(const CopyTask *tasks, int rowblocks);
 template <typename T> __global__ void k_axpy(T *Y, const T *X, int64_t ld, int64_t n, int nrhs, double a);
 __global__ void k_residual(const double *B, int64_t ldb, double *R, int64_t ldr, int64_t N, int nrhs);
@@ -59,5 +64,11 @@ __global__ void k_update(double *X, int64_t ldx, const double *D, int64_t ldd, i
 __global__ void k_colnorms(const double *U, int64_t ldu, const double *V, int64_t ldv, int64_t N, int nrhs,
                            double *acc);
 __global__ void k_zero(double *p, int64_t n);
+__global__ void k_mdot_part(const double *V, const double *W, int64_t N, int nrhs, int64_t chunk, double *part);
+__global__ void k_mdot_finish(const double *part, int nchunk, int njc, double *out);
+__global__ void k_maxpy(double *W, const double *V, const double *h, int nv, int64_t N, int nrhs);
+__global__ void k_lincomb(double *U, const double *V, const double *y, int nv, int64_t N, int nrhs);
+__global__ void k_scale_cols(double *D, const double *W, const double *sc, int64_t N, int nrhs);
+__global__ void k_sub_from(const double *B, int64_t ldb, double *R, int64_t N, int nrhs);
 
 }  // namespace askit

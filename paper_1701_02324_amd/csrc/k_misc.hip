@@ -31,6 +31,37 @@ __global__ void k_scatter_rhs(const T *__restrict__ W, int64_t ldw, const int64_
     else *dst = v;
 }
 
+// batched permutation of right-hand sides (pointer table on the device);
+// grid = problem * blocks_per_task
+template <typename T>
+__global__ void k_gather_multi(const GatherTask *__restrict__ tasks, const double *const *__restrict__ B, int nrhs,
+                               int bpt) {
+    const int p = blockIdx.x / bpt;
+    const GatherTask t = tasks[p];
+    const int64_t e = (int64_t)(blockIdx.x % bpt) * blockDim.x + threadIdx.x;
+    if (e >= t.N * nrhs) return;
+    const int64_t pos = e / nrhs;
+    const int c = (int)(e % nrhs);
+    ((T *)t.W)[pos * t.ldw + c] = (T)B[p][t.perm[pos] + (int64_t)c * t.N];
+}
+
+template <typename T>
+__global__ void k_scatter_multi(const GatherTask *__restrict__ tasks, double *const *__restrict__ X, int nrhs,
+                                int bpt) {
+    const int p = blockIdx.x / bpt;
+    const GatherTask t = tasks[p];
+    const int64_t e = (int64_t)(blockIdx.x % bpt) * blockDim.x + threadIdx.x;
+    if (e >= t.N * nrhs) return;
+    const int64_t pos = e / nrhs;
+    const int c = (int)(e % nrhs);
+    X[p][t.perm[pos] + (int64_t)c * t.N] = (double)((const T *)t.W)[pos * t.ldw + c];
+}
+
+template __global__ void k_gather_multi<double>(const GatherTask *, const double *const *, int, int);
+template __global__ void k_gather_multi<float>(const GatherTask *, const double *const *, int, int);
+template __global__ void k_scatter_multi<double>(const GatherTask *, double *const *, int, int);
+template __global__ void k_scatter_multi<float>(const GatherTask *, double *const *, int, int);
+
 // lambda I + K(X_a, X_a) in column-major; grid = task * n_max + column
 __global__ void k_leaf_block(const LeafTask *__restrict__ tasks, int nmax, int d) {
     const LeafTask t = tasks[blockIdx.x / nmax];
@@ -52,13 +83,12 @@ __global__ void k_leaf_block(const LeafTask *__restrict__ tasks, int nmax, int d
     }
 }
 
-// n x n identity blocks (column-major, ld = n), one block per matrix
-__global__ void k_identity(double *__restrict__ Z, int n, int64_t stride, int count) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t per = (int64_t)n * n;
-    if (t >= per * count) return;
-    int64_t m = t / per, e = t % per;
-    Z[m * stride + e] = (e % n == e / n) ? 1.0 : 0.0;
+// n x n identity blocks (column-major, ld = n); grid = task * blocks_per_matrix
+__global__ void k_identity(const IdTask *__restrict__ tasks, int bpm) {
+    const IdTask t = tasks[blockIdx.x / bpm];
+    const int64_t e = (int64_t)(blockIdx.x % bpm) * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)t.n * t.n) return;
+    t.Z[e] = (e % t.n == e / t.n) ? 1.0 : 0.0;
 }
 
 // dst(r, c) = src(r, c) with precision conversion; grid = task * rowblocks + rb
@@ -127,6 +157,75 @@ __global__ void k_colnorms(const double *__restrict__ U, int64_t ldu, const doub
         atomicAdd(acc + c, su[0]);
         atomicAdd(acc + nrhs + c, sv[0]);
     }
+}
+
+// --- batched Krylov helpers on column-major N x nrhs blocks (ld = N) ------
+// vectors V_j are stored back to back: V + j * N * nrhs
+
+// partial[(j * nrhs + c) * nchunk + chunk] = sum over the chunk of V_j(:,c) W(:,c)
+// grid: x = j * nrhs + c, y = chunk; rows of a chunk summed in a fixed order
+__global__ void k_mdot_part(const double *__restrict__ V, const double *__restrict__ W, int64_t N, int nrhs,
+                            int64_t chunk, double *__restrict__ part) {
+    __shared__ double sh[256];
+    const int jc = blockIdx.x, c = jc % nrhs, j = jc / nrhs;
+    const double *v = V + (int64_t)j * N * nrhs + (int64_t)c * N, *w = W + (int64_t)c * N;
+    const int64_t r0 = (int64_t)blockIdx.y * chunk, r1 = min(N, r0 + chunk);
+    double acc = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) acc = fma(v[i], w[i], acc);
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)jc * gridDim.y + blockIdx.y] = sh[0];
+}
+
+// out[jc] = sum of the nchunk partials of jc, in chunk order
+__global__ void k_mdot_finish(const double *__restrict__ part, int nchunk, int njc, double *__restrict__ out) {
+    int jc = blockIdx.x * blockDim.x + threadIdx.x;
+    if (jc >= njc) return;
+    double acc = 0.0;
+    for (int k = 0; k < nchunk; k++) acc += part[(int64_t)jc * nchunk + k];
+    out[jc] = acc;
+}
+
+// W(:,c) -= sum_{j < nv} h[j * nrhs + c] V_j(:,c)
+__global__ void k_maxpy(double *__restrict__ W, const double *__restrict__ V, const double *__restrict__ h, int nv,
+                        int64_t N, int nrhs) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * nrhs) return;
+    const int c = (int)(t / N);
+    double acc = W[t];
+    for (int j = 0; j < nv; j++) acc = fma(-h[j * nrhs + c], V[(int64_t)j * N * nrhs + t], acc);
+    W[t] = acc;
+}
+
+// U(:,c) = sum_{j < nv} y[j * nrhs + c] V_j(:,c)
+__global__ void k_lincomb(double *__restrict__ U, const double *__restrict__ V, const double *__restrict__ y, int nv,
+                          int64_t N, int nrhs) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * nrhs) return;
+    const int c = (int)(t / N);
+    double acc = 0.0;
+    for (int j = 0; j < nv; j++) acc = fma(y[j * nrhs + c], V[(int64_t)j * N * nrhs + t], acc);
+    U[t] = acc;
+}
+
+// D(:,c) = W(:,c) * sc[c]
+__global__ void k_scale_cols(double *__restrict__ D, const double *__restrict__ W, const double *__restrict__ sc,
+                             int64_t N, int nrhs) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * nrhs) return;
+    D[t] = W[t] * sc[t / N];
+}
+
+// R = B - R (column-major, R with ld N, B with ldb); X += D (X with ldx)
+__global__ void k_sub_from(const double *__restrict__ B, int64_t ldb, double *__restrict__ R, int64_t N, int nrhs) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * nrhs) return;
+    int64_t i = t % N, c = t / N;
+    R[t] = B[i + c * ldb] - R[t];
 }
 
 __global__ void k_zero(double *__restrict__ p, int64_t n) {

@@ -52,7 +52,7 @@ __device__ inline void store_out(T *C, int64_t off, T v, int op) {
 __device__ inline int src_count(const PtSrc &s) { return s.cnt ? *s.cnt : s.n; }
 __device__ inline int64_t src_pos(const PtSrc &s, int i) { return s.idx ? (int64_t)s.idx[i] : s.base + i; }
 
-template <typename T, typename TO, int TC>
+template <typename T, typename TB, typename TO, int TC>
 __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, const TileItem *__restrict__ items,
                                              int ncol, int d) {
     constexpr int NB = TC / 16;
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, 
     }
     typename Acc<T>::type acc[NB];
     for (int b = 0; b < NB; b++) acc[b] = typename Acc<T>::type{0, 0, 0, 0};
-    const T *B = (const T *)t.B;
+    const TB *B = (const TB *)t.B;
     for (int ks = t.k0; ks < k1; ks += kKS) {
         const int kn = min(kKS, k1 - ks);
         __syncthreads();
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, 
         }
         for (int i = tid; i < kKS * TC; i += 256) {
             int k = i / TC, c = i % TC;
-            sB[k][c] = (k < kn && c0 + c < ncol) ? B[(int64_t)(ks - t.k0 + k) * t.ldb + c0 + c] : (T)0;
+            sB[k][c] = (k < kn && c0 + c < ncol) ? (T)B[(int64_t)(ks - t.k0 + k) * t.ldb + c0 + c] : (T)0;
         }
         __syncthreads();
         // generate the kernel tile: 64 x 16 entries, 4 per thread
@@ -204,10 +204,13 @@ __global__ void k_reduce(const RedTask *__restrict__ tasks, int ncol, int blocks
     store_out((TO *)t.dst, (int64_t)r * t.drs + (int64_t)c * t.dcs, (TO)acc, t.op);
 }
 
-#define KMM_INST(T, TO, TC) template __global__ void k_kmm<T, TO, TC>(const KmmTask *, const TileItem *, int, int);
-KMM_INST(double, double, 16) KMM_INST(double, double, 64) KMM_INST(double, double, 128)
-KMM_INST(float, float, 16) KMM_INST(float, float, 64) KMM_INST(float, float, 128)
-KMM_INST(float, double, 16) KMM_INST(float, double, 64) KMM_INST(float, double, 128)
+#define KMM_INST(T, TB, TO, TC) \
+    template __global__ void k_kmm<T, TB, TO, TC>(const KmmTask *, const TileItem *, int, int);
+#define KMM_ALL(T, TB, TO) KMM_INST(T, TB, TO, 16) KMM_INST(T, TB, TO, 64) KMM_INST(T, TB, TO, 128)
+KMM_ALL(double, double, double)
+KMM_ALL(float, float, float)
+KMM_ALL(float, float, double)
+KMM_ALL(double, float, double)
 #define GMM_INST(T, TC) template __global__ void k_gmm<T, TC>(const GmmTask *, const TileItem *, int, int);
 GMM_INST(double, 16) GMM_INST(double, 64) GMM_INST(double, 128)
 GMM_INST(float, 16) GMM_INST(float, 64) GMM_INST(float, 128)

@@ -134,7 +134,7 @@ __device__ double block_sum(double v, double *red) {
 constexpr int kQrMaxCols = 2048;
 constexpr int kQrMaxRows = 4096;
 
-__global__ __launch_bounds__(kQrThreads) void k_qrcp(const SkelTask *__restrict__ tasks, int s, int cmax, int ldm) {
+__global__ __launch_bounds__(kQrThreads) void k_qrcp(const SkelTask *__restrict__ tasks, int s, int ldm) {
     __shared__ double nrm[kQrMaxCols];
     __shared__ int32_t piv[kQrMaxCols];
     __shared__ double vh[kQrMaxRows];
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kQrThreads) void k_qrcp(const SkelTask *__restrict_
     // children's skeletons in the halves [0, s) and [s, 2s)
     auto prow = [&](int c) { return t.leaf ? c : (c < sl ? c : s + (c - sl)); };
 
-    for (int64_t i = tid; i < (int64_t)cmax * s; i += kQrThreads) t.Pt[i] = 0.0;
+    for (int64_t i = tid; i < (int64_t)t.cmax * s; i += kQrThreads) t.Pt[i] = 0.0;
     if (ncand <= s) {  // no compression: skeleton = candidates, P = I
         __syncthreads();
         for (int k = tid; k < s; k += kQrThreads) t.skel[k] = k < ncand ? cand_pos(t, k, sl) : -1;

@@ -88,20 +88,26 @@ __global__ void k_tree_chunk_scatter(const double *__restrict__ X, const int64_t
     part[((int64_t)node * maxch + c) * npair + q] = acc;
 }
 
-// thread -> node: scatter matrix, power iteration, sign rule -> axis v
-__global__ void k_tree_axis(const int64_t *__restrict__ nb, const int64_t *__restrict__ ne, int64_t first, int cnt,
-                            int maxch, int d, const int16_t *__restrict__ pa, const int16_t *__restrict__ pc,
-                            int npair, double *__restrict__ part, double *__restrict__ S, double *__restrict__ axis) {
-    int node = blockIdx.x * blockDim.x + threadIdx.x;
-    if (node >= cnt) return;
+// thread -> (node, pair): scatter matrix entry by pairwise halving
+__global__ void k_tree_scatter(const int64_t *__restrict__ nb, const int64_t *__restrict__ ne, int64_t first, int cnt,
+                               int maxch, int d, const int16_t *__restrict__ pa, const int16_t *__restrict__ pc,
+                               int npair, double *__restrict__ part, double *__restrict__ S) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt * npair) return;
+    int node = t / npair, q = t % npair;
     int64_t n = ne[first + node] - nb[first + node];
     int64_t nch = (n + kTreeChunk - 1) / kTreeChunk;
+    double v = pairwise_total(part + (int64_t)node * maxch * npair + q, nch, npair);
     double *Sn = S + (int64_t)node * d * d;
-    for (int q = 0; q < npair; q++) {
-        double v = pairwise_total(part + (int64_t)node * maxch * npair + q, nch, npair);
-        Sn[pa[q] * d + pc[q]] = v;
-        Sn[pc[q] * d + pa[q]] = v;
-    }
+    Sn[pa[q] * d + pc[q]] = v;
+    Sn[pc[q] * d + pa[q]] = v;
+}
+
+// thread -> node: power iteration, sign rule -> axis v
+__global__ void k_tree_axis(int cnt, int d, const double *__restrict__ S, double *__restrict__ axis) {
+    int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= cnt) return;
+    const double *Sn = S + (int64_t)node * d * d;
     double v[kMaxDim], w[kMaxDim];
     double v0 = 1.0 / sqrt((double)d);
     for (int k = 0; k < d; k++) v[k] = v0;

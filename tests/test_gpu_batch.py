@@ -1,0 +1,108 @@
+"""Batched execution: many independent problems of uneven size factorized and
+solved with one launch per kernel and tree height, replayed from hipGraphs.
+Each problem is checked against its own oracle (1e-10 on the oracle's
+skeletons) and against the unbatched GPU path (identical skeletons)."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import colrel, oracle_skeletons
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ak():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1701_02324_amd as ak
+    ak.load()
+    return ak
+
+
+def _problems(count=7, nmin=300, nmax=3000):
+    """Shapes of the batched workload (log-uniform sizes, 4-cluster mixtures in
+    8-D, h ~ U[0.5, 2], lambda ~ 10^U[-1, 0]), scaled down: m = 32, s = 16."""
+    probs = synth.batched_problems(count=count, nrhs=3, nmin=nmin, nmax=nmax)
+    for p in probs:
+        p["m"], p["s"], p["nsamp"] = 32, 16, 64
+        p["lam"] = max(p["lam"], 0.1)  # keep every problem well conditioned at this size
+    return probs
+
+
+def test_batched_matches_oracle_and_unbatched(ak, orc):
+    import torch
+    probs = _problems()
+    say(f"[gpu batch] {len(probs)} problems, N = {[len(p['X']) for p in probs]}")
+    trees = [ak.Tree(torch.as_tensor(p["X"], device="cuda"), p["m"], p["s"], p["h"], n_samples=p["nsamp"],
+                     seed=p["seed"], problem=p["problem"]) for p in probs]
+    ak.askit_skeletonize_batched(trees)
+    # unbatched skeletons must be identical (same per-node kernels)
+    for p, t in zip(probs, trees):
+        t2 = ak.Tree(torch.as_tensor(p["X"], device="cuda"), p["m"], p["s"], p["h"], n_samples=p["nsamp"],
+                     seed=p["seed"], problem=p["problem"])
+        t2.skeletonize()
+        a, b = t.export_skeletons(), t2.export_skeletons()
+        assert all(np.array_equal(x, y) for x, y in zip(a, b))  # root slots included: both -1
+        t2.close()
+    # oracle skeletons imported so that the factorization can be compared at 1e-10
+    oracles = []
+    for p, t in zip(probs, trees):
+        o = orc.Oracle(p["X"], p["m"], p["s"], p["h"], nsamp=p["nsamp"], seed=p["seed"], problem=p["problem"])
+        o.build_tree()
+        o.skeletonize()
+        o.factorize(p["lam"])
+        t.import_skeletons(*oracle_skeletons(o, t.s, t.cmax))
+        oracles.append(o)
+    batch = ak.Batch(trees, [p["lam"] for p in probs], ak.ASKIT_FP64, nrhs=3)
+    for rep in range(2):  # replay both graphs twice, with host work in between
+        batch.factorize()
+        xs = batch.solve([torch.as_tensor(p["B"], device="cuda") for p in probs])
+        torch.cuda.synchronize()
+        for p, o, x in zip(probs, oracles, xs):
+            err = colrel(x.cpu().numpy(), o.solve(p["B"]))
+            assert err < 1e-10, (rep, len(p["X"]), err)
+        ratio, _ = batch.check()
+        assert ratio > 1e-12
+    # the batched factors are ordinary factors for the other entry points
+    f0 = batch.factor_handle(0)
+    xt = ak.askit_solve_transpose(f0, torch.as_tensor(probs[0]["B"], device="cuda")).cpu().numpy()
+    assert colrel(xt, oracles[0].solve_t(probs[0]["B"])) < 1e-10
+    batch.close()
+    for t in trees:
+        t.close()
+
+
+def test_batched_mixed_precision(ak):
+    """Mixed-precision batch factors: unrefined solves within 1e-2 of FP64;
+    refined against the FP64 operator (GMRES-IR on the batch's own factor
+    handles) within 1e-6."""
+    import torch
+    probs = _problems(count=4)
+    trees = [ak.Tree(torch.as_tensor(p["X"], device="cuda"), p["m"], p["s"], p["h"], n_samples=p["nsamp"],
+                     seed=p["seed"], problem=p["problem"]) for p in probs]
+    ak.askit_skeletonize_batched(trees)
+    b64 = ak.Batch(trees, [p["lam"] for p in probs], ak.ASKIT_FP64, nrhs=3)
+    b32 = ak.Batch(trees, [p["lam"] for p in probs], ak.ASKIT_MIXED, nrhs=3)
+    b64.factorize()
+    b32.factorize()
+    Bs = [torch.as_tensor(p["B"], device="cuda") for p in probs]
+    x64 = b64.solve(Bs)
+    x32 = b32.solve(Bs)
+    for i, (a, b) in enumerate(zip(x32, x64)):
+        err = colrel(a.cpu().numpy(), b.cpu().numpy())
+        assert err < 1e-2, (i, err)
+        xr = ak.askit_solve(b32.factor_handle(i), Bs[i])
+        info = ak.askit_last_solve_info(b32.factor_handle(i))
+        errr = colrel(xr.cpu().numpy(), b.cpu().numpy())
+        say(f"  problem {i}: unrefined {err:.1e}, refined {errr:.1e} ({info['iterations']} iterations)")
+        assert errr <= 1e-6
+    b64.close()
+    b32.close()

@@ -1,0 +1,135 @@
+"""GPU parity of the adjoint gradients (differentiation w.r.t. b, lambda, h).
+
+Checked against (a) the oracle's adjoint gradient on the same skeletons,
+(b) a dense FP64 gradient from the explicitly assembled lambda I + Ktilde, and
+(c) central finite differences (step 1e-5) with the skeletons frozen, at the
+N = 4096 check size of the differentiation workload and at its full size."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import oracle_skeletons
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ak():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1701_02324_amd as ak
+    ak.load()
+    return ak
+
+
+def _loss_and_grads(ak, tree, B, Y, lam, h):
+    import torch
+    b = torch.as_tensor(B, device="cuda").clone().requires_grad_(True)
+    lt = torch.tensor(lam, dtype=torch.float64, requires_grad=True)
+    ht = torch.tensor(h, dtype=torch.float64, requires_grad=True)
+    x = ak.kernel_solve(b, lt, ht, tree)
+    loss = ((x - torch.as_tensor(Y, device="cuda")) ** 2).sum()
+    loss.backward()
+    return float(loss), b.grad.cpu().numpy(), float(lt.grad), float(ht.grad)
+
+
+def _loss_only(ak, tree, B, Y, lam, h):
+    import torch
+    tree.set_bandwidth(h)
+    f = tree.factorize(lam, ak.ASKIT_FP64)
+    x = f.solve(torch.as_tensor(B, device="cuda"))
+    v = float(((x - torch.as_tensor(Y, device="cuda")) ** 2).sum())
+    f.close()
+    return v
+
+
+@pytest.fixture(scope="module")
+def small(ak, orc):
+    import torch
+    c = synth.config(5, N=4096)
+    X, B, Y = c["X"], c["B"], c["Y"]
+    say("[gpu grad] differentiation workload at N=4096 (d=8, m=256, s=128, h=1, lambda=0.05)")
+    o = orc.Oracle(X, c["m"], c["s"], c["h"], seed=c["seed"])
+    o.build_tree()
+    o.skeletonize()
+    o.factorize(c["lam"])
+    t = ak.Tree(torch.as_tensor(X, device="cuda"), c["m"], c["s"], c["h"], seed=c["seed"])
+    t.import_skeletons(*oracle_skeletons(o, t.s, t.cmax))
+    return c, o, t
+
+
+def test_adjoint_matches_oracle(ak, small):
+    c, o, t = small
+    loss, gb, gl, gh = _loss_and_grads(ak, t, c["B"], c["Y"], c["lam"], c["h"])
+    lo, xo, zo, dlo, dho = o.gradient(c["B"], c["Y"])
+    say(f"  loss {loss:.6e} oracle {lo:.6e}; dlam {gl:.6e} / {dlo:.6e}; dh {gh:.6e} / {dho:.6e}")
+    assert abs(loss - lo) <= 1e-10 * lo
+    assert np.linalg.norm(gb - zo) <= 1e-9 * np.linalg.norm(zo)
+    assert abs(gl - dlo) <= 1e-9 * abs(dlo)
+    assert abs(gh - dho) <= 1e-9 * abs(dho)
+
+
+def test_adjoint_matches_dense_gradient(ak, small):
+    c, o, t = small
+    loss, gb, gl, gh = _loss_and_grads(ak, t, c["B"], c["Y"], c["lam"], c["h"])
+    A = o.dense()
+    dA = o.dense(1)
+    x = np.linalg.solve(A, c["B"])
+    z = np.linalg.solve(A.T, 2.0 * (x - c["Y"]))
+    assert np.linalg.norm(gb - z) <= 1e-9 * np.linalg.norm(z)
+    assert abs(gl + np.sum(z * x)) <= 1e-9 * abs(np.sum(z * x))
+    assert abs(gh + np.sum(z * (dA @ x))) <= 1e-9 * abs(np.sum(z * (dA @ x)))
+
+
+def test_adjoint_matches_finite_differences_small(ak, small):
+    c, o, t = small
+    _, gb, gl, gh = _loss_and_grads(ak, t, c["B"], c["Y"], c["lam"], c["h"])
+    eps = 1e-5
+    fl = (_loss_only(ak, t, c["B"], c["Y"], c["lam"] + eps, c["h"]) -
+          _loss_only(ak, t, c["B"], c["Y"], c["lam"] - eps, c["h"])) / (2 * eps)
+    fh = (_loss_only(ak, t, c["B"], c["Y"], c["lam"], c["h"] + eps) -
+          _loss_only(ak, t, c["B"], c["Y"], c["lam"], c["h"] - eps)) / (2 * eps)
+    t.set_bandwidth(c["h"])
+    d = np.random.default_rng(3).standard_normal(c["B"].shape)
+    fb = (_loss_only(ak, t, c["B"] + eps * d, c["Y"], c["lam"], c["h"]) -
+          _loss_only(ak, t, c["B"] - eps * d, c["Y"], c["lam"], c["h"])) / (2 * eps)
+    say(f"  FD: dlam {fl:.6e} adj {gl:.6e}; dh {fh:.6e} adj {gh:.6e}")
+    assert abs(fl - gl) <= 1e-6 * abs(gl)
+    assert abs(fh - gh) <= 1e-6 * abs(gh)
+    assert abs(fb - np.sum(gb * d)) <= 1e-6 * abs(fb)
+
+
+def _richardson(F, x0, eps):
+    """Central differences at eps and 2 eps combined by Richardson extrapolation
+    (error O(eps^4)); also returns the plain central difference at eps."""
+    d1 = (F(x0 + eps) - F(x0 - eps)) / (2 * eps)
+    d2 = (F(x0 + 2 * eps) - F(x0 - 2 * eps)) / (4 * eps)
+    return (4 * d1 - d2) / 3, d1
+
+
+def test_adjoint_full_size_finite_differences(ak):
+    """N = 262,144 (d=8, 8 clusters, h=1, lambda=0.05, m=256, s=128, 4 RHS):
+    adjoint vs central differences (step 1e-5) with the GPU's own skeletons
+    frozen.  At this size lambda I + Ktilde is poorly conditioned (the loss is
+    ~1e14), so the O(eps^2) error of the plain central difference reaches
+    1e-4; Richardson extrapolation of steps 1e-5 and 2e-5 removes it."""
+    import torch
+    c = synth.config(5)
+    say(f"[gpu grad] differentiation workload at N={len(c['X'])}")
+    t = ak.Tree(torch.as_tensor(c["X"], device="cuda"), c["m"], c["s"], c["h"], seed=c["seed"])
+    t.skeletonize()
+    loss, gb, gl, gh = _loss_and_grads(ak, t, c["B"], c["Y"], c["lam"], c["h"])
+    eps = 1e-5
+    fl, fl1 = _richardson(lambda v: _loss_only(ak, t, c["B"], c["Y"], v, c["h"]), c["lam"], eps)
+    fh, fh1 = _richardson(lambda v: _loss_only(ak, t, c["B"], c["Y"], c["lam"], v), c["h"], eps)
+    say(f"  loss {loss:.3e}; dlam adj {gl:.8e} FD {fl1:.8e} Richardson {fl:.8e}; "
+        f"dh adj {gh:.8e} FD {fh1:.8e} Richardson {fh:.8e}")
+    assert abs(fl - gl) <= 1e-6 * abs(gl)
+    assert abs(fh - gh) <= 1e-6 * abs(gh)
