@@ -268,12 +268,26 @@ void gmm_add(GmmBuild &gb, GmmTask t, int ncap, int64_t KC, char *ws, int64_t &o
     gb.ws_elems = std::max(gb.ws_elems, off);
 }
 
+// Renumber tile items so that consecutive items (which share operands) run
+// on one XCD: block b executes item xcd * chunk + slot with xcd = b % 8,
+// slot = b / 8; positions past the end hold a no-op item (task -1).
+void xcd_order(std::vector<TileItem> &items) {
+    const int64_t n = (int64_t)items.size(), chunk = cdiv(n, 8);
+    std::vector<TileItem> out((size_t)(8 * chunk), TileItem{-1, 0, 0, 0});
+    for (int64_t b = 0; b < 8 * chunk; b++) {
+        const int64_t L = (b % 8) * chunk + b / 8;
+        if (L < n) out[(size_t)b] = items[(size_t)L];
+    }
+    items.swap(out);
+}
+
 template <typename T, typename TB, typename TO>
 hipError_t launch_kmm(const KmmTask *tasks, const TileItem *items, int nitems, int ncol, int d, int tc,
                       hipStream_t st) {
-    if (tc == 128) hipLaunchKernelGGL((k_kmm<T, TB, TO, 128>), dim3(nitems), dim3(256), 0, st, tasks, items, ncol, d);
-    else if (tc == 64) hipLaunchKernelGGL((k_kmm<T, TB, TO, 64>), dim3(nitems), dim3(256), 0, st, tasks, items, ncol, d);
-    else hipLaunchKernelGGL((k_kmm<T, TB, TO, 16>), dim3(nitems), dim3(256), 0, st, tasks, items, ncol, d);
+    const size_t lds = sizeof(T) * (64 + 16) * d;
+    if (tc == 128) hipLaunchKernelGGL((k_kmm<T, TB, TO, 128>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
+    else if (tc == 64) hipLaunchKernelGGL((k_kmm<T, TB, TO, 64>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
+    else hipLaunchKernelGGL((k_kmm<T, TB, TO, 16>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
     return hipGetLastError();
 }
 
@@ -289,6 +303,7 @@ askit_status kmm_commit(Plan &P, KmmBuild &kb, Prec tin, Prec tout, int d, int r
     if (kb.tasks.empty()) return ASKIT_OK;
     const Prec tb = tbin < 0 ? tin : (Prec)tbin;
     DBuf *bt = P.own(), *bi = P.own();
+    xcd_order(kb.items);
     ST_TRY(upload(*bt, kb.tasks));
     ST_TRY(upload(*bi, kb.items));
     const KmmTask *tp = bt->as<KmmTask>();
@@ -318,6 +333,7 @@ askit_status kmm_commit(Plan &P, KmmBuild &kb, Prec tin, Prec tout, int d, int r
 askit_status gmm_commit(Plan &P, GmmBuild &gb, Prec t, int rows_red_max) {
     if (gb.tasks.empty()) return ASKIT_OK;
     DBuf *bt = P.own(), *bi = P.own();
+    xcd_order(gb.items);
     ST_TRY(upload(*bt, gb.tasks));
     ST_TRY(upload(*bi, gb.items));
     const GmmTask *tp = bt->as<GmmTask>();
@@ -368,14 +384,13 @@ askit_status lu_commit(Plan &P, const std::vector<LuTask> &v) {
 // LU solves with nrhs = fixed (>0) or the run-time column count (fixed = 0)
 template <typename T, bool TR>
 hipError_t launch_lusolve(const LuTask *tp, int n, int nrhs, hipStream_t st) {
-    if (nrhs > 16) {
-        const int panels = (int)cdiv(nrhs, 32);
-        hipLaunchKernelGGL((k_lusolve<T, 32, TR>), dim3(n * panels), dim3(256), 0, st, tp, nrhs, panels);
-    } else {
-        hipLaunchKernelGGL((k_lusolve<T, 16, TR>), dim3(n), dim3(256), 0, st, tp, nrhs, 1);
-    }
+    const int panels = nrhs > 16 ? (int)cdiv(nrhs, 32) : 1;
+    const int grid = 8 * (int)cdiv((int64_t)n * panels, 8);
+    if (nrhs > 16) hipLaunchKernelGGL((k_lusolve<T, 32, TR>), dim3(grid), dim3(256), 0, st, tp, n, nrhs, panels);
+    else hipLaunchKernelGGL((k_lusolve<T, 16, TR>), dim3(grid), dim3(256), 0, st, tp, n, nrhs, 1);
     return hipGetLastError();
 }
+
 
 askit_status getrs_commit(Plan &P, const std::vector<LuTask> &v, Prec t, bool trans, int fixed) {
     if (v.empty()) return ASKIT_OK;
@@ -729,9 +744,10 @@ static askit_status skeletonize_impl(askit_tree *trees, int count, hipStream_t s
             hipLaunchKernelGGL(k_sample, dim3(n), dim3(64), 0, st, dsamp.as<SampTask>(), nsamp_max, err.as<int32_t>());
             return hipGetLastError();
         }));
-        const int rt = (int)cdiv(nsamp_max, 64);
+        const int rt = (int)cdiv(nsamp_max, 64), ct = (int)cdiv(cmax, 64);
         HIP_TRY(timed("skel:k_sample_block", st, [&] {
-            hipLaunchKernelGGL(k_sample_block, dim3(n * rt), dim3(256), 0, st, dsk.as<SkelTask>(), rt, nsamp_max, d);
+            hipLaunchKernelGGL(k_sample_block, dim3(n * rt * ct), dim3(256), sizeof(double) * 128 * d, st,
+                               dsk.as<SkelTask>(), rt, nsamp_max, d, ct);
             return hipGetLastError();
         }));
         HIP_TRY(timed("skel:k_qrcp", st, [&] {
@@ -884,9 +900,9 @@ static askit_status factor_plan(const std::vector<askit_factor> &fs, Plan &P) {
         DBuf *b = P.own();
         ST_TRY(upload(*b, lt));
         const LeafTask *lp = b->as<LeafTask>();
-        const int nl = (int)lt.size(), mm = mmax;
+        const int nl = (int)lt.size(), tl = (int)cdiv(mmax, 64);
         P.add("k_leaf_block", [=](hipStream_t st, int) -> hipError_t {
-            hipLaunchKernelGGL(k_leaf_block, dim3(nl * mm), dim3(256), 0, st, lp, mm, d);
+            hipLaunchKernelGGL(k_leaf_block, dim3(nl * tl * tl), dim3(256), sizeof(double) * 128 * d, st, lp, tl, d);
             return hipGetLastError();
         });
         ST_TRY(lu_commit(P, lu));

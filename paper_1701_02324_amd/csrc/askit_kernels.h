@@ -30,13 +30,14 @@ __global__ void k_check_finite(const double *X, int64_t n, int32_t *bad);
 
 // skeletons (k_skel.hip)
 __global__ void k_sample(const SampTask *tasks, int nsamp, int32_t *err);
-__global__ void k_sample_block(const SkelTask *tasks, int rowtiles, int ldm, int d);
+__global__ void k_sample_block(const SkelTask *tasks, int rowtiles, int ldm, int d, int coltiles);
 __global__ void k_qrcp(const SkelTask *tasks, int s, int ldm);
 
 // LU (k_lu.hip)
 __global__ void k_lu(const LuTask *tasks);
 __global__ void k_lu_diaginv(const LuTask *tasks);
-template <typename T, int NR, bool TRANS> __global__ void k_lusolve(const LuTask *tasks, int nrhs, int panels);
+template <typename T, int NR, bool TRANS>
+__global__ void k_lusolve(const LuTask *tasks, int ntask, int nrhs, int panels);
 
 // products (k_prod.hip)
 template <typename T, typename TB, typename TO, int TC>
@@ -51,7 +52,7 @@ __global__ void k_gather_rhs(const double *B, int64_t ldb, const int64_t *perm, 
 template <typename T>
 __global__ void k_scatter_rhs(const T *W, int64_t ldw, const int64_t *perm, int64_t N, int nrhs, double *X,
                               int64_t ldx, int add);
-__global__ void k_leaf_block(const LeafTask *tasks, int nmax, int d);
+__global__ void k_leaf_block(const LeafTask *tasks, int tiles, int d);
 template <typename T>
 __global__ void k_gather_multi(const GatherTask *tasks, const double *const *B, int nrhs, int bpt);
 template <typename T>

@@ -14,7 +14,7 @@
 namespace askit {
 
 constexpr int kLuThreads = 256;
-constexpr int kPanel = 16;
+constexpr int kPanel = 32;
 constexpr int kLuMaxN = 512;
 
 __device__ inline void argmax_abs(double v, int i, double &bv, int &bi) {
@@ -26,7 +26,6 @@ __device__ inline void argmax_abs(double v, int i, double &bv, int &bi) {
 }
 
 __global__ __launch_bounds__(kLuThreads) void k_lu(const LuTask *__restrict__ tasks) {
-    __shared__ double Lp[kLuMaxN * kPanel];   // panel columns below the diagonal block (col-major, ld = n)
     __shared__ double Up[kPanel * kLuMaxN];   // U block row (row-major, ld = n)
     __shared__ double redv[kLuThreads / kWave];
     __shared__ int redi[kLuThreads / kWave];
@@ -123,33 +122,53 @@ __global__ __launch_bounds__(kLuThreads) void k_lu(const LuTask *__restrict__ ta
                 Up[r * n + (j - j0)] = u[r];
             }
         }
-        for (int idx = tid; idx < nt * kPanel; idx += kLuThreads) {
-            int i = idx % nt, c = idx / nt;
-            Lp[c * nt + i] = c < nb ? A[j0 + i + (int64_t)(kb + c) * lda] : 0.0;
-        }
         if (nb < kPanel)
             for (int idx = tid; idx < (kPanel - nb) * nt; idx += kLuThreads) Up[(nb + idx / nt) * n + idx % nt] = 0.0;
         __syncthreads();
-        // ---- trailing update A22 -= L21 U12 with 16x16 MFMA tiles; each
-        // wave owns whole 16x16 output blocks
+        // ---- trailing update A22 -= L21 U12, computed as its transpose
+        // U12^T L21^T so that an accumulator register holds 16 consecutive
+        // rows of a column of A22 (coalesced column-major access).  Wave w
+        // owns the 16-row stripes w, w+4, ...; its L21 stripe stays in
+        // registers, U12 is read from LDS, four 16x16 blocks per pass.
         const int bt = (nt + 15) / 16;
-        for (int blk = wave; blk < bt * bt; blk += kLuThreads / kWave) {
-            const int bi0 = (blk % bt) * 16, bj0 = (blk / bt) * 16;
-            const int row = lane % 16, kq = lane / 16;
-            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-            for (int k4 = 0; k4 < kPanel; k4 += 4) {
-                int ai = bi0 + row, bj = bj0 + row;
-                double a = ai < nt ? Lp[(k4 + kq) * nt + ai] : 0.0;
-                double b = bj < nt ? Up[(k4 + kq) * n + bj] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        const int row = lane % 16, kq = lane / 16;
+        for (int st = wave; st < bt; st += kLuThreads / kWave) {
+            const int i0 = st * 16;
+            double lb[kPanel / 4];
+#pragma unroll
+            for (int kk = 0; kk < kPanel / 4; kk++) {
+                const int ii = i0 + row, k = 4 * kk + kq;
+                lb[kk] = (ii < nt && k < nb) ? A[j0 + ii + (int64_t)(kb + k) * lda] : 0.0;
             }
-            // acc[r] -> (row 4r + lane/16, col lane % 16) of the block (FP64 layout)
-            const int cj = bj0 + lane % 16;
-            if (cj < nt) {
-                for (int r = 0; r < 4; r++) {
-                    int ci = bi0 + 4 * r + kq;
-                    if (ci < nt) A[j0 + ci + (int64_t)(j0 + cj) * lda] -= acc[r];
+            for (int cb0 = 0; cb0 < bt; cb0 += 4) {
+                dbl4 acc[4];
+                double cv[4][4];
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    acc[q] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        const int ci = i0 + row, cj = (cb0 + q) * 16 + 4 * r + kq;
+                        cv[q][r] = (ci < nt && cj < nt) ? A[j0 + ci + (int64_t)(j0 + cj) * lda] : 0.0;
+                    }
                 }
+#pragma unroll
+                for (int kk = 0; kk < kPanel / 4; kk++) {
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const int cj = (cb0 + q) * 16 + row;
+                        const double ua = cj < nt ? Up[(4 * kk + kq) * n + cj] : 0.0;
+                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua, lb[kk], acc[q], 0, 0, 0);
+                    }
+                }
+                // acc[q][r] = (U12^T L21^T)[4r + lane/16][lane%16] = A22 entry (i0 + lane%16, (cb0+q)*16 + 4r + lane/16)
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        const int ci = i0 + row, cj = (cb0 + q) * 16 + 4 * r + kq;
+                        if (ci < nt && cj < nt) A[j0 + ci + (int64_t)(j0 + cj) * lda] = cv[q][r] - acc[q][r];
+                    }
             }
         }
         __syncthreads();
@@ -243,11 +262,18 @@ __device__ inline void block_update(double (*S)[NR + 1], int i0, int jb0, int jb
     __syncthreads();
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8); the (matrix, panel) pairs are numbered so that the panels of one
+// matrix land on the same XCD and share its factors in that XCD's L2.
 template <typename T, int NR, bool TRANS>
-__global__ __launch_bounds__(kLuThreads) void k_lusolve(const LuTask *__restrict__ tasks, int nrhs, int panels) {
+__global__ __launch_bounds__(kLuThreads) void k_lusolve(const LuTask *__restrict__ tasks, int ntask, int nrhs,
+                                                        int panels) {
     __shared__ double S[kLuMaxN][NR + 1];
-    const LuTask t = tasks[blockIdx.x / panels];
-    const int c0 = (blockIdx.x % panels) * NR;
+    const int total = ntask * panels, chunk = (total + 7) / 8;
+    const int L = (blockIdx.x % 8) * chunk + blockIdx.x / 8;
+    if (L >= total) return;
+    const LuTask t = tasks[L / panels];
+    const int c0 = (L % panels) * NR;
     if (c0 >= nrhs) return;
     const int ncols = min(NR, nrhs - c0);
     const int n = t.n, lda = t.lda, nb = (n + 15) / 16, tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
@@ -308,8 +334,8 @@ __global__ __launch_bounds__(kLuThreads) void k_lusolve(const LuTask *__restrict
 }
 
 #define LUS_INST(T, NR)                                                              \
-    template __global__ void k_lusolve<T, NR, false>(const LuTask *, int, int);      \
-    template __global__ void k_lusolve<T, NR, true>(const LuTask *, int, int);
+    template __global__ void k_lusolve<T, NR, false>(const LuTask *, int, int, int); \
+    template __global__ void k_lusolve<T, NR, true>(const LuTask *, int, int, int);
 LUS_INST(double, 16) LUS_INST(double, 32) LUS_INST(float, 16) LUS_INST(float, 32)
 
 }  // namespace askit

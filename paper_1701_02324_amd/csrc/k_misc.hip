@@ -62,24 +62,36 @@ template __global__ void k_gather_multi<float>(const GatherTask *, const double 
 template __global__ void k_scatter_multi<double>(const GatherTask *, double *const *, int, int);
 template __global__ void k_scatter_multi<float>(const GatherTask *, double *const *, int, int);
 
-// lambda I + K(X_a, X_a) in column-major; grid = task * n_max + column
-__global__ void k_leaf_block(const LeafTask *__restrict__ tasks, int nmax, int d) {
-    const LeafTask t = tasks[blockIdx.x / nmax];
-    const int j = blockIdx.x % nmax;
-    if (j >= t.n) return;
-    const double *y = t.X + (t.b + j) * d;
-    double yc[kMaxDim];
-    for (int k = 0; k < d; k++) yc[k] = y[k];
-    for (int i = threadIdx.x; i < t.n; i += blockDim.x) {
-        const double *x = t.X + (t.b + i) * d;
+// lambda I + K(X_a, X_a) in column-major, 64 x 64 tiles with both point
+// sets staged in LDS; grid = task * tiles^2 + tile
+__global__ __launch_bounds__(256) void k_leaf_block(const LeafTask *__restrict__ tasks, int tiles, int d) {
+    extern __shared__ double dyn_lds[];  // 2 x 64 x d doubles
+    double *ys = dyn_lds, *xs = dyn_lds + 64 * d;
+    const int per = tiles * tiles;
+    const LeafTask t = tasks[blockIdx.x / per];
+    const int rt = (blockIdx.x % per) % tiles, ct = (blockIdx.x % per) / tiles;
+    const int r0 = rt * 64, c0 = ct * 64;
+    if (r0 >= t.n || c0 >= t.n) return;
+    const int nr = min(64, t.n - r0), nc = min(64, t.n - c0);
+    for (int i = threadIdx.x; i < 64 * d; i += blockDim.x) {
+        const int a = i / d, k = i % d;
+        ys[i] = a < nr ? t.X[(t.b + r0 + a) * d + k] : 0.0;
+        xs[i] = a < nc ? t.X[(t.b + c0 + a) * d + k] : 0.0;
+    }
+    __syncthreads();
+    const int r = threadIdx.x % 64;
+    if (r >= nr) return;
+    const double *y = ys + r * d;
+    for (int c = threadIdx.x / 64; c < nc; c += 4) {
+        const double *x = xs + c * d;
         double r2 = 0.0;
         for (int k = 0; k < d; k++) {
-            double df = x[k] - yc[k];
+            const double df = y[k] - x[k];
             r2 = fma(df, df, r2);
         }
         double v = exp(r2 * t.scale);
-        if (i == j) v += t.lambda;
-        t.A[i + (int64_t)j * t.lda] = v;
+        if (r0 + r == c0 + c) v += t.lambda;
+        t.A[(r0 + r) + (int64_t)(c0 + c) * t.lda] = v;
     }
 }
 

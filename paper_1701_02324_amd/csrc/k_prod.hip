@@ -58,9 +58,10 @@ __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, 
     constexpr int NB = TC / 16;
     __shared__ T sA[kTR][kKS + 1];
     __shared__ T sB[kKS][TC + 1];
-    __shared__ T sR[kTR * kMaxDim];
-    __shared__ T sS[kKS * kMaxDim];
+    extern __shared__ double dyn_lds[];  // (64 + 16) x d elements of T
+    T *sR = (T *)dyn_lds, *sS = (T *)dyn_lds + kTR * d;
     const TileItem it = items[blockIdx.x];
+    if (it.task < 0) return;
     const KmmTask t = tasks[it.task];
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
     const int nrow = src_count(t.R);
@@ -143,6 +144,7 @@ __global__ __launch_bounds__(256) void k_gmm(const GmmTask *__restrict__ tasks, 
     __shared__ T sA[kTR][kKS + 1];
     __shared__ T sB[kKS][TC + 1];
     const TileItem it = items[blockIdx.x];
+    if (it.task < 0) return;
     const GmmTask t = tasks[it.task];
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
     const int r0 = it.rt * kTR, c0 = it.ct * TC;

@@ -86,25 +86,32 @@ __device__ inline double sqdist(const double *x, const double *y, int d) {
     return r2;
 }
 
-// block: 256 threads = 64 sampled rows x 4 column lanes; the 64 sampled
-// points are staged in LDS, every candidate point is read once per block
-__global__ __launch_bounds__(256) void k_sample_block(const SkelTask *__restrict__ tasks, int rowtiles, int ldm, int d) {
-    __shared__ double ys[64 * kMaxDim];
-    const int task = blockIdx.x / rowtiles, r0 = (blockIdx.x % rowtiles) * 64;
+// block: 256 threads on a 64 x 64 tile (sampled rows x candidate columns);
+// both point sets are staged in LDS, each thread writes 16 entries of one
+// column (consecutive rows across lanes: coalesced column-major stores)
+__global__ __launch_bounds__(256) void k_sample_block(const SkelTask *__restrict__ tasks, int rowtiles, int ldm, int d,
+                                                      int coltiles) {
+    extern __shared__ double dyn_lds[];  // 2 x 64 x d doubles
+    double *ys = dyn_lds, *xs = dyn_lds + 64 * d;
+    const int per = rowtiles * coltiles;
+    const int task = blockIdx.x / per, rt = (blockIdx.x % per) % rowtiles, ct = (blockIdx.x % per) / rowtiles;
     const SkelTask t = tasks[task];
-    if (r0 >= t.nq) return;
+    const int r0 = rt * 64, c0 = ct * 64;
     const int sl = t.leaf ? 0 : *t.srl;
     const int ncand = t.leaf ? t.n : sl + *t.srr;
-    const int nr = t.nq - r0 < 64 ? t.nq - r0 : 64;
-    for (int i = threadIdx.x; i < nr * d; i += blockDim.x) ys[i] = t.X[(int64_t)t.q[r0 + i / d] * d + i % d];
+    if (r0 >= t.nq || c0 >= ncand) return;
+    const int nr = min(64, t.nq - r0), nc = min(64, ncand - c0);
+    for (int i = threadIdx.x; i < 64 * d; i += blockDim.x) {
+        const int a = i / d, k = i % d;
+        ys[i] = a < nr ? t.X[(int64_t)t.q[r0 + a] * d + k] : 0.0;
+        xs[i] = a < nc ? t.X[(int64_t)cand_pos(t, c0 + a, sl) * d + k] : 0.0;
+    }
     __syncthreads();
     const int r = threadIdx.x % 64;
     if (r >= nr) return;
     const double *y = ys + r * d;
-    for (int c = threadIdx.x / 64; c < ncand; c += 4) {
-        const double *x = t.X + (int64_t)cand_pos(t, c, sl) * d;
-        t.M[(int64_t)c * ldm + r0 + r] = exp(sqdist(x, y, d) * t.scale);
-    }
+    for (int c = threadIdx.x / 64; c < nc; c += 4)
+        t.M[(int64_t)(c0 + c) * ldm + r0 + r] = exp(sqdist(xs + c * d, y, d) * t.scale);
 }
 
 // ---------------------------------------------------------------------------
@@ -181,98 +188,164 @@ __global__ __launch_bounds__(kQrThreads) void k_qrcp(const SkelTask *__restrict_
         s_zero = 0;
     }
     __syncthreads();
+    // Pivot steps.  Every wave finds the pivot itself from the norms in LDS
+    // (no barrier); wave 0 swaps the columns in memory, builds the reflector
+    // and publishes it in LDS; one barrier; all waves apply it to the
+    // trailing columns (two at a time, held in registers when the sampled
+    // block has at most 1024 rows) and recompute their norms; one barrier.
+    __shared__ double s_tau;
+    __shared__ int32_t s_stop;
+    if (tid == 0) s_stop = 0;
+    __syncthreads();
     double r00 = 0.0;
     for (int j = 0; j < steps; j++) {
-        // pivot: largest norm, lowest column on ties
         double bv = -1.0;
         int bi = 0x7fffffff;
-        for (int c = j + tid; c < ncand; c += kQrThreads) {
-            double v = nrm[c];
+        for (int c = j + lane; c < ncand; c += kWave) {
+            const double v = nrm[c];
             if (v > bv || (v == bv && c < bi)) {
                 bv = v;
                 bi = c;
             }
         }
         for (int o = kWave / 2; o > 0; o >>= 1) {
-            double ov = __shfl_xor(bv, o);
-            int oi = __shfl_xor(bi, o);
+            const double ov = __shfl_xor(bv, o);
+            const int oi = __shfl_xor(bi, o);
             if (ov > bv || (ov == bv && oi < bi)) {
                 bv = ov;
                 bi = oi;
             }
         }
-        if (lane == 0) {
-            redv[wave] = bv;
-            redi[wave] = bi;
+        const int p = bi;
+        if (wave == 0) {
+            double *col = M + (int64_t)j * ldm;
+            double xn = 0.0, aj = 0.0;  // aj: entry (j, j) after the swap, held by lane j % 64
+            if (p != j) {
+                double *cp = M + (int64_t)p * ldm;
+                for (int i = lane; i < rows; i += kWave) {
+                    const double a = col[i], b = cp[i];
+                    col[i] = b;
+                    cp[i] = a;
+                    if (i > j) xn = fma(b, b, xn);
+                    if (i == j) aj = b;
+                }
+                if (lane == 0) {
+                    const int ti = piv[j];
+                    piv[j] = piv[p];
+                    piv[p] = ti;
+                }
+            } else {
+                for (int i = j + 1 + lane; i < rows; i += kWave) xn = fma(col[i], col[i], xn);
+                if (lane == j % kWave) aj = col[j];
+            }
+            xn = wave_sum(xn);
+            const double alpha = __shfl(aj, j % kWave);
+            double beta, tau, sc;
+            if (xn == 0.0) {
+                beta = alpha; tau = 0.0; sc = 0.0;
+            } else {
+                beta = -copysign(sqrt(alpha * alpha + xn), alpha);
+                tau = (beta - alpha) / beta;
+                sc = 1.0 / (alpha - beta);
+            }
+            const double r0 = j == 0 ? fabs(beta) : r00;
+            const bool stop = (j > 0 && fabs(beta) <= kRankGuard * r0) || (j == 0 && r0 == 0.0);
+            if (stop) {
+                if (lane == 0) {
+                    s_rank = j == 0 ? 1 : j;
+                    s_zero = (j == 0);
+                    s_stop = 1;
+                }
+            } else {
+                for (int i = j + 1 + lane; i < rows; i += kWave) {
+                    const double v = col[i] * sc;
+                    vh[i] = v;
+                    col[i] = v;
+                }
+                if (lane == 0) {
+                    vh[j] = 1.0;
+                    col[j] = beta;
+                    s_tau = tau;
+                }
+            }
         }
         __syncthreads();
-        int p = redi[0];
-        double pv = redv[0];
-        for (int w = 1; w < kQrWaves; w++)
-            if (redv[w] > pv || (redv[w] == pv && redi[w] < p)) {
-                pv = redv[w];
-                p = redi[w];
+        if (s_stop) break;
+        if (j == 0) r00 = fabs(M[0]);
+        const double tau = s_tau;
+        // apply H to the columns right of j; new squared norms over rows j+1..
+        if (rows - j <= 16 * kWave) {
+            double vr[16];
+#pragma unroll
+            for (int t = 0; t < 16; t++) {
+                const int i = j + lane + t * kWave;
+                vr[t] = i < rows ? vh[i] : 0.0;
             }
-        if (p != j) {
-            for (int i = tid; i < rows; i += kQrThreads) {
-                double a = M[(int64_t)j * ldm + i];
-                M[(int64_t)j * ldm + i] = M[(int64_t)p * ldm + i];
-                M[(int64_t)p * ldm + i] = a;
+            for (int c = j + 1 + 2 * wave; c < ncand; c += 2 * kQrWaves) {
+                const bool two = c + 1 < ncand;
+                double *c0 = M + (int64_t)c * ldm, *c1 = M + (int64_t)(two ? c + 1 : c) * ldm;
+                double a0[16], a1[16];
+                double w0 = 0.0, w1 = 0.0;
+#pragma unroll
+                for (int t = 0; t < 16; t++) {
+                    const int i = j + lane + t * kWave;
+                    a0[t] = i < rows ? c0[i] : 0.0;
+                    a1[t] = i < rows ? c1[i] : 0.0;
+                }
+#pragma unroll
+                for (int t = 0; t < 16; t++) {
+                    w0 = fma(vr[t], a0[t], w0);
+                    w1 = fma(vr[t], a1[t], w1);
+                }
+                for (int o = kWave / 2; o > 0; o >>= 1) {
+                    w0 += __shfl_xor(w0, o);
+                    w1 += __shfl_xor(w1, o);
+                }
+                w0 *= tau;
+                w1 *= tau;
+                double n0 = 0.0, n1 = 0.0;
+#pragma unroll
+                for (int t = 0; t < 16; t++) {
+                    const int i = j + lane + t * kWave;
+                    a0[t] = fma(-vr[t], w0, a0[t]);
+                    a1[t] = fma(-vr[t], w1, a1[t]);
+                    if (i > j && i < rows) {
+                        n0 = fma(a0[t], a0[t], n0);
+                        n1 = fma(a1[t], a1[t], n1);
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < 16; t++) {
+                    const int i = j + lane + t * kWave;
+                    if (i < rows) {
+                        c0[i] = a0[t];
+                        if (two) c1[i] = a1[t];
+                    }
+                }
+                for (int o = kWave / 2; o > 0; o >>= 1) {
+                    n0 += __shfl_xor(n0, o);
+                    n1 += __shfl_xor(n1, o);
+                }
+                if (lane == 0) {
+                    nrm[c] = n0;
+                    if (two) nrm[c + 1] = n1;
+                }
             }
-        }
-        __syncthreads();
-        if (tid == 0 && p != j) {
-            int ti = piv[j]; piv[j] = piv[p]; piv[p] = ti;
-            double tv = nrm[j]; nrm[j] = nrm[p]; nrm[p] = tv;
-        }
-        // Householder reflector of column j, rows j..rows-1
-        double *col = M + (int64_t)j * ldm;
-        const double alpha = col[j];  // read before the barriers of block_sum
-        double part = 0.0;
-        for (int i = j + 1 + tid; i < rows; i += kQrThreads) part = fma(col[i], col[i], part);
-        double xn = block_sum(part, red);
-        double beta, tau, sc;
-        if (xn == 0.0) {
-            beta = alpha; tau = 0.0; sc = 0.0;
         } else {
-            beta = -copysign(sqrt(alpha * alpha + xn), alpha);
-            tau = (beta - alpha) / beta;
-            sc = 1.0 / (alpha - beta);
-        }
-        if (j == 0) r00 = fabs(beta);
-        bool stop = (j > 0 && fabs(beta) <= kRankGuard * r00) || (j == 0 && r00 == 0.0);
-        if (stop) {
-            if (tid == 0) {
-                s_rank = j == 0 ? 1 : j;
-                s_zero = (j == 0);
+            for (int c = j + 1 + wave; c < ncand; c += kQrWaves) {
+                double *ck = M + (int64_t)c * ldm;
+                double w = 0.0;
+                for (int i = j + lane; i < rows; i += kWave) w = fma(vh[i], ck[i], w);
+                w = wave_sum(w) * tau;
+                double acc = 0.0;
+                for (int i = j + lane; i < rows; i += kWave) {
+                    const double v = fma(-vh[i], w, ck[i]);
+                    ck[i] = v;
+                    if (i > j) acc = fma(v, v, acc);
+                }
+                acc = wave_sum(acc);
+                if (lane == 0) nrm[c] = acc;
             }
-            __syncthreads();
-            break;
-        }
-        for (int i = j + 1 + tid; i < rows; i += kQrThreads) {
-            double v = col[i] * sc;
-            vh[i] = v;
-            col[i] = v;
-        }
-        if (tid == 0) {
-            vh[j] = 1.0;
-            col[j] = beta;
-        }
-        __syncthreads();
-        // apply H to the columns right of j; new norms over rows j+1..
-        for (int c = j + 1 + wave; c < ncand; c += kQrWaves) {
-            double *ck = M + (int64_t)c * ldm;
-            double w = 0.0;
-            for (int i = j + lane; i < rows; i += kWave) w = fma(vh[i], ck[i], w);
-            w = wave_sum(w) * tau;
-            double acc = 0.0;
-            for (int i = j + lane; i < rows; i += kWave) {
-                double v = fma(-vh[i], w, ck[i]);
-                ck[i] = v;
-                if (i > j) acc = fma(v, v, acc);
-            }
-            acc = wave_sum(acc);
-            if (lane == 0) nrm[c] = acc;
         }
         __syncthreads();
     }
