@@ -38,23 +38,112 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_counts(N, d, m, s, D, nsamp, nrhs):
-    """Per-kernel algorithmic flops and bytes of one step (FP64 element = 8 B)."""
-    n_c = lambda l: N / 2 ** (l + 1)  # noqa: E731  child size at level l
-    # QRCP of nsamp x 2s (or m) blocks, s steps, one read + one write of the
-    # trailing block per step (norms fused into the update)
-    qr_bytes = qr_flops = 0.0
-    for lvl in range(1, D + 1):
-        cols = m if lvl == D else 2 * s
-        rows = min(nsamp, N - N / 2 ** lvl)
-        nodes = 2 ** lvl
-        for j in range(min(s, cols)):
-            area = (rows - j) * (cols - j - 1)
-            qr_bytes += nodes * 16.0 * area
-            qr_flops += nodes * 6.0 * area
-    z_flops = sum(2.0 * s * s * N for _ in range(D))                     # Z blocks, eq. (8)
-    tele_flops = sum(2.0 * s * s * N for l in range(1, D))               # telescoping, eq. (10)
-    return dict(qr_bytes=qr_bytes, qr_flops=qr_flops, z_flops=z_flops, tele_flops=tele_flops)
+def node_sizes(N, D):
+    """Points per heap node of the complete tree (left child gets floor(n/2))."""
+    n = np.zeros((2 << D) - 1, dtype=np.int64)
+    n[0] = N
+    for i in range((1 << D) - 1):
+        n[2 * i + 1] = n[i] // 2
+        n[2 * i + 2] = n[i] - n[i] // 2
+    return n
+
+
+def algorithmic_counts(N, d, m, s, D, nsamp, nrhs, ranks=None):
+    """Algorithmic flops and bytes of each kernel family in one step, from the
+    tree's actual skeleton ranks s_a (ranks[i] for heap node i; full rank s
+    when None).  These are the counts the method needs, not what the kernels
+    execute:
+      skel:k_qrcp         pivot step j of an r x c sampled block: 6 (r-j)(c-j-1)
+                          flops (reflector dot 2 + axpy 2 + column norm 2 per
+                          trailing element), s_a steps, then T = R11^-1 R12:
+                          s_a^2 (c - s_a); nothing when c <= s (P = I)
+      skel:k_sample_block 3d + 1 flops per sampled kernel entry (difference,
+                          fma, exp counted as one), nodes with c > s only
+      factor:k_lu         (2/3) n^3 per LU (leaf n = m, internal n = s_l + s_r)
+      factor:k_lusolve    2 n^2 s_a (leaf Phat, internal Z^-1 P_c below the root)
+      factor:k_kmm        2 s_l n_r s_r + 2 s_r n_l s_l per internal node (eq. (8))
+      factor:k_gmm        2 (n_l s_l + n_r s_r) s_a per internal non-root node
+                          (telescoping, eq. (10))
+      solve:k_lusolve     LU factors read once (8 n^2 bytes) + right-hand sides
+                          read and written (16 n nrhs bytes) per node
+      solve:k_kmm         2 (s_l n_r + s_r n_l) nrhs per internal node
+    """
+    nn = (2 << D) - 1
+    sz = node_sizes(N, D)
+    r = np.full(nn, s, dtype=np.int64) if ranks is None else np.asarray(ranks, dtype=np.int64)
+    first_leaf = (1 << D) - 1
+    c = {k: 0.0 for k in ("qr", "samp", "lu", "fsolve", "zblk", "tele", "sbytes", "sflops", "skmm")}
+    for i in range(nn):
+        n = float(sz[i])
+        leaf = i >= first_leaf
+        if i > 0:
+            cols = n if leaf else float(r[2 * i + 1] + r[2 * i + 2])
+            if cols > s:
+                rows = float(min(nsamp, N - n))
+                k = int(r[i])
+                c["qr"] += sum(6.0 * (rows - j) * (cols - j - 1) for j in range(k)) + k * k * (cols - k)
+                c["samp"] += rows * cols * (3.0 * d + 1)
+        nlu = n if leaf else float(r[2 * i + 1] + r[2 * i + 2])
+        c["lu"] += (2.0 / 3.0) * nlu ** 3
+        if i > 0:
+            c["fsolve"] += 2.0 * nlu * nlu * r[i]
+        c["sflops"] += 2.0 * nlu * nlu * nrhs
+        c["sbytes"] += 8.0 * nlu * nlu + 16.0 * nlu * nrhs
+        if not leaf:
+            l, rr = 2 * i + 1, 2 * i + 2
+            sl, sr, nl, nr = float(r[l]), float(r[rr]), float(sz[l]), float(sz[rr])
+            c["zblk"] += 2.0 * sl * nr * sr + 2.0 * sr * nl * sl
+            c["skmm"] += 2.0 * (sl * nr + sr * nl) * nrhs
+            if i > 0:
+                c["tele"] += 2.0 * (nl * sl + nr * sr) * r[i]
+    return c
+
+
+# Kernel families reported against their roofline: (profile key, count key,
+# bound, peak key, unit).  FP64 vector and FP64 MFMA share one peak on MI355X;
+# the mixed path's products run FP32 MFMA.
+ROOF_TABLE = [
+    ("skel:k_qrcp", "qr", "alu", "fp64", "TFLOP/s", lambda D: D),
+    ("skel:k_sample_block", "samp", "alu", "fp64", "TFLOP/s", lambda D: D),
+    ("factor:k_lu", "lu", "alu", "fp64", "TFLOP/s", lambda D: D + 1),
+    ("factor:k_lusolve", "fsolve", "mfma", "fp64", "TFLOP/s", lambda D: D),
+    ("factor:k_kmm", "zblk", "mfma", "fp32", "TFLOP/s", lambda D: D),
+    ("factor:k_gmm", "tele", "mfma", "fp32", "TFLOP/s", lambda D: D - 1),
+    ("solve:k_lusolve", "sbytes", "hbm", None, "GB/s", lambda D: D + 1),
+    ("solve:k_kmm", "skmm", "mfma", "fp32", "TFLOP/s", lambda D: D),
+]
+
+# HBM bytes of k_qrcp from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (KiB per
+# dispatch, averaged over the level launches of one step), scaled by what the
+# same counters read for a plain 1 GiB read + 1 GiB write (torch.neg).  Valid
+# only for the kernel source they were taken on: the sha256 of k_skel.hip.
+QRCP_TRAFFIC = None
+
+
+def kernel_source_sha(name):
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1701_02324_amd", "csrc", name), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def roofline_of(key, cnt_key, bound, peak_key, unit, nlaunch, prof, cnt, D):
+    """Algorithmic work of one pass of the kernel family divided over the
+    launches one pass makes (one per tree level); the solve plan runs once per
+    operator application, so the measured launch count may be a multiple."""
+    if key not in prof:
+        return None
+    ms, launches = prof[key]
+    per_launch_ms = ms / launches
+    work_per_launch = cnt[cnt_key] / nlaunch(D)
+    if unit == "GB/s":
+        achieved = work_per_launch / (per_launch_ms * 1e-3) / 1e9
+        peak = HBM_PEAK_GBS
+    else:
+        achieved = work_per_launch / (per_launch_ms * 1e-3) / 1e12
+        peak = PEAK_TFLOPS[peak_key]
+    return dict(kernel=key, bound=bound, achieved=achieved, peak=peak, unit=unit, frac=achieved / peak,
+                traffic=None, avg_launch_ms=per_launch_ms, launches=launches,
+                work_per_launch=work_per_launch)
 
 
 def main():
@@ -66,7 +155,7 @@ def main():
     ap.add_argument("--nrhs", type=int, default=64)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-sample", type=int, default=8192, help="points in the oracle's sample problem")
+    ap.add_argument("--cpu-sample", type=int, default=262144, help="points in the oracle's sample problem")
     ap.add_argument("--max-refine", type=int, default=10, help="GMRES-IR operator applications (mixed path)")
     ap.add_argument("--no-stable-check", action="store_true",
                     help="skip the mixed-vs-FP64 check on the N=65536 d=8 mixture (lambda=0.1)")
@@ -182,28 +271,28 @@ def main():
         f64.close()
         del x64, r64, xref
 
-    # roofline of the dominant kernel (largest total time in the timed steps)
-    D = tree.D
-    cnt = algorithmic_counts(N, d, m, s, D, nsamp, args.nrhs)
+    # roofline of every reported kernel family; the dominant one (largest
+    # total time in the timed steps) is the headline
+    ranks, cands = tree.skeleton_sizes()
+    cnt = algorithmic_counts(N, d, m, s, tree.D, nsamp, args.nrhs, ranks)
+    rank_levels = {}
+    for lvl in range(1, tree.D + 1):
+        rl = ranks[(1 << lvl) - 1:(2 << lvl) - 1]
+        rank_levels[lvl] = [int(rl.min()), round(float(rl.mean()), 1), int(rl.max())]
+    rooflines = {}
+    for key, ck, bound, pk, unit, nl in ROOF_TABLE:
+        r = roofline_of(key, ck, bound, pk, unit, nl, prof, cnt, tree.D)
+        if r is not None:
+            rooflines[key] = r
+    # the headline is the kernel that dominates the metric's value (the
+    # skeletonize + factorize time)
     top = sorted(prof.items(), key=lambda kv: -kv[1][0])
-    dom, (dom_ms, dom_n) = top[0]
-    per_launch_ms = dom_ms / dom_n
-    roof = None
-    if dom.endswith("k_qrcp"):
-        bytes_per_launch = cnt["qr_bytes"] / D  # launches: one per level
-        achieved = bytes_per_launch / (per_launch_ms * 1e-3) / 1e9
-        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                    traffic=None, kernel=dom, algorithmic="16 B per trailing element per pivot step",
-                    avg_launch_ms=per_launch_ms)
-    elif dom.endswith("k_kmm") and dom.startswith("factor"):
-        fl = cnt["z_flops"] / D
-        achieved = fl / (per_launch_ms * 1e-3) / 1e12
-        roof = dict(bound="mfma", achieved=achieved, peak=PEAK_TFLOPS["fp32"], unit="TFLOP/s",
-                    frac=achieved / PEAK_TFLOPS["fp32"], traffic=None, kernel=dom,
-                    algorithmic="2 s^2 N flop per level", avg_launch_ms=per_launch_ms)
-    else:
-        roof = dict(bound="unknown", achieved=None, peak=None, unit=None, frac=None, traffic=None, kernel=dom,
-                    avg_launch_ms=per_launch_ms)
+    dom = next((k for k, _ in top if k in rooflines and k.split(":")[0] in ("skel", "factor")), None)
+    roof = dict(rooflines[dom]) if dom else None
+    if roof is not None and dom == "skel:k_qrcp" and QRCP_TRAFFIC is not None \
+            and QRCP_TRAFFIC["src_sha256"] == kernel_source_sha("k_skel.hip") \
+            and QRCP_TRAFFIC["workload"] == (N, d, m, s, nsamp):
+        roof["traffic"] = QRCP_TRAFFIC["bytes_per_launch"]
 
     stable = None
     if not args.no_stable_check:
@@ -231,7 +320,9 @@ def main():
         "skeletonize_s": t_skel, "factorize_s": t_fac, "solve_s": t_sol, "solves_per_s": args.nrhs / t_sol,
         "refinement": info, "tree_s": t_tree,
         **res,
+        "skeleton_ranks_min_mean_max": rank_levels,
         "roofline": roof,
+        "rooflines": rooflines,
         "mixed_on_stable_config": stable,
         "cpu_baseline": cpu,
         "kernels_ms": {k: [round(v[0] / args.steps, 3), v[1] // args.steps] for k, v in top[:12]},

@@ -91,8 +91,11 @@ askit_status askit_skeletonize(askit_tree t, void *stream);
  * (i = 1 .. 2^(D+1)-2; entry 0 is the root and stays 0).  ids holds
  * nnodes * rank int32 and P nnodes * rank * cmax doubles with
  * cmax = max(leaf_size, 2 rank), node i at offset i * rank (ids) and
- * i * rank * cmax (P).  All three are HOST pointers.  Import replaces the
- * skeletons of a built tree (used to factor on a given set of skeletons). */
+ * i * rank * cmax (P).  All three are HOST pointers.  Export with ids and P
+ * both NULL fills only sizes.  Import replaces the skeletons of a built tree
+ * (used to factor on a given set of skeletons).  The ranks fix the shapes of
+ * every later step: Z of node alpha has order s_l + s_r, Phat_alpha has
+ * s_alpha columns. */
 askit_status askit_skeletons_export(askit_tree t, int32_t *ids, double *P, int32_t *sizes);
 askit_status askit_skeletons_import(askit_tree t, const int32_t *ids, const double *P, const int32_t *sizes);
 

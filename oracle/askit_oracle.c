@@ -542,7 +542,11 @@ void orc_skel_get(const orc_t *o, int64_t id, int64_t *skel_pos, double *P) {
 /* Replace one node's skeleton (used by tests that plant a mistake in the
  * oracle, and to build the identity case); the candidates stay as defined. */
 int orc_skel_set(orc_t *o, int64_t id, int sr, const int64_t *skel_pos, const double *P) {
-    if (id <= 0 || id >= o->nnodes || sr < 1 || sr > o->nc[id]) return ORC_ERR_ARG;
+    if (id <= 0 || id >= o->nnodes) return ORC_ERR_ARG;
+    /* the candidate set follows the children's current skeletons, which an
+     * earlier import may have changed (imports go bottom-up) */
+    o->nc[id] = is_leaf(o, id) ? (int)(o->ne[id] - o->nb[id]) : o->sr[2 * id + 1] + o->sr[2 * id + 2];
+    if (sr < 1 || sr > o->nc[id]) return ORC_ERR_ARG;
     free(o->skel[id]); free(o->P[id]);
     o->sr[id] = sr;
     o->skel[id] = (int64_t *)malloc(sizeof(int64_t) * sr);

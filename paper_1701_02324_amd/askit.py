@@ -151,11 +151,16 @@ def askit_skeletonize(tree, stream=None):
     _check(load().askit_skeletonize(tree, _stream(stream)))
 
 
-def askit_skeletons_export(tree, nnodes, rank, cmax):
+def askit_skeletons_export(tree, nnodes, rank, cmax, sizes_only=False):
+    """(ids, P, sizes); with sizes_only, ids and P are None and only the
+    per-node (s_alpha, |C|) pairs are fetched."""
     import numpy as np
+    sizes = np.zeros(2 * nnodes, dtype=np.int32)
+    if sizes_only:
+        _check(load().askit_skeletons_export(tree, None, None, sizes.ctypes.data))
+        return None, None, sizes
     ids = np.zeros(nnodes * rank, dtype=np.int32)
     P = np.zeros(nnodes * rank * cmax, dtype=np.float64)
-    sizes = np.zeros(2 * nnodes, dtype=np.int32)
     _check(load().askit_skeletons_export(tree, ids.ctypes.data, P.ctypes.data, sizes.ctypes.data))
     return ids, P, sizes
 
@@ -287,6 +292,11 @@ class Tree:
 
     def export_skeletons(self):
         return askit_skeletons_export(self.handle, self.nnodes, self.s, self.cmax)
+
+    def skeleton_sizes(self):
+        """(ranks s_alpha, candidate counts |C|) per heap node (root: 0, 0)."""
+        sizes = askit_skeletons_export(self.handle, self.nnodes, self.s, self.cmax, sizes_only=True)[2]
+        return sizes[0::2].copy(), sizes[1::2].copy()
 
     def import_skeletons(self, ids, P, sizes):
         askit_skeletons_import(self.handle, ids, P, sizes)

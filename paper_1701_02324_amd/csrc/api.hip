@@ -198,6 +198,7 @@ void kmm_add(KmmBuild &kb, KmmTask t, int kcap, int ncap, int64_t KC, int b_elem
     rd.drs = t.crs;
     rd.dcs = t.ccs;
     rd.op = t.op;
+    rd.ncol = t.ncol;
     for (int64_t c = 0; c < nch; c++) {
         KmmTask u = t;
         u.k0 = (int32_t)(c * KC);
@@ -248,6 +249,7 @@ void gmm_add(GmmBuild &gb, GmmTask t, int ncap, int64_t KC, char *ws, int64_t &o
     rd.drs = t.crs;
     rd.dcs = t.ccs;
     rd.op = t.op;
+    rd.ncol = t.ncol;
     for (int64_t c = 0; c < nch; c++) {
         GmmTask u = t;
         int64_t k0 = c * KC;
@@ -455,6 +457,7 @@ struct askit_tree_s {
     std::vector<int64_t> nb, ne;  // host node ranges
     DBuf X, Xp, perm, dnb, dne;
     DBuf srank, trunc, skel, Pt, samp;
+    std::vector<int32_t> hsr;  // host copy of the ranks s_alpha (root: 0)
     bool skel_ok = false;
     int refs = 0;
     double t_tree = 0, t_skel = 0;
@@ -757,9 +760,18 @@ static askit_status skeletonize_impl(askit_tree *trees, int count, hipStream_t s
     }
     int32_t herr = 0;
     HIP_TRY(hipMemcpyAsync(&herr, err.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    // the ranks decide the shapes of every later launch: keep them on the host
+    for (int i = 0; i < count; i++) {
+        trees[i]->hsr.assign(trees[i]->nnodes, 0);
+        HIP_TRY(hipMemcpyAsync(trees[i]->hsr.data(), trees[i]->srank.p, sizeof(int32_t) * trees[i]->nnodes,
+                               hipMemcpyDeviceToHost, st));
+    }
     HIP_TRY(hipStreamSynchronize(st));
     if (herr) return fail(ASKIT_ERR_HIP, "row sampling did not terminate");
-    for (int i = 0; i < count; i++) trees[i]->skel_ok = true;
+    for (int i = 0; i < count; i++) {
+        trees[i]->hsr[0] = 0;
+        trees[i]->skel_ok = true;
+    }
     return ASKIT_OK;
 }
 
@@ -773,8 +785,18 @@ askit_status askit_skeletonize(askit_tree t, void *stream) {
 }
 
 askit_status askit_skeletons_export(askit_tree t, int32_t *ids, double *P, int32_t *sizes) {
-    if (!t || !ids || !P || !sizes) return fail(ASKIT_ERR_ARG, "NULL argument");
+    if (!t || !sizes || (!ids) != (!P)) return fail(ASKIT_ERR_ARG, "NULL argument");
     if (!t->skel_ok) return fail(ASKIT_ERR_STATE, "tree not skeletonized");
+    if (!ids) {  // sizes only
+        for (int64_t id = 0; id < t->nnodes; id++) {
+            int lvl = 0;
+            while (((int64_t)2 << lvl) - 1 <= id) lvl++;
+            const bool leaf = (lvl == t->D);
+            sizes[2 * id] = id ? t->hsr[id] : 0;
+            sizes[2 * id + 1] = !id ? 0 : leaf ? (int)(t->ne[id] - t->nb[id]) : t->hsr[2 * id + 1] + t->hsr[2 * id + 2];
+        }
+        return ASKIT_OK;
+    }
     std::vector<int32_t> sr(t->nnodes);
     HIP_TRY(hipMemcpy(ids, t->skel.p, sizeof(int32_t) * t->nnodes * t->s, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(sr.data(), t->srank.p, sizeof(int32_t) * t->nnodes, hipMemcpyDeviceToHost));
@@ -834,6 +856,7 @@ askit_status askit_skeletons_import(askit_tree t, const int32_t *ids, const doub
     HIP_TRY(hipMemcpy(t->trunc.p, tr.data(), sizeof(int32_t) * t->nnodes, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(t->skel.p, sk.data(), sizeof(int32_t) * sk.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(t->Pt.p, Pt.data(), sizeof(double) * Pt.size(), hipMemcpyHostToDevice));
+    t->hsr = sr;
     t->skel_ok = true;
     return ASKIT_OK;
 }
@@ -889,10 +912,11 @@ static askit_status factor_plan(const std::vector<askit_factor> &fs, Plan &P) {
                     c.sld = s;
                     c.dld = s;
                     c.rows = a.n;
-                    c.cols = s;
+                    c.cols = t->hsr[id];
                     cp.push_back(c);
                     u.B = c.dst;
                     u.ldb = s;
+                    u.nrhs = t->hsr[id];
                     rs.push_back(u);
                 }
             }
@@ -928,55 +952,53 @@ static askit_status factor_plan(const std::vector<askit_factor> &fs, Plan &P) {
             int64_t wsoff = 0;
             for (int64_t id = f0; id < f0 + cnt; id++) {
                 const int64_t lc = 2 * id + 1, rc = 2 * id + 2;
+                // Z = [I, K1 Phat_r; K2 Phat_l, I] of order n = s_l + s_r,
+                // column-major with leading dimension n (eq. (8))
+                const int sl = t->hsr[lc], sr = t->hsr[rc], n = sl + sr, sa = t->hsr[id];
                 double *Z = f->lu_of(id);
-                ident.push_back({Z, s2, 0});
+                ident.push_back({Z, n, 0});
                 for (int side = 0; side < 2; side++) {
                     const int64_t a = side ? rc : lc, o = side ? lc : rc;  // skeleton of a vs points of o
                     KmmTask k{};
                     k.X = t->Xp.as<double>();
                     k.R.idx = t->skel.as<int32_t>() + a * s;
-                    k.R.cnt = t->srank.as<int32_t>() + a;
-                    k.R.n = s;
+                    k.R.n = t->hsr[a];
                     k.S.base = t->nb[o];
                     k.S.n = (int32_t)(t->ne[o] - t->nb[o]);
                     k.B = (const char *)f->ph(l + 1) + t->nb[o] * s * el;
                     k.ldb = s;
-                    k.C = side ? Z + s : Z + (int64_t)s * s2;
+                    k.C = side ? Z + sl : Z + (int64_t)sl * n;
                     k.crs = 1;
-                    k.ccs = s2;
+                    k.ccs = n;
                     k.scale = -1.0 / (2.0 * f->h * f->h);
                     k.op = OP_STORE;
-                    k.rcap = s;
-                    kmm_add(kb, k, k.S.n, s, kChunk, el, f->ws.as<char>(), wsoff);
+                    k.rcap = t->hsr[a];
+                    k.ncol = t->hsr[o];
+                    kmm_add(kb, k, k.S.n, k.ncol, kChunk, el, f->ws.as<char>(), wsoff);
                 }
                 LuTask u{};
                 u.A = Z;
                 u.piv = f->piv_of(id);
                 u.dinv = f->dinv_of(id);
-                u.n = s2;
-                u.lda = s2;
+                u.n = n;
+                u.lda = n;
                 u.ratio = f->ratio.as<double>() + id;
                 lu.push_back(u);
                 if (l >= 1) {
+                    // Xc = Z^{-1} P_c with P_c = P_{alpha~ [l~ r~]}^T (n x s_alpha,
+                    // row stride s), then Phat_alpha = blockdiag(Phat_l, Phat_r) Xc
                     double *xc = f->Xc.as<double>() + (id - f0) * (int64_t)s2 * s;
-                    CopyTask c{};
-                    c.src = t->Pt.as<double>() + id * (int64_t)t->cmax * s;
-                    c.dst = xc;
-                    c.sld = s;
-                    c.dld = s;
-                    c.rows = s2;
-                    c.cols = s;
-                    cp.push_back(c);
+                    const double *pt = t->Pt.as<double>() + id * (int64_t)t->cmax * s;
+                    cp.push_back(CopyTask{pt, xc, s, s, sl, sa});
+                    cp.push_back(CopyTask{pt + (int64_t)s * s, xc + (int64_t)sl * s, s, s, sr, sa});
                     u.B = xc;
                     u.ldb = s;
+                    u.nrhs = sa;
                     rs.push_back(u);
                     const void *xb = xc;
                     if (pr == P32) {
                         float *xf = f->Xcf.as<float>() + (id - f0) * (int64_t)s2 * s;
-                        CopyTask c2 = c;
-                        c2.src = xc;
-                        c2.dst = xf;
-                        cp32.push_back(c2);
+                        cp32.push_back(CopyTask{xc, xf, s, s, n, sa});
                         xb = xf;
                     }
                     for (int side = 0; side < 2; side++) {
@@ -985,17 +1007,18 @@ static askit_status factor_plan(const std::vector<askit_factor> &fs, Plan &P) {
                         g.A = (const char *)f->ph(l + 1) + t->nb[ch] * s * el;
                         g.ars = s;
                         g.acs = 1;
-                        g.B = (const char *)xb + (int64_t)side * s * s * el;
+                        g.B = (const char *)xb + (int64_t)(side ? sl : 0) * s * el;
                         g.brs = s;
                         g.bcs = 1;
                         g.C = (char *)f->ph(l) + t->nb[ch] * s * el;
                         g.crs = s;
                         g.ccs = 1;
                         g.rows = (int32_t)(t->ne[ch] - t->nb[ch]);
-                        g.kdim = s;
+                        g.kdim = t->hsr[ch];
                         g.op = OP_STORE;
+                        g.ncol = sa;
                         int64_t none = 0;
-                        gmm_add(gb, g, s, 1 << 30, nullptr, none);
+                        gmm_add(gb, g, sa, 1 << 30, nullptr, none);
                     }
                 }
             }
@@ -1188,32 +1211,34 @@ static askit_status solve_plan(const std::vector<askit_factor> &fs, Plan &P) {
             int64_t wsoff = 0;
             for (int64_t id = t->first(l); id < t->first(l + 1); id++) {
                 const int64_t lc = 2 * id + 1, rc = 2 * id + 2;
+                // t = [K1 w_r; K2 w_l] (s_l + s_r rows), y = Z^{-1} t,
+                // w_l -= Phat_l y_top, w_r -= Phat_r y_bot
                 char *tb = f->TB.as<char>() + id * (int64_t)s2 * cap * el;
+                const int sl = t->hsr[lc], n = sl + t->hsr[rc];
                 for (int side = 0; side < 2; side++) {
                     const int64_t a = side ? rc : lc, o = side ? lc : rc;
                     KmmTask k{};
                     k.X = t->Xp.as<double>();
                     k.R.idx = t->skel.as<int32_t>() + a * s;
-                    k.R.cnt = t->srank.as<int32_t>() + a;
-                    k.R.n = s;
+                    k.R.n = t->hsr[a];
                     k.S.base = t->nb[o];
                     k.S.n = (int32_t)(t->ne[o] - t->nb[o]);
                     k.B = W + t->nb[o] * cap * el;
                     k.ldb = cap;
-                    k.C = tb + (int64_t)side * s * cap * el;
+                    k.C = tb + (int64_t)(side ? sl : 0) * cap * el;
                     k.crs = cap;
                     k.ccs = 1;
                     k.scale = -1.0 / (2.0 * f->h * f->h);
                     k.op = OP_STORE;
-                    k.rcap = s;
+                    k.rcap = t->hsr[a];
                     kmm_add(kb, k, k.S.n, cap, kChunk, el, f->wsS.as<char>(), wsoff);
                 }
                 LuTask u{};
                 u.A = f->lu_of(id);
                 u.piv = f->piv_of(id);
                 u.dinv = f->dinv_of(id);
-                u.n = s2;
-                u.lda = s2;
+                u.n = n;
+                u.lda = n;
                 u.B = tb;
                 u.ldb = cap;
                 zs.push_back(u);
@@ -1223,14 +1248,14 @@ static askit_status solve_plan(const std::vector<askit_factor> &fs, Plan &P) {
                     g.A = (const char *)f->ph(l + 1) + t->nb[ch] * s * el;
                     g.ars = s;
                     g.acs = 1;
-                    g.B = tb + (int64_t)side * s * cap * el;
+                    g.B = tb + (int64_t)(side ? sl : 0) * cap * el;
                     g.brs = cap;
                     g.bcs = 1;
                     g.C = W + t->nb[ch] * cap * el;
                     g.crs = cap;
                     g.ccs = 1;
                     g.rows = (int32_t)(t->ne[ch] - t->nb[ch]);
-                    g.kdim = s;
+                    g.kdim = t->hsr[ch];
                     g.op = OP_SUB;
                     int64_t none = 0;
                     gmm_add(gb, g, cap, 1 << 30, nullptr, none);
@@ -1262,6 +1287,7 @@ static askit_status solvet_plan(askit_factor f, Plan &P) {
         for (int64_t id = t->first(l); id < t->first(l + 1); id++) {
             const int64_t lc = 2 * id + 1, rc = 2 * id + 2;
             char *tb = f->TB.as<char>() + id * (int64_t)s2 * cap * el;
+            const int sl = t->hsr[lc], n = sl + t->hsr[rc];
             for (int side = 0; side < 2; side++) {  // gt = [Phat_l^T w_l ; Phat_r^T w_r]
                 const int64_t ch = side ? rc : lc;
                 GmmTask g{};
@@ -1271,10 +1297,10 @@ static askit_status solvet_plan(askit_factor f, Plan &P) {
                 g.B = W + t->nb[ch] * cap * el;
                 g.brs = cap;
                 g.bcs = 1;
-                g.C = tb + (int64_t)side * s * cap * el;
+                g.C = tb + (int64_t)(side ? sl : 0) * cap * el;
                 g.crs = cap;
                 g.ccs = 1;
-                g.rows = s;
+                g.rows = t->hsr[ch];
                 g.kdim = (int32_t)(t->ne[ch] - t->nb[ch]);
                 g.op = OP_STORE;
                 gmm_add(gb, g, cap, kChunk, f->wsS.as<char>(), wsoff);
@@ -1283,8 +1309,8 @@ static askit_status solvet_plan(askit_factor f, Plan &P) {
             u.A = f->lu_of(id);
             u.piv = f->piv_of(id);
             u.dinv = f->dinv_of(id);
-            u.n = s2;
-            u.lda = s2;
+            u.n = n;
+            u.lda = n;
             u.B = tb;
             u.ldb = cap;
             zs.push_back(u);
@@ -1295,9 +1321,8 @@ static askit_status solvet_plan(askit_factor f, Plan &P) {
                 k.R.base = t->nb[ch];
                 k.R.n = (int32_t)(t->ne[ch] - t->nb[ch]);
                 k.S.idx = t->skel.as<int32_t>() + a * s;
-                k.S.cnt = t->srank.as<int32_t>() + a;
-                k.S.n = s;
-                k.B = tb + (int64_t)(side ? 0 : s) * cap * el;
+                k.S.n = t->hsr[a];
+                k.B = tb + (int64_t)(side ? 0 : sl) * cap * el;
                 k.ldb = cap;
                 k.C = W + t->nb[ch] * cap * el;
                 k.crs = cap;
@@ -1305,7 +1330,7 @@ static askit_status solvet_plan(askit_factor f, Plan &P) {
                 k.scale = -1.0 / (2.0 * f->h * f->h);
                 k.op = OP_SUB;
                 k.rcap = k.R.n;
-                kmm_add(kb, k, s, cap, 1 << 30, el, nullptr, none);
+                kmm_add(kb, k, k.S.n, cap, 1 << 30, el, nullptr, none);
             }
         }
         ST_TRY(gmm_commit(P, gb, pr, s));
@@ -1380,8 +1405,7 @@ static askit_status matvec_plan(askit_factor f, int which, Plan &P) {
                 KmmTask k{};
                 k.X = t->Xp.as<double>();
                 k.R.idx = t->skel.as<int32_t>() + a * s;
-                k.R.cnt = t->srank.as<int32_t>() + a;
-                k.R.n = s;
+                k.R.n = t->hsr[a];
                 k.S.base = t->nb[o];
                 k.S.n = (int32_t)(t->ne[o] - t->nb[o]);
                 k.B = WX + t->nb[o] * cap;
@@ -1393,7 +1417,7 @@ static askit_status matvec_plan(askit_factor f, int which, Plan &P) {
                 k.hinv = 1.0 / f->h;
                 k.which = which;
                 k.op = OP_STORE;
-                k.rcap = s;
+                k.rcap = t->hsr[a];
                 kmm_add(kl, k, k.S.n, cap, kChunk, 8, f->wsS.as<char>(), wsoff);
             }
         }
@@ -1416,8 +1440,8 @@ static askit_status matvec_plan(askit_factor f, int which, Plan &P) {
                 g.C = CB + (2 * id + 1 + side) * (int64_t)s * cap;
                 g.crs = cap;
                 g.ccs = 1;
-                g.rows = s;
-                g.kdim = s;
+                g.rows = t->hsr[2 * id + 1 + side];
+                g.kdim = t->hsr[id];
                 g.op = OP_ADD;
                 gmm_add(gb, g, cap, 1 << 30, nullptr, wsoff);
             }
@@ -1440,7 +1464,7 @@ static askit_status matvec_plan(askit_factor f, int which, Plan &P) {
             g.crs = cap;
             g.ccs = 1;
             g.rows = (int32_t)(t->ne[id] - t->nb[id]);
-            g.kdim = s;
+            g.kdim = t->hsr[id];
             g.op = OP_ADD;
             gmm_add(gb, g, cap, 1 << 30, nullptr, wsoff);
         }

@@ -45,7 +45,8 @@ struct KmmTask {
     int32_t which;         // 0: K, 1: dK/dh
     int32_t op;            // OutOp
     int32_t rcap;          // rows written: r < count gets the product, count <= r < rcap
-    int32_t pad;           // gets 0 when op == OP_STORE (padded skeleton slots)
+                           // gets 0 when op == OP_STORE (padded skeleton slots)
+    int32_t ncol;          // columns of this task (0: the launch's column count)
 };
 
 // One plain product task:  C(r, c) op= sum_k A(r, k) B(k, c)
@@ -54,7 +55,7 @@ struct GmmTask {
     const void *B;  int64_t brs, bcs;
     void *C;        int64_t crs, ccs;
     int32_t rows, kdim;
-    int32_t op, pad;
+    int32_t op, ncol;      // ncol: columns of this task (0: the launch's column count)
 };
 
 // Work item of a tiled launch: task index, row tile, column tile.
@@ -71,7 +72,7 @@ struct RedTask {
     int32_t np, rows;
     void *dst;
     int64_t drs, dcs;
-    int32_t op, pad;
+    int32_t op, ncol;      // ncol: columns of this task (0: the launch's column count)
 };
 
 // Strided block copy / cast: dst(r, c) = src(r, c), r < rows, c < cols.
@@ -115,6 +116,7 @@ struct LuTask {
     int64_t ldb;
     double *ratio;        // pivot ratio output (factor)
     double *dinv;         // inverses of the 16 x 16 diagonal blocks of L and U
+    int32_t nrhs, pad;    // right-hand sides of this task (0: the launch's count)
 };
 
 // Sampling task (uniform rows outside a node, SplitMix64 stream).

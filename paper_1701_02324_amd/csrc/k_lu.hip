@@ -274,6 +274,7 @@ __global__ __launch_bounds__(kLuThreads) void k_lusolve(const LuTask *__restrict
     if (L >= total) return;
     const LuTask t = tasks[L / panels];
     const int c0 = (L % panels) * NR;
+    if (t.nrhs > 0) nrhs = min(nrhs, t.nrhs);
     if (c0 >= nrhs) return;
     const int ncols = min(NR, nrhs - c0);
     const int n = t.n, lda = t.lda, nb = (n + 15) / 16, tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;

@@ -65,6 +65,7 @@ __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, 
     const KmmTask t = tasks[it.task];
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
     const int nrow = src_count(t.R);
+    if (t.ncol > 0) ncol = min(ncol, t.ncol);
     const int r0 = it.rt * kTR, c0 = it.ct * TC;
     TO *C = (TO *)t.C;
     if (r0 >= nrow) {  // tile of padded rows: zero-fill on store
@@ -149,6 +150,7 @@ __global__ __launch_bounds__(256) void k_gmm(const GmmTask *__restrict__ tasks, 
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
     const int r0 = it.rt * kTR, c0 = it.ct * TC;
     if (r0 >= t.rows) return;
+    if (t.ncol > 0) ncol = min(ncol, t.ncol);
     // optional split of the contraction: item.pad = chunk index
     const int kb = it.pad * kchunk, ke = min(t.kdim, kb + kchunk);
     const T *A = (const T *)t.A, *B = (const T *)t.B;
@@ -198,6 +200,7 @@ template <typename T, typename TO>
 __global__ void k_reduce(const RedTask *__restrict__ tasks, int ncol, int blocks_per_task) {
     const RedTask t = tasks[blockIdx.x / blocks_per_task];
     const int64_t e = (int64_t)(blockIdx.x % blocks_per_task) * blockDim.x + threadIdx.x;
+    if (t.ncol > 0) ncol = min(ncol, t.ncol);
     if (e >= (int64_t)t.rows * ncol) return;
     const int r = (int)(e / ncol), c = (int)(e % ncol);
     const T *src = (const T *)t.src;

@@ -160,11 +160,14 @@ __global__ __launch_bounds__(kQrThreads) void k_qrcp(const SkelTask *__restrict_
     // children's skeletons in the halves [0, s) and [s, 2s)
     auto prow = [&](int c) { return t.leaf ? c : (c < sl ? c : s + (c - sl)); };
 
-    for (int64_t i = tid; i < (int64_t)t.cmax * s; i += kQrThreads) t.Pt[i] = 0.0;
+    // P is written in the rows of the candidates and the columns below the
+    // rank only: nothing reads the rest of the padded slot
     if (ncand <= s) {  // no compression: skeleton = candidates, P = I
-        __syncthreads();
         for (int k = tid; k < s; k += kQrThreads) t.skel[k] = k < ncand ? cand_pos(t, k, sl) : -1;
-        for (int c = tid; c < ncand; c += kQrThreads) t.Pt[(int64_t)prow(c) * s + c] = 1.0;
+        for (int64_t i = tid; i < (int64_t)ncand * ncand; i += kQrThreads) {
+            const int c = (int)(i / ncand), k = (int)(i % ncand);
+            t.Pt[(int64_t)prow(c) * s + k] = k == c ? 1.0 : 0.0;
+        }
         if (tid == 0) {
             *t.sr = ncand;
             *t.trunc = 0;
@@ -375,7 +378,7 @@ __global__ __launch_bounds__(kQrThreads) void k_qrcp(const SkelTask *__restrict_
     for (int jc = tid; jc < ncand; jc += kQrThreads) {
         double *row = t.Pt + (int64_t)prow(piv[jc]) * s;
         if (jc < rank) {
-            row[jc] = 1.0;
+            for (int k = 0; k < rank; k++) row[k] = k == jc ? 1.0 : 0.0;
         } else {
             const double *tc = M + (int64_t)jc * ldm;
             for (int k = 0; k < rank; k++) row[k] = tc[k];
