@@ -122,13 +122,18 @@ askit_status askit_solve(askit_factor f, const double *B, int64_t ldb, int32_t n
 
 /* X = (lambda I + Ktilde)^{-T} B: the transpose of the same factorization
  * (Ktilde is not symmetric in the form of eq. (6)), applied from the root
- * down: Ktilde_aa^{-T} = D^{-T} (I - V^T Z^{-T} W^T).  Same conventions. */
+ * down: Ktilde_aa^{-T} = D^{-T} (I - V^T Z^{-T} W^T).  Same conventions,
+ * including refinement (GMRES on the transposed operator, askit_matvec with
+ * which = 2, preconditioned by the transposed factors). */
 askit_status askit_solve_transpose(askit_factor f, const double *B, int64_t ldb, int32_t nrhs, double *X,
                                    int64_t ldx, void *stream);
 
-/* Y = (lambda I + Ktilde) X (which = 0) or Y = dKtilde/dh X (which = 1,
- * skeletons held fixed), the hierarchical matvec of Sec. 2.1 in the form of
- * eq. (6), FP64, kernel blocks recomputed.  Same layout conventions. */
+/* Y = (lambda I + Ktilde) X (which = 0), Y = dKtilde/dh X (which = 1,
+ * skeletons held fixed) or Y = (lambda I + Ktilde)^T X (which = 2), the
+ * hierarchical matvec of Sec. 2.1 in the form of eq. (6), FP64, kernel blocks
+ * recomputed.  The transpose evaluates skeleton charges P_{a a~}^T x_a,
+ * gathered upward through the projections, at the sibling's points.  Same
+ * layout conventions. */
 askit_status askit_matvec(askit_factor f, int32_t which, const double *X, int64_t ldx, int32_t nrhs, double *Y,
                           int64_t ldy, void *stream);
 

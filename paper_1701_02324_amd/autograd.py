@@ -20,9 +20,11 @@ from .askit import ASKIT_FP64
 
 class KernelSolve(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, b, lam, h, tree, precision):
+    def forward(ctx, b, lam, h, tree, precision, refine):
         tree.set_bandwidth(float(h))
         f = tree.factorize(float(lam), precision)
+        if refine is not None:
+            f.set_refinement(int(refine[0]), float(refine[1]))
         x = f.solve(b)
         ctx.factor = f
         ctx.save_for_backward(x)
@@ -36,12 +38,15 @@ class KernelSolve(torch.autograd.Function):
         dlam, dh = f.adjoint_scalars(x, z)
         gl = torch.tensor(dlam, dtype=torch.float64)
         gh = torch.tensor(dh, dtype=torch.float64)
-        return z, gl, gh, None, None
+        return z, gl, gh, None, None, None
 
 
-def kernel_solve(b, lam, h, tree, precision=ASKIT_FP64):
+def kernel_solve(b, lam, h, tree, precision=ASKIT_FP64, refine=None):
     """x = (lambda I + Ktilde(h))^{-1} b on a skeletonized `Tree`; differentiable
-    in b (CUDA tensor, N or N x nrhs), lam and h (0-dim float64 tensors)."""
+    in b (CUDA tensor, N or N x nrhs), lam and h (0-dim float64 tensors).
+    refine = (max operator applications, relative residual) refines both the
+    solve and the transpose solve of the backward pass by GMRES against the
+    FP64 hierarchical operator."""
     lam = lam if isinstance(lam, torch.Tensor) else torch.tensor(float(lam), dtype=torch.float64)
     h = h if isinstance(h, torch.Tensor) else torch.tensor(float(h), dtype=torch.float64)
-    return KernelSolve.apply(b, lam, h, tree, precision)
+    return KernelSolve.apply(b, lam, h, tree, precision, refine)

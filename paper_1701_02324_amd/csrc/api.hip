@@ -475,7 +475,7 @@ struct askit_factor_s {
     // solve state
     int cap = 0;
     DBuf W, TB, WX, WY, CB, wsS, R, Dx, nrm, Vk, kpart, ksmall;
-    std::unique_ptr<Plan> solve_plan, solvet_plan, mv_plan[2];
+    std::unique_ptr<Plan> solve_plan, solvet_plan, mv_plan[3];
     int max_refine = 10;
     double refine_tol = 1e-11;
     askit_solve_info info{};
@@ -1165,6 +1165,7 @@ static askit_status ensure_cap(askit_factor f, int nrhs) {
     f->solvet_plan.reset();
     f->mv_plan[0].reset();
     f->mv_plan[1].reset();
+    f->mv_plan[2].reset();
     return ASKIT_OK;
 }
 
@@ -1354,7 +1355,10 @@ static askit_status solvet_plan(askit_factor f, Plan &P) {
 }
 
 // (lambda I + Ktilde) x or dKtilde/dh x in FP64 (WX -> WY)
+static askit_status matvec_t_plan(askit_factor f, Plan &P);
+
 static askit_status matvec_plan(askit_factor f, int which, Plan &P) {
+    if (which == 2) return matvec_t_plan(f, P);
     askit_tree t = f->t;
     const int s = t->s, D = t->D, d = t->d, cap = f->cap;
     double *WX = f->WX.as<double>(), *WY = f->WY.as<double>(), *CB = f->CB.as<double>();
@@ -1473,6 +1477,123 @@ static askit_status matvec_plan(askit_factor f, int which, Plan &P) {
     return ASKIT_OK;
 }
 
+// (lambda I + Ktilde)^T x in FP64 (WX -> WY).  The off-diagonal block (l, r)
+// of Ktilde is P_{l l~} K_{l~ r}, so its transpose K_{r l~} P_{l l~}^T acts
+// through skeleton charges q_a = P_{a a~}^T x_a, gathered upward with the
+// telescoped projections (q_a = P_c^T [q_l; q_r]), then evaluated at the
+// sibling's points: y_r += K_{r l~} q_l, y_l += K_{l r~} q_r.
+static askit_status matvec_t_plan(askit_factor f, Plan &P) {
+    askit_tree t = f->t;
+    const int s = t->s, D = t->D, d = t->d, cap = f->cap;
+    double *WX = f->WX.as<double>(), *WY = f->WY.as<double>(), *CB = f->CB.as<double>();
+    const double scale = -1.0 / (2.0 * f->h * f->h);
+    const int tc = cap >= 128 ? 128 : (cap >= 64 ? 64 : 16);
+    {  // leaves: symmetric diagonal blocks, plus lambda x
+        KmmBuild kb;
+        kb.tc = tc;
+        int64_t none = 0;
+        for (int64_t id = t->first(D); id < t->nnodes; id++) {
+            KmmTask k{};
+            k.X = t->Xp.as<double>();
+            k.R.base = t->nb[id];
+            k.R.n = (int32_t)(t->ne[id] - t->nb[id]);
+            k.S = k.R;
+            k.B = WX + t->nb[id] * cap;
+            k.ldb = cap;
+            k.C = WY + t->nb[id] * cap;
+            k.crs = cap;
+            k.ccs = 1;
+            k.scale = scale;
+            k.op = OP_STORE;
+            k.rcap = k.R.n;
+            kmm_add(kb, k, k.S.n, cap, 1 << 30, 8, nullptr, none);
+        }
+        ST_TRY(kmm_commit(P, kb, P64, P64, d, 0));
+        const double lam = f->lambda;
+        const int64_t N = t->N;
+        P.add("k_axpy", [=](hipStream_t st, int ncol) -> hipError_t {
+            hipLaunchKernelGGL(k_axpy<double>, dim3(grid1(N * ncol)), dim3(256), 0, st, WY, WX, (int64_t)cap, N,
+                               ncol, lam);
+            return hipGetLastError();
+        });
+    }
+    if (D == 0) return ASKIT_OK;
+    {  // leaf charges q_a = P_{a~ a} x_a
+        GmmBuild gb;
+        gb.tc = tc;
+        int64_t none = 0;
+        for (int64_t id = t->first(D); id < t->nnodes; id++) {
+            GmmTask g{};
+            g.A = t->Pt.as<double>() + id * (int64_t)t->cmax * s;
+            g.ars = 1;
+            g.acs = s;
+            g.B = WX + t->nb[id] * cap;
+            g.brs = cap;
+            g.bcs = 1;
+            g.C = CB + id * (int64_t)s * cap;
+            g.crs = cap;
+            g.ccs = 1;
+            g.rows = t->hsr[id];
+            g.kdim = (int32_t)(t->ne[id] - t->nb[id]);
+            g.op = OP_STORE;
+            gmm_add(gb, g, cap, 1 << 30, nullptr, none);
+        }
+        ST_TRY(gmm_commit(P, gb, P64, 0));
+    }
+    for (int l = D - 1; l >= 1; l--) {  // q_a = P_c^T [q_l; q_r], bottom-up
+        for (int side = 0; side < 2; side++) {
+            GmmBuild gb;
+            gb.tc = tc;
+            int64_t none = 0;
+            for (int64_t id = t->first(l); id < t->first(l + 1); id++) {
+                const int64_t ch = 2 * id + 1 + side;
+                GmmTask g{};
+                g.A = t->Pt.as<double>() + id * (int64_t)t->cmax * s + (int64_t)side * s * s;
+                g.ars = 1;
+                g.acs = s;
+                g.B = CB + ch * (int64_t)s * cap;
+                g.brs = cap;
+                g.bcs = 1;
+                g.C = CB + id * (int64_t)s * cap;
+                g.crs = cap;
+                g.ccs = 1;
+                g.rows = t->hsr[id];
+                g.kdim = t->hsr[ch];
+                g.op = side ? OP_ADD : OP_STORE;
+                gmm_add(gb, g, cap, 1 << 30, nullptr, none);
+            }
+            ST_TRY(gmm_commit(P, gb, P64, 0));
+        }
+    }
+    for (int l = 0; l < D; l++) {  // y_r += K_{r l~} q_l, y_l += K_{l r~} q_r
+        KmmBuild kb;
+        kb.tc = tc;
+        int64_t none = 0;
+        for (int64_t id = t->first(l); id < t->first(l + 1); id++) {
+            for (int side = 0; side < 2; side++) {
+                const int64_t src = 2 * id + 1 + side, dst = 2 * id + 2 - side;
+                KmmTask k{};
+                k.X = t->Xp.as<double>();
+                k.R.base = t->nb[dst];
+                k.R.n = (int32_t)(t->ne[dst] - t->nb[dst]);
+                k.S.idx = t->skel.as<int32_t>() + src * s;
+                k.S.n = t->hsr[src];
+                k.B = CB + src * (int64_t)s * cap;
+                k.ldb = cap;
+                k.C = WY + t->nb[dst] * cap;
+                k.crs = cap;
+                k.ccs = 1;
+                k.scale = scale;
+                k.op = OP_ADD;
+                k.rcap = k.R.n;
+                kmm_add(kb, k, k.S.n, cap, 1 << 30, 8, nullptr, none);
+            }
+        }
+        ST_TRY(kmm_commit(P, kb, P64, P64, d, 0));
+    }
+    return ASKIT_OK;
+}
+
 static askit_status check_solve_args(askit_factor f, const double *B, int64_t ldb, int32_t nrhs, double *X,
                                      int64_t ldx) {
     if (!f) return fail(ASKIT_ERR_ARG, "NULL factor");
@@ -1518,7 +1639,7 @@ static askit_status matvec_impl(askit_factor f, int which, const double *Xin, in
     ST_TRY(ensure_cap(f, nrhs));
     if (!f->mv_plan[which]) {
         f->mv_plan[which].reset(new Plan());
-        f->mv_plan[which]->tag = which ? "matvec_dh" : "matvec";
+        f->mv_plan[which]->tag = which == 1 ? "matvec_dh" : which == 2 ? "matvec_t" : "matvec";
         ST_TRY(matvec_plan(f, which, *f->mv_plan[which]));
     }
     const int64_t N = t->N;
@@ -1595,7 +1716,8 @@ static askit_status put_small(askit_factor f, const std::vector<double> &v, hipS
 }
 
 static askit_status gmres_refine(askit_factor f, const double *B, int64_t ldb, int nrhs, double *X, int64_t ldx,
-                                 hipStream_t st) {
+                                 bool trans, hipStream_t st) {
+    const int op = trans ? 2 : 0;  // operator: A or A^T
     const int64_t N = f->t->N, NR = N * (int64_t)nrhs;
     const int m = kRestart;
     const size_t need = sizeof(double) * (size_t)NR;
@@ -1616,14 +1738,14 @@ static askit_status gmres_refine(askit_factor f, const double *B, int64_t ldb, i
     // ... except for the residuals, so keep b in the last Krylov slot)
     double *Bc = V + (size_t)m * NR;
     HIP_TRY(hipMemcpyAsync(Bc, R, need, hipMemcpyDeviceToDevice, st));
-    ST_TRY(apply_inverse(f, B, ldb, nrhs, X, ldx, false, st));
+    ST_TRY(apply_inverse(f, B, ldb, nrhs, X, ldx, trans, st));
     int it = 0;
     double res = INFINITY, res0 = -1.0;
     std::vector<double> H((size_t)nrhs * (m + 1) * m), g((size_t)nrhs * (m + 1)), cs((size_t)nrhs * m),
         sn((size_t)nrhs * m), sc(nrhs), y;
     while (true) {
         // r = b - A x
-        ST_TRY(matvec_impl(f, 0, X, ldx, nrhs, R, N, st));
+        ST_TRY(matvec_impl(f, op, X, ldx, nrhs, R, N, st));
         hipLaunchKernelGGL(k_sub_from, dim3(grid1(NR)), dim3(256), 0, st, Bc, N, R, N, nrhs);
         HIP_TRY(hipGetLastError());
         std::vector<double> rn;
@@ -1645,8 +1767,8 @@ static askit_status gmres_refine(askit_factor f, const double *B, int64_t ldb, i
         int used = 0;
         for (int j = 0; j < mm && it < f->max_refine; j++) {
             double *Vj = V + (size_t)j * NR, *W = R;
-            ST_TRY(apply_inverse(f, Vj, N, nrhs, Z, N, false, st));
-            ST_TRY(matvec_impl(f, 0, Z, N, nrhs, W, N, st));
+            ST_TRY(apply_inverse(f, Vj, N, nrhs, Z, N, trans, st));
+            ST_TRY(matvec_impl(f, op, Z, N, nrhs, W, N, st));
             // classical Gram-Schmidt, twice
             ST_TRY(mdot(f, V, W, j + 1, nrhs, st, h1));
             ST_TRY(put_small(f, h1, st));
@@ -1703,7 +1825,7 @@ static askit_status gmres_refine(askit_factor f, const double *B, int64_t ldb, i
         ST_TRY(put_small(f, y, st));
         hipLaunchKernelGGL(k_lincomb, dim3(grid1(NR)), dim3(256), 0, st, R, V, f->ksmall.as<double>(), used, N, nrhs);
         HIP_TRY(hipGetLastError());
-        ST_TRY(apply_inverse(f, R, N, nrhs, Z, N, false, st));
+        ST_TRY(apply_inverse(f, R, N, nrhs, Z, N, trans, st));
         hipLaunchKernelGGL(k_update, dim3(grid1(NR)), dim3(256), 0, st, X, ldx, Z, N, N, nrhs);
         HIP_TRY(hipGetLastError());
     }
@@ -1728,7 +1850,7 @@ askit_status askit_solve(askit_factor f, const double *B, int64_t ldb, int32_t n
         f->t_solve = ms_since(t0);
         return ASKIT_OK;
     }
-    ST_TRY(gmres_refine(f, B, ldb, nrhs, X, ldx, st));
+    ST_TRY(gmres_refine(f, B, ldb, nrhs, X, ldx, false, st));
     f->t_solve = ms_since(t0);
     return ASKIT_OK;
 }
@@ -1736,13 +1858,15 @@ askit_status askit_solve(askit_factor f, const double *B, int64_t ldb, int32_t n
 askit_status askit_solve_transpose(askit_factor f, const double *B, int64_t ldb, int32_t nrhs, double *X,
                                    int64_t ldx, void *stream) {
     ST_TRY(check_solve_args(f, B, ldb, nrhs, X, ldx));
-    return apply_inverse(f, B, ldb, nrhs, X, ldx, true, (hipStream_t)stream);
+    f->info = askit_solve_info{};
+    if (f->max_refine == 0) return apply_inverse(f, B, ldb, nrhs, X, ldx, true, (hipStream_t)stream);
+    return gmres_refine(f, B, ldb, nrhs, X, ldx, true, (hipStream_t)stream);
 }
 
 askit_status askit_matvec(askit_factor f, int32_t which, const double *Xin, int64_t ldx, int32_t nrhs, double *Y,
                           int64_t ldy, void *stream) {
     ST_TRY(check_solve_args(f, Xin, ldx, nrhs, Y, ldy));
-    if (which != 0 && which != 1) return fail(ASKIT_ERR_ARG, "which must be 0 or 1");
+    if (which < 0 || which > 2) return fail(ASKIT_ERR_ARG, "which must be 0, 1 or 2");
     return matvec_impl(f, which, Xin, ldx, nrhs, Y, ldy, (hipStream_t)stream);
 }
 

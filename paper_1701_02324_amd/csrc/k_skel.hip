@@ -146,15 +146,15 @@ __global__ __launch_bounds__(kQrThreads) void k_qrcp(const SkelTask *__restrict_
     __shared__ int32_t piv[kQrMaxCols];
     __shared__ double vh[kQrMaxRows];
     __shared__ double red[kQrWaves];
-    __shared__ double redv[kQrThreads / kWave];
-    __shared__ int32_t redi[kQrThreads / kWave];
+    __shared__ int32_t rmap[kQrMaxRows];
+    __shared__ int32_t wcnt[kQrWaves];
     __shared__ int32_t s_rank, s_zero;
 
     const SkelTask t = tasks[blockIdx.x];
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
     const int sl = t.leaf ? 0 : *t.srl;
     const int ncand = t.leaf ? t.n : sl + *t.srr;
-    const int rows = t.nq;
+    int rows = t.nq;
     double *M = t.M;
     // padded row of candidate c in P_{C alpha~}: internal nodes keep the two
     // children's skeletons in the halves [0, s) and [s, 2s)
@@ -173,6 +173,58 @@ __global__ __launch_bounds__(kQrThreads) void k_qrcp(const SkelTask *__restrict_
             *t.trunc = 0;
         }
         return;
+    }
+    // Rows of the sampled block whose squared norm is below 1e-60 of the
+    // block's squared Frobenius norm are dropped (the rest keep their order).
+    // Their total weight, under 1e-57 of the block's, is far below FP64
+    // rounding of every column norm and of the rank guard's threshold, so the
+    // pivots, R and T are those of the whole block up to rounding; the trailing
+    // updates then stream only the rows that carry the interaction.
+    {
+        for (int i = tid; i < rows; i += kQrThreads) {
+            double a = 0.0;
+            for (int c = 0; c < ncand; c++) {
+                const double v = M[(int64_t)c * ldm + i];
+                a = fma(v, v, a);
+            }
+            vh[i] = a;
+        }
+        __syncthreads();
+        double part = 0.0;
+        for (int i = tid; i < rows; i += kQrThreads) part += vh[i];
+        const double thr = 1e-60 * block_sum(part, red);
+        int kept = 0;
+        for (int base = 0; base < rows; base += kQrThreads) {
+            const int i = base + tid;
+            const bool keep = i < rows && vh[i] > thr;
+            const unsigned long long bal = __ballot(keep);
+            const int below = __popcll(bal & ((1ull << lane) - 1ull));
+            if (lane == 0) wcnt[wave] = __popcll(bal);
+            __syncthreads();
+            int wofs = 0, tot = 0;
+            for (int w = 0; w < kQrWaves; w++) {
+                if (w < wave) wofs += wcnt[w];
+                tot += wcnt[w];
+            }
+            if (i < rows) rmap[i] = keep ? kept + wofs + below : -1;
+            kept += tot;
+            __syncthreads();
+        }
+        if (kept < rows) {
+            // compaction in place, one wave per column: every row moves up or
+            // stays, and a wave reads a 64-row chunk before writing it
+            for (int c = wave; c < ncand; c += kQrWaves) {
+                double *col = M + (int64_t)c * ldm;
+                for (int base = 0; base < rows; base += kWave) {
+                    const int i = base + lane;
+                    const double v = i < rows ? col[i] : 0.0;
+                    const int dst = i < rows ? rmap[i] : -1;
+                    if (dst >= 0) col[dst] = v;
+                }
+            }
+            rows = kept > 0 ? kept : 1;
+            __syncthreads();
+        }
     }
     int steps = s < rows ? s : rows;
     for (int c = tid; c < ncand; c += kQrThreads) piv[c] = c;

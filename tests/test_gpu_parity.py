@@ -132,6 +132,46 @@ def test_matvec_on_oracle_skeletons(setup, imported, which):
     assert colrel(y, setup["o"].matvec(B, which)) < 1e-12
 
 
+def test_matvec_transpose_on_oracle_skeletons(setup, imported):
+    """(lambda I + Ktilde)^T x (which = 2): against the transposed dense
+    assembly where it is small, and at every size through the adjoint identity
+    X^T (A Y) = (A^T X)^T Y with the oracle's A Y."""
+    o, B = setup["o"], setup["B"]
+    N = len(setup["X"])
+    rng = np.random.default_rng(11)
+    Xr = rng.standard_normal((N, 3))
+    Yr = rng.standard_normal((N, 3))
+    atx = _np(imported.matvec(_cuda(Xr), 2))
+    ay = o.matvec(Yr, 0)
+    lhs, rhs = Xr.T @ ay, atx.T @ Yr
+    scale = np.linalg.norm(Xr) * np.linalg.norm(ay)
+    say(f"  adjoint identity {np.abs(lhs - rhs).max() / scale:.2e}")
+    assert np.abs(lhs - rhs).max() <= 1e-12 * scale
+    if N <= 4096:
+        y = _np(imported.matvec(_cuda(B), 2))
+        assert colrel(y, o.dense(0).T @ B.reshape(N, -1)) < 1e-12
+
+
+def test_solve_transpose_refined(setup, ak):
+    """Transpose solve refined by GMRES on the transposed operator: residual
+    |b - A^T z| / |b| at the refinement target, and the oracle's A^{-T} b."""
+    t, o = _tree(ak, setup), setup["o"]
+    ids, P, sizes = oracle_skeletons(o, t.s, t.cmax)
+    t.import_skeletons(ids, P, sizes)
+    f = t.factorize(setup["lam"], ak.ASKIT_FP64)
+    f.set_refinement(40, 1e-12)
+    B = _cuda(setup["B"])
+    z = f.solve_transpose(B)
+    info = f.info()
+    r = B - f.matvec(z, 2)
+    res = float((r.norm(dim=0) / B.norm(dim=0)).max()) if B.dim() > 1 else float(r.norm() / B.norm())
+    err = colrel(_np(z), o.solve_t(setup["B"]))
+    say(f"  refined transpose solve: residual {res:.2e}, vs oracle {err:.2e}, {info}")
+    assert info["converged"] and res <= 2e-12
+    assert err < setup["tol"]
+    f.close()
+
+
 def test_solve_on_oracle_skeletons(setup, imported):
     B = setup["B"]
     x = _np(imported.solve(_cuda(B)))
