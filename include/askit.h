@@ -55,12 +55,16 @@ typedef struct askit_factor_s *askit_factor;
 /* Method parameters.  leaf_size = m (>= 2), rank = s (>= 1; fixed rank,
  * clamped per node to the number of candidates), n_samples = rows sampled
  * per node for the ID (0 -> 4 s), seed = sampling seed, problem = index
- * folded into the sampling streams, h = kernel bandwidth (> 0). */
+ * folded into the sampling streams, h = kernel bandwidth (> 0).
+ * qr_split_levels chooses the launch shape of the pivoted QR, not its
+ * result: nodes at tree levels 1 .. L are factored by several workgroups
+ * each, one launch per pivot step, the deeper ones by one workgroup each
+ * (0 -> L = 6, -1 -> none).  Both shapes give bit-identical skeletons. */
 typedef struct {
     int32_t leaf_size;
     int32_t rank;
     int32_t n_samples;
-    int32_t reserved;
+    int32_t qr_split_levels;
     uint64_t seed;
     int64_t problem;
     double h;

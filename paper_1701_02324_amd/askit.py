@@ -37,7 +37,7 @@ class AskitError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("leaf_size", ctypes.c_int32), ("rank", ctypes.c_int32), ("n_samples", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64), ("problem", ctypes.c_int64),
+                ("qr_split_levels", ctypes.c_int32), ("seed", ctypes.c_uint64), ("problem", ctypes.c_int64),
                 ("h", ctypes.c_double)]
 
 
@@ -126,10 +126,11 @@ def _colmajor(B):
 # thin wrappers with the C names
 # ---------------------------------------------------------------------------
 
-def askit_build_tree(X, leaf_size, rank, h, n_samples=0, seed=0, problem=0, stream=None):
+def askit_build_tree(X, leaf_size, rank, h, n_samples=0, seed=0, problem=0, stream=None, qr_split_levels=0):
     X = _dev64(X, "X").contiguous()
     N, d = X.shape
-    opt = Options(int(leaf_size), int(rank), int(n_samples), 0, int(seed) & 0xFFFFFFFFFFFFFFFF, int(problem), float(h))
+    opt = Options(int(leaf_size), int(rank), int(n_samples), int(qr_split_levels), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                  int(problem), float(h))
     out = _vp()
     _check(load().askit_build_tree(_vp(X.data_ptr()), N, d, ctypes.byref(opt), _stream(stream), ctypes.byref(out)))
     return out
@@ -272,11 +273,11 @@ def askit_factor_destroy(factor):
 class Tree:
     """Tree + skeletons of one problem (points X on the GPU, FP64)."""
 
-    def __init__(self, X, leaf_size, rank, h, n_samples=0, seed=0, problem=0, stream=None):
+    def __init__(self, X, leaf_size, rank, h, n_samples=0, seed=0, problem=0, stream=None, qr_split_levels=0):
         self.N, self.d = X.shape
         self.m, self.s, self.h = int(leaf_size), int(rank), float(h)
         self.nsamp = int(n_samples) or 4 * self.s
-        self.handle = askit_build_tree(X, leaf_size, rank, h, n_samples, seed, problem, stream)
+        self.handle = askit_build_tree(X, leaf_size, rank, h, n_samples, seed, problem, stream, qr_split_levels)
         self.D = askit_tree_depth(self.handle)
         self.nnodes = (2 << self.D) - 1
         self.mmax = -(-self.N // (1 << self.D))

@@ -447,6 +447,11 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 // ---------------------------------------------------------------------------
 // handles
 // ---------------------------------------------------------------------------
+// Tree levels 1 .. kSplitLevels (at most 64 nodes per tree) run the split
+// QRCP by default (several workgroups per node, one launch per pivot step);
+// deeper levels run one workgroup per node.  Both give identical skeletons.
+static const int kSplitLevels = 6;
+
 struct askit_tree_s {
     int64_t N = 0;
     int d = 0, m = 0, s = 0, nsamp = 0, D = 0, cmax = 0, mmax = 0;
@@ -458,6 +463,7 @@ struct askit_tree_s {
     DBuf X, Xp, perm, dnb, dne;
     DBuf srank, trunc, skel, Pt, samp;
     std::vector<int32_t> hsr;  // host copy of the ranks s_alpha (root: 0)
+    int split_levels = 0;      // tree levels 1 .. split_levels use the split QRCP
     bool skel_ok = false;
     int refs = 0;
     double t_tree = 0, t_skel = 0;
@@ -544,6 +550,7 @@ askit_status askit_build_tree(const double *X, int64_t N, int32_t d, const askit
     if (opt->rank < 1) return fail(ASKIT_ERR_ARG, "rank must be >= 1");
     if (!(opt->h > 0.0) || !std::isfinite(opt->h)) return fail(ASKIT_ERR_ARG, "h must be positive and finite");
     if (opt->n_samples < 0) return fail(ASKIT_ERR_ARG, "n_samples must be >= 0");
+    if (opt->qr_split_levels < -1) return fail(ASKIT_ERR_ARG, "qr_split_levels must be >= -1");
     hipStream_t st = (hipStream_t)stream;
     std::unique_ptr<askit_tree_s> t(new askit_tree_s());
     t->N = N;
@@ -551,6 +558,7 @@ askit_status askit_build_tree(const double *X, int64_t N, int32_t d, const askit
     t->m = opt->leaf_size;
     t->s = opt->rank;
     t->nsamp = opt->n_samples ? opt->n_samples : 4 * opt->rank;
+    t->split_levels = opt->qr_split_levels == 0 ? kSplitLevels : std::max(0, opt->qr_split_levels);
     t->seed = opt->seed;
     t->problem = opt->problem;
     t->h = opt->h;
@@ -689,31 +697,35 @@ static askit_status skeletonize_impl(askit_tree *trees, int count, hipStream_t s
         if (trees[i]->s != s || trees[i]->d != d)
             return fail(ASKIT_ERR_ARG, "batched trees must share rank and dimension");
         if (!trees[i]->samp.p) ST_TRY(trees[i]->samp.alloc(sizeof(int32_t) * trees[i]->nnodes * trees[i]->nsamp));
+        trees[i]->hsr.assign(trees[i]->nnodes, 0);
     }
-    // per height: task lists
-    std::vector<std::vector<SampTask>> samp(Hmax);
-    std::vector<std::vector<SkelTask>> sk(Hmax);
-    int64_t maxnodes = 0;
+    const int64_t slot = (int64_t)nsamp_max * cmax;  // sampled block per node, column-major, ld nsamp_max
+    DBuf M, err, dsamp, dsk, dqr, dsplit;
+    DBuf wpart, wrmap, wrows, wnrm, wpos, wdiag, wst;
+    ST_TRY(err.alloc(sizeof(int32_t)));
+    HIP_TRY(hipMemsetAsync(err.p, 0, sizeof(int32_t), st));
     for (int hgt = 0; hgt < Hmax; hgt++) {
+        // the children's ranks (decided at the previous height) fix the
+        // candidate counts: nodes with |C| <= s keep all candidates (P = I)
+        // and need neither samples nor a QR
+        if (hgt > 0)
+            for (int i = 0; i < count; i++)
+                HIP_TRY(hipMemcpyAsync(trees[i]->hsr.data(), trees[i]->srank.p, sizeof(int32_t) * trees[i]->nnodes,
+                                       hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        std::vector<SampTask> samp_one, samp_split;
+        std::vector<SkelTask> qr_one, qr_split, ident;
+        int split_cols = 0, split_steps = 0;
         for (int i = 0; i < count; i++) {
             askit_tree t = trees[i];
-            int l = t->D - hgt;
+            const int l = t->D - hgt;
             if (l < 1) continue;
             for (int64_t id = t->first(l); id < t->first(l + 1); id++) {
-                SampTask a{};
-                a.b = t->nb[id];
-                a.e = t->ne[id];
-                a.N = t->N;
-                a.state = node_state(t->seed, t->problem, id);
-                a.out = t->samp.as<int32_t>() + id * t->nsamp;
-                samp[hgt].push_back(a);
                 SkelTask k{};
                 k.X = t->Xp.as<double>();
-                k.q = a.out;
-                k.nq = (int32_t)std::min<int64_t>(t->nsamp, t->N - (a.e - a.b));
                 k.leaf = (l == t->D);
-                k.b = a.b;
-                k.n = (int32_t)(a.e - a.b);
+                k.b = t->nb[id];
+                k.n = (int32_t)(t->ne[id] - t->nb[id]);
                 k.cmax = t->cmax;
                 if (!k.leaf) {
                     k.skl = t->skel.as<int32_t>() + (2 * id + 1) * t->s;
@@ -726,46 +738,104 @@ static askit_status skeletonize_impl(askit_tree *trees, int count, hipStream_t s
                 k.trunc = t->trunc.as<int32_t>() + id;
                 k.Pt = t->Pt.as<double>() + id * (int64_t)t->cmax * t->s;
                 k.scale = -1.0 / (2.0 * t->h * t->h);
-                sk[hgt].push_back(k);
+                const int ncand = k.leaf ? k.n : t->hsr[2 * id + 1] + t->hsr[2 * id + 2];
+                if (ncand <= s) {
+                    ident.push_back(k);
+                    continue;
+                }
+                SampTask a{};
+                a.b = t->nb[id];
+                a.e = t->ne[id];
+                a.N = t->N;
+                a.state = node_state(t->seed, t->problem, id);
+                a.out = t->samp.as<int32_t>() + id * t->nsamp;
+                k.q = a.out;
+                k.nq = (int32_t)std::min<int64_t>(t->nsamp, t->N - (a.e - a.b));
+                if (l <= t->split_levels) {
+                    samp_split.push_back(a);
+                    qr_split.push_back(k);
+                    split_cols = std::max(split_cols, ncand);
+                    split_steps = std::max(split_steps, std::min(s, k.nq));
+                } else {
+                    samp_one.push_back(a);
+                    qr_one.push_back(k);
+                }
             }
         }
-        maxnodes = std::max<int64_t>(maxnodes, (int64_t)sk[hgt].size());
-    }
-    DBuf M, err, dsamp, dsk;
-    ST_TRY(M.alloc(sizeof(double) * std::max<int64_t>(1, maxnodes) * nsamp_max * cmax));
-    ST_TRY(err.alloc(sizeof(int32_t)));
-    HIP_TRY(hipMemsetAsync(err.p, 0, sizeof(int32_t), st));
-    for (int hgt = 0; hgt < Hmax; hgt++) {
-        if (sk[hgt].empty()) continue;
-        for (size_t j = 0; j < sk[hgt].size(); j++) sk[hgt][j].M = M.as<double>() + (int64_t)j * nsamp_max * cmax;
-        HIP_TRY(hipStreamSynchronize(st));
-        ST_TRY(upload(dsamp, samp[hgt]));
-        ST_TRY(upload(dsk, sk[hgt]));
-        const int n = (int)sk[hgt].size();
-        // all trees of a batch share nsamp (checked by the batched entry point)
-        HIP_TRY(timed("skel:k_sample", st, [&] {
-            hipLaunchKernelGGL(k_sample, dim3(n), dim3(64), 0, st, dsamp.as<SampTask>(), nsamp_max, err.as<int32_t>());
-            return hipGetLastError();
-        }));
-        const int rt = (int)cdiv(nsamp_max, 64), ct = (int)cdiv(cmax, 64);
-        HIP_TRY(timed("skel:k_sample_block", st, [&] {
-            hipLaunchKernelGGL(k_sample_block, dim3(n * rt * ct), dim3(256), sizeof(double) * 128 * d, st,
-                               dsk.as<SkelTask>(), rt, nsamp_max, d, ct);
-            return hipGetLastError();
-        }));
-        HIP_TRY(timed("skel:k_qrcp", st, [&] {
-            hipLaunchKernelGGL(k_qrcp, dim3(n), dim3(512), 0, st, dsk.as<SkelTask>(), s, nsamp_max);
-            return hipGetLastError();
-        }));
+        // sampled nodes: one-workgroup ones first, then the split ones
+        std::vector<SampTask> samp(samp_one);
+        samp.insert(samp.end(), samp_split.begin(), samp_split.end());
+        std::vector<SkelTask> qr(qr_one);
+        qr.insert(qr.end(), qr_split.begin(), qr_split.end());
+        const int nqr = (int)qr.size(), none_ = (int)qr_one.size(), nsp = (int)qr_split.size();
+        if ((int64_t)M.bytes < (int64_t)sizeof(double) * nqr * slot) ST_TRY(M.alloc(sizeof(double) * nqr * slot));
+        for (int j = 0; j < nqr; j++) qr[j].M = M.as<double>() + (int64_t)j * slot;
+        for (int j = 0; j < nsp; j++) qr_split[j].M = qr[none_ + j].M;
+        std::vector<SkelTask> one(qr.begin(), qr.begin() + none_);
+        one.insert(one.end(), ident.begin(), ident.end());
+        if (nqr > 0) {
+            ST_TRY(upload(dsamp, samp));
+            ST_TRY(upload(dsk, qr));
+            // all trees of a batch share nsamp (checked by the batched entry point)
+            HIP_TRY(timed("skel:k_sample", st, [&] {
+                hipLaunchKernelGGL(k_sample, dim3(nqr), dim3(64), 0, st, dsamp.as<SampTask>(), nsamp_max,
+                                   err.as<int32_t>());
+                return hipGetLastError();
+            }));
+            const int rt = (int)cdiv(nsamp_max, 64), ct = (int)cdiv(cmax, 64);
+            HIP_TRY(timed("skel:k_sample_block", st, [&] {
+                hipLaunchKernelGGL(k_sample_block, dim3(nqr * rt * ct), dim3(256), sizeof(double) * 128 * d, st,
+                                   dsk.as<SkelTask>(), rt, nsamp_max, d, ct);
+                return hipGetLastError();
+            }));
+        }
+        if (!one.empty()) {
+            ST_TRY(upload(dqr, one));
+            const int n1 = (int)one.size();
+            HIP_TRY(timed("skel:k_qrcp", st, [&] {
+                hipLaunchKernelGGL(k_qrcp, dim3(n1), dim3(512), 0, st, dqr.as<SkelTask>(), s, nsamp_max);
+                return hipGetLastError();
+            }));
+        }
+        if (nsp > 0) {
+            QrWork w{};
+            w.cmax = cmax;
+            w.rcap = nsamp_max;
+            w.slices = (int)cdiv(split_cols, kQsCols);
+            ST_TRY(upload(dsplit, qr_split));
+            ST_TRY(wpart.alloc(sizeof(double) * (size_t)nsp * w.slices * w.rcap));
+            ST_TRY(wrmap.alloc(sizeof(int32_t) * (size_t)nsp * w.rcap));
+            ST_TRY(wrows.alloc(sizeof(int32_t) * (size_t)nsp));
+            ST_TRY(wnrm.alloc(sizeof(double) * (size_t)nsp * 2 * cmax));
+            ST_TRY(wpos.alloc(sizeof(int32_t) * (size_t)nsp * 2 * cmax));
+            ST_TRY(wdiag.alloc(sizeof(double) * (size_t)nsp * cmax));
+            ST_TRY(wst.alloc(sizeof(int32_t) * (size_t)nsp * 4));
+            w.part = wpart.as<double>();
+            w.rmap = wrmap.as<int32_t>();
+            w.rows = wrows.as<int32_t>();
+            w.nrm = wnrm.as<double>();
+            w.pos = wpos.as<int32_t>();
+            w.diag = wdiag.as<double>();
+            w.st = wst.as<int32_t>();
+            const SkelTask *tp = dsplit.as<SkelTask>();
+            const unsigned g = (unsigned)(nsp * w.slices);
+            HIP_TRY(timed("skel:k_qrcp_split", st, [&] {
+                hipLaunchKernelGGL(k_qs_rows, dim3(g), dim3(256), 0, st, tp, w, nsamp_max);
+                hipLaunchKernelGGL(k_qs_rowmap, dim3(nsp), dim3(512), 0, st, tp, w);
+                hipLaunchKernelGGL(k_qs_init, dim3(g), dim3(256), 0, st, tp, w, s, nsamp_max);
+                for (int j = 0; j < split_steps; j++)
+                    hipLaunchKernelGGL(k_qs_step, dim3(g), dim3(256), 0, st, tp, w, j, nsamp_max);
+                hipLaunchKernelGGL(k_qs_finish, dim3(nsp), dim3(512), 0, st, tp, w, s, nsamp_max);
+                return hipGetLastError();
+            }));
+        }
     }
     int32_t herr = 0;
     HIP_TRY(hipMemcpyAsync(&herr, err.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     // the ranks decide the shapes of every later launch: keep them on the host
-    for (int i = 0; i < count; i++) {
-        trees[i]->hsr.assign(trees[i]->nnodes, 0);
+    for (int i = 0; i < count; i++)
         HIP_TRY(hipMemcpyAsync(trees[i]->hsr.data(), trees[i]->srank.p, sizeof(int32_t) * trees[i]->nnodes,
                                hipMemcpyDeviceToHost, st));
-    }
     HIP_TRY(hipStreamSynchronize(st));
     if (herr) return fail(ASKIT_ERR_HIP, "row sampling did not terminate");
     for (int i = 0; i < count; i++) {

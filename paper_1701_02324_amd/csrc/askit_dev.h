@@ -12,6 +12,7 @@ constexpr int kMaxDim = 64;      // largest point dimension d accepted
 constexpr int kTreeChunk = 256;  // positions per chunk of the tree reductions
 constexpr int kPowerIters = 50;  // power iterations for the principal axis
 constexpr double kRankGuard = 1e-14;
+constexpr int kQsCols = 8;       // columns per workgroup of the split QRCP
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
@@ -142,6 +143,19 @@ struct SkelTask {
     int32_t *trunc;        // out: rank-guard flag
     double *Pt;            // out: cmax x s row-major P_{C alpha~} (rows padded)
     double scale;          // -1 / (2 h^2)
+};
+
+// Work arrays of the split QRCP (several workgroups per node, one launch per
+// pivot step); node i of a launch owns the i-th slot of every array.
+struct QrWork {
+    double *part;      // slices x rcap partial squared row norms per node
+    int32_t *rmap;     // rcap: new row index or -1
+    int32_t *rows;     // 1: kept rows, then rows in use
+    double *nrm;       // 2 x cmax squared trailing norms (buffers by step parity)
+    int32_t *pos;      // 2 x cmax pivot order (buffers by step parity)
+    double *diag;      // cmax: R_jj
+    int32_t *st;       // 4: stopped, stop step, zero block, steps
+    int32_t cmax, rcap, slices, pad;
 };
 
 // Output operations of the product kernels.

@@ -115,17 +115,24 @@ __global__ __launch_bounds__(256) void k_sample_block(const SkelTask *__restrict
 }
 
 // ---------------------------------------------------------------------------
-// QRCP + interpolative decomposition, one workgroup per node
+// QRCP + interpolative decomposition.  Two launch shapes share every piece of
+// arithmetic below, so they give bit-identical skeletons:
+//  * k_qrcp: one 512-thread workgroup per node (levels with many nodes);
+//  * k_qs_*: several workgroups per node, one launch per pivot step (levels
+//    with few nodes, where one workgroup per node would leave the GPU idle).
 // ---------------------------------------------------------------------------
 constexpr int kQrThreads = 512;
 constexpr int kQrWaves = kQrThreads / kWave;
+constexpr int kQsThreads = 256;
+constexpr int kQsWaves = kQsThreads / kWave;
+static_assert(kQsCols == 2 * kQsWaves, "two columns per wave in the split form");
 
 __device__ inline double wave_sum(double v) {
     for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
 
-// block-wide sum (all threads get the result); red: kQrWaves doubles of LDS
+// block-wide sum over kQrThreads threads (all get the result); red: kQrWaves
 __device__ double block_sum(double v, double *red) {
     v = wave_sum(v);
     const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
@@ -140,28 +147,228 @@ __device__ double block_sum(double v, double *red) {
 // LDS budget: norms and pivots per candidate column, Householder vector
 constexpr int kQrMaxCols = 2048;
 constexpr int kQrMaxRows = 4096;
+constexpr int kQrMaxRank = 256;
 
+__device__ inline int node_ncand(const SkelTask &t) { return t.leaf ? t.n : *t.srl + *t.srr; }
+
+// squared norm of row i over the columns [c0, c1) of the block
+__device__ inline double row_part(const double *M, int ldm, int i, int c0, int c1) {
+    double p = 0.0;
+    for (int c = c0; c < c1; c++) {
+        const double v = M[(int64_t)c * ldm + i];
+        p = fma(v, v, p);
+    }
+    return p;
+}
+
+// Rows of the sampled block whose squared norm is below 1e-60 of the block's
+// squared Frobenius norm are dropped (the rest keep their order).  Their total
+// weight, under 1e-57 of the block's, is far below FP64 rounding of every
+// column norm and of the rank guard's threshold, so the pivots, R and T are
+// those of the whole block up to rounding; the trailing updates then stream
+// only the rows that carry the interaction.  rn: squared row norms (summed
+// over groups of kQsCols columns in order); all kQrThreads threads call this;
+// returns the number of kept rows and fills rmap (new index or -1).
+template <typename IT>
+__device__ int row_map(const double *rn, int rows, IT *rmap, int32_t *wcnt, double *red) {
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    double part = 0.0;
+    for (int i = tid; i < rows; i += kQrThreads) part += rn[i];
+    const double thr = 1e-60 * block_sum(part, red);
+    int kept = 0;
+    for (int base = 0; base < rows; base += kQrThreads) {
+        const int i = base + tid;
+        const bool keep = i < rows && rn[i] > thr;
+        const unsigned long long bal = __ballot(keep);
+        const int below = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) wcnt[wave] = __popcll(bal);
+        __syncthreads();
+        int wofs = 0, tot = 0;
+        for (int w = 0; w < kQrWaves; w++) {
+            if (w < wave) wofs += wcnt[w];
+            tot += wcnt[w];
+        }
+        if (i < rows) rmap[i] = (IT)(keep ? kept + wofs + below : -1);
+        kept += tot;
+        __syncthreads();
+    }
+    return kept;
+}
+
+// in-place compaction of one column by one wave: rows only move up, and a
+// wave reads a 64-row chunk before writing it
+template <typename IT>
+__device__ inline void compact_col(double *col, const IT *rmap, int rows, int lane) {
+    for (int base = 0; base < rows; base += kWave) {
+        const int i = base + lane;
+        const double v = i < rows ? col[i] : 0.0;
+        const int dst = i < rows ? (int)rmap[i] : -1;
+        if (dst >= 0) col[dst] = v;
+    }
+}
+
+// squared norm of rows [0, rows) of a column (one wave)
+__device__ inline double col_norm(const double *col, int rows, int lane) {
+    double acc = 0.0;
+    for (int i = lane; i < rows; i += kWave) acc = fma(col[i], col[i], acc);
+    return wave_sum(acc);
+}
+
+// Householder reflector of pivot step j from the pivot column x (one wave):
+// LAPACK convention beta = -sign(alpha) |x|, tau = (beta - alpha) / beta,
+// v = x / (alpha - beta) below the diagonal.  Lane l sums the rows i > j with
+// i = l mod 64 in increasing order.
+struct Refl {
+    double alpha, beta, tau, sc;
+};
+__device__ inline Refl reflector(const double *x, int j, int rows, int lane) {
+    double xn = 0.0;
+    for (int i = lane; i < rows; i += kWave)
+        if (i > j) xn = fma(x[i], x[i], xn);
+    xn = wave_sum(xn);
+    Refl r;
+    r.alpha = x[j];
+    if (xn == 0.0) {
+        r.beta = r.alpha;
+        r.tau = 0.0;
+        r.sc = 0.0;
+    } else {
+        r.beta = -copysign(sqrt(r.alpha * r.alpha + xn), r.alpha);
+        r.tau = (r.beta - r.alpha) / r.beta;
+        r.sc = 1.0 / (r.alpha - r.beta);
+    }
+    return r;
+}
+
+__device__ inline bool guard_stop(int j, double beta, double r00) {
+    const double r0 = j == 0 ? fabs(beta) : r00;
+    return (j > 0 && fabs(beta) <= kRankGuard * r0) || (j == 0 && r0 == 0.0);
+}
+
+// apply H = I - tau v v^T (v in LDS, v_j = 1) to rows [j, rows) of one column
+// (one wave) and return the new squared norm of its rows below j
+__device__ inline double apply_col(double *col, const double *vh, int j, int rows, double tau, int lane) {
+    if (rows - j <= 16 * kWave) {
+        double a[16], vr[16];
+#pragma unroll
+        for (int t = 0; t < 16; t++) {
+            const int i = j + lane + t * kWave;
+            vr[t] = i < rows ? vh[i] : 0.0;
+            a[t] = i < rows ? col[i] : 0.0;
+        }
+        double w = 0.0;
+#pragma unroll
+        for (int t = 0; t < 16; t++) w = fma(vr[t], a[t], w);
+        w = wave_sum(w) * tau;
+        double n = 0.0;
+#pragma unroll
+        for (int t = 0; t < 16; t++) {
+            const int i = j + lane + t * kWave;
+            a[t] = fma(-vr[t], w, a[t]);
+            if (i > j && i < rows) n = fma(a[t], a[t], n);
+        }
+#pragma unroll
+        for (int t = 0; t < 16; t++) {
+            const int i = j + lane + t * kWave;
+            if (i < rows) col[i] = a[t];
+        }
+        return wave_sum(n);
+    }
+    double w = 0.0;
+    for (int i = j + lane; i < rows; i += kWave) w = fma(vh[i], col[i], w);
+    w = wave_sum(w) * tau;
+    double n = 0.0;
+    for (int i = j + lane; i < rows; i += kWave) {
+        const double v = fma(-vh[i], w, col[i]);
+        col[i] = v;
+        if (i > j) n = fma(v, v, n);
+    }
+    return wave_sum(n);
+}
+
+// T = R11^{-1} R12 in place of R12 and the outputs (skeleton positions, rank,
+// rows of P_{C alpha~}); pos[q] = column at pivot position q, Rjj = diagonal
+// of R.  All kQrThreads threads.
+__device__ void id_finish(const SkelTask &t, double *M, int ldm, int s, int sl, int ncand, int rank, bool zero,
+                          const int32_t *pos, const double *Rjj) {
+    const int tid = threadIdx.x;
+    auto prow = [&](int c) { return t.leaf ? c : (c < sl ? c : s + (c - sl)); };
+    for (int q = rank + tid; q < ncand; q += kQrThreads) {
+        double *tc = M + (int64_t)pos[q] * ldm;
+        for (int i = rank - 1; i >= 0; i--) {
+            if (zero) {
+                tc[i] = 0.0;
+                continue;
+            }
+            double acc = tc[i];
+            for (int k = i + 1; k < rank; k++) acc = fma(-M[(int64_t)pos[k] * ldm + i], tc[k], acc);
+            tc[i] = acc / Rjj[i];
+        }
+    }
+    __syncthreads();
+    for (int k = tid; k < s; k += kQrThreads) t.skel[k] = k < rank ? cand_pos(t, pos[k], sl) : -1;
+    if (tid == 0) {
+        *t.sr = rank;
+        *t.trunc = (rank < (s < ncand ? s : ncand)) ? 1 : 0;
+    }
+    // P is written in the rows of the candidates and the columns below the
+    // rank only: nothing reads the rest of the padded slot
+    for (int q = tid; q < ncand; q += kQrThreads) {
+        double *row = t.Pt + (int64_t)prow(pos[q]) * s;
+        if (q < rank) {
+            for (int k = 0; k < rank; k++) row[k] = k == q ? 1.0 : 0.0;
+        } else {
+            const double *tc = M + (int64_t)pos[q] * ldm;
+            for (int k = 0; k < rank; k++) row[k] = tc[k];
+        }
+    }
+}
+
+// pivot choice: largest norm over positions [j, ncand) (value nrm[pos[k]]),
+// lowest position on ties; one wave, result in every lane
+__device__ inline int pick_pivot(const double *nrm, const int32_t *pos, int j, int ncand, int lane) {
+    double bv = -1.0;
+    int bk = 0x7fffffff;
+    for (int k = j + lane; k < ncand; k += kWave) {
+        const double v = nrm[pos[k]];
+        if (v > bv || (v == bv && k < bk)) {
+            bv = v;
+            bk = k;
+        }
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(bv, o);
+        const int ok = __shfl_xor(bk, o);
+        if (ov > bv || (ov == bv && ok < bk)) {
+            bv = ov;
+            bk = ok;
+        }
+    }
+    return bk;
+}
+
+// ---------------------------------------------------------------------------
+// one workgroup per node: block, norms and reflector traffic through L2/HBM,
+// the pivot bookkeeping in LDS
+// ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kQrThreads) void k_qrcp(const SkelTask *__restrict__ tasks, int s, int ldm) {
     __shared__ double nrm[kQrMaxCols];
-    __shared__ int32_t piv[kQrMaxCols];
+    __shared__ int32_t pos[kQrMaxCols];
+    __shared__ double Rjj[kQrMaxRank];
     __shared__ double vh[kQrMaxRows];
+    __shared__ int16_t rmap[kQrMaxRows];
     __shared__ double red[kQrWaves];
-    __shared__ int32_t rmap[kQrMaxRows];
     __shared__ int32_t wcnt[kQrWaves];
-    __shared__ int32_t s_rank, s_zero;
+    __shared__ int32_t s_stop, s_rank, s_zero;
+    __shared__ double s_tau;
 
     const SkelTask t = tasks[blockIdx.x];
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
     const int sl = t.leaf ? 0 : *t.srl;
-    const int ncand = t.leaf ? t.n : sl + *t.srr;
-    int rows = t.nq;
+    const int ncand = node_ncand(t);
     double *M = t.M;
-    // padded row of candidate c in P_{C alpha~}: internal nodes keep the two
-    // children's skeletons in the halves [0, s) and [s, 2s)
     auto prow = [&](int c) { return t.leaf ? c : (c < sl ? c : s + (c - sl)); };
 
-    // P is written in the rows of the candidates and the columns below the
-    // rank only: nothing reads the rest of the padded slot
     if (ncand <= s) {  // no compression: skeleton = candidates, P = I
         for (int k = tid; k < s; k += kQrThreads) t.skel[k] = k < ncand ? cand_pos(t, k, sl) : -1;
         for (int64_t i = tid; i < (int64_t)ncand * ncand; i += kQrThreads) {
@@ -174,268 +381,215 @@ __global__ __launch_bounds__(kQrThreads) void k_qrcp(const SkelTask *__restrict_
         }
         return;
     }
-    // Rows of the sampled block whose squared norm is below 1e-60 of the
-    // block's squared Frobenius norm are dropped (the rest keep their order).
-    // Their total weight, under 1e-57 of the block's, is far below FP64
-    // rounding of every column norm and of the rank guard's threshold, so the
-    // pivots, R and T are those of the whole block up to rounding; the trailing
-    // updates then stream only the rows that carry the interaction.
-    {
-        for (int i = tid; i < rows; i += kQrThreads) {
-            double a = 0.0;
-            for (int c = 0; c < ncand; c++) {
-                const double v = M[(int64_t)c * ldm + i];
-                a = fma(v, v, a);
-            }
-            vh[i] = a;
-        }
-        __syncthreads();
-        double part = 0.0;
-        for (int i = tid; i < rows; i += kQrThreads) part += vh[i];
-        const double thr = 1e-60 * block_sum(part, red);
-        int kept = 0;
-        for (int base = 0; base < rows; base += kQrThreads) {
-            const int i = base + tid;
-            const bool keep = i < rows && vh[i] > thr;
-            const unsigned long long bal = __ballot(keep);
-            const int below = __popcll(bal & ((1ull << lane) - 1ull));
-            if (lane == 0) wcnt[wave] = __popcll(bal);
-            __syncthreads();
-            int wofs = 0, tot = 0;
-            for (int w = 0; w < kQrWaves; w++) {
-                if (w < wave) wofs += wcnt[w];
-                tot += wcnt[w];
-            }
-            if (i < rows) rmap[i] = keep ? kept + wofs + below : -1;
-            kept += tot;
-            __syncthreads();
-        }
-        if (kept < rows) {
-            // compaction in place, one wave per column: every row moves up or
-            // stays, and a wave reads a 64-row chunk before writing it
-            for (int c = wave; c < ncand; c += kQrWaves) {
-                double *col = M + (int64_t)c * ldm;
-                for (int base = 0; base < rows; base += kWave) {
-                    const int i = base + lane;
-                    const double v = i < rows ? col[i] : 0.0;
-                    const int dst = i < rows ? rmap[i] : -1;
-                    if (dst >= 0) col[dst] = v;
-                }
-            }
-            rows = kept > 0 ? kept : 1;
-            __syncthreads();
-        }
+    int rows = t.nq;
+    // drop the numerically zero rows
+    for (int i = tid; i < rows; i += kQrThreads) {
+        double a = 0.0;
+        for (int g = 0; g < ncand; g += kQsCols) a += row_part(M, ldm, i, g, min(ncand, g + kQsCols));
+        vh[i] = a;
     }
-    int steps = s < rows ? s : rows;
-    for (int c = tid; c < ncand; c += kQrThreads) piv[c] = c;
-    // initial squared column norms (one wave per column)
+    __syncthreads();
+    const int kept = row_map(vh, rows, rmap, wcnt, red);
+    if (kept < rows) {
+        for (int c = wave; c < ncand; c += kQrWaves) compact_col(M + (int64_t)c * ldm, rmap, rows, lane);
+        rows = kept > 0 ? kept : 1;
+        __syncthreads();
+    }
+    const int steps = s < rows ? s : rows;
+    for (int c = tid; c < ncand; c += kQrThreads) pos[c] = c;
     for (int c = wave; c < ncand; c += kQrWaves) {
-        double acc = 0.0;
-        for (int i = lane; i < rows; i += kWave) {
-            double v = M[(int64_t)c * ldm + i];
-            acc = fma(v, v, acc);
-        }
-        acc = wave_sum(acc);
-        if (lane == 0) nrm[c] = acc;
+        const double v = col_norm(M + (int64_t)c * ldm, rows, lane);
+        if (lane == 0) nrm[c] = v;
     }
     if (tid == 0) {
         s_rank = steps;
         s_zero = 0;
+        s_stop = 0;
     }
     __syncthreads();
-    // Pivot steps.  Every wave finds the pivot itself from the norms in LDS
-    // (no barrier); wave 0 swaps the columns in memory, builds the reflector
-    // and publishes it in LDS; one barrier; all waves apply it to the
-    // trailing columns (two at a time, held in registers when the sampled
-    // block has at most 1024 rows) and recompute their norms; one barrier.
-    __shared__ double s_tau;
-    __shared__ int32_t s_stop;
-    if (tid == 0) s_stop = 0;
-    __syncthreads();
+    // Pivot steps (columns stay in place; pos is the pivot order): wave 0
+    // picks the pivot, builds the reflector in LDS and swaps the positions;
+    // one barrier; all waves update the trailing columns and their norms;
+    // one barrier.
     double r00 = 0.0;
     for (int j = 0; j < steps; j++) {
-        double bv = -1.0;
-        int bi = 0x7fffffff;
-        for (int c = j + lane; c < ncand; c += kWave) {
-            const double v = nrm[c];
-            if (v > bv || (v == bv && c < bi)) {
-                bv = v;
-                bi = c;
-            }
-        }
-        for (int o = kWave / 2; o > 0; o >>= 1) {
-            const double ov = __shfl_xor(bv, o);
-            const int oi = __shfl_xor(bi, o);
-            if (ov > bv || (ov == bv && oi < bi)) {
-                bv = ov;
-                bi = oi;
-            }
-        }
-        const int p = bi;
         if (wave == 0) {
-            double *col = M + (int64_t)j * ldm;
-            double xn = 0.0, aj = 0.0;  // aj: entry (j, j) after the swap, held by lane j % 64
-            if (p != j) {
-                double *cp = M + (int64_t)p * ldm;
-                for (int i = lane; i < rows; i += kWave) {
-                    const double a = col[i], b = cp[i];
-                    col[i] = b;
-                    cp[i] = a;
-                    if (i > j) xn = fma(b, b, xn);
-                    if (i == j) aj = b;
-                }
-                if (lane == 0) {
-                    const int ti = piv[j];
-                    piv[j] = piv[p];
-                    piv[p] = ti;
-                }
-            } else {
-                for (int i = j + 1 + lane; i < rows; i += kWave) xn = fma(col[i], col[i], xn);
-                if (lane == j % kWave) aj = col[j];
-            }
-            xn = wave_sum(xn);
-            const double alpha = __shfl(aj, j % kWave);
-            double beta, tau, sc;
-            if (xn == 0.0) {
-                beta = alpha; tau = 0.0; sc = 0.0;
-            } else {
-                beta = -copysign(sqrt(alpha * alpha + xn), alpha);
-                tau = (beta - alpha) / beta;
-                sc = 1.0 / (alpha - beta);
-            }
-            const double r0 = j == 0 ? fabs(beta) : r00;
-            const bool stop = (j > 0 && fabs(beta) <= kRankGuard * r0) || (j == 0 && r0 == 0.0);
-            if (stop) {
+            const int k = pick_pivot(nrm, pos, j, ncand, lane);
+            const int p = pos[k];
+            const double *x = M + (int64_t)p * ldm;
+            const Refl r = reflector(x, j, rows, lane);
+            if (guard_stop(j, r.beta, r00)) {
                 if (lane == 0) {
                     s_rank = j == 0 ? 1 : j;
                     s_zero = (j == 0);
                     s_stop = 1;
                 }
             } else {
-                for (int i = j + 1 + lane; i < rows; i += kWave) {
-                    const double v = col[i] * sc;
-                    vh[i] = v;
-                    col[i] = v;
-                }
+                for (int i = j + 1 + lane; i < rows; i += kWave) vh[i] = x[i] * r.sc;
                 if (lane == 0) {
                     vh[j] = 1.0;
-                    col[j] = beta;
-                    s_tau = tau;
+                    s_tau = r.tau;
+                    Rjj[j] = r.beta;
+                    pos[k] = pos[j];
+                    pos[j] = p;
                 }
             }
         }
         __syncthreads();
         if (s_stop) break;
-        if (j == 0) r00 = fabs(M[0]);
+        if (j == 0) r00 = fabs(Rjj[0]);
         const double tau = s_tau;
-        // apply H to the columns right of j; new squared norms over rows j+1..
-        if (rows - j <= 16 * kWave) {
-            double vr[16];
-#pragma unroll
-            for (int t = 0; t < 16; t++) {
-                const int i = j + lane + t * kWave;
-                vr[t] = i < rows ? vh[i] : 0.0;
-            }
-            for (int c = j + 1 + 2 * wave; c < ncand; c += 2 * kQrWaves) {
-                const bool two = c + 1 < ncand;
-                double *c0 = M + (int64_t)c * ldm, *c1 = M + (int64_t)(two ? c + 1 : c) * ldm;
-                double a0[16], a1[16];
-                double w0 = 0.0, w1 = 0.0;
-#pragma unroll
-                for (int t = 0; t < 16; t++) {
-                    const int i = j + lane + t * kWave;
-                    a0[t] = i < rows ? c0[i] : 0.0;
-                    a1[t] = i < rows ? c1[i] : 0.0;
-                }
-#pragma unroll
-                for (int t = 0; t < 16; t++) {
-                    w0 = fma(vr[t], a0[t], w0);
-                    w1 = fma(vr[t], a1[t], w1);
-                }
-                for (int o = kWave / 2; o > 0; o >>= 1) {
-                    w0 += __shfl_xor(w0, o);
-                    w1 += __shfl_xor(w1, o);
-                }
-                w0 *= tau;
-                w1 *= tau;
-                double n0 = 0.0, n1 = 0.0;
-#pragma unroll
-                for (int t = 0; t < 16; t++) {
-                    const int i = j + lane + t * kWave;
-                    a0[t] = fma(-vr[t], w0, a0[t]);
-                    a1[t] = fma(-vr[t], w1, a1[t]);
-                    if (i > j && i < rows) {
-                        n0 = fma(a0[t], a0[t], n0);
-                        n1 = fma(a1[t], a1[t], n1);
-                    }
-                }
-#pragma unroll
-                for (int t = 0; t < 16; t++) {
-                    const int i = j + lane + t * kWave;
-                    if (i < rows) {
-                        c0[i] = a0[t];
-                        if (two) c1[i] = a1[t];
-                    }
-                }
-                for (int o = kWave / 2; o > 0; o >>= 1) {
-                    n0 += __shfl_xor(n0, o);
-                    n1 += __shfl_xor(n1, o);
-                }
-                if (lane == 0) {
-                    nrm[c] = n0;
-                    if (two) nrm[c + 1] = n1;
-                }
-            }
-        } else {
-            for (int c = j + 1 + wave; c < ncand; c += kQrWaves) {
-                double *ck = M + (int64_t)c * ldm;
-                double w = 0.0;
-                for (int i = j + lane; i < rows; i += kWave) w = fma(vh[i], ck[i], w);
-                w = wave_sum(w) * tau;
-                double acc = 0.0;
-                for (int i = j + lane; i < rows; i += kWave) {
-                    const double v = fma(-vh[i], w, ck[i]);
-                    ck[i] = v;
-                    if (i > j) acc = fma(v, v, acc);
-                }
-                acc = wave_sum(acc);
-                if (lane == 0) nrm[c] = acc;
-            }
+        for (int q = j + 1 + wave; q < ncand; q += kQrWaves) {
+            const int c = pos[q];
+            const double v = apply_col(M + (int64_t)c * ldm, vh, j, rows, tau, lane);
+            if (lane == 0) nrm[c] = v;
         }
         __syncthreads();
     }
-    const int rank = s_rank;
-    const bool zero = s_zero != 0;
-    // T = R11^{-1} R12 in place of R12 (one thread per column)
-    const int nr = ncand - rank;
-    for (int c = tid; c < nr; c += kQrThreads) {
-        double *tc = M + (int64_t)(rank + c) * ldm;
-        for (int i = rank - 1; i >= 0; i--) {
-            if (zero) {
-                tc[i] = 0.0;
-                continue;
+    id_finish(t, M, ldm, s, sl, ncand, s_rank, s_zero != 0, pos, Rjj);
+}
+
+// ---------------------------------------------------------------------------
+// split form: kQsCols columns per 256-thread workgroup, one launch per step
+// ---------------------------------------------------------------------------
+// partial squared row norms over the workgroup's column group
+__global__ __launch_bounds__(kQsThreads) void k_qs_rows(const SkelTask *__restrict__ tasks, QrWork w, int ldm) {
+    const int node = blockIdx.x / w.slices, slice = blockIdx.x % w.slices;
+    const SkelTask t = tasks[node];
+    const int ncand = node_ncand(t), c0 = slice * kQsCols;
+    if (c0 >= ncand) return;
+    double *part = w.part + ((int64_t)node * w.slices + slice) * w.rcap;
+    for (int i = threadIdx.x; i < t.nq; i += kQsThreads) part[i] = row_part(t.M, ldm, i, c0, min(ncand, c0 + kQsCols));
+}
+
+// row norms (groups summed in order), kept rows and their new indices
+__global__ __launch_bounds__(kQrThreads) void k_qs_rowmap(const SkelTask *__restrict__ tasks, QrWork w) {
+    __shared__ double rn[kQrMaxRows];
+    __shared__ double red[kQrWaves];
+    __shared__ int32_t wcnt[kQrWaves];
+    const int node = blockIdx.x;
+    const SkelTask t = tasks[node];
+    const int ncand = node_ncand(t), groups = (ncand + kQsCols - 1) / kQsCols, rows = t.nq;
+    const double *part = w.part + (int64_t)node * w.slices * w.rcap;
+    for (int i = threadIdx.x; i < rows; i += kQrThreads) {
+        double a = 0.0;
+        for (int g = 0; g < groups; g++) a += part[(int64_t)g * w.rcap + i];
+        rn[i] = a;
+    }
+    __syncthreads();
+    const int kept = row_map(rn, rows, w.rmap + (int64_t)node * w.rcap, wcnt, red);
+    if (threadIdx.x == 0) w.rows[node] = kept;
+}
+
+// compaction of the group's columns, initial norms, pivot order and state
+__global__ __launch_bounds__(kQsThreads) void k_qs_init(const SkelTask *__restrict__ tasks, QrWork w, int s,
+                                                         int ldm) {
+    const int node = blockIdx.x / w.slices, slice = blockIdx.x % w.slices;
+    const SkelTask t = tasks[node];
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    const int ncand = node_ncand(t), kept = w.rows[node];
+    const int rows = kept < t.nq ? (kept > 0 ? kept : 1) : t.nq;  // as in k_qrcp
+    const int32_t *rmap = w.rmap + (int64_t)node * w.rcap;
+    double *nrm = w.nrm + (int64_t)node * 2 * w.cmax;
+    for (int q = 0; q < 2; q++) {
+        const int c = slice * kQsCols + 2 * wave + q;
+        if (c >= ncand) continue;
+        double *col = t.M + (int64_t)c * ldm;
+        if (kept < t.nq) compact_col(col, rmap, t.nq, lane);
+        const double v = col_norm(col, rows, lane);
+        if (lane == 0) nrm[c] = v;
+    }
+    if (slice == 0) {
+        int32_t *pos = w.pos + (int64_t)node * 2 * w.cmax;
+        for (int k = tid; k < ncand; k += kQsThreads) pos[k] = k;
+        if (tid == 0) {
+            int32_t *st = w.st + 4 * node;
+            st[0] = 0;
+            st[1] = 0;
+            st[2] = 0;
+            st[3] = s < rows ? s : rows;
+        }
+    }
+}
+
+// pivot step j: every workgroup of a node picks the same pivot and builds the
+// same reflector from the state of step j - 1 (norms and positions in the
+// buffer j % 2), then updates its own trailing columns into the other buffer
+__global__ __launch_bounds__(kQsThreads) void k_qs_step(const SkelTask *__restrict__ tasks, QrWork w, int j,
+                                                         int ldm) {
+    __shared__ double vh[kQrMaxRows];
+    __shared__ int32_t s_k, s_stop;
+    __shared__ double s_tau;
+    const int node = blockIdx.x / w.slices, slice = blockIdx.x % w.slices;
+    int32_t *st = w.st + 4 * node;
+    if (st[0] || j >= st[3]) return;
+    const SkelTask t = tasks[node];
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    const int ncand = node_ncand(t), kept = w.rows[node];
+    const int rows = kept < t.nq ? (kept > 0 ? kept : 1) : t.nq;
+    if (slice * kQsCols >= ncand) return;
+    const double *nin = w.nrm + (int64_t)node * 2 * w.cmax + (int64_t)(j & 1) * w.cmax;
+    double *nout = w.nrm + (int64_t)node * 2 * w.cmax + (int64_t)((j + 1) & 1) * w.cmax;
+    const int32_t *pin = w.pos + (int64_t)node * 2 * w.cmax + (int64_t)(j & 1) * w.cmax;
+    int32_t *pout = w.pos + (int64_t)node * 2 * w.cmax + (int64_t)((j + 1) & 1) * w.cmax;
+    double *Rjj = w.diag + (int64_t)node * w.cmax;
+    if (wave == 0) {
+        const int k = pick_pivot(nin, pin, j, ncand, lane);
+        const double *x = t.M + (int64_t)pin[k] * ldm;
+        const Refl r = reflector(x, j, rows, lane);
+        const bool stop = guard_stop(j, r.beta, j == 0 ? 0.0 : fabs(Rjj[0]));
+        if (!stop)
+            for (int i = j + 1 + lane; i < rows; i += kWave) vh[i] = x[i] * r.sc;
+        if (lane == 0) {
+            s_stop = stop;
+            s_k = k;
+            s_tau = r.tau;
+            vh[j] = 1.0;
+            if (slice == 0) {
+                if (stop) {
+                    st[0] = 1;
+                    st[1] = j;
+                    st[2] = (j == 0);
+                } else {
+                    Rjj[j] = r.beta;
+                }
             }
-            double acc = tc[i];
-            for (int k = i + 1; k < rank; k++) acc = fma(-M[(int64_t)k * ldm + i], tc[k], acc);
-            tc[i] = acc / M[(int64_t)i * ldm + i];
         }
     }
     __syncthreads();
-    // outputs: skeleton positions, rank, P_{C alpha~} rows
-    for (int k = tid; k < s; k += kQrThreads) t.skel[k] = k < rank ? cand_pos(t, piv[k], sl) : -1;
-    if (tid == 0) {
-        *t.sr = rank;
-        *t.trunc = (rank < (s < ncand ? s : ncand)) ? 1 : 0;
+    if (s_stop) return;
+    const int k = s_k, p = pin[k];
+    const double tau = s_tau;
+    // the next pivot order: positions j and k exchanged
+    if (slice == 0)
+        for (int q = tid; q < ncand; q += kQsThreads) pout[q] = q == j ? p : (q == k ? pin[j] : pin[q]);
+    // trailing columns of this group: those at positions > j
+    for (int q = 0; q < 2; q++) {
+        const int c = slice * kQsCols + 2 * wave + q;
+        if (c >= ncand || c == p) continue;
+        // position of c: done columns sit at positions < j
+        bool trailing = true;
+        for (int i = lane; i < j; i += kWave)
+            if (pin[i] == c) trailing = false;
+        if (__ballot(!trailing) != 0ull) continue;
+        const double v = apply_col(t.M + (int64_t)c * ldm, vh, j, rows, tau, lane);
+        if (lane == 0) nout[c] = v;
     }
-    for (int jc = tid; jc < ncand; jc += kQrThreads) {
-        double *row = t.Pt + (int64_t)prow(piv[jc]) * s;
-        if (jc < rank) {
-            for (int k = 0; k < rank; k++) row[k] = k == jc ? 1.0 : 0.0;
-        } else {
-            const double *tc = M + (int64_t)jc * ldm;
-            for (int k = 0; k < rank; k++) row[k] = tc[k];
-        }
-    }
+}
+
+// T = R11^{-1} R12 and the outputs
+__global__ __launch_bounds__(kQrThreads) void k_qs_finish(const SkelTask *__restrict__ tasks, QrWork w, int s,
+                                                           int ldm) {
+    const int node = blockIdx.x;
+    const SkelTask t = tasks[node];
+    const int32_t *st = w.st + 4 * node;
+    const int sl = t.leaf ? 0 : *t.srl, ncand = node_ncand(t);
+    const bool stopped = st[0] != 0, zero = st[2] != 0;
+    const int jstop = st[1], steps = st[3];
+    const int done = stopped ? jstop : steps;
+    const int rank = stopped ? (jstop == 0 ? 1 : jstop) : steps;
+    const int32_t *pos = w.pos + (int64_t)node * 2 * w.cmax + (int64_t)(done & 1) * w.cmax;
+    id_finish(t, t.M, ldm, s, sl, ncand, rank, zero, pos, w.diag + (int64_t)node * w.cmax);
 }
 
 }  // namespace askit

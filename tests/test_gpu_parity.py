@@ -110,6 +110,22 @@ def test_skeletons_match_oracle(setup):
         assert abs(eg - eo) <= 1e-9 + 1e-3 * eo, (node, eg, eo)
 
 
+def test_split_qrcp_matches_one_workgroup(setup, ak):
+    """The pivoted QR run by several workgroups per node (one launch per
+    pivot step) and by one workgroup per node: bit-identical skeletons."""
+    X = _cuda(setup["X"])
+    out = []
+    for levels in (-1, 99):
+        t = ak.Tree(X, setup["m"], setup["s"], setup["h"], seed=setup["seed"], qr_split_levels=levels)
+        t.skeletonize()
+        out.append(t.export_skeletons())
+        t.close()
+    (i1, p1, z1), (i2, p2, z2) = out
+    assert np.array_equal(z1, z2)
+    assert np.array_equal(i1, i2)
+    assert np.array_equal(p1, p2)
+
+
 def _tree(ak, setup):
     return ak.Tree(_cuda(setup["X"]), setup["m"], setup["s"], setup["h"], seed=setup["seed"])
 
