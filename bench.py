@@ -48,7 +48,7 @@ def node_sizes(N, D):
     return n
 
 
-def algorithmic_counts(N, d, m, s, D, nsamp, nrhs, ranks=None):
+def algorithmic_counts(N, d, m, s, D, nsamp, nrhs, ranks=None, split_levels=6):
     """Algorithmic flops and bytes of each kernel family in one step, from the
     tree's actual skeleton ranks s_a (ranks[i] for heap node i; full rank s
     when None).  These are the counts the method needs, not what the kernels
@@ -56,7 +56,9 @@ def algorithmic_counts(N, d, m, s, D, nsamp, nrhs, ranks=None):
       skel:k_qrcp         pivot step j of an r x c sampled block: 6 (r-j)(c-j-1)
                           flops (reflector dot 2 + axpy 2 + column norm 2 per
                           trailing element), s_a steps, then T = R11^-1 R12:
-                          s_a^2 (c - s_a); nothing when c <= s (P = I)
+                          s_a^2 (c - s_a); nothing when c <= s (P = I).
+                          Nodes at tree levels <= split_levels count for the
+                          split form (skel:k_qrcp_split), the rest for k_qrcp
       skel:k_sample_block 3d + 1 flops per sampled kernel entry (difference,
                           fma, exp counted as one), nodes with c > s only
       factor:k_lu         (2/3) n^3 per LU (leaf n = m, internal n = s_l + s_r)
@@ -72,7 +74,7 @@ def algorithmic_counts(N, d, m, s, D, nsamp, nrhs, ranks=None):
     sz = node_sizes(N, D)
     r = np.full(nn, s, dtype=np.int64) if ranks is None else np.asarray(ranks, dtype=np.int64)
     first_leaf = (1 << D) - 1
-    c = {k: 0.0 for k in ("qr", "samp", "lu", "fsolve", "zblk", "tele", "sbytes", "sflops", "skmm")}
+    c = {k: 0.0 for k in ("qr", "qr1", "qrs", "samp", "lu", "fsolve", "zblk", "tele", "sbytes", "sflops", "skmm")}
     for i in range(nn):
         n = float(sz[i])
         leaf = i >= first_leaf
@@ -81,7 +83,9 @@ def algorithmic_counts(N, d, m, s, D, nsamp, nrhs, ranks=None):
             if cols > s:
                 rows = float(min(nsamp, N - n))
                 k = int(r[i])
-                c["qr"] += sum(6.0 * (rows - j) * (cols - j - 1) for j in range(k)) + k * k * (cols - k)
+                w = sum(6.0 * (rows - j) * (cols - j - 1) for j in range(k)) + k * k * (cols - k)
+                c["qr"] += w
+                c["qrs" if int(np.log2(i + 1)) <= split_levels else "qr1"] += w
                 c["samp"] += rows * cols * (3.0 * d + 1)
         nlu = n if leaf else float(r[2 * i + 1] + r[2 * i + 2])
         c["lu"] += (2.0 / 3.0) * nlu ** 3
@@ -103,7 +107,11 @@ def algorithmic_counts(N, d, m, s, D, nsamp, nrhs, ranks=None):
 # bound, peak key, unit).  FP64 vector and FP64 MFMA share one peak on MI355X;
 # the mixed path's products run FP32 MFMA.
 ROOF_TABLE = [
-    ("skel:k_qrcp", "qr", "alu", "fp64", "TFLOP/s", lambda D: D),
+    # (profile key, count key, bound, peak, unit, launches of one pass: a
+    # function of the depth, or None when the count varies with the ranks --
+    # then the measured launches of the timed steps are used)
+    ("skel:k_qrcp", "qr1", "alu", "fp64", "TFLOP/s", None),
+    ("skel:k_qrcp_split", "qrs", "alu", "fp64", "TFLOP/s", None),
     ("skel:k_sample_block", "samp", "alu", "fp64", "TFLOP/s", lambda D: D),
     ("factor:k_lu", "lu", "alu", "fp64", "TFLOP/s", lambda D: D + 1),
     ("factor:k_lusolve", "fsolve", "mfma", "fp64", "TFLOP/s", lambda D: D),
@@ -126,7 +134,7 @@ def kernel_source_sha(name):
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def roofline_of(key, cnt_key, bound, peak_key, unit, nlaunch, prof, cnt, D):
+def roofline_of(key, cnt_key, bound, peak_key, unit, nlaunch, prof, cnt, D, steps):
     """Algorithmic work of one pass of the kernel family divided over the
     launches one pass makes (one per tree level); the solve plan runs once per
     operator application, so the measured launch count may be a multiple."""
@@ -134,7 +142,7 @@ def roofline_of(key, cnt_key, bound, peak_key, unit, nlaunch, prof, cnt, D):
         return None
     ms, launches = prof[key]
     per_launch_ms = ms / launches
-    work_per_launch = cnt[cnt_key] / nlaunch(D)
+    work_per_launch = cnt[cnt_key] / (nlaunch(D) if nlaunch else launches / steps)
     if unit == "GB/s":
         achieved = work_per_launch / (per_launch_ms * 1e-3) / 1e9
         peak = HBM_PEAK_GBS
@@ -281,7 +289,7 @@ def main():
         rank_levels[lvl] = [int(rl.min()), round(float(rl.mean()), 1), int(rl.max())]
     rooflines = {}
     for key, ck, bound, pk, unit, nl in ROOF_TABLE:
-        r = roofline_of(key, ck, bound, pk, unit, nl, prof, cnt, tree.D)
+        r = roofline_of(key, ck, bound, pk, unit, nl, prof, cnt, tree.D, args.steps)
         if r is not None:
             rooflines[key] = r
     # the headline is the kernel that dominates the metric's value (the

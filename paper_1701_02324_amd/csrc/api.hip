@@ -286,7 +286,7 @@ void xcd_order(std::vector<TileItem> &items) {
 template <typename T, typename TB, typename TO>
 hipError_t launch_kmm(const KmmTask *tasks, const TileItem *items, int nitems, int ncol, int d, int tc,
                       hipStream_t st) {
-    const size_t lds = sizeof(T) * (64 + 16) * d;
+    const size_t lds = sizeof(T) * (64 * (d | 1) + 16 * d);
     if (tc == 128) hipLaunchKernelGGL((k_kmm<T, TB, TO, 128>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
     else if (tc == 64) hipLaunchKernelGGL((k_kmm<T, TB, TO, 64>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
     else hipLaunchKernelGGL((k_kmm<T, TB, TO, 16>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
@@ -388,8 +388,9 @@ template <typename T, bool TR>
 hipError_t launch_lusolve(const LuTask *tp, int n, int nrhs, hipStream_t st) {
     const int panels = nrhs > 16 ? (int)cdiv(nrhs, 32) : 1;
     const int grid = 8 * (int)cdiv((int64_t)n * panels, 8);
-    if (nrhs > 16) hipLaunchKernelGGL((k_lusolve<T, 32, TR>), dim3(grid), dim3(256), 0, st, tp, n, nrhs, panels);
-    else hipLaunchKernelGGL((k_lusolve<T, 16, TR>), dim3(grid), dim3(256), 0, st, tp, n, nrhs, 1);
+    if (nrhs > 16)
+        hipLaunchKernelGGL((k_lusolve<T, 32, TR>), dim3(grid), dim3(kLsThreads), 0, st, tp, n, nrhs, panels);
+    else hipLaunchKernelGGL((k_lusolve<T, 16, TR>), dim3(grid), dim3(kLsThreads), 0, st, tp, n, nrhs, 1);
     return hipGetLastError();
 }
 
@@ -784,7 +785,7 @@ static askit_status skeletonize_impl(askit_tree *trees, int count, hipStream_t s
             }));
             const int rt = (int)cdiv(nsamp_max, 64), ct = (int)cdiv(cmax, 64);
             HIP_TRY(timed("skel:k_sample_block", st, [&] {
-                hipLaunchKernelGGL(k_sample_block, dim3(nqr * rt * ct), dim3(256), sizeof(double) * 128 * d, st,
+                hipLaunchKernelGGL(k_sample_block, dim3(nqr * rt * ct), dim3(256), sizeof(double) * (64 * (d | 1) + 64 * d), st,
                                    dsk.as<SkelTask>(), rt, nsamp_max, d, ct);
                 return hipGetLastError();
             }));
@@ -996,7 +997,8 @@ static askit_status factor_plan(const std::vector<askit_factor> &fs, Plan &P) {
         const LeafTask *lp = b->as<LeafTask>();
         const int nl = (int)lt.size(), tl = (int)cdiv(mmax, 64);
         P.add("k_leaf_block", [=](hipStream_t st, int) -> hipError_t {
-            hipLaunchKernelGGL(k_leaf_block, dim3(nl * tl * tl), dim3(256), sizeof(double) * 128 * d, st, lp, tl, d);
+            hipLaunchKernelGGL(k_leaf_block, dim3(nl * tl * tl), dim3(256), sizeof(double) * (64 * (d | 1) + 64 * d), st,
+                               lp, tl, d);
             return hipGetLastError();
         });
         ST_TRY(lu_commit(P, lu));

@@ -243,21 +243,36 @@ __device__ inline void diag_apply(double (*S)[NR + 1], int r0, const double *D, 
 // S[J block] -= M(J, I) S[I block] for the blocks J in [jb0, jb1); element
 // (r, c) of the 16 x 16 coupling block is read through get(row, col) with
 // global row/column indices
+// Each wave takes the jobs wave, wave + 16, ... and loads the coupling blocks
+// of four jobs before their products, so that a workgroup keeps up to 64
+// block loads in flight.
 template <int NR, typename G>
 __device__ inline void block_update(double (*S)[NR + 1], int i0, int jb0, int jb1, G get, int lane, int wave) {
-    constexpr int CB = NR / 16;
-    const int nw = kLuThreads / kWave;
-    for (int job = wave; job < (jb1 - jb0) * CB; job += nw) {
-        const int J = jb0 + job / CB, cb = job % CB;
-        dbl4 acc = {0, 0, 0, 0};
+    constexpr int CB = NR / 16, NW = kLsThreads / kWave, U = 4;
+    const int njobs = (jb1 - jb0) * CB;
+    for (int base = wave; base < njobs; base += NW * U) {
+        double a[U][4];
 #pragma unroll
-        for (int k4 = 0; k4 < 16; k4 += 4) {
-            const int kk = k4 + lane / 16;
-            double a = get(J * 16 + lane % 16, i0 + kk);
-            double b = S[i0 + kk][cb * 16 + lane % 16];
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        for (int u = 0; u < U; u++) {
+            const int job = base + u * NW;
+            const int J = jb0 + job / CB;
+#pragma unroll
+            for (int k4 = 0; k4 < 4; k4++)
+                a[u][k4] = job < njobs ? get(J * 16 + lane % 16, i0 + 4 * k4 + lane / 16) : 0.0;
         }
-        for (int q = 0; q < 4; q++) S[J * 16 + 4 * q + lane / 16][cb * 16 + lane % 16] -= acc[q];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int job = base + u * NW;
+            if (job >= njobs) break;
+            const int J = jb0 + job / CB, cb = job % CB;
+            dbl4 acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int k4 = 0; k4 < 4; k4++) {
+                double b = S[i0 + 4 * k4 + lane / 16][cb * 16 + lane % 16];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][k4], b, acc, 0, 0, 0);
+            }
+            for (int q = 0; q < 4; q++) S[J * 16 + 4 * q + lane / 16][cb * 16 + lane % 16] -= acc[q];
+        }
     }
     __syncthreads();
 }
@@ -266,7 +281,7 @@ __device__ inline void block_update(double (*S)[NR + 1], int i0, int jb0, int jb
 // b % 8); the (matrix, panel) pairs are numbered so that the panels of one
 // matrix land on the same XCD and share its factors in that XCD's L2.
 template <typename T, int NR, bool TRANS>
-__global__ __launch_bounds__(kLuThreads) void k_lusolve(const LuTask *__restrict__ tasks, int ntask, int nrhs,
+__global__ __launch_bounds__(kLsThreads) void k_lusolve(const LuTask *__restrict__ tasks, int ntask, int nrhs,
                                                         int panels) {
     __shared__ double S[kLuMaxN][NR + 1];
     const int total = ntask * panels, chunk = (total + 7) / 8;
@@ -280,7 +295,7 @@ __global__ __launch_bounds__(kLuThreads) void k_lusolve(const LuTask *__restrict
     const int n = t.n, lda = t.lda, nb = (n + 15) / 16, tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
     const double *A = t.A;
     T *B = (T *)t.B;
-    for (int i = tid; i < nb * 16 * NR; i += kLuThreads) {
+    for (int i = tid; i < nb * 16 * NR; i += kLsThreads) {
         const int r = i / NR, c = i % NR;
         S[r][c] = (r < n && c < ncols) ? (double)B[(int64_t)r * t.ldb + c0 + c] : 0.0;
     }
@@ -328,7 +343,7 @@ __global__ __launch_bounds__(kLuThreads) void k_lusolve(const LuTask *__restrict
             }
         __syncthreads();
     }
-    for (int i = tid; i < n * NR; i += kLuThreads) {
+    for (int i = tid; i < n * NR; i += kLsThreads) {
         const int r = i / NR, c = i % NR;
         if (c < ncols) B[(int64_t)r * t.ldb + c0 + c] = (T)S[r][c];
     }

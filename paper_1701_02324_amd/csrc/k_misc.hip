@@ -65,8 +65,11 @@ template __global__ void k_scatter_multi<float>(const GatherTask *, double *cons
 // lambda I + K(X_a, X_a) in column-major, 64 x 64 tiles with both point
 // sets staged in LDS; grid = task * tiles^2 + tile
 __global__ __launch_bounds__(256) void k_leaf_block(const LeafTask *__restrict__ tasks, int tiles, int d) {
-    extern __shared__ double dyn_lds[];  // 2 x 64 x d doubles
-    double *ys = dyn_lds, *xs = dyn_lds + 64 * d;
+    // row points at an odd stride (lanes read different points: no bank
+    // conflicts), column points at stride d (one point per wave: broadcast)
+    extern __shared__ double dyn_lds[];  // 64 (d | 1) + 64 d doubles
+    const int dp = d | 1;
+    double *ys = dyn_lds, *xs = dyn_lds + 64 * dp;
     const int per = tiles * tiles;
     const LeafTask t = tasks[blockIdx.x / per];
     const int rt = (blockIdx.x % per) % tiles, ct = (blockIdx.x % per) / tiles;
@@ -75,13 +78,13 @@ __global__ __launch_bounds__(256) void k_leaf_block(const LeafTask *__restrict__
     const int nr = min(64, t.n - r0), nc = min(64, t.n - c0);
     for (int i = threadIdx.x; i < 64 * d; i += blockDim.x) {
         const int a = i / d, k = i % d;
-        ys[i] = a < nr ? t.X[(t.b + r0 + a) * d + k] : 0.0;
+        ys[a * dp + k] = a < nr ? t.X[(t.b + r0 + a) * d + k] : 0.0;
         xs[i] = a < nc ? t.X[(t.b + c0 + a) * d + k] : 0.0;
     }
     __syncthreads();
     const int r = threadIdx.x % 64;
     if (r >= nr) return;
-    const double *y = ys + r * d;
+    const double *y = ys + r * dp;
     for (int c = threadIdx.x / 64; c < nc; c += 4) {
         const double *x = xs + c * d;
         double r2 = 0.0;

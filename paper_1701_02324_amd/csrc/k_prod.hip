@@ -58,8 +58,11 @@ __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, 
     constexpr int NB = TC / 16;
     __shared__ T sA[kTR][kKS + 1];
     __shared__ T sB[kKS][TC + 1];
-    extern __shared__ double dyn_lds[];  // (64 + 16) x d elements of T
-    T *sR = (T *)dyn_lds, *sS = (T *)dyn_lds + kTR * d;
+    // row points at an odd stride (lanes read different rows: no bank
+    // conflicts), contraction points at stride d (broadcast within a wave)
+    extern __shared__ double dyn_lds[];  // 64 (d | 1) + 16 d elements of T
+    const int dp = d | 1;
+    T *sR = (T *)dyn_lds, *sS = (T *)dyn_lds + kTR * dp;
     const TileItem it = items[blockIdx.x];
     if (it.task < 0) return;
     const KmmTask t = tasks[it.task];
@@ -82,7 +85,7 @@ __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, 
     // stage the row points (fixed for the whole contraction)
     for (int i = tid; i < kTR * d; i += 256) {
         int r = i / d, k = i % d;
-        sR[i] = r0 + r < nrow ? (T)t.X[src_pos(t.R, r0 + r) * d + k] : (T)0;
+        sR[r * dp + k] = r0 + r < nrow ? (T)t.X[src_pos(t.R, r0 + r) * d + k] : (T)0;
     }
     typename Acc<T>::type acc[NB];
     for (int b = 0; b < NB; b++) acc[b] = typename Acc<T>::type{0, 0, 0, 0};
@@ -104,7 +107,7 @@ __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, 
             int r = i % kTR, k = i / kTR;
             T v = (T)0;
             if (k < kn && r0 + r < nrow) {
-                const T *x = sR + r * d, *y = sS + k * d;
+                const T *x = sR + r * dp, *y = sS + k * d;
                 T r2 = 0;
                 for (int q = 0; q < d; q++) {
                     T df = x[q] - y[q];

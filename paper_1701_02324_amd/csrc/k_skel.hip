@@ -91,8 +91,11 @@ __device__ inline double sqdist(const double *x, const double *y, int d) {
 // column (consecutive rows across lanes: coalesced column-major stores)
 __global__ __launch_bounds__(256) void k_sample_block(const SkelTask *__restrict__ tasks, int rowtiles, int ldm, int d,
                                                       int coltiles) {
-    extern __shared__ double dyn_lds[];  // 2 x 64 x d doubles
-    double *ys = dyn_lds, *xs = dyn_lds + 64 * d;
+    // row points at an odd stride (lanes read different points: no bank
+    // conflicts), column points at stride d (one point per wave: broadcast)
+    extern __shared__ double dyn_lds[];  // 64 (d | 1) + 64 d doubles
+    const int dp = d | 1;
+    double *ys = dyn_lds, *xs = dyn_lds + 64 * dp;
     const int per = rowtiles * coltiles;
     const int task = blockIdx.x / per, rt = (blockIdx.x % per) % rowtiles, ct = (blockIdx.x % per) / rowtiles;
     const SkelTask t = tasks[task];
@@ -103,13 +106,13 @@ __global__ __launch_bounds__(256) void k_sample_block(const SkelTask *__restrict
     const int nr = min(64, t.nq - r0), nc = min(64, ncand - c0);
     for (int i = threadIdx.x; i < 64 * d; i += blockDim.x) {
         const int a = i / d, k = i % d;
-        ys[i] = a < nr ? t.X[(int64_t)t.q[r0 + a] * d + k] : 0.0;
+        ys[a * dp + k] = a < nr ? t.X[(int64_t)t.q[r0 + a] * d + k] : 0.0;
         xs[i] = a < nc ? t.X[(int64_t)cand_pos(t, c0 + a, sl) * d + k] : 0.0;
     }
     __syncthreads();
     const int r = threadIdx.x % 64;
     if (r >= nr) return;
-    const double *y = ys + r * d;
+    const double *y = ys + r * dp;
     for (int c = threadIdx.x / 64; c < nc; c += 4)
         t.M[(int64_t)(c0 + c) * ldm + r0 + r] = exp(sqdist(xs + c * d, y, d) * t.scale);
 }
