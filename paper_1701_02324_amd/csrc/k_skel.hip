@@ -156,11 +156,13 @@ __device__ inline int node_ncand(const SkelTask &t) { return t.leaf ? t.n : *t.s
 
 // squared norm of row i over the columns [c0, c1) of the block
 __device__ inline double row_part(const double *M, int ldm, int i, int c0, int c1) {
+    double v[kQsCols];
+#pragma unroll
+    for (int u = 0; u < kQsCols; u++) v[u] = c0 + u < c1 ? M[(int64_t)(c0 + u) * ldm + i] : 0.0;
     double p = 0.0;
-    for (int c = c0; c < c1; c++) {
-        const double v = M[(int64_t)c * ldm + i];
-        p = fma(v, v, p);
-    }
+#pragma unroll
+    for (int u = 0; u < kQsCols; u++)
+        if (c0 + u < c1) p = fma(v[u], v[u], p);
     return p;
 }
 
@@ -199,21 +201,39 @@ __device__ int row_map(const double *rn, int rows, IT *rmap, int32_t *wcnt, doub
 }
 
 // in-place compaction of one column by one wave: rows only move up, and a
-// wave reads a 64-row chunk before writing it
+// wave reads a block of 1024 rows (16 per lane) before writing it
 template <typename IT>
 __device__ inline void compact_col(double *col, const IT *rmap, int rows, int lane) {
-    for (int base = 0; base < rows; base += kWave) {
-        const int i = base + lane;
-        const double v = i < rows ? col[i] : 0.0;
-        const int dst = i < rows ? (int)rmap[i] : -1;
-        if (dst >= 0) col[dst] = v;
+    for (int base = 0; base < rows; base += 16 * kWave) {
+        double v[16];
+#pragma unroll
+        for (int t = 0; t < 16; t++) {
+            const int i = base + lane + t * kWave;
+            v[t] = i < rows ? col[i] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < 16; t++) {
+            const int i = base + lane + t * kWave;
+            const int dst = i < rows ? (int)rmap[i] : -1;
+            if (dst >= 0) col[dst] = v[t];
+        }
     }
 }
 
 // squared norm of rows [0, rows) of a column (one wave)
 __device__ inline double col_norm(const double *col, int rows, int lane) {
     double acc = 0.0;
-    for (int i = lane; i < rows; i += kWave) acc = fma(col[i], col[i], acc);
+    for (int base = 0; base < rows; base += 4 * kWave) {
+        double v[4];
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const int i = base + lane + t * kWave;
+            v[t] = i < rows ? col[i] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; t++)
+            if (base + lane + t * kWave < rows) acc = fma(v[t], v[t], acc);
+    }
     return wave_sum(acc);
 }
 
@@ -289,13 +309,80 @@ __device__ inline double apply_col(double *col, const double *vh, int j, int row
     return wave_sum(n);
 }
 
+// the same update for NC columns at once (positions q0 + u qstride < qend):
+// all their loads are issued before the first product; rows - j <= 64 NT.
+// The per-column arithmetic is that of apply_col (chunks past the rows add
+// exact zeros), so the grouping does not change any result.
+template <int NT, int NC>
+__device__ inline void apply_group(double *M, int ldm, const int32_t *pos, int q0, int qstride, int qend,
+                                   const double *vh, int j, int rows, double tau, int lane, double *nrm) {
+    double vr[NT], a[NC][NT];
+    int c[NC];
+#pragma unroll
+    for (int t = 0; t < NT; t++) {
+        const int i = j + lane + t * kWave;
+        vr[t] = i < rows ? vh[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < NC; u++) {
+        const int q = q0 + u * qstride;
+        c[u] = q < qend ? pos[q] : -1;
+#pragma unroll
+        for (int t = 0; t < NT; t++) {
+            const int i = j + lane + t * kWave;
+            a[u][t] = (c[u] >= 0 && i < rows) ? M[(int64_t)c[u] * ldm + i] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < NC; u++) {
+        if (c[u] < 0) break;
+        double w = 0.0;
+#pragma unroll
+        for (int t = 0; t < NT; t++) w = fma(vr[t], a[u][t], w);
+        w = wave_sum(w) * tau;
+        double n = 0.0;
+#pragma unroll
+        for (int t = 0; t < NT; t++) {
+            const int i = j + lane + t * kWave;
+            a[u][t] = fma(-vr[t], w, a[u][t]);
+            if (i > j && i < rows) n = fma(a[u][t], a[u][t], n);
+        }
+        double *col = M + (int64_t)c[u] * ldm;
+#pragma unroll
+        for (int t = 0; t < NT; t++) {
+            const int i = j + lane + t * kWave;
+            if (i < rows) col[i] = a[u][t];
+        }
+        n = wave_sum(n);
+        if (lane == 0) nrm[c[u]] = n;
+    }
+}
+
+template <int NT, int NC>
+__device__ inline void apply_all(double *M, int ldm, const int32_t *pos, int j, int ncand, const double *vh, int rows,
+                                 double tau, int lane, int wave, double *nrm) {
+    for (int q0 = j + 1 + wave; q0 < ncand; q0 += kQrWaves * NC)
+        apply_group<NT, NC>(M, ldm, pos, q0, kQrWaves, ncand, vh, j, rows, tau, lane, nrm);
+}
+
 // T = R11^{-1} R12 in place of R12 and the outputs (skeleton positions, rank,
 // rows of P_{C alpha~}); pos[q] = column at pivot position q, Rjj = diagonal
 // of R.  All kQrThreads threads.
+// lds: scratch of ldsn doubles; the strict upper triangle of R11 is staged
+// there (row-major, packed) when it fits.
 __device__ void id_finish(const SkelTask &t, double *M, int ldm, int s, int sl, int ncand, int rank, bool zero,
-                          const int32_t *pos, const double *Rjj) {
+                          const int32_t *pos, const double *Rjj, double *lds, int ldsn) {
     const int tid = threadIdx.x;
     auto prow = [&](int c) { return t.leaf ? c : (c < sl ? c : s + (c - sl)); };
+    const bool staged = !zero && rank * (rank - 1) / 2 <= ldsn;
+    auto off = [&](int i) { return i * (rank - 1) - i * (i - 1) / 2; };  // row i, column i + 1
+    if (staged) {
+        for (int e = tid; e < rank * rank; e += kQrThreads) {
+            const int i = e / rank, k = e % rank;
+            if (k > i) lds[off(i) + (k - i - 1)] = M[(int64_t)pos[k] * ldm + i];
+        }
+    }
+    __syncthreads();
     for (int q = rank + tid; q < ncand; q += kQrThreads) {
         double *tc = M + (int64_t)pos[q] * ldm;
         for (int i = rank - 1; i >= 0; i--) {
@@ -304,7 +391,12 @@ __device__ void id_finish(const SkelTask &t, double *M, int ldm, int s, int sl, 
                 continue;
             }
             double acc = tc[i];
-            for (int k = i + 1; k < rank; k++) acc = fma(-M[(int64_t)pos[k] * ldm + i], tc[k], acc);
+            if (staged) {
+                const double *Ri = lds + off(i) - (i + 1);
+                for (int k = i + 1; k < rank; k++) acc = fma(-Ri[k], tc[k], acc);
+            } else {
+                for (int k = i + 1; k < rank; k++) acc = fma(-M[(int64_t)pos[k] * ldm + i], tc[k], acc);
+            }
             tc[i] = acc / Rjj[i];
         }
     }
@@ -442,14 +534,20 @@ __global__ __launch_bounds__(kQrThreads) void k_qrcp(const SkelTask *__restrict_
         if (s_stop) break;
         if (j == 0) r00 = fabs(Rjj[0]);
         const double tau = s_tau;
-        for (int q = j + 1 + wave; q < ncand; q += kQrWaves) {
-            const int c = pos[q];
-            const double v = apply_col(M + (int64_t)c * ldm, vh, j, rows, tau, lane);
-            if (lane == 0) nrm[c] = v;
-        }
+        const int span = rows - j;
+        if (span <= kWave) apply_all<1, 16>(M, ldm, pos, j, ncand, vh, rows, tau, lane, wave, nrm);
+        else if (span <= 2 * kWave) apply_all<2, 8>(M, ldm, pos, j, ncand, vh, rows, tau, lane, wave, nrm);
+        else if (span <= 4 * kWave) apply_all<4, 4>(M, ldm, pos, j, ncand, vh, rows, tau, lane, wave, nrm);
+        else if (span <= 8 * kWave) apply_all<8, 2>(M, ldm, pos, j, ncand, vh, rows, tau, lane, wave, nrm);
+        else
+            for (int q = j + 1 + wave; q < ncand; q += kQrWaves) {
+                const int c = pos[q];
+                const double v = apply_col(M + (int64_t)c * ldm, vh, j, rows, tau, lane);
+                if (lane == 0) nrm[c] = v;
+            }
         __syncthreads();
     }
-    id_finish(t, M, ldm, s, sl, ncand, s_rank, s_zero != 0, pos, Rjj);
+    id_finish(t, M, ldm, s, sl, ncand, s_rank, s_zero != 0, pos, Rjj, vh, kQrMaxRows);
 }
 
 // ---------------------------------------------------------------------------
@@ -583,6 +681,7 @@ __global__ __launch_bounds__(kQsThreads) void k_qs_step(const SkelTask *__restri
 // T = R11^{-1} R12 and the outputs
 __global__ __launch_bounds__(kQrThreads) void k_qs_finish(const SkelTask *__restrict__ tasks, QrWork w, int s,
                                                            int ldm) {
+    __shared__ double buf[kQrMaxRows];
     const int node = blockIdx.x;
     const SkelTask t = tasks[node];
     const int32_t *st = w.st + 4 * node;
@@ -592,7 +691,7 @@ __global__ __launch_bounds__(kQrThreads) void k_qs_finish(const SkelTask *__rest
     const int done = stopped ? jstop : steps;
     const int rank = stopped ? (jstop == 0 ? 1 : jstop) : steps;
     const int32_t *pos = w.pos + (int64_t)node * 2 * w.cmax + (int64_t)(done & 1) * w.cmax;
-    id_finish(t, t.M, ldm, s, sl, ncand, rank, zero, pos, w.diag + (int64_t)node * w.cmax);
+    id_finish(t, t.M, ldm, s, sl, ncand, rank, zero, pos, w.diag + (int64_t)node * w.cmax, buf, kQrMaxRows);
 }
 
 }  // namespace askit
