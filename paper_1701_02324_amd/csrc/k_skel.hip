@@ -367,37 +367,75 @@ __device__ inline void apply_all(double *M, int ldm, const int32_t *pos, int j, 
 
 // T = R11^{-1} R12 in place of R12 and the outputs (skeleton positions, rank,
 // rows of P_{C alpha~}); pos[q] = column at pivot position q, Rjj = diagonal
-// of R.  All kQrThreads threads.
-// lds: scratch of ldsn doubles; the strict upper triangle of R11 is staged
-// there (row-major, packed) when it fits.
+// of R.  All kQrThreads threads.  Back substitution by columns: each wave
+// takes groups of kTq right-hand columns, lane l holding their rows
+// l + 64 u in registers; from the last row up, t_i = r_i / R_ii is taken
+// from its lane and column i of R11 (rows 0 .. i-1 of column pos[i],
+// contiguous, loaded one step ahead) updates the rows above.
+constexpr int kTq = 8;
+constexpr int kTu = kQrMaxRank / kWave;
 __device__ void id_finish(const SkelTask &t, double *M, int ldm, int s, int sl, int ncand, int rank, bool zero,
-                          const int32_t *pos, const double *Rjj, double *lds, int ldsn) {
-    const int tid = threadIdx.x;
+                          const int32_t *pos, const double *Rjj) {
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
     auto prow = [&](int c) { return t.leaf ? c : (c < sl ? c : s + (c - sl)); };
-    const bool staged = !zero && rank * (rank - 1) / 2 <= ldsn;
-    auto off = [&](int i) { return i * (rank - 1) - i * (i - 1) / 2; };  // row i, column i + 1
-    if (staged) {
-        for (int e = tid; e < rank * rank; e += kQrThreads) {
-            const int i = e / rank, k = e % rank;
-            if (k > i) lds[off(i) + (k - i - 1)] = M[(int64_t)pos[k] * ldm + i];
+    const int nr = ncand - rank;
+    for (int g = wave * kTq; g < nr; g += kQrWaves * kTq) {
+        double r[kTq][kTu];
+        int cq[kTq];
+#pragma unroll
+        for (int u = 0; u < kTq; u++) {
+            const int q = rank + g + u;
+            cq[u] = q < ncand ? pos[q] : -1;
+#pragma unroll
+            for (int v = 0; v < kTu; v++) {
+                const int k = lane + v * kWave;
+                r[u][v] = (cq[u] >= 0 && k < rank && !zero) ? M[(int64_t)cq[u] * ldm + k] : 0.0;
+            }
         }
-    }
-    __syncthreads();
-    for (int q = rank + tid; q < ncand; q += kQrThreads) {
-        double *tc = M + (int64_t)pos[q] * ldm;
-        for (int i = rank - 1; i >= 0; i--) {
-            if (zero) {
-                tc[i] = 0.0;
-                continue;
+        if (!zero) {
+            double rk[kTu], rn[kTu];
+            {
+                const double *Ri = M + (int64_t)pos[rank - 1] * ldm;
+#pragma unroll
+                for (int v = 0; v < kTu; v++) {
+                    const int k = lane + v * kWave;
+                    rk[v] = k < rank - 1 ? Ri[k] : 0.0;
+                }
             }
-            double acc = tc[i];
-            if (staged) {
-                const double *Ri = lds + off(i) - (i + 1);
-                for (int k = i + 1; k < rank; k++) acc = fma(-Ri[k], tc[k], acc);
-            } else {
-                for (int k = i + 1; k < rank; k++) acc = fma(-M[(int64_t)pos[k] * ldm + i], tc[k], acc);
+#pragma unroll
+            for (int vi = kTu - 1; vi >= 0; vi--) {
+                for (int src = kWave - 1; src >= 0; src--) {
+                    const int i = vi * kWave + src;
+                    if (i >= rank) continue;
+                    if (i > 0) {
+                        const double *Rn = M + (int64_t)pos[i - 1] * ldm;
+#pragma unroll
+                        for (int v = 0; v < kTu; v++) {
+                            const int k = lane + v * kWave;
+                            rn[v] = k < i - 1 ? Rn[k] : 0.0;
+                        }
+                    }
+                    const double d = Rjj[i];
+#pragma unroll
+                    for (int u = 0; u < kTq; u++) {
+                        const double ti = __shfl(r[u][vi], src) / d;
+                        if (lane == src) r[u][vi] = ti;
+#pragma unroll
+                        for (int v = 0; v <= vi; v++) r[u][v] = fma(-rk[v], ti, r[u][v]);
+                    }
+#pragma unroll
+                    for (int v = 0; v < kTu; v++) rk[v] = rn[v];
+                }
             }
-            tc[i] = acc / Rjj[i];
+        }
+#pragma unroll
+        for (int u = 0; u < kTq; u++) {
+            if (cq[u] < 0) break;
+#pragma unroll
+            for (int v = 0; v < kTu; v++) {
+                const int k = lane + v * kWave;
+                if (k < rank) M[(int64_t)cq[u] * ldm + k] = r[u][v];
+            }
         }
     }
     __syncthreads();
@@ -547,7 +585,7 @@ __global__ __launch_bounds__(kQrThreads) void k_qrcp(const SkelTask *__restrict_
             }
         __syncthreads();
     }
-    id_finish(t, M, ldm, s, sl, ncand, s_rank, s_zero != 0, pos, Rjj, vh, kQrMaxRows);
+    id_finish(t, M, ldm, s, sl, ncand, s_rank, s_zero != 0, pos, Rjj);
 }
 
 // ---------------------------------------------------------------------------
@@ -681,7 +719,6 @@ __global__ __launch_bounds__(kQsThreads) void k_qs_step(const SkelTask *__restri
 // T = R11^{-1} R12 and the outputs
 __global__ __launch_bounds__(kQrThreads) void k_qs_finish(const SkelTask *__restrict__ tasks, QrWork w, int s,
                                                            int ldm) {
-    __shared__ double buf[kQrMaxRows];
     const int node = blockIdx.x;
     const SkelTask t = tasks[node];
     const int32_t *st = w.st + 4 * node;
@@ -691,7 +728,7 @@ __global__ __launch_bounds__(kQrThreads) void k_qs_finish(const SkelTask *__rest
     const int done = stopped ? jstop : steps;
     const int rank = stopped ? (jstop == 0 ? 1 : jstop) : steps;
     const int32_t *pos = w.pos + (int64_t)node * 2 * w.cmax + (int64_t)(done & 1) * w.cmax;
-    id_finish(t, t.M, ldm, s, sl, ncand, rank, zero, pos, w.diag + (int64_t)node * w.cmax, buf, kQrMaxRows);
+    id_finish(t, t.M, ldm, s, sl, ncand, rank, zero, pos, w.diag + (int64_t)node * w.cmax);
 }
 
 }  // namespace askit
