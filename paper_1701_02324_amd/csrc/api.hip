@@ -373,7 +373,7 @@ askit_status lu_commit(Plan &P, const std::vector<LuTask> &v) {
     const LuTask *tp = b->as<LuTask>();
     const int n = (int)v.size();
     P.add("k_lu", [=](hipStream_t st, int) -> hipError_t {
-        hipLaunchKernelGGL(k_lu, dim3(n), dim3(256), 0, st, tp);
+        hipLaunchKernelGGL(k_lu, dim3(n), dim3(kLuFThreads), 0, st, tp);
         return hipGetLastError();
     });
     P.add("k_lu_diaginv", [=](hipStream_t st, int) -> hipError_t {

@@ -14,6 +14,7 @@ constexpr int kPowerIters = 50;  // power iterations for the principal axis
 constexpr double kRankGuard = 1e-14;
 constexpr int kQsCols = 8;       // columns per workgroup of the split QRCP
 constexpr int kLsThreads = 1024; // batched LU solves: 16 waves keep many block loads in flight
+constexpr int kLuFThreads = 512; // batched LU factorization
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));

@@ -15,6 +15,7 @@ namespace askit {
 
 constexpr int kLuThreads = 256;
 constexpr int kPanel = 32;
+static_assert(kLuFThreads % kWave == 0, "whole waves");
 constexpr int kLuMaxN = 512;
 
 __device__ inline void argmax_abs(double v, int i, double &bv, int &bi) {
@@ -25,10 +26,19 @@ __device__ inline void argmax_abs(double v, int i, double &bv, int &bi) {
     }
 }
 
-__global__ __launch_bounds__(kLuThreads) void k_lu(const LuTask *__restrict__ tasks) {
-    __shared__ double Up[kPanel * kLuMaxN];   // U block row (row-major, ld = n)
-    __shared__ double redv[kLuThreads / kWave];
-    __shared__ int redi[kLuThreads / kWave];
+__global__ __launch_bounds__(kLuFThreads) void k_lu(const LuTask *__restrict__ tasks) {
+    constexpr int NT = kLuFThreads, NW = NT / kWave;
+    // W: the panel (column-major, ld = n - kb) while it is factored, then the
+    // U block row (row-major, ld = n); L11: the unit lower panel triangle
+    __shared__ double W[kPanel * kLuMaxN];
+    __shared__ double L11[kPanel * kPanel];
+    __shared__ double redv[NW];
+    __shared__ int redi[NW];
+    __shared__ int32_t sp[kPanel];
+    // logical row i of the matrix is stored in physical row prow[i]: row
+    // exchanges only swap entries here; one pass at the end puts every row
+    // in place
+    __shared__ int32_t prow[kLuMaxN];
     __shared__ double s_min, s_max;
     const LuTask t = tasks[blockIdx.x];
     const int n = t.n, lda = t.lda, tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
@@ -37,16 +47,23 @@ __global__ __launch_bounds__(kLuThreads) void k_lu(const LuTask *__restrict__ ta
         s_min = INFINITY;
         s_max = 0.0;
     }
+    for (int i = tid; i < n; i += NT) prow[i] = i;
+    __syncthreads();
     for (int kb = 0; kb < n; kb += kPanel) {
-        const int nb = n - kb < kPanel ? n - kb : kPanel;
-        // ---- panel factorization (columns kb .. kb+nb-1, rows kb .. n-1)
-        for (int k = kb; k < kb + nb; k++) {
+        const int nb = n - kb < kPanel ? n - kb : kPanel, m = n - kb;
+        // ---- panel factorization in LDS (columns kb .. kb+nb-1, rows kb .. n-1)
+        for (int e = tid; e < m * nb; e += NT) {
+            const int r = e % m, c = e / m;
+            W[e] = A[prow[kb + r] + (int64_t)(kb + c) * lda];
+        }
+        __syncthreads();
+        for (int k = 0; k < nb; k++) {
             double bv = -1.0;
             int bi = 0x7fffffff;
-            for (int i = k + tid; i < n; i += kLuThreads) argmax_abs(A[i + (int64_t)k * lda], i, bv, bi);
+            for (int r = k + tid; r < m; r += NT) argmax_abs(W[r + k * m], r, bv, bi);
             for (int o = kWave / 2; o > 0; o >>= 1) {
-                double ov = __shfl_xor(bv, o);
-                int oi = __shfl_xor(bi, o);
+                const double ov = __shfl_xor(bv, o);
+                const int oi = __shfl_xor(bi, o);
                 if (ov > bv || (ov == bv && oi < bi)) {
                     bv = ov;
                     bi = oi;
@@ -59,86 +76,85 @@ __global__ __launch_bounds__(kLuThreads) void k_lu(const LuTask *__restrict__ ta
             __syncthreads();
             int p = redi[0];
             double pv = redv[0];
-            for (int w = 1; w < kLuThreads / kWave; w++)
+            for (int w = 1; w < NW; w++)
                 if (redv[w] > pv || (redv[w] == pv && redi[w] < p)) {
                     pv = redv[w];
                     p = redi[w];
                 }
-            // exchange rows k and p inside the panel only
             if (p != k && tid < nb) {
-                int j = kb + tid;
-                double a = A[k + (int64_t)j * lda];
-                A[k + (int64_t)j * lda] = A[p + (int64_t)j * lda];
-                A[p + (int64_t)j * lda] = a;
+                const double a = W[k + tid * m];
+                W[k + tid * m] = W[p + tid * m];
+                W[p + tid * m] = a;
             }
-            if (tid == 0) t.piv[k] = p;
-            __syncthreads();
-            const double ukk = A[k + (int64_t)k * lda];
             if (tid == 0) {
-                double au = fabs(ukk);
+                sp[k] = kb + p;
+                const int x = prow[kb + k];
+                prow[kb + k] = prow[kb + p];
+                prow[kb + p] = x;
+            }
+            __syncthreads();
+            const double ukk = W[k + k * m];
+            if (tid == 0) {
+                const double au = fabs(ukk);
                 s_min = fmin(s_min, au);
                 s_max = fmax(s_max, au);
             }
-            // scale the column and update the rest of the panel
-            if (ukk != 0.0) {
-                for (int i = k + 1 + tid; i < n; i += kLuThreads) A[i + (int64_t)k * lda] /= ukk;
-            }
+            if (ukk != 0.0)
+                for (int r = k + 1 + tid; r < m; r += NT) W[r + k * m] /= ukk;
             __syncthreads();
-            const int rem = kb + nb - k - 1;
+            const int rem = nb - k - 1;
             if (ukk != 0.0 && rem > 0) {
-                const int rows = n - k - 1;
-                for (int idx = tid; idx < rows * rem; idx += kLuThreads) {
-                    int i = k + 1 + idx % rows, j = k + 1 + idx / rows;
-                    A[i + (int64_t)j * lda] -= A[i + (int64_t)k * lda] * A[k + (int64_t)j * lda];
+                const int rows = m - k - 1;
+                for (int e = tid; e < rows * rem; e += NT) {
+                    const int r = k + 1 + e % rows, j = k + 1 + e / rows;
+                    W[r + j * m] -= W[r + k * m] * W[k + j * m];
                 }
             }
             __syncthreads();
         }
-        // ---- row exchanges of this panel applied to the other columns
-        for (int j = tid; j < n; j += kLuThreads) {
-            if (j >= kb && j < kb + nb) continue;
-            for (int k = kb; k < kb + nb; k++) {
-                int p = t.piv[k];
-                if (p != k) {
-                    double a = A[k + (int64_t)j * lda];
-                    A[k + (int64_t)j * lda] = A[p + (int64_t)j * lda];
-                    A[p + (int64_t)j * lda] = a;
-                }
-            }
+        // write the factored panel back; keep L11 (unit lower) in LDS
+        for (int e = tid; e < m * nb; e += NT) {
+            const int r = e % m, c = e / m;
+            A[prow[kb + r] + (int64_t)(kb + c) * lda] = W[e];
         }
+        for (int e = tid; e < nb * nb; e += NT) {
+            const int r = e % nb, c = e / nb;
+            L11[r + c * kPanel] = W[r + c * m];
+        }
+        if (tid < nb) t.piv[kb + tid] = sp[tid];
         __syncthreads();
         const int j0 = kb + nb, nt = n - j0;
-        if (nt <= 0) break;
+        if (nt <= 0) continue;
         // ---- U block row: A[kb:kb+nb, j0:n] = L11^{-1} A[kb:kb+nb, j0:n]
-        for (int j = j0 + tid; j < n; j += kLuThreads) {
-            double u[kPanel];
+        // (solved in place in W, one column per thread)
+        for (int j = j0 + tid; j < n; j += NT) {
+            double *u = W + (j - j0);
+            for (int r = 0; r < nb; r++) u[r * n] = A[prow[kb + r] + (int64_t)j * lda];
             for (int r = 0; r < nb; r++) {
-                double acc = A[kb + r + (int64_t)j * lda];
-                for (int c = 0; c < r; c++) acc = fma(-A[kb + r + (int64_t)(kb + c) * lda], u[c], acc);
-                u[r] = acc;
-            }
-            for (int r = 0; r < nb; r++) {
-                A[kb + r + (int64_t)j * lda] = u[r];
-                Up[r * n + (j - j0)] = u[r];
+                double acc = u[r * n];
+                for (int c = 0; c < r; c++) acc = fma(-L11[r + c * kPanel], u[c * n], acc);
+                u[r * n] = acc;
+                A[prow[kb + r] + (int64_t)j * lda] = acc;
             }
         }
         if (nb < kPanel)
-            for (int idx = tid; idx < (kPanel - nb) * nt; idx += kLuThreads) Up[(nb + idx / nt) * n + idx % nt] = 0.0;
+            for (int idx = tid; idx < (kPanel - nb) * nt; idx += NT) W[(nb + idx / nt) * n + idx % nt] = 0.0;
         __syncthreads();
         // ---- trailing update A22 -= L21 U12, computed as its transpose
         // U12^T L21^T so that an accumulator register holds 16 consecutive
         // rows of a column of A22 (coalesced column-major access).  Wave w
-        // owns the 16-row stripes w, w+4, ...; its L21 stripe stays in
+        // owns the 16-row stripes w, w + NW, ...; its L21 stripe stays in
         // registers, U12 is read from LDS, four 16x16 blocks per pass.
+        const double *Up = W;
         const int bt = (nt + 15) / 16;
         const int row = lane % 16, kq = lane / 16;
-        for (int st = wave; st < bt; st += kLuThreads / kWave) {
+        for (int st = wave; st < bt; st += NW) {
             const int i0 = st * 16;
             double lb[kPanel / 4];
 #pragma unroll
             for (int kk = 0; kk < kPanel / 4; kk++) {
                 const int ii = i0 + row, k = 4 * kk + kq;
-                lb[kk] = (ii < nt && k < nb) ? A[j0 + ii + (int64_t)(kb + k) * lda] : 0.0;
+                lb[kk] = (ii < nt && k < nb) ? A[prow[j0 + ii] + (int64_t)(kb + k) * lda] : 0.0;
             }
             for (int cb0 = 0; cb0 < bt; cb0 += 4) {
                 dbl4 acc[4];
@@ -149,7 +165,7 @@ __global__ __launch_bounds__(kLuThreads) void k_lu(const LuTask *__restrict__ ta
 #pragma unroll
                     for (int r = 0; r < 4; r++) {
                         const int ci = i0 + row, cj = (cb0 + q) * 16 + 4 * r + kq;
-                        cv[q][r] = (ci < nt && cj < nt) ? A[j0 + ci + (int64_t)(j0 + cj) * lda] : 0.0;
+                        cv[q][r] = (ci < nt && cj < nt) ? A[prow[j0 + ci] + (int64_t)(j0 + cj) * lda] : 0.0;
                     }
                 }
 #pragma unroll
@@ -167,9 +183,23 @@ __global__ __launch_bounds__(kLuThreads) void k_lu(const LuTask *__restrict__ ta
 #pragma unroll
                     for (int r = 0; r < 4; r++) {
                         const int ci = i0 + row, cj = (cb0 + q) * 16 + 4 * r + kq;
-                        if (ci < nt && cj < nt) A[j0 + ci + (int64_t)(j0 + cj) * lda] = cv[q][r] - acc[q][r];
+                        if (ci < nt && cj < nt) A[prow[j0 + ci] + (int64_t)(j0 + cj) * lda] = cv[q][r] - acc[q][r];
                     }
             }
+        }
+        __syncthreads();
+    }
+    // rows in place: column batches of kPanel staged in W
+    for (int cb = 0; cb < n; cb += kPanel) {
+        const int nc = n - cb < kPanel ? n - cb : kPanel;
+        for (int e = tid; e < n * nc; e += NT) {
+            const int r = e % n, c = e / n;
+            W[e] = A[prow[r] + (int64_t)(cb + c) * lda];
+        }
+        __syncthreads();
+        for (int e = tid; e < n * nc; e += NT) {
+            const int r = e % n, c = e / n;
+            A[r + (int64_t)(cb + c) * lda] = W[e];
         }
         __syncthreads();
     }
