@@ -125,7 +125,11 @@ ROOF_TABLE = [
 # dispatch, averaged over the level launches of one step), scaled by what the
 # same counters read for a plain 1 GiB read + 1 GiB write (torch.neg).  Valid
 # only for the kernel source they were taken on: the sha256 of k_skel.hip.
-QRCP_TRAFFIC = None
+QRCP_TRAFFIC = {
+    "src_sha256": "02c6af8df939ce51d29cb04176817ca9a8b0cc18fd15ee0b0f094227666c767c",
+    "workload": (1048576, 16, 512, 256, 1024),
+    "bytes_per_launch": 11278112646.99728,
+}
 
 
 def kernel_source_sha(name):
