@@ -244,6 +244,18 @@ def main():
     T1 = time.perf_counter()
     prof = ak.askit_profile_report()
     ak.askit_profile_enable(False)
+    # the stored mixed factors applied once (no refinement): 64 right-hand
+    # sides, and one right-hand side (latency)
+    fmx.set_refinement(0, args.tol)
+    direct = {}
+    for name, Bx in (("nrhs", B), ("one_rhs", B[:, :1].contiguous())):
+        fmx.solve(Bx)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        fmx.solve(Bx)
+        torch.cuda.synchronize()
+        direct[name] = time.perf_counter() - a
+    fmx.set_refinement(args.max_refine, args.tol)
     ms_step = 1e3 * (T1 - T0) / args.steps
     t_skel = float(np.mean([r["skel"] for r in runs]))
     t_fac = float(np.mean([r["factor"] for r in runs]))
@@ -330,6 +342,8 @@ def main():
                    "N": N, "d": d, "leaf_size": m, "rank": s, "n_samples": nsamp, "nrhs": args.nrhs,
                    "precision": "mixed"},
         "skeletonize_s": t_skel, "factorize_s": t_fac, "solve_s": t_sol, "solves_per_s": args.nrhs / t_sol,
+        "direct_solve_s": direct["nrhs"], "direct_solves_per_s": args.nrhs / direct["nrhs"],
+        "one_rhs_direct_solve_s": direct["one_rhs"],
         "refinement": info, "tree_s": t_tree,
         **res,
         "skeleton_ranks_min_mean_max": rank_levels,
