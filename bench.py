@@ -115,8 +115,8 @@ ROOF_TABLE = [
     ("skel:k_sample_block", "samp", "alu", "fp64", "TFLOP/s", lambda D: D),
     ("factor:k_lu", "lu", "alu", "fp64", "TFLOP/s", lambda D: D + 1),
     ("factor:k_lusolve", "fsolve", "mfma", "fp64", "TFLOP/s", lambda D: D),
-    ("factor:k_kmm", "zblk", "mfma", "fp32", "TFLOP/s", lambda D: D),
-    ("factor:k_gmm", "tele", "mfma", "fp32", "TFLOP/s", lambda D: D - 1),
+    ("factor:k_kmm", "zblk", "mfma", "fp32", "TFLOP/s", None),
+    ("factor:k_gmm", "tele", "mfma", "fp32", "TFLOP/s", None),
     ("solve:k_lusolve", "sbytes", "hbm", None, "GB/s", lambda D: D + 1),
     ("solve:k_kmm", "skmm", "mfma", "fp32", "TFLOP/s", lambda D: D),
 ]
@@ -171,9 +171,13 @@ def main():
     ap.add_argument("--max-refine", type=int, default=10, help="GMRES-IR operator applications (mixed path)")
     ap.add_argument("--no-stable-check", action="store_true",
                     help="skip the mixed-vs-FP64 check on the N=65536 d=8 mixture (lambda=0.1)")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the timings of the other forms (batched problems, gradient, transpose solve)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB elementwise copy (reference for the HBM byte counters)")
     ap.add_argument("--tol", type=float, default=1e-11, help="target relative residual of the refined solves")
+    ap.add_argument("--qr-split-levels", type=int, default=0,
+                    help="tree levels factored by the split pivoted QR (0: library default, -1: none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built",
@@ -195,7 +199,7 @@ def main():
     torch.cuda.synchronize()
 
     t0 = time.perf_counter()
-    tree = ak.Tree(X, m, s, h, n_samples=nsamp, seed=c["seed"])
+    tree = ak.Tree(X, m, s, h, n_samples=nsamp, seed=c["seed"], qr_split_levels=args.qr_split_levels)
     torch.cuda.synchronize()
     t_tree = time.perf_counter() - t0
     log(f"[bench] tree built in {t_tree:.3f} s (depth {tree.D})")
@@ -298,7 +302,8 @@ def main():
     # roofline of every reported kernel family; the dominant one (largest
     # total time in the timed steps) is the headline
     ranks, cands = tree.skeleton_sizes()
-    cnt = algorithmic_counts(N, d, m, s, tree.D, nsamp, args.nrhs, ranks)
+    split = {0: tree.D - 1, -1: 0}.get(args.qr_split_levels, args.qr_split_levels)
+    cnt = algorithmic_counts(N, d, m, s, tree.D, nsamp, args.nrhs, ranks, split)
     rank_levels = {}
     for lvl in range(1, tree.D + 1):
         rl = ranks[(1 << lvl) - 1:(2 << lvl) - 1]
@@ -318,6 +323,9 @@ def main():
             and QRCP_TRAFFIC["workload"] == (N, d, m, s, nsamp):
         roof["traffic"] = QRCP_TRAFFIC["bytes_per_launch"]
 
+    forms = None
+    if not args.no_forms:
+        forms = forms_timings(ak, torch, dev, tree, lam, B)
     stable = None
     if not args.no_stable_check:
         stable = stable_config_check(ak, torch, dev, args.tol)
@@ -350,10 +358,82 @@ def main():
         "roofline": roof,
         "rooflines": rooflines,
         "mixed_on_stable_config": stable,
+        "forms": forms,
         "cpu_baseline": cpu,
         "kernels_ms": {k: [round(v[0] / args.steps, 3), v[1] // args.steps] for k, v in top[:12]},
     }
     print(json.dumps(out))
+
+
+def _timed(torch, fn, reps=1):
+    fn()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - a) / reps, out
+
+
+def forms_timings(ak, torch, dev, tree, lam, B):
+    """Timings of the forms beside the plain solve, each on its own workload:
+    the FP64 transpose solve and hierarchical matvecs of the 1M workload
+    (64 right-hand sides); one adjoint gradient (forward solve, transpose
+    solve, derivative matvec) on the differentiation workload (N = 262,144,
+    d = 8, h = 1, lambda = 0.05, m = 256, s = 128, 4 right-hand sides); and the
+    batched workload: 256 independent problems with N log-uniform in
+    [2048, 32768], d = 8, m = 128, s = 64, 8 right-hand sides each,
+    skeletonized together, then factorized and solved by hipGraph replays."""
+    import synth
+    out = {}
+    f = tree.factorize(lam, ak.ASKIT_FP64)
+    out["fp64_solve_transpose_s"], _ = _timed(torch, lambda: f.solve_transpose(B))
+    out["fp64_matvec_s"], _ = _timed(torch, lambda: f.matvec(B, 0))
+    out["fp64_matvec_transpose_s"], _ = _timed(torch, lambda: f.matvec(B, 2))
+    out["fp64_matvec_dh_s"], _ = _timed(torch, lambda: f.matvec(B, 1))
+    f.close()
+    # adjoint gradient
+    c = synth.config(5)
+    t5 = ak.Tree(torch.as_tensor(c["X"], device=dev), c["m"], c["s"], c["h"], seed=c["seed"])
+    t5.skeletonize()
+    B5 = torch.as_tensor(c["B"], device=dev)
+    Y5 = torch.as_tensor(c["Y"], device=dev)
+
+    def grad():
+        b = B5.clone().requires_grad_(True)
+        lt = torch.tensor(c["lam"], dtype=torch.float64, requires_grad=True)
+        ht = torch.tensor(c["h"], dtype=torch.float64, requires_grad=True)
+        x = ak.kernel_solve(b, lt, ht, t5)
+        ((x - Y5) ** 2).sum().backward()
+        return float(lt.grad)
+    out["gradient_n262144_s"], _ = _timed(torch, grad)
+    t5.close()
+    # batched problems
+    probs = synth.batched_problems()
+    trees = [ak.Tree(torch.as_tensor(p["X"], device=dev), p["m"], p["s"], p["h"], n_samples=p["nsamp"],
+                     seed=p["seed"], problem=p["problem"]) for p in probs]
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    ak.askit_skeletonize_batched(trees)
+    torch.cuda.synchronize()
+    t_skel = time.perf_counter() - a
+    a = time.perf_counter()
+    batch = ak.Batch(trees, [p["lam"] for p in probs], ak.ASKIT_FP64, nrhs=8)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - a
+    Bs = [torch.as_tensor(p["B"], device=dev) for p in probs]
+    t_fac, _ = _timed(torch, batch.factorize, reps=3)
+    t_sol, _ = _timed(torch, lambda: batch.solve(Bs), reps=3)
+    ratio, worst = batch.check()
+    out["batched"] = {"problems": len(probs), "points": int(sum(len(p["X"]) for p in probs)),
+                      "skeletonize_s": t_skel, "plan_and_capture_s": t_create, "factorize_graph_s": t_fac,
+                      "solve_graph_s": t_sol, "factorizations_per_s": len(probs) / t_fac,
+                      "min_pivot_ratio": ratio}
+    log(f"[bench] forms: {out}")
+    batch.close()
+    for t in trees:
+        t.close()
+    return out
 
 
 def stable_config_check(ak, torch, dev, tol):

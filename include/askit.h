@@ -59,7 +59,8 @@ typedef struct askit_factor_s *askit_factor;
  * qr_split_levels chooses the launch shape of the pivoted QR, not its
  * result: nodes at tree levels 1 .. L are factored by several workgroups
  * each, one launch per pivot step, the deeper ones by one workgroup each
- * (0 -> L = 6, -1 -> none).  Both shapes give bit-identical skeletons. */
+ * (0 -> L = D - 1, every internal level; -1 -> none).  Both shapes give
+ * bit-identical skeletons. */
 typedef struct {
     int32_t leaf_size;
     int32_t rank;
@@ -143,7 +144,11 @@ askit_status askit_matvec(askit_factor f, int32_t which, const double *X, int64_
 
 /* Refinement controls: max_refine = largest number of preconditioned
  * operator applications (0 = plain direct solve; defaults: MIXED 100, FP64 0),
- * refine_tol = target relative residual (default 1e-11). */
+ * refine_tol = target relative residual (default 1e-11).  The refinement
+ * also stops when it stagnates: a restart cycle ends once four Arnoldi steps
+ * gain less than 5% in the estimated residual, and the refinement ends once
+ * a cycle fails to halve the true residual (askit_last_solve_info then
+ * reports converged = 0 with the residual reached). */
 askit_status askit_set_refinement(askit_factor f, int32_t max_refine, double refine_tol);
 
 typedef struct {

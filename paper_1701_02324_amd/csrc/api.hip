@@ -448,10 +448,9 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 // ---------------------------------------------------------------------------
 // handles
 // ---------------------------------------------------------------------------
-// Tree levels 1 .. kSplitLevels (at most 64 nodes per tree) run the split
-// QRCP by default (several workgroups per node, one launch per pivot step);
-// deeper levels run one workgroup per node.  Both give identical skeletons.
-static const int kSplitLevels = 6;
+// By default the internal levels run the split QRCP (several workgroups per
+// node, one launch per pivot step) and the leaves, the widest level, one
+// workgroup per node.  Both give identical skeletons.
 
 struct askit_tree_s {
     int64_t N = 0;
@@ -559,13 +558,14 @@ askit_status askit_build_tree(const double *X, int64_t N, int32_t d, const askit
     t->m = opt->leaf_size;
     t->s = opt->rank;
     t->nsamp = opt->n_samples ? opt->n_samples : 4 * opt->rank;
-    t->split_levels = opt->qr_split_levels == 0 ? kSplitLevels : std::max(0, opt->qr_split_levels);
+
     t->seed = opt->seed;
     t->problem = opt->problem;
     t->h = opt->h;
     t->hfac = opt->h;
     while ((int64_t)t->m * ((int64_t)1 << t->D) < N) t->D++;
     t->nnodes = ((int64_t)2 << t->D) - 1;
+    t->split_levels = opt->qr_split_levels == 0 ? t->D - 1 : std::max(0, opt->qr_split_levels);
     t->mmax = (int)cdiv(N, (int64_t)1 << t->D);
     t->cmax = std::max(t->mmax, 2 * t->s);
     if (t->mmax > 512 || 2 * t->s > 512)
@@ -1812,7 +1812,7 @@ static askit_status gmres_refine(askit_factor f, const double *B, int64_t ldb, i
     HIP_TRY(hipMemcpyAsync(Bc, R, need, hipMemcpyDeviceToDevice, st));
     ST_TRY(apply_inverse(f, B, ldb, nrhs, X, ldx, trans, st));
     int it = 0;
-    double res = INFINITY, res0 = -1.0;
+    double res = INFINITY, res0 = -1.0, prev = INFINITY;
     std::vector<double> H((size_t)nrhs * (m + 1) * m), g((size_t)nrhs * (m + 1)), cs((size_t)nrhs * m),
         sn((size_t)nrhs * m), sc(nrhs), y;
     while (true) {
@@ -1829,6 +1829,11 @@ static askit_status gmres_refine(askit_factor f, const double *B, int64_t ldb, i
         }
         if (res0 < 0) res0 = res;
         if (res <= f->refine_tol || it >= f->max_refine) break;
+        // stagnation: a restart cycle that did not halve the true residual
+        // ends the refinement (rounding floor reached, or a preconditioner
+        // too far from the operator)
+        if (res > 0.5 * prev) break;
+        prev = res;
         // Arnoldi with the last Krylov slot kept for b: at most m - 1 steps
         const int mm = m - 1;
         for (int c = 0; c < nrhs; c++) sc[c] = rn[c] > 0 ? 1.0 / rn[c] : 0.0;
@@ -1837,6 +1842,7 @@ static askit_status gmres_refine(askit_factor f, const double *B, int64_t ldb, i
         std::fill(g.begin(), g.end(), 0.0);
         for (int c = 0; c < nrhs; c++) g[(size_t)c * (m + 1)] = rn[c];
         int used = 0;
+        std::vector<double> est;  // estimated residual after each Arnoldi step
         for (int j = 0; j < mm && it < f->max_refine; j++) {
             double *Vj = V + (size_t)j * NR, *W = R;
             ST_TRY(apply_inverse(f, Vj, N, nrhs, Z, N, trans, st));
@@ -1881,6 +1887,9 @@ static askit_status gmres_refine(askit_factor f, const double *B, int64_t ldb, i
                 worst = std::max(worst, std::fabs(gc[j + 1]) / bn[c]);
             }
             if (worst <= 0.5 * f->refine_tol) break;
+            // the cycle stalls when four steps gain less than 5%
+            est.push_back(worst);
+            if (est.size() >= 5 && worst > 0.95 * est[est.size() - 5]) break;
         }
         if (used == 0) break;
         // x += Ahat^{-1} V y
