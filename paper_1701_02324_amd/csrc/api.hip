@@ -366,14 +366,17 @@ askit_status gmm_commit(Plan &P, GmmBuild &gb, Prec t, int rows_red_max) {
     return ASKIT_OK;
 }
 
-askit_status lu_commit(Plan &P, const std::vector<LuTask> &v) {
+// spd: every matrix is symmetric positive definite (factored without row
+// exchanges)
+askit_status lu_commit(Plan &P, const std::vector<LuTask> &v, bool spd = false) {
     if (v.empty()) return ASKIT_OK;
     DBuf *b = P.own();
     ST_TRY(upload(*b, v));
     const LuTask *tp = b->as<LuTask>();
     const int n = (int)v.size();
     P.add("k_lu", [=](hipStream_t st, int) -> hipError_t {
-        hipLaunchKernelGGL(k_lu, dim3(n), dim3(kLuFThreads), 0, st, tp);
+        if (spd) hipLaunchKernelGGL(k_lu_nopiv, dim3(n), dim3(kLuFThreads), 0, st, tp);
+        else hipLaunchKernelGGL(k_lu, dim3(n), dim3(kLuFThreads), 0, st, tp);
         return hipGetLastError();
     });
     P.add("k_lu_diaginv", [=](hipStream_t st, int) -> hipError_t {
@@ -1001,7 +1004,10 @@ static askit_status factor_plan(const std::vector<askit_factor> &fs, Plan &P) {
                                lp, tl, d);
             return hipGetLastError();
         });
-        ST_TRY(lu_commit(P, lu));
+        // lambda I + K_aa is symmetric positive definite for lambda > 0
+        bool spd = true;
+        for (auto f : fs) spd = spd && f->lambda > 0.0;
+        ST_TRY(lu_commit(P, lu, spd));
         ST_TRY(copy_commit(P, cp, P64, pr, mmax, s));
         ST_TRY(getrs_commit(P, rs, pr, false, s));
     }

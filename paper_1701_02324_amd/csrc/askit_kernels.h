@@ -40,6 +40,7 @@ __global__ void k_qs_finish(const SkelTask *tasks, QrWork w, int s, int ldm);
 
 // LU (k_lu.hip)
 __global__ void k_lu(const LuTask *tasks);
+__global__ void k_lu_nopiv(const LuTask *tasks);
 __global__ void k_lu_diaginv(const LuTask *tasks);
 template <typename T, int NR, bool TRANS>
 __global__ void k_lusolve(const LuTask *tasks, int ntask, int nrhs, int panels);

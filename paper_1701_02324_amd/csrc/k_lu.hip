@@ -207,6 +207,190 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu(const LuTask *__restrict__ t
 }
 
 // ---------------------------------------------------------------------------
+// LU without row exchanges for symmetric positive definite matrices (the leaf
+// blocks lambda I + K_aa, lambda > 0): elimination without pivoting is
+// backward stable there and gives the factors GETRF gives whenever it
+// exchanges no rows.  Blocked by 32 columns: the diagonal block is factored
+// by one wave with its rows in registers (pivot rows shared by lane
+// shuffles); its triangles are inverted in LDS; L21 = A21 U11^{-1} and
+// U12 = L11^{-1} A12 are products on FP64 MFMA; the trailing update is the
+// one of k_lu.  piv[k] = k.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kLuFThreads) void k_lu_nopiv(const LuTask *__restrict__ tasks) {
+    constexpr int NT = kLuFThreads, NW = NT / kWave, DL = kPanel + 1;
+    __shared__ double Up[kPanel * kLuMaxN];  // U block row (row-major, ld = n)
+    __shared__ double Dg[kPanel * DL];       // factored diagonal block (row-major)
+    __shared__ double LI[kPanel * DL];       // L11^{-1} (row-major)
+    __shared__ double UI[kPanel * DL];       // U11^{-1} (row-major)
+    __shared__ double s_min, s_max;
+    const LuTask t = tasks[blockIdx.x];
+    const int n = t.n, lda = t.lda, tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    double *A = t.A;
+    if (tid == 0) {
+        s_min = INFINITY;
+        s_max = 0.0;
+    }
+    for (int i = tid; i < n; i += NT) t.piv[i] = i;
+    for (int kb = 0; kb < n; kb += kPanel) {
+        const int nb = n - kb < kPanel ? n - kb : kPanel;
+        // ---- diagonal block, factored in LDS by wave 0: lane i < nb owns
+        // row i; the pivot row k is final once step k - 1 has ended, and the
+        // wave-scope fences order each step's row updates before the next
+        // step's reads
+        if (wave == 0) {
+            if (lane < kPanel)
+                for (int j = 0; j < kPanel; j++)
+                    Dg[lane * DL + j] = (lane < nb && j < nb) ? A[kb + lane + (int64_t)(kb + j) * lda]
+                                                              : (lane == j ? 1.0 : 0.0);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll 1
+            for (int k = 0; k < nb; k++) {
+                if (lane > k && lane < nb) {
+                    const double ukk = Dg[k * DL + k];
+                    const double l = ukk != 0.0 ? Dg[lane * DL + k] / ukk : 0.0;
+                    Dg[lane * DL + k] = l;
+                    for (int j = k + 1; j < nb; j++) Dg[lane * DL + j] = fma(-l, Dg[k * DL + j], Dg[lane * DL + j]);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            if (lane < nb)
+                for (int j = 0; j < nb; j++) A[kb + lane + (int64_t)(kb + j) * lda] = Dg[lane * DL + j];
+        }
+        __syncthreads();
+        // ---- inverses of the triangles (column j of U^{-1}: thread j; of
+        // L^{-1}: thread 64 + j), pivot magnitudes
+        if (tid < kPanel) {
+            const int j = tid;
+#pragma unroll 1
+            for (int i = kPanel - 1; i >= 0; i--) {
+                double acc = i == j ? 1.0 : 0.0;
+                if (i < j)
+#pragma unroll 1
+                    for (int k = i + 1; k <= j; k++) acc = fma(-Dg[i * DL + k], UI[k * DL + j], acc);
+                const double u = Dg[i * DL + i];
+                UI[i * DL + j] = i > j ? 0.0 : (u != 0.0 ? acc / u : 0.0);
+            }
+        } else if (tid >= kWave && tid < kWave + kPanel) {
+            const int j = tid - kWave;
+#pragma unroll 1
+            for (int i = 0; i < kPanel; i++) {
+                double acc = i == j ? 1.0 : 0.0;
+                if (i > j)
+#pragma unroll 1
+                    for (int k = j; k < i; k++) acc = fma(-Dg[i * DL + k], LI[k * DL + j], acc);
+                LI[i * DL + j] = i < j ? 0.0 : acc;
+            }
+        } else if (tid == 2 * kWave) {
+            for (int i = 0; i < nb; i++) {
+                const double au = fabs(Dg[i * DL + i]);
+                s_min = fmin(s_min, au);
+                s_max = fmax(s_max, au);
+            }
+        }
+        __syncthreads();
+        const int j0 = kb + nb, nt = n - j0;
+        if (nt <= 0) continue;  // only the last panel can be narrower than kPanel
+        const int rr = lane % 16, kq = lane / 16;
+        // ---- L21 = A21 U11^{-1}, 16-row stripes
+#pragma unroll 1
+        for (int st = wave; st < (nt + 15) / 16; st += NW) {
+            const int i0 = st * 16;
+            dbl4 acc[2] = {dbl4{0, 0, 0, 0}, dbl4{0, 0, 0, 0}};
+            double a[kPanel / 4];
+#pragma unroll
+            for (int kk = 0; kk < kPanel / 4; kk++)
+                a[kk] = i0 + rr < nt ? A[j0 + i0 + rr + (int64_t)(kb + 4 * kk + kq) * lda] : 0.0;
+#pragma unroll
+            for (int kk = 0; kk < kPanel / 4; kk++)
+#pragma unroll
+                for (int cb = 0; cb < 2; cb++)
+                    acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], UI[(4 * kk + kq) * DL + cb * 16 + rr],
+                                                                   acc[cb], 0, 0, 0);
+#pragma unroll
+            for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const int r = i0 + 4 * q + kq;
+                    if (r < nt) A[j0 + r + (int64_t)(kb + cb * 16 + rr) * lda] = acc[cb][q];
+                }
+        }
+        // ---- U12 = L11^{-1} A12, 16-column blocks (also staged in Up)
+#pragma unroll 1
+        for (int cbk = wave; cbk < (nt + 15) / 16; cbk += NW) {
+            const int c0 = cbk * 16;
+            dbl4 acc[2] = {dbl4{0, 0, 0, 0}, dbl4{0, 0, 0, 0}};
+            double b[kPanel / 4];
+#pragma unroll
+            for (int kk = 0; kk < kPanel / 4; kk++)
+                b[kk] = c0 + rr < nt ? A[kb + 4 * kk + kq + (int64_t)(j0 + c0 + rr) * lda] : 0.0;
+#pragma unroll
+            for (int kk = 0; kk < kPanel / 4; kk++)
+#pragma unroll
+                for (int rb = 0; rb < 2; rb++)
+                    acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(LI[(rb * 16 + rr) * DL + 4 * kk + kq], b[kk],
+                                                                   acc[rb], 0, 0, 0);
+#pragma unroll
+            for (int rb = 0; rb < 2; rb++)
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const int r = rb * 16 + 4 * q + kq, c = c0 + rr;
+                    if (c < nt) {
+                        A[kb + r + (int64_t)(j0 + c) * lda] = acc[rb][q];
+                        Up[r * n + c] = acc[rb][q];
+                    }
+                }
+        }
+        __syncthreads();
+        // ---- trailing update A22 -= L21 U12 (as in k_lu)
+        const int bt = (nt + 15) / 16;
+#pragma unroll 1
+        for (int st = wave; st < bt; st += NW) {
+            const int i0 = st * 16;
+            double lb[kPanel / 4];
+#pragma unroll
+            for (int kk = 0; kk < kPanel / 4; kk++) {
+                const int ii = i0 + rr, k = 4 * kk + kq;
+                lb[kk] = ii < nt ? A[j0 + ii + (int64_t)(kb + k) * lda] : 0.0;
+            }
+#pragma unroll 1
+            for (int cb0 = 0; cb0 < bt; cb0 += 4) {
+                dbl4 acc[4];
+                double cv[4][4];
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    acc[q] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        const int ci = i0 + rr, cj = (cb0 + q) * 16 + 4 * r + kq;
+                        cv[q][r] = (ci < nt && cj < nt) ? A[j0 + ci + (int64_t)(j0 + cj) * lda] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int kk = 0; kk < kPanel / 4; kk++) {
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const int cj = (cb0 + q) * 16 + rr;
+                        const double ua = cj < nt ? Up[(4 * kk + kq) * n + cj] : 0.0;
+                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua, lb[kk], acc[q], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        const int ci = i0 + rr, cj = (cb0 + q) * 16 + 4 * r + kq;
+                        if (ci < nt && cj < nt) A[j0 + ci + (int64_t)(j0 + cj) * lda] = cv[q][r] - acc[q][r];
+                    }
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && t.ratio) *t.ratio = n ? (s_max > 0.0 ? s_min / s_max : 0.0) : 1.0;
+}
+
+// ---------------------------------------------------------------------------
 // Inverses of the 16 x 16 diagonal blocks of L (unit lower) and U, used by the
 // blocked triangular solves: Dinv[2b] = L_bb^{-1}, Dinv[2b+1] = U_bb^{-1}
 // (column-major 16 x 16; a partial last block is completed by the identity).
