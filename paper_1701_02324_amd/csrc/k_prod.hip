@@ -90,18 +90,39 @@ __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, 
     typename Acc<T>::type acc[NB];
     for (int b = 0; b < NB; b++) acc[b] = typename Acc<T>::type{0, 0, 0, 0};
     const TB *B = (const TB *)t.B;
+    // the next stage's contraction points and B rows are fetched into
+    // registers while the current stage is generated and multiplied
+    constexpr int PS = kKS * kMaxDim / 256, PB = kKS * TC / 256;
+    T pS[PS], pB[PB];
+    auto fetch = [&](int ks) {
+        const int kn = min(kKS, k1 - ks);
+#pragma unroll
+        for (int u = 0; u < PS; u++) {
+            const int i = tid + u * 256, r = i / d, k = i % d;
+            pS[u] = (i < kKS * d && r < kn) ? (T)t.X[src_pos(t.S, ks + r) * d + k] : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < PB; u++) {
+            const int i = tid + u * 256, k = i / TC, c = i % TC;
+            pB[u] = (k < kn && c0 + c < ncol) ? (T)B[(int64_t)(ks - t.k0 + k) * t.ldb + c0 + c] : (T)0;
+        }
+    };
+    if (t.k0 < k1) fetch(t.k0);
     for (int ks = t.k0; ks < k1; ks += kKS) {
         const int kn = min(kKS, k1 - ks);
         __syncthreads();
-        for (int i = tid; i < kKS * d; i += 256) {
-            int r = i / d, k = i % d;
-            sS[i] = r < kn ? (T)t.X[src_pos(t.S, ks + r) * d + k] : (T)0;
+#pragma unroll
+        for (int u = 0; u < PS; u++) {
+            const int i = tid + u * 256;
+            if (i < kKS * d) sS[i] = pS[u];
         }
-        for (int i = tid; i < kKS * TC; i += 256) {
-            int k = i / TC, c = i % TC;
-            sB[k][c] = (k < kn && c0 + c < ncol) ? (T)B[(int64_t)(ks - t.k0 + k) * t.ldb + c0 + c] : (T)0;
+#pragma unroll
+        for (int u = 0; u < PB; u++) {
+            const int i = tid + u * 256;
+            sB[i / TC][i % TC] = pB[u];
         }
         __syncthreads();
+        if (ks + kKS < k1) fetch(ks + kKS);
         // generate the kernel tile: 64 x 16 entries, 4 per thread
         for (int i = tid; i < kTR * kKS; i += 256) {
             int r = i % kTR, k = i / kTR;
@@ -160,22 +181,50 @@ __global__ __launch_bounds__(256) void k_gmm(const GmmTask *__restrict__ tasks, 
     const bool a_kfast = (t.acs == 1), b_cfast = (t.bcs == 1);
     typename Acc<T>::type acc[NB];
     for (int b = 0; b < NB; b++) acc[b] = typename Acc<T>::type{0, 0, 0, 0};
-    for (int ks = kb; ks < ke; ks += kKS) {
+    // the next stage's A and B tiles are fetched into registers while the
+    // current stage is multiplied
+    constexpr int PA = kTR * kKS / 256, PB = kKS * TC / 256;
+    T pA[PA], pB[PB];
+    auto fetch = [&](int ks) {
         const int kn = min(kKS, ke - ks);
-        __syncthreads();
-        for (int i = tid; i < kTR * kKS; i += 256) {
+#pragma unroll
+        for (int u = 0; u < PA; u++) {
+            const int i = tid + u * 256;
             int r, k;
             if (a_kfast) { r = i / kKS; k = i % kKS; }
             else { r = i % kTR; k = i / kTR; }
-            sA[r][k] = (k < kn && r0 + r < t.rows) ? A[(int64_t)(r0 + r) * t.ars + (int64_t)(ks + k) * t.acs] : (T)0;
+            pA[u] = (k < kn && r0 + r < t.rows) ? A[(int64_t)(r0 + r) * t.ars + (int64_t)(ks + k) * t.acs] : (T)0;
         }
-        for (int i = tid; i < kKS * TC; i += 256) {
+#pragma unroll
+        for (int u = 0; u < PB; u++) {
+            const int i = tid + u * 256;
             int k, c;
             if (b_cfast) { k = i / TC; c = i % TC; }
             else { k = i % kKS; c = i / kKS; }
-            sB[k][c] = (k < kn && c0 + c < ncol) ? B[(int64_t)(ks + k) * t.brs + (int64_t)(c0 + c) * t.bcs] : (T)0;
+            pB[u] = (k < kn && c0 + c < ncol) ? B[(int64_t)(ks + k) * t.brs + (int64_t)(c0 + c) * t.bcs] : (T)0;
+        }
+    };
+    if (kb < ke) fetch(kb);
+    for (int ks = kb; ks < ke; ks += kKS) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PA; u++) {
+            const int i = tid + u * 256;
+            int r, k;
+            if (a_kfast) { r = i / kKS; k = i % kKS; }
+            else { r = i % kTR; k = i / kTR; }
+            sA[r][k] = pA[u];
+        }
+#pragma unroll
+        for (int u = 0; u < PB; u++) {
+            const int i = tid + u * 256;
+            int k, c;
+            if (b_cfast) { k = i / TC; c = i % TC; }
+            else { k = i % kKS; c = i / kKS; }
+            sB[k][c] = pB[u];
         }
         __syncthreads();
+        if (ks + kKS < ke) fetch(ks + kKS);
 #pragma unroll
         for (int k4 = 0; k4 < kKS; k4 += 4) {
             T a = sA[wave * 16 + lane % 16][k4 + lane / 16];
