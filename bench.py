@@ -61,7 +61,8 @@ def algorithmic_counts(N, d, m, s, D, nsamp, nrhs, ranks=None, split_levels=6):
                           split form (skel:k_qrcp_split), the rest for k_qrcp
       skel:k_sample_block 3d + 1 flops per sampled kernel entry (difference,
                           fma, exp counted as one), nodes with c > s only
-      factor:k_lu         (2/3) n^3 per LU (leaf n = m, internal n = s_l + s_r)
+      factor:k_lu_nopiv   (2/3) m^3 per leaf LU (no row exchanges)
+      factor:k_lu         (2/3) n^3 per Z LU (n = s_l + s_r, partial pivoting)
       factor:k_lusolve    2 n^2 s_a (leaf Phat, internal Z^-1 P_c below the root)
       factor:k_kmm        2 s_l n_r s_r + 2 s_r n_l s_l per internal node (eq. (8))
       factor:k_gmm        2 (n_l s_l + n_r s_r) s_a per internal non-root node
@@ -74,7 +75,8 @@ def algorithmic_counts(N, d, m, s, D, nsamp, nrhs, ranks=None, split_levels=6):
     sz = node_sizes(N, D)
     r = np.full(nn, s, dtype=np.int64) if ranks is None else np.asarray(ranks, dtype=np.int64)
     first_leaf = (1 << D) - 1
-    c = {k: 0.0 for k in ("qr", "qr1", "qrs", "samp", "lu", "fsolve", "zblk", "tele", "sbytes", "sflops", "skmm")}
+    c = {k: 0.0 for k in ("qr", "qr1", "qrs", "samp", "lu", "lu_leaf", "lu_z", "fsolve", "zblk", "tele", "sbytes",
+                          "sflops", "skmm")}
     for i in range(nn):
         n = float(sz[i])
         leaf = i >= first_leaf
@@ -89,6 +91,7 @@ def algorithmic_counts(N, d, m, s, D, nsamp, nrhs, ranks=None, split_levels=6):
                 c["samp"] += rows * cols * (3.0 * d + 1)
         nlu = n if leaf else float(r[2 * i + 1] + r[2 * i + 2])
         c["lu"] += (2.0 / 3.0) * nlu ** 3
+        c["lu_leaf" if leaf else "lu_z"] += (2.0 / 3.0) * nlu ** 3
         if i > 0:
             c["fsolve"] += 2.0 * nlu * nlu * r[i]
         c["sflops"] += 2.0 * nlu * nlu * nrhs
@@ -113,7 +116,8 @@ ROOF_TABLE = [
     ("skel:k_qrcp", "qr1", "alu", "fp64", "TFLOP/s", None),
     ("skel:k_qrcp_split", "qrs", "alu", "fp64", "TFLOP/s", None),
     ("skel:k_sample_block", "samp", "alu", "fp64", "TFLOP/s", lambda D: D),
-    ("factor:k_lu", "lu", "alu", "fp64", "TFLOP/s", lambda D: D + 1),
+    ("factor:k_lu_nopiv", "lu_leaf", "mfma", "fp64", "TFLOP/s", lambda D: 1),
+    ("factor:k_lu", "lu_z", "alu", "fp64", "TFLOP/s", lambda D: D),
     ("factor:k_lusolve", "fsolve", "mfma", "fp64", "TFLOP/s", lambda D: D),
     ("factor:k_kmm", "zblk", "mfma", "fp32", "TFLOP/s", None),
     ("factor:k_gmm", "tele", "mfma", "fp32", "TFLOP/s", None),
@@ -121,15 +125,12 @@ ROOF_TABLE = [
     ("solve:k_kmm", "skmm", "mfma", "fp32", "TFLOP/s", lambda D: D),
 ]
 
-# HBM bytes of k_qrcp from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (KiB per
-# dispatch, averaged over the level launches of one step), scaled by what the
-# same counters read for a plain 1 GiB read + 1 GiB write (torch.neg).  Valid
-# only for the kernel source they were taken on: the sha256 of k_skel.hip.
-QRCP_TRAFFIC = {
-    "src_sha256": "02c6af8df939ce51d29cb04176817ca9a8b0cc18fd15ee0b0f094227666c767c",
-    "workload": (1048576, 16, 512, 256, 1024),
-    "bytes_per_launch": 11278112646.99728,
-}
+# HBM bytes per launch of single kernels, from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch, averaged over the launches of one step),
+# scaled by what the same counters read for a plain 1 GiB read + 1 GiB write
+# (torch.neg).  Valid only for the kernel source they were taken on (sha256 of
+# the file) and for this workload; otherwise "traffic" is null.
+TRAFFIC = {}
 
 
 def kernel_source_sha(name):
@@ -316,12 +317,14 @@ def main():
     # the headline is the kernel that dominates the metric's value (the
     # skeletonize + factorize time)
     top = sorted(prof.items(), key=lambda kv: -kv[1][0])
-    dom = next((k for k, _ in top if k in rooflines and k.split(":")[0] in ("skel", "factor")), None)
+    # (single kernels only: the split QR family is a sequence of launches)
+    dom = next((k for k, _ in top if k in rooflines and k.split(":")[0] in ("skel", "factor")
+                and k != "skel:k_qrcp_split"), None)
     roof = dict(rooflines[dom]) if dom else None
-    if roof is not None and dom == "skel:k_qrcp" and QRCP_TRAFFIC is not None \
-            and QRCP_TRAFFIC["src_sha256"] == kernel_source_sha("k_skel.hip") \
-            and QRCP_TRAFFIC["workload"] == (N, d, m, s, nsamp):
-        roof["traffic"] = QRCP_TRAFFIC["bytes_per_launch"]
+    tr = TRAFFIC.get(dom) if dom else None
+    if roof is not None and tr is not None and tr["src_sha256"] == kernel_source_sha(tr["source"]) \
+            and tr["workload"] == (N, d, m, s, nsamp):
+        roof["traffic"] = tr["bytes_per_launch"]
 
     forms = None
     if not args.no_forms:

@@ -374,7 +374,7 @@ askit_status lu_commit(Plan &P, const std::vector<LuTask> &v, bool spd = false) 
     ST_TRY(upload(*b, v));
     const LuTask *tp = b->as<LuTask>();
     const int n = (int)v.size();
-    P.add("k_lu", [=](hipStream_t st, int) -> hipError_t {
+    P.add(spd ? "k_lu_nopiv" : "k_lu", [=](hipStream_t st, int) -> hipError_t {
         if (spd) hipLaunchKernelGGL(k_lu_nopiv, dim3(n), dim3(kLuFThreads), 0, st, tp);
         else hipLaunchKernelGGL(k_lu, dim3(n), dim3(kLuFThreads), 0, st, tp);
         return hipGetLastError();
@@ -813,7 +813,7 @@ static askit_status skeletonize_impl(askit_tree *trees, int count, hipStream_t s
             ST_TRY(wnrm.alloc(sizeof(double) * (size_t)nsp * 2 * cmax));
             ST_TRY(wpos.alloc(sizeof(int32_t) * (size_t)nsp * 2 * cmax));
             ST_TRY(wdiag.alloc(sizeof(double) * (size_t)nsp * cmax));
-            ST_TRY(wst.alloc(sizeof(int32_t) * (size_t)nsp * 4));
+            ST_TRY(wst.alloc(sizeof(int32_t) * (size_t)nsp * kQsState));
             w.part = wpart.as<double>();
             w.rmap = wrmap.as<int32_t>();
             w.rows = wrows.as<int32_t>();

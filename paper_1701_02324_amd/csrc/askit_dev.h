@@ -13,6 +13,7 @@ constexpr int kTreeChunk = 256;  // positions per chunk of the tree reductions
 constexpr int kPowerIters = 50;  // power iterations for the principal axis
 constexpr double kRankGuard = 1e-14;
 constexpr int kQsCols = 8;       // columns per workgroup of the split QRCP
+constexpr int kQsState = 8;      // ints of per-node state of the split QRCP
 constexpr int kLsThreads = 1024; // batched LU solves: 16 waves keep many block loads in flight
 constexpr int kLuFThreads = 512; // batched LU factorization
 
@@ -153,10 +154,10 @@ struct QrWork {
     double *part;      // slices x rcap partial squared row norms per node
     int32_t *rmap;     // rcap: new row index or -1
     int32_t *rows;     // 1: kept rows, then rows in use
-    double *nrm;       // 2 x cmax squared trailing norms (buffers by step parity)
-    int32_t *pos;      // 2 x cmax pivot order (buffers by step parity)
+    double *nrm;       // 2 x cmax squared trailing norms by pivot position (buffers by step parity)
+    int32_t *pos;      // 2 x cmax pivot order: column at each position (buffers by step parity)
     double *diag;      // cmax: R_jj
-    int32_t *st;       // 4: stopped, stop step, zero block, steps
+    int32_t *st;       // kQsState: stopped, stop step, zero block, steps, rows, candidates
     int32_t cmax, rcap, slices, pad;
 };
 

@@ -620,7 +620,9 @@ __global__ __launch_bounds__(kQrThreads) void k_qs_rowmap(const SkelTask *__rest
     if (threadIdx.x == 0) w.rows[node] = kept;
 }
 
-// compaction of the group's columns, initial norms, pivot order and state
+// compaction of the group's columns, initial norms, pivot order and state.
+// From here on a workgroup owns pivot positions (not columns): norms are kept
+// by position and the column at a position is read from the pivot order.
 __global__ __launch_bounds__(kQsThreads) void k_qs_init(const SkelTask *__restrict__ tasks, QrWork w, int s,
                                                          int ldm) {
     const int node = blockIdx.x / w.slices, slice = blockIdx.x % w.slices;
@@ -630,65 +632,90 @@ __global__ __launch_bounds__(kQsThreads) void k_qs_init(const SkelTask *__restri
     const int rows = kept < t.nq ? (kept > 0 ? kept : 1) : t.nq;  // as in k_qrcp
     const int32_t *rmap = w.rmap + (int64_t)node * w.rcap;
     double *nrm = w.nrm + (int64_t)node * 2 * w.cmax;
+    int32_t *pos = w.pos + (int64_t)node * 2 * w.cmax;
     for (int q = 0; q < 2; q++) {
         const int c = slice * kQsCols + 2 * wave + q;
         if (c >= ncand) continue;
         double *col = t.M + (int64_t)c * ldm;
         if (kept < t.nq) compact_col(col, rmap, t.nq, lane);
         const double v = col_norm(col, rows, lane);
-        if (lane == 0) nrm[c] = v;
-    }
-    if (slice == 0) {
-        int32_t *pos = w.pos + (int64_t)node * 2 * w.cmax;
-        for (int k = tid; k < ncand; k += kQsThreads) pos[k] = k;
-        if (tid == 0) {
-            int32_t *st = w.st + 4 * node;
-            st[0] = 0;
-            st[1] = 0;
-            st[2] = 0;
-            st[3] = s < rows ? s : rows;
+        if (lane == 0) {
+            nrm[c] = v;
+            pos[c] = c;
         }
+    }
+    if (slice == 0 && tid == 0) {
+        int32_t *st = w.st + kQsState * node;
+        st[0] = 0;
+        st[1] = 0;
+        st[2] = 0;
+        st[3] = s < rows ? s : rows;
+        st[4] = rows;
+        st[5] = ncand;
     }
 }
 
-// pivot step j: every workgroup of a node picks the same pivot and builds the
-// same reflector from the state of step j - 1 (norms and positions in the
-// buffer j % 2), then updates its own trailing columns into the other buffer
+// pivot step j: every workgroup of a node picks the same pivot (largest norm
+// over positions j .., lowest position on ties) and builds the same
+// reflector from the state of step j - 1 (buffers j % 2), then updates the
+// columns at its own positions > j into the other buffers
 __global__ __launch_bounds__(kQsThreads) void k_qs_step(const SkelTask *__restrict__ tasks, QrWork w, int j,
                                                          int ldm) {
     __shared__ double vh[kQrMaxRows];
-    __shared__ int32_t s_k, s_stop;
+    __shared__ int32_t s_k, s_p, s_stop;
     __shared__ double s_tau;
     const int node = blockIdx.x / w.slices, slice = blockIdx.x % w.slices;
-    int32_t *st = w.st + 4 * node;
-    if (st[0] || j >= st[3]) return;
-    const SkelTask t = tasks[node];
+    const int32_t *st = w.st + kQsState * node;
+    const int stopped = st[0], steps = st[3], rows = st[4], ncand = st[5];
+    double *M = tasks[node].M;
+    if (stopped || j >= steps) return;
+    const int q0 = slice * kQsCols;
+    if (q0 >= ncand) return;
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
-    const int ncand = node_ncand(t), kept = w.rows[node];
-    const int rows = kept < t.nq ? (kept > 0 ? kept : 1) : t.nq;
-    if (slice * kQsCols >= ncand) return;
     const double *nin = w.nrm + (int64_t)node * 2 * w.cmax + (int64_t)(j & 1) * w.cmax;
     double *nout = w.nrm + (int64_t)node * 2 * w.cmax + (int64_t)((j + 1) & 1) * w.cmax;
     const int32_t *pin = w.pos + (int64_t)node * 2 * w.cmax + (int64_t)(j & 1) * w.cmax;
     int32_t *pout = w.pos + (int64_t)node * 2 * w.cmax + (int64_t)((j + 1) & 1) * w.cmax;
     double *Rjj = w.diag + (int64_t)node * w.cmax;
+    // this wave's positions and their columns (read early)
+    const int qa = q0 + 2 * wave, qb = qa + 1;
+    const int ca = qa < ncand ? pin[qa] : -1, cb = qb < ncand ? pin[qb] : -1;
     if (wave == 0) {
-        const int k = pick_pivot(nin, pin, j, ncand, lane);
-        const double *x = t.M + (int64_t)pin[k] * ldm;
+        double bv = -1.0;
+        int bk = 0x7fffffff;
+        for (int k = j + lane; k < ncand; k += kWave) {
+            const double v = nin[k];
+            if (v > bv || (v == bv && k < bk)) {
+                bv = v;
+                bk = k;
+            }
+        }
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(bv, o);
+            const int ok = __shfl_xor(bk, o);
+            if (ov > bv || (ov == bv && ok < bk)) {
+                bv = ov;
+                bk = ok;
+            }
+        }
+        const int p = pin[bk];
+        const double *x = M + (int64_t)p * ldm;
         const Refl r = reflector(x, j, rows, lane);
         const bool stop = guard_stop(j, r.beta, j == 0 ? 0.0 : fabs(Rjj[0]));
         if (!stop)
             for (int i = j + 1 + lane; i < rows; i += kWave) vh[i] = x[i] * r.sc;
         if (lane == 0) {
             s_stop = stop;
-            s_k = k;
+            s_k = bk;
+            s_p = p;
             s_tau = r.tau;
             vh[j] = 1.0;
             if (slice == 0) {
                 if (stop) {
-                    st[0] = 1;
-                    st[1] = j;
-                    st[2] = (j == 0);
+                    int32_t *stw = w.st + kQsState * node;
+                    stw[0] = 1;
+                    stw[1] = j;
+                    stw[2] = (j == 0);
                 } else {
                     Rjj[j] = r.beta;
                 }
@@ -697,22 +724,19 @@ __global__ __launch_bounds__(kQsThreads) void k_qs_step(const SkelTask *__restri
     }
     __syncthreads();
     if (s_stop) return;
-    const int k = s_k, p = pin[k];
+    const int k = s_k, p = s_p;
     const double tau = s_tau;
-    // the next pivot order: positions j and k exchanged
-    if (slice == 0)
-        for (int q = tid; q < ncand; q += kQsThreads) pout[q] = q == j ? p : (q == k ? pin[j] : pin[q]);
-    // trailing columns of this group: those at positions > j
-    for (int q = 0; q < 2; q++) {
-        const int c = slice * kQsCols + 2 * wave + q;
-        if (c >= ncand || c == p) continue;
-        // position of c: done columns sit at positions < j
-        bool trailing = true;
-        for (int i = lane; i < j; i += kWave)
-            if (pin[i] == c) trailing = false;
-        if (__ballot(!trailing) != 0ull) continue;
-        const double v = apply_col(t.M + (int64_t)c * ldm, vh, j, rows, tau, lane);
-        if (lane == 0) nout[c] = v;
+    // the next pivot order at this wave's positions: positions j and k
+    // exchanged; the column now at position q > j is updated and its norm
+    // stored at q
+    for (int u = 0; u < 2; u++) {
+        const int q = u ? qb : qa;
+        if (q >= ncand) continue;
+        const int c = q == j ? p : (q == k ? pin[j] : (u ? cb : ca));
+        if (lane == 0) pout[q] = c;
+        if (q <= j) continue;
+        const double v = apply_col(M + (int64_t)c * ldm, vh, j, rows, tau, lane);
+        if (lane == 0) nout[q] = v;
     }
 }
 
@@ -721,7 +745,7 @@ __global__ __launch_bounds__(kQrThreads) void k_qs_finish(const SkelTask *__rest
                                                            int ldm) {
     const int node = blockIdx.x;
     const SkelTask t = tasks[node];
-    const int32_t *st = w.st + 4 * node;
+    const int32_t *st = w.st + kQsState * node;
     const int sl = t.leaf ? 0 : *t.srl, ncand = node_ncand(t);
     const bool stopped = st[0] != 0, zero = st[2] != 0;
     const int jstop = st[1], steps = st[3];
