@@ -824,11 +824,11 @@ static askit_status skeletonize_impl(askit_tree *trees, int count, hipStream_t s
             const SkelTask *tp = dsplit.as<SkelTask>();
             const unsigned g = (unsigned)(nsp * w.slices);
             HIP_TRY(timed("skel:k_qrcp_split", st, [&] {
-                hipLaunchKernelGGL(k_qs_rows, dim3(g), dim3(256), 0, st, tp, w, nsamp_max);
+                hipLaunchKernelGGL(k_qs_rows, dim3(g), dim3(kQsThreads), 0, st, tp, w, nsamp_max);
                 hipLaunchKernelGGL(k_qs_rowmap, dim3(nsp), dim3(512), 0, st, tp, w);
-                hipLaunchKernelGGL(k_qs_init, dim3(g), dim3(256), 0, st, tp, w, s, nsamp_max);
+                hipLaunchKernelGGL(k_qs_init, dim3(g), dim3(kQsThreads), 0, st, tp, w, s, nsamp_max);
                 for (int j = 0; j < split_steps; j++)
-                    hipLaunchKernelGGL(k_qs_step, dim3(g), dim3(256), 0, st, tp, w, j, nsamp_max);
+                    hipLaunchKernelGGL(k_qs_step, dim3(g), dim3(kQsThreads), 0, st, tp, w, j, nsamp_max);
                 hipLaunchKernelGGL(k_qs_finish, dim3(nsp), dim3(512), 0, st, tp, w, s, nsamp_max);
                 return hipGetLastError();
             }));

@@ -12,7 +12,8 @@ constexpr int kMaxDim = 64;      // largest point dimension d accepted
 constexpr int kTreeChunk = 256;  // positions per chunk of the tree reductions
 constexpr int kPowerIters = 50;  // power iterations for the principal axis
 constexpr double kRankGuard = 1e-14;
-constexpr int kQsCols = 8;       // columns per workgroup of the split QRCP
+constexpr int kQsThreads = 256;  // threads per workgroup of the split QRCP
+constexpr int kQsCols = 8;       // columns per workgroup of the split QRCP (two per wave)
 constexpr int kQsState = 8;      // ints of per-node state of the split QRCP
 constexpr int kLsThreads = 1024; // batched LU solves: 16 waves keep many block loads in flight
 constexpr int kLuFThreads = 512; // batched LU factorization

@@ -126,7 +126,6 @@ __global__ __launch_bounds__(256) void k_sample_block(const SkelTask *__restrict
 // ---------------------------------------------------------------------------
 constexpr int kQrThreads = 512;
 constexpr int kQrWaves = kQrThreads / kWave;
-constexpr int kQsThreads = 256;
 constexpr int kQsWaves = kQsThreads / kWave;
 static_assert(kQsCols == 2 * kQsWaves, "two columns per wave in the split form");
 
