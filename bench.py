@@ -130,7 +130,14 @@ ROOF_TABLE = [
 # scaled by what the same counters read for a plain 1 GiB read + 1 GiB write
 # (torch.neg).  Valid only for the kernel source they were taken on (sha256 of
 # the file) and for this workload; otherwise "traffic" is null.
-TRAFFIC = {}
+TRAFFIC = {
+    "skel:k_qrcp": {
+        "source": "k_skel.hip",
+        "src_sha256": "e3a301015e2336e0235b2b9a80db212b6ba7a442d10523a67cc042566c7c5cad",
+        "workload": (1048576, 16, 512, 256, 1024),
+        "bytes_per_launch": 10392836359.332882,
+    },
+}
 
 
 def kernel_source_sha(name):
