@@ -233,30 +233,35 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu_nopiv(const LuTask *__restri
     for (int i = tid; i < n; i += NT) t.piv[i] = i;
     for (int kb = 0; kb < n; kb += kPanel) {
         const int nb = n - kb < kPanel ? n - kb : kPanel;
-        // ---- diagonal block, factored in LDS by wave 0: lane i < nb owns
-        // row i; the pivot row k is final once step k - 1 has ended, and the
-        // wave-scope fences order each step's row updates before the next
-        // step's reads
+        // ---- diagonal block, factored by wave 0: lane i < nb holds row i in
+        // registers, the pivot row is broadcast by lane shuffles (fully
+        // unrolled: every register index is static)
         if (wave == 0) {
-            if (lane < kPanel)
-                for (int j = 0; j < kPanel; j++)
-                    Dg[lane * DL + j] = (lane < nb && j < nb) ? A[kb + lane + (int64_t)(kb + j) * lda]
-                                                              : (lane == j ? 1.0 : 0.0);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll 1
-            for (int k = 0; k < nb; k++) {
-                if (lane > k && lane < nb) {
-                    const double ukk = Dg[k * DL + k];
-                    const double l = ukk != 0.0 ? Dg[lane * DL + k] / ukk : 0.0;
-                    Dg[lane * DL + k] = l;
-                    for (int j = k + 1; j < nb; j++) Dg[lane * DL + j] = fma(-l, Dg[k * DL + j], Dg[lane * DL + j]);
+            double rw[kPanel];
+#pragma unroll
+            for (int j = 0; j < kPanel; j++)
+                rw[j] = (lane < nb && j < nb) ? A[kb + lane + (int64_t)(kb + j) * lda] : (lane == j ? 1.0 : 0.0);
+#pragma unroll
+            for (int k = 0; k < kPanel; k++) {
+                const double ukk = __shfl(rw[k], k);
+                const bool act = k < nb && lane > k && lane < nb;
+                const double l = (act && ukk != 0.0) ? rw[k] / ukk : 0.0;
+                if (act) rw[k] = l;
+#pragma unroll
+                for (int j = k + 1; j < kPanel; j++) {
+                    const double pj = __shfl(rw[j], k);
+                    if (act) rw[j] = fma(-l, pj, rw[j]);
                 }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
-            if (lane < nb)
-                for (int j = 0; j < nb; j++) A[kb + lane + (int64_t)(kb + j) * lda] = Dg[lane * DL + j];
+            if (lane < kPanel) {
+#pragma unroll
+                for (int j = 0; j < kPanel; j++) Dg[lane * DL + j] = rw[j];
+            }
+            if (lane < nb) {
+#pragma unroll
+                for (int j = 0; j < kPanel; j++)
+                    if (j < nb) A[kb + lane + (int64_t)(kb + j) * lda] = rw[j];
+            }
         }
         __syncthreads();
         // ---- inverses of the triangles (column j of U^{-1}: thread j; of
