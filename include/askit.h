@@ -75,8 +75,11 @@ typedef struct {
  * depth D = ceil(log2(N / m)); each node's points are split in two halves
  * (floor(n/2) to the left) by the hyperplane through their median along
  * their principal axis.  X: device, N x d row-major FP64, copied.  Blocks
- * until the tree is built.  Errors: ASKIT_ERR_ARG for N < 1, d < 1 or
- * d > 64, m < 2, s < 1, h <= 0, non-finite coordinates. */
+ * until the tree is built.  Errors: ASKIT_ERR_ARG for N < 1 or N >= 2^31,
+ * d < 1 or d > 64, m < 2, s < 1, h <= 0 or not finite, n_samples < 0 or
+ * > 4096, qr_split_levels < -1, a largest leaf ceil(N / 2^D) above 512
+ * points or 2 s above 512 (the kernels hold a leaf block and a reduced
+ * system of order s_l + s_r in one workgroup). */
 askit_status askit_build_tree(const double *X, int64_t N, int32_t d, const askit_options *opt, void *stream,
                               askit_tree *out);
 

@@ -573,7 +573,7 @@ askit_status askit_build_tree(const double *X, int64_t N, int32_t d, const askit
     t->cmax = std::max(t->mmax, 2 * t->s);
     if (t->mmax > 512 || 2 * t->s > 512)
         return fail(ASKIT_ERR_ARG, "leaf size and 2 * rank must not exceed 512");
-    if (t->nsamp > 4096 || t->cmax > 2048) return fail(ASKIT_ERR_ARG, "n_samples must be <= 4096");
+    if (t->nsamp > 4096) return fail(ASKIT_ERR_ARG, "n_samples must be <= 4096");
     t->nb.assign(t->nnodes, 0);
     t->ne.assign(t->nnodes, 0);
     t->ne[0] = N;
