@@ -7,14 +7,16 @@ clusters with centres ~ U[-10,10]^16 and sigma ~ U[0.5,2]; h = 2, lambda = 0.01,
 64 right-hand sides ~ N(0,1).
 
 One step = skeletonize (sampled ID, FP64 QRCP) + factorize (mixed precision:
-FP32 kernel blocks and level products, FP64 LUs) + solve of the 64 right-hand
-sides with iterative refinement against the FP64 operator.  Inputs are resident
-in HBM before the timed region; the tree is built once, outside it.
+FP32 kernel blocks and level products, FP64 LUs), as the one pipelined call
+askit_skeletonize_factorize, + solve of the 64 right-hand sides with iterative
+refinement against the FP64 operator.  Inputs are resident in HBM before the
+timed region; the tree is built once, outside it.
 
 Printed: one JSON line.  value = factor time (skeletonize + factorize) of the
-mixed path in seconds; solves/s, the plain FP64 path (timed once after the
-steps), the mixed-vs-FP64 relative error, the roofline of the dominant kernel
-(per-kernel HIP-event timings) and the oracle CPU baseline are included.
+mixed path in seconds; the same step through the two separate calls, solves/s,
+the plain FP64 path (timed once after the steps), the mixed-vs-FP64 relative
+error, the roofline of the dominant kernel (per-kernel HIP-event timings) and
+the oracle CPU baseline are included.
 """
 from __future__ import annotations
 
@@ -212,13 +214,19 @@ def main():
     t_tree = time.perf_counter() - t0
     log(f"[bench] tree built in {t_tree:.3f} s (depth {tree.D})")
 
-    def step(prec, keep=False):
+    def step(prec, keep=False, fused=True):
+        # fused: askit_skeletonize_factorize (the two phases pipelined over
+        # two streams); else the two separate calls
         torch.cuda.synchronize()
         a = time.perf_counter()
-        tree.skeletonize()
-        torch.cuda.synchronize()
-        b = time.perf_counter()
-        f = tree.factorize(lam, prec)
+        if fused:
+            f = tree.skeletonize_factorize(lam, prec)
+            b = None
+        else:
+            tree.skeletonize()
+            torch.cuda.synchronize()
+            b = time.perf_counter()
+            f = tree.factorize(lam, prec)
         if prec == ak.ASKIT_MIXED:
             f.set_refinement(args.max_refine, args.tol)
         torch.cuda.synchronize()
@@ -229,7 +237,8 @@ def main():
         info = f.info() if prec == ak.ASKIT_MIXED else None
         if info is not None:
             info["min_pivot_ratio"] = f.pivot_ratio()[0]
-        out = dict(skel=b - a, factor=cc - b, solve=e - cc, info=info)
+        out = dict(total=cc - a, skel=None if b is None else b - a, factor=None if b is None else cc - b,
+                   solve=e - cc, info=info)
         if keep:
             return out, f, x
         f.close()
@@ -238,7 +247,7 @@ def main():
 
     for w in range(args.warmup):
         r, _, _ = step(ak.ASKIT_MIXED)
-        log(f"[bench] warmup {w}: skel {r['skel']:.3f} s factor {r['factor']:.3f} s solve {r['solve']:.3f} s")
+        log(f"[bench] warmup {w}: skeletonize+factorize {r['total']:.3f} s solve {r['solve']:.3f} s")
 
     ak.askit_profile_enable(True)
     torch.cuda.synchronize()
@@ -250,7 +259,7 @@ def main():
         runs.append(r)
         if f is not None:
             fmx, xmx = f, x
-        log(f"[bench] step {k}: skel {r['skel']:.3f} s factor {r['factor']:.3f} s solve {r['solve']:.3f} s "
+        log(f"[bench] step {k}: skeletonize+factorize {r['total']:.3f} s solve {r['solve']:.3f} s "
             f"refine {r['info']}")
     torch.cuda.synchronize()
     T1 = time.perf_counter()
@@ -267,18 +276,26 @@ def main():
         fmx.solve(Bx)
         torch.cuda.synchronize()
         direct[name] = time.perf_counter() - a
-    fmx.set_refinement(args.max_refine, args.tol)
+    fmx.close()
     ms_step = 1e3 * (T1 - T0) / args.steps
-    t_skel = float(np.mean([r["skel"] for r in runs]))
-    t_fac = float(np.mean([r["factor"] for r in runs]))
+    t_total = float(np.mean([r["total"] for r in runs]))
     t_sol = float(np.mean([r["solve"] for r in runs]))
     info = runs[-1]["info"]
+    # the same step through the two separate calls (no overlap), once
+    r2, _, _ = step(ak.ASKIT_MIXED, fused=False)
+    two_call = dict(skeletonize_s=r2["skel"], factorize_s=r2["factor"], total_s=r2["total"])
+    log(f"[bench] separate calls: skeletonize {r2['skel']:.3f} s factorize {r2['factor']:.3f} s")
 
     res = {}
     if not args.no_fp64:
         a = time.perf_counter()
-        f64 = tree.factorize(lam, ak.ASKIT_FP64)
+        f64 = tree.skeletonize_factorize(lam, ak.ASKIT_FP64)
         torch.cuda.synchronize()
+        b = time.perf_counter()
+        f64b = tree.factorize(lam, ak.ASKIT_FP64)
+        torch.cuda.synchronize()
+        t_f64_only = time.perf_counter() - b
+        f64b.close()
         b = time.perf_counter()
         x64 = f64.solve(B)
         torch.cuda.synchronize()
@@ -296,13 +313,14 @@ def main():
         info64["min_pivot_ratio"] = f64.pivot_ratio()[0]
         err = float(((xmx - xref).norm(dim=0) / xref.norm(dim=0)).max())
         err_direct = float(((xmx - x64).norm(dim=0) / x64.norm(dim=0)).max())
-        res = dict(fp64_factor_s=t_skel + (b - a), fp64_factorize_only_s=b - a, fp64_solve_s=e - b,
+        res = dict(fp64_factor_s=b - a, fp64_factorize_only_s=t_f64_only, fp64_solve_s=e - b,
                    fp64_solves_per_s=args.nrhs / (e - b), fp64_residual=eps64,
                    fp64_refined_solve_s=g1 - g0, fp64_refinement=info64,
                    mixed_vs_fp64_rel_err=err, mixed_vs_fp64_direct_rel_err=err_direct,
-                   speedup_factor_mixed_over_fp64=(t_skel + (b - a)) / (t_skel + t_fac),
-                   speedup_factorize_only=(b - a) / t_fac)
-        log(f"[bench] fp64: factorize {b - a:.3f} s solve {e - b:.3f} s (residual {eps64:.2e}); refined "
+                   speedup_factor_mixed_over_fp64=(b - a) / t_total,
+                   speedup_factorize_only=t_f64_only / two_call["factorize_s"])
+        log(f"[bench] fp64: skeletonize+factorize {b - a:.3f} s (factorize alone {t_f64_only:.3f} s) solve "
+            f"{e - b:.3f} s (residual {eps64:.2e}); refined "
             f"{g1 - g0:.3f} s {info64}; mixed vs fp64 refined {err:.2e}, vs fp64 direct {err_direct:.2e}")
         f64.close()
         del x64, r64, xref
@@ -353,13 +371,13 @@ def main():
         cpu = cpu_baseline(c, args.cpu_sample, args.nrhs)
 
     out = {
-        "metric": METRIC, "value": t_skel + t_fac, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "metric": METRIC, "value": t_total, "unit": "s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"gaussian-mixture N={N} d={d} m={m} s={s} h={h} lambda={lam} nrhs={args.nrhs}",
                    "N": N, "d": d, "leaf_size": m, "rank": s, "n_samples": nsamp, "nrhs": args.nrhs,
                    "precision": "mixed"},
-        "skeletonize_s": t_skel, "factorize_s": t_fac, "solve_s": t_sol, "solves_per_s": args.nrhs / t_sol,
+        "skeletonize_factorize_s": t_total, "separate_calls": two_call, "solve_s": t_sol, "solves_per_s": args.nrhs / t_sol,
         "direct_solve_s": direct["nrhs"], "direct_solves_per_s": args.nrhs / direct["nrhs"],
         "one_rhs_direct_solve_s": direct["one_rhs"],
         "refinement": info, "tree_s": t_tree,

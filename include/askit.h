@@ -116,6 +116,16 @@ askit_status askit_skeletons_import(askit_tree t, const int32_t *ids, const doub
  * max|U_ii| of some block is below 1e-12. */
 askit_status askit_factorize(askit_tree t, double lambda, int32_t precision, void *stream, askit_factor *out);
 
+/* askit_skeletonize followed by askit_factorize (Alg. 1 then Alg. 2) as one
+ * call, with the same results bit for bit.  The factorization of height h
+ * needs only the skeletons of heights <= h, so it runs on a library-owned
+ * non-blocking stream one height behind the skeletonization, which runs on
+ * `stream`; the leaf LUs start at once.  The call returns when both are done
+ * (`stream` is ordered after the factorization).  Errors as for the two
+ * calls; ASKIT_ERR_STATE if factors of this tree still exist. */
+askit_status askit_skeletonize_factorize(askit_tree t, double lambda, int32_t precision, void *stream,
+                                         askit_factor *out);
+
 /* X = (lambda I + Ktilde)^{-1} B (Alg. 3).  B, X: device, N x nrhs
  * column-major (ldb, ldx >= N); B and X may alias.  With refinement enabled
  * (the default for a MIXED factor, see askit_set_refinement) the result is
@@ -216,7 +226,10 @@ askit_status askit_get_stats(askit_tree t, askit_factor f, char *json, size_t ca
 /* Per-kernel timing: with profiling on, every launch of the library is
  * bracketed by HIP events on its stream; askit_profile_report writes
  * {"phase:kernel": [total_ms, launches], ...} (it synchronizes on the pending
- * events).  Enabling resets the totals. */
+ * events).  Enabling resets the totals.  on = 2 keeps the totals per tree
+ * height for the skeletonization and factorization launches, named
+ * "phase:kernel@h<height>" (height 0 = leaves); plans built while it is on
+ * keep those names. */
 askit_status askit_profile_enable(int32_t on);
 askit_status askit_profile_report(char *json, size_t cap);
 

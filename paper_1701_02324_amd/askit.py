@@ -25,7 +25,7 @@ EXPORTED = [
     "askit_last_error", "askit_tree_destroy", "askit_factor_destroy", "askit_profile_enable",
     "askit_profile_report", "askit_tree_set_bandwidth", "askit_adjoint_scalars", "askit_skeletonize_batched",
     "askit_batch_create", "askit_batch_factorize", "askit_batch_check", "askit_batch_solve", "askit_batch_factor",
-    "askit_batch_destroy",
+    "askit_batch_destroy", "askit_skeletonize_factorize",
 ]
 
 
@@ -68,6 +68,7 @@ def load(path: str = LIB_PATH):
     L.askit_skeletons_export.argtypes = [_vp, _vp, _vp, _vp]
     L.askit_skeletons_import.argtypes = [_vp, _vp, _vp, _vp]
     L.askit_factorize.argtypes = [_vp, ctypes.c_double, _i32, _vp, ctypes.POINTER(_vp)]
+    L.askit_skeletonize_factorize.argtypes = [_vp, ctypes.c_double, _i32, _vp, ctypes.POINTER(_vp)]
     for f in ("askit_solve", "askit_solve_transpose"):
         getattr(L, f).argtypes = [_vp, _vp, _i64, _i32, _vp, _i64, _vp]
     L.askit_matvec.argtypes = [_vp, _i32, _vp, _i64, _i32, _vp, _i64, _vp]
@@ -181,6 +182,13 @@ def askit_factorize(tree, lam, precision=ASKIT_FP64, stream=None):
     return out, st
 
 
+def askit_skeletonize_factorize(tree, lam, precision=ASKIT_FP64, stream=None):
+    out = _vp()
+    st = load().askit_skeletonize_factorize(tree, float(lam), int(precision), _stream(stream), ctypes.byref(out))
+    _check(st, allow_warn=True)
+    return out, st
+
+
 def _apply(fn, factor, B, stream, *pre):
     B = _dev64(B, "B")
     Bc, vec = _colmajor(B)
@@ -244,8 +252,9 @@ def askit_get_stats(tree=None, factor=None):
     return json.loads(buf.value.decode())
 
 
-def askit_profile_enable(on=True):
-    _check(load().askit_profile_enable(1 if on else 0))
+def askit_profile_enable(on=True, per_height=False):
+    """Per-kernel HIP-event timing; per_height keeps totals per tree height."""
+    _check(load().askit_profile_enable((2 if per_height else 1) if on else 0))
 
 
 def askit_profile_report():
@@ -305,6 +314,10 @@ class Tree:
     def factorize(self, lam, precision=ASKIT_FP64, stream=None):
         return Factor(self, lam, precision, stream)
 
+    def skeletonize_factorize(self, lam, precision=ASKIT_FP64, stream=None):
+        """skeletonize() then factorize(), pipelined over two streams."""
+        return Factor(self, lam, precision, stream, fused=True)
+
     def set_bandwidth(self, h):
         """Bandwidth of subsequent factorizations (skeletons frozen)."""
         askit_tree_set_bandwidth(self.handle, h)
@@ -327,11 +340,12 @@ class Tree:
 class Factor:
     """Factorization of lambda I + Ktilde on a skeletonized tree."""
 
-    def __init__(self, tree, lam, precision=ASKIT_FP64, stream=None):
+    def __init__(self, tree, lam, precision=ASKIT_FP64, stream=None, fused=False):
         self.tree = tree
         self.lam = float(lam)
         self.precision = precision
-        self.handle, self.status = askit_factorize(tree.handle, lam, precision, stream)
+        make = askit_skeletonize_factorize if fused else askit_factorize
+        self.handle, self.status = make(tree.handle, lam, precision, stream)
 
     def solve(self, B, stream=None):
         return askit_solve(self.handle, B, stream)

@@ -79,6 +79,18 @@ template <class T> askit_status upload(DBuf &b, const std::vector<T> &v) {
     return ASKIT_OK;
 }
 
+// device buffer that only grows: a height reuses the previous height's
+// allocation when it fits (no hipFree, which would wait for every stream)
+template <class T> askit_status upload_grow(DBuf &b, const std::vector<T> &v) {
+    if (b.bytes < sizeof(T) * std::max<size_t>(v.size(), 1)) ST_TRY(b.alloc(sizeof(T) * std::max<size_t>(v.size(), 1)));
+    if (!v.empty()) HIP_TRY(hipMemcpy(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    return ASKIT_OK;
+}
+static askit_status grow(DBuf &b, size_t n) {
+    if (b.bytes < n) ST_TRY(b.alloc(n));
+    return ASKIT_OK;
+}
+
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline unsigned grid1(int64_t n, int bs = 256) { return (unsigned)std::max<int64_t>(1, cdiv(n, bs)); }
 
@@ -110,6 +122,7 @@ struct ProfRec {
 };
 struct Prof {
     bool on = false;
+    bool heights = false;  // label each launch with the tree height it serves
     std::vector<ProfRec> pend;
     std::map<std::string, std::pair<double, int64_t>> acc;
 };
@@ -125,6 +138,9 @@ template <class F> hipError_t timed(const std::string &name, hipStream_t st, F &
     g_prof.pend.push_back({name, a, b});
     return e;
 }
+
+// "@h<height>" when launches are profiled per tree height, else ""
+std::string prof_height(int hgt) { return g_prof.heights ? "@h" + std::to_string(hgt) : std::string(); }
 
 hipError_t prof_flush() {
     for (auto &r : g_prof.pend) {
@@ -143,17 +159,19 @@ hipError_t prof_flush() {
 }
 
 struct Plan {
-    std::string tag;
+    std::string tag, sub;  // step names are tag:name<sub>
     std::vector<std::pair<std::string, Launch>> steps;
     std::vector<std::unique_ptr<DBuf>> bufs;
     DBuf *own() {
         bufs.emplace_back(new DBuf());
         return bufs.back().get();
     }
-    void add(const char *name, Launch f) { steps.emplace_back(tag + ":" + name, std::move(f)); }
-    hipError_t run(hipStream_t st, int ncol) const {
-        for (const auto &s : steps) {
-            hipError_t e = timed(s.first, st, [&] { return s.second(st, ncol); });
+    void add(const char *name, Launch f) { steps.emplace_back(tag + ":" + name + sub, std::move(f)); }
+    hipError_t run(hipStream_t st, int ncol) const { return run_from(st, ncol, 0); }
+    // enqueue steps i0 .. end
+    hipError_t run_from(hipStream_t st, int ncol, size_t i0) const {
+        for (size_t i = i0; i < steps.size(); i++) {
+            hipError_t e = timed(steps[i].first, st, [&] { return steps[i].second(st, ncol); });
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -518,6 +536,7 @@ askit_status askit_profile_enable(int32_t on) {
     HIP_TRY(prof_flush());
     g_prof.acc.clear();
     g_prof.on = on != 0;
+    g_prof.heights = on == 2;
     return ASKIT_OK;
 }
 
@@ -690,36 +709,62 @@ void askit_tree_destroy(askit_tree t) { delete t; }
 // ---------------------------------------------------------------------------
 // skeletonization (Alg. 1), level by level from the leaves up
 // ---------------------------------------------------------------------------
-static askit_status skeletonize_impl(askit_tree *trees, int count, hipStream_t st) {
-    // heights from the leaves: all trees' nodes of one height in one launch
-    int Hmax = 0;
-    for (int i = 0; i < count; i++) Hmax = std::max(Hmax, trees[i]->D);
-    int nsamp_max = 0, cmax = 0, s = trees[0]->s, d = trees[0]->d;
-    for (int i = 0; i < count; i++) {
-        nsamp_max = std::max(nsamp_max, trees[i]->nsamp);
-        cmax = std::max(cmax, trees[i]->cmax);
-        if (trees[i]->s != s || trees[i]->d != d)
-            return fail(ASKIT_ERR_ARG, "batched trees must share rank and dimension");
-        if (!trees[i]->samp.p) ST_TRY(trees[i]->samp.alloc(sizeof(int32_t) * trees[i]->nnodes * trees[i]->nsamp));
-        trees[i]->hsr.assign(trees[i]->nnodes, 0);
-    }
-    const int64_t slot = (int64_t)nsamp_max * cmax;  // sampled block per node, column-major, ld nsamp_max
+// One skeletonization pass over a set of trees, height by height.  prepare()
+// waits for the previous height, reads the ranks it decided (they fix the
+// candidate counts and so every launch shape of this height) and uploads the
+// task lists; launch() only enqueues kernels, so that a caller can enqueue
+// other work in between without waiting on this stream.
+struct SkelRun {
+    askit_tree *trees = nullptr;
+    int count = 0, Hmax = 0, nsamp_max = 0, cmax = 0, s = 0, d = 0;
+    hipStream_t st = nullptr;
     DBuf M, err, dsamp, dsk, dqr, dsplit;
     DBuf wpart, wrmap, wrows, wnrm, wpos, wdiag, wst;
-    ST_TRY(err.alloc(sizeof(int32_t)));
-    HIP_TRY(hipMemsetAsync(err.p, 0, sizeof(int32_t), st));
-    for (int hgt = 0; hgt < Hmax; hgt++) {
+    // launch parameters of the prepared height
+    int nqr = 0, n1 = 0, nsp = 0, split_steps = 0;
+    QrWork w{};
+
+    askit_status begin(askit_tree *tr, int cnt, hipStream_t stream) {
+        trees = tr;
+        count = cnt;
+        st = stream;
+        for (int i = 0; i < count; i++) Hmax = std::max(Hmax, trees[i]->D);
+        s = trees[0]->s;
+        d = trees[0]->d;
+        for (int i = 0; i < count; i++) {
+            nsamp_max = std::max(nsamp_max, trees[i]->nsamp);
+            cmax = std::max(cmax, trees[i]->cmax);
+            if (trees[i]->s != s || trees[i]->d != d)
+                return fail(ASKIT_ERR_ARG, "batched trees must share rank and dimension");
+            if (!trees[i]->samp.p) ST_TRY(trees[i]->samp.alloc(sizeof(int32_t) * trees[i]->nnodes * trees[i]->nsamp));
+            trees[i]->hsr.assign(trees[i]->nnodes, 0);
+            trees[i]->skel_ok = false;
+        }
+        ST_TRY(err.alloc(sizeof(int32_t)));
+        HIP_TRY(hipMemsetAsync(err.p, 0, sizeof(int32_t), st));
+        return ASKIT_OK;
+    }
+
+    // the ranks decided so far, on the host
+    askit_status read_ranks() {
+        for (int i = 0; i < count; i++)
+            HIP_TRY(hipMemcpyAsync(trees[i]->hsr.data(), trees[i]->srank.p, sizeof(int32_t) * trees[i]->nnodes,
+                                   hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int i = 0; i < count; i++) trees[i]->hsr[0] = 0;
+        return ASKIT_OK;
+    }
+
+    askit_status prepare(int hgt) {
         // the children's ranks (decided at the previous height) fix the
         // candidate counts: nodes with |C| <= s keep all candidates (P = I)
         // and need neither samples nor a QR
-        if (hgt > 0)
-            for (int i = 0; i < count; i++)
-                HIP_TRY(hipMemcpyAsync(trees[i]->hsr.data(), trees[i]->srank.p, sizeof(int32_t) * trees[i]->nnodes,
-                                       hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
+        if (hgt > 0) ST_TRY(read_ranks());
+        else HIP_TRY(hipStreamSynchronize(st));
         std::vector<SampTask> samp_one, samp_split;
         std::vector<SkelTask> qr_one, qr_split, ident;
-        int split_cols = 0, split_steps = 0;
+        int split_cols = 0;
+        split_steps = 0;
         for (int i = 0; i < count; i++) {
             askit_tree t = trees[i];
             const int l = t->D - hgt;
@@ -771,49 +816,34 @@ static askit_status skeletonize_impl(askit_tree *trees, int count, hipStream_t s
         samp.insert(samp.end(), samp_split.begin(), samp_split.end());
         std::vector<SkelTask> qr(qr_one);
         qr.insert(qr.end(), qr_split.begin(), qr_split.end());
-        const int nqr = (int)qr.size(), none_ = (int)qr_one.size(), nsp = (int)qr_split.size();
-        if ((int64_t)M.bytes < (int64_t)sizeof(double) * nqr * slot) ST_TRY(M.alloc(sizeof(double) * nqr * slot));
+        nqr = (int)qr.size();
+        nsp = (int)qr_split.size();
+        const int none_ = (int)qr_one.size();
+        const int64_t slot = (int64_t)nsamp_max * cmax;  // sampled block per node, column-major, ld nsamp_max
+        ST_TRY(grow(M, sizeof(double) * std::max(nqr, 1) * slot));
         for (int j = 0; j < nqr; j++) qr[j].M = M.as<double>() + (int64_t)j * slot;
         for (int j = 0; j < nsp; j++) qr_split[j].M = qr[none_ + j].M;
         std::vector<SkelTask> one(qr.begin(), qr.begin() + none_);
         one.insert(one.end(), ident.begin(), ident.end());
+        n1 = (int)one.size();
         if (nqr > 0) {
-            ST_TRY(upload(dsamp, samp));
-            ST_TRY(upload(dsk, qr));
-            // all trees of a batch share nsamp (checked by the batched entry point)
-            HIP_TRY(timed("skel:k_sample", st, [&] {
-                hipLaunchKernelGGL(k_sample, dim3(nqr), dim3(64), 0, st, dsamp.as<SampTask>(), nsamp_max,
-                                   err.as<int32_t>());
-                return hipGetLastError();
-            }));
-            const int rt = (int)cdiv(nsamp_max, 64), ct = (int)cdiv(cmax, 64);
-            HIP_TRY(timed("skel:k_sample_block", st, [&] {
-                hipLaunchKernelGGL(k_sample_block, dim3(nqr * rt * ct), dim3(256), sizeof(double) * (64 * (d | 1) + 64 * d), st,
-                                   dsk.as<SkelTask>(), rt, nsamp_max, d, ct);
-                return hipGetLastError();
-            }));
+            ST_TRY(upload_grow(dsamp, samp));
+            ST_TRY(upload_grow(dsk, qr));
         }
-        if (!one.empty()) {
-            ST_TRY(upload(dqr, one));
-            const int n1 = (int)one.size();
-            HIP_TRY(timed("skel:k_qrcp", st, [&] {
-                hipLaunchKernelGGL(k_qrcp, dim3(n1), dim3(512), 0, st, dqr.as<SkelTask>(), s, nsamp_max);
-                return hipGetLastError();
-            }));
-        }
+        if (n1 > 0) ST_TRY(upload_grow(dqr, one));
         if (nsp > 0) {
-            QrWork w{};
+            w = QrWork{};
             w.cmax = cmax;
             w.rcap = nsamp_max;
             w.slices = (int)cdiv(split_cols, kQsCols);
-            ST_TRY(upload(dsplit, qr_split));
-            ST_TRY(wpart.alloc(sizeof(double) * (size_t)nsp * w.slices * w.rcap));
-            ST_TRY(wrmap.alloc(sizeof(int32_t) * (size_t)nsp * w.rcap));
-            ST_TRY(wrows.alloc(sizeof(int32_t) * (size_t)nsp));
-            ST_TRY(wnrm.alloc(sizeof(double) * (size_t)nsp * 2 * cmax));
-            ST_TRY(wpos.alloc(sizeof(int32_t) * (size_t)nsp * 2 * cmax));
-            ST_TRY(wdiag.alloc(sizeof(double) * (size_t)nsp * cmax));
-            ST_TRY(wst.alloc(sizeof(int32_t) * (size_t)nsp * kQsState));
+            ST_TRY(upload_grow(dsplit, qr_split));
+            ST_TRY(grow(wpart, sizeof(double) * (size_t)nsp * w.slices * w.rcap));
+            ST_TRY(grow(wrmap, sizeof(int32_t) * (size_t)nsp * w.rcap));
+            ST_TRY(grow(wrows, sizeof(int32_t) * (size_t)nsp));
+            ST_TRY(grow(wnrm, sizeof(double) * (size_t)nsp * 2 * cmax));
+            ST_TRY(grow(wpos, sizeof(int32_t) * (size_t)nsp * 2 * cmax));
+            ST_TRY(grow(wdiag, sizeof(double) * (size_t)nsp * cmax));
+            ST_TRY(grow(wst, sizeof(int32_t) * (size_t)nsp * kQsState));
             w.part = wpart.as<double>();
             w.rmap = wrmap.as<int32_t>();
             w.rows = wrows.as<int32_t>();
@@ -821,32 +851,69 @@ static askit_status skeletonize_impl(askit_tree *trees, int count, hipStream_t s
             w.pos = wpos.as<int32_t>();
             w.diag = wdiag.as<double>();
             w.st = wst.as<int32_t>();
-            const SkelTask *tp = dsplit.as<SkelTask>();
-            const unsigned g = (unsigned)(nsp * w.slices);
-            HIP_TRY(timed("skel:k_qrcp_split", st, [&] {
-                hipLaunchKernelGGL(k_qs_rows, dim3(g), dim3(kQsThreads), 0, st, tp, w, nsamp_max);
-                hipLaunchKernelGGL(k_qs_rowmap, dim3(nsp), dim3(512), 0, st, tp, w);
-                hipLaunchKernelGGL(k_qs_init, dim3(g), dim3(kQsThreads), 0, st, tp, w, s, nsamp_max);
-                for (int j = 0; j < split_steps; j++)
-                    hipLaunchKernelGGL(k_qs_step, dim3(g), dim3(kQsThreads), 0, st, tp, w, j, nsamp_max);
-                hipLaunchKernelGGL(k_qs_finish, dim3(nsp), dim3(512), 0, st, tp, w, s, nsamp_max);
+        }
+        return ASKIT_OK;
+    }
+
+    askit_status launch(int hgt) {
+        if (nqr > 0) {
+            // all trees of a batch share nsamp (checked by the batched entry point)
+            HIP_TRY(timed("skel:k_sample" + prof_height(hgt), st, [&] {
+                hipLaunchKernelGGL(k_sample, dim3(nqr), dim3(64), 0, st, dsamp.as<SampTask>(), nsamp_max,
+                                   err.as<int32_t>());
+                return hipGetLastError();
+            }));
+            const int rt = (int)cdiv(nsamp_max, 64), ct = (int)cdiv(cmax, 64);
+            HIP_TRY(timed("skel:k_sample_block" + prof_height(hgt), st, [&] {
+                hipLaunchKernelGGL(k_sample_block, dim3(nqr * rt * ct), dim3(256),
+                                   sizeof(double) * (64 * (d | 1) + 64 * d), st, dsk.as<SkelTask>(), rt, nsamp_max, d,
+                                   ct);
                 return hipGetLastError();
             }));
         }
+        if (n1 > 0) {
+            HIP_TRY(timed("skel:k_qrcp" + prof_height(hgt), st, [&] {
+                hipLaunchKernelGGL(k_qrcp, dim3(n1), dim3(512), 0, st, dqr.as<SkelTask>(), s, nsamp_max);
+                return hipGetLastError();
+            }));
+        }
+        if (nsp > 0) {
+            const SkelTask *tp = dsplit.as<SkelTask>();
+            const QrWork wk = w;
+            const unsigned g = (unsigned)(nsp * wk.slices);
+            HIP_TRY(timed("skel:k_qrcp_split" + prof_height(hgt), st, [&] {
+                hipLaunchKernelGGL(k_qs_rows, dim3(g), dim3(kQsThreads), 0, st, tp, wk, nsamp_max);
+                hipLaunchKernelGGL(k_qs_rowmap, dim3(nsp), dim3(512), 0, st, tp, wk);
+                hipLaunchKernelGGL(k_qs_init, dim3(g), dim3(kQsThreads), 0, st, tp, wk, s, nsamp_max);
+                for (int j = 0; j < split_steps; j++)
+                    hipLaunchKernelGGL(k_qs_step, dim3(g), dim3(kQsThreads), 0, st, tp, wk, j, nsamp_max);
+                hipLaunchKernelGGL(k_qs_finish, dim3(nsp), dim3(512), 0, st, tp, wk, s, nsamp_max);
+                return hipGetLastError();
+            }));
+        }
+        return ASKIT_OK;
     }
-    int32_t herr = 0;
-    HIP_TRY(hipMemcpyAsync(&herr, err.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+
     // the ranks decide the shapes of every later launch: keep them on the host
-    for (int i = 0; i < count; i++)
-        HIP_TRY(hipMemcpyAsync(trees[i]->hsr.data(), trees[i]->srank.p, sizeof(int32_t) * trees[i]->nnodes,
-                               hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    if (herr) return fail(ASKIT_ERR_HIP, "row sampling did not terminate");
-    for (int i = 0; i < count; i++) {
-        trees[i]->hsr[0] = 0;
-        trees[i]->skel_ok = true;
+    askit_status end() {
+        int32_t herr = 0;
+        HIP_TRY(hipMemcpyAsync(&herr, err.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        ST_TRY(read_ranks());
+        if (herr) return fail(ASKIT_ERR_HIP, "row sampling did not terminate");
+        for (int i = 0; i < count; i++) trees[i]->skel_ok = true;
+        return ASKIT_OK;
     }
-    return ASKIT_OK;
+};
+
+// skeletonization (Alg. 1), level by level from the leaves up
+static askit_status skeletonize_impl(askit_tree *trees, int count, hipStream_t st) {
+    SkelRun R;
+    ST_TRY(R.begin(trees, count, st));
+    for (int hgt = 0; hgt < R.Hmax; hgt++) {
+        ST_TRY(R.prepare(hgt));
+        ST_TRY(R.launch(hgt));
+    }
+    return R.end();
 }
 
 askit_status askit_skeletonize(askit_tree t, void *stream) {
@@ -943,7 +1010,11 @@ static const int64_t kChunk = 4096;  // contraction chunk of the split products
 // Factorization plan for one or several factors of equal rank, dimension and
 // precision: one launch per kernel and tree height (distance from the
 // leaves), covering the nodes of every tree at that height.
-static askit_status factor_plan(const std::vector<askit_factor> &fs, Plan &P) {
+// One part of the factorization plan: part -1 = the leaf LUs of
+// lambda I + K_aa (they need no skeletons), part 0 = the leaves' Phat, part
+// h >= 1 = the internal nodes at height h.  Part h >= 0 reads the ranks and
+// skeletons of heights <= h only.
+static askit_status factor_plan_part(const std::vector<askit_factor> &fs, Plan &P, int part) {
     askit_tree t0 = fs[0]->t;
     const int s = t0->s, d = t0->d, s2 = 2 * s;
     const Prec pr = fs[0]->prec;
@@ -953,8 +1024,9 @@ static askit_status factor_plan(const std::vector<askit_factor> &fs, Plan &P) {
         Hmax = std::max(Hmax, f->t->D);
         mmax = std::max(mmax, f->t->mmax);
     }
+    P.sub = prof_height(std::max(part, 0));
     // height 0: leaves -- lambda I + K_aa, LU, Phat = A^{-1} P_{alpha alpha~}
-    {
+    if (part <= 0) {
         std::vector<LeafTask> lt;
         std::vector<LuTask> lu, rs;
         std::vector<CopyTask> cp;
@@ -995,24 +1067,27 @@ static askit_status factor_plan(const std::vector<askit_factor> &fs, Plan &P) {
                 }
             }
         }
-        DBuf *b = P.own();
-        ST_TRY(upload(*b, lt));
-        const LeafTask *lp = b->as<LeafTask>();
-        const int nl = (int)lt.size(), tl = (int)cdiv(mmax, 64);
-        P.add("k_leaf_block", [=](hipStream_t st, int) -> hipError_t {
-            hipLaunchKernelGGL(k_leaf_block, dim3(nl * tl * tl), dim3(256), sizeof(double) * (64 * (d | 1) + 64 * d), st,
-                               lp, tl, d);
-            return hipGetLastError();
-        });
-        // lambda I + K_aa is symmetric positive definite for lambda > 0
-        bool spd = true;
-        for (auto f : fs) spd = spd && f->lambda > 0.0;
-        ST_TRY(lu_commit(P, lu, spd));
-        ST_TRY(copy_commit(P, cp, P64, pr, mmax, s));
-        ST_TRY(getrs_commit(P, rs, pr, false, s));
+        if (part < 0) {
+            DBuf *b = P.own();
+            ST_TRY(upload(*b, lt));
+            const LeafTask *lp = b->as<LeafTask>();
+            const int nl = (int)lt.size(), tl = (int)cdiv(mmax, 64);
+            P.add("k_leaf_block", [=](hipStream_t st, int) -> hipError_t {
+                hipLaunchKernelGGL(k_leaf_block, dim3(nl * tl * tl), dim3(256),
+                                   sizeof(double) * (64 * (d | 1) + 64 * d), st, lp, tl, d);
+                return hipGetLastError();
+            });
+            // lambda I + K_aa is symmetric positive definite for lambda > 0
+            bool spd = true;
+            for (auto f : fs) spd = spd && f->lambda > 0.0;
+            ST_TRY(lu_commit(P, lu, spd));
+        } else {
+            ST_TRY(copy_commit(P, cp, P64, pr, mmax, s));
+            ST_TRY(getrs_commit(P, rs, pr, false, s));
+        }
     }
     // heights 1 .. Hmax: internal nodes, bottom-up
-    for (int hgt = 1; hgt <= Hmax; hgt++) {
+    for (int hgt = std::max(part, 1); hgt <= std::min(part, Hmax); hgt++) {
         std::vector<IdTask> ident;
         KmmBuild kb;
         kb.tc = s >= 128 ? 128 : (s >= 64 ? 64 : 16);
@@ -1110,6 +1185,18 @@ static askit_status factor_plan(const std::vector<askit_factor> &fs, Plan &P) {
         if (pr == P32) ST_TRY(copy_commit(P, cp32, P64, P32, s2, s));
         ST_TRY(gmm_commit(P, gb, pr, 0));
     }
+    P.sub.clear();
+    return ASKIT_OK;
+}
+
+static int factor_height_max(const std::vector<askit_factor> &fs) {
+    int H = 0;
+    for (auto f : fs) H = std::max(H, f->t->D);
+    return H;
+}
+
+static askit_status factor_plan(const std::vector<askit_factor> &fs, Plan &P) {
+    for (int part = -1; part <= factor_height_max(fs); part++) ST_TRY(factor_plan_part(fs, P, part));
     return ASKIT_OK;
 }
 
@@ -1191,6 +1278,81 @@ static askit_status factorize_impl(askit_tree t, double lambda, int precision, h
     t->refs++;
     *out = f.release();
     return ratio_status(*out);
+}
+
+// Skeletonization and factorization as one pipeline over two streams: the
+// caller's stream skeletonizes height h while an internal stream factorizes
+// height h - 1 (which reads only the ranks, skeletons and projections of
+// heights <= h - 1); the leaf LUs, which need no skeletons, start at once.
+// Each kernel sees the inputs it sees in the two separate calls, so the
+// results are the same bit for bit.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t e = nullptr;
+    ~SideStream() {
+        if (e) hipEventDestroy(e);
+        if (s) hipStreamDestroy(s);
+    }
+};
+
+static askit_status skel_factor_impl(askit_tree t, double lambda, int precision, hipStream_t st, askit_factor *out,
+                                     double &t_skel) {
+    auto t0 = std::chrono::steady_clock::now();
+    SkelRun R;
+    ST_TRY(R.begin(&t, 1, st));
+    std::unique_ptr<askit_factor_s> f;
+    ST_TRY(factor_alloc(t, lambda, precision, f));
+    SideStream B;
+    // non-blocking: no implicit ordering against the legacy default stream
+    HIP_TRY(hipStreamCreateWithFlags(&B.s, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&B.e, hipEventDisableTiming));
+    const std::vector<askit_factor> fs{f.get()};
+    Plan P;
+    P.tag = "factor";
+    ST_TRY(factor_plan_part(fs, P, -1));
+    // the side stream starts after the work already queued on the caller's
+    HIP_TRY(hipEventRecord(B.e, st));
+    HIP_TRY(hipStreamWaitEvent(B.s, B.e, 0));
+    HIP_TRY(P.run_from(B.s, t->s, 0));
+    size_t done = P.steps.size();
+    for (int hgt = 0; hgt <= R.Hmax; hgt++) {
+        // wait for height hgt - 1 and read its ranks; uploads of both plans
+        // are made before this height's launches, while the caller's stream
+        // is idle
+        if (hgt < R.Hmax) ST_TRY(R.prepare(hgt));
+        else {
+            ST_TRY(R.end());
+            t_skel = ms_since(t0);
+        }
+        if (hgt > 0) ST_TRY(factor_plan_part(fs, P, hgt - 1));
+        if (hgt < R.Hmax) ST_TRY(R.launch(hgt));
+        HIP_TRY(P.run_from(B.s, t->s, done));
+        done = P.steps.size();
+    }
+    ST_TRY(factor_plan_part(fs, P, R.Hmax));
+    HIP_TRY(P.run_from(B.s, t->s, done));
+    // the caller's stream continues after the factorization
+    HIP_TRY(hipEventRecord(B.e, B.s));
+    HIP_TRY(hipStreamWaitEvent(st, B.e, 0));
+    ST_TRY(factor_ratio(f.get(), st));
+    t->refs++;
+    *out = f.release();
+    return ratio_status(*out);
+}
+
+askit_status askit_skeletonize_factorize(askit_tree t, double lambda, int32_t precision, void *stream,
+                                         askit_factor *out) {
+    if (!t || !out) return fail(ASKIT_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    if (t->refs) return fail(ASKIT_ERR_STATE, "destroy the factors of this tree before re-skeletonizing");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(ASKIT_ERR_ARG, "lambda must be >= 0 and finite");
+    if (precision != ASKIT_FP64 && precision != ASKIT_MIXED) return fail(ASKIT_ERR_ARG, "unknown precision");
+    auto t0 = std::chrono::steady_clock::now();
+    double ts = 0.0;
+    askit_status st = skel_factor_impl(t, lambda, precision, (hipStream_t)stream, out, ts);
+    t->t_skel = ts;
+    if (*out) (*out)->t_factor = ms_since(t0) - ts;
+    return st;
 }
 
 askit_status askit_factorize(askit_tree t, double lambda, int32_t precision, void *stream, askit_factor *out) {
