@@ -229,7 +229,9 @@ askit_status askit_get_stats(askit_tree t, askit_factor f, char *json, size_t ca
  * events).  Enabling resets the totals.  on = 2 keeps the totals per tree
  * height for the skeletonization and factorization launches, named
  * "phase:kernel@h<height>" (height 0 = leaves); plans built while it is on
- * keep those names. */
+ * keep those names.  on = 3 also records every launch's start and end (ms
+ * from the first profiled launch, across streams), reported as
+ * "@timeline": [[name, start, end], ...]. */
 askit_status askit_profile_enable(int32_t on);
 askit_status askit_profile_report(char *json, size_t cap);
 

@@ -252,17 +252,25 @@ def askit_get_stats(tree=None, factor=None):
     return json.loads(buf.value.decode())
 
 
-def askit_profile_enable(on=True, per_height=False):
-    """Per-kernel HIP-event timing; per_height keeps totals per tree height."""
-    _check(load().askit_profile_enable((2 if per_height else 1) if on else 0))
+def askit_profile_enable(on=True, per_height=False, timeline=False):
+    """Per-kernel HIP-event timing; per_height keeps totals per tree height,
+    timeline also every launch's start and end."""
+    _check(load().askit_profile_enable((3 if timeline else 2 if per_height else 1) if on else 0))
 
 
 def askit_profile_report():
     """{"phase:kernel": (total_ms, launches)} since profiling was enabled."""
     import json
-    buf = ctypes.create_string_buffer(1 << 16)
-    _check(load().askit_profile_report(buf, 1 << 16))
-    return {k: tuple(v) for k, v in json.loads(buf.value.decode()).items()}
+    cap = 1 << 16
+    while True:
+        buf = ctypes.create_string_buffer(cap)
+        st = load().askit_profile_report(buf, cap)
+        if st != ASKIT_ERR_ARG or cap >= 1 << 28:
+            break
+        cap *= 8
+    _check(st)
+    d = json.loads(buf.value.decode())
+    return {k: (v if k == "@timeline" else tuple(v)) for k, v in d.items()}
 
 
 def askit_tree_destroy(tree):

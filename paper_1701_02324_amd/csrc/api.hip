@@ -11,6 +11,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -73,9 +74,14 @@ struct DBuf {
     template <class T> T *as() const { return (T *)p; }
 };
 
+static askit_status copy_up(void *dst, const void *src, size_t bytes) {
+    HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    return ASKIT_OK;
+}
+
 template <class T> askit_status upload(DBuf &b, const std::vector<T> &v) {
     ST_TRY(b.alloc(sizeof(T) * std::max<size_t>(v.size(), 1)));
-    if (!v.empty()) HIP_TRY(hipMemcpy(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    if (!v.empty()) ST_TRY(copy_up(b.p, v.data(), sizeof(T) * v.size()));
     return ASKIT_OK;
 }
 
@@ -83,7 +89,7 @@ template <class T> askit_status upload(DBuf &b, const std::vector<T> &v) {
 // allocation when it fits (no hipFree, which would wait for every stream)
 template <class T> askit_status upload_grow(DBuf &b, const std::vector<T> &v) {
     if (b.bytes < sizeof(T) * std::max<size_t>(v.size(), 1)) ST_TRY(b.alloc(sizeof(T) * std::max<size_t>(v.size(), 1)));
-    if (!v.empty()) HIP_TRY(hipMemcpy(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    if (!v.empty()) ST_TRY(copy_up(b.p, v.data(), sizeof(T) * v.size()));
     return ASKIT_OK;
 }
 static askit_status grow(DBuf &b, size_t n) {
@@ -122,9 +128,12 @@ struct ProfRec {
 };
 struct Prof {
     bool on = false;
-    bool heights = false;  // label each launch with the tree height it serves
+    bool heights = false;   // label each launch with the tree height it serves
+    bool timeline = false;  // keep every launch's start and end
     std::vector<ProfRec> pend;
     std::map<std::string, std::pair<double, int64_t>> acc;
+    hipEvent_t origin = nullptr;  // times of the timeline are relative to this event
+    std::vector<std::pair<std::string, std::pair<double, double>>> tl;
 };
 Prof g_prof;
 
@@ -151,7 +160,17 @@ hipError_t prof_flush() {
         auto &v = g_prof.acc[r.name];
         v.first += ms;
         v.second += 1;
-        hipEventDestroy(r.a);
+        if (g_prof.timeline) {
+            if (!g_prof.origin) {
+                g_prof.origin = r.a;  // kept until profiling is reset
+                r.a = nullptr;
+            }
+            float t0 = 0.f, t1 = 0.f;
+            if (r.a) hipEventElapsedTime(&t0, g_prof.origin, r.a);
+            hipEventElapsedTime(&t1, g_prof.origin, r.b);
+            g_prof.tl.push_back({r.name, {t0, t1}});
+        }
+        if (r.a) hipEventDestroy(r.a);
         hipEventDestroy(r.b);
     }
     g_prof.pend.clear();
@@ -535,8 +554,12 @@ const char *askit_last_error(void) { return g_err.c_str(); }
 askit_status askit_profile_enable(int32_t on) {
     HIP_TRY(prof_flush());
     g_prof.acc.clear();
+    g_prof.tl.clear();
+    if (g_prof.origin) hipEventDestroy(g_prof.origin);
+    g_prof.origin = nullptr;
     g_prof.on = on != 0;
-    g_prof.heights = on == 2;
+    g_prof.heights = on == 2 || on == 3;
+    g_prof.timeline = on == 3;
     return ASKIT_OK;
 }
 
@@ -551,6 +574,16 @@ askit_status askit_profile_report(char *json, size_t cap) {
                  (long long)kv.second.second);
         o += b;
         first = false;
+    }
+    if (g_prof.timeline) {
+        o += first ? "\"@timeline\": [" : ", \"@timeline\": [";
+        for (size_t i = 0; i < g_prof.tl.size(); i++) {
+            char b[256];
+            snprintf(b, sizeof b, "%s[\"%s\", %.4f, %.4f]", i ? ", " : "", g_prof.tl[i].first.c_str(),
+                     g_prof.tl[i].second.first, g_prof.tl[i].second.second);
+            o += b;
+        }
+        o += "]";
     }
     o += "}";
     if (o.size() + 1 > cap) return fail(ASKIT_ERR_ARG, "buffer too small");

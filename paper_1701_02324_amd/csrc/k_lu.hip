@@ -5,186 +5,227 @@
 // One workgroup per matrix.  Column-major matrices; pivot = row of largest
 // |a| in the column, lowest row on ties; piv[k] = row exchanged with row k.
 // The factor works blocked: a panel of kPanel columns is factored with
-// rank-1 updates restricted to the panel, the row exchanges are applied to
-// the rest of the matrix, the block row of U is solved with the unit lower
-// panel triangle, and the trailing matrix receives one rank-kPanel update
-// computed with FP64 MFMA (v_mfma_f64_16x16x4f64) from LDS-staged panels.
+// rank-1 updates restricted to the panel (rows held in registers, one thread
+// per row), the row exchanges are kept as a permutation of row positions,
+// the block row of U is solved with the unit lower panel triangle, and the
+// trailing matrix receives one rank-kPanel update computed with FP64 MFMA
+// (v_mfma_f64_16x16x4f64) from the LDS-staged U block row.
 #include "askit_dev.h"
 
 namespace askit {
 
-constexpr int kLuThreads = 256;
 constexpr int kPanel = 32;
 static_assert(kLuFThreads % kWave == 0, "whole waves");
 constexpr int kLuMaxN = 512;
+static_assert(kLuFThreads >= kLuMaxN, "one thread per row of the largest matrix");
 
-__device__ inline void argmax_abs(double v, int i, double &bv, int &bi) {
-    double a = fabs(v);
-    if (a > bv || (a == bv && i < bi)) {
-        bv = a;
-        bi = i;
-    }
+// ---------------------------------------------------------------------------
+// Cross-lane reductions for the pivot search: rows of 16 lanes by DPP (quad
+// xor 1, quad xor 2, half-row mirror, row mirror), then the four row results
+// by readlane.  Every lane receives the wave's result.
+// ---------------------------------------------------------------------------
+template <int CTRL> __device__ inline int dpp_i(int x) { return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false); }
+template <int CTRL> __device__ inline double dpp_d(double x) {
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = dpp_i<CTRL>((int)b), hi = dpp_i<CTRL>((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline double readlane_d(double x, int l) {
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline double wave_max_d(double v) {
+    v = fmax(v, dpp_d<0xB1>(v));
+    v = fmax(v, dpp_d<0x4E>(v));
+    v = fmax(v, dpp_d<0x141>(v));
+    v = fmax(v, dpp_d<0x140>(v));
+    return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
+}
+__device__ inline int wave_min_i(int k) {
+    k = min(k, dpp_i<0xB1>(k));
+    k = min(k, dpp_i<0x4E>(k));
+    k = min(k, dpp_i<0x141>(k));
+    k = min(k, dpp_i<0x140>(k));
+    return min(min(__builtin_amdgcn_readlane(k, 0), __builtin_amdgcn_readlane(k, 16)),
+               min(__builtin_amdgcn_readlane(k, 32), __builtin_amdgcn_readlane(k, 48)));
 }
 
 __global__ __launch_bounds__(kLuFThreads) void k_lu(const LuTask *__restrict__ tasks) {
     constexpr int NT = kLuFThreads, NW = NT / kWave;
-    // W: the panel (column-major, ld = n - kb) while it is factored, then the
-    // U block row (row-major, ld = n); L11: the unit lower panel triangle
+    // W: the U block row (row-major, ld = n), then staging of the final row
+    // pass; L11: the unit lower panel triangle; prb: the pivot row
     __shared__ double W[kPanel * kLuMaxN];
     __shared__ double L11[kPanel * kPanel];
     __shared__ double redv[NW];
-    __shared__ int redi[NW];
+    __shared__ int redk[NW];
+    __shared__ double prb[kPanel];
     __shared__ int32_t sp[kPanel];
     // logical row i of the matrix is stored in physical row prow[i]: row
     // exchanges only swap entries here; one pass at the end puts every row
     // in place
     __shared__ int32_t prow[kLuMaxN];
-    __shared__ double s_min, s_max;
     const LuTask t = tasks[blockIdx.x];
     const int n = t.n, lda = t.lda, tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
     double *A = t.A;
-    if (tid == 0) {
-        s_min = INFINITY;
-        s_max = 0.0;
-    }
+    // smallest and largest |pivot| (every thread sees every pivot)
+    double s_min = INFINITY, s_max = 0.0;
     for (int i = tid; i < n; i += NT) prow[i] = i;
     __syncthreads();
     for (int kb = 0; kb < n; kb += kPanel) {
         const int nb = n - kb < kPanel ? n - kb : kPanel, m = n - kb;
-        // ---- panel factorization in LDS (columns kb .. kb+nb-1, rows kb .. n-1)
-        for (int e = tid; e < m * nb; e += NT) {
-            const int r = e % m, c = e / m;
-            W[e] = A[prow[kb + r] + (int64_t)(kb + c) * lda];
-        }
-        __syncthreads();
-        for (int k = 0; k < nb; k++) {
-            double bv = -1.0;
-            int bi = 0x7fffffff;
-            for (int r = k + tid; r < m; r += NT) argmax_abs(W[r + k * m], r, bv, bi);
-            for (int o = kWave / 2; o > 0; o >>= 1) {
-                const double ov = __shfl_xor(bv, o);
-                const int oi = __shfl_xor(bi, o);
-                if (ov > bv || (ov == bv && oi < bi)) {
-                    bv = ov;
-                    bi = oi;
+        // ---- panel (columns kb .. kb+nb-1, rows kb .. n-1): thread r < m
+        // holds panel row r in registers.  Rows do not move: each keeps its
+        // logical position lp and an exchange only swaps two positions, so a
+        // column step is one pivot search over the rows not chosen yet, one
+        // broadcast of the pivot row through LDS and a local rank-1 update.
+        {
+            const bool own = tid < m;
+            const int32_t arow = own ? prow[kb + tid] : 0;
+            double rw[kPanel];
+#pragma unroll
+            for (int j = 0; j < kPanel; j++) rw[j] = (own && j < nb) ? A[arow + (int64_t)(kb + j) * lda] : 0.0;
+            int lp = tid;
+            bool done = !own;
+#pragma unroll
+            for (int k = 0; k < kPanel; k++) {
+                if (k < nb) {
+                    // largest |a| of column k over the remaining rows (a NaN
+                    // counts as infinite), ties to the lowest position: the
+                    // maximum first, then the smallest key = position * 1024
+                    // + row among the rows holding it
+                    const double a = rw[k];
+                    const double v = done ? -1.0 : (a != a ? INFINITY : fabs(a));
+                    const double wm = wave_max_d(v);
+                    const int wk = wave_min_i(v == wm ? ((lp << 10) | tid) : 0x7fffffff);
+                    if (lane == 0) {
+                        redv[wave] = wm;
+                        redk[wave] = wk;
+                    }
+                    __syncthreads();
+                    double bv = redv[0];
+#pragma unroll
+                    for (int w = 1; w < NW; w++) bv = fmax(bv, redv[w]);
+                    int bk = 0x7fffffff;
+#pragma unroll
+                    for (int w = 0; w < NW; w++) bk = redv[w] == bv ? min(bk, redk[w]) : bk;
+                    const int P = bk & 1023, p = bk >> 10;
+                    if (tid == P) {
+#pragma unroll
+                        for (int j = 0; j < kPanel; j++) prb[j] = rw[j];
+                        done = true;
+                    }
+                    if (tid == 0) sp[k] = kb + p;
+                    if (lp == k) lp = p;  // the row at position k moves to p
+                    if (tid == P) lp = k;
+                    __syncthreads();
+                    const double ukk = prb[k];
+                    const double au = fabs(ukk);
+                    s_min = au == au ? fmin(s_min, au) : 0.0;
+                    s_max = fmax(s_max, au);
+                    if (!done && ukk != 0.0) {
+                        const double l = rw[k] / ukk;
+                        rw[k] = l;
+#pragma unroll
+                        for (int j = k + 1; j < kPanel; j++) rw[j] = fma(-l, prb[j], rw[j]);
+                    }
                 }
             }
-            if (lane == 0) {
-                redv[wave] = bv;
-                redi[wave] = bi;
-            }
-            __syncthreads();
-            int p = redi[0];
-            double pv = redv[0];
-            for (int w = 1; w < NW; w++)
-                if (redv[w] > pv || (redv[w] == pv && redi[w] < p)) {
-                    pv = redv[w];
-                    p = redi[w];
+            // rows stay where they are in A; their positions go into prow
+            if (own) {
+#pragma unroll
+                for (int j = 0; j < kPanel; j++)
+                    if (j < nb) A[arow + (int64_t)(kb + j) * lda] = rw[j];
+                if (lp < nb) {
+#pragma unroll
+                    for (int c = 0; c < kPanel; c++)
+                        if (c < nb) L11[lp + c * kPanel] = rw[c];
                 }
-            if (p != k && tid < nb) {
-                const double a = W[k + tid * m];
-                W[k + tid * m] = W[p + tid * m];
-                W[p + tid * m] = a;
+                prow[kb + lp] = arow;
             }
-            if (tid == 0) {
-                sp[k] = kb + p;
-                const int x = prow[kb + k];
-                prow[kb + k] = prow[kb + p];
-                prow[kb + p] = x;
-            }
-            __syncthreads();
-            const double ukk = W[k + k * m];
-            if (tid == 0) {
-                const double au = fabs(ukk);
-                s_min = fmin(s_min, au);
-                s_max = fmax(s_max, au);
-            }
-            if (ukk != 0.0)
-                for (int r = k + 1 + tid; r < m; r += NT) W[r + k * m] /= ukk;
-            __syncthreads();
-            const int rem = nb - k - 1;
-            if (ukk != 0.0 && rem > 0) {
-                const int rows = m - k - 1;
-                for (int e = tid; e < rows * rem; e += NT) {
-                    const int r = k + 1 + e % rows, j = k + 1 + e / rows;
-                    W[r + j * m] -= W[r + k * m] * W[k + j * m];
-                }
-            }
+            if (tid < nb) t.piv[kb + tid] = sp[tid];
             __syncthreads();
         }
-        // write the factored panel back; keep L11 (unit lower) in LDS
-        for (int e = tid; e < m * nb; e += NT) {
-            const int r = e % m, c = e / m;
-            A[prow[kb + r] + (int64_t)(kb + c) * lda] = W[e];
-        }
-        for (int e = tid; e < nb * nb; e += NT) {
-            const int r = e % nb, c = e / nb;
-            L11[r + c * kPanel] = W[r + c * m];
-        }
-        if (tid < nb) t.piv[kb + tid] = sp[tid];
-        __syncthreads();
         const int j0 = kb + nb, nt = n - j0;
-        if (nt <= 0) continue;
-        // ---- U block row: A[kb:kb+nb, j0:n] = L11^{-1} A[kb:kb+nb, j0:n]
-        // (solved in place in W, one column per thread)
-        for (int j = j0 + tid; j < n; j += NT) {
-            double *u = W + (j - j0);
-            for (int r = 0; r < nb; r++) u[r * n] = A[prow[kb + r] + (int64_t)j * lda];
-            for (int r = 0; r < nb; r++) {
-                double acc = u[r * n];
-                for (int c = 0; c < r; c++) acc = fma(-L11[r + c * kPanel], u[c * n], acc);
-                u[r * n] = acc;
-                A[prow[kb + r] + (int64_t)j * lda] = acc;
+        if (nt <= 0) continue;  // only the last panel can be narrower than kPanel
+        // ---- U block row: A[kb:kb+32, j0:n] = L11^{-1} A[kb:kb+32, j0:n],
+        // thread j solves column j0 + j in registers (the same operations,
+        // in the same order, as row-by-row substitution); the rows are also
+        // staged in W for the trailing update
+        if (tid < nt) {
+            const int64_t col = (int64_t)(j0 + tid) * lda;
+            double u[kPanel];
+#pragma unroll
+            for (int r = 0; r < kPanel; r++) u[r] = A[prow[kb + r] + col];
+#pragma unroll
+            for (int c = 0; c < kPanel; c++)
+#pragma unroll
+                for (int r = c + 1; r < kPanel; r++) u[r] = fma(-L11[r + c * kPanel], u[c], u[r]);
+#pragma unroll
+            for (int r = 0; r < kPanel; r++) {
+                A[prow[kb + r] + col] = u[r];
+                W[r * n + tid] = u[r];
             }
         }
-        if (nb < kPanel)
-            for (int idx = tid; idx < (kPanel - nb) * nt; idx += NT) W[(nb + idx / nt) * n + idx % nt] = 0.0;
         __syncthreads();
         // ---- trailing update A22 -= L21 U12, computed as its transpose
         // U12^T L21^T so that an accumulator register holds 16 consecutive
         // rows of a column of A22 (coalesced column-major access).  Wave w
-        // owns the 16-row stripes w, w + NW, ...; its L21 stripe stays in
-        // registers, U12 is read from LDS, four 16x16 blocks per pass.
-        const double *Up = W;
-        const int bt = (nt + 15) / 16;
-        const int row = lane % 16, kq = lane / 16;
-        for (int st = wave; st < bt; st += NW) {
-            const int i0 = st * 16;
-            double lb[kPanel / 4];
+        // takes the 16-row stripes w, w + NW, ... in 64-column blocks; the
+        // next block's A22 and L21 values are fetched before the current
+        // block's products.
+        {
+            const int bt = (nt + 15) / 16, ncb = (bt + 3) / 4;
+            const int nst = wave < bt ? (bt - wave + NW - 1) / NW : 0, nit = nst * ncb;
+            const int row = lane % 16, kq = lane / 16;
+            auto fetch = [&](int it, double (&c)[4][4], double (&l)[kPanel / 4]) {
+                const int st = wave + NW * (it / ncb), cb0 = 4 * (it % ncb), ci = st * 16 + row;
+                const int64_t rb = ci < nt ? prow[j0 + ci] : 0;
 #pragma unroll
-            for (int kk = 0; kk < kPanel / 4; kk++) {
-                const int ii = i0 + row, k = 4 * kk + kq;
-                lb[kk] = (ii < nt && k < nb) ? A[prow[j0 + ii] + (int64_t)(kb + k) * lda] : 0.0;
-            }
-            for (int cb0 = 0; cb0 < bt; cb0 += 4) {
-                dbl4 acc[4];
-                double cv[4][4];
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    acc[q] = dbl4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int r = 0; r < 4; r++) {
-                        const int ci = i0 + row, cj = (cb0 + q) * 16 + 4 * r + kq;
-                        cv[q][r] = (ci < nt && cj < nt) ? A[prow[j0 + ci] + (int64_t)(j0 + cj) * lda] : 0.0;
-                    }
-                }
-#pragma unroll
-                for (int kk = 0; kk < kPanel / 4; kk++) {
-#pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        const int cj = (cb0 + q) * 16 + row;
-                        const double ua = cj < nt ? Up[(4 * kk + kq) * n + cj] : 0.0;
-                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua, lb[kk], acc[q], 0, 0, 0);
-                    }
-                }
-                // acc[q][r] = (U12^T L21^T)[4r + lane/16][lane%16] = A22 entry (i0 + lane%16, (cb0+q)*16 + 4r + lane/16)
+                for (int kk = 0; kk < kPanel / 4; kk++)
+                    l[kk] = ci < nt ? A[rb + (int64_t)(kb + 4 * kk + kq) * lda] : 0.0;
 #pragma unroll
                 for (int q = 0; q < 4; q++)
 #pragma unroll
                     for (int r = 0; r < 4; r++) {
-                        const int ci = i0 + row, cj = (cb0 + q) * 16 + 4 * r + kq;
-                        if (ci < nt && cj < nt) A[prow[j0 + ci] + (int64_t)(j0 + cj) * lda] = cv[q][r] - acc[q][r];
+                        const int cj = (cb0 + q) * 16 + 4 * r + kq;
+                        c[q][r] = (ci < nt && cj < nt) ? A[rb + (int64_t)(j0 + cj) * lda] : 0.0;
                     }
+            };
+            auto update = [&](int it, const double (&c)[4][4], const double (&l)[kPanel / 4]) {
+                const int st = wave + NW * (it / ncb), cb0 = 4 * (it % ncb), ci = st * 16 + row;
+                dbl4 acc[4];
+#pragma unroll
+                for (int q = 0; q < 4; q++) acc[q] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kk = 0; kk < kPanel / 4; kk++)
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const int cj = (cb0 + q) * 16 + row;
+                        const double ua = cj < nt ? W[(4 * kk + kq) * n + cj] : 0.0;
+                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua, l[kk], acc[q], 0, 0, 0);
+                    }
+                // acc[q][r] = A22 entry (st*16 + lane%16, (cb0+q)*16 + 4r + lane/16)
+                if (ci < nt) {
+                    const int64_t rb = prow[j0 + ci];
+#pragma unroll
+                    for (int q = 0; q < 4; q++)
+#pragma unroll
+                        for (int r = 0; r < 4; r++) {
+                            const int cj = (cb0 + q) * 16 + 4 * r + kq;
+                            if (cj < nt) A[rb + (int64_t)(j0 + cj) * lda] = c[q][r] - acc[q][r];
+                        }
+                }
+            };
+            double c0[4][4], l0[kPanel / 4], c1[4][4], l1[kPanel / 4];
+            if (nit > 0) fetch(0, c0, l0);
+            for (int it = 0; it < nit; it += 2) {
+                if (it + 1 < nit) fetch(it + 1, c1, l1);
+                update(it, c0, l0);
+                if (it + 1 < nit) {
+                    if (it + 2 < nit) fetch(it + 2, c0, l0);
+                    update(it + 1, c1, l1);
+                }
             }
         }
         __syncthreads();
