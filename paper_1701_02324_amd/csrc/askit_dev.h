@@ -19,6 +19,13 @@ constexpr int kLsThreads = 1024; // batched LU solves: 16 waves keep many block 
 constexpr int kLuFThreads = 512; // batched LU factorization
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Pointers taken from task structs are generic (flat) to the compiler, and
+// flat loads count against the LDS wait counter too: a kernel that waits for
+// an LDS read then also waits for every global load in flight.  Kernels hold
+// such pointers as global-address-space pointers (GLB) instead.
+#define GLB __attribute__((address_space(1)))
+template <class T> __device__ __forceinline__ GLB T *glb(T *p) { return (GLB T *)p; }
 typedef float flt4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------

@@ -51,10 +51,79 @@ __device__ inline int wave_min_i(int k) {
                min(__builtin_amdgcn_readlane(k, 32), __builtin_amdgcn_readlane(k, 48)));
 }
 
+// ---------------------------------------------------------------------------
+// Trailing update A22 -= L21 U12 of a blocked LU (panel columns kb..kb+31,
+// trailing rows and columns from j0, nt of them), computed as its transpose
+// U12^T L21^T so that an accumulator register holds 16 consecutive rows of a
+// column of A22 (coalesced column-major access).  Logical row i of A is
+// physical row rowof(i).  U12 is staged in LDS, row-major with leading
+// dimension ldw = nt rounded up to 64, zero beyond column nt.  Wave w takes
+// the 16-row stripes w, w + NW, ... in 64-column blocks; the next block's
+// A22 and L21 values are fetched before the current block's products, and
+// each block's 32 U12 operands are read from LDS before its 32 products.
+// ---------------------------------------------------------------------------
+template <int NW, class RowOf>
+__device__ inline void trailing_update(GLB double *A, int lda, int kb, int j0, int nt, const double *W, int ldw,
+                                       RowOf rowof, int wave, int lane) {
+    const int bt = (nt + 15) / 16, ncb = ldw / 64;
+    const int nst = wave < bt ? (bt - wave + NW - 1) / NW : 0, nit = nst * ncb;
+    const int row = lane % 16, kq = lane / 16;
+    auto fetch = [&](int it, double (&c)[4][4], double (&l)[kPanel / 4]) {
+        const int st = wave + NW * (it / ncb), cb0 = 4 * (it % ncb), ci = st * 16 + row;
+        const int64_t rb = ci < nt ? rowof(j0 + ci) : 0;
+#pragma unroll
+        for (int kk = 0; kk < kPanel / 4; kk++) l[kk] = ci < nt ? A[rb + (int64_t)(kb + 4 * kk + kq) * lda] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int cj = (cb0 + q) * 16 + 4 * r + kq;
+                c[q][r] = (ci < nt && cj < nt) ? A[rb + (int64_t)(j0 + cj) * lda] : 0.0;
+            }
+    };
+    auto update = [&](int it, const double (&c)[4][4], const double (&l)[kPanel / 4]) {
+        const int st = wave + NW * (it / ncb), cb0 = 4 * (it % ncb), ci = st * 16 + row;
+        double ua[kPanel / 4][4];
+#pragma unroll
+        for (int kk = 0; kk < kPanel / 4; kk++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) ua[kk][q] = W[(4 * kk + kq) * ldw + (cb0 + q) * 16 + row];
+        dbl4 acc[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) acc[q] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < kPanel / 4; kk++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[kk][q], l[kk], acc[q], 0, 0, 0);
+        // acc[q][r] = A22 entry (st*16 + lane%16, (cb0+q)*16 + 4r + lane/16)
+        if (ci < nt) {
+            const int64_t rb = rowof(j0 + ci);
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int cj = (cb0 + q) * 16 + 4 * r + kq;
+                    if (cj < nt) A[rb + (int64_t)(j0 + cj) * lda] = c[q][r] - acc[q][r];
+                }
+        }
+    };
+    double c0[4][4], l0[kPanel / 4], c1[4][4], l1[kPanel / 4];
+    if (nit > 0) fetch(0, c0, l0);
+    for (int it = 0; it < nit; it += 2) {
+        if (it + 1 < nit) fetch(it + 1, c1, l1);
+        update(it, c0, l0);
+        if (it + 1 < nit) {
+            if (it + 2 < nit) fetch(it + 2, c0, l0);
+            update(it + 1, c1, l1);
+        }
+    }
+}
+
 __global__ __launch_bounds__(kLuFThreads) void k_lu(const LuTask *__restrict__ tasks) {
     constexpr int NT = kLuFThreads, NW = NT / kWave;
-    // W: the U block row (row-major, ld = n), then staging of the final row
-    // pass; L11: the unit lower panel triangle; prb: the pivot row
+    // W: the U block row (row-major, ld = nt rounded up to 64), then staging
+    // of the final row pass; L11: the unit lower panel triangle; prb: the
+    // pivot row
     __shared__ double W[kPanel * kLuMaxN];
     __shared__ double L11[kPanel * kPanel];
     __shared__ double redv[NW];
@@ -67,7 +136,7 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu(const LuTask *__restrict__ t
     __shared__ int32_t prow[kLuMaxN];
     const LuTask t = tasks[blockIdx.x];
     const int n = t.n, lda = t.lda, tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
-    double *A = t.A;
+    GLB double *A = glb(t.A);
     // smallest and largest |pivot| (every thread sees every pivot)
     double s_min = INFINITY, s_max = 0.0;
     for (int i = tid; i < n; i += NT) prow[i] = i;
@@ -143,7 +212,7 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu(const LuTask *__restrict__ t
                 }
                 prow[kb + lp] = arow;
             }
-            if (tid < nb) t.piv[kb + tid] = sp[tid];
+            if (tid < nb) glb(t.piv)[kb + tid] = sp[tid];
             __syncthreads();
         }
         const int j0 = kb + nb, nt = n - j0;
@@ -151,7 +220,12 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu(const LuTask *__restrict__ t
         // ---- U block row: A[kb:kb+32, j0:n] = L11^{-1} A[kb:kb+32, j0:n],
         // thread j solves column j0 + j in registers (the same operations,
         // in the same order, as row-by-row substitution); the rows are also
-        // staged in W for the trailing update
+        // staged in W for the trailing update, zero-padded to ldw columns
+        const int ldw = (nt + 63) & ~63;
+        if (tid >= nt && tid < ldw) {
+#pragma unroll
+            for (int r = 0; r < kPanel; r++) W[r * ldw + tid] = 0.0;
+        }
         if (tid < nt) {
             const int64_t col = (int64_t)(j0 + tid) * lda;
             double u[kPanel];
@@ -164,70 +238,11 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu(const LuTask *__restrict__ t
 #pragma unroll
             for (int r = 0; r < kPanel; r++) {
                 A[prow[kb + r] + col] = u[r];
-                W[r * n + tid] = u[r];
+                W[r * ldw + tid] = u[r];
             }
         }
         __syncthreads();
-        // ---- trailing update A22 -= L21 U12, computed as its transpose
-        // U12^T L21^T so that an accumulator register holds 16 consecutive
-        // rows of a column of A22 (coalesced column-major access).  Wave w
-        // takes the 16-row stripes w, w + NW, ... in 64-column blocks; the
-        // next block's A22 and L21 values are fetched before the current
-        // block's products.
-        {
-            const int bt = (nt + 15) / 16, ncb = (bt + 3) / 4;
-            const int nst = wave < bt ? (bt - wave + NW - 1) / NW : 0, nit = nst * ncb;
-            const int row = lane % 16, kq = lane / 16;
-            auto fetch = [&](int it, double (&c)[4][4], double (&l)[kPanel / 4]) {
-                const int st = wave + NW * (it / ncb), cb0 = 4 * (it % ncb), ci = st * 16 + row;
-                const int64_t rb = ci < nt ? prow[j0 + ci] : 0;
-#pragma unroll
-                for (int kk = 0; kk < kPanel / 4; kk++)
-                    l[kk] = ci < nt ? A[rb + (int64_t)(kb + 4 * kk + kq) * lda] : 0.0;
-#pragma unroll
-                for (int q = 0; q < 4; q++)
-#pragma unroll
-                    for (int r = 0; r < 4; r++) {
-                        const int cj = (cb0 + q) * 16 + 4 * r + kq;
-                        c[q][r] = (ci < nt && cj < nt) ? A[rb + (int64_t)(j0 + cj) * lda] : 0.0;
-                    }
-            };
-            auto update = [&](int it, const double (&c)[4][4], const double (&l)[kPanel / 4]) {
-                const int st = wave + NW * (it / ncb), cb0 = 4 * (it % ncb), ci = st * 16 + row;
-                dbl4 acc[4];
-#pragma unroll
-                for (int q = 0; q < 4; q++) acc[q] = dbl4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int kk = 0; kk < kPanel / 4; kk++)
-#pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        const int cj = (cb0 + q) * 16 + row;
-                        const double ua = cj < nt ? W[(4 * kk + kq) * n + cj] : 0.0;
-                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua, l[kk], acc[q], 0, 0, 0);
-                    }
-                // acc[q][r] = A22 entry (st*16 + lane%16, (cb0+q)*16 + 4r + lane/16)
-                if (ci < nt) {
-                    const int64_t rb = prow[j0 + ci];
-#pragma unroll
-                    for (int q = 0; q < 4; q++)
-#pragma unroll
-                        for (int r = 0; r < 4; r++) {
-                            const int cj = (cb0 + q) * 16 + 4 * r + kq;
-                            if (cj < nt) A[rb + (int64_t)(j0 + cj) * lda] = c[q][r] - acc[q][r];
-                        }
-                }
-            };
-            double c0[4][4], l0[kPanel / 4], c1[4][4], l1[kPanel / 4];
-            if (nit > 0) fetch(0, c0, l0);
-            for (int it = 0; it < nit; it += 2) {
-                if (it + 1 < nit) fetch(it + 1, c1, l1);
-                update(it, c0, l0);
-                if (it + 1 < nit) {
-                    if (it + 2 < nit) fetch(it + 2, c0, l0);
-                    update(it + 1, c1, l1);
-                }
-            }
-        }
+        trailing_update<NW>(A, lda, kb, j0, nt, W, ldw, [&](int i) -> int64_t { return prow[i]; }, wave, lane);
         __syncthreads();
     }
     // rows in place: column batches of kPanel staged in W
@@ -244,7 +259,7 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu(const LuTask *__restrict__ t
         }
         __syncthreads();
     }
-    if (tid == 0 && t.ratio) *t.ratio = n ? (s_max > 0.0 ? s_min / s_max : 0.0) : 1.0;
+    if (tid == 0 && t.ratio) *glb(t.ratio) = n ? (s_max > 0.0 ? s_min / s_max : 0.0) : 1.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -259,19 +274,19 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu(const LuTask *__restrict__ t
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kLuFThreads) void k_lu_nopiv(const LuTask *__restrict__ tasks) {
     constexpr int NT = kLuFThreads, NW = NT / kWave, DL = kPanel + 1;
-    __shared__ double Up[kPanel * kLuMaxN];  // U block row (row-major, ld = n)
+    __shared__ double Up[kPanel * kLuMaxN];  // U block row (row-major, ld = nt rounded up to 64)
     __shared__ double Dg[kPanel * DL];       // factored diagonal block (row-major)
     __shared__ double LI[kPanel * DL];       // L11^{-1} (row-major)
     __shared__ double UI[kPanel * DL];       // U11^{-1} (row-major)
     __shared__ double s_min, s_max;
     const LuTask t = tasks[blockIdx.x];
     const int n = t.n, lda = t.lda, tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
-    double *A = t.A;
+    GLB double *A = glb(t.A);
     if (tid == 0) {
         s_min = INFINITY;
         s_max = 0.0;
     }
-    for (int i = tid; i < n; i += NT) t.piv[i] = i;
+    for (int i = tid; i < n; i += NT) glb(t.piv)[i] = i;
     for (int kb = 0; kb < n; kb += kPanel) {
         const int nb = n - kb < kPanel ? n - kb : kPanel;
         // ---- diagonal block, factored by wave 0: lane i < nb holds row i in
@@ -284,13 +299,13 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu_nopiv(const LuTask *__restri
                 rw[j] = (lane < nb && j < nb) ? A[kb + lane + (int64_t)(kb + j) * lda] : (lane == j ? 1.0 : 0.0);
 #pragma unroll
             for (int k = 0; k < kPanel; k++) {
-                const double ukk = __shfl(rw[k], k);
+                const double ukk = readlane_d(rw[k], k);
                 const bool act = k < nb && lane > k && lane < nb;
                 const double l = (act && ukk != 0.0) ? rw[k] / ukk : 0.0;
                 if (act) rw[k] = l;
 #pragma unroll
                 for (int j = k + 1; j < kPanel; j++) {
-                    const double pj = __shfl(rw[j], k);
+                    const double pj = readlane_d(rw[j], k);
                     if (act) rw[j] = fma(-l, pj, rw[j]);
                 }
             }
@@ -305,30 +320,36 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu_nopiv(const LuTask *__restri
             }
         }
         __syncthreads();
-        // ---- inverses of the triangles (column j of U^{-1}: thread j; of
-        // L^{-1}: thread 64 + j), pivot magnitudes
-        if (tid < kPanel) {
-            const int j = tid;
-#pragma unroll 1
+        // ---- inverses of the triangles, one column per lane in registers:
+        // column j of U^{-1} by lane j of wave 1, of L^{-1} by lane j of
+        // wave 2 (terms with a zero factor included: they leave the sums
+        // unchanged); pivot magnitudes by wave 3
+        if (wave == 1 && lane < kPanel) {
+            const int j = lane;
+            double x[kPanel];
+#pragma unroll
             for (int i = kPanel - 1; i >= 0; i--) {
                 double acc = i == j ? 1.0 : 0.0;
-                if (i < j)
-#pragma unroll 1
-                    for (int k = i + 1; k <= j; k++) acc = fma(-Dg[i * DL + k], UI[k * DL + j], acc);
+#pragma unroll
+                for (int k = i + 1; k < kPanel; k++) acc = fma(-Dg[i * DL + k], x[k], acc);
                 const double u = Dg[i * DL + i];
-                UI[i * DL + j] = i > j ? 0.0 : (u != 0.0 ? acc / u : 0.0);
+                x[i] = i > j ? 0.0 : (u != 0.0 ? acc / u : 0.0);
             }
-        } else if (tid >= kWave && tid < kWave + kPanel) {
-            const int j = tid - kWave;
-#pragma unroll 1
+#pragma unroll
+            for (int i = 0; i < kPanel; i++) UI[i * DL + j] = x[i];
+        } else if (wave == 2 && lane < kPanel) {
+            const int j = lane;
+            double x[kPanel];
+#pragma unroll
             for (int i = 0; i < kPanel; i++) {
                 double acc = i == j ? 1.0 : 0.0;
-                if (i > j)
-#pragma unroll 1
-                    for (int k = j; k < i; k++) acc = fma(-Dg[i * DL + k], LI[k * DL + j], acc);
-                LI[i * DL + j] = i < j ? 0.0 : acc;
+#pragma unroll
+                for (int k = 0; k < i; k++) acc = fma(-Dg[i * DL + k], x[k], acc);
+                x[i] = i < j ? 0.0 : acc;
             }
-        } else if (tid == 2 * kWave) {
+#pragma unroll
+            for (int i = 0; i < kPanel; i++) LI[i * DL + j] = x[i];
+        } else if (wave == 3 && lane == 0) {
             for (int i = 0; i < nb; i++) {
                 const double au = fabs(Dg[i * DL + i]);
                 s_min = fmin(s_min, au);
@@ -362,7 +383,10 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu_nopiv(const LuTask *__restri
                     if (r < nt) A[j0 + r + (int64_t)(kb + cb * 16 + rr) * lda] = acc[cb][q];
                 }
         }
-        // ---- U12 = L11^{-1} A12, 16-column blocks (also staged in Up)
+        // ---- U12 = L11^{-1} A12, 16-column blocks (also staged in Up,
+        // zero-padded to ldw columns)
+        const int ldw = (nt + 63) & ~63;
+        for (int e = tid; e < kPanel * (ldw - nt); e += NT) Up[(e / (ldw - nt)) * ldw + nt + e % (ldw - nt)] = 0.0;
 #pragma unroll 1
         for (int cbk = wave; cbk < (nt + 15) / 16; cbk += NW) {
             const int c0 = cbk * 16;
@@ -384,56 +408,16 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu_nopiv(const LuTask *__restri
                     const int r = rb * 16 + 4 * q + kq, c = c0 + rr;
                     if (c < nt) {
                         A[kb + r + (int64_t)(j0 + c) * lda] = acc[rb][q];
-                        Up[r * n + c] = acc[rb][q];
+                        Up[r * ldw + c] = acc[rb][q];
                     }
                 }
         }
         __syncthreads();
-        // ---- trailing update A22 -= L21 U12 (as in k_lu)
-        const int bt = (nt + 15) / 16;
-#pragma unroll 1
-        for (int st = wave; st < bt; st += NW) {
-            const int i0 = st * 16;
-            double lb[kPanel / 4];
-#pragma unroll
-            for (int kk = 0; kk < kPanel / 4; kk++) {
-                const int ii = i0 + rr, k = 4 * kk + kq;
-                lb[kk] = ii < nt ? A[j0 + ii + (int64_t)(kb + k) * lda] : 0.0;
-            }
-#pragma unroll 1
-            for (int cb0 = 0; cb0 < bt; cb0 += 4) {
-                dbl4 acc[4];
-                double cv[4][4];
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    acc[q] = dbl4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int r = 0; r < 4; r++) {
-                        const int ci = i0 + rr, cj = (cb0 + q) * 16 + 4 * r + kq;
-                        cv[q][r] = (ci < nt && cj < nt) ? A[j0 + ci + (int64_t)(j0 + cj) * lda] : 0.0;
-                    }
-                }
-#pragma unroll
-                for (int kk = 0; kk < kPanel / 4; kk++) {
-#pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        const int cj = (cb0 + q) * 16 + rr;
-                        const double ua = cj < nt ? Up[(4 * kk + kq) * n + cj] : 0.0;
-                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua, lb[kk], acc[q], 0, 0, 0);
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < 4; q++)
-#pragma unroll
-                    for (int r = 0; r < 4; r++) {
-                        const int ci = i0 + rr, cj = (cb0 + q) * 16 + 4 * r + kq;
-                        if (ci < nt && cj < nt) A[j0 + ci + (int64_t)(j0 + cj) * lda] = cv[q][r] - acc[q][r];
-                    }
-            }
-        }
+        // ---- trailing update A22 -= L21 U12
+        trailing_update<NW>(A, lda, kb, j0, nt, Up, ldw, [](int i) -> int64_t { return i; }, wave, lane);
         __syncthreads();
     }
-    if (tid == 0 && t.ratio) *t.ratio = n ? (s_max > 0.0 ? s_min / s_max : 0.0) : 1.0;
+    if (tid == 0 && t.ratio) *glb(t.ratio) = n ? (s_max > 0.0 ? s_min / s_max : 0.0) : 1.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -448,11 +432,11 @@ __global__ __launch_bounds__(256) void k_lu_diaginv(const LuTask *__restrict__ t
     for (int job = threadIdx.x; job < nb * 32; job += blockDim.x) {
         const int b = job / 32, j = job % 16, upper = (job % 32) / 16, b0 = b * 16;
         double x[16];
-        double *out = t.dinv + ((int64_t)(2 * b + upper)) * 256;
+        GLB double *out = glb(t.dinv) + ((int64_t)(2 * b + upper)) * 256;
         auto a = [&](int r, int c) -> double {
             int gr = b0 + r, gc = b0 + c;
             if (gr >= n || gc >= n) return r == c ? 1.0 : 0.0;
-            return t.A[gr + (int64_t)gc * lda];
+            return glb((const double *)t.A)[gr + (int64_t)gc * lda];
         };
         if (!upper) {  // x = L^{-1} e_j, unit diagonal
             for (int i = 0; i < 16; i++) {
@@ -480,7 +464,7 @@ __global__ __launch_bounds__(256) void k_lu_diaginv(const LuTask *__restrict__ t
 // receive a rank-16 update, both on the FP64 matrix cores.
 // ---------------------------------------------------------------------------
 template <int NR>
-__device__ inline void diag_apply(double (*S)[NR + 1], int r0, const double *D, bool transD, int lane, int wave) {
+__device__ inline void diag_apply(double (*S)[NR + 1], int r0, const GLB double *D, bool transD, int lane, int wave) {
     // S[r0:r0+16, :] = D' S[r0:r0+16, :] with D' = D or D^T (16 x 16, column-major)
     constexpr int CB = NR / 16;
     dbl4 acc = {0, 0, 0, 0};
@@ -553,8 +537,10 @@ __global__ __launch_bounds__(kLsThreads) void k_lusolve(const LuTask *__restrict
     if (c0 >= nrhs) return;
     const int ncols = min(NR, nrhs - c0);
     const int n = t.n, lda = t.lda, nb = (n + 15) / 16, tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
-    const double *A = t.A;
-    T *B = (T *)t.B;
+    const GLB double *A = glb((const double *)t.A);
+    GLB T *B = glb((T *)t.B);
+    const GLB double *dinv = glb((const double *)t.dinv);
+    const GLB int32_t *piv = glb((const int32_t *)t.piv);
     for (int i = tid; i < nb * 16 * NR; i += kLsThreads) {
         const int r = i / NR, c = i % NR;
         S[r][c] = (r < n && c < ncols) ? (double)B[(int64_t)r * t.ldb + c0 + c] : 0.0;
@@ -565,7 +551,7 @@ __global__ __launch_bounds__(kLsThreads) void k_lusolve(const LuTask *__restrict
     if (!TRANS) {
         if (tid < NR)
             for (int k = 0; k < n; k++) {
-                const int p = t.piv[k];
+                const int p = piv[k];
                 if (p != k) {
                     double a = S[k][tid];
                     S[k][tid] = S[p][tid];
@@ -574,27 +560,27 @@ __global__ __launch_bounds__(kLsThreads) void k_lusolve(const LuTask *__restrict
             }
         __syncthreads();
         for (int ib = 0; ib < nb; ib++) {  // L y = P b
-            diag_apply<NR>(S, ib * 16, t.dinv + (int64_t)(2 * ib) * 256, false, lane, wave);
+            diag_apply<NR>(S, ib * 16, dinv + (int64_t)(2 * ib) * 256, false, lane, wave);
             block_update<NR>(S, ib * 16, ib + 1, nb, Lget, lane, wave);
         }
         for (int ib = nb - 1; ib >= 0; ib--) {  // U x = y
-            diag_apply<NR>(S, ib * 16, t.dinv + (int64_t)(2 * ib + 1) * 256, false, lane, wave);
+            diag_apply<NR>(S, ib * 16, dinv + (int64_t)(2 * ib + 1) * 256, false, lane, wave);
             block_update<NR>(S, ib * 16, 0, ib, Uget, lane, wave);
         }
     } else {
         auto UTget = [&](int r, int c) -> double { return Uget(c, r); };
         auto LTget = [&](int r, int c) -> double { return Lget(c, r); };
         for (int ib = 0; ib < nb; ib++) {  // U^T z = b
-            diag_apply<NR>(S, ib * 16, t.dinv + (int64_t)(2 * ib + 1) * 256, true, lane, wave);
+            diag_apply<NR>(S, ib * 16, dinv + (int64_t)(2 * ib + 1) * 256, true, lane, wave);
             block_update<NR>(S, ib * 16, ib + 1, nb, UTget, lane, wave);
         }
         for (int ib = nb - 1; ib >= 0; ib--) {  // L^T w = z
-            diag_apply<NR>(S, ib * 16, t.dinv + (int64_t)(2 * ib) * 256, true, lane, wave);
+            diag_apply<NR>(S, ib * 16, dinv + (int64_t)(2 * ib) * 256, true, lane, wave);
             block_update<NR>(S, ib * 16, 0, ib, LTget, lane, wave);
         }
         if (tid < NR)
             for (int k = n - 1; k >= 0; k--) {
-                const int p = t.piv[k];
+                const int p = piv[k];
                 if (p != k) {
                     double a = S[k][tid];
                     S[k][tid] = S[p][tid];

@@ -78,8 +78,8 @@ __global__ __launch_bounds__(256) void k_leaf_block(const LeafTask *__restrict__
     const int nr = min(64, t.n - r0), nc = min(64, t.n - c0);
     for (int i = threadIdx.x; i < 64 * d; i += blockDim.x) {
         const int a = i / d, k = i % d;
-        ys[a * dp + k] = a < nr ? t.X[(t.b + r0 + a) * d + k] : 0.0;
-        xs[i] = a < nc ? t.X[(t.b + c0 + a) * d + k] : 0.0;
+        ys[a * dp + k] = a < nr ? glb(t.X)[(t.b + r0 + a) * d + k] : 0.0;
+        xs[i] = a < nc ? glb(t.X)[(t.b + c0 + a) * d + k] : 0.0;
     }
     __syncthreads();
     const int r = threadIdx.x % 64;
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void k_leaf_block(const LeafTask *__restrict__
         }
         double v = exp(r2 * t.scale);
         if (r0 + r == c0 + c) v += t.lambda;
-        t.A[(r0 + r) + (int64_t)(c0 + c) * t.lda] = v;
+        glb(t.A)[(r0 + r) + (int64_t)(c0 + c) * t.lda] = v;
     }
 }
 
@@ -103,7 +103,7 @@ __global__ void k_identity(const IdTask *__restrict__ tasks, int bpm) {
     const IdTask t = tasks[blockIdx.x / bpm];
     const int64_t e = (int64_t)(blockIdx.x % bpm) * blockDim.x + threadIdx.x;
     if (e >= (int64_t)t.n * t.n) return;
-    t.Z[e] = (e % t.n == e / t.n) ? 1.0 : 0.0;
+    glb(t.Z)[e] = (e % t.n == e / t.n) ? 1.0 : 0.0;
 }
 
 // dst(r, c) = src(r, c) with precision conversion; grid = task * rowblocks + rb
@@ -113,7 +113,7 @@ __global__ void k_copy(const CopyTask *__restrict__ tasks, int rowblocks) {
     const int64_t e = (int64_t)(blockIdx.x % rowblocks) * blockDim.x + threadIdx.x;
     if (e >= (int64_t)t.rows * t.cols) return;
     const int64_t r = e / t.cols, c = e % t.cols;
-    ((TD *)t.dst)[r * t.dld + c] = (TD)((const TS *)t.src)[r * t.sld + c];
+    glb((TD *)t.dst)[r * t.dld + c] = (TD)glb((const TS *)t.src)[r * t.sld + c];
 }
 
 // Y(r, c) += a * X(r, c) over n rows x nrhs columns (row-major, stride ld)

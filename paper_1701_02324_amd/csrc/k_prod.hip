@@ -42,15 +42,15 @@ __device__ inline float kexp(float x) { return expf(x); }
 constexpr int kTR = 64;   // tile rows
 constexpr int kKS = 16;   // contraction per stage
 
-template <typename T>
-__device__ inline void store_out(T *C, int64_t off, T v, int op) {
+template <typename P, typename T>
+__device__ inline void store_out(P C, int64_t off, T v, int op) {
     if (op == OP_STORE) C[off] = v;
     else if (op == OP_ADD) C[off] += v;
     else C[off] -= v;
 }
 
-__device__ inline int src_count(const PtSrc &s) { return s.cnt ? *s.cnt : s.n; }
-__device__ inline int64_t src_pos(const PtSrc &s, int i) { return s.idx ? (int64_t)s.idx[i] : s.base + i; }
+__device__ inline int src_count(const PtSrc &s) { return s.cnt ? *glb(s.cnt) : s.n; }
+__device__ inline int64_t src_pos(const PtSrc &s, int i) { return s.idx ? (int64_t)glb(s.idx)[i] : s.base + i; }
 
 template <typename T, typename TB, typename TO, int TC>
 __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, const TileItem *__restrict__ items,
@@ -70,7 +70,8 @@ __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, 
     const int nrow = src_count(t.R);
     if (t.ncol > 0) ncol = min(ncol, t.ncol);
     const int r0 = it.rt * kTR, c0 = it.ct * TC;
-    TO *C = (TO *)t.C;
+    GLB TO *C = glb((TO *)t.C);
+    const GLB double *X = glb(t.X);
     if (r0 >= nrow) {  // tile of padded rows: zero-fill on store
         if (t.op == OP_STORE)
             for (int i = tid; i < kTR * TC; i += 256) {
@@ -80,16 +81,16 @@ __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, 
         return;
     }
     int k1 = t.k1;
-    if (t.S.cnt) k1 = min(k1, *t.S.cnt);
+    if (t.S.cnt) k1 = min(k1, *glb(t.S.cnt));
     const T scale = (T)t.scale, hinv = (T)t.hinv;
     // stage the row points (fixed for the whole contraction)
     for (int i = tid; i < kTR * d; i += 256) {
         int r = i / d, k = i % d;
-        sR[r * dp + k] = r0 + r < nrow ? (T)t.X[src_pos(t.R, r0 + r) * d + k] : (T)0;
+        sR[r * dp + k] = r0 + r < nrow ? (T)X[src_pos(t.R, r0 + r) * d + k] : (T)0;
     }
     typename Acc<T>::type acc[NB];
     for (int b = 0; b < NB; b++) acc[b] = typename Acc<T>::type{0, 0, 0, 0};
-    const TB *B = (const TB *)t.B;
+    const GLB TB *B = glb((const TB *)t.B);
     // the next stage's contraction points and B rows are fetched into
     // registers while the current stage is generated and multiplied
     constexpr int PS = kKS * kMaxDim / 256, PB = kKS * TC / 256;
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, 
 #pragma unroll
         for (int u = 0; u < PS; u++) {
             const int i = tid + u * 256, r = i / d, k = i % d;
-            pS[u] = (i < kKS * d && r < kn) ? (T)t.X[src_pos(t.S, ks + r) * d + k] : (T)0;
+            pS[u] = (i < kKS * d && r < kn) ? (T)X[src_pos(t.S, ks + r) * d + k] : (T)0;
         }
 #pragma unroll
         for (int u = 0; u < PB; u++) {
@@ -177,7 +178,7 @@ __global__ __launch_bounds__(256) void k_gmm(const GmmTask *__restrict__ tasks, 
     if (t.ncol > 0) ncol = min(ncol, t.ncol);
     // optional split of the contraction: item.pad = chunk index
     const int kb = it.pad * kchunk, ke = min(t.kdim, kb + kchunk);
-    const T *A = (const T *)t.A, *B = (const T *)t.B;
+    const GLB T *A = glb((const T *)t.A), *B = glb((const T *)t.B);
     const bool a_kfast = (t.acs == 1), b_cfast = (t.bcs == 1);
     typename Acc<T>::type acc[NB];
     for (int b = 0; b < NB; b++) acc[b] = typename Acc<T>::type{0, 0, 0, 0};
@@ -235,7 +236,7 @@ __global__ __launch_bounds__(256) void k_gmm(const GmmTask *__restrict__ tasks, 
             }
         }
     }
-    T *C = (T *)t.C;
+    GLB T *C = glb((T *)t.C);
 #pragma unroll
     for (int b = 0; b < NB; b++) {
         const int c = c0 + b * 16 + lane % 16;
@@ -255,10 +256,10 @@ __global__ void k_reduce(const RedTask *__restrict__ tasks, int ncol, int blocks
     if (t.ncol > 0) ncol = min(ncol, t.ncol);
     if (e >= (int64_t)t.rows * ncol) return;
     const int r = (int)(e / ncol), c = (int)(e % ncol);
-    const T *src = (const T *)t.src;
+    const GLB T *src = glb((const T *)t.src);
     double acc = 0.0;
     for (int p = 0; p < t.np; p++) acc += (double)src[p * t.pstride + (int64_t)r * t.prs + c];
-    store_out((TO *)t.dst, (int64_t)r * t.drs + (int64_t)c * t.dcs, (TO)acc, t.op);
+    store_out(glb((TO *)t.dst), (int64_t)r * t.drs + (int64_t)c * t.dcs, (TO)acc, t.op);
 }
 
 #define KMM_INST(T, TB, TO, TC) \

@@ -12,6 +12,8 @@
 //    T = R11^{-1} R12 and the projection P = [I T] Pi^T, written transposed.
 #include "askit_dev.h"
 
+#include <type_traits>
+
 namespace askit {
 
 // ---------------------------------------------------------------------------
@@ -74,7 +76,7 @@ __global__ __launch_bounds__(64) void k_sample(const SampTask *__restrict__ task
 // ---------------------------------------------------------------------------
 __device__ inline int32_t cand_pos(const SkelTask &t, int c, int sl) {
     if (t.leaf) return (int32_t)(t.b + c);
-    return c < sl ? t.skl[c] : t.skr[c - sl];
+    return c < sl ? glb(t.skl)[c] : glb(t.skr)[c - sl];
 }
 
 __device__ inline double sqdist(const double *x, const double *y, int d) {
@@ -100,21 +102,23 @@ __global__ __launch_bounds__(256) void k_sample_block(const SkelTask *__restrict
     const int task = blockIdx.x / per, rt = (blockIdx.x % per) % rowtiles, ct = (blockIdx.x % per) / rowtiles;
     const SkelTask t = tasks[task];
     const int r0 = rt * 64, c0 = ct * 64;
-    const int sl = t.leaf ? 0 : *t.srl;
-    const int ncand = t.leaf ? t.n : sl + *t.srr;
+    const int sl = t.leaf ? 0 : *glb(t.srl);
+    const int ncand = t.leaf ? t.n : sl + *glb(t.srr);
+    const GLB double *X = glb(t.X);
+    const GLB int32_t *q = glb(t.q);
     if (r0 >= t.nq || c0 >= ncand) return;
     const int nr = min(64, t.nq - r0), nc = min(64, ncand - c0);
     for (int i = threadIdx.x; i < 64 * d; i += blockDim.x) {
         const int a = i / d, k = i % d;
-        ys[a * dp + k] = a < nr ? t.X[(int64_t)t.q[r0 + a] * d + k] : 0.0;
-        xs[i] = a < nc ? t.X[(int64_t)cand_pos(t, c0 + a, sl) * d + k] : 0.0;
+        ys[a * dp + k] = a < nr ? X[(int64_t)q[r0 + a] * d + k] : 0.0;
+        xs[i] = a < nc ? X[(int64_t)cand_pos(t, c0 + a, sl) * d + k] : 0.0;
     }
     __syncthreads();
     const int r = threadIdx.x % 64;
     if (r >= nr) return;
     const double *y = ys + r * dp;
     for (int c = threadIdx.x / 64; c < nc; c += 4)
-        t.M[(int64_t)(c0 + c) * ldm + r0 + r] = exp(sqdist(xs + c * d, y, d) * t.scale);
+        glb(t.M)[(int64_t)(c0 + c) * ldm + r0 + r] = exp(sqdist(xs + c * d, y, d) * t.scale);
 }
 
 // ---------------------------------------------------------------------------
@@ -151,10 +155,11 @@ constexpr int kQrMaxCols = 2048;
 constexpr int kQrMaxRows = 4096;
 constexpr int kQrMaxRank = 256;
 
-__device__ inline int node_ncand(const SkelTask &t) { return t.leaf ? t.n : *t.srl + *t.srr; }
+__device__ inline int node_ncand(const SkelTask &t) { return t.leaf ? t.n : *glb(t.srl) + *glb(t.srr); }
 
 // squared norm of row i over the columns [c0, c1) of the block
-__device__ inline double row_part(const double *M, int ldm, int i, int c0, int c1) {
+template <typename PM>
+__device__ inline double row_part(PM M, int ldm, int i, int c0, int c1) {
     double v[kQsCols];
 #pragma unroll
     for (int u = 0; u < kQsCols; u++) v[u] = c0 + u < c1 ? M[(int64_t)(c0 + u) * ldm + i] : 0.0;
@@ -173,8 +178,9 @@ __device__ inline double row_part(const double *M, int ldm, int i, int c0, int c
 // only the rows that carry the interaction.  rn: squared row norms (summed
 // over groups of kQsCols columns in order); all kQrThreads threads call this;
 // returns the number of kept rows and fills rmap (new index or -1).
-template <typename IT>
-__device__ int row_map(const double *rn, int rows, IT *rmap, int32_t *wcnt, double *red) {
+template <typename PR, typename PI>
+__device__ inline int row_map(PR rn, int rows, PI rmap, int32_t *wcnt, double *red) {
+    typedef typename std::remove_cv<typename std::remove_reference<decltype(rmap[0])>::type>::type IT;
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
     double part = 0.0;
     for (int i = tid; i < rows; i += kQrThreads) part += rn[i];
@@ -201,8 +207,8 @@ __device__ int row_map(const double *rn, int rows, IT *rmap, int32_t *wcnt, doub
 
 // in-place compaction of one column by one wave: rows only move up, and a
 // wave reads a block of 1024 rows (16 per lane) before writing it
-template <typename IT>
-__device__ inline void compact_col(double *col, const IT *rmap, int rows, int lane) {
+template <typename PC, typename PI>
+__device__ inline void compact_col(PC col, PI rmap, int rows, int lane) {
     for (int base = 0; base < rows; base += 16 * kWave) {
         double v[16];
 #pragma unroll
@@ -220,7 +226,8 @@ __device__ inline void compact_col(double *col, const IT *rmap, int rows, int la
 }
 
 // squared norm of rows [0, rows) of a column (one wave)
-__device__ inline double col_norm(const double *col, int rows, int lane) {
+template <typename PC>
+__device__ inline double col_norm(PC col, int rows, int lane) {
     double acc = 0.0;
     for (int base = 0; base < rows; base += 4 * kWave) {
         double v[4];
@@ -243,7 +250,8 @@ __device__ inline double col_norm(const double *col, int rows, int lane) {
 struct Refl {
     double alpha, beta, tau, sc;
 };
-__device__ inline Refl reflector(const double *x, int j, int rows, int lane) {
+template <typename PX>
+__device__ inline Refl reflector(PX x, int j, int rows, int lane) {
     double xn = 0.0;
     for (int i = lane; i < rows; i += kWave)
         if (i > j) xn = fma(x[i], x[i], xn);
@@ -269,7 +277,8 @@ __device__ inline bool guard_stop(int j, double beta, double r00) {
 
 // apply H = I - tau v v^T (v in LDS, v_j = 1) to rows [j, rows) of one column
 // (one wave) and return the new squared norm of its rows below j
-__device__ inline double apply_col(double *col, const double *vh, int j, int rows, double tau, int lane) {
+template <typename PC>
+__device__ inline double apply_col(PC col, const double *vh, int j, int rows, double tau, int lane) {
     if (rows - j <= 16 * kWave) {
         double a[16], vr[16];
 #pragma unroll
@@ -312,9 +321,9 @@ __device__ inline double apply_col(double *col, const double *vh, int j, int row
 // all their loads are issued before the first product; rows - j <= 64 NT.
 // The per-column arithmetic is that of apply_col (chunks past the rows add
 // exact zeros), so the grouping does not change any result.
-template <int NT, int NC>
-__device__ inline void apply_group(double *M, int ldm, const int32_t *pos, int q0, int qstride, int qend,
-                                   const double *vh, int j, int rows, double tau, int lane, double *nrm) {
+template <int NT, int NC, typename PM, typename PP, typename PN>
+__device__ inline void apply_group(PM M, int ldm, PP pos, int q0, int qstride, int qend, const double *vh, int j,
+                                   int rows, double tau, int lane, PN nrm) {
     double vr[NT], a[NC][NT];
     int c[NC];
 #pragma unroll
@@ -346,7 +355,7 @@ __device__ inline void apply_group(double *M, int ldm, const int32_t *pos, int q
             a[u][t] = fma(-vr[t], w, a[u][t]);
             if (i > j && i < rows) n = fma(a[u][t], a[u][t], n);
         }
-        double *col = M + (int64_t)c[u] * ldm;
+        auto col = M + (int64_t)c[u] * ldm;
 #pragma unroll
         for (int t = 0; t < NT; t++) {
             const int i = j + lane + t * kWave;
@@ -357,9 +366,9 @@ __device__ inline void apply_group(double *M, int ldm, const int32_t *pos, int q
     }
 }
 
-template <int NT, int NC>
-__device__ inline void apply_all(double *M, int ldm, const int32_t *pos, int j, int ncand, const double *vh, int rows,
-                                 double tau, int lane, int wave, double *nrm) {
+template <int NT, int NC, typename PM, typename PP, typename PN>
+__device__ inline void apply_all(PM M, int ldm, PP pos, int j, int ncand, const double *vh, int rows, double tau,
+                                 int lane, int wave, PN nrm) {
     for (int q0 = j + 1 + wave; q0 < ncand; q0 += kQrWaves * NC)
         apply_group<NT, NC>(M, ldm, pos, q0, kQrWaves, ncand, vh, j, rows, tau, lane, nrm);
 }
@@ -373,8 +382,9 @@ __device__ inline void apply_all(double *M, int ldm, const int32_t *pos, int j, 
 // contiguous, loaded one step ahead) updates the rows above.
 constexpr int kTq = 8;
 constexpr int kTu = kQrMaxRank / kWave;
-__device__ void id_finish(const SkelTask &t, double *M, int ldm, int s, int sl, int ncand, int rank, bool zero,
-                          const int32_t *pos, const double *Rjj) {
+template <typename PM, typename PP, typename PR>
+__device__ inline void id_finish(const SkelTask &t, PM M, int ldm, int s, int sl, int ncand, int rank, bool zero,
+                                 PP pos, PR Rjj) {
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
     auto prow = [&](int c) { return t.leaf ? c : (c < sl ? c : s + (c - sl)); };
     const int nr = ncand - rank;
@@ -394,7 +404,7 @@ __device__ void id_finish(const SkelTask &t, double *M, int ldm, int s, int sl, 
         if (!zero) {
             double rk[kTu], rn[kTu];
             {
-                const double *Ri = M + (int64_t)pos[rank - 1] * ldm;
+                const auto Ri = M + (int64_t)pos[rank - 1] * ldm;
 #pragma unroll
                 for (int v = 0; v < kTu; v++) {
                     const int k = lane + v * kWave;
@@ -407,7 +417,7 @@ __device__ void id_finish(const SkelTask &t, double *M, int ldm, int s, int sl, 
                     const int i = vi * kWave + src;
                     if (i >= rank) continue;
                     if (i > 0) {
-                        const double *Rn = M + (int64_t)pos[i - 1] * ldm;
+                        const auto Rn = M + (int64_t)pos[i - 1] * ldm;
 #pragma unroll
                         for (int v = 0; v < kTu; v++) {
                             const int k = lane + v * kWave;
@@ -438,19 +448,19 @@ __device__ void id_finish(const SkelTask &t, double *M, int ldm, int s, int sl, 
         }
     }
     __syncthreads();
-    for (int k = tid; k < s; k += kQrThreads) t.skel[k] = k < rank ? cand_pos(t, pos[k], sl) : -1;
+    for (int k = tid; k < s; k += kQrThreads) glb(t.skel)[k] = k < rank ? cand_pos(t, pos[k], sl) : -1;
     if (tid == 0) {
-        *t.sr = rank;
-        *t.trunc = (rank < (s < ncand ? s : ncand)) ? 1 : 0;
+        *glb(t.sr) = rank;
+        *glb(t.trunc) = (rank < (s < ncand ? s : ncand)) ? 1 : 0;
     }
     // P is written in the rows of the candidates and the columns below the
     // rank only: nothing reads the rest of the padded slot
     for (int q = tid; q < ncand; q += kQrThreads) {
-        double *row = t.Pt + (int64_t)prow(pos[q]) * s;
+        GLB double *row = glb(t.Pt) + (int64_t)prow(pos[q]) * s;
         if (q < rank) {
             for (int k = 0; k < rank; k++) row[k] = k == q ? 1.0 : 0.0;
         } else {
-            const double *tc = M + (int64_t)pos[q] * ldm;
+            const auto tc = M + (int64_t)pos[q] * ldm;
             for (int k = 0; k < rank; k++) row[k] = tc[k];
         }
     }
@@ -458,7 +468,8 @@ __device__ void id_finish(const SkelTask &t, double *M, int ldm, int s, int sl, 
 
 // pivot choice: largest norm over positions [j, ncand) (value nrm[pos[k]]),
 // lowest position on ties; one wave, result in every lane
-__device__ inline int pick_pivot(const double *nrm, const int32_t *pos, int j, int ncand, int lane) {
+template <typename PN, typename PP>
+__device__ inline int pick_pivot(PN nrm, PP pos, int j, int ncand, int lane) {
     double bv = -1.0;
     int bk = 0x7fffffff;
     for (int k = j + lane; k < ncand; k += kWave) {
@@ -483,7 +494,7 @@ __device__ inline int pick_pivot(const double *nrm, const int32_t *pos, int j, i
 // one workgroup per node: block, norms and reflector traffic through L2/HBM,
 // the pivot bookkeeping in LDS
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kQrThreads) void k_qrcp(const SkelTask *__restrict__ tasks, int s, int ldm) {
+__global__ __launch_bounds__(kQrThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_qrcp(const SkelTask *__restrict__ tasks, int s, int ldm) {
     __shared__ double nrm[kQrMaxCols];
     __shared__ int32_t pos[kQrMaxCols];
     __shared__ double Rjj[kQrMaxRank];
@@ -496,20 +507,20 @@ __global__ __launch_bounds__(kQrThreads) void k_qrcp(const SkelTask *__restrict_
 
     const SkelTask t = tasks[blockIdx.x];
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
-    const int sl = t.leaf ? 0 : *t.srl;
+    const int sl = t.leaf ? 0 : *glb(t.srl);
     const int ncand = node_ncand(t);
-    double *M = t.M;
+    GLB double *M = glb(t.M);
     auto prow = [&](int c) { return t.leaf ? c : (c < sl ? c : s + (c - sl)); };
 
     if (ncand <= s) {  // no compression: skeleton = candidates, P = I
-        for (int k = tid; k < s; k += kQrThreads) t.skel[k] = k < ncand ? cand_pos(t, k, sl) : -1;
+        for (int k = tid; k < s; k += kQrThreads) glb(t.skel)[k] = k < ncand ? cand_pos(t, k, sl) : -1;
         for (int64_t i = tid; i < (int64_t)ncand * ncand; i += kQrThreads) {
             const int c = (int)(i / ncand), k = (int)(i % ncand);
-            t.Pt[(int64_t)prow(c) * s + k] = k == c ? 1.0 : 0.0;
+            glb(t.Pt)[(int64_t)prow(c) * s + k] = k == c ? 1.0 : 0.0;
         }
         if (tid == 0) {
-            *t.sr = ncand;
-            *t.trunc = 0;
+            *glb(t.sr) = ncand;
+            *glb(t.trunc) = 0;
         }
         return;
     }
@@ -548,7 +559,7 @@ __global__ __launch_bounds__(kQrThreads) void k_qrcp(const SkelTask *__restrict_
         if (wave == 0) {
             const int k = pick_pivot(nrm, pos, j, ncand, lane);
             const int p = pos[k];
-            const double *x = M + (int64_t)p * ldm;
+            const auto x = M + (int64_t)p * ldm;
             const Refl r = reflector(x, j, rows, lane);
             if (guard_stop(j, r.beta, r00)) {
                 if (lane == 0) {
@@ -596,8 +607,9 @@ __global__ __launch_bounds__(kQsThreads) void k_qs_rows(const SkelTask *__restri
     const SkelTask t = tasks[node];
     const int ncand = node_ncand(t), c0 = slice * kQsCols;
     if (c0 >= ncand) return;
-    double *part = w.part + ((int64_t)node * w.slices + slice) * w.rcap;
-    for (int i = threadIdx.x; i < t.nq; i += kQsThreads) part[i] = row_part(t.M, ldm, i, c0, min(ncand, c0 + kQsCols));
+    GLB double *part = glb(w.part) + ((int64_t)node * w.slices + slice) * w.rcap;
+    const GLB double *M = glb(t.M);
+    for (int i = threadIdx.x; i < t.nq; i += kQsThreads) part[i] = row_part(M, ldm, i, c0, min(ncand, c0 + kQsCols));
 }
 
 // row norms (groups summed in order), kept rows and their new indices
@@ -608,15 +620,15 @@ __global__ __launch_bounds__(kQrThreads) void k_qs_rowmap(const SkelTask *__rest
     const int node = blockIdx.x;
     const SkelTask t = tasks[node];
     const int ncand = node_ncand(t), groups = (ncand + kQsCols - 1) / kQsCols, rows = t.nq;
-    const double *part = w.part + (int64_t)node * w.slices * w.rcap;
+    const GLB double *part = glb(w.part) + (int64_t)node * w.slices * w.rcap;
     for (int i = threadIdx.x; i < rows; i += kQrThreads) {
         double a = 0.0;
         for (int g = 0; g < groups; g++) a += part[(int64_t)g * w.rcap + i];
         rn[i] = a;
     }
     __syncthreads();
-    const int kept = row_map(rn, rows, w.rmap + (int64_t)node * w.rcap, wcnt, red);
-    if (threadIdx.x == 0) w.rows[node] = kept;
+    const int kept = row_map(rn, rows, glb(w.rmap) + (int64_t)node * w.rcap, wcnt, red);
+    if (threadIdx.x == 0) glb(w.rows)[node] = kept;
 }
 
 // compaction of the group's columns, initial norms, pivot order and state.
@@ -627,15 +639,15 @@ __global__ __launch_bounds__(kQsThreads) void k_qs_init(const SkelTask *__restri
     const int node = blockIdx.x / w.slices, slice = blockIdx.x % w.slices;
     const SkelTask t = tasks[node];
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
-    const int ncand = node_ncand(t), kept = w.rows[node];
+    const int ncand = node_ncand(t), kept = glb(w.rows)[node];
     const int rows = kept < t.nq ? (kept > 0 ? kept : 1) : t.nq;  // as in k_qrcp
-    const int32_t *rmap = w.rmap + (int64_t)node * w.rcap;
-    double *nrm = w.nrm + (int64_t)node * 2 * w.cmax;
-    int32_t *pos = w.pos + (int64_t)node * 2 * w.cmax;
+    const GLB int32_t *rmap = glb(w.rmap) + (int64_t)node * w.rcap;
+    GLB double *nrm = glb(w.nrm) + (int64_t)node * 2 * w.cmax;
+    GLB int32_t *pos = glb(w.pos) + (int64_t)node * 2 * w.cmax;
     for (int q = 0; q < 2; q++) {
         const int c = slice * kQsCols + 2 * wave + q;
         if (c >= ncand) continue;
-        double *col = t.M + (int64_t)c * ldm;
+        GLB double *col = glb(t.M) + (int64_t)c * ldm;
         if (kept < t.nq) compact_col(col, rmap, t.nq, lane);
         const double v = col_norm(col, rows, lane);
         if (lane == 0) {
@@ -644,7 +656,7 @@ __global__ __launch_bounds__(kQsThreads) void k_qs_init(const SkelTask *__restri
         }
     }
     if (slice == 0 && tid == 0) {
-        int32_t *st = w.st + kQsState * node;
+        GLB int32_t *st = glb(w.st) + kQsState * node;
         st[0] = 0;
         st[1] = 0;
         st[2] = 0;
@@ -664,18 +676,18 @@ __global__ __launch_bounds__(kQsThreads) void k_qs_step(const SkelTask *__restri
     __shared__ int32_t s_k, s_p, s_stop;
     __shared__ double s_tau;
     const int node = blockIdx.x / w.slices, slice = blockIdx.x % w.slices;
-    const int32_t *st = w.st + kQsState * node;
+    const GLB int32_t *st = glb(w.st) + kQsState * node;
     const int stopped = st[0], steps = st[3], rows = st[4], ncand = st[5];
-    double *M = tasks[node].M;
+    GLB double *M = glb(tasks[node].M);
     if (stopped || j >= steps) return;
     const int q0 = slice * kQsCols;
     if (q0 >= ncand) return;
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
-    const double *nin = w.nrm + (int64_t)node * 2 * w.cmax + (int64_t)(j & 1) * w.cmax;
-    double *nout = w.nrm + (int64_t)node * 2 * w.cmax + (int64_t)((j + 1) & 1) * w.cmax;
-    const int32_t *pin = w.pos + (int64_t)node * 2 * w.cmax + (int64_t)(j & 1) * w.cmax;
-    int32_t *pout = w.pos + (int64_t)node * 2 * w.cmax + (int64_t)((j + 1) & 1) * w.cmax;
-    double *Rjj = w.diag + (int64_t)node * w.cmax;
+    const GLB double *nin = glb(w.nrm) + (int64_t)node * 2 * w.cmax + (int64_t)(j & 1) * w.cmax;
+    GLB double *nout = glb(w.nrm) + (int64_t)node * 2 * w.cmax + (int64_t)((j + 1) & 1) * w.cmax;
+    const GLB int32_t *pin = glb(w.pos) + (int64_t)node * 2 * w.cmax + (int64_t)(j & 1) * w.cmax;
+    GLB int32_t *pout = glb(w.pos) + (int64_t)node * 2 * w.cmax + (int64_t)((j + 1) & 1) * w.cmax;
+    GLB double *Rjj = glb(w.diag) + (int64_t)node * w.cmax;
     // this wave's positions and their columns (read early)
     const int qa = q0 + 2 * wave, qb = qa + 1;
     const int ca = qa < ncand ? pin[qa] : -1, cb = qb < ncand ? pin[qb] : -1;
@@ -698,7 +710,7 @@ __global__ __launch_bounds__(kQsThreads) void k_qs_step(const SkelTask *__restri
             }
         }
         const int p = pin[bk];
-        const double *x = M + (int64_t)p * ldm;
+        const auto x = M + (int64_t)p * ldm;
         const Refl r = reflector(x, j, rows, lane);
         const bool stop = guard_stop(j, r.beta, j == 0 ? 0.0 : fabs(Rjj[0]));
         if (!stop)
@@ -711,7 +723,7 @@ __global__ __launch_bounds__(kQsThreads) void k_qs_step(const SkelTask *__restri
             vh[j] = 1.0;
             if (slice == 0) {
                 if (stop) {
-                    int32_t *stw = w.st + kQsState * node;
+                    GLB int32_t *stw = glb(w.st) + kQsState * node;
                     stw[0] = 1;
                     stw[1] = j;
                     stw[2] = (j == 0);
@@ -744,14 +756,14 @@ __global__ __launch_bounds__(kQrThreads) void k_qs_finish(const SkelTask *__rest
                                                            int ldm) {
     const int node = blockIdx.x;
     const SkelTask t = tasks[node];
-    const int32_t *st = w.st + kQsState * node;
-    const int sl = t.leaf ? 0 : *t.srl, ncand = node_ncand(t);
+    const GLB int32_t *st = glb(w.st) + kQsState * node;
+    const int sl = t.leaf ? 0 : *glb(t.srl), ncand = node_ncand(t);
     const bool stopped = st[0] != 0, zero = st[2] != 0;
     const int jstop = st[1], steps = st[3];
     const int done = stopped ? jstop : steps;
     const int rank = stopped ? (jstop == 0 ? 1 : jstop) : steps;
-    const int32_t *pos = w.pos + (int64_t)node * 2 * w.cmax + (int64_t)(done & 1) * w.cmax;
-    id_finish(t, t.M, ldm, s, sl, ncand, rank, zero, pos, w.diag + (int64_t)node * w.cmax);
+    const GLB int32_t *pos = glb(w.pos) + (int64_t)node * 2 * w.cmax + (int64_t)(done & 1) * w.cmax;
+    id_finish(t, glb(t.M), ldm, s, sl, ncand, rank, zero, pos, glb(w.diag) + (int64_t)node * w.cmax);
 }
 
 }  // namespace askit
