@@ -29,6 +29,55 @@ template <class T> __device__ __forceinline__ GLB T *glb(T *p) { return (GLB T *
 typedef float flt4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
+// Cross-lane reductions: rows of 16 lanes by DPP (quad xor 1, quad xor 2,
+// half-row mirror, row mirror), then the four row results by readlane.
+// Every lane receives the wave's result, and the same value (the pairings
+// are symmetric).  The whole wave must be active.
+// ---------------------------------------------------------------------------
+template <int CTRL> __device__ inline int dpp_i(int x) { return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false); }
+template <int CTRL> __device__ inline double dpp_d(double x) {
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = dpp_i<CTRL>((int)b), hi = dpp_i<CTRL>((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+// value of x in lane l (l uniform across the wave)
+__device__ inline double readlane_d(double x, int l) {
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline double wave_max_d(double v) {
+    v = fmax(v, dpp_d<0xB1>(v));
+    v = fmax(v, dpp_d<0x4E>(v));
+    v = fmax(v, dpp_d<0x141>(v));
+    v = fmax(v, dpp_d<0x140>(v));
+    return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
+}
+__device__ inline int wave_min_i(int k) {
+    k = min(k, dpp_i<0xB1>(k));
+    k = min(k, dpp_i<0x4E>(k));
+    k = min(k, dpp_i<0x141>(k));
+    k = min(k, dpp_i<0x140>(k));
+    return min(min(__builtin_amdgcn_readlane(k, 0), __builtin_amdgcn_readlane(k, 16)),
+               min(__builtin_amdgcn_readlane(k, 32), __builtin_amdgcn_readlane(k, 48)));
+}
+// sum over the wave: pairs within quads, quads, half rows, rows, then
+// (row 0 + row 1) + (row 2 + row 3)
+__device__ inline double wave_sum_d(double v) {
+    v += dpp_d<0xB1>(v);
+    v += dpp_d<0x4E>(v);
+    v += dpp_d<0x141>(v);
+    v += dpp_d<0x140>(v);
+    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+// index of the largest v over the wave, the smallest index k on ties (v >= 0
+// for candidates; -1 or NaN never wins); 0x7fffffff if no lane has v >= 0
+__device__ inline int wave_argmax(double v, int k) {
+    const double m = wave_max_d(v);
+    return wave_min_i(v == m && m >= 0.0 ? k : 0x7fffffff);
+}
+
+// ---------------------------------------------------------------------------
 // Point sources: a contiguous range of tree positions, or a list of positions
 // (skeletons) whose length lives in device memory (ranks are decided on the
 // device).  Positions index the permuted point array.

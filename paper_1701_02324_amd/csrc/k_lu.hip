@@ -20,38 +20,6 @@ constexpr int kLuMaxN = 512;
 static_assert(kLuFThreads >= kLuMaxN, "one thread per row of the largest matrix");
 
 // ---------------------------------------------------------------------------
-// Cross-lane reductions for the pivot search: rows of 16 lanes by DPP (quad
-// xor 1, quad xor 2, half-row mirror, row mirror), then the four row results
-// by readlane.  Every lane receives the wave's result.
-// ---------------------------------------------------------------------------
-template <int CTRL> __device__ inline int dpp_i(int x) { return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false); }
-template <int CTRL> __device__ inline double dpp_d(double x) {
-    const long long b = __builtin_bit_cast(long long, x);
-    const int lo = dpp_i<CTRL>((int)b), hi = dpp_i<CTRL>((int)(b >> 32));
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ inline double readlane_d(double x, int l) {
-    const long long b = __builtin_bit_cast(long long, x);
-    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ inline double wave_max_d(double v) {
-    v = fmax(v, dpp_d<0xB1>(v));
-    v = fmax(v, dpp_d<0x4E>(v));
-    v = fmax(v, dpp_d<0x141>(v));
-    v = fmax(v, dpp_d<0x140>(v));
-    return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
-}
-__device__ inline int wave_min_i(int k) {
-    k = min(k, dpp_i<0xB1>(k));
-    k = min(k, dpp_i<0x4E>(k));
-    k = min(k, dpp_i<0x141>(k));
-    k = min(k, dpp_i<0x140>(k));
-    return min(min(__builtin_amdgcn_readlane(k, 0), __builtin_amdgcn_readlane(k, 16)),
-               min(__builtin_amdgcn_readlane(k, 32), __builtin_amdgcn_readlane(k, 48)));
-}
-
-// ---------------------------------------------------------------------------
 // Trailing update A22 -= L21 U12 of a blocked LU (panel columns kb..kb+31,
 // trailing rows and columns from j0, nt of them), computed as its transpose
 // U12^T L21^T so that an accumulator register holds 16 consecutive rows of a

@@ -133,10 +133,7 @@ constexpr int kQrWaves = kQrThreads / kWave;
 constexpr int kQsWaves = kQsThreads / kWave;
 static_assert(kQsCols == 2 * kQsWaves, "two columns per wave in the split form");
 
-__device__ inline double wave_sum(double v) {
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
+__device__ inline double wave_sum(double v) { return wave_sum_d(v); }
 
 // block-wide sum over kQrThreads threads (all get the result); red: kQrWaves
 __device__ double block_sum(double v, double *red) {
@@ -427,7 +424,7 @@ __device__ inline void id_finish(const SkelTask &t, PM M, int ldm, int s, int sl
                     const double d = Rjj[i];
 #pragma unroll
                     for (int u = 0; u < kTq; u++) {
-                        const double ti = __shfl(r[u][vi], src) / d;
+                        const double ti = readlane_d(r[u][vi], src) / d;
                         if (lane == src) r[u][vi] = ti;
 #pragma unroll
                         for (int v = 0; v <= vi; v++) r[u][v] = fma(-rk[v], ti, r[u][v]);
@@ -474,20 +471,13 @@ __device__ inline int pick_pivot(PN nrm, PP pos, int j, int ncand, int lane) {
     int bk = 0x7fffffff;
     for (int k = j + lane; k < ncand; k += kWave) {
         const double v = nrm[pos[k]];
-        if (v > bv || (v == bv && k < bk)) {
+        if (v > bv) {  // positions ascend within a lane: the first of equal norms stays
             bv = v;
             bk = k;
         }
     }
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(bv, o);
-        const int ok = __shfl_xor(bk, o);
-        if (ov > bv || (ov == bv && ok < bk)) {
-            bv = ov;
-            bk = ok;
-        }
-    }
-    return bk;
+    const int k = wave_argmax(bv, bk);
+    return k == 0x7fffffff ? j : k;  // no comparable norm (NaN): keep the order
 }
 
 // ---------------------------------------------------------------------------
@@ -692,24 +682,22 @@ __global__ __launch_bounds__(kQsThreads) void k_qs_step(const SkelTask *__restri
     const int qa = q0 + 2 * wave, qb = qa + 1;
     const int ca = qa < ncand ? pin[qa] : -1, cb = qb < ncand ? pin[qb] : -1;
     if (wave == 0) {
+        // each lane reads the norms and the columns of its positions, so the
+        // pivot's column comes from the winning lane instead of another load
         double bv = -1.0;
-        int bk = 0x7fffffff;
+        int bk = 0x7fffffff, bc = -1;
         for (int k = j + lane; k < ncand; k += kWave) {
             const double v = nin[k];
-            if (v > bv || (v == bv && k < bk)) {
+            const int c = pin[k];
+            if (v > bv) {  // positions ascend within a lane: the first of equal norms stays
                 bv = v;
                 bk = k;
+                bc = c;
             }
         }
-        for (int o = kWave / 2; o > 0; o >>= 1) {
-            const double ov = __shfl_xor(bv, o);
-            const int ok = __shfl_xor(bk, o);
-            if (ov > bv || (ov == bv && ok < bk)) {
-                bv = ov;
-                bk = ok;
-            }
-        }
-        const int p = pin[bk];
+        const int kw = wave_argmax(bv, bk);
+        bk = kw == 0x7fffffff ? j : kw;  // no comparable norm (NaN): keep the order
+        const int p = kw == 0x7fffffff ? pin[j] : __builtin_amdgcn_readlane(bc, (kw - j) & (kWave - 1));
         const auto x = M + (int64_t)p * ldm;
         const Refl r = reflector(x, j, rows, lane);
         const bool stop = guard_stop(j, r.beta, j == 0 ? 0.0 : fabs(Rjj[0]));
