@@ -323,10 +323,19 @@ void xcd_order(std::vector<TileItem> &items) {
 template <typename T, typename TB, typename TO>
 hipError_t launch_kmm(const KmmTask *tasks, const TileItem *items, int nitems, int ncol, int d, int tc,
                       hipStream_t st) {
+    if (d <= kXrDim) {  // row points in registers
+        const size_t lds = sizeof(T) * 16 * kXrDim;
+        if (tc == 128)
+            hipLaunchKernelGGL((k_kmm<T, TB, TO, 128, true>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
+        else if (tc == 64)
+            hipLaunchKernelGGL((k_kmm<T, TB, TO, 64, true>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
+        else hipLaunchKernelGGL((k_kmm<T, TB, TO, 16, true>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
+        return hipGetLastError();
+    }
     const size_t lds = sizeof(T) * (64 * (d | 1) + 16 * d);
-    if (tc == 128) hipLaunchKernelGGL((k_kmm<T, TB, TO, 128>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
-    else if (tc == 64) hipLaunchKernelGGL((k_kmm<T, TB, TO, 64>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
-    else hipLaunchKernelGGL((k_kmm<T, TB, TO, 16>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
+    if (tc == 128) hipLaunchKernelGGL((k_kmm<T, TB, TO, 128, false>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
+    else if (tc == 64) hipLaunchKernelGGL((k_kmm<T, TB, TO, 64, false>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
+    else hipLaunchKernelGGL((k_kmm<T, TB, TO, 16, false>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
     return hipGetLastError();
 }
 

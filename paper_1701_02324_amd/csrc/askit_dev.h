@@ -17,6 +17,7 @@ constexpr int kQsCols = 8;       // columns per workgroup of the split QRCP (two
 constexpr int kQsState = 8;      // ints of per-node state of the split QRCP
 constexpr int kLsThreads = 1024; // batched LU solves: 16 waves keep many block loads in flight
 constexpr int kLuFThreads = 512; // batched LU factorization
+constexpr int kXrDim = 16;       // kernel-block products keep row points in registers up to this dimension
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 

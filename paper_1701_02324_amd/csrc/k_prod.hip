@@ -52,17 +52,23 @@ __device__ inline void store_out(P C, int64_t off, T v, int op) {
 __device__ inline int src_count(const PtSrc &s) { return s.cnt ? *glb(s.cnt) : s.n; }
 __device__ inline int64_t src_pos(const PtSrc &s, int i) { return s.idx ? (int64_t)glb(s.idx)[i] : s.base + i; }
 
-template <typename T, typename TB, typename TO, int TC>
+// XR (d <= kXrDim): lane l generates the kernel entries of tile row l only,
+// so its row point stays in registers for the whole contraction and the
+// contraction points are staged at stride kXrDim, zero-padded (the padded
+// coordinates add exact zeros to the squared distance).  Otherwise the row
+// points are staged in LDS at an odd stride (lanes read different rows: no
+// bank conflicts) and the contraction points at stride d (broadcast within a
+// wave).
+template <typename T, typename TB, typename TO, int TC, bool XR>
 __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, const TileItem *__restrict__ items,
                                              int ncol, int d) {
     constexpr int NB = TC / 16;
     __shared__ T sA[kTR][kKS + 1];
     __shared__ T sB[kKS][TC + 1];
-    // row points at an odd stride (lanes read different rows: no bank
-    // conflicts), contraction points at stride d (broadcast within a wave)
-    extern __shared__ double dyn_lds[];  // 64 (d | 1) + 16 d elements of T
+    // XR: 16 kXrDim elements of T; else 64 (d | 1) + 16 d
+    extern __shared__ double dyn_lds[];
     const int dp = d | 1;
-    T *sR = (T *)dyn_lds, *sS = (T *)dyn_lds + kTR * dp;
+    T *sR = (T *)dyn_lds, *sS = XR ? (T *)dyn_lds : (T *)dyn_lds + kTR * dp;
     const TileItem it = items[blockIdx.x];
     if (it.task < 0) return;
     const KmmTask t = tasks[it.task];
@@ -83,24 +89,38 @@ __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, 
     int k1 = t.k1;
     if (t.S.cnt) k1 = min(k1, *glb(t.S.cnt));
     const T scale = (T)t.scale, hinv = (T)t.hinv;
-    // stage the row points (fixed for the whole contraction)
-    for (int i = tid; i < kTR * d; i += 256) {
-        int r = i / d, k = i % d;
-        sR[r * dp + k] = r0 + r < nrow ? (T)X[src_pos(t.R, r0 + r) * d + k] : (T)0;
+    // the row points (fixed for the whole contraction)
+    T xr[XR ? kXrDim : 1];
+    if constexpr (XR) {
+        const bool live = r0 + lane < nrow;
+        const int64_t pr = live ? src_pos(t.R, r0 + lane) * d : 0;
+#pragma unroll
+        for (int q = 0; q < kXrDim; q++) xr[q] = (live && q < d) ? (T)X[pr + q] : (T)0;
+    } else {
+        for (int i = tid; i < kTR * d; i += 256) {
+            int r = i / d, k = i % d;
+            sR[r * dp + k] = r0 + r < nrow ? (T)X[src_pos(t.R, r0 + r) * d + k] : (T)0;
+        }
     }
     typename Acc<T>::type acc[NB];
     for (int b = 0; b < NB; b++) acc[b] = typename Acc<T>::type{0, 0, 0, 0};
     const GLB TB *B = glb((const TB *)t.B);
     // the next stage's contraction points and B rows are fetched into
     // registers while the current stage is generated and multiplied
-    constexpr int PS = kKS * kMaxDim / 256, PB = kKS * TC / 256;
+    constexpr int PS = (XR ? kKS * kXrDim : kKS * kMaxDim) / 256, PB = kKS * TC / 256;
     T pS[PS], pB[PB];
     auto fetch = [&](int ks) {
         const int kn = min(kKS, k1 - ks);
 #pragma unroll
         for (int u = 0; u < PS; u++) {
-            const int i = tid + u * 256, r = i / d, k = i % d;
-            pS[u] = (i < kKS * d && r < kn) ? (T)X[src_pos(t.S, ks + r) * d + k] : (T)0;
+            const int i = tid + u * 256;
+            if constexpr (XR) {
+                const int r = i / kXrDim, k = i % kXrDim;
+                pS[u] = (k < d && r < kn) ? (T)X[src_pos(t.S, ks + r) * d + k] : (T)0;
+            } else {
+                const int r = i / d, k = i % d;
+                pS[u] = (i < kKS * d && r < kn) ? (T)X[src_pos(t.S, ks + r) * d + k] : (T)0;
+            }
         }
 #pragma unroll
         for (int u = 0; u < PB; u++) {
@@ -115,7 +135,7 @@ __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, 
 #pragma unroll
         for (int u = 0; u < PS; u++) {
             const int i = tid + u * 256;
-            if (i < kKS * d) sS[i] = pS[u];
+            if (XR || i < kKS * d) sS[i] = pS[u];
         }
 #pragma unroll
         for (int u = 0; u < PB; u++) {
@@ -124,21 +144,42 @@ __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, 
         }
         __syncthreads();
         if (ks + kKS < k1) fetch(ks + kKS);
-        // generate the kernel tile: 64 x 16 entries, 4 per thread
-        for (int i = tid; i < kTR * kKS; i += 256) {
-            int r = i % kTR, k = i / kTR;
-            T v = (T)0;
-            if (k < kn && r0 + r < nrow) {
-                const T *x = sR + r * dp, *y = sS + k * d;
-                T r2 = 0;
-                for (int q = 0; q < d; q++) {
-                    T df = x[q] - y[q];
-                    r2 = fma(df, df, r2);
+        // generate the kernel tile: 64 x 16 entries, 4 per thread (thread
+        // tid: row tid % 64 = its lane, columns tid / 64 + 4 m)
+        if constexpr (XR) {
+#pragma unroll
+            for (int m = 0; m < 4; m++) {
+                const int k = wave + 4 * m;
+                T v = (T)0;
+                if (k < kn && r0 + lane < nrow) {
+                    const T *y = sS + k * kXrDim;
+                    T r2 = 0;
+#pragma unroll
+                    for (int q = 0; q < kXrDim; q++) {
+                        T df = xr[q] - y[q];
+                        r2 = fma(df, df, r2);
+                    }
+                    v = kexp(r2 * scale);
+                    if (t.which) v = v * r2 * hinv * hinv * hinv;
                 }
-                v = kexp(r2 * scale);
-                if (t.which) v = v * r2 * hinv * hinv * hinv;
+                sA[lane][k] = v;
             }
-            sA[r][k] = v;
+        } else {
+            for (int i = tid; i < kTR * kKS; i += 256) {
+                int r = i % kTR, k = i / kTR;
+                T v = (T)0;
+                if (k < kn && r0 + r < nrow) {
+                    const T *x = sR + r * dp, *y = sS + k * d;
+                    T r2 = 0;
+                    for (int q = 0; q < d; q++) {
+                        T df = x[q] - y[q];
+                        r2 = fma(df, df, r2);
+                    }
+                    v = kexp(r2 * scale);
+                    if (t.which) v = v * r2 * hinv * hinv * hinv;
+                }
+                sA[r][k] = v;
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -262,8 +303,9 @@ __global__ void k_reduce(const RedTask *__restrict__ tasks, int ncol, int blocks
     store_out(glb((TO *)t.dst), (int64_t)r * t.drs + (int64_t)c * t.dcs, (TO)acc, t.op);
 }
 
-#define KMM_INST(T, TB, TO, TC) \
-    template __global__ void k_kmm<T, TB, TO, TC>(const KmmTask *, const TileItem *, int, int);
+#define KMM_INST(T, TB, TO, TC)                                                                    \
+    template __global__ void k_kmm<T, TB, TO, TC, false>(const KmmTask *, const TileItem *, int, int); \
+    template __global__ void k_kmm<T, TB, TO, TC, true>(const KmmTask *, const TileItem *, int, int);
 #define KMM_ALL(T, TB, TO) KMM_INST(T, TB, TO, 16) KMM_INST(T, TB, TO, 64) KMM_INST(T, TB, TO, 128)
 KMM_ALL(double, double, double)
 KMM_ALL(float, float, float)
