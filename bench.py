@@ -131,21 +131,25 @@ ROOF_TABLE = [
 # WRITE_SIZE (KiB per dispatch, averaged over the launches of one step),
 # scaled by what the same counters read for a plain 1 GiB read + 1 GiB write
 # (torch.neg).  Valid only for the kernel source they were taken on (sha256 of
-# the file) and for this workload; otherwise "traffic" is null.
+# its files) and for this workload; otherwise "traffic" is null.
 TRAFFIC = {
-    "skel:k_qrcp": {
-        "source": "k_skel.hip",
-        "src_sha256": "e3a301015e2336e0235b2b9a80db212b6ba7a442d10523a67cc042566c7c5cad",
+    "factor:k_lu_nopiv": {
+        "source": ["k_lu.hip", "askit_dev.h"],
+        "src_sha256": "399212e376a08bb21c3f99a181537f38ad15e4e84c64cb0f1afe5cec8aacf42e",
         "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": 10392836359.332882,
+        "bytes_per_launch": 56175158084.934166,
     },
 }
 
 
-def kernel_source_sha(name):
+def kernel_source_sha(names):
+    """sha256 over the kernel's source files (a file name or a list), in order."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_1701_02324_amd", "csrc", name), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in [names] if isinstance(names, str) else names:
+        with open(os.path.join(ROOT, "paper_1701_02324_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def roofline_of(key, cnt_key, bound, peak_key, unit, nlaunch, prof, cnt, D, steps):
@@ -181,6 +185,8 @@ def main():
     ap.add_argument("--max-refine", type=int, default=10, help="GMRES-IR operator applications (mixed path)")
     ap.add_argument("--no-stable-check", action="store_true",
                     help="skip the mixed-vs-FP64 check on the N=65536 d=8 mixture (lambda=0.1)")
+    ap.add_argument("--no-separate", action="store_true",
+                    help="skip the extra step through the two separate calls")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the timings of the other forms (batched problems, gradient, transpose solve)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -282,12 +288,18 @@ def main():
     t_sol = float(np.mean([r["solve"] for r in runs]))
     info = runs[-1]["info"]
     # the same step through the two separate calls (no overlap), once
-    r2, _, _ = step(ak.ASKIT_MIXED, fused=False)
-    two_call = dict(skeletonize_s=r2["skel"], factorize_s=r2["factor"], total_s=r2["total"])
-    log(f"[bench] separate calls: skeletonize {r2['skel']:.3f} s factorize {r2['factor']:.3f} s")
+    two_call = None
+    if not args.no_separate:
+        r2, _, _ = step(ak.ASKIT_MIXED, fused=False)
+        two_call = dict(skeletonize_s=r2["skel"], factorize_s=r2["factor"], total_s=r2["total"])
+        log(f"[bench] separate calls: skeletonize {r2['skel']:.3f} s factorize {r2['factor']:.3f} s")
 
     res = {}
     if not args.no_fp64:
+        # one untimed FP64 pass first (its first allocations), like the
+        # warm-up of the timed mixed steps
+        tree.skeletonize_factorize(lam, ak.ASKIT_FP64).close()
+        torch.cuda.synchronize()
         a = time.perf_counter()
         f64 = tree.skeletonize_factorize(lam, ak.ASKIT_FP64)
         torch.cuda.synchronize()
@@ -318,7 +330,7 @@ def main():
                    fp64_refined_solve_s=g1 - g0, fp64_refinement=info64,
                    mixed_vs_fp64_rel_err=err, mixed_vs_fp64_direct_rel_err=err_direct,
                    speedup_factor_mixed_over_fp64=(b - a) / t_total,
-                   speedup_factorize_only=t_f64_only / two_call["factorize_s"])
+                   speedup_factorize_only=t_f64_only / two_call["factorize_s"] if two_call else None)
         log(f"[bench] fp64: skeletonize+factorize {b - a:.3f} s (factorize alone {t_f64_only:.3f} s) solve "
             f"{e - b:.3f} s (residual {eps64:.2e}); refined "
             f"{g1 - g0:.3f} s {info64}; mixed vs fp64 refined {err:.2e}, vs fp64 direct {err_direct:.2e}")
