@@ -267,9 +267,67 @@ __device__ inline Refl reflector(PX x, int j, int rows, int lane) {
     return r;
 }
 
+// the same for rows - j <= 16 * 64 with the column's rows j + lane + 64 t
+// kept in xv (zero past the rows): lane l sums the rows i > j with
+// i = j + l mod 64, in increasing order
+template <typename PX>
+__device__ inline Refl reflector_reg(PX x, int j, int rows, int lane, double (&xv)[16]) {
+#pragma unroll
+    for (int t = 0; t < 16; t++) {
+        const int i = j + lane + t * kWave;
+        xv[t] = i < rows ? x[i] : 0.0;
+    }
+    double xn = 0.0;
+#pragma unroll
+    for (int t = 0; t < 16; t++) {
+        const int i = j + lane + t * kWave;
+        if (i > j && i < rows) xn = fma(xv[t], xv[t], xn);
+    }
+    xn = wave_sum(xn);
+    Refl r;
+    r.alpha = readlane_d(xv[0], 0);
+    if (xn == 0.0) {
+        r.beta = r.alpha;
+        r.tau = 0.0;
+        r.sc = 0.0;
+    } else {
+        r.beta = -copysign(sqrt(r.alpha * r.alpha + xn), r.alpha);
+        r.tau = (r.beta - r.alpha) / r.beta;
+        r.sc = 1.0 / (r.alpha - r.beta);
+    }
+    return r;
+}
+
+// reflector of pivot step j, its Householder vector written to vh (v_j = 1
+// by the caller) unless the rank guard stops; returns whether it stops
+template <typename PX>
+__device__ inline Refl reflector_to_lds(PX x, int j, int rows, int lane, double r00, double *vh, bool &stop);
+
 __device__ inline bool guard_stop(int j, double beta, double r00) {
     const double r0 = j == 0 ? fabs(beta) : r00;
     return (j > 0 && fabs(beta) <= kRankGuard * r0) || (j == 0 && r0 == 0.0);
+}
+
+template <typename PX>
+__device__ inline Refl reflector_to_lds(PX x, int j, int rows, int lane, double r00, double *vh, bool &stop) {
+    if (rows - j <= 16 * kWave) {
+        double xv[16];
+        const Refl r = reflector_reg(x, j, rows, lane, xv);
+        stop = guard_stop(j, r.beta, r00);
+        if (!stop) {
+#pragma unroll
+            for (int t = 0; t < 16; t++) {
+                const int i = j + lane + t * kWave;
+                if (i > j && i < rows) vh[i] = xv[t] * r.sc;
+            }
+        }
+        return r;
+    }
+    const Refl r = reflector(x, j, rows, lane);
+    stop = guard_stop(j, r.beta, r00);
+    if (!stop)
+        for (int i = j + 1 + lane; i < rows; i += kWave) vh[i] = x[i] * r.sc;
+    return r;
 }
 
 // apply H = I - tau v v^T (v in LDS, v_j = 1) to rows [j, rows) of one column
@@ -549,16 +607,15 @@ __global__ __launch_bounds__(kQrThreads) __attribute__((amdgpu_waves_per_eu(4)))
         if (wave == 0) {
             const int k = pick_pivot(nrm, pos, j, ncand, lane);
             const int p = pos[k];
-            const auto x = M + (int64_t)p * ldm;
-            const Refl r = reflector(x, j, rows, lane);
-            if (guard_stop(j, r.beta, r00)) {
+            bool stop;
+            const Refl r = reflector_to_lds(M + (int64_t)p * ldm, j, rows, lane, r00, vh, stop);
+            if (stop) {
                 if (lane == 0) {
                     s_rank = j == 0 ? 1 : j;
                     s_zero = (j == 0);
                     s_stop = 1;
                 }
             } else {
-                for (int i = j + 1 + lane; i < rows; i += kWave) vh[i] = x[i] * r.sc;
                 if (lane == 0) {
                     vh[j] = 1.0;
                     s_tau = r.tau;
@@ -698,11 +755,8 @@ __global__ __launch_bounds__(kQsThreads) void k_qs_step(const SkelTask *__restri
         const int kw = wave_argmax(bv, bk);
         bk = kw == 0x7fffffff ? j : kw;  // no comparable norm (NaN): keep the order
         const int p = kw == 0x7fffffff ? pin[j] : __builtin_amdgcn_readlane(bc, (kw - j) & (kWave - 1));
-        const auto x = M + (int64_t)p * ldm;
-        const Refl r = reflector(x, j, rows, lane);
-        const bool stop = guard_stop(j, r.beta, j == 0 ? 0.0 : fabs(Rjj[0]));
-        if (!stop)
-            for (int i = j + 1 + lane; i < rows; i += kWave) vh[i] = x[i] * r.sc;
+        bool stop;
+        const Refl r = reflector_to_lds(M + (int64_t)p * ldm, j, rows, lane, j == 0 ? 0.0 : fabs(Rjj[0]), vh, stop);
         if (lane == 0) {
             s_stop = stop;
             s_k = bk;
