@@ -151,6 +151,8 @@ __device__ double block_sum(double v, double *red) {
 constexpr int kQrMaxCols = 2048;
 constexpr int kQrMaxRows = 4096;
 constexpr int kQrMaxRank = 256;
+// positions per lane in the split step's pivot scan (2 kQrMaxRank candidates)
+constexpr int kQsScan = 2 * kQrMaxRank / kWave;
 
 __device__ inline int node_ncand(const SkelTask &t) { return t.leaf ? t.n : *glb(t.srl) + *glb(t.srr); }
 
@@ -739,17 +741,26 @@ __global__ __launch_bounds__(kQsThreads) void k_qs_step(const SkelTask *__restri
     const int qa = q0 + 2 * wave, qb = qa + 1;
     const int ca = qa < ncand ? pin[qa] : -1, cb = qb < ncand ? pin[qb] : -1;
     if (wave == 0) {
-        // each lane reads the norms and the columns of its positions, so the
+        // each lane reads the norms and the columns of its positions (at
+        // most kQsScan: a split node has at most 2 s <= 2 kQrMaxRank
+        // candidates), all loads before the first comparison, so the
         // pivot's column comes from the winning lane instead of another load
+        double nv[kQsScan];
+        int pc[kQsScan];
+#pragma unroll
+        for (int u = 0; u < kQsScan; u++) {
+            const int k = j + lane + u * kWave;
+            nv[u] = k < ncand ? nin[k] : -1.0;
+            pc[u] = k < ncand ? pin[k] : -1;
+        }
         double bv = -1.0;
         int bk = 0x7fffffff, bc = -1;
-        for (int k = j + lane; k < ncand; k += kWave) {
-            const double v = nin[k];
-            const int c = pin[k];
-            if (v > bv) {  // positions ascend within a lane: the first of equal norms stays
-                bv = v;
-                bk = k;
-                bc = c;
+#pragma unroll
+        for (int u = 0; u < kQsScan; u++) {
+            if (nv[u] > bv) {  // positions ascend within a lane: the first of equal norms stays
+                bv = nv[u];
+                bk = j + lane + u * kWave;
+                bc = pc[u];
             }
         }
         const int kw = wave_argmax(bv, bk);
