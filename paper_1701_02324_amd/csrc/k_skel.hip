@@ -728,6 +728,9 @@ __global__ __launch_bounds__(kQsThreads) void k_qs_step(const SkelTask *__restri
     const GLB int32_t *st = glb(w.st) + kQsState * node;
     const int stopped = st[0], steps = st[3], rows = st[4], ncand = st[5];
     GLB double *M = glb(tasks[node].M);
+    // |R_00| for the rank guard, read with the node state (meaningless, and
+    // unused, at step 0)
+    const double r00 = fabs(glb(w.diag)[(int64_t)node * w.cmax]);
     if (stopped || j >= steps) return;
     const int q0 = slice * kQsCols;
     if (q0 >= ncand) return;
@@ -767,7 +770,7 @@ __global__ __launch_bounds__(kQsThreads) void k_qs_step(const SkelTask *__restri
         bk = kw == 0x7fffffff ? j : kw;  // no comparable norm (NaN): keep the order
         const int p = kw == 0x7fffffff ? pin[j] : __builtin_amdgcn_readlane(bc, (kw - j) & (kWave - 1));
         bool stop;
-        const Refl r = reflector_to_lds(M + (int64_t)p * ldm, j, rows, lane, j == 0 ? 0.0 : fabs(Rjj[0]), vh, stop);
+        const Refl r = reflector_to_lds(M + (int64_t)p * ldm, j, rows, lane, j == 0 ? 0.0 : r00, vh, stop);
         if (lane == 0) {
             s_stop = stop;
             s_k = bk;
