@@ -509,7 +509,7 @@ struct askit_tree_s {
     double h = 1.0;      // bandwidth of the skeletonization
     double hfac = 1.0;   // bandwidth of the next factorization (skeletons frozen)
     std::vector<int64_t> nb, ne;  // host node ranges
-    DBuf X, Xp, perm, dnb, dne;
+    DBuf X, Xp, perm, iperm, dnb, dne;  // iperm[original index] = tree position
     DBuf srank, trunc, skel, Pt, samp;
     std::vector<int32_t> hsr;  // host copy of the ranks s_alpha (root: 0)
     int split_levels = 0;      // tree levels 1 .. split_levels use the split QRCP
@@ -715,6 +715,9 @@ askit_status askit_build_tree(const double *X, int64_t N, int32_t d, const askit
     }
     hipLaunchKernelGGL(k_gather_points, dim3(grid1(N * d)), dim3(256), 0, st, t->X.as<double>(),
                        t->perm.as<int64_t>(), d, N, t->Xp.as<double>());
+    ST_TRY(t->iperm.alloc(sizeof(int64_t) * N));
+    hipLaunchKernelGGL(k_invert_perm, dim3(grid1(N)), dim3(256), 0, st, t->perm.as<int64_t>(), N,
+                       t->iperm.as<int64_t>());
     HIP_TRY(hipGetLastError());
     int32_t hbad = 0;
     HIP_TRY(hipMemcpyAsync(&hbad, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -1897,20 +1900,21 @@ static askit_status apply_inverse(askit_factor f, const double *B, int64_t ldb, 
         ST_TRY(trans ? solvet_plan(f, *pl) : solve_plan({f}, *pl));
     }
     const int64_t N = t->N;
+    const dim3 tg((unsigned)cdiv(N, 64), (unsigned)cdiv(nrhs, 64));
     if (f->prec == P64)
-        hipLaunchKernelGGL(k_gather_rhs<double>, dim3(grid1(N * nrhs)), dim3(256), 0, st, B, ldb,
-                           t->perm.as<int64_t>(), N, nrhs, f->W.as<double>(), (int64_t)f->cap);
+        hipLaunchKernelGGL(k_gather_rhs_t<double>, tg, dim3(256), 0, st, B, ldb, t->iperm.as<int64_t>(), N, nrhs,
+                           f->W.as<double>(), (int64_t)f->cap);
     else
-        hipLaunchKernelGGL(k_gather_rhs<float>, dim3(grid1(N * nrhs)), dim3(256), 0, st, B, ldb,
-                           t->perm.as<int64_t>(), N, nrhs, f->W.as<float>(), (int64_t)f->cap);
+        hipLaunchKernelGGL(k_gather_rhs_t<float>, tg, dim3(256), 0, st, B, ldb, t->iperm.as<int64_t>(), N, nrhs,
+                           f->W.as<float>(), (int64_t)f->cap);
     HIP_TRY(hipGetLastError());
     HIP_TRY(pl->run(st, nrhs));
     if (f->prec == P64)
-        hipLaunchKernelGGL(k_scatter_rhs<double>, dim3(grid1(N * nrhs)), dim3(256), 0, st, f->W.as<double>(),
-                           (int64_t)f->cap, t->perm.as<int64_t>(), N, nrhs, X, ldx, 0);
+        hipLaunchKernelGGL(k_scatter_rhs_t<double>, tg, dim3(256), 0, st, f->W.as<double>(), (int64_t)f->cap,
+                           t->iperm.as<int64_t>(), N, nrhs, X, ldx, 0);
     else
-        hipLaunchKernelGGL(k_scatter_rhs<float>, dim3(grid1(N * nrhs)), dim3(256), 0, st, f->W.as<float>(),
-                           (int64_t)f->cap, t->perm.as<int64_t>(), N, nrhs, X, ldx, 0);
+        hipLaunchKernelGGL(k_scatter_rhs_t<float>, tg, dim3(256), 0, st, f->W.as<float>(), (int64_t)f->cap,
+                           t->iperm.as<int64_t>(), N, nrhs, X, ldx, 0);
     HIP_TRY(hipGetLastError());
     return ASKIT_OK;
 }
@@ -1925,12 +1929,13 @@ static askit_status matvec_impl(askit_factor f, int which, const double *Xin, in
         ST_TRY(matvec_plan(f, which, *f->mv_plan[which]));
     }
     const int64_t N = t->N;
-    hipLaunchKernelGGL(k_gather_rhs<double>, dim3(grid1(N * nrhs)), dim3(256), 0, st, Xin, ldx,
-                       t->perm.as<int64_t>(), N, nrhs, f->WX.as<double>(), (int64_t)f->cap);
+    const dim3 tg((unsigned)cdiv(N, 64), (unsigned)cdiv(nrhs, 64));
+    hipLaunchKernelGGL(k_gather_rhs_t<double>, tg, dim3(256), 0, st, Xin, ldx, t->iperm.as<int64_t>(), N, nrhs,
+                       f->WX.as<double>(), (int64_t)f->cap);
     HIP_TRY(hipGetLastError());
     HIP_TRY(f->mv_plan[which]->run(st, nrhs));
-    hipLaunchKernelGGL(k_scatter_rhs<double>, dim3(grid1(N * nrhs)), dim3(256), 0, st, f->WY.as<double>(),
-                       (int64_t)f->cap, t->perm.as<int64_t>(), N, nrhs, Y, ldy, 0);
+    hipLaunchKernelGGL(k_scatter_rhs_t<double>, tg, dim3(256), 0, st, f->WY.as<double>(), (int64_t)f->cap,
+                       t->iperm.as<int64_t>(), N, nrhs, Y, ldy, 0);
     HIP_TRY(hipGetLastError());
     return ASKIT_OK;
 }

@@ -53,11 +53,12 @@ template <typename T, typename TO> __global__ void k_reduce(const RedTask *tasks
 
 // misc (k_misc.hip)
 template <typename T>
-__global__ void k_gather_rhs(const double *B, int64_t ldb, const int64_t *perm, int64_t N, int nrhs, T *W,
-                             int64_t ldw);
+__global__ void k_gather_rhs_t(const double *B, int64_t ldb, const int64_t *iperm, int64_t N, int nrhs, T *W,
+                               int64_t ldw);
 template <typename T>
-__global__ void k_scatter_rhs(const T *W, int64_t ldw, const int64_t *perm, int64_t N, int nrhs, double *X,
-                              int64_t ldx, int add);
+__global__ void k_scatter_rhs_t(const T *W, int64_t ldw, const int64_t *iperm, int64_t N, int nrhs, double *X,
+                                int64_t ldx, int add);
+__global__ void k_invert_perm(const int64_t *perm, int64_t N, int64_t *iperm);
 __global__ void k_leaf_block(const LeafTask *tasks, int tiles, int d);
 template <typename T>
 __global__ void k_gather_multi(const GatherTask *tasks, const double *const *B, int nrhs, int bpt);

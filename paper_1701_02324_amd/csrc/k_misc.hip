@@ -6,29 +6,62 @@
 
 namespace askit {
 
-// W(pos, c) = B[perm[pos] + c * ldb]   (W row-major, row stride ldw)
+// Permutation of right-hand sides between the caller's point order and tree
+// order (W row-major in tree order, row stride ldw), by tiles of 64 points x
+// 64 columns through LDS, over the caller's point order i (iperm[i] = tree
+// position of point i): the caller's column-major block is read and written
+// by whole columns, the tree-order block by whole rows, both coalesced.  256
+// threads; grid = (ceil(N / 64), ceil(nrhs / 64)).
+// W(iperm[i], c) = B[i + c * ldb]
 template <typename T>
-__global__ void k_gather_rhs(const double *__restrict__ B, int64_t ldb, const int64_t *__restrict__ perm, int64_t N,
-                             int nrhs, T *__restrict__ W, int64_t ldw) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= N * nrhs) return;
-    int64_t pos = t / nrhs;
-    int c = (int)(t % nrhs);
-    W[pos * ldw + c] = (T)B[perm[pos] + (int64_t)c * ldb];
+__global__ __launch_bounds__(256) void k_gather_rhs_t(const double *__restrict__ B, int64_t ldb,
+                                                      const int64_t *__restrict__ iperm, int64_t N, int nrhs,
+                                                      T *__restrict__ W, int64_t ldw) {
+    __shared__ double tile[64][65];
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int c0 = blockIdx.y * 64, lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const GLB double *Bg = glb(B);
+    for (int cc = wave; cc < 64; cc += 4)
+        tile[lane][cc] = (i0 + lane < N && c0 + cc < nrhs) ? Bg[(i0 + lane) + (int64_t)(c0 + cc) * ldb] : 0.0;
+    __syncthreads();
+    GLB T *Wg = glb(W);
+    for (int r = wave; r < 64; r += 4) {
+        if (i0 + r >= N) break;
+        const int64_t row = glb(iperm)[i0 + r];
+        if (c0 + lane < nrhs) Wg[row * ldw + c0 + lane] = (T)tile[r][lane];
+    }
 }
 
-// X[perm[pos] + c * ldx] (op)= W(pos, c); op 0: store, 1: add
+// X[i + c * ldx] (op)= W(iperm[i], c); op 0: store, 1: add
 template <typename T>
-__global__ void k_scatter_rhs(const T *__restrict__ W, int64_t ldw, const int64_t *__restrict__ perm, int64_t N,
-                              int nrhs, double *__restrict__ X, int64_t ldx, int add) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= N * nrhs) return;
-    int64_t pos = t / nrhs;
-    int c = (int)(t % nrhs);
-    double v = (double)W[pos * ldw + c];
-    double *dst = X + perm[pos] + (int64_t)c * ldx;
-    if (add) *dst += v;
-    else *dst = v;
+__global__ __launch_bounds__(256) void k_scatter_rhs_t(const T *__restrict__ W, int64_t ldw,
+                                                       const int64_t *__restrict__ iperm, int64_t N, int nrhs,
+                                                       double *__restrict__ X, int64_t ldx, int add) {
+    __shared__ double tile[64][65];
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int c0 = blockIdx.y * 64, lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const GLB T *Wg = glb(W);
+    for (int r = wave; r < 64; r += 4) {
+        const bool live = i0 + r < N;
+        const int64_t row = live ? glb(iperm)[i0 + r] : 0;
+        tile[r][lane] = (live && c0 + lane < nrhs) ? (double)Wg[row * ldw + c0 + lane] : 0.0;
+    }
+    __syncthreads();
+    GLB double *Xg = glb(X);
+    for (int cc = wave; cc < 64; cc += 4) {
+        if (c0 + cc >= nrhs) break;
+        if (i0 + lane < N) {
+            GLB double *dst = Xg + (i0 + lane) + (int64_t)(c0 + cc) * ldx;
+            if (add) *dst += tile[lane][cc];
+            else *dst = tile[lane][cc];
+        }
+    }
+}
+
+// iperm[perm[p]] = p
+__global__ void k_invert_perm(const int64_t *__restrict__ perm, int64_t N, int64_t *__restrict__ iperm) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < N) glb(iperm)[glb(perm)[p]] = p;
 }
 
 // batched permutation of right-hand sides (pointer table on the device);
@@ -248,10 +281,10 @@ __global__ void k_zero(double *__restrict__ p, int64_t n) {
     if (i < n) p[i] = 0.0;
 }
 
-template __global__ void k_gather_rhs<double>(const double *, int64_t, const int64_t *, int64_t, int, double *, int64_t);
-template __global__ void k_gather_rhs<float>(const double *, int64_t, const int64_t *, int64_t, int, float *, int64_t);
-template __global__ void k_scatter_rhs<double>(const double *, int64_t, const int64_t *, int64_t, int, double *, int64_t, int);
-template __global__ void k_scatter_rhs<float>(const float *, int64_t, const int64_t *, int64_t, int, double *, int64_t, int);
+template __global__ void k_gather_rhs_t<double>(const double *, int64_t, const int64_t *, int64_t, int, double *, int64_t);
+template __global__ void k_gather_rhs_t<float>(const double *, int64_t, const int64_t *, int64_t, int, float *, int64_t);
+template __global__ void k_scatter_rhs_t<double>(const double *, int64_t, const int64_t *, int64_t, int, double *, int64_t, int);
+template __global__ void k_scatter_rhs_t<float>(const float *, int64_t, const int64_t *, int64_t, int, double *, int64_t, int);
 template __global__ void k_copy<double, double>(const CopyTask *, int);
 template __global__ void k_copy<double, float>(const CopyTask *, int);
 template __global__ void k_copy<float, double>(const CopyTask *, int);
