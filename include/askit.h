@@ -235,6 +235,17 @@ askit_status askit_get_stats(askit_tree t, askit_factor f, char *json, size_t ca
 askit_status askit_profile_enable(int32_t on);
 askit_status askit_profile_report(char *json, size_t cap);
 
+/* Device memory cache.  Released device blocks of 64 MiB or more (a
+ * factorization's arenas, the refinement's Krylov basis) are kept by the
+ * library, per device, and reused by later allocations of about the same
+ * size; a block enters the cache only after its device has been synchronized.
+ * This call frees every cached block of every device (hipFree) and writes the
+ * number of bytes freed to *bytes_released when that pointer is not NULL.
+ * Buffers of live trees and factors are not touched.  Allocation failures
+ * empty the cache of the failing device by themselves before they are
+ * reported. */
+askit_status askit_release_cached_memory(uint64_t *bytes_released);
+
 const char *askit_last_error(void);
 void askit_tree_destroy(askit_tree t);
 void askit_factor_destroy(askit_factor f);

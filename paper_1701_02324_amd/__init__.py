@@ -8,7 +8,8 @@ from .askit import (ASKIT_FP64, ASKIT_MIXED, AskitError, Batch, Factor, Tree, as
                     askit_batch_destroy, askit_batch_factor, askit_batch_factorize, askit_batch_solve,
                     askit_skeletonize_batched, askit_build_tree,  # noqa: F401
                     askit_factor_destroy, askit_factor_pivot_ratio, askit_factorize, askit_get_stats,
-                    askit_last_solve_info, askit_matvec, askit_profile_enable, askit_profile_report, askit_set_refinement, askit_skeletonize,
+                    askit_last_solve_info, askit_matvec, askit_profile_enable, askit_profile_report, askit_release_cached_memory,
+                    askit_set_refinement, askit_skeletonize,
                     askit_skeletons_export, askit_skeletons_import, askit_solve, askit_solve_transpose,
                     askit_tree_depth, askit_tree_destroy, askit_tree_perm, askit_tree_set_bandwidth, askit_adjoint_scalars,
                     load)

@@ -25,7 +25,7 @@ EXPORTED = [
     "askit_last_error", "askit_tree_destroy", "askit_factor_destroy", "askit_profile_enable",
     "askit_profile_report", "askit_tree_set_bandwidth", "askit_adjoint_scalars", "askit_skeletonize_batched",
     "askit_batch_create", "askit_batch_factorize", "askit_batch_check", "askit_batch_solve", "askit_batch_factor",
-    "askit_batch_destroy", "askit_skeletonize_factorize",
+    "askit_batch_destroy", "askit_skeletonize_factorize", "askit_release_cached_memory",
 ]
 
 
@@ -271,6 +271,13 @@ def askit_profile_report():
     _check(st)
     d = json.loads(buf.value.decode())
     return {k: (v if k == "@timeline" else tuple(v)) for k, v in d.items()}
+
+
+def askit_release_cached_memory():
+    """Frees the library's cache of released device blocks; returns the bytes freed."""
+    n = ctypes.c_uint64(0)
+    _check(load().askit_release_cached_memory(ctypes.byref(n)))
+    return int(n.value)
 
 
 def askit_tree_destroy(tree):

@@ -16,6 +16,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -48,22 +49,104 @@ askit_status fail(askit_status st, const std::string &msg) {
 // ---------------------------------------------------------------------------
 // device memory
 // ---------------------------------------------------------------------------
+// Cache of large device blocks.  A factorization's arenas (leaf LUs, the
+// per-level bases, the refinement's Krylov basis) are several GB each; a
+// fresh hipMalloc of that size can stall for hundreds of ms in the runtime,
+// and repeated factorizations of one problem (new lambda, another precision,
+// a serving loop) ask for the same sizes again.  Blocks of kCacheMin bytes or
+// more are therefore kept on a per-device free list when released and handed
+// out again to a request of at most 1/8 less; the device is synchronized
+// before a block enters the list (as hipFree would), so no queued kernel
+// still uses it when it is reused.  A failed hipMalloc empties the list of
+// that device and tries once more; askit_release_cached_memory empties it on
+// request.
+constexpr size_t kCacheMin = (size_t)64 << 20;
+constexpr size_t kCacheGrain = (size_t)2 << 20;
+struct CachedBlock {
+    void *p;
+    size_t bytes;
+    int dev;
+};
+std::mutex g_cache_mu;
+std::vector<CachedBlock> g_cache;
+
+void cache_flush(int dev) {  // dev < 0: every device
+    std::vector<CachedBlock> out;
+    {
+        std::lock_guard<std::mutex> g(g_cache_mu);
+        std::vector<CachedBlock> keep;
+        for (auto &b : g_cache) (dev < 0 || b.dev == dev ? out : keep).push_back(b);
+        g_cache.swap(keep);
+    }
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto &b : out) {
+        if (b.dev != cur) (void)hipSetDevice(b.dev);
+        (void)hipFree(b.p);
+        if (b.dev != cur) (void)hipSetDevice(cur);
+    }
+}
+
+hipError_t dev_malloc(void **p, size_t *n, int *dev) {
+    (void)hipGetDevice(dev);
+    if (*n < kCacheMin) return hipMalloc(p, *n);
+    *n = (*n + kCacheGrain - 1) / kCacheGrain * kCacheGrain;
+    {
+        std::lock_guard<std::mutex> g(g_cache_mu);
+        int best = -1;
+        for (int i = 0; i < (int)g_cache.size(); i++) {
+            const CachedBlock &b = g_cache[i];
+            if (b.dev == *dev && b.bytes >= *n && b.bytes - *n <= *n / 8 &&
+                (best < 0 || b.bytes < g_cache[best].bytes))
+                best = i;
+        }
+        if (best >= 0) {
+            *p = g_cache[best].p;
+            *n = g_cache[best].bytes;
+            g_cache.erase(g_cache.begin() + best);
+            return hipSuccess;
+        }
+    }
+    hipError_t e = hipMalloc(p, *n);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        cache_flush(*dev);
+        e = hipMalloc(p, *n);
+    }
+    return e;
+}
+
+void dev_free(void *p, size_t n, int dev) {
+    if (n < kCacheMin) {
+        (void)hipFree(p);
+        return;
+    }
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (dev != cur) (void)hipSetDevice(dev);
+    (void)hipDeviceSynchronize();
+    if (dev != cur) (void)hipSetDevice(cur);
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    g_cache.push_back({p, n, dev});
+}
+
 struct DBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    int dev = 0;
     DBuf() = default;
     DBuf(const DBuf &) = delete;
     DBuf &operator=(const DBuf &) = delete;
     ~DBuf() { release(); }
     void release() {
-        if (p) hipFree(p);
+        if (p) dev_free(p, bytes, dev);
         p = nullptr;
         bytes = 0;
     }
     askit_status alloc(size_t n) {
         release();
         if (n == 0) n = 8;
-        if (hipMalloc(&p, n) != hipSuccess) {
+        if (dev_malloc(&p, &n, &dev) != hipSuccess) {
             p = nullptr;
             (void)hipGetLastError();
             return fail(ASKIT_ERR_ALLOC, "device allocation of " + std::to_string(n) + " bytes failed");
@@ -559,6 +642,17 @@ struct askit_factor_s {
 extern "C" {
 
 const char *askit_last_error(void) { return g_err.c_str(); }
+
+askit_status askit_release_cached_memory(uint64_t *bytes_released) {
+    uint64_t tot = 0;
+    {
+        std::lock_guard<std::mutex> g(g_cache_mu);
+        for (auto &b : g_cache) tot += b.bytes;
+    }
+    cache_flush(-1);
+    if (bytes_released) *bytes_released = tot;
+    return ASKIT_OK;
+}
 
 askit_status askit_profile_enable(int32_t on) {
     HIP_TRY(prof_flush());
