@@ -1002,17 +1002,25 @@ struct SkelRun {
                                    err.as<int32_t>());
                 return hipGetLastError();
             }));
-            const int rt = (int)cdiv(nsamp_max, 64), ct = (int)cdiv(cmax, 64);
-            HIP_TRY(timed("skel:k_sample_block" + prof_height(hgt), st, [&] {
-                hipLaunchKernelGGL(k_sample_block, dim3(nqr * rt * ct), dim3(256),
-                                   sizeof(double) * (64 * (d | 1) + 64 * d), st, dsk.as<SkelTask>(), rt, nsamp_max, d,
-                                   ct);
-                return hipGetLastError();
-            }));
+            // the QR tasks hold the one-workgroup nodes first, then the split ones
+            const int rt = (int)cdiv(nsamp_max, 64), ct = (int)cdiv(cmax, 64), none_ = nqr - nsp;
+            const size_t lds = sizeof(double) * (64 * (d | 1) + 64 * d);
+            if (none_ > 0)
+                HIP_TRY(timed("skel:k_sample_rownorm" + prof_height(hgt), st, [&] {
+                    hipLaunchKernelGGL(k_sample_rownorm, dim3(none_ * rt * ct), dim3(256), lds, st,
+                                       dsk.as<SkelTask>(), rt, nsamp_max, d, ct);
+                    return hipGetLastError();
+                }));
+            if (nsp > 0)
+                HIP_TRY(timed("skel:k_sample_block" + prof_height(hgt), st, [&] {
+                    hipLaunchKernelGGL(k_sample_block, dim3(nsp * rt * ct), dim3(256), lds, st,
+                                       dsk.as<SkelTask>() + none_, rt, nsamp_max, d, ct);
+                    return hipGetLastError();
+                }));
         }
         if (n1 > 0) {
             HIP_TRY(timed("skel:k_qrcp" + prof_height(hgt), st, [&] {
-                hipLaunchKernelGGL(k_qrcp, dim3(n1), dim3(512), 0, st, dqr.as<SkelTask>(), s, nsamp_max);
+                hipLaunchKernelGGL(k_qrcp, dim3(n1), dim3(512), 0, st, dqr.as<SkelTask>(), s, nsamp_max, d);
                 return hipGetLastError();
             }));
         }

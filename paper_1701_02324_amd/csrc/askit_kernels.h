@@ -31,7 +31,8 @@ __global__ void k_check_finite(const double *X, int64_t n, int32_t *bad);
 // skeletons (k_skel.hip)
 __global__ void k_sample(const SampTask *tasks, int nsamp, int32_t *err);
 __global__ void k_sample_block(const SkelTask *tasks, int rowtiles, int ldm, int d, int coltiles);
-__global__ void k_qrcp(const SkelTask *tasks, int s, int ldm);
+__global__ void k_sample_rownorm(const SkelTask *tasks, int rowtiles, int ldm, int d, int coltiles);
+__global__ void k_qrcp(const SkelTask *tasks, int s, int ldm, int d);
 __global__ void k_qs_rows(const SkelTask *tasks, QrWork w, int ldm);
 __global__ void k_qs_rowmap(const SkelTask *tasks, QrWork w);
 __global__ void k_qs_init(const SkelTask *tasks, QrWork w, int s, int ldm);

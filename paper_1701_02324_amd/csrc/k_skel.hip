@@ -5,7 +5,11 @@
 //    positions outside the node, drawn uniformly with SplitMix64 (Steele, Lea
 //    & Flood 2014) from the node's own stream, duplicates rejected; when the
 //    complement has at most nsamp positions it is taken whole, in order.
-//  * k_sample_block: the kernel block K(X_S', X_C) in FP64, column-major.
+//  * k_sample_block: the kernel block K(X_S', X_C) in FP64, column-major
+//    (levels factored by the split QR).
+//  * k_sample_rownorm: for the levels factored by k_qrcp, only the squared
+//    row norms of that block in groups of kQsCols columns; k_qrcp generates
+//    the rows it keeps itself.
 //  * k_qrcp: column-pivoted Householder QR of that block, truncated at the
 //    rank s (trailing column norms recomputed at every step, largest norm
 //    first, lowest column on ties), the rank guard |R_jj| <= 1e-14 |R_00|,
@@ -119,6 +123,48 @@ __global__ __launch_bounds__(256) void k_sample_block(const SkelTask *__restrict
     const double *y = ys + r * dp;
     for (int c = threadIdx.x / 64; c < nc; c += 4)
         glb(t.M)[(int64_t)(c0 + c) * ldm + r0 + r] = exp(sqdist(xs + c * d, y, d) * t.scale);
+}
+
+// The one-workgroup QR's input: instead of the block, the squared norm of
+// each row over each group of kQsCols columns (g = 0, kQsCols, ...; the sums
+// row_part forms, in the same order), written as entry (row i, column
+// g / kQsCols) of the node's block.  Same tiling, staging and entries as
+// k_sample_block; a thread forms the group sums of one row.  The block itself
+// is never stored: k_qrcp generates the rows that carry weight (gen_rows).
+__global__ __launch_bounds__(256) void k_sample_rownorm(const SkelTask *__restrict__ tasks, int rowtiles, int ldm,
+                                                        int d, int coltiles) {
+    extern __shared__ double dyn_lds[];  // 64 (d | 1) + 64 d doubles
+    const int dp = d | 1;
+    double *ys = dyn_lds, *xs = dyn_lds + 64 * dp;
+    const int per = rowtiles * coltiles;
+    const int task = blockIdx.x / per, rt = (blockIdx.x % per) % rowtiles, ct = (blockIdx.x % per) / rowtiles;
+    const SkelTask t = tasks[task];
+    const int r0 = rt * 64, c0 = ct * 64;
+    const int sl = t.leaf ? 0 : *glb(t.srl);
+    const int ncand = t.leaf ? t.n : sl + *glb(t.srr);
+    const GLB double *X = glb(t.X);
+    const GLB int32_t *q = glb(t.q);
+    if (r0 >= t.nq || c0 >= ncand) return;
+    const int nr = min(64, t.nq - r0), nc = min(64, ncand - c0);
+    for (int i = threadIdx.x; i < 64 * d; i += blockDim.x) {
+        const int a = i / d, k = i % d;
+        ys[a * dp + k] = a < nr ? X[(int64_t)q[r0 + a] * d + k] : 0.0;
+        xs[i] = a < nc ? X[(int64_t)cand_pos(t, c0 + a, sl) * d + k] : 0.0;
+    }
+    __syncthreads();
+    const int r = threadIdx.x % 64;
+    if (r >= nr) return;
+    const double *y = ys + r * dp;
+    for (int cg = (threadIdx.x / 64) * kQsCols; cg < nc; cg += 4 * kQsCols) {
+        double v[kQsCols];
+#pragma unroll
+        for (int u = 0; u < kQsCols; u++) v[u] = cg + u < nc ? exp(sqdist(xs + (cg + u) * d, y, d) * t.scale) : 0.0;
+        double p = 0.0;
+#pragma unroll
+        for (int u = 0; u < kQsCols; u++)
+            if (cg + u < nc) p = fma(v[u], v[u], p);
+        glb(t.M)[(int64_t)((c0 + cg) / kQsCols) * ldm + r0 + r] = p;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -540,11 +586,54 @@ __device__ inline int pick_pivot(PN nrm, PP pos, int j, int ncand, int lane) {
     return k == 0x7fffffff ? j : k;  // no comparable norm (NaN): keep the order
 }
 
+// Rows of the sampled block generated in place, compacted: entry (k, c) =
+// K(x of sampled row src[k], x of candidate c) for k < nk, by the arithmetic
+// of k_sample_block (so the values are those the block would hold).  Each
+// wave takes columns wave, wave + kQrWaves, ...; lane l the rows l + 64 u;
+// for d <= kXrDim a lane keeps its row point in registers.
+template <typename PM, typename PS>
+__device__ inline void gen_rows(const SkelTask &t, PM M, int ldm, int d, int sl, int ncand, PS src, int nk) {
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    const GLB double *X = glb(t.X);
+    const GLB int32_t *q = glb(t.q);
+    for (int k0 = 0; k0 < nk; k0 += kWave) {
+        const int k = k0 + lane;
+        const bool live = k < nk;
+        const int64_t yrow = live ? (int64_t)q[src[k]] * d : 0;
+        if (d <= kXrDim) {
+            double y[kXrDim];
+#pragma unroll
+            for (int e = 0; e < kXrDim; e++) y[e] = e < d ? X[yrow + e] : 0.0;
+            for (int c = wave; c < ncand; c += kQrWaves) {
+                const int64_t xc = (int64_t)cand_pos(t, c, sl) * d;
+                double r2 = 0.0;
+#pragma unroll
+                for (int e = 0; e < kXrDim; e++)
+                    if (e < d) {
+                        const double df = X[xc + e] - y[e];
+                        r2 = fma(df, df, r2);
+                    }
+                if (live) M[(int64_t)c * ldm + k] = exp(r2 * t.scale);
+            }
+        } else {
+            for (int c = wave; c < ncand; c += kQrWaves) {
+                const int64_t xc = (int64_t)cand_pos(t, c, sl) * d;
+                double r2 = 0.0;
+                for (int e = 0; e < d; e++) {
+                    const double df = X[xc + e] - X[yrow + e];
+                    r2 = fma(df, df, r2);
+                }
+                if (live) M[(int64_t)c * ldm + k] = exp(r2 * t.scale);
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // one workgroup per node: block, norms and reflector traffic through L2/HBM,
 // the pivot bookkeeping in LDS
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kQrThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_qrcp(const SkelTask *__restrict__ tasks, int s, int ldm) {
+__global__ __launch_bounds__(kQrThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_qrcp(const SkelTask *__restrict__ tasks, int s, int ldm, int d) {
     __shared__ double nrm[kQrMaxCols];
     __shared__ int32_t pos[kQrMaxCols];
     __shared__ double Rjj[kQrMaxRank];
@@ -575,19 +664,26 @@ __global__ __launch_bounds__(kQrThreads) __attribute__((amdgpu_waves_per_eu(4)))
         return;
     }
     int rows = t.nq;
-    // drop the numerically zero rows
+    // drop the numerically zero rows: row norms from the group sums that
+    // k_sample_rownorm left in the block's first columns, then the kept rows
+    // (all rows when none is dropped, row 0 when every row is zero) generated
+    // in their compacted places
     for (int i = tid; i < rows; i += kQrThreads) {
         double a = 0.0;
-        for (int g = 0; g < ncand; g += kQsCols) a += row_part(M, ldm, i, g, min(ncand, g + kQsCols));
+        for (int g = 0; g < ncand; g += kQsCols) a += M[(int64_t)(g / kQsCols) * ldm + i];
         vh[i] = a;
     }
     __syncthreads();
     const int kept = row_map(vh, rows, rmap, wcnt, red);
-    if (kept < rows) {
-        for (int c = wave; c < ncand; c += kQrWaves) compact_col(M + (int64_t)c * ldm, rmap, rows, lane);
-        rows = kept > 0 ? kept : 1;
-        __syncthreads();
+    int32_t *src = reinterpret_cast<int32_t *>(vh);  // the row norms are consumed
+    for (int i = tid; i < rows; i += kQrThreads) {
+        const int k = kept > 0 ? (int)rmap[i] : (i == 0 ? 0 : -1);
+        if (k >= 0) src[k] = i;
     }
+    if (kept < rows) rows = kept > 0 ? kept : 1;
+    __syncthreads();
+    gen_rows(t, M, ldm, d, sl, ncand, src, rows);
+    __syncthreads();
     const int steps = s < rows ? s : rows;
     for (int c = tid; c < ncand; c += kQrThreads) pos[c] = c;
     for (int c = wave; c < ncand; c += kQrWaves) {
