@@ -215,13 +215,15 @@ __device__ inline double row_part(PM M, int ldm, int i, int c0, int c1) {
     return p;
 }
 
-// Rows of the sampled block whose squared norm is below 1e-60 of the block's
-// squared Frobenius norm are dropped (the rest keep their order).  Their total
-// weight, under 1e-57 of the block's, is far below FP64 rounding of every
-// column norm and of the rank guard's threshold, so the pivots, R and T are
-// those of the whole block up to rounding; the trailing updates then stream
-// only the rows that carry the interaction.  rn: squared row norms (summed
-// over groups of kQsCols columns in order); all kQrThreads threads call this;
+// Rows of the sampled block whose squared norm is below 1e-44 of the block's
+// squared Frobenius norm are dropped (the rest keep their order).  Taken
+// together (at most 4096 rows) they are a perturbation of the block of
+// Frobenius norm below 6.4e-21 of the block's, some 17,000 times smaller than
+// the backward error FP64 Householder QR commits anyway (at least the unit
+// roundoff 1.1e-16 times the block's norm), so the pivots, R and T are those
+// of the whole block up to rounding; the trailing updates then stream only
+// the rows that carry the interaction.  rn: squared row norms (summed over
+// groups of kQsCols columns in order); all kQrThreads threads call this;
 // returns the number of kept rows and fills rmap (new index or -1).
 template <typename PR, typename PI>
 __device__ inline int row_map(PR rn, int rows, PI rmap, int32_t *wcnt, double *red) {
@@ -229,7 +231,7 @@ __device__ inline int row_map(PR rn, int rows, PI rmap, int32_t *wcnt, double *r
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
     double part = 0.0;
     for (int i = tid; i < rows; i += kQrThreads) part += rn[i];
-    const double thr = 1e-60 * block_sum(part, red);
+    const double thr = 1e-44 * block_sum(part, red);
     int kept = 0;
     for (int base = 0; base < rows; base += kQrThreads) {
         const int i = base + tid;
