@@ -20,69 +20,79 @@ constexpr int kLuMaxN = 512;
 static_assert(kLuFThreads >= kLuMaxN, "one thread per row of the largest matrix");
 
 // ---------------------------------------------------------------------------
-// Trailing update A22 -= L21 U12 of a blocked LU (panel columns kb..kb+31,
-// trailing rows and columns from j0, nt of them), computed as its transpose
+// Trailing update A22 -= L21 U12 of a blocked LU of depth KP (kPanel): the
+// rows r0 + ci (ci < nr) and columns c0 + cj (cj < nc) of A receive the
+// product of L21 = A(rows, kb .. kb+KP-1) and U12, computed as its transpose
 // U12^T L21^T so that an accumulator register holds 16 consecutive rows of a
-// column of A22 (coalesced column-major access).  Logical row i of A is
-// physical row rowof(i).  U12 is staged in LDS, row-major with leading
-// dimension ldw = nt rounded up to 64, zero beyond column nt.  Wave w takes
-// the 16-row stripes w, w + NW, ... in 64-column blocks; the next block's
-// A22 and L21 values are fetched before the current block's products, and
-// each block's 32 U12 operands are read from LDS before its 32 products.
+// column (coalesced column-major access).  Logical row i of A is physical
+// row rowof(i).  U12 is staged in LDS, row-major: W[k * ldw + cj] for cj in
+// whole 64-column blocks covering nc (values past nc are never written
+// back).  Wave w takes the 16-row stripes w, w + NW, ...: it loads the
+// stripe's L21 rows once, then goes over 64-column blocks, fetching the next
+// block's A22 values before the current block's products; a block's U12
+// operands are read from LDS (4 rows of k at a time) before their products.
 // ---------------------------------------------------------------------------
-template <int NW, class RowOf>
-__device__ inline void trailing_update(GLB double *A, int lda, int kb, int j0, int nt, const double *W, int ldw,
-                                       RowOf rowof, int wave, int lane) {
-    const int bt = (nt + 15) / 16, ncb = ldw / 64;
-    const int nst = wave < bt ? (bt - wave + NW - 1) / NW : 0, nit = nst * ncb;
+template <int NW, int KP, class RowOf>
+__device__ inline void trailing_update(GLB double *A, int lda, int kb, int r0, int nr, int c0, int nc,
+                                       const double *W, int ldw, RowOf rowof, int wave, int lane) {
+    static_assert(KP % 16 == 0, "depth in multiples of 16");
+    const int bt = (nr + 15) / 16, ncb = (nc + 63) / 64;
     const int row = lane % 16, kq = lane / 16;
-    auto fetch = [&](int it, double (&c)[4][4], double (&l)[kPanel / 4]) {
-        const int st = wave + NW * (it / ncb), cb0 = 4 * (it % ncb), ci = st * 16 + row;
-        const int64_t rb = ci < nt ? rowof(j0 + ci) : 0;
+    for (int st = wave; st < bt; st += NW) {
+        const int ci = st * 16 + row;
+        const int64_t rb = ci < nr ? rowof(r0 + ci) : 0;
+        // this stripe's L21 rows, kept for all its column blocks
+        double l[KP / 4];
 #pragma unroll
-        for (int kk = 0; kk < kPanel / 4; kk++) l[kk] = ci < nt ? A[rb + (int64_t)(kb + 4 * kk + kq) * lda] : 0.0;
-#pragma unroll
-        for (int q = 0; q < 4; q++)
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int cj = (cb0 + q) * 16 + 4 * r + kq;
-                c[q][r] = (ci < nt && cj < nt) ? A[rb + (int64_t)(j0 + cj) * lda] : 0.0;
-            }
-    };
-    auto update = [&](int it, const double (&c)[4][4], const double (&l)[kPanel / 4]) {
-        const int st = wave + NW * (it / ncb), cb0 = 4 * (it % ncb), ci = st * 16 + row;
-        double ua[kPanel / 4][4];
-#pragma unroll
-        for (int kk = 0; kk < kPanel / 4; kk++)
-#pragma unroll
-            for (int q = 0; q < 4; q++) ua[kk][q] = W[(4 * kk + kq) * ldw + (cb0 + q) * 16 + row];
-        dbl4 acc[4];
-#pragma unroll
-        for (int q = 0; q < 4; q++) acc[q] = dbl4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int kk = 0; kk < kPanel / 4; kk++)
-#pragma unroll
-            for (int q = 0; q < 4; q++) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[kk][q], l[kk], acc[q], 0, 0, 0);
-        // acc[q][r] = A22 entry (st*16 + lane%16, (cb0+q)*16 + 4r + lane/16)
-        if (ci < nt) {
-            const int64_t rb = rowof(j0 + ci);
+        for (int kk = 0; kk < KP / 4; kk++) l[kk] = ci < nr ? A[rb + (int64_t)(kb + 4 * kk + kq) * lda] : 0.0;
+        auto fetch = [&](int cbk, double (&c)[4][4]) {
 #pragma unroll
             for (int q = 0; q < 4; q++)
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
-                    const int cj = (cb0 + q) * 16 + 4 * r + kq;
-                    if (cj < nt) A[rb + (int64_t)(j0 + cj) * lda] = c[q][r] - acc[q][r];
+                    const int cj = (4 * cbk + q) * 16 + 4 * r + kq;
+                    c[q][r] = (ci < nr && cj < nc) ? A[rb + (int64_t)(c0 + cj) * lda] : 0.0;
                 }
-        }
-    };
-    double c0[4][4], l0[kPanel / 4], c1[4][4], l1[kPanel / 4];
-    if (nit > 0) fetch(0, c0, l0);
-    for (int it = 0; it < nit; it += 2) {
-        if (it + 1 < nit) fetch(it + 1, c1, l1);
-        update(it, c0, l0);
-        if (it + 1 < nit) {
-            if (it + 2 < nit) fetch(it + 2, c0, l0);
-            update(it + 1, c1, l1);
+        };
+        auto update = [&](int cbk, const double (&c)[4][4]) {
+            const int cb0 = 4 * cbk;
+            dbl4 acc[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) acc[q] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int h = 0; h < KP / 16; h++) {
+                double ua[4][4];
+#pragma unroll
+                for (int kk = 0; kk < 4; kk++)
+#pragma unroll
+                    for (int q = 0; q < 4; q++)
+                        ua[kk][q] = W[(4 * (4 * h + kk) + kq) * ldw + (cb0 + q) * 16 + row];
+#pragma unroll
+                for (int kk = 0; kk < 4; kk++)
+#pragma unroll
+                    for (int q = 0; q < 4; q++)
+                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[kk][q], l[4 * h + kk], acc[q], 0, 0, 0);
+            }
+            // acc[q][r] = entry (row st*16 + lane%16, column (cb0+q)*16 + 4r + lane/16)
+            if (ci < nr) {
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        const int cj = (cb0 + q) * 16 + 4 * r + kq;
+                        if (cj < nc) A[rb + (int64_t)(c0 + cj) * lda] = c[q][r] - acc[q][r];
+                    }
+            }
+        };
+        double cA[4][4], cB[4][4];
+        fetch(0, cA);
+        for (int cbk = 0; cbk < ncb; cbk += 2) {
+            if (cbk + 1 < ncb) fetch(cbk + 1, cB);
+            update(cbk, cA);
+            if (cbk + 1 < ncb) {
+                if (cbk + 2 < ncb) fetch(cbk + 2, cA);
+                update(cbk + 1, cB);
+            }
         }
     }
 }
@@ -210,7 +220,8 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu(const LuTask *__restrict__ t
             }
         }
         __syncthreads();
-        trailing_update<NW>(A, lda, kb, j0, nt, W, ldw, [&](int i) -> int64_t { return prow[i]; }, wave, lane);
+        trailing_update<NW, kPanel>(A, lda, kb, j0, nt, j0, nt, W, ldw, [&](int i) -> int64_t { return prow[i]; }, wave,
+                                    lane);
         __syncthreads();
     }
     // rows in place: column batches of kPanel staged in W
@@ -382,7 +393,7 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu_nopiv(const LuTask *__restri
         }
         __syncthreads();
         // ---- trailing update A22 -= L21 U12
-        trailing_update<NW>(A, lda, kb, j0, nt, Up, ldw, [](int i) -> int64_t { return i; }, wave, lane);
+        trailing_update<NW, kPanel>(A, lda, kb, j0, nt, j0, nt, Up, ldw, [](int i) -> int64_t { return i; }, wave, lane);
         __syncthreads();
     }
     if (tid == 0 && t.ratio) *glb(t.ratio) = n ? (s_max > 0.0 ? s_min / s_max : 0.0) : 1.0;
@@ -496,6 +507,7 @@ template <typename T, int NR, bool TRANS>
 __global__ __launch_bounds__(kLsThreads) void k_lusolve(const LuTask *__restrict__ tasks, int ntask, int nrhs,
                                                         int panels) {
     __shared__ double S[kLuMaxN][NR + 1];
+    __shared__ int32_t P[kLuMaxN];  // row interchanges, applied in order from LDS
     const int total = ntask * panels, chunk = (total + 7) / 8;
     const int L = (blockIdx.x % 8) * chunk + blockIdx.x / 8;
     if (L >= total) return;
@@ -513,13 +525,14 @@ __global__ __launch_bounds__(kLsThreads) void k_lusolve(const LuTask *__restrict
         const int r = i / NR, c = i % NR;
         S[r][c] = (r < n && c < ncols) ? (double)B[(int64_t)r * t.ldb + c0 + c] : 0.0;
     }
+    for (int k = tid; k < n; k += kLsThreads) P[k] = piv[k];
     __syncthreads();
     auto Lget = [&](int r, int c) -> double { return (r < n && c < n && r > c) ? A[r + (int64_t)c * lda] : 0.0; };
     auto Uget = [&](int r, int c) -> double { return (r < n && c < n && r <= c) ? A[r + (int64_t)c * lda] : 0.0; };
     if (!TRANS) {
         if (tid < NR)
             for (int k = 0; k < n; k++) {
-                const int p = piv[k];
+                const int p = P[k];
                 if (p != k) {
                     double a = S[k][tid];
                     S[k][tid] = S[p][tid];
@@ -548,7 +561,7 @@ __global__ __launch_bounds__(kLsThreads) void k_lusolve(const LuTask *__restrict
         }
         if (tid < NR)
             for (int k = n - 1; k >= 0; k--) {
-                const int p = piv[k];
+                const int p = P[k];
                 if (p != k) {
                     double a = S[k][tid];
                     S[k][tid] = S[p][tid];
