@@ -157,10 +157,30 @@ struct DBuf {
     template <class T> T *as() const { return (T *)p; }
 };
 
+// Host-to-device uploads of task lists are synchronous copies, except while
+// an upload stream is set (UploadOnStream): then they are queued on that
+// stream from host copies kept until the guard ends, so they neither wait
+// for nor delay the kernels queued on other streams.
+hipStream_t g_upload_stream = nullptr;
+std::vector<std::vector<char>> g_upload_keep;
+
 static askit_status copy_up(void *dst, const void *src, size_t bytes) {
-    HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    if (g_upload_stream) {
+        g_upload_keep.emplace_back((const char *)src, (const char *)src + bytes);
+        HIP_TRY(hipMemcpyAsync(dst, g_upload_keep.back().data(), bytes, hipMemcpyHostToDevice, g_upload_stream));
+    } else {
+        HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    }
     return ASKIT_OK;
 }
+
+// uploads queued on `s` while the guard lives; the kept host copies are
+// released at the end of the call that owns the guard (after it has
+// synchronized with `s`)
+struct UploadOnStream {
+    explicit UploadOnStream(hipStream_t s) { g_upload_stream = s; }
+    ~UploadOnStream() { g_upload_stream = nullptr; }
+};
 
 template <class T> askit_status upload(DBuf &b, const std::vector<T> &v) {
     ST_TRY(b.alloc(sizeof(T) * std::max<size_t>(v.size(), 1)));
@@ -1442,6 +1462,18 @@ struct SideStream {
     }
 };
 
+// releases the host copies of queued uploads once every stream that read
+// them has been synchronized (end of the owning call, also on errors: the
+// error paths synchronize the device first)
+struct UploadKeep {
+    ~UploadKeep() {
+        if (!g_upload_keep.empty()) {
+            (void)hipDeviceSynchronize();
+            g_upload_keep.clear();
+        }
+    }
+};
+
 static askit_status skel_factor_impl(askit_tree t, double lambda, int precision, hipStream_t st, askit_factor *out,
                                      double &t_skel) {
     auto t0 = std::chrono::steady_clock::now();
@@ -1453,6 +1485,13 @@ static askit_status skel_factor_impl(askit_tree t, double lambda, int precision,
     // non-blocking: no implicit ordering against the legacy default stream
     HIP_TRY(hipStreamCreateWithFlags(&B.s, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&B.e, hipEventDisableTiming));
+    // uploads of the factorization's task lists go through their own
+    // stream, so building the plan of height h - 1 neither waits for the
+    // skeletonization of height h queued before it nor holds it back
+    SideStream U;
+    HIP_TRY(hipStreamCreateWithFlags(&U.s, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&U.e, hipEventDisableTiming));
+    UploadKeep keep;
     const std::vector<askit_factor> fs{f.get()};
     Plan P;
     P.tag = "factor";
@@ -1462,22 +1501,31 @@ static askit_status skel_factor_impl(askit_tree t, double lambda, int precision,
     HIP_TRY(hipStreamWaitEvent(B.s, B.e, 0));
     HIP_TRY(P.run_from(B.s, t->s, 0));
     size_t done = P.steps.size();
+    auto factor_part = [&](int part) -> askit_status {
+        {
+            UploadOnStream g(U.s);
+            ST_TRY(factor_plan_part(fs, P, part));
+        }
+        HIP_TRY(hipEventRecord(U.e, U.s));
+        HIP_TRY(hipStreamWaitEvent(B.s, U.e, 0));
+        HIP_TRY(P.run_from(B.s, t->s, done));
+        done = P.steps.size();
+        return ASKIT_OK;
+    };
     for (int hgt = 0; hgt <= R.Hmax; hgt++) {
-        // wait for height hgt - 1 and read its ranks; uploads of both plans
-        // are made before this height's launches, while the caller's stream
-        // is idle
-        if (hgt < R.Hmax) ST_TRY(R.prepare(hgt));
-        else {
+        // wait for height hgt - 1 and read its ranks (the skeletonization
+        // uploads are made while the caller's stream is idle), launch height
+        // hgt, then build and queue the factorization of height hgt - 1
+        if (hgt < R.Hmax) {
+            ST_TRY(R.prepare(hgt));
+            ST_TRY(R.launch(hgt));
+        } else {
             ST_TRY(R.end());
             t_skel = ms_since(t0);
         }
-        if (hgt > 0) ST_TRY(factor_plan_part(fs, P, hgt - 1));
-        if (hgt < R.Hmax) ST_TRY(R.launch(hgt));
-        HIP_TRY(P.run_from(B.s, t->s, done));
-        done = P.steps.size();
+        if (hgt > 0) ST_TRY(factor_part(hgt - 1));
     }
-    ST_TRY(factor_plan_part(fs, P, R.Hmax));
-    HIP_TRY(P.run_from(B.s, t->s, done));
+    ST_TRY(factor_part(R.Hmax));
     // the caller's stream continues after the factorization
     HIP_TRY(hipEventRecord(B.e, B.s));
     HIP_TRY(hipStreamWaitEvent(st, B.e, 0));
