@@ -135,9 +135,9 @@ ROOF_TABLE = [
 TRAFFIC = {
     "factor:k_lu_nopiv": {
         "source": ["k_lu.hip", "askit_dev.h"],
-        "src_sha256": "399212e376a08bb21c3f99a181537f38ad15e4e84c64cb0f1afe5cec8aacf42e",
+        "src_sha256": "5f4bcaa35ef5ca90be67b09b781a7a2034a707d96be223f0d897f74a8afb9721",
         "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": 56175158084.934166,
+        "bytes_per_launch": 53925018875.768906,
     },
 }
 
