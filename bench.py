@@ -62,7 +62,10 @@ def algorithmic_counts(N, d, m, s, D, nsamp, nrhs, ranks=None, split_levels=6):
                           Nodes at tree levels <= split_levels count for the
                           split form (skel:k_qrcp_split), the rest for k_qrcp
       skel:k_sample_block 3d + 1 flops per sampled kernel entry (difference,
-                          fma, exp counted as one), nodes with c > s only
+                          fma, exp counted as one), nodes with c > s only, at
+                          the split levels; skel:k_sample_rownorm the same at
+                          the other levels (it forms the entries and their
+                          row sums, k_qrcp regenerates the kept rows)
       factor:k_lu_nopiv   (2/3) m^3 per leaf LU (no row exchanges)
       factor:k_lu         (2/3) n^3 per Z LU (n = s_l + s_r, partial pivoting)
       factor:k_lusolve    2 n^2 s_a (leaf Phat, internal Z^-1 P_c below the root)
@@ -77,8 +80,8 @@ def algorithmic_counts(N, d, m, s, D, nsamp, nrhs, ranks=None, split_levels=6):
     sz = node_sizes(N, D)
     r = np.full(nn, s, dtype=np.int64) if ranks is None else np.asarray(ranks, dtype=np.int64)
     first_leaf = (1 << D) - 1
-    c = {k: 0.0 for k in ("qr", "qr1", "qrs", "samp", "lu", "lu_leaf", "lu_z", "fsolve", "zblk", "tele", "sbytes",
-                          "sflops", "skmm")}
+    c = {k: 0.0 for k in ("qr", "qr1", "qrs", "samp", "samp1", "samps", "lu", "lu_leaf", "lu_z", "fsolve", "zblk",
+                          "tele", "sbytes", "sflops", "skmm")}
     for i in range(nn):
         n = float(sz[i])
         leaf = i >= first_leaf
@@ -89,8 +92,10 @@ def algorithmic_counts(N, d, m, s, D, nsamp, nrhs, ranks=None, split_levels=6):
                 k = int(r[i])
                 w = sum(6.0 * (rows - j) * (cols - j - 1) for j in range(k)) + k * k * (cols - k)
                 c["qr"] += w
-                c["qrs" if int(np.log2(i + 1)) <= split_levels else "qr1"] += w
+                split_node = int(np.log2(i + 1)) <= split_levels
+                c["qrs" if split_node else "qr1"] += w
                 c["samp"] += rows * cols * (3.0 * d + 1)
+                c["samps" if split_node else "samp1"] += rows * cols * (3.0 * d + 1)
         nlu = n if leaf else float(r[2 * i + 1] + r[2 * i + 2])
         c["lu"] += (2.0 / 3.0) * nlu ** 3
         c["lu_leaf" if leaf else "lu_z"] += (2.0 / 3.0) * nlu ** 3
@@ -117,7 +122,8 @@ ROOF_TABLE = [
     # then the measured launches of the timed steps are used)
     ("skel:k_qrcp", "qr1", "alu", "fp64", "TFLOP/s", None),
     ("skel:k_qrcp_split", "qrs", "alu", "fp64", "TFLOP/s", None),
-    ("skel:k_sample_block", "samp", "alu", "fp64", "TFLOP/s", lambda D: D),
+    ("skel:k_sample_rownorm", "samp1", "alu", "fp64", "TFLOP/s", None),
+    ("skel:k_sample_block", "samps", "alu", "fp64", "TFLOP/s", None),
     ("factor:k_lu_nopiv", "lu_leaf", "mfma", "fp64", "TFLOP/s", lambda D: 1),
     ("factor:k_lu", "lu_z", "alu", "fp64", "TFLOP/s", lambda D: D),
     ("factor:k_lusolve", "fsolve", "mfma", "fp64", "TFLOP/s", lambda D: D),
