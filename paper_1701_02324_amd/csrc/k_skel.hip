@@ -590,45 +590,142 @@ __device__ inline int pick_pivot(PN nrm, PP pos, int j, int ncand, int lane) {
 
 // Rows of the sampled block generated in place, compacted: entry (k, c) =
 // K(x of sampled row src[k], x of candidate c) for k < nk, by the arithmetic
-// of k_sample_block (so the values are those the block would hold).  Each
-// wave takes columns wave, wave + kQrWaves, ...; lane l the rows l + 64 u;
-// for d <= kXrDim a lane keeps its row point in registers.
+// of k_sample_block (so the values are those the block would hold).  The
+// candidate points are staged in xs (capacity xcap doubles) by chunks of
+// xcap / d columns; each wave takes the chunk's columns wave, wave +
+// kQrWaves, ...; lane l the rows l + 64 u.  For d <= kXrDim a lane keeps its
+// row point in registers.  All kQrThreads threads call this.
 template <typename PM, typename PS>
-__device__ inline void gen_rows(const SkelTask &t, PM M, int ldm, int d, int sl, int ncand, PS src, int nk) {
+__device__ inline void gen_rows(const SkelTask &t, PM M, int ldm, int d, int sl, int ncand, PS src, int nk,
+                                double *xs, int xcap) {
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
     const GLB double *X = glb(t.X);
     const GLB int32_t *q = glb(t.q);
-    for (int k0 = 0; k0 < nk; k0 += kWave) {
-        const int k = k0 + lane;
-        const bool live = k < nk;
-        const int64_t yrow = live ? (int64_t)q[src[k]] * d : 0;
-        if (d <= kXrDim) {
-            double y[kXrDim];
+    const int cc = xcap / d;
+    for (int c0 = 0; c0 < ncand; c0 += cc) {
+        const int nc = min(cc, ncand - c0);
+        __syncthreads();
+        for (int e = tid; e < nc * d; e += kQrThreads) xs[e] = X[(int64_t)cand_pos(t, c0 + e / d, sl) * d + e % d];
+        __syncthreads();
+        for (int k0 = 0; k0 < nk; k0 += kWave) {
+            const int k = k0 + lane;
+            const bool live = k < nk;
+            const int64_t yrow = live ? (int64_t)q[src[k]] * d : 0;
+            if (d <= kXrDim) {
+                double y[kXrDim];
 #pragma unroll
-            for (int e = 0; e < kXrDim; e++) y[e] = e < d ? X[yrow + e] : 0.0;
-            for (int c = wave; c < ncand; c += kQrWaves) {
-                const int64_t xc = (int64_t)cand_pos(t, c, sl) * d;
-                double r2 = 0.0;
+                for (int e = 0; e < kXrDim; e++) y[e] = e < d ? X[yrow + e] : 0.0;
+                for (int c = wave; c < nc; c += kQrWaves) {
+                    const double *xc = xs + c * d;
+                    double r2 = 0.0;
 #pragma unroll
-                for (int e = 0; e < kXrDim; e++)
-                    if (e < d) {
-                        const double df = X[xc + e] - y[e];
+                    for (int e = 0; e < kXrDim; e++)
+                        if (e < d) {
+                            const double df = xc[e] - y[e];
+                            r2 = fma(df, df, r2);
+                        }
+                    if (live) M[(int64_t)(c0 + c) * ldm + k] = exp(r2 * t.scale);
+                }
+            } else {
+                for (int c = wave; c < nc; c += kQrWaves) {
+                    const double *xc = xs + c * d;
+                    double r2 = 0.0;
+                    for (int e = 0; e < d; e++) {
+                        const double df = xc[e] - X[yrow + e];
                         r2 = fma(df, df, r2);
                     }
-                if (live) M[(int64_t)c * ldm + k] = exp(r2 * t.scale);
-            }
-        } else {
-            for (int c = wave; c < ncand; c += kQrWaves) {
-                const int64_t xc = (int64_t)cand_pos(t, c, sl) * d;
-                double r2 = 0.0;
-                for (int e = 0; e < d; e++) {
-                    const double df = X[xc + e] - X[yrow + e];
-                    r2 = fma(df, df, r2);
+                    if (live) M[(int64_t)(c0 + c) * ldm + k] = exp(r2 * t.scale);
                 }
-                if (live) M[(int64_t)c * ldm + k] = exp(r2 * t.scale);
             }
         }
     }
+}
+
+// squared norms of rows [0, rows) of the columns at positions 0 .. ncand-1
+// (as col_norm, with the loads of eight columns issued together when
+// rows <= 4 * kWave); one wave per column group
+template <typename PM, typename PN>
+__device__ inline void col_norms(PM M, int ldm, int ncand, int rows, PN nrm, int lane, int wave) {
+    if (rows > 4 * kWave) {
+        for (int c = wave; c < ncand; c += kQrWaves) {
+            const double v = col_norm(M + (int64_t)c * ldm, rows, lane);
+            if (lane == 0) nrm[c] = v;
+        }
+        return;
+    }
+    constexpr int G = 8;
+    for (int c0 = wave; c0 < ncand; c0 += kQrWaves * G) {
+        double v[G][4];
+#pragma unroll
+        for (int u = 0; u < G; u++) {
+            const int c = c0 + u * kQrWaves;
+#pragma unroll
+            for (int t4 = 0; t4 < 4; t4++) {
+                const int i = lane + t4 * kWave;
+                v[u][t4] = (c < ncand && i < rows) ? M[(int64_t)c * ldm + i] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < G; u++) {
+            const int c = c0 + u * kQrWaves;
+            double acc = 0.0;
+#pragma unroll
+            for (int t4 = 0; t4 < 4; t4++)
+                if (lane + t4 * kWave < rows) acc = fma(v[u][t4], v[u][t4], acc);
+            acc = wave_sum(acc);
+            if (lane == 0 && c < ncand) nrm[c] = acc;
+        }
+    }
+}
+
+// Nodes with |C| <= s: skeleton = candidates, P = I (all kQrThreads threads)
+__device__ inline void qr_identity(const SkelTask &t, int s, int sl, int ncand) {
+    const int tid = threadIdx.x;
+    auto prow = [&](int c) { return t.leaf ? c : (c < sl ? c : s + (c - sl)); };
+    for (int k = tid; k < s; k += kQrThreads) glb(t.skel)[k] = k < ncand ? cand_pos(t, k, sl) : -1;
+    for (int64_t i = tid; i < (int64_t)ncand * ncand; i += kQrThreads) {
+        const int c = (int)(i / ncand), k = (int)(i % ncand);
+        glb(t.Pt)[(int64_t)prow(c) * s + k] = k == c ? 1.0 : 0.0;
+    }
+    if (tid == 0) {
+        *glb(t.sr) = ncand;
+        *glb(t.trunc) = 0;
+    }
+}
+
+// Rows kept by the QR (R29): row norms from the group sums k_sample_rownorm
+// left in the block's first columns, the row map, and src[k] = sampled row
+// of kept row k (in vh, reused as int32).  Returns the rows in use: the kept
+// ones, all rows when none is dropped, row 0 when every row is zero.  All
+// kQrThreads threads; the block itself is not touched.
+template <typename PM>
+__device__ inline int qr_row_select(const SkelTask &t, PM M, int ldm, int ncand, double *vh, int16_t *rmap,
+                                    int32_t *wcnt, double *red) {
+    const int tid = threadIdx.x;
+    int rows = t.nq;
+    const int ngrp = (ncand + kQsCols - 1) / kQsCols;
+    for (int i = tid; i < rows; i += kQrThreads) {
+        double a = 0.0;
+        for (int g0 = 0; g0 < ngrp; g0 += 16) {  // 16 loads in flight, then added in order
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; u++) v[u] = g0 + u < ngrp ? M[(int64_t)(g0 + u) * ldm + i] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 16; u++)
+                if (g0 + u < ngrp) a += v[u];
+        }
+        vh[i] = a;
+    }
+    __syncthreads();
+    const int kept = row_map(vh, rows, rmap, wcnt, red);
+    int32_t *src = reinterpret_cast<int32_t *>(vh);  // the row norms are consumed
+    for (int i = tid; i < rows; i += kQrThreads) {
+        const int k = kept > 0 ? (int)rmap[i] : (i == 0 ? 0 : -1);
+        if (k >= 0) src[k] = i;
+    }
+    if (kept < rows) rows = kept > 0 ? kept : 1;
+    __syncthreads();
+    return rows;
 }
 
 // ---------------------------------------------------------------------------
@@ -651,47 +748,17 @@ __global__ __launch_bounds__(kQrThreads) __attribute__((amdgpu_waves_per_eu(4)))
     const int sl = t.leaf ? 0 : *glb(t.srl);
     const int ncand = node_ncand(t);
     GLB double *M = glb(t.M);
-    auto prow = [&](int c) { return t.leaf ? c : (c < sl ? c : s + (c - sl)); };
-
     if (ncand <= s) {  // no compression: skeleton = candidates, P = I
-        for (int k = tid; k < s; k += kQrThreads) glb(t.skel)[k] = k < ncand ? cand_pos(t, k, sl) : -1;
-        for (int64_t i = tid; i < (int64_t)ncand * ncand; i += kQrThreads) {
-            const int c = (int)(i / ncand), k = (int)(i % ncand);
-            glb(t.Pt)[(int64_t)prow(c) * s + k] = k == c ? 1.0 : 0.0;
-        }
-        if (tid == 0) {
-            *glb(t.sr) = ncand;
-            *glb(t.trunc) = 0;
-        }
+        qr_identity(t, s, sl, ncand);
         return;
     }
-    int rows = t.nq;
-    // drop the numerically zero rows: row norms from the group sums that
-    // k_sample_rownorm left in the block's first columns, then the kept rows
-    // (all rows when none is dropped, row 0 when every row is zero) generated
-    // in their compacted places
-    for (int i = tid; i < rows; i += kQrThreads) {
-        double a = 0.0;
-        for (int g = 0; g < ncand; g += kQsCols) a += M[(int64_t)(g / kQsCols) * ldm + i];
-        vh[i] = a;
-    }
-    __syncthreads();
-    const int kept = row_map(vh, rows, rmap, wcnt, red);
-    int32_t *src = reinterpret_cast<int32_t *>(vh);  // the row norms are consumed
-    for (int i = tid; i < rows; i += kQrThreads) {
-        const int k = kept > 0 ? (int)rmap[i] : (i == 0 ? 0 : -1);
-        if (k >= 0) src[k] = i;
-    }
-    if (kept < rows) rows = kept > 0 ? kept : 1;
-    __syncthreads();
-    gen_rows(t, M, ldm, d, sl, ncand, src, rows);
+    int rows = qr_row_select(t, M, ldm, ncand, vh, rmap, wcnt, red);
+    const int32_t *src = reinterpret_cast<const int32_t *>(vh);
+    gen_rows(t, M, ldm, d, sl, ncand, src, rows, nrm, kQrMaxCols);  // nrm is free until the norms
     __syncthreads();
     const int steps = s < rows ? s : rows;
     for (int c = tid; c < ncand; c += kQrThreads) pos[c] = c;
-    for (int c = wave; c < ncand; c += kQrWaves) {
-        const double v = col_norm(M + (int64_t)c * ldm, rows, lane);
-        if (lane == 0) nrm[c] = v;
-    }
+    col_norms(M, ldm, ncand, rows, nrm, lane, wave);
     if (tid == 0) {
         s_rank = steps;
         s_zero = 0;
