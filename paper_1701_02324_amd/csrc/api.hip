@@ -242,13 +242,19 @@ Prof g_prof;
 
 template <class F> hipError_t timed(const std::string &name, hipStream_t st, F &&f) {
     if (!g_prof.on) return f();
-    hipEvent_t a, b;
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return hipErrorOutOfMemory;
-    hipEventRecord(a, st);
-    hipError_t e = f();
-    hipEventRecord(b, st);
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = hipEventRecord(a, st);
+    if (e != hipSuccess) {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+        return e;
+    }
+    e = f();
+    const hipError_t e2 = hipEventRecord(b, st);
     g_prof.pend.push_back({name, a, b});
-    return e;
+    return e != hipSuccess ? e : e2;
 }
 
 // "@h<height>" when launches are profiled per tree height, else ""
@@ -259,7 +265,8 @@ hipError_t prof_flush() {
         hipError_t e = hipEventSynchronize(r.b);
         if (e != hipSuccess) return e;
         float ms = 0.f;
-        hipEventElapsedTime(&ms, r.a, r.b);
+        e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) return e;
         auto &v = g_prof.acc[r.name];
         v.first += ms;
         v.second += 1;
@@ -269,12 +276,13 @@ hipError_t prof_flush() {
                 r.a = nullptr;
             }
             float t0 = 0.f, t1 = 0.f;
-            if (r.a) hipEventElapsedTime(&t0, g_prof.origin, r.a);
-            hipEventElapsedTime(&t1, g_prof.origin, r.b);
+            if (r.a) e = hipEventElapsedTime(&t0, g_prof.origin, r.a);
+            if (e == hipSuccess) e = hipEventElapsedTime(&t1, g_prof.origin, r.b);
+            if (e != hipSuccess) return e;
             g_prof.tl.push_back({r.name, {t0, t1}});
         }
-        if (r.a) hipEventDestroy(r.a);
-        hipEventDestroy(r.b);
+        if (r.a) (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
     }
     g_prof.pend.clear();
     return hipSuccess;
@@ -678,7 +686,7 @@ askit_status askit_profile_enable(int32_t on) {
     HIP_TRY(prof_flush());
     g_prof.acc.clear();
     g_prof.tl.clear();
-    if (g_prof.origin) hipEventDestroy(g_prof.origin);
+    if (g_prof.origin) (void)hipEventDestroy(g_prof.origin);
     g_prof.origin = nullptr;
     g_prof.on = on != 0;
     g_prof.heights = on == 2 || on == 3;
@@ -1457,8 +1465,8 @@ struct SideStream {
     hipStream_t s = nullptr;
     hipEvent_t e = nullptr;
     ~SideStream() {
-        if (e) hipEventDestroy(e);
-        if (s) hipStreamDestroy(s);
+        if (e) (void)hipEventDestroy(e);
+        if (s) (void)hipStreamDestroy(s);
     }
 };
 
@@ -2387,10 +2395,10 @@ struct askit_batch_s {
     hipGraph_t fgraph = nullptr, sgraph = nullptr;
     DBuf ptrs, gtasks;
     ~askit_batch_s() {
-        if (fexec) hipGraphExecDestroy(fexec);
-        if (sexec) hipGraphExecDestroy(sexec);
-        if (fgraph) hipGraphDestroy(fgraph);
-        if (sgraph) hipGraphDestroy(sgraph);
+        if (fexec) (void)hipGraphExecDestroy(fexec);
+        if (sexec) (void)hipGraphExecDestroy(sexec);
+        if (fgraph) (void)hipGraphDestroy(fgraph);
+        if (sgraph) (void)hipGraphDestroy(sgraph);
         for (auto f : fs) askit_factor_destroy(f);
     }
 };
@@ -2411,7 +2419,7 @@ static askit_status capture(const Plan &P, int ncol, hipGraph_t *g, hipGraphExec
     g_prof.on = prof;
     if (e == hipSuccess) e = e2;
     if (e == hipSuccess) e = hipGraphInstantiate(ex, *g, nullptr, nullptr, 0);
-    hipStreamDestroy(cs);
+    (void)hipStreamDestroy(cs);
     HIP_TRY(e);
     return ASKIT_OK;
 }
