@@ -27,18 +27,21 @@ static_assert(kLuFThreads >= kLuMaxN, "one thread per row of the largest matrix"
 // column (coalesced column-major access).  Logical row i of A is physical
 // row rowof(i).  U12 is staged in LDS, row-major: W[k * ldw + cj] for cj in
 // whole 64-column blocks covering nc (values past nc are never written
-// back).  Wave w takes the 16-row stripes w, w + NW, ...: it loads the
+// back).  With LOWER, column blocks entirely above the diagonal (global
+// column > global row) are skipped.  Wave w takes the 16-row stripes w, w + NW, ...: it loads the
 // stripe's L21 rows once, then goes over 64-column blocks, fetching the next
 // block's A22 values before the current block's products; a block's U12
 // operands are read from LDS (4 rows of k at a time) before their products.
 // ---------------------------------------------------------------------------
-template <int NW, int KP, class RowOf>
+template <int NW, int KP, bool LOWER = false, class RowOf>
 __device__ inline void trailing_update(GLB double *A, int lda, int kb, int r0, int nr, int c0, int nc,
                                        const double *W, int ldw, RowOf rowof, int wave, int lane) {
     static_assert(KP % 16 == 0, "depth in multiples of 16");
-    const int bt = (nr + 15) / 16, ncb = (nc + 63) / 64;
+    const int bt = (nr + 15) / 16, ncb_all = (nc + 63) / 64;
     const int row = lane % 16, kq = lane / 16;
     for (int st = wave; st < bt; st += NW) {
+        // LOWER: only the column blocks that reach the diagonal or below
+        const int ncb = LOWER ? min(ncb_all, (r0 - c0 + st * 16 + 15) / 64 + 1) : ncb_all;
         const int ci = st * 16 + row;
         const int64_t rb = ci < nr ? rowof(r0 + ci) : 0;
         // this stripe's L21 rows, kept for all its column blocks
@@ -339,6 +342,37 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu_nopiv(const LuTask *__restri
         const int j0 = kb + nb, nt = n - j0;
         if (nt <= 0) continue;  // only the last panel can be narrower than kPanel
         const int rr = lane % 16, kq = lane / 16;
+        // ---- U12 = L11^{-1} A12 with A12 = A21^T read from the lower part
+        // (the trailing matrix is symmetric; its upper part is not kept up
+        // to date), 16-column blocks, also staged in Up (zero-padded to ldw
+        // columns); before L21 overwrites A21
+        const int ldw = (nt + 63) & ~63;
+        for (int e = tid; e < kPanel * (ldw - nt); e += NT) Up[(e / (ldw - nt)) * ldw + nt + e % (ldw - nt)] = 0.0;
+#pragma unroll 1
+        for (int cbk = wave; cbk < (nt + 15) / 16; cbk += NW) {
+            const int c0 = cbk * 16;
+            dbl4 acc[2] = {dbl4{0, 0, 0, 0}, dbl4{0, 0, 0, 0}};
+            double b[kPanel / 4];
+#pragma unroll
+            for (int kk = 0; kk < kPanel / 4; kk++)
+                b[kk] = c0 + rr < nt ? A[j0 + c0 + rr + (int64_t)(kb + 4 * kk + kq) * lda] : 0.0;
+#pragma unroll
+            for (int kk = 0; kk < kPanel / 4; kk++)
+#pragma unroll
+                for (int rb = 0; rb < 2; rb++)
+                    acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(LI[(rb * 16 + rr) * DL + 4 * kk + kq], b[kk],
+                                                                   acc[rb], 0, 0, 0);
+#pragma unroll
+            for (int rb = 0; rb < 2; rb++)
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const int r = rb * 16 + 4 * q + kq, c = c0 + rr;
+                    if (c < nt) {
+                        A[kb + r + (int64_t)(j0 + c) * lda] = acc[rb][q];
+                        Up[r * ldw + c] = acc[rb][q];
+                    }
+                }
+        }
         // ---- L21 = A21 U11^{-1}, 16-row stripes
 #pragma unroll 1
         for (int st = wave; st < (nt + 15) / 16; st += NW) {
@@ -362,38 +396,10 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu_nopiv(const LuTask *__restri
                     if (r < nt) A[j0 + r + (int64_t)(kb + cb * 16 + rr) * lda] = acc[cb][q];
                 }
         }
-        // ---- U12 = L11^{-1} A12, 16-column blocks (also staged in Up,
-        // zero-padded to ldw columns)
-        const int ldw = (nt + 63) & ~63;
-        for (int e = tid; e < kPanel * (ldw - nt); e += NT) Up[(e / (ldw - nt)) * ldw + nt + e % (ldw - nt)] = 0.0;
-#pragma unroll 1
-        for (int cbk = wave; cbk < (nt + 15) / 16; cbk += NW) {
-            const int c0 = cbk * 16;
-            dbl4 acc[2] = {dbl4{0, 0, 0, 0}, dbl4{0, 0, 0, 0}};
-            double b[kPanel / 4];
-#pragma unroll
-            for (int kk = 0; kk < kPanel / 4; kk++)
-                b[kk] = c0 + rr < nt ? A[kb + 4 * kk + kq + (int64_t)(j0 + c0 + rr) * lda] : 0.0;
-#pragma unroll
-            for (int kk = 0; kk < kPanel / 4; kk++)
-#pragma unroll
-                for (int rb = 0; rb < 2; rb++)
-                    acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(LI[(rb * 16 + rr) * DL + 4 * kk + kq], b[kk],
-                                                                   acc[rb], 0, 0, 0);
-#pragma unroll
-            for (int rb = 0; rb < 2; rb++)
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const int r = rb * 16 + 4 * q + kq, c = c0 + rr;
-                    if (c < nt) {
-                        A[kb + r + (int64_t)(j0 + c) * lda] = acc[rb][q];
-                        Up[r * ldw + c] = acc[rb][q];
-                    }
-                }
-        }
         __syncthreads();
         // ---- trailing update A22 -= L21 U12
-        trailing_update<NW, kPanel>(A, lda, kb, j0, nt, j0, nt, Up, ldw, [](int i) -> int64_t { return i; }, wave, lane);
+        trailing_update<NW, kPanel, true>(A, lda, kb, j0, nt, j0, nt, Up, ldw, [](int i) -> int64_t { return i; }, wave,
+                                          lane);
         __syncthreads();
     }
     if (tid == 0 && t.ratio) *glb(t.ratio) = n ? (s_max > 0.0 ? s_min / s_max : 0.0) : 1.0;
