@@ -250,15 +250,17 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu(const LuTask *__restrict__ t
 // backward stable there and gives the factors GETRF gives whenever it
 // exchanges no rows.  Blocked by 32 columns: the diagonal block is factored
 // by one wave with its rows in registers (pivot rows shared by lane
-// shuffles); its triangles are inverted in LDS; L21 = A21 U11^{-1} and
-// U12 = L11^{-1} A12 are products on FP64 MFMA; the trailing update is the
-// one of k_lu.  piv[k] = k.
+// shuffles); U11 is inverted in registers; L21 = A21 U11^{-1} is a product on
+// FP64 MFMA and U12 = D L21^T (D = diag(U11)), as the factors of a symmetric
+// matrix without row exchanges satisfy U = D L^T.  The trailing matrix stays
+// symmetric, so only its blocks on or below the diagonal are updated (the
+// trailing update of k_lu restricted to them); each upper entry is written
+// once, as part of U12.  piv[k] = k.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kLuFThreads) void k_lu_nopiv(const LuTask *__restrict__ tasks) {
     constexpr int NT = kLuFThreads, NW = NT / kWave, DL = kPanel + 1;
     __shared__ double Up[kPanel * kLuMaxN];  // U block row (row-major, ld = nt rounded up to 64)
     __shared__ double Dg[kPanel * DL];       // factored diagonal block (row-major)
-    __shared__ double LI[kPanel * DL];       // L11^{-1} (row-major)
     __shared__ double UI[kPanel * DL];       // U11^{-1} (row-major)
     __shared__ double s_min, s_max;
     const LuTask t = tasks[blockIdx.x];
@@ -302,10 +304,9 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu_nopiv(const LuTask *__restri
             }
         }
         __syncthreads();
-        // ---- inverses of the triangles, one column per lane in registers:
-        // column j of U^{-1} by lane j of wave 1, of L^{-1} by lane j of
-        // wave 2 (terms with a zero factor included: they leave the sums
-        // unchanged); pivot magnitudes by wave 3
+        // ---- inverse of U11, one column per lane in registers: column j
+        // of U^{-1} by lane j of wave 1 (terms with a zero factor included:
+        // they leave the sums unchanged); pivot magnitudes by wave 3
         if (wave == 1 && lane < kPanel) {
             const int j = lane;
             double x[kPanel];
@@ -319,18 +320,6 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu_nopiv(const LuTask *__restri
             }
 #pragma unroll
             for (int i = 0; i < kPanel; i++) UI[i * DL + j] = x[i];
-        } else if (wave == 2 && lane < kPanel) {
-            const int j = lane;
-            double x[kPanel];
-#pragma unroll
-            for (int i = 0; i < kPanel; i++) {
-                double acc = i == j ? 1.0 : 0.0;
-#pragma unroll
-                for (int k = 0; k < i; k++) acc = fma(-Dg[i * DL + k], x[k], acc);
-                x[i] = i < j ? 0.0 : acc;
-            }
-#pragma unroll
-            for (int i = 0; i < kPanel; i++) LI[i * DL + j] = x[i];
         } else if (wave == 3 && lane == 0) {
             for (int i = 0; i < nb; i++) {
                 const double au = fabs(Dg[i * DL + i]);
@@ -342,38 +331,13 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu_nopiv(const LuTask *__restri
         const int j0 = kb + nb, nt = n - j0;
         if (nt <= 0) continue;  // only the last panel can be narrower than kPanel
         const int rr = lane % 16, kq = lane / 16;
-        // ---- U12 = L11^{-1} A12 with A12 = A21^T read from the lower part
-        // (the trailing matrix is symmetric; its upper part is not kept up
-        // to date), 16-column blocks, also staged in Up (zero-padded to ldw
-        // columns); before L21 overwrites A21
+        // ---- L21 = A21 U11^{-1}, 16-row stripes, and with it U12 = D L21^T
+        // (D = diag(U11)): without row exchanges the factors of a symmetric
+        // matrix satisfy U = D L^T, so the block row of U comes from L21 (the
+        // trailing matrix's upper part is not kept up to date).  U12 is also
+        // staged in Up (zero-padded to ldw columns).
         const int ldw = (nt + 63) & ~63;
         for (int e = tid; e < kPanel * (ldw - nt); e += NT) Up[(e / (ldw - nt)) * ldw + nt + e % (ldw - nt)] = 0.0;
-#pragma unroll 1
-        for (int cbk = wave; cbk < (nt + 15) / 16; cbk += NW) {
-            const int c0 = cbk * 16;
-            dbl4 acc[2] = {dbl4{0, 0, 0, 0}, dbl4{0, 0, 0, 0}};
-            double b[kPanel / 4];
-#pragma unroll
-            for (int kk = 0; kk < kPanel / 4; kk++)
-                b[kk] = c0 + rr < nt ? A[j0 + c0 + rr + (int64_t)(kb + 4 * kk + kq) * lda] : 0.0;
-#pragma unroll
-            for (int kk = 0; kk < kPanel / 4; kk++)
-#pragma unroll
-                for (int rb = 0; rb < 2; rb++)
-                    acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(LI[(rb * 16 + rr) * DL + 4 * kk + kq], b[kk],
-                                                                   acc[rb], 0, 0, 0);
-#pragma unroll
-            for (int rb = 0; rb < 2; rb++)
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const int r = rb * 16 + 4 * q + kq, c = c0 + rr;
-                    if (c < nt) {
-                        A[kb + r + (int64_t)(j0 + c) * lda] = acc[rb][q];
-                        Up[r * ldw + c] = acc[rb][q];
-                    }
-                }
-        }
-        // ---- L21 = A21 U11^{-1}, 16-row stripes
 #pragma unroll 1
         for (int st = wave; st < (nt + 15) / 16; st += NW) {
             const int i0 = st * 16;
@@ -389,12 +353,20 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu_nopiv(const LuTask *__restri
                     acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], UI[(4 * kk + kq) * DL + cb * 16 + rr],
                                                                    acc[cb], 0, 0, 0);
 #pragma unroll
-            for (int cb = 0; cb < 2; cb++)
+            for (int cb = 0; cb < 2; cb++) {
+                const int k = cb * 16 + rr;
+                const double dk = Dg[k * DL + k];
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
                     const int r = i0 + 4 * q + kq;
-                    if (r < nt) A[j0 + r + (int64_t)(kb + cb * 16 + rr) * lda] = acc[cb][q];
+                    if (r < nt) {
+                        A[j0 + r + (int64_t)(kb + k) * lda] = acc[cb][q];
+                        const double u = dk * acc[cb][q];
+                        A[kb + k + (int64_t)(j0 + r) * lda] = u;
+                        Up[k * ldw + r] = u;
+                    }
                 }
+            }
         }
         __syncthreads();
         // ---- trailing update A22 -= L21 U12
