@@ -141,9 +141,9 @@ ROOF_TABLE = [
 TRAFFIC = {
     "factor:k_lu_nopiv": {
         "source": ["k_lu.hip", "askit_dev.h"],
-        "src_sha256": "5f4bcaa35ef5ca90be67b09b781a7a2034a707d96be223f0d897f74a8afb9721",
+        "src_sha256": "a2724c02882fe4cea5ad9ac5050c8110e45c92b0bc5dfe2d184dae61d9d285d7",
         "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": 53925018875.768906,
+        "bytes_per_launch": 32473539893.51195,
     },
 }
 
