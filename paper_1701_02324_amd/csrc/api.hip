@@ -2098,27 +2098,6 @@ static askit_status matvec_impl(askit_factor f, int which, const double *Xin, in
     return ASKIT_OK;
 }
 
-// max over columns of |U_c| / |V_c| (two-norms)
-static askit_status colratio(askit_factor f, const double *U, int64_t ldu, const double *V, int64_t ldv, int nrhs,
-                             hipStream_t st, double *out) {
-    const int64_t N = f->t->N;
-    if (f->nrm.bytes < sizeof(double) * 2 * nrhs) ST_TRY(f->nrm.alloc(sizeof(double) * 2 * nrhs));
-    hipLaunchKernelGGL(k_zero, dim3(grid1(2 * nrhs)), dim3(256), 0, st, f->nrm.as<double>(), (int64_t)2 * nrhs);
-    int gx = (int)std::min<int64_t>(1024, cdiv(N, 256));
-    hipLaunchKernelGGL(k_colnorms, dim3(gx, nrhs), dim3(256), 0, st, U, ldu, V, ldv, N, nrhs, f->nrm.as<double>());
-    HIP_TRY(hipGetLastError());
-    std::vector<double> h(2 * nrhs);
-    HIP_TRY(hipMemcpyAsync(h.data(), f->nrm.p, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    double worst = 0.0;
-    for (int c = 0; c < nrhs; c++) {
-        double r = h[nrhs + c] > 0 ? std::sqrt(h[c] / h[nrhs + c]) : (h[c] > 0 ? INFINITY : 0.0);
-        worst = std::max(worst, r);
-    }
-    *out = worst;
-    return ASKIT_OK;
-}
-
 // ---------------------------------------------------------------------------
 // Refinement against the FP64 operator: restarted GMRES on (lambda I +
 // Ktilde) x = b, right-preconditioned with the stored factorization (GMRES-IR,

@@ -70,8 +70,6 @@ template <typename TS, typename TD> __global__ void k_copy(const CopyTask *tasks
 template <typename T> __global__ void k_axpy(T *Y, const T *X, int64_t ld, int64_t n, int nrhs, double a);
 __global__ void k_residual(const double *B, int64_t ldb, double *R, int64_t ldr, int64_t N, int nrhs);
 __global__ void k_update(double *X, int64_t ldx, const double *D, int64_t ldd, int64_t N, int nrhs);
-__global__ void k_colnorms(const double *U, int64_t ldu, const double *V, int64_t ldv, int64_t N, int nrhs,
-                           double *acc);
 __global__ void k_zero(double *p, int64_t n);
 __global__ void k_mdot_part(const double *V, const double *W, int64_t N, int nrhs, int64_t chunk, double *part);
 __global__ void k_mdot_finish(const double *part, int nchunk, int njc, double *out);

@@ -179,34 +179,6 @@ __global__ void k_update(double *__restrict__ X, int64_t ldx, const double *__re
     X[i + c * ldx] += D[i + c * ldd];
 }
 
-// per column: acc[c] += |u|^2, acc[nrhs + c] += |v|^2 (block partials, fixed order
-// per block, blocks combined with atomics: the values only steer the loop)
-__global__ void k_colnorms(const double *__restrict__ U, int64_t ldu, const double *__restrict__ V, int64_t ldv,
-                           int64_t N, int nrhs, double *__restrict__ acc) {
-    __shared__ double su[256], sv[256];
-    const int c = blockIdx.y;
-    double pu = 0.0, pv = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
-        double u = U[i + c * ldu], v = V[i + c * ldv];
-        pu = fma(u, u, pu);
-        pv = fma(v, v, pv);
-    }
-    su[threadIdx.x] = pu;
-    sv[threadIdx.x] = pv;
-    __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) {
-            su[threadIdx.x] += su[threadIdx.x + o];
-            sv[threadIdx.x] += sv[threadIdx.x + o];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        atomicAdd(acc + c, su[0]);
-        atomicAdd(acc + nrhs + c, sv[0]);
-    }
-}
-
 // --- batched Krylov helpers on column-major N x nrhs blocks (ld = N) ------
 // vectors V_j are stored back to back: V + j * N * nrhs
 

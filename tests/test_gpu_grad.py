@@ -37,7 +37,7 @@ def _loss_and_grads(ak, tree, B, Y, lam, h, refine=None):
     x = ak.kernel_solve(b, lt, ht, tree, refine=refine)
     loss = ((x - torch.as_tensor(Y, device="cuda")) ** 2).sum()
     loss.backward()
-    return float(loss), b.grad.cpu().numpy(), float(lt.grad), float(ht.grad)
+    return float(loss.detach()), b.grad.cpu().numpy(), float(lt.grad), float(ht.grad)
 
 
 def _loss_only(ak, tree, B, Y, lam, h, refine=None):
