@@ -223,7 +223,8 @@ void askit_batch_destroy(askit_batch b);
 /* Per-phase timings (ms) and sizes of the last calls on a handle, as JSON. */
 askit_status askit_get_stats(askit_tree t, askit_factor f, char *json, size_t cap);
 
-/* Per-kernel timing: with profiling on, every launch of the library is
+/* Per-kernel timing (process-wide state: meant for runs where one thread
+ * calls the library): with profiling on, every launch of the library is
  * bracketed by HIP events on its stream; askit_profile_report writes
  * {"phase:kernel": [total_ms, launches], ...} (it synchronizes on the pending
  * events).  Enabling resets the totals.  on = 2 keeps the totals per tree

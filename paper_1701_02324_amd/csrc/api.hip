@@ -161,8 +161,8 @@ struct DBuf {
 // an upload stream is set (UploadOnStream): then they are queued on that
 // stream from host copies kept until the guard ends, so they neither wait
 // for nor delay the kernels queued on other streams.
-hipStream_t g_upload_stream = nullptr;
-std::vector<std::vector<char>> g_upload_keep;
+thread_local hipStream_t g_upload_stream = nullptr;  // per calling thread: calls on other handles may overlap
+thread_local std::vector<std::vector<char>> g_upload_keep;
 
 static askit_status copy_up(void *dst, const void *src, size_t bytes) {
     if (g_upload_stream) {
