@@ -348,7 +348,9 @@ def main():
     # roofline of every reported kernel family; the dominant one (largest
     # total time in the timed steps) is the headline
     ranks, cands = tree.skeleton_sizes()
-    split = {0: tree.D - 1, -1: 0}.get(args.qr_split_levels, args.qr_split_levels)
+    # the library's default split levels in the pipelined call (the timed
+    # steps): those with fewer than 1024 nodes
+    split = {0: min(tree.D - 1, 9), -1: 0}.get(args.qr_split_levels, args.qr_split_levels)
     cnt = algorithmic_counts(N, d, m, s, tree.D, nsamp, args.nrhs, ranks, split)
     rank_levels = {}
     for lvl in range(1, tree.D + 1):

@@ -59,8 +59,10 @@ typedef struct askit_factor_s *askit_factor;
  * qr_split_levels chooses the launch shape of the pivoted QR, not its
  * result: nodes at tree levels 1 .. L are factored by several workgroups
  * each, one launch per pivot step, the deeper ones by one workgroup each
- * (0 -> L = D - 1, every internal level; -1 -> none).  Both shapes give
- * bit-identical skeletons. */
+ * (0 -> L = D - 1, every internal level, in askit_skeletonize and
+ * L = min(D - 1, 9), the levels with fewer than 1024 nodes, in
+ * askit_skeletonize_factorize; -1 -> none).  Both shapes give bit-identical
+ * skeletons. */
 typedef struct {
     int32_t leaf_size;
     int32_t rank;

@@ -624,6 +624,7 @@ struct askit_tree_s {
     DBuf srank, trunc, skel, Pt, samp;
     std::vector<int32_t> hsr;  // host copy of the ranks s_alpha (root: 0)
     int split_levels = 0;      // tree levels 1 .. split_levels use the split QRCP
+    bool split_default = true; // split_levels was left to the library
     bool skel_ok = false;
     int refs = 0;
     double t_tree = 0, t_skel = 0;
@@ -751,7 +752,10 @@ askit_status askit_build_tree(const double *X, int64_t N, int32_t d, const askit
     t->hfac = opt->h;
     while ((int64_t)t->m * ((int64_t)1 << t->D) < N) t->D++;
     t->nnodes = ((int64_t)2 << t->D) - 1;
+    // default: the split QR on every internal level (the pipelined call
+    // narrows it, see SkelRun::split_of)
     t->split_levels = opt->qr_split_levels == 0 ? t->D - 1 : std::max(0, opt->qr_split_levels);
+    t->split_default = opt->qr_split_levels == 0;
     t->mmax = (int)cdiv(N, (int64_t)1 << t->D);
     t->cmax = std::max(t->mmax, 2 * t->s);
     if (t->mmax > 512 || 2 * t->s > 512)
@@ -891,6 +895,16 @@ struct SkelRun {
     int nqr = 0, n1 = 0, nsp = 0, split_steps = 0;
     QrWork w{};
 
+    // In the pipelined call the skeletonization of a level overlaps the
+    // factorization below it; there a level with 2^kOneWgLevel nodes or more
+    // does better with one workgroup per node than with one launch per pivot
+    // step (measured at the 1M workload), so the library's default narrows to
+    // the levels with fewer nodes.  Both shapes give the same skeletons.
+    bool pipelined = false;
+    int split_of(askit_tree t) const {
+        return pipelined && t->split_default ? std::min(t->split_levels, kOneWgLevel - 1) : t->split_levels;
+    }
+
     askit_status begin(askit_tree *tr, int cnt, hipStream_t stream) {
         trees = tr;
         count = cnt;
@@ -967,7 +981,7 @@ struct SkelRun {
                 a.out = t->samp.as<int32_t>() + id * t->nsamp;
                 k.q = a.out;
                 k.nq = (int32_t)std::min<int64_t>(t->nsamp, t->N - (a.e - a.b));
-                if (l <= t->split_levels) {
+                if (l <= split_of(t)) {
                     samp_split.push_back(a);
                     qr_split.push_back(k);
                     split_cols = std::max(split_cols, ncand);
@@ -1486,6 +1500,7 @@ static askit_status skel_factor_impl(askit_tree t, double lambda, int precision,
                                      double &t_skel) {
     auto t0 = std::chrono::steady_clock::now();
     SkelRun R;
+    R.pipelined = true;
     ST_TRY(R.begin(&t, 1, st));
     std::unique_ptr<askit_factor_s> f;
     ST_TRY(factor_alloc(t, lambda, precision, f));

@@ -15,6 +15,7 @@ constexpr double kRankGuard = 1e-14;
 constexpr int kQsThreads = 256;  // threads per workgroup of the split QRCP
 constexpr int kQsCols = 8;       // columns per workgroup of the split QRCP (two per wave)
 constexpr int kQsState = 8;      // ints of per-node state of the split QRCP
+constexpr int kOneWgLevel = 10;  // pipelined call, by default: tree levels from here (>= 1024 nodes) use one workgroup per node
 constexpr int kLsThreads = 1024; // batched LU solves: 16 waves keep many block loads in flight
 constexpr int kLuFThreads = 512; // batched LU factorization
 constexpr int kXrDim = 16;       // kernel-block products keep row points in registers up to this dimension
