@@ -141,9 +141,15 @@ ROOF_TABLE = [
 TRAFFIC = {
     "factor:k_lu_nopiv": {
         "source": ["k_lu.hip", "askit_dev.h"],
-        "src_sha256": "a2724c02882fe4cea5ad9ac5050c8110e45c92b0bc5dfe2d184dae61d9d285d7",
+        "src_sha256": "f035a70ab213be21117889822efc73e7bacb56cd10b17924934bfb14fc40de8f",
         "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": 32473539893.51195,
+        "bytes_per_launch": 32438113222.372303,
+    },
+    "skel:k_qrcp": {
+        "source": ["k_skel.hip", "askit_dev.h"],
+        "src_sha256": "cb8a0a7156b2875e40639a698592faf35b9f7f0f35d6d9d42c9c18b027af95ef",
+        "workload": (1048576, 16, 512, 256, 1024),
+        "bytes_per_launch": 3895457711.466586,
     },
 }
 
