@@ -1076,7 +1076,8 @@ struct SkelRun {
                 hipLaunchKernelGGL(k_qs_init, dim3(g), dim3(kQsThreads), 0, st, tp, wk, s, nsamp_max);
                 for (int j = 0; j < split_steps; j++)
                     hipLaunchKernelGGL(k_qs_step, dim3(g), dim3(kQsThreads), 0, st, tp, wk, j, nsamp_max);
-                hipLaunchKernelGGL(k_qs_finish, dim3(nsp), dim3(512), 0, st, tp, wk, s, nsamp_max);
+                hipLaunchKernelGGL(k_qs_finish, dim3(nsp, (unsigned)cdiv(wk.slices * kQsCols, kQsFinishCols)), dim3(512), 0,
+                                   st, tp, wk, s, nsamp_max);
                 return hipGetLastError();
             }));
         }

@@ -14,6 +14,7 @@ constexpr int kPowerIters = 50;  // power iterations for the principal axis
 constexpr double kRankGuard = 1e-14;
 constexpr int kQsThreads = 256;  // threads per workgroup of the split QRCP
 constexpr int kQsCols = 8;       // columns per workgroup of the split QRCP (two per wave)
+constexpr int kQsFinishCols = 64;  // columns of T = R11^-1 R12 per workgroup of the split QRCP's last kernel
 constexpr int kQsState = 8;      // ints of per-node state of the split QRCP
 constexpr int kOneWgLevel = 10;  // pipelined call, by default: tree levels from here (>= 1024 nodes) use one workgroup per node
 constexpr int kLsThreads = 1024; // batched LU solves: 16 waves keep many block loads in flight

@@ -478,22 +478,26 @@ __device__ inline void apply_all(PM M, int ldm, PP pos, int j, int ncand, const 
         apply_group<NT, NC>(M, ldm, pos, q0, kQrWaves, ncand, vh, j, rows, tau, lane, nrm);
 }
 
-// T = R11^{-1} R12 in place of R12 and the outputs (skeleton positions, rank,
-// rows of P_{C alpha~}); pos[q] = column at pivot position q, Rjj = diagonal
-// of R.  All kQrThreads threads.  Back substitution by columns: each wave
-// takes groups of kTq right-hand columns, lane l holding their rows
-// l + 64 u in registers; from the last row up, t_i = r_i / R_ii is taken
-// from its lane and column i of R11 (rows 0 .. i-1 of column pos[i],
-// contiguous, loaded one step ahead) updates the rows above.
+// T = R11^{-1} R12 and the rows of P_{C alpha~} that it fills, for the
+// column groups g0, g0 + gstep, ... of kTq right-hand columns (positions
+// rank + g ..); pos[q] = column at pivot position q, Rjj = diagonal of R.
+// One wave per group: lane l holds the group's rows l + 64 u in registers;
+// from the last row up, t_i = r_i / R_ii is taken from its lane and column i
+// of R11 (rows 0 .. i-1 of column pos[i], contiguous, loaded one step ahead)
+// updates the rows above.  The solved column is stored straight into its row
+// of P (lanes along the row).
 constexpr int kTq = 8;
 constexpr int kTu = kQrMaxRank / kWave;
+static_assert(kQrWaves * kTq == kQsFinishCols, "k_qs_finish column split");
+__device__ inline int p_row(const SkelTask &t, int c, int s, int sl) {
+    return t.leaf ? c : (c < sl ? c : s + (c - sl));
+}
 template <typename PM, typename PP, typename PR>
-__device__ inline void id_finish(const SkelTask &t, PM M, int ldm, int s, int sl, int ncand, int rank, bool zero,
-                                 PP pos, PR Rjj) {
-    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
-    auto prow = [&](int c) { return t.leaf ? c : (c < sl ? c : s + (c - sl)); };
+__device__ inline void id_solve_rows(const SkelTask &t, PM M, int ldm, int s, int sl, int ncand, int rank, bool zero,
+                                     PP pos, PR Rjj, int g0, int gstep) {
+    const int lane = threadIdx.x % kWave;
     const int nr = ncand - rank;
-    for (int g = wave * kTq; g < nr; g += kQrWaves * kTq) {
+    for (int g = g0; g < nr; g += gstep) {
         double r[kTq][kTu];
         int cq[kTq];
 #pragma unroll
@@ -542,32 +546,34 @@ __device__ inline void id_finish(const SkelTask &t, PM M, int ldm, int s, int sl
                 }
             }
         }
+        // P is written in the rows of the candidates and the columns below
+        // the rank only: nothing reads the rest of the padded slot
 #pragma unroll
         for (int u = 0; u < kTq; u++) {
             if (cq[u] < 0) break;
+            GLB double *row = glb(t.Pt) + (int64_t)p_row(t, cq[u], s, sl) * s;
 #pragma unroll
             for (int v = 0; v < kTu; v++) {
                 const int k = lane + v * kWave;
-                if (k < rank) M[(int64_t)cq[u] * ldm + k] = r[u][v];
+                if (k < rank) row[k] = r[u][v];
             }
         }
     }
-    __syncthreads();
+}
+
+// the skeleton positions, rank, truncation flag and the identity rows of P
+// (one wave per row).  All kQrThreads threads.
+template <typename PP>
+__device__ inline void id_outputs(const SkelTask &t, int s, int sl, int ncand, int rank, PP pos) {
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
     for (int k = tid; k < s; k += kQrThreads) glb(t.skel)[k] = k < rank ? cand_pos(t, pos[k], sl) : -1;
     if (tid == 0) {
         *glb(t.sr) = rank;
         *glb(t.trunc) = (rank < (s < ncand ? s : ncand)) ? 1 : 0;
     }
-    // P is written in the rows of the candidates and the columns below the
-    // rank only: nothing reads the rest of the padded slot
-    for (int q = tid; q < ncand; q += kQrThreads) {
-        GLB double *row = glb(t.Pt) + (int64_t)prow(pos[q]) * s;
-        if (q < rank) {
-            for (int k = 0; k < rank; k++) row[k] = k == q ? 1.0 : 0.0;
-        } else {
-            const auto tc = M + (int64_t)pos[q] * ldm;
-            for (int k = 0; k < rank; k++) row[k] = tc[k];
-        }
+    for (int q = wave; q < rank; q += kQrWaves) {
+        GLB double *row = glb(t.Pt) + (int64_t)p_row(t, pos[q], s, sl) * s;
+        for (int k = lane; k < rank; k += kWave) row[k] = k == q ? 1.0 : 0.0;
     }
 }
 
@@ -809,7 +815,8 @@ __global__ __launch_bounds__(kQrThreads) __attribute__((amdgpu_waves_per_eu(4)))
             }
         __syncthreads();
     }
-    id_finish(t, M, ldm, s, sl, ncand, s_rank, s_zero != 0, pos, Rjj);
+    id_solve_rows(t, M, ldm, s, sl, ncand, s_rank, s_zero != 0, pos, Rjj, wave * kTq, kQrWaves * kTq);
+    id_outputs(t, s, sl, ncand, s_rank, pos);
 }
 
 // ---------------------------------------------------------------------------
@@ -972,10 +979,12 @@ __global__ __launch_bounds__(kQsThreads) void k_qs_step(const SkelTask *__restri
     }
 }
 
-// T = R11^{-1} R12 and the outputs
+// T = R11^{-1} R12 and the outputs; blockIdx.y takes the column groups
+// y, y + gridDim.y, ... of kQsFinishCols columns each, workgroup 0 of a node
+// also writes the per-node outputs
 __global__ __launch_bounds__(kQrThreads) void k_qs_finish(const SkelTask *__restrict__ tasks, QrWork w, int s,
                                                            int ldm) {
-    const int node = blockIdx.x;
+    const int node = blockIdx.x, wave = threadIdx.x / kWave;
     const SkelTask t = tasks[node];
     const GLB int32_t *st = glb(w.st) + kQsState * node;
     const int sl = t.leaf ? 0 : *glb(t.srl), ncand = node_ncand(t);
@@ -984,7 +993,9 @@ __global__ __launch_bounds__(kQrThreads) void k_qs_finish(const SkelTask *__rest
     const int done = stopped ? jstop : steps;
     const int rank = stopped ? (jstop == 0 ? 1 : jstop) : steps;
     const GLB int32_t *pos = glb(w.pos) + (int64_t)node * 2 * w.cmax + (int64_t)(done & 1) * w.cmax;
-    id_finish(t, glb(t.M), ldm, s, sl, ncand, rank, zero, pos, glb(w.diag) + (int64_t)node * w.cmax);
+    id_solve_rows(t, glb(t.M), ldm, s, sl, ncand, rank, zero, pos, glb(w.diag) + (int64_t)node * w.cmax,
+                  (int)(blockIdx.y * kQrWaves + wave) * kTq, (int)gridDim.y * kQsFinishCols);
+    if (blockIdx.y == 0) id_outputs(t, s, sl, ncand, rank, pos);
 }
 
 }  // namespace askit
