@@ -141,15 +141,15 @@ ROOF_TABLE = [
 TRAFFIC = {
     "factor:k_lu_nopiv": {
         "source": ["k_lu.hip", "askit_dev.h"],
-        "src_sha256": "f035a70ab213be21117889822efc73e7bacb56cd10b17924934bfb14fc40de8f",
+        "src_sha256": "5b2819c17ec7374da3c112dc76273c139a7c74eda652d6d610105d445e3491d1",
         "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": 32438113222.372303,
+        "bytes_per_launch": 32444892314.45556,
     },
     "skel:k_qrcp": {
         "source": ["k_skel.hip", "askit_dev.h"],
-        "src_sha256": "cb8a0a7156b2875e40639a698592faf35b9f7f0f35d6d9d42c9c18b027af95ef",
+        "src_sha256": "ae68a230ac29fd16ece83bac547a85b59b1d3a662c6d526ee8770fb36885aac6",
         "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": 3895457711.466586,
+        "bytes_per_launch": 3816749862.353338,
     },
 }
 
