@@ -21,13 +21,17 @@
 namespace askit {
 
 // ---------------------------------------------------------------------------
-// sampling: one wave per node; lane 0 runs the sequential rejection loop with
-// an open-addressing set in LDS
+// sampling: one wave per node.  Draw i (i = 1, 2, ..) of the node's stream is
+// the SplitMix64 output of state + i * gamma, so the 64 lanes take 64
+// consecutive draws per round.  A draw is kept when its point was drawn
+// neither in an earlier round (open-addressing set in LDS) nor by a lower
+// lane of this round; kept draws go out in draw order until nsamp are held.
 // ---------------------------------------------------------------------------
 constexpr int kSampHashBits = 13;  // 8192 slots: nsamp <= 4096
+constexpr uint64_t kSplitMixGamma = 0x9E3779B97F4A7C15ULL;
 
-__device__ inline uint64_t splitmix_next(uint64_t &st) {
-    uint64_t z = (st += 0x9E3779B97F4A7C15ULL);
+__device__ inline uint64_t splitmix_at(uint64_t state, uint64_t i) {
+    uint64_t z = state + i * kSplitMixGamma;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
     return z ^ (z >> 31);
@@ -35,42 +39,56 @@ __device__ inline uint64_t splitmix_next(uint64_t &st) {
 
 __global__ __launch_bounds__(64) void k_sample(const SampTask *__restrict__ tasks, int nsamp, int32_t *__restrict__ err) {
     __shared__ int32_t table[1 << kSampHashBits];
+    constexpr uint32_t mask = (1u << kSampHashBits) - 1u;
     const SampTask t = tasks[blockIdx.x];
     const int64_t n = t.e - t.b, c = t.N - n;
+    const int lane = threadIdx.x;
     if (c <= nsamp) {
-        for (int64_t i = threadIdx.x; i < c; i += kWave) t.out[i] = (int32_t)(i < t.b ? i : i + n);
+        for (int64_t i = lane; i < c; i += kWave) t.out[i] = (int32_t)(i < t.b ? i : i + n);
         return;
     }
-    for (int i = threadIdx.x; i < (1 << kSampHashBits); i += kWave) table[i] = 0;
+    for (int i = lane; i < (1 << kSampHashBits); i += kWave) table[i] = 0;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t st = t.state;
-        const uint64_t cap = 64ULL * (uint64_t)(c + nsamp);
-        int k = 0;
-        uint64_t draws = 0;
-        while (k < nsamp) {
-            if (++draws > cap) {
-                atomicOr(err, 1);
-                break;
-            }
-            uint64_t r = __umul64hi(splitmix_next(st), (uint64_t)c);
-            int64_t pos = (int64_t)r < t.b ? (int64_t)r : (int64_t)r + n;
-            uint32_t key = (uint32_t)pos + 1u;
-            uint32_t slot = (uint32_t)(((uint64_t)pos * 0x9E3779B97F4A7C15ULL) >> (64 - kSampHashBits));
-            bool dup = false;
-            while (true) {
-                int32_t v = table[slot];
-                if (v == 0) {
-                    table[slot] = (int32_t)key;
-                    break;
-                }
+    // at most cap draws (a stream that cannot fill the sample is an error)
+    const uint64_t cap = 64ULL * (uint64_t)(c + nsamp);
+    int k = 0;
+    for (uint64_t base = 0; k < nsamp; base += kWave) {
+        const uint64_t i = base + (uint64_t)lane + 1;
+        const bool valid = i <= cap;
+        const uint64_t r = __umul64hi(splitmix_at(t.state, i), (uint64_t)c);
+        const int64_t pos = (int64_t)r < t.b ? (int64_t)r : (int64_t)r + n;
+        const uint32_t key = (uint32_t)pos + 1u;
+        const uint32_t slot = (uint32_t)(((uint64_t)pos * kSplitMixGamma) >> (64 - kSampHashBits));
+        bool fresh = valid;
+        if (valid) {
+            for (uint32_t sl = slot;; sl = (sl + 1) & mask) {
+                const int32_t v = table[sl];
+                if (v == 0) break;
                 if ((uint32_t)v == key) {
-                    dup = true;
+                    fresh = false;
                     break;
                 }
-                slot = (slot + 1) & ((1u << kSampHashBits) - 1);
             }
-            if (!dup) t.out[k++] = (int32_t)pos;
+        }
+        for (int u = 0; u < kWave - 1; u++) {
+            const uint32_t ku = (uint32_t)__builtin_amdgcn_readlane((int)key, u);
+            if (u < lane && ku == key) fresh = false;
+        }
+        const unsigned long long bal = __ballot(fresh);
+        const int before = __popcll(bal & ((1ull << lane) - 1ull));
+        const int need = nsamp - k;
+        if (fresh && before < need) {
+            t.out[k + before] = (int32_t)pos;
+            // the keys of a round are distinct and absent from the set
+            for (uint32_t sl = slot;; sl = (sl + 1) & mask)
+                if (atomicCAS(&table[sl], 0, (int32_t)key) == 0) break;
+        }
+        __syncthreads();
+        const int got = __popcll(bal);
+        k += got < need ? got : need;
+        if (k < nsamp && base + kWave >= cap) {
+            if (lane == 0) atomicOr(err, 1);
+            break;
         }
     }
 }
