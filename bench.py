@@ -147,9 +147,9 @@ TRAFFIC = {
     },
     "skel:k_qrcp": {
         "source": ["k_skel.hip", "askit_dev.h"],
-        "src_sha256": "ae68a230ac29fd16ece83bac547a85b59b1d3a662c6d526ee8770fb36885aac6",
+        "src_sha256": "88879bf3a579a06c7f1a8c9956337b093968cc75e018ff72d89e06d08f387dfd",
         "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": 3816749862.353338,
+        "bytes_per_launch": 3819166883.375679,
     },
 }
 
