@@ -6,17 +6,23 @@ Gaussian mixture in place of its datasets): N = 1,048,576 points in 16-D, 32
 clusters with centres ~ U[-10,10]^16 and sigma ~ U[0.5,2]; h = 2, lambda = 0.01,
 64 right-hand sides ~ N(0,1).
 
-One step = skeletonize (sampled ID, FP64 QRCP) + factorize (mixed precision:
-FP32 kernel blocks and level products, FP64 LUs), as the one pipelined call
-askit_skeletonize_factorize, + solve of the 64 right-hand sides with iterative
-refinement against the FP64 operator.  Inputs are resident in HBM before the
-timed region; the tree is built once, outside it.
+One step = skeletonize (sampled ID, FP64 pivoted QR) + factorize (FP64), as
+the one pipelined call askit_skeletonize_factorize, + the direct solve of the
+64 right-hand sides.  Inputs are resident in HBM before the timed region; the
+tree is built once, outside it.
 
-Printed: one JSON line.  value = factor time (skeletonize + factorize) of the
-mixed path in seconds; the same step through the two separate calls, solves/s,
-the plain FP64 path (timed once after the steps), the mixed-vs-FP64 relative
-error, the roofline of the dominant kernel (per-kernel HIP-event timings) and
-the oracle CPU baseline are included.
+value = the factor time (skeletonize + factorize) of the FP64 path in seconds,
+the paper's precision.  The mixed path (FP32 kernel blocks and level products,
+FP64 LUs) is timed the same way and reported beside it with its accuracy gate
+(relative error to the refined FP64 solution <= 1e-6 with converged
+refinement); it is the headline only if that gate holds.
+
+The timed steps run without per-launch events.  Per-kernel times come from a
+separate pass of the same steps with HIP events around every launch
+(askit_profile_enable), and give the rooflines.  The oracle (plain C, OpenMP)
+is the CPU baseline: by default on a bounded sample of the workload, with
+--cpu-full on the whole workload, where it also checks the GPU's tree,
+skeletons and FP64 solution.
 """
 from __future__ import annotations
 
@@ -34,6 +40,7 @@ sys.path.insert(0, ROOT)
 METRIC = "N=1M d=16 s=256: factor time (s), solves/s; mixed vs FP64 at rel err≤1e-6"
 HBM_PEAK_GBS = 8000.0
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+MIXED_GATE = 1e-6
 
 
 def log(*a):
@@ -50,108 +57,107 @@ def node_sizes(N, D):
     return n
 
 
-def algorithmic_counts(N, d, m, s, D, nsamp, nrhs, ranks=None, split_levels=6):
-    """Algorithmic flops and bytes of each kernel family in one step, from the
-    tree's actual skeleton ranks s_a (ranks[i] for heap node i; full rank s
-    when None).  These are the counts the method needs, not what the kernels
+def algorithmic_counts(N, d, m, s, D, nsamp, nrhs, ranks, qrows, split_levels, fp64=True):
+    """Algorithmic flops and bytes of each kernel of one step, from the tree's
+    actual skeleton ranks s_a (ranks[i] for heap node i) and the rows each
+    node's pivoted QR factored (qrows[i], numerically zero sampled rows
+    dropped).  These are the counts the method needs, not what the kernels
     execute:
-      skel:k_qrcp         pivot step j of an r x c sampled block: 6 (r-j)(c-j-1)
-                          flops (reflector dot 2 + axpy 2 + column norm 2 per
-                          trailing element), s_a steps, then T = R11^-1 R12:
-                          s_a^2 (c - s_a); nothing when c <= s (P = I).
-                          Nodes at tree levels <= split_levels count for the
-                          split form (skel:k_qrcp_split), the rest for k_qrcp
-      skel:k_sample_block 3d + 1 flops per sampled kernel entry (difference,
-                          fma, exp counted as one), nodes with c > s only, at
-                          the split levels; skel:k_sample_rownorm the same at
-                          the other levels (it forms the entries and their
-                          row sums, k_qrcp regenerates the kept rows)
-      factor:k_lu_nopiv   (2/3) m^3 per leaf LU (no row exchanges)
-      factor:k_lu         (2/3) n^3 per Z LU (n = s_l + s_r, partial pivoting)
-      factor:k_lusolve    2 n^2 s_a (leaf Phat, internal Z^-1 P_c below the root)
-      factor:k_kmm        2 s_l n_r s_r + 2 s_r n_l s_l per internal node (eq. (8))
-      factor:k_gmm        2 (n_l s_l + n_r s_r) s_a per internal non-root node
-                          (telescoping, eq. (10))
-      solve:k_lusolve     LU factors read once (8 n^2 bytes) + right-hand sides
-                          read and written (16 n nrhs bytes) per node
-      solve:k_kmm         2 (s_l n_r + s_r n_l) nrhs per internal node
+      skel:k_qrcp          nodes at levels > split_levels with c > s candidate
+                           columns and r factored rows: pivot step j costs
+                           6 (r-j)(c-j-1) (reflector dot 2, update 2, column
+                           norm 2 per trailing element), s_a steps; then
+                           T = R11^-1 R12: s_a^2 (c - s_a); plus (3d+1) r c
+                           for the kept rows it generates
+      skel:k_qs_step       the pivot steps of the nodes at levels 1..split_levels
+      skel:k_qs_finish     their s_a^2 (c - s_a)
+      skel:k_sample_rownorm (3d+1) flops per sampled kernel entry (difference,
+                           fma, exp counted as one), nsamp' x c per node, one-
+                           workgroup levels; skel:k_sample_block the same at
+                           the split levels
+      factor:k_lu_nopiv    (2/3) n^3 per leaf LU
+      factor:k_lu          (2/3) n^3 per Z LU (n = s_l + s_r)
+      factor:k_lusolve     2 n^2 s_a (leaf Phat, internal Z^-1 P_c)
+      factor:k_kmm         2 s_l n_r s_r + 2 s_r n_l s_l per internal node (eq. (8))
+      factor:k_gmm         2 (n_l s_l + n_r s_r) s_a per internal non-root node
+                           (telescoping, eq. (10))
+      solve:k_lusolve      LU factors read once (8 n^2 bytes) + right-hand
+                           sides read and written (2 w n nrhs bytes, w = 8 in
+                           FP64) per node
+      solve:k_kmm          2 (s_l n_r + s_r n_l) nrhs per internal node
+      solve:k_gmm          2 (n_l s_l + n_r s_r) nrhs per internal node
     """
     nn = (2 << D) - 1
     sz = node_sizes(N, D)
-    r = np.full(nn, s, dtype=np.int64) if ranks is None else np.asarray(ranks, dtype=np.int64)
+    r = np.asarray(ranks, dtype=np.int64)
+    qr = np.asarray(qrows, dtype=np.int64)
     first_leaf = (1 << D) - 1
-    c = {k: 0.0 for k in ("qr", "qr1", "qrs", "samp", "samp1", "samps", "lu", "lu_leaf", "lu_z", "fsolve", "zblk",
-                          "tele", "sbytes", "sflops", "skmm")}
+    keys = ("skel:k_qrcp", "skel:k_qs_step", "skel:k_qs_finish", "skel:k_sample_rownorm",
+            "skel:k_sample_block", "factor:k_lu_nopiv", "factor:k_lu", "factor:k_lusolve", "factor:k_kmm",
+            "factor:k_gmm", "solve:k_lusolve", "solve:k_kmm", "solve:k_gmm")
+    c = {k: 0.0 for k in keys}
+    w = 8.0 if fp64 else 4.0
     for i in range(nn):
         n = float(sz[i])
         leaf = i >= first_leaf
+        lvl = int(np.log2(i + 1))
         if i > 0:
             cols = n if leaf else float(r[2 * i + 1] + r[2 * i + 2])
             if cols > s:
-                rows = float(min(nsamp, N - n))
+                rows_s = float(min(nsamp, N - n))
+                rows = float(qr[i])
                 k = int(r[i])
-                w = sum(6.0 * (rows - j) * (cols - j - 1) for j in range(k)) + k * k * (cols - k)
-                c["qr"] += w
-                split_node = int(np.log2(i + 1)) <= split_levels
-                c["qrs" if split_node else "qr1"] += w
-                c["samp"] += rows * cols * (3.0 * d + 1)
-                c["samps" if split_node else "samp1"] += rows * cols * (3.0 * d + 1)
+                steps = sum(6.0 * (rows - j) * (cols - j - 1) for j in range(k))
+                tsolve = k * k * (cols - k)
+                samp = rows_s * cols * (3.0 * d + 1)
+                if lvl <= split_levels:
+                    c["skel:k_qs_step"] += steps
+                    c["skel:k_qs_finish"] += tsolve
+                    c["skel:k_sample_block"] += samp
+                else:
+                    c["skel:k_qrcp"] += steps + tsolve + rows * cols * (3.0 * d + 1)
+                    c["skel:k_sample_rownorm"] += samp
         nlu = n if leaf else float(r[2 * i + 1] + r[2 * i + 2])
-        c["lu"] += (2.0 / 3.0) * nlu ** 3
-        c["lu_leaf" if leaf else "lu_z"] += (2.0 / 3.0) * nlu ** 3
+        c["factor:k_lu_nopiv" if leaf else "factor:k_lu"] += (2.0 / 3.0) * nlu ** 3
         if i > 0:
-            c["fsolve"] += 2.0 * nlu * nlu * r[i]
-        c["sflops"] += 2.0 * nlu * nlu * nrhs
-        c["sbytes"] += 8.0 * nlu * nlu + 16.0 * nlu * nrhs
+            c["factor:k_lusolve"] += 2.0 * nlu * nlu * r[i]
+        c["solve:k_lusolve"] += 8.0 * nlu * nlu + 2.0 * w * nlu * nrhs
         if not leaf:
             l, rr = 2 * i + 1, 2 * i + 2
             sl, sr, nl, nr = float(r[l]), float(r[rr]), float(sz[l]), float(sz[rr])
-            c["zblk"] += 2.0 * sl * nr * sr + 2.0 * sr * nl * sl
-            c["skmm"] += 2.0 * (sl * nr + sr * nl) * nrhs
+            c["factor:k_kmm"] += 2.0 * sl * nr * sr + 2.0 * sr * nl * sl
+            c["solve:k_kmm"] += 2.0 * (sl * nr + sr * nl) * nrhs
+            c["solve:k_gmm"] += 2.0 * (nl * sl + nr * sr) * nrhs
             if i > 0:
-                c["tele"] += 2.0 * (nl * sl + nr * sr) * r[i]
+                c["factor:k_gmm"] += 2.0 * (nl * sl + nr * sr) * r[i]
     return c
 
 
-# Kernel families reported against their roofline: (profile key, count key,
-# bound, peak key, unit).  FP64 vector and FP64 MFMA share one peak on MI355X;
-# the mixed path's products run FP32 MFMA.
-ROOF_TABLE = [
-    # (profile key, count key, bound, peak, unit, launches of one pass: a
-    # function of the depth, or None when the count varies with the ranks --
-    # then the measured launches of the timed steps are used)
-    ("skel:k_qrcp", "qr1", "alu", "fp64", "TFLOP/s", None),
-    ("skel:k_qrcp_split", "qrs", "alu", "fp64", "TFLOP/s", None),
-    ("skel:k_sample_rownorm", "samp1", "alu", "fp64", "TFLOP/s", None),
-    ("skel:k_sample_block", "samps", "alu", "fp64", "TFLOP/s", None),
-    ("factor:k_lu_nopiv", "lu_leaf", "mfma", "fp64", "TFLOP/s", lambda D: 1),
-    ("factor:k_lu", "lu_z", "alu", "fp64", "TFLOP/s", lambda D: D),
-    ("factor:k_lusolve", "fsolve", "mfma", "fp64", "TFLOP/s", lambda D: D),
-    ("factor:k_kmm", "zblk", "mfma", "fp32", "TFLOP/s", None),
-    ("factor:k_gmm", "tele", "mfma", "fp32", "TFLOP/s", None),
-    ("solve:k_lusolve", "sbytes", "hbm", None, "GB/s", lambda D: D + 1),
-    ("solve:k_kmm", "skmm", "mfma", "fp32", "TFLOP/s", lambda D: D),
-]
+# Kernels reported against their roofline: key -> (bound, peak key, unit).
+# FP64 vector and FP64 MFMA share one peak on MI355X (78.6 TFLOP/s); the
+# products of the mixed path would run FP32 MFMA, the timed FP64 path does not.
+ROOF_KIND = {
+    "skel:k_qrcp": ("alu", "fp64", "TFLOP/s"),
+    "skel:k_qs_step": ("alu", "fp64", "TFLOP/s"),
+    "skel:k_qs_finish": ("alu", "fp64", "TFLOP/s"),
+    "skel:k_sample_rownorm": ("alu", "fp64", "TFLOP/s"),
+    "skel:k_sample_block": ("alu", "fp64", "TFLOP/s"),
+    "factor:k_lu_nopiv": ("mfma", "fp64", "TFLOP/s"),
+    "factor:k_lu": ("mfma", "fp64", "TFLOP/s"),
+    "factor:k_lusolve": ("mfma", "fp64", "TFLOP/s"),
+    "factor:k_kmm": ("mfma", "fp64", "TFLOP/s"),
+    "factor:k_gmm": ("mfma", "fp64", "TFLOP/s"),
+    "solve:k_lusolve": ("hbm", None, "GB/s"),
+    "solve:k_kmm": ("mfma", "fp64", "TFLOP/s"),
+    "solve:k_gmm": ("mfma", "fp64", "TFLOP/s"),
+}
 
 # HBM bytes per launch of single kernels, from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE (KiB per dispatch, averaged over the launches of one step),
 # scaled by what the same counters read for a plain 1 GiB read + 1 GiB write
 # (torch.neg).  Valid only for the kernel source they were taken on (sha256 of
 # its files) and for this workload; otherwise "traffic" is null.
-TRAFFIC = {
-    "factor:k_lu_nopiv": {
-        "source": ["k_lu.hip", "askit_dev.h"],
-        "src_sha256": "5b2819c17ec7374da3c112dc76273c139a7c74eda652d6d610105d445e3491d1",
-        "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": 32444892314.45556,
-    },
-    "skel:k_qrcp": {
-        "source": ["k_skel.hip", "askit_dev.h"],
-        "src_sha256": "88879bf3a579a06c7f1a8c9956337b093968cc75e018ff72d89e06d08f387dfd",
-        "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": 3819166883.375679,
-    },
-}
+TRAFFIC = {}
 
 
 def kernel_source_sha(names):
@@ -164,24 +170,25 @@ def kernel_source_sha(names):
     return h.hexdigest()
 
 
-def roofline_of(key, cnt_key, bound, peak_key, unit, nlaunch, prof, cnt, D, steps):
-    """Algorithmic work of one pass of the kernel family divided over the
-    launches one pass makes (one per tree level); the solve plan runs once per
-    operator application, so the measured launch count may be a multiple."""
-    if key not in prof:
-        return None
-    ms, launches = prof[key]
-    per_launch_ms = ms / launches
-    work_per_launch = cnt[cnt_key] / (nlaunch(D) if nlaunch else launches / steps)
-    if unit == "GB/s":
-        achieved = work_per_launch / (per_launch_ms * 1e-3) / 1e9
-        peak = HBM_PEAK_GBS
-    else:
-        achieved = work_per_launch / (per_launch_ms * 1e-3) / 1e12
-        peak = PEAK_TFLOPS[peak_key]
-    return dict(kernel=key, bound=bound, achieved=achieved, peak=peak, unit=unit, frac=achieved / peak,
-                traffic=None, avg_launch_ms=per_launch_ms, launches=launches,
-                work_per_launch=work_per_launch)
+def rooflines_of(prof, cnt, steps):
+    """Per kernel: algorithmic work of one step over its launches in one step,
+    divided by its average launch duration (HIP events on its stream)."""
+    out = {}
+    for key, (bound, pk, unit) in ROOF_KIND.items():
+        if key not in prof or cnt.get(key, 0.0) <= 0.0:
+            continue
+        ms, launches = prof[key]
+        per_step = launches / steps
+        per_launch_ms = ms / launches
+        work = cnt[key] / per_step
+        if unit == "GB/s":
+            achieved, peak = work / (per_launch_ms * 1e-3) / 1e9, HBM_PEAK_GBS
+        else:
+            achieved, peak = work / (per_launch_ms * 1e-3) / 1e12, PEAK_TFLOPS[pk]
+        out[key] = dict(kernel=key, bound=bound, achieved=achieved, peak=peak, unit=unit, frac=achieved / peak,
+                        traffic=None, avg_launch_ms=per_launch_ms, launches_per_step=per_step,
+                        work_per_launch=work, step_ms=ms / steps)
+    return out
 
 
 def main():
@@ -191,10 +198,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--N", type=int, default=1 << 20)
     ap.add_argument("--nrhs", type=int, default=64)
-    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision steps")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-sample", type=int, default=262144, help="points in the oracle's sample problem")
-    ap.add_argument("--max-refine", type=int, default=10, help="GMRES-IR operator applications (mixed path)")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="run the oracle on the whole workload (several minutes on 16 cores) and check the GPU's "
+                         "tree, skeletons and FP64 solution against it")
+    ap.add_argument("--cpu-sample", type=int, default=262144,
+                    help="points of the oracle's bounded sample (without --cpu-full)")
+    ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel profiled pass")
+    ap.add_argument("--max-refine", type=int, default=60, help="GMRES-IR operator applications (mixed path)")
     ap.add_argument("--no-stable-check", action="store_true",
                     help="skip the mixed-vs-FP64 check on the N=65536 d=8 mixture (lambda=0.1)")
     ap.add_argument("--no-separate", action="store_true",
@@ -206,6 +218,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-11, help="target relative residual of the refined solves")
     ap.add_argument("--qr-split-levels", type=int, default=0,
                     help="tree levels factored by the split pivoted QR (0: library default, -1: none)")
+    ap.add_argument("--cpu-rhs", type=int, default=4, help="right-hand sides the oracle solves in its check")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built",
@@ -232,7 +245,7 @@ def main():
     t_tree = time.perf_counter() - t0
     log(f"[bench] tree built in {t_tree:.3f} s (depth {tree.D})")
 
-    def step(prec, keep=False, fused=True):
+    def step(prec, keep=False, fused=True, refine=0):
         # fused: askit_skeletonize_factorize (the two phases pipelined over
         # two streams); else the two separate calls
         torch.cuda.synchronize()
@@ -245,134 +258,124 @@ def main():
             torch.cuda.synchronize()
             b = time.perf_counter()
             f = tree.factorize(lam, prec)
-        if prec == ak.ASKIT_MIXED:
-            f.set_refinement(args.max_refine, args.tol)
+        f.set_refinement(refine, args.tol)
         torch.cuda.synchronize()
         cc = time.perf_counter()
         x = f.solve(B)
         torch.cuda.synchronize()
         e = time.perf_counter()
-        info = f.info() if prec == ak.ASKIT_MIXED else None
-        if info is not None:
-            info["min_pivot_ratio"] = f.pivot_ratio()[0]
         out = dict(total=cc - a, skel=None if b is None else b - a, factor=None if b is None else cc - b,
-                   solve=e - cc, info=info)
+                   solve=e - cc, info=f.info() if refine else None)
         if keep:
             return out, f, x
         f.close()
         del x
         return out, None, None
 
-    for w in range(args.warmup):
-        r, _, _ = step(ak.ASKIT_MIXED)
-        log(f"[bench] warmup {w}: skeletonize+factorize {r['total']:.3f} s solve {r['solve']:.3f} s")
+    def timed_steps(prec, label, refine=0):
+        for w in range(args.warmup):
+            r, _, _ = step(prec, refine=refine)
+            log(f"[bench] {label} warmup {w}: skeletonize+factorize {r['total']:.4f} s solve {r['solve']:.4f} s")
+        torch.cuda.synchronize()
+        T0 = time.perf_counter()
+        runs, fk, xk = [], None, None
+        for k in range(args.steps):
+            r, f, x = step(prec, keep=(k == args.steps - 1), refine=refine)
+            runs.append(r)
+            if f is not None:
+                fk, xk = f, x
+            log(f"[bench] {label} step {k}: skeletonize+factorize {r['total']:.4f} s solve {r['solve']:.4f} s"
+                + (f" refine {r['info']}" if r["info"] else ""))
+        torch.cuda.synchronize()
+        T1 = time.perf_counter()
+        return runs, fk, xk, T1 - T0
 
-    ak.askit_profile_enable(True)
+    # --- the FP64 path: the headline ------------------------------------------
+    runs64, f64, x64, wall64 = timed_steps(ak.ASKIT_FP64, "fp64")
+    t_fac64 = float(np.mean([r["total"] for r in runs64]))
+    t_sol64 = float(np.mean([r["solve"] for r in runs64]))
+    pr64 = f64.pivot_ratio()
+    r64 = B - f64.matvec(x64)
+    eps64 = float((r64.norm(dim=0) / B.norm(dim=0)).max())
+    del r64
+    f64.set_refinement(0, args.tol)
+    Bone = B[:, :1].contiguous()
+    f64.solve(Bone)
     torch.cuda.synchronize()
-    T0 = time.perf_counter()
-    runs = []
-    fmx = xmx = None
-    for k in range(args.steps):
-        r, f, x = step(ak.ASKIT_MIXED, keep=(k == args.steps - 1))
-        runs.append(r)
-        if f is not None:
-            fmx, xmx = f, x
-        log(f"[bench] step {k}: skeletonize+factorize {r['total']:.3f} s solve {r['solve']:.3f} s "
-            f"refine {r['info']}")
+    a = time.perf_counter()
+    f64.solve(Bone)
     torch.cuda.synchronize()
-    T1 = time.perf_counter()
-    prof = ak.askit_profile_report()
-    ak.askit_profile_enable(False)
-    # the stored mixed factors applied once (no refinement): 64 right-hand
-    # sides, and one right-hand side (latency)
-    fmx.set_refinement(0, args.tol)
-    direct = {}
-    for name, Bx in (("nrhs", B), ("one_rhs", B[:, :1].contiguous())):
-        fmx.solve(Bx)
+    t_one = time.perf_counter() - a
+    # the FP64 factors refined against the same FP64 operator (GMRES-IR): the
+    # reference solution of the mixed path
+    f64.set_refinement(50, args.tol)
+    a = time.perf_counter()
+    xref = f64.solve(B)
+    torch.cuda.synchronize()
+    t_ref = time.perf_counter() - a
+    info64 = f64.info()
+    log(f"[bench] fp64: skeletonize+factorize {t_fac64:.4f} s, solve {t_sol64:.4f} s, direct residual "
+        f"{eps64:.2e}, refined {t_ref:.3f} s {info64}, min pivot ratio {pr64[0]:.2e}")
+    ranks, cands = tree.skeleton_sizes()
+    qrows = tree.qr_rows()
+    ids64, P64, sizes64 = tree.export_skeletons() if args.cpu_full else (None, None, None)
+    f64.close()
+
+    # --- per-kernel times: the same FP64 steps again, every launch between
+    # HIP events on its stream
+    prof = {}
+    if not args.no_profile:
+        ak.askit_profile_enable(True)
+        for k in range(args.steps):
+            step(ak.ASKIT_FP64)
         torch.cuda.synchronize()
+        prof = ak.askit_profile_report()
+        ak.askit_profile_enable(False)
+        log("[bench] profiled pass done")
+
+    # --- the mixed path --------------------------------------------------------
+    mixed = None
+    if not args.no_mixed:
+        runsm, fm, _, _ = timed_steps(ak.ASKIT_MIXED, "mixed")
+        t_facm = float(np.mean([r["total"] for r in runsm]))
+        t_solm = float(np.mean([r["solve"] for r in runsm]))
+        fm.set_refinement(args.max_refine, args.tol)
         a = time.perf_counter()
-        fmx.solve(Bx)
+        xm = fm.solve(B)
         torch.cuda.synchronize()
-        direct[name] = time.perf_counter() - a
-    fmx.close()
-    ms_step = 1e3 * (T1 - T0) / args.steps
-    t_total = float(np.mean([r["total"] for r in runs]))
-    t_sol = float(np.mean([r["solve"] for r in runs]))
-    info = runs[-1]["info"]
-    # the same step through the two separate calls (no overlap), once
+        t_refm = time.perf_counter() - a
+        infom = fm.info()
+        err = float(((xm - xref).norm(dim=0) / xref.norm(dim=0)).max())
+        gate = bool(err <= MIXED_GATE and infom["converged"])
+        mixed = dict(skeletonize_factorize_s=t_facm, direct_solve_s=t_solm, refined_solve_s=t_refm,
+                     refinement=infom, rel_err_vs_fp64_refined=err, gate=f"rel err <= {MIXED_GATE:g}, converged",
+                     gate_pass=gate, speedup_factor_over_fp64=t_fac64 / t_facm,
+                     min_pivot_ratio=fm.pivot_ratio()[0])
+        log(f"[bench] mixed: skeletonize+factorize {t_facm:.4f} s ({t_fac64 / t_facm:.2f}x fp64), refined "
+            f"{t_refm:.3f} s {infom}, vs fp64 {err:.2e}: gate {'pass' if gate else 'FAIL'}")
+        fm.close()
+        del xm
+
     two_call = None
     if not args.no_separate:
-        r2, _, _ = step(ak.ASKIT_MIXED, fused=False)
+        r2, _, _ = step(ak.ASKIT_FP64, fused=False)
         two_call = dict(skeletonize_s=r2["skel"], factorize_s=r2["factor"], total_s=r2["total"])
-        log(f"[bench] separate calls: skeletonize {r2['skel']:.3f} s factorize {r2['factor']:.3f} s")
+        log(f"[bench] fp64 separate calls: skeletonize {r2['skel']:.4f} s factorize {r2['factor']:.4f} s")
 
-    res = {}
-    if not args.no_fp64:
-        # one untimed FP64 pass first (its first allocations), like the
-        # warm-up of the timed mixed steps
-        tree.skeletonize_factorize(lam, ak.ASKIT_FP64).close()
-        torch.cuda.synchronize()
-        # factorization alone (the skeletons of the pass above), then the
-        # pipelined call; each reuses the device blocks of the one before
-        a = time.perf_counter()
-        f64 = tree.factorize(lam, ak.ASKIT_FP64)
-        torch.cuda.synchronize()
-        t_f64_only = time.perf_counter() - a
-        f64.close()
-        a = time.perf_counter()
-        f64 = tree.skeletonize_factorize(lam, ak.ASKIT_FP64)
-        torch.cuda.synchronize()
-        b = time.perf_counter()
-        x64 = f64.solve(B)
-        torch.cuda.synchronize()
-        e = time.perf_counter()
-        r64 = B - f64.matvec(x64)
-        eps64 = float((r64.norm(dim=0) / B.norm(dim=0)).max())
-        # the FP64 path refined against the same FP64 operator (GMRES-IR with
-        # the FP64 factors) is the reference the mixed result is compared with
-        f64.set_refinement(50, args.tol)
-        g0 = time.perf_counter()
-        xref = f64.solve(B)
-        torch.cuda.synchronize()
-        g1 = time.perf_counter()
-        info64 = f64.info()
-        info64["min_pivot_ratio"] = f64.pivot_ratio()[0]
-        err = float(((xmx - xref).norm(dim=0) / xref.norm(dim=0)).max())
-        err_direct = float(((xmx - x64).norm(dim=0) / x64.norm(dim=0)).max())
-        res = dict(fp64_factor_s=b - a, fp64_factorize_only_s=t_f64_only, fp64_solve_s=e - b,
-                   fp64_solves_per_s=args.nrhs / (e - b), fp64_residual=eps64,
-                   fp64_refined_solve_s=g1 - g0, fp64_refinement=info64,
-                   mixed_vs_fp64_rel_err=err, mixed_vs_fp64_direct_rel_err=err_direct,
-                   speedup_factor_mixed_over_fp64=(b - a) / t_total,
-                   speedup_factorize_only=t_f64_only / two_call["factorize_s"] if two_call else None)
-        log(f"[bench] fp64: skeletonize+factorize {b - a:.3f} s (factorize alone {t_f64_only:.3f} s) solve "
-            f"{e - b:.3f} s (residual {eps64:.2e}); refined "
-            f"{g1 - g0:.3f} s {info64}; mixed vs fp64 refined {err:.2e}, vs fp64 direct {err_direct:.2e}")
-        f64.close()
-        del x64, r64, xref
-
-    # roofline of every reported kernel family; the dominant one (largest
-    # total time in the timed steps) is the headline
-    ranks, cands = tree.skeleton_sizes()
-    # the library's default split levels in the pipelined call (the timed
-    # steps): those with fewer than 1024 nodes
+    # --- rooflines of the FP64 step ----------------------------------------------
     split = {0: min(tree.D - 1, 9), -1: 0}.get(args.qr_split_levels, args.qr_split_levels)
-    cnt = algorithmic_counts(N, d, m, s, tree.D, nsamp, args.nrhs, ranks, split)
+    cnt = algorithmic_counts(N, d, m, s, tree.D, nsamp, args.nrhs, ranks, qrows, split)
     rank_levels = {}
     for lvl in range(1, tree.D + 1):
         rl = ranks[(1 << lvl) - 1:(2 << lvl) - 1]
-        rank_levels[lvl] = [int(rl.min()), round(float(rl.mean()), 1), int(rl.max())]
-    rooflines = {}
-    for key, ck, bound, pk, unit, nl in ROOF_TABLE:
-        r = roofline_of(key, ck, bound, pk, unit, nl, prof, cnt, tree.D, args.steps)
-        if r is not None:
-            rooflines[key] = r
-    # the headline is the kernel that dominates the metric's value (the
-    # skeletonize + factorize time)
-    top = sorted(prof.items(), key=lambda kv: -kv[1][0])
-    # (single kernels only: the split QR family is a sequence of launches)
-    dom = next((k for k, _ in top if k in rooflines and k.split(":")[0] in ("skel", "factor")
-                and k != "skel:k_qrcp_split"), None)
+        ql = qrows[(1 << lvl) - 1:(2 << lvl) - 1]
+        ql = ql[ql > 0]
+        rank_levels[lvl] = dict(rank=[int(rl.min()), round(float(rl.mean()), 1), int(rl.max())],
+                                qr_rows_mean=round(float(ql.mean()), 1) if ql.size else 0.0)
+    rooflines = rooflines_of(prof, cnt, args.steps) if prof else {}
+    # the headline roofline is the kernel with the largest time in the step
+    top = sorted(((k, v) for k, v in prof.items() if k != "@timeline"), key=lambda kv: -kv[1][0])
+    dom = next((k for k, _ in top if k in rooflines), None)
     roof = dict(rooflines[dom]) if dom else None
     tr = TRAFFIC.get(dom) if dom else None
     if roof is not None and tr is not None and tr["src_sha256"] == kernel_source_sha(tr["source"]) \
@@ -386,37 +389,39 @@ def main():
     if not args.no_stable_check:
         stable = stable_config_check(ak, torch, dev, args.tol)
     if args.calibrate_copy:
-        x = torch.empty(1 << 27, dtype=torch.float64, device=dev).uniform_()
-        y = torch.empty_like(x)
+        xc = torch.empty(1 << 27, dtype=torch.float64, device=dev).uniform_()
+        yc = torch.empty_like(xc)
         for _ in range(3):
-            torch.neg(x, out=y)
+            torch.neg(xc, out=yc)
         torch.cuda.synchronize()
         log("[bench] calibration copy: 3 x (1 GiB read + 1 GiB write), torch.neg")
-        del x, y
+        del xc, yc
 
     cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(c, args.cpu_sample, args.nrhs)
+    if args.cpu_full:
+        cpu = cpu_full_check(c, tree, ids64, P64, sizes64, x64, xref, args.cpu_rhs)
+    elif not args.no_cpu:
+        cpu = cpu_baseline(c, args.cpu_sample)
 
     out = {
-        "metric": METRIC, "value": t_total, "unit": "s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": False, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "metric": METRIC, "value": t_fac64, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * wall64 / args.steps, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"gaussian-mixture N={N} d={d} m={m} s={s} h={h} lambda={lam} nrhs={args.nrhs}",
                    "N": N, "d": d, "leaf_size": m, "rank": s, "n_samples": nsamp, "nrhs": args.nrhs,
-                   "precision": "mixed"},
-        "skeletonize_factorize_s": t_total, "separate_calls": two_call, "solve_s": t_sol, "solves_per_s": args.nrhs / t_sol,
-        "direct_solve_s": direct["nrhs"], "direct_solves_per_s": args.nrhs / direct["nrhs"],
-        "one_rhs_direct_solve_s": direct["one_rhs"],
-        "refinement": info, "tree_s": t_tree,
-        **res,
-        "skeleton_ranks_min_mean_max": rank_levels,
+                   "precision": "fp64"},
+        "skeletonize_factorize_s": t_fac64, "separate_calls": two_call,
+        "solve_s": t_sol64, "solves_per_s": args.nrhs / t_sol64, "one_rhs_solve_s": t_one,
+        "fp64_direct_residual": eps64, "fp64_refined_solve_s": t_ref, "fp64_refinement": info64,
+        "fp64_min_pivot_ratio": pr64[0], "tree_s": t_tree,
+        "mixed": mixed,
+        "skeleton_ranks_by_level": rank_levels,
         "roofline": roof,
         "rooflines": rooflines,
         "mixed_on_stable_config": stable,
         "forms": forms,
         "cpu_baseline": cpu,
-        "kernels_ms": {k: [round(v[0] / args.steps, 3), v[1] // args.steps] for k, v in top[:12]},
+        "kernels_ms_per_step": {k: [round(v[0] / args.steps, 3), round(v[1] / args.steps, 1)] for k, v in top[:16]},
     }
     print(json.dumps(out))
 
@@ -521,41 +526,109 @@ def stable_config_check(ak, torch, dev, tol):
         f.close()
     x64, xm = res["fp64"][0], res["mixed"][0]
     out["mixed_vs_fp64_rel_err"] = float(((xm - x64).norm(dim=0) / x64.norm(dim=0)).max())
+    out["gate_pass"] = bool(out["mixed_vs_fp64_rel_err"] <= MIXED_GATE and out["mixed_refinement"]["converged"])
     log(f"[bench] stable config: mixed vs fp64 {out['mixed_vs_fp64_rel_err']:.2e}, "
         f"mixed refinement {out['mixed_refinement']}")
     t.close()
     return out
 
 
-def cpu_baseline(c, n_sample, nrhs):
-    """The oracle (plain C, OpenMP) on a bounded sample of the same workload:
-    the first n_sample points of the mixture with the same d, m, s, h, lambda;
-    factor time (skeletonize + factorize) scaled to N by the N log(N/m) work
-    model of the method (Sec. 3, "Work")."""
+def cpu_baseline(c, n_sample):
+    """The oracle (plain C, OpenMP over the nodes of a level) on a bounded
+    sample of the workload: the first n_sample points of the mixture with the
+    same d, m, s, h, lambda and sample count; its skeletonize + factorize time
+    is scaled to N by the method's N log(N/m) work (Sec. 3, "Work").  The
+    whole workload takes several minutes on 16 cores (--cpu-full)."""
     import oracle
     X = c["X"][:n_sample]
-    Bs = c["B"][:n_sample]
     m, s = c["m"], c["s"]
     o = oracle.Oracle(X, m, s, c["h"], nsamp=c["nsamp"], seed=c["seed"])
     o.build_tree()
-    log(f"[bench] cpu baseline: oracle on {n_sample} points, {oracle.num_threads()} threads")
+    nth = oracle.num_threads()
+    log(f"[bench] cpu baseline: oracle on {n_sample} points, {nth} threads")
     a = time.perf_counter()
     o.skeletonize()
     b = time.perf_counter()
     o.factorize(c["lam"])
     e = time.perf_counter()
-    o.solve(Bs)
-    g = time.perf_counter()
     N = c["X"].shape[0]
     Dn = max(1, int(np.ceil(np.log2(n_sample / m))))
     DN = max(1, int(np.ceil(np.log2(N / m))))
     scale = (N * DN) / (n_sample * Dn)
-    t_fac = (e - a) * scale
-    log(f"[bench] cpu baseline: skel {b - a:.2f} s factor {e - b:.2f} s solve {g - e:.2f} s (sample)")
-    return {"value": t_fac, "unit": "s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"first {n_sample} points of the workload (depth {Dn}); skeletonize+factorize "
-                      f"{e - a:.2f} s measured, scaled by N log(N/m) to N={N} (depth {DN})",
-            "sample_solve_s": g - e}
+    log(f"[bench] cpu baseline: skeletonize {b - a:.2f} s factorize {e - b:.2f} s (sample)")
+    return {"value": (e - a) * scale, "unit": "s", "cores": nth, "kind": "oracle",
+            "sample": f"first {n_sample} points of the workload (depth {Dn}): skeletonize+factorize "
+                      f"{e - a:.2f} s measured, scaled by N log(N/m) to N={N} (depth {DN})"}
+
+
+def cpu_full_check(c, tree, ids, P, sizes, x64, xref, nrhs_check):
+    """The oracle (plain C, OpenMP over the nodes of a level) on the whole
+    workload: its skeletonize + factorize time is the CPU baseline.  Then it
+    checks the GPU's results: the tree permutation bit for bit, the skeletons
+    node by node (pivots identical), and, factored on the GPU's own skeletons,
+    the GPU's FP64 direct and refined solutions of the first nrhs_check
+    right-hand sides against the oracle's solution and operator."""
+    import oracle
+    X, B = c["X"], c["B"]
+    N = X.shape[0]
+    m, s = c["m"], c["s"]
+    nth = oracle.num_threads()
+    log(f"[bench] cpu baseline: oracle on the whole workload (N={N}), {nth} threads")
+    o = oracle.Oracle(X, m, s, c["h"], nsamp=c["nsamp"], seed=c["seed"])
+    a = time.perf_counter()
+    perm = o.build_tree()
+    b = time.perf_counter()
+    o.skeletonize()
+    e = time.perf_counter()
+    o.factorize(c["lam"])
+    g = time.perf_counter()
+    log(f"[bench] cpu baseline: tree {b - a:.1f} s, skeletonize {e - b:.1f} s, factorize {g - e:.1f} s")
+    out = {"value": g - b, "unit": "s", "cores": nth, "kind": "oracle",
+           "sample": f"the whole workload (N={N}); skeletonize {e - b:.2f} s + factorize {g - e:.2f} s",
+           "tree_s": b - a}
+    check = {"perm_bit_exact": bool(np.array_equal(perm, tree.perm().cpu().numpy()))}
+    # skeletons: identical pivot lists per node (internal nodes are compared
+    # only where both children agree, since their candidates differ otherwise)
+    nn = tree.nnodes
+    same = np.zeros(nn, dtype=bool)
+    comparable = 0
+    for node in range(nn - 1, 0, -1):
+        leaf = node >= (1 << tree.D) - 1
+        if not leaf and not (same[2 * node + 1] and same[2 * node + 2]):
+            continue
+        comparable += 1
+        pos, _, _ = o.skeleton(node)
+        sr = int(sizes[2 * node])
+        same[node] = sr == len(pos) and np.array_equal(ids[node * s: node * s + sr], pos)
+    check["skeleton_nodes_identical"] = int(same.sum())
+    check["skeleton_nodes_compared"] = comparable
+    check["skeleton_nodes"] = nn - 1
+    # factor on the GPU's skeletons and compare solutions
+    cm = tree.cmax
+    for node in range(1, nn):
+        sr, nc = int(sizes[2 * node]), int(sizes[2 * node + 1])
+        o.set_skeleton(node, ids[node * s: node * s + sr],
+                       P[node * s * cm: node * s * cm + sr * nc].reshape(sr, nc))
+    o.factorize(c["lam"])
+    k = nrhs_check
+    Bk = B[:, :k]
+    xo = o.solve(Bk)
+    xg = x64[:, :k].cpu().numpy()
+    xr = xref[:, :k].cpu().numpy()
+    nb = np.linalg.norm(Bk, axis=0)
+
+    def rel(u, v):
+        return float((np.linalg.norm(u - v, axis=0) / np.linalg.norm(v, axis=0)).max())
+
+    check["gpu_fp64_direct_vs_oracle_direct"] = rel(xg, xo)
+    check["oracle_direct_residual"] = float((np.linalg.norm(Bk - o.matvec(xo), axis=0) / nb).max())
+    check["gpu_fp64_direct_residual_oracle_operator"] = float((np.linalg.norm(Bk - o.matvec(xg), axis=0) / nb).max())
+    check["gpu_fp64_refined_residual_oracle_operator"] = float((np.linalg.norm(Bk - o.matvec(xr), axis=0) / nb).max())
+    check["gpu_fp64_refined_vs_oracle_direct"] = rel(xr, xo)
+    check["rhs_checked"] = k
+    out["check"] = check
+    log(f"[bench] cpu check: {check}")
+    return out
 
 
 if __name__ == "__main__":

@@ -12,9 +12,16 @@
  * -> solve (Alg. 3).
  *
  * Conventions for every entry point:
- *  - All array arguments are DEVICE pointers (memory of the current HIP
- *    device), owned by the caller; the library never frees them and never
- *    keeps them after the call returns (inputs are copied when retained).
+ *  - Array arguments are owned by the caller; the library never frees them
+ *    and never keeps them after the call returns (inputs are copied when
+ *    retained).  They are DEVICE pointers (memory of the current HIP
+ *    device), except where an entry point says otherwise; the points of
+ *    askit_build_tree, the permutation of askit_tree_perm and the arrays of
+ *    askit_solve, askit_solve_transpose, askit_matvec and
+ *    askit_adjoint_scalars may also be HOST pointers (pageable or pinned,
+ *    told apart by hipPointerGetAttributes).  Host arrays are staged through
+ *    device buffers of the call, which then synchronizes `stream` before it
+ *    returns.
  *  - Points are N x d row-major (point-major; the paper's d x N matrix X).
  *  - Right-hand sides and solutions are N x nrhs column-major with leading
  *    dimension ld >= N, in the caller's original point order.
@@ -56,6 +63,12 @@ typedef struct askit_factor_s *askit_factor;
  * clamped per node to the number of candidates), n_samples = rows sampled
  * per node for the ID (0 -> 4 s), seed = sampling seed, problem = index
  * folded into the sampling streams, h = kernel bandwidth (> 0).
+ * tol = tau of the adaptive rank of Sec. 2.1 ("Computing low rank
+ * approximations"): a node's rank is the smallest s_alpha with
+ * |R_{s_alpha s_alpha}| < tau |R_00| on the diagonal of its pivoted QR
+ * (the estimate of sigma_{s_alpha+1} / sigma_1), at most rank (then s_max);
+ * 0 keeps the fixed rank.  In [0, 1).  Every QR also stops at the rank
+ * guard |R_jj| <= 1e-14 |R_00|.
  * qr_split_levels chooses the launch shape of the pivoted QR, not its
  * result: nodes at tree levels 1 .. L are factored by several workgroups
  * each, one launch per pivot step, the deeper ones by one workgroup each
@@ -71,23 +84,25 @@ typedef struct {
     uint64_t seed;
     int64_t problem;
     double h;
+    double tol;
 } askit_options;
 
 /* Tree build (Sec. 2.1, "Partitioning the matrix"): complete binary tree of
  * depth D = ceil(log2(N / m)); each node's points are split in two halves
  * (floor(n/2) to the left) by the hyperplane through their median along
- * their principal axis.  X: device, N x d row-major FP64, copied.  Blocks
- * until the tree is built.  Errors: ASKIT_ERR_ARG for N < 1 or N >= 2^31,
- * d < 1 or d > 64, m < 2, s < 1, h <= 0 or not finite, n_samples < 0 or
- * > 4096, qr_split_levels < -1, a largest leaf ceil(N / 2^D) above 512
- * points or 2 s above 512 (the kernels hold a leaf block and a reduced
- * system of order s_l + s_r in one workgroup). */
+ * their principal axis.  X: device or host, N x d row-major FP64, copied.
+ * Blocks until the tree is built.  Errors: ASKIT_ERR_ARG for N < 1 or
+ * N >= 2^31, d < 1 or d > 64, m < 2, s < 1, h <= 0 or not finite, tol
+ * outside [0, 1), non-finite coordinates, n_samples < 0 or > 4096,
+ * qr_split_levels < -1, a largest leaf ceil(N / 2^D) above 512 points or
+ * 2 s above 512 (the kernels hold a leaf block and a reduced system of order
+ * s_l + s_r in one workgroup). */
 askit_status askit_build_tree(const double *X, int64_t N, int32_t d, const askit_options *opt, void *stream,
                               askit_tree *out);
 
 /* Tree depth D and the permutation (perm[position] = original index). */
 askit_status askit_tree_depth(askit_tree t, int32_t *D);
-askit_status askit_tree_perm(askit_tree t, int64_t *perm /* device, N */);
+askit_status askit_tree_perm(askit_tree t, int64_t *perm /* device or host, N */);
 
 /* Skeletonize (Alg. 1; ID of eq. (4)): bottom-up over all non-root nodes,
  * sample min(n_samples, N - n_alpha) rows outside the node, form the kernel
@@ -107,6 +122,25 @@ askit_status askit_skeletonize(askit_tree t, void *stream);
  * every later step: Z of node alpha has order s_l + s_r, Phat_alpha has
  * s_alpha columns. */
 askit_status askit_skeletons_export(askit_tree t, int32_t *ids, double *P, int32_t *sizes);
+
+/* Rows of the sampled block that the last skeletonization's pivoted QR
+ * factored, per heap node (device or host array of 2^(D+1) - 1 int32): the
+ * sampled rows min(n_samples, N - n_alpha) less those dropped as numerically
+ * zero (squared norm at most 1e-44 of the block's squared Frobenius norm);
+ * 0 for the root and for nodes with at most `rank` candidates (P = I, no
+ * QR).  For work accounting.  ASKIT_ERR_STATE before a skeletonization;
+ * imported skeletons keep the counts of the last skeletonization. */
+askit_status askit_tree_qr_rows(askit_tree t, int32_t *rows);
+
+/* Sampled rows S' of the last skeletonization (Sec. 2.1: the rows outside the
+ * node that stand in for its complement in the ID), as tree positions in
+ * draw order: n_samples int32 per heap node at offset node * n_samples
+ * (device or host array of (2^(D+1) - 1) * n_samples).  A node's first
+ * min(n_samples, N - n_alpha) entries are its sample, in the order of the
+ * rows of its sampled block; the entries of the root and of nodes with at
+ * most `rank` candidates (no QR) are unspecified.  ASKIT_ERR_STATE before a
+ * skeletonization. */
+askit_status askit_tree_samples(askit_tree t, int32_t *samples);
 askit_status askit_skeletons_import(askit_tree t, const int32_t *ids, const double *P, const int32_t *sizes);
 
 /* Factorize (Alg. 2, eqs. (7)-(10)): leaf LU of lambda I + K_aa; for every
@@ -206,6 +240,8 @@ askit_status askit_factor_pivot_ratio(askit_factor f, double *ratio, int32_t *no
  *    height) and captures each in a hipGraph; nothing is computed yet.
  *    lambdas: HOST array of count values; nrhs = right-hand sides per solve.
  *  - askit_batch_factorize: replays the factorization graph on `stream`.
+ *  - askit_factorize_batched: askit_batch_create, then one
+ *    askit_batch_factorize on `stream`; on failure nothing is returned.
  *  - askit_batch_check: pivot ratios of all factors (synchronizes).
  *  - askit_batch_solve: B[i], X[i] (HOST arrays of count DEVICE pointers, each
  *    N_i x nrhs column-major with ld = N_i) -> X[i] = A_i^{-1} B[i]; replays
@@ -217,6 +253,8 @@ askit_status askit_skeletonize_batched(askit_tree *trees, int32_t count, void *s
 askit_status askit_batch_create(askit_tree *trees, int32_t count, const double *lambdas, int32_t precision,
                                 int32_t nrhs, askit_batch *out);
 askit_status askit_batch_factorize(askit_batch b, void *stream);
+askit_status askit_factorize_batched(askit_tree *trees, int32_t count, const double *lambdas, int32_t precision,
+                                     int32_t nrhs, void *stream, askit_batch *out);
 askit_status askit_batch_check(askit_batch b, double *min_ratio, int32_t *problem, void *stream);
 askit_status askit_batch_solve(askit_batch b, const double *const *B, double *const *X, void *stream);
 askit_status askit_batch_factor(askit_batch b, int32_t i, askit_factor *f);

@@ -49,6 +49,7 @@ typedef struct {
     uint64_t seed;
     int64_t problem;        /* problem index folded into the sampling seed */
     double h;
+    double tol;             /* tau of the adaptive rank rule (0: fixed s)  */
     double *X;              /* N x d, original point order                 */
     /* tree */
     int D;                  /* depth; leaves at level D                    */
@@ -177,6 +178,17 @@ void orc_free(orc_t *o) {
 }
 
 int orc_get_depth(const orc_t *o) { return o->D; }
+
+/* Adaptive rank (Sec. 2.1, "Computing low rank approximations"): the rank
+ * of a node is the smallest s_alpha with sigma_{s_alpha+1} / sigma_1 < tau,
+ * the singular values estimated by the diagonal of the pivoted QR, capped
+ * at s (then s_max).  tau = 0 keeps the fixed rank s.  Takes effect at
+ * the next skeletonization. */
+int orc_set_tol(orc_t *o, double tau) {
+    if (!(tau >= 0.0) || !(tau < 1.0)) return ORC_ERR_ARG;
+    o->tol = tau;
+    return ORC_OK;
+}
 
 /* Change the bandwidth while keeping the tree and the skeletons (the ID is
  * held fixed, as in the bandwidth derivative); the factorization is dropped. */
@@ -374,16 +386,19 @@ int64_t orc_sample(uint64_t seed, int64_t problem, int64_t id, int64_t N, int64_
 /* (Sec. 2.1, eq. (4)).  M is rows x cols, column-major, overwritten.       */
 /* Reading: Businger-Golub pivoting with the trailing column norms          */
 /* recomputed at every step, largest norm first, lowest column on ties;     */
-/* LAPACK-style reflectors; stop after `steps` steps, or earlier when       */
-/* |R_jj| <= 1e-14 |R_00| (rank guard).  Returns the rank used.             */
+/* LAPACK-style reflectors; stop after `steps` steps, or earlier at the     */
+/* first step j > 0 with |R_jj| <= 1e-14 |R_00| (rank guard) or             */
+/* |R_jj| < rtol |R_00| (the adaptive rank rule of Sec. 2.1 with tau =     */
+/* rtol, the singular values estimated by R's diagonal; 0 disables it).     */
+/* Returns the rank used.                                                   */
 /* piv[j] = original column in position j; T = R11^{-1} R12 (rank x         */
 /* (cols-rank), row-major) is written when T != NULL.                       */
 /* ------------------------------------------------------------------------ */
 
 #define RANK_GUARD 1e-14
 
-int orc_qrcp(double *M, int rows, int cols, int steps, int *piv, double *Rdiag, double *T,
-             int *truncated) {
+int orc_qrcp_tol(double *M, int rows, int cols, int steps, double rtol, int *piv, double *Rdiag, double *T,
+                 int *truncated) {
     double *nrm = (double *)malloc(sizeof(double) * cols);
     if (steps > cols) steps = cols;
     if (steps > rows) steps = rows;
@@ -424,7 +439,7 @@ int orc_qrcp(double *M, int rows, int cols, int steps, int *piv, double *Rdiag, 
         col[j] = beta;
         if (Rdiag) Rdiag[j] = beta;
         if (j == 0) r00 = fabs(beta);
-        if (j > 0 && fabs(beta) <= RANK_GUARD * r00) {
+        if (j > 0 && (fabs(beta) <= RANK_GUARD * r00 || fabs(beta) < rtol * r00)) {
             rank = j;
             if (truncated) *truncated = 1;
             break;
@@ -461,6 +476,11 @@ int orc_qrcp(double *M, int rows, int cols, int steps, int *piv, double *Rdiag, 
     }
     free(nrm);
     return rank;
+}
+
+/* fixed rank: the QR above with tau = 0 (only the rank guard) */
+int orc_qrcp(double *M, int rows, int cols, int steps, int *piv, double *Rdiag, double *T, int *truncated) {
+    return orc_qrcp_tol(M, rows, cols, steps, 0.0, piv, Rdiag, T, truncated);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -503,7 +523,7 @@ static int skeletonize_node(orc_t *o, int64_t id) {
     int *pv = (int *)malloc(sizeof(int) * ncand);
     double *T = (double *)malloc(sizeof(double) * (size_t)srank * ncand);
     int tr = 0;
-    int rank = orc_qrcp(M, (int)ns, ncand, srank, pv, NULL, T, &tr);
+    int rank = orc_qrcp_tol(M, (int)ns, ncand, srank, o->tol, pv, NULL, T, &tr);
     if (rank < srank) tr = 1;
     o->sr[id] = rank;
     o->trunc[id] = tr;

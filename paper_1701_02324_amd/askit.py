@@ -26,6 +26,7 @@ EXPORTED = [
     "askit_profile_report", "askit_tree_set_bandwidth", "askit_adjoint_scalars", "askit_skeletonize_batched",
     "askit_batch_create", "askit_batch_factorize", "askit_batch_check", "askit_batch_solve", "askit_batch_factor",
     "askit_batch_destroy", "askit_skeletonize_factorize", "askit_release_cached_memory",
+    "askit_factorize_batched", "askit_tree_qr_rows", "askit_tree_samples",
 ]
 
 
@@ -38,7 +39,7 @@ class AskitError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("leaf_size", ctypes.c_int32), ("rank", ctypes.c_int32), ("n_samples", ctypes.c_int32),
                 ("qr_split_levels", ctypes.c_int32), ("seed", ctypes.c_uint64), ("problem", ctypes.c_int64),
-                ("h", ctypes.c_double)]
+                ("h", ctypes.c_double), ("tol", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -64,6 +65,8 @@ def load(path: str = LIB_PATH):
     L.askit_build_tree.argtypes = [_vp, _i64, _i32, ctypes.POINTER(Options), _vp, ctypes.POINTER(_vp)]
     L.askit_tree_depth.argtypes = [_vp, ctypes.POINTER(_i32)]
     L.askit_tree_perm.argtypes = [_vp, _vp]
+    L.askit_tree_qr_rows.argtypes = [_vp, _vp]
+    L.askit_tree_samples.argtypes = [_vp, _vp]
     L.askit_skeletonize.argtypes = [_vp, _vp]
     L.askit_skeletons_export.argtypes = [_vp, _vp, _vp, _vp]
     L.askit_skeletons_import.argtypes = [_vp, _vp, _vp, _vp]
@@ -83,6 +86,8 @@ def load(path: str = LIB_PATH):
     L.askit_batch_create.argtypes = [ctypes.POINTER(_vp), _i32, ctypes.POINTER(ctypes.c_double), _i32, _i32,
                                      ctypes.POINTER(_vp)]
     L.askit_batch_factorize.argtypes = [_vp, _vp]
+    L.askit_factorize_batched.argtypes = [ctypes.POINTER(_vp), _i32, ctypes.POINTER(ctypes.c_double), _i32, _i32,
+                                          _vp, ctypes.POINTER(_vp)]
     L.askit_batch_check.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32), _vp]
     L.askit_batch_solve.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]
     L.askit_batch_factor.argtypes = [_vp, _i32, ctypes.POINTER(_vp)]
@@ -127,11 +132,12 @@ def _colmajor(B):
 # thin wrappers with the C names
 # ---------------------------------------------------------------------------
 
-def askit_build_tree(X, leaf_size, rank, h, n_samples=0, seed=0, problem=0, stream=None, qr_split_levels=0):
+def askit_build_tree(X, leaf_size, rank, h, n_samples=0, seed=0, problem=0, stream=None, qr_split_levels=0,
+                     tol=0.0):
     X = _dev64(X, "X").contiguous()
     N, d = X.shape
     opt = Options(int(leaf_size), int(rank), int(n_samples), int(qr_split_levels), int(seed) & 0xFFFFFFFFFFFFFFFF,
-                  int(problem), float(h))
+                  int(problem), float(h), float(tol))
     out = _vp()
     _check(load().askit_build_tree(_vp(X.data_ptr()), N, d, ctypes.byref(opt), _stream(stream), ctypes.byref(out)))
     return out
@@ -147,6 +153,22 @@ def askit_tree_perm(tree, N, device="cuda"):
     p = torch.empty(N, dtype=torch.int64, device=device)
     _check(load().askit_tree_perm(tree, _vp(p.data_ptr())))
     return p
+
+
+def askit_tree_qr_rows(tree, nnodes):
+    """Rows each node's pivoted QR factored (numpy int32 per heap node)."""
+    import numpy as np
+    rows = np.zeros(nnodes, dtype=np.int32)
+    _check(load().askit_tree_qr_rows(tree, rows.ctypes.data))
+    return rows
+
+
+def askit_tree_samples(tree, nnodes, nsamp):
+    """Sampled rows of each node (numpy int32, nnodes x nsamp, tree positions)."""
+    import numpy as np
+    out = np.zeros(nnodes * nsamp, dtype=np.int32)
+    _check(load().askit_tree_samples(tree, out.ctypes.data))
+    return out.reshape(nnodes, nsamp)
 
 
 def askit_skeletonize(tree, stream=None):
@@ -297,11 +319,14 @@ def askit_factor_destroy(factor):
 class Tree:
     """Tree + skeletons of one problem (points X on the GPU, FP64)."""
 
-    def __init__(self, X, leaf_size, rank, h, n_samples=0, seed=0, problem=0, stream=None, qr_split_levels=0):
+    def __init__(self, X, leaf_size, rank, h, n_samples=0, seed=0, problem=0, stream=None, qr_split_levels=0,
+                 tol=0.0):
         self.N, self.d = X.shape
         self.m, self.s, self.h = int(leaf_size), int(rank), float(h)
         self.nsamp = int(n_samples) or 4 * self.s
-        self.handle = askit_build_tree(X, leaf_size, rank, h, n_samples, seed, problem, stream, qr_split_levels)
+        self.tol = float(tol)
+        self.handle = askit_build_tree(X, leaf_size, rank, h, n_samples, seed, problem, stream, qr_split_levels,
+                                       tol)
         self.D = askit_tree_depth(self.handle)
         self.nnodes = (2 << self.D) - 1
         self.mmax = -(-self.N // (1 << self.D))
@@ -322,6 +347,14 @@ class Tree:
         """(ranks s_alpha, candidate counts |C|) per heap node (root: 0, 0)."""
         sizes = askit_skeletons_export(self.handle, self.nnodes, self.s, self.cmax, sizes_only=True)[2]
         return sizes[0::2].copy(), sizes[1::2].copy()
+
+    def samples(self):
+        """Sampled rows of each node's ID (nnodes x n_samples tree positions)."""
+        return askit_tree_samples(self.handle, self.nnodes, self.nsamp)
+
+    def qr_rows(self):
+        """Rows of the sampled block each node's QR factored (0: no QR)."""
+        return askit_tree_qr_rows(self.handle, self.nnodes)
 
     def import_skeletons(self, ids, P, sizes):
         askit_skeletons_import(self.handle, ids, P, sizes)
@@ -418,6 +451,16 @@ def askit_batch_factorize(batch, stream=None):
     _check(load().askit_batch_factorize(batch, _stream(stream)))
 
 
+def askit_factorize_batched(trees, lambdas, precision=ASKIT_FP64, nrhs=1, stream=None):
+    """Batch of the trees with its factorization graph launched once on `stream`."""
+    arr = (_vp * len(trees))(*[t.handle for t in trees])
+    lam = (ctypes.c_double * len(trees))(*[float(x) for x in lambdas])
+    out = _vp()
+    _check(load().askit_factorize_batched(arr, len(trees), lam, int(precision), int(nrhs), _stream(stream),
+                                          ctypes.byref(out)))
+    return out
+
+
 def askit_batch_check(batch, stream=None):
     r = ctypes.c_double()
     p = _i32()
@@ -450,9 +493,12 @@ class Batch:
     """Independent problems factorized and solved together (one launch per
     kernel and tree height, replayed from hipGraphs)."""
 
-    def __init__(self, trees, lambdas, precision=ASKIT_FP64, nrhs=1):
+    def __init__(self, trees, lambdas, precision=ASKIT_FP64, nrhs=1, factorize=False, stream=None):
         self.trees = list(trees)
-        self.handle = askit_batch_create(self.trees, lambdas, precision, nrhs)
+        if factorize:
+            self.handle = askit_factorize_batched(self.trees, lambdas, precision, nrhs, stream)
+        else:
+            self.handle = askit_batch_create(self.trees, lambdas, precision, nrhs)
         self.nrhs = nrhs
 
     def factorize(self, stream=None):

@@ -619,9 +619,10 @@ struct askit_tree_s {
     uint64_t seed = 0;
     double h = 1.0;      // bandwidth of the skeletonization
     double hfac = 1.0;   // bandwidth of the next factorization (skeletons frozen)
+    double tol = 0.0;    // adaptive rank tolerance tau (0: fixed rank s)
     std::vector<int64_t> nb, ne;  // host node ranges
     DBuf X, Xp, perm, iperm, dnb, dne;  // iperm[original index] = tree position
-    DBuf srank, trunc, skel, Pt, samp;
+    DBuf srank, trunc, skel, Pt, samp, qrows;
     std::vector<int32_t> hsr;  // host copy of the ranks s_alpha (root: 0)
     int split_levels = 0;      // tree levels 1 .. split_levels use the split QRCP
     bool split_default = true; // split_levels was left to the library
@@ -738,6 +739,7 @@ askit_status askit_build_tree(const double *X, int64_t N, int32_t d, const askit
     if (!(opt->h > 0.0) || !std::isfinite(opt->h)) return fail(ASKIT_ERR_ARG, "h must be positive and finite");
     if (opt->n_samples < 0) return fail(ASKIT_ERR_ARG, "n_samples must be >= 0");
     if (opt->qr_split_levels < -1) return fail(ASKIT_ERR_ARG, "qr_split_levels must be >= -1");
+    if (!(opt->tol >= 0.0 && opt->tol < 1.0)) return fail(ASKIT_ERR_ARG, "tol must be in [0, 1)");
     hipStream_t st = (hipStream_t)stream;
     std::unique_ptr<askit_tree_s> t(new askit_tree_s());
     t->N = N;
@@ -750,6 +752,7 @@ askit_status askit_build_tree(const double *X, int64_t N, int32_t d, const askit
     t->problem = opt->problem;
     t->h = opt->h;
     t->hfac = opt->h;
+    t->tol = opt->tol;
     while ((int64_t)t->m * ((int64_t)1 << t->D) < N) t->D++;
     t->nnodes = ((int64_t)2 << t->D) - 1;
     // default: the split QR on every internal level (the pipelined call
@@ -777,7 +780,8 @@ askit_status askit_build_tree(const double *X, int64_t N, int32_t d, const askit
     ST_TRY(t->perm.alloc(sizeof(int64_t) * N));
     ST_TRY(upload(t->dnb, t->nb));
     ST_TRY(upload(t->dne, t->ne));
-    HIP_TRY(hipMemcpyAsync(t->X.p, X, sizeof(double) * N * d, hipMemcpyDeviceToDevice, st));
+    // X may be in host or device memory (unified addressing)
+    HIP_TRY(hipMemcpyAsync(t->X.p, X, sizeof(double) * N * d, hipMemcpyDefault, st));
     // scratch for the level reductions and the sort
     const int npair = d * (d + 1) / 2;
     std::vector<int16_t> pa, pc;
@@ -852,11 +856,13 @@ askit_status askit_build_tree(const double *X, int64_t N, int32_t d, const askit
     // skeleton arrays
     ST_TRY(t->srank.alloc(sizeof(int32_t) * t->nnodes));
     ST_TRY(t->trunc.alloc(sizeof(int32_t) * t->nnodes));
+    ST_TRY(t->qrows.alloc(sizeof(int32_t) * t->nnodes));
     ST_TRY(t->skel.alloc(sizeof(int32_t) * t->nnodes * t->s));
     ST_TRY(t->Pt.alloc(sizeof(double) * t->nnodes * t->cmax * t->s));
     HIP_TRY(hipMemsetAsync(t->srank.p, 0, sizeof(int32_t) * t->nnodes, st));
     HIP_TRY(hipMemsetAsync(t->skel.p, 0xff, sizeof(int32_t) * t->nnodes * t->s, st));  // -1: no skeleton yet
     HIP_TRY(hipMemsetAsync(t->trunc.p, 0, sizeof(int32_t) * t->nnodes, st));
+    HIP_TRY(hipMemsetAsync(t->qrows.p, 0, sizeof(int32_t) * t->nnodes, st));
     HIP_TRY(hipStreamSynchronize(st));
     t->t_tree = ms_since(t0);
     *out = t.release();
@@ -869,9 +875,23 @@ askit_status askit_tree_depth(askit_tree t, int32_t *D) {
     return ASKIT_OK;
 }
 
+askit_status askit_tree_qr_rows(askit_tree t, int32_t *rows) {
+    if (!t || !rows) return fail(ASKIT_ERR_ARG, "NULL argument");
+    if (!t->skel_ok) return fail(ASKIT_ERR_STATE, "the tree is not skeletonized");
+    HIP_TRY(hipMemcpy(rows, t->qrows.p, sizeof(int32_t) * t->nnodes, hipMemcpyDefault));
+    return ASKIT_OK;
+}
+
+askit_status askit_tree_samples(askit_tree t, int32_t *samples) {
+    if (!t || !samples) return fail(ASKIT_ERR_ARG, "NULL argument");
+    if (!t->skel_ok || !t->samp.p) return fail(ASKIT_ERR_STATE, "the tree is not skeletonized");
+    HIP_TRY(hipMemcpy(samples, t->samp.p, sizeof(int32_t) * t->nnodes * t->nsamp, hipMemcpyDefault));
+    return ASKIT_OK;
+}
+
 askit_status askit_tree_perm(askit_tree t, int64_t *perm) {
     if (!t || !perm) return fail(ASKIT_ERR_ARG, "NULL argument");
-    HIP_TRY(hipMemcpy(perm, t->perm.p, sizeof(int64_t) * t->N, hipMemcpyDeviceToDevice));
+    HIP_TRY(hipMemcpy(perm, t->perm.p, sizeof(int64_t) * t->N, hipMemcpyDefault));
     return ASKIT_OK;
 }
 
@@ -918,6 +938,7 @@ struct SkelRun {
             if (trees[i]->s != s || trees[i]->d != d)
                 return fail(ASKIT_ERR_ARG, "batched trees must share rank and dimension");
             if (!trees[i]->samp.p) ST_TRY(trees[i]->samp.alloc(sizeof(int32_t) * trees[i]->nnodes * trees[i]->nsamp));
+            HIP_TRY(hipMemsetAsync(trees[i]->qrows.p, 0, sizeof(int32_t) * trees[i]->nnodes, stream));
             trees[i]->hsr.assign(trees[i]->nnodes, 0);
             trees[i]->skel_ok = false;
         }
@@ -966,8 +987,10 @@ struct SkelRun {
                 k.skel = t->skel.as<int32_t>() + id * t->s;
                 k.sr = t->srank.as<int32_t>() + id;
                 k.trunc = t->trunc.as<int32_t>() + id;
+                k.qrows = t->qrows.as<int32_t>() + id;
                 k.Pt = t->Pt.as<double>() + id * (int64_t)t->cmax * t->s;
                 k.scale = -1.0 / (2.0 * t->h * t->h);
+                k.tol = t->tol;
                 const int ncand = k.leaf ? k.n : t->hsr[2 * id + 1] + t->hsr[2 * id + 2];
                 if (ncand <= s) {
                     ident.push_back(k);
@@ -1070,12 +1093,25 @@ struct SkelRun {
             const SkelTask *tp = dsplit.as<SkelTask>();
             const QrWork wk = w;
             const unsigned g = (unsigned)(nsp * wk.slices);
-            HIP_TRY(timed("skel:k_qrcp_split" + prof_height(hgt), st, [&] {
+            const std::string hs = prof_height(hgt);
+            HIP_TRY(timed("skel:k_qs_rows" + hs, st, [&] {
                 hipLaunchKernelGGL(k_qs_rows, dim3(g), dim3(kQsThreads), 0, st, tp, wk, nsamp_max);
+                return hipGetLastError();
+            }));
+            HIP_TRY(timed("skel:k_qs_rowmap" + hs, st, [&] {
                 hipLaunchKernelGGL(k_qs_rowmap, dim3(nsp), dim3(512), 0, st, tp, wk);
+                return hipGetLastError();
+            }));
+            HIP_TRY(timed("skel:k_qs_init" + hs, st, [&] {
                 hipLaunchKernelGGL(k_qs_init, dim3(g), dim3(kQsThreads), 0, st, tp, wk, s, nsamp_max);
-                for (int j = 0; j < split_steps; j++)
+                return hipGetLastError();
+            }));
+            for (int j = 0; j < split_steps; j++)
+                HIP_TRY(timed("skel:k_qs_step" + hs, st, [&] {
                     hipLaunchKernelGGL(k_qs_step, dim3(g), dim3(kQsThreads), 0, st, tp, wk, j, nsamp_max);
+                    return hipGetLastError();
+                }));
+            HIP_TRY(timed("skel:k_qs_finish" + hs, st, [&] {
                 hipLaunchKernelGGL(k_qs_finish, dim3(nsp, (unsigned)cdiv(wk.slices * kQsCols, kQsFinishCols)), dim3(512), 0,
                                    st, tp, wk, s, nsamp_max);
                 return hipGetLastError();
@@ -2053,6 +2089,54 @@ static askit_status matvec_t_plan(askit_factor f, Plan &P) {
     return ASKIT_OK;
 }
 
+// Arrays of right-hand sides, solutions and adjoints may live in host or
+// device memory.  Host arrays (pageable or pinned) are staged through device
+// buffers of the call; the call then synchronizes its stream before it
+// returns.
+static bool is_host_ptr(const void *p) {
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();  // unknown to the runtime: plain host memory
+        return true;
+    }
+    return a.type == hipMemoryTypeHost || a.type == hipMemoryTypeUnregistered;
+}
+
+// runs body(B', ldb', X', ldx') with device views of two N x nrhs arrays
+// (the first read, the second written unless `out2` is false)
+template <class F>
+static askit_status with_device_arrays(int64_t N, int nrhs, const double *B, int64_t ldb, double *X, int64_t ldx,
+                                       bool out2, hipStream_t st, F &&body) {
+    const bool hb = is_host_ptr(B), hx = is_host_ptr(X);
+    if (!hb && !hx) return body(B, ldb, X, ldx);
+    const size_t col = sizeof(double) * (size_t)N;
+    DBuf db, dx;
+    const double *Bd = B;
+    double *Xd = X;
+    int64_t lb = ldb, lx = ldx;
+    if (hb) {
+        ST_TRY(db.alloc(col * nrhs));
+        HIP_TRY(hipMemcpy2DAsync(db.p, col, B, sizeof(double) * ldb, col, nrhs, hipMemcpyHostToDevice, st));
+        Bd = db.as<double>();
+        lb = N;
+    }
+    if (hx) {
+        ST_TRY(dx.alloc(col * nrhs));
+        if (!out2)
+            HIP_TRY(hipMemcpy2DAsync(dx.p, col, X, sizeof(double) * ldx, col, nrhs, hipMemcpyHostToDevice, st));
+        Xd = dx.as<double>();
+        lx = N;
+    }
+    const askit_status rc = body(Bd, lb, Xd, lx);
+    if (rc == ASKIT_OK && hx && out2)
+        HIP_TRY(hipMemcpy2DAsync(X, sizeof(double) * ldx, Xd, col, col, nrhs, hipMemcpyDeviceToHost, st));
+    // the staging buffers are released only after the queued work is done
+    const hipError_t e = hipStreamSynchronize(st);
+    if (rc != ASKIT_OK) return rc;
+    HIP_TRY(e);
+    return ASKIT_OK;
+}
+
 static askit_status check_solve_args(askit_factor f, const double *B, int64_t ldb, int32_t nrhs, double *X,
                                      int64_t ldx) {
     if (!f) return fail(ASKIT_ERR_ARG, "NULL factor");
@@ -2294,12 +2378,11 @@ askit_status askit_solve(askit_factor f, const double *B, int64_t ldb, int32_t n
     hipStream_t st = (hipStream_t)stream;
     auto t0 = std::chrono::steady_clock::now();
     f->info = askit_solve_info{};
-    if (f->max_refine == 0) {
-        ST_TRY(apply_inverse(f, B, ldb, nrhs, X, ldx, false, st));
-        f->t_solve = ms_since(t0);
-        return ASKIT_OK;
-    }
-    ST_TRY(gmres_refine(f, B, ldb, nrhs, X, ldx, false, st));
+    ST_TRY(with_device_arrays(f->t->N, nrhs, B, ldb, X, ldx, true, st,
+                              [&](const double *Bd, int64_t lb, double *Xd, int64_t lx) {
+                                  if (f->max_refine == 0) return apply_inverse(f, Bd, lb, nrhs, Xd, lx, false, st);
+                                  return gmres_refine(f, Bd, lb, nrhs, Xd, lx, false, st);
+                              }));
     f->t_solve = ms_since(t0);
     return ASKIT_OK;
 }
@@ -2307,16 +2390,24 @@ askit_status askit_solve(askit_factor f, const double *B, int64_t ldb, int32_t n
 askit_status askit_solve_transpose(askit_factor f, const double *B, int64_t ldb, int32_t nrhs, double *X,
                                    int64_t ldx, void *stream) {
     ST_TRY(check_solve_args(f, B, ldb, nrhs, X, ldx));
+    hipStream_t st = (hipStream_t)stream;
     f->info = askit_solve_info{};
-    if (f->max_refine == 0) return apply_inverse(f, B, ldb, nrhs, X, ldx, true, (hipStream_t)stream);
-    return gmres_refine(f, B, ldb, nrhs, X, ldx, true, (hipStream_t)stream);
+    return with_device_arrays(f->t->N, nrhs, B, ldb, X, ldx, true, st,
+                              [&](const double *Bd, int64_t lb, double *Xd, int64_t lx) {
+                                  if (f->max_refine == 0) return apply_inverse(f, Bd, lb, nrhs, Xd, lx, true, st);
+                                  return gmres_refine(f, Bd, lb, nrhs, Xd, lx, true, st);
+                              });
 }
 
 askit_status askit_matvec(askit_factor f, int32_t which, const double *Xin, int64_t ldx, int32_t nrhs, double *Y,
                           int64_t ldy, void *stream) {
     ST_TRY(check_solve_args(f, Xin, ldx, nrhs, Y, ldy));
     if (which < 0 || which > 2) return fail(ASKIT_ERR_ARG, "which must be 0, 1 or 2");
-    return matvec_impl(f, which, Xin, ldx, nrhs, Y, ldy, (hipStream_t)stream);
+    hipStream_t st = (hipStream_t)stream;
+    return with_device_arrays(f->t->N, nrhs, Xin, ldx, Y, ldy, true, st,
+                              [&](const double *Xd, int64_t lxd, double *Yd, int64_t lyd) {
+                                  return matvec_impl(f, which, Xd, lxd, nrhs, Yd, lyd, st);
+                              });
 }
 
 askit_status askit_set_refinement(askit_factor f, int32_t max_refine, double refine_tol) {
@@ -2339,11 +2430,23 @@ askit_status askit_tree_set_bandwidth(askit_tree t, double h) {
     return ASKIT_OK;
 }
 
+static askit_status adjoint_impl(askit_factor f, const double *Xs, int64_t ldx, const double *Zs, int64_t ldz,
+                                 int32_t nrhs, double *dlambda, double *dh, hipStream_t st);
+
 askit_status askit_adjoint_scalars(askit_factor f, const double *Xs, const double *Zs, int64_t ld, int32_t nrhs,
                                    double *dlambda, double *dh, void *stream) {
     ST_TRY(check_solve_args(f, Xs, ld, nrhs, (double *)Zs, ld));
     if (!dlambda || !dh) return fail(ASKIT_ERR_ARG, "NULL output");
     hipStream_t st = (hipStream_t)stream;
+    // X and Z are both inputs here
+    return with_device_arrays(f->t->N, nrhs, Xs, ld, (double *)Zs, ld, false, st,
+                              [&](const double *Xd, int64_t lxd, double *Zd, int64_t lzd) {
+                                  return adjoint_impl(f, Xd, lxd, Zd, lzd, nrhs, dlambda, dh, st);
+                              });
+}
+
+static askit_status adjoint_impl(askit_factor f, const double *Xs, int64_t ldx, const double *Zs, int64_t ldz,
+                                 int32_t nrhs, double *dlambda, double *dh, hipStream_t st) {
     const int64_t N = f->t->N, NR = N * (int64_t)nrhs;
     if (f->R.bytes < sizeof(double) * NR || f->Dx.bytes < sizeof(double) * NR) {
         HIP_TRY(hipStreamSynchronize(st));
@@ -2351,7 +2454,7 @@ askit_status askit_adjoint_scalars(askit_factor f, const double *Xs, const doubl
         ST_TRY(f->Dx.alloc(sizeof(double) * NR));
     }
     double *Xc = f->Dx.as<double>(), *Y = f->R.as<double>();
-    HIP_TRY(hipMemcpy2DAsync(Xc, sizeof(double) * N, Xs, sizeof(double) * ld, sizeof(double) * N, nrhs,
+    HIP_TRY(hipMemcpy2DAsync(Xc, sizeof(double) * N, Xs, sizeof(double) * ldx, sizeof(double) * N, nrhs,
                              hipMemcpyDeviceToDevice, st));
     ST_TRY(matvec_impl(f, 1, Xc, N, nrhs, Y, N, st));
     // Zs may have a leading dimension above N: the dots read it through a
@@ -2361,7 +2464,7 @@ askit_status askit_adjoint_scalars(askit_factor f, const double *Xs, const doubl
         ST_TRY(f->Vk.alloc(sizeof(double) * NR));
     }
     double *Zc = f->Vk.as<double>();
-    HIP_TRY(hipMemcpy2DAsync(Zc, sizeof(double) * N, Zs, sizeof(double) * ld, sizeof(double) * N, nrhs,
+    HIP_TRY(hipMemcpy2DAsync(Zc, sizeof(double) * N, Zs, sizeof(double) * ldz, sizeof(double) * N, nrhs,
                              hipMemcpyDeviceToDevice, st));
     std::vector<double> zx, zy;
     ST_TRY(mdot(f, Zc, Xc, 1, nrhs, st, zx));
@@ -2501,6 +2604,17 @@ askit_status askit_batch_factorize(askit_batch b, void *stream) {
     if (!b) return fail(ASKIT_ERR_ARG, "NULL batch");
     HIP_TRY(hipGraphLaunch(b->fexec, (hipStream_t)stream));
     return ASKIT_OK;
+}
+
+askit_status askit_factorize_batched(askit_tree *trees, int32_t count, const double *lambdas, int32_t precision,
+                                     int32_t nrhs, void *stream, askit_batch *out) {
+    ST_TRY(askit_batch_create(trees, count, lambdas, precision, nrhs, out));
+    const askit_status rc = askit_batch_factorize(*out, stream);
+    if (rc != ASKIT_OK) {
+        askit_batch_destroy(*out);
+        *out = nullptr;
+    }
+    return rc;
 }
 
 askit_status askit_batch_check(askit_batch b, double *min_ratio, int32_t *problem, void *stream) {

@@ -204,8 +204,10 @@ struct SkelTask {
     int32_t *skel;         // out: s positions (-1 padded)
     int32_t *sr;           // out: rank
     int32_t *trunc;        // out: rank-guard flag
+    int32_t *qrows;        // out: rows of the sampled block the QR factors (numerically zero rows dropped)
     double *Pt;            // out: cmax x s row-major P_{C alpha~} (rows padded)
     double scale;          // -1 / (2 h^2)
+    double tol;            // adaptive rank: stop at |R_jj| < tol |R_00| (0: fixed rank)
 };
 
 // Work arrays of the split QRCP (several workgroups per node, one launch per

@@ -13,6 +13,8 @@
 //  * k_qrcp: column-pivoted Householder QR of that block, truncated at the
 //    rank s (trailing column norms recomputed at every step, largest norm
 //    first, lowest column on ties), the rank guard |R_jj| <= 1e-14 |R_00|,
+//    the adaptive rank rule |R_jj| < tol |R_00| when tol > 0 (the ratio of
+//    singular values of Sec. 2.1, estimated by R's diagonal),
 //    T = R11^{-1} R12 and the projection P = [I T] Pi^T, written transposed.
 #include "askit_dev.h"
 
@@ -367,21 +369,25 @@ __device__ inline Refl reflector_reg(PX x, int j, int rows, int lane, double (&x
 }
 
 // reflector of pivot step j, its Householder vector written to vh (v_j = 1
-// by the caller) unless the rank guard stops; returns whether it stops
+// by the caller) unless the rank rule stops; returns whether it stops
 template <typename PX>
-__device__ inline Refl reflector_to_lds(PX x, int j, int rows, int lane, double r00, double *vh, bool &stop);
+__device__ inline Refl reflector_to_lds(PX x, int j, int rows, int lane, double r00, double tol, double *vh,
+                                        bool &stop);
 
-__device__ inline bool guard_stop(int j, double beta, double r00) {
+// the rank is j when |R_jj| falls to the guard 1e-14 |R_00| or below
+// tol |R_00| (adaptive rank); a zero block stops at step 0 with rank 1
+__device__ inline bool guard_stop(int j, double beta, double r00, double tol) {
     const double r0 = j == 0 ? fabs(beta) : r00;
-    return (j > 0 && fabs(beta) <= kRankGuard * r0) || (j == 0 && r0 == 0.0);
+    return (j > 0 && (fabs(beta) <= kRankGuard * r0 || fabs(beta) < tol * r0)) || (j == 0 && r0 == 0.0);
 }
 
 template <typename PX>
-__device__ inline Refl reflector_to_lds(PX x, int j, int rows, int lane, double r00, double *vh, bool &stop) {
+__device__ inline Refl reflector_to_lds(PX x, int j, int rows, int lane, double r00, double tol, double *vh,
+                                        bool &stop) {
     if (rows - j <= 16 * kWave) {
         double xv[16];
         const Refl r = reflector_reg(x, j, rows, lane, xv);
-        stop = guard_stop(j, r.beta, r00);
+        stop = guard_stop(j, r.beta, r00, tol);
         if (!stop) {
 #pragma unroll
             for (int t = 0; t < 16; t++) {
@@ -392,7 +398,7 @@ __device__ inline Refl reflector_to_lds(PX x, int j, int rows, int lane, double 
         return r;
     }
     const Refl r = reflector(x, j, rows, lane);
-    stop = guard_stop(j, r.beta, r00);
+    stop = guard_stop(j, r.beta, r00, tol);
     if (!stop)
         for (int i = j + 1 + lane; i < rows; i += kWave) vh[i] = x[i] * r.sc;
     return r;
@@ -777,6 +783,7 @@ __global__ __launch_bounds__(kQrThreads) __attribute__((amdgpu_waves_per_eu(4)))
         return;
     }
     int rows = qr_row_select(t, M, ldm, ncand, vh, rmap, wcnt, red);
+    if (tid == 0) *glb(t.qrows) = rows;
     const int32_t *src = reinterpret_cast<const int32_t *>(vh);
     gen_rows(t, M, ldm, d, sl, ncand, src, rows, nrm, kQrMaxCols);  // nrm is free until the norms
     __syncthreads();
@@ -799,7 +806,7 @@ __global__ __launch_bounds__(kQrThreads) __attribute__((amdgpu_waves_per_eu(4)))
             const int k = pick_pivot(nrm, pos, j, ncand, lane);
             const int p = pos[k];
             bool stop;
-            const Refl r = reflector_to_lds(M + (int64_t)p * ldm, j, rows, lane, r00, vh, stop);
+            const Refl r = reflector_to_lds(M + (int64_t)p * ldm, j, rows, lane, r00, t.tol, vh, stop);
             if (stop) {
                 if (lane == 0) {
                     s_rank = j == 0 ? 1 : j;
@@ -902,6 +909,7 @@ __global__ __launch_bounds__(kQsThreads) void k_qs_init(const SkelTask *__restri
         st[3] = s < rows ? s : rows;
         st[4] = rows;
         st[5] = ncand;
+        *glb(t.qrows) = rows;
     }
 }
 
@@ -960,7 +968,8 @@ __global__ __launch_bounds__(kQsThreads) void k_qs_step(const SkelTask *__restri
         bk = kw == 0x7fffffff ? j : kw;  // no comparable norm (NaN): keep the order
         const int p = kw == 0x7fffffff ? pin[j] : __builtin_amdgcn_readlane(bc, (kw - j) & (kWave - 1));
         bool stop;
-        const Refl r = reflector_to_lds(M + (int64_t)p * ldm, j, rows, lane, j == 0 ? 0.0 : r00, vh, stop);
+        const Refl r = reflector_to_lds(M + (int64_t)p * ldm, j, rows, lane, j == 0 ? 0.0 : r00, tasks[node].tol, vh,
+                                        stop);
         if (lane == 0) {
             s_stop = stop;
             s_k = bk;

@@ -48,6 +48,8 @@ def test_argument_validation_without_gpu(lib):
         (100, 3, A.Options(64, 8, 0, 0, 0, 0, float("nan"))),
         (5000, 3, A.Options(1024, 8, 0, 0, 0, 0, 1.0)),  # leaf blocks above 512
         (100, 3, A.Options(64, 300, 0, 0, 0, 0, 1.0)),  # 2 s above 512
+        (100, 3, A.Options(64, 8, 0, 0, 0, 0, 1.0, -1e-3)),  # tol < 0
+        (100, 3, A.Options(64, 8, 0, 0, 0, 0, 1.0, 1.0)),    # tol >= 1
     ]
     for N, d, opt in bad:
         st = lib.askit_build_tree(fake, N, d, ctypes.byref(opt), None, ctypes.byref(out))

@@ -1,0 +1,222 @@
+"""GPU parity at the shapes of the benchmark workloads, with the GPU's own
+skeletons: the 1M workload's distribution, leaf size, rank and sample count
+at N = 65,536; the batched workload's problems at their own shape; the
+adaptive rank; the sampler where the complement barely exceeds the sample."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import colrel, oracle_skeletons, skeleton_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ak():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1701_02324_amd as ak
+    ak.load()
+    return ak
+
+
+def _cuda(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _import_into_oracle(o, ids, P, sizes, rank, cmax):
+    for node in range(1, o.nnodes):
+        sr, nc = int(sizes[2 * node]), int(sizes[2 * node + 1])
+        o.set_skeleton(node, ids[node * rank: node * rank + sr],
+                       P[node * rank * cmax: node * rank * cmax + sr * nc].reshape(sr, nc))
+
+
+def _colres(o, B, x):
+    return float(np.max(np.linalg.norm(B - o.matvec(x), axis=0) / np.linalg.norm(B, axis=0)))
+
+
+@pytest.fixture(scope="module")
+def c3(ak, orc):
+    """The 1M workload's distribution (32 clusters in 16-D, sigma ~ U[0.5, 2],
+    h = 2, lambda = 0.01, m = 512, s = 256, 1024 samples) at N = 65,536."""
+    c = synth.config(3, N=65536, nrhs=8)
+    say(f"[gpu headline] 1M-workload shape at N=65536: oracle tree and skeletons")
+    o = orc.Oracle(c["X"], c["m"], c["s"], c["h"], nsamp=c["nsamp"], seed=c["seed"])
+    o.build_tree()
+    o.skeletonize()
+    t = ak.Tree(_cuda(c["X"]), c["m"], c["s"], c["h"], n_samples=c["nsamp"], seed=c["seed"])
+    t.skeletonize()
+    yield dict(c=c, o=o, t=t)
+    t.close()
+
+
+def test_c3_tree_and_samples(c3):
+    c, o, t = c3["c"], c3["o"], c3["t"]
+    assert np.array_equal(_np(t.perm()), o.perm())
+    import oracle as orc_mod
+    samp = t.samples()
+    ranks, cands = t.skeleton_sizes()
+    n = 0
+    for node in range(1, t.nnodes):
+        if cands[node] <= t.s:
+            continue
+        b, e = o.node_range(node)
+        q = orc_mod.sample(c["seed"], 0, node, o.N, b, e, o.nsamp)
+        assert np.array_equal(samp[node, :len(q)], q), node
+        n += 1
+    say(f"  tree permutation bit-exact, samples identical on {n} nodes")
+
+
+def test_c3_skeletons(c3):
+    import oracle as orc_mod
+    c, o, t = c3["c"], c3["o"], c3["t"]
+    ids, P, sizes = t.export_skeletons()
+    rep = skeleton_parity(orc_mod, o, c["X"], c["h"], c["seed"], ids, P, sizes, t.s, t.cmax)
+    say(f"  skeletons: {rep['identical']}/{rep['compared']} compared nodes identical, {rep['near_tie']} near-ties, "
+        f"{rep['elementwise']} element-wise (worst |dP|/bar {rep['worst_dP_over_bar']:.2e}), "
+        f"worst ID residual excess {rep['worst_resid_excess']:.1e}; QR rows per level "
+        f"{[int(np.mean(r[r > 0])) if np.any(r > 0) else 0 for r in np.split(t.qr_rows(), [2 ** l - 1 for l in range(1, t.D + 1)])][1:]}")
+    assert not rep["failures"], rep["failures"][:5]
+    assert rep["identical"] >= (1 << t.D) // 2
+
+
+def test_c3_solve_on_gpu_skeletons(c3, ak, orc):
+    """GPU FP64 factorization and solve on the GPU's skeletons, against the
+    oracle factored on the same skeletons: the solution within 1e-10, or 10x
+    the spread of two FP64 orderings of the oracle (the paper's telescoping
+    and its push-through form) where the recursion amplifies rounding past
+    that; and the GPU solution's residual under the oracle's operator within
+    10x the oracle's own."""
+    c, t = c3["c"], c3["t"]
+    ids, P, sizes = t.export_skeletons()
+    B = c["B"]
+    f = t.factorize(c["lam"], ak.ASKIT_FP64)
+    x = _np(f.solve(_cuda(B)))
+    f.close()
+    o0 = orc.Oracle(c["X"], c["m"], c["s"], c["h"], nsamp=c["nsamp"], seed=c["seed"])
+    o0.build_tree()
+    o0.skeletonize()
+    _import_into_oracle(o0, ids, P, sizes, t.s, t.cmax)
+    o0.factorize(c["lam"], 2)
+    x2 = o0.solve(B)
+    o0.factorize(c["lam"], 0)
+    xo = o0.solve(B)
+    spread = colrel(x2, xo)
+    bar = max(1e-10, 10 * spread)
+    err = colrel(x, xo)
+    ro, rg = _colres(o0, B, xo), _colres(o0, B, x)
+    say(f"  solve vs oracle {err:.2e} (bar {bar:.1e}, spread {spread:.1e}); residual under the oracle's operator: "
+        f"GPU {rg:.2e}, oracle {ro:.2e}")
+    assert err < bar
+    assert rg < max(1e-10, 10 * ro)
+
+
+def test_adaptive_rank_matches_oracle(ak, orc):
+    """tau > 0 (Sec. 2.1): the GPU's ranks and skeletons follow the oracle's
+    rule |R_ss| < tau |R_00|, node by node."""
+    import oracle as orc_mod
+    X, B = synth.small(6000, 8, 6000, nrhs=2, kind="mixture", scale=3.0)
+    m, s, h, seed = 128, 48, 1.5, 11
+    for tau in (1e-3, 1e-6):
+        o = orc.Oracle(X, m, s, h, seed=seed, tol=tau)
+        o.build_tree()
+        o.skeletonize()
+        t = ak.Tree(_cuda(X), m, s, h, seed=seed, tol=tau)
+        t.skeletonize()
+        ids, P, sizes = t.export_skeletons()
+        rep = skeleton_parity(orc_mod, o, X, h, seed, ids, P, sizes, s, t.cmax, tau=tau)
+        r = sizes[2::2]
+        say(f"  tau {tau:g}: ranks {r.min()}-{r.max()} (mean {r.mean():.1f}); {rep['identical']}/{rep['compared']} "
+            f"identical, {rep['near_tie']} near-ties")
+        assert not rep["failures"], rep["failures"][:5]
+        assert r.max() < s  # the tolerance, not the cap, sets the ranks here
+        t.close()
+
+
+def test_sampler_complement_just_above_sample(ak, orc):
+    """Leaves whose complement holds one position more than the sample (874
+    of 875 drawn by rejection) and level-2 nodes whose complement is taken
+    whole: the GPU's rows, in draw order, against the oracle's."""
+    import oracle as orc_mod
+    X, _ = synth.small(1000, 3, 1000, kind="uniform")
+    m, s, h, seed, nsamp = 128, 16, 0.3, 5, 874
+    t = ak.Tree(_cuda(X), m, s, h, n_samples=nsamp, seed=seed)
+    o = orc.Oracle(X, m, s, h, nsamp=nsamp, seed=seed)
+    o.build_tree()
+    t.skeletonize()
+    samp = t.samples()
+    ranks, cands = t.skeleton_sizes()
+    full = partial = 0
+    for node in range(1, t.nnodes):
+        if cands[node] <= s:
+            continue
+        b, e = o.node_range(node)
+        q = orc_mod.sample(seed, 0, node, o.N, b, e, nsamp)
+        assert np.array_equal(samp[node, :len(q)], q), node
+        if o.N - (e - b) <= nsamp:
+            full += 1
+        else:
+            partial += 1
+            assert o.N - (e - b) == nsamp + 1
+    say(f"  {partial} nodes sampled with c = nsamp + 1, {full} with the whole complement")
+    assert partial == 8 and full >= 2
+
+
+def test_batched_at_workload_shape(ak, orc):
+    """Problems of the batched workload at its own shape (m = 128, s = 64,
+    256 samples, 8-D 4-cluster mixtures), with its largest size, its widest
+    bandwidth and its smallest lambda among them: batched FP64 factors and
+    solves on the oracle's skeletons against each problem's oracle."""
+    import torch
+    probs = synth.batched_problems(count=256)
+    # the largest N, the smallest lambda, the widest h, and three others
+    pick = {int(np.argmax([len(p["X"]) for p in probs])), int(np.argmin([p["lam"] for p in probs])),
+            int(np.argmax([p["h"] for p in probs])), 0, 1, 2}
+    sel = [probs[i] for i in sorted(pick)]
+    # the extreme corner of the workload's parameter box on the largest problem
+    big = dict(sel[0])
+    big.update(X=probs[int(np.argmax([len(p["X"]) for p in probs]))]["X"],
+               B=probs[int(np.argmax([len(p["X"]) for p in probs]))]["B"], h=2.0, lam=1e-3, problem=999)
+    sel.append(big)
+    say(f"[gpu headline] batched shape: N = {[len(p['X']) for p in sel]}, lambda = "
+        f"{[round(p['lam'], 4) for p in sel]}, h = {[round(p['h'], 2) for p in sel]}")
+    trees, oracles, bars = [], [], []
+    for p in sel:
+        t = ak.Tree(torch.as_tensor(p["X"], device="cuda"), p["m"], p["s"], p["h"], n_samples=p["nsamp"],
+                    seed=p["seed"], problem=p["problem"])
+        o = orc.Oracle(p["X"], p["m"], p["s"], p["h"], nsamp=p["nsamp"], seed=p["seed"], problem=p["problem"])
+        o.build_tree()
+        o.skeletonize()
+        o.factorize(p["lam"], 2)
+        x2 = o.solve(p["B"])
+        o.factorize(p["lam"], 0)
+        bars.append(max(1e-10, 10 * colrel(x2, o.solve(p["B"]))))
+        t.import_skeletons(*oracle_skeletons(o, t.s, t.cmax))
+        trees.append(t)
+        oracles.append(o)
+    batch = ak.Batch(trees, [p["lam"] for p in sel], ak.ASKIT_FP64, nrhs=8, factorize=True)
+    xs = batch.solve([torch.as_tensor(p["B"], device="cuda") for p in sel])
+    torch.cuda.synchronize()
+    for p, o, x, bar in zip(sel, oracles, xs, bars):
+        xo = o.solve(p["B"])
+        err = colrel(_np(x), xo)
+        rg, ro = _colres(o, p["B"], _np(x)), _colres(o, p["B"], xo)
+        say(f"  N={len(p['X'])} lambda={p['lam']:.1e} h={p['h']:.2f}: vs oracle {err:.1e} (bar {bar:.1e}), "
+            f"residual GPU {rg:.1e} oracle {ro:.1e}")
+        assert err < bar
+        assert rg < max(1e-10, 10 * ro)
+    batch.close()
+    for t in trees:
+        t.close()

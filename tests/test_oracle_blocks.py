@@ -142,6 +142,41 @@ def test_qrcp_rank_guard(orc):
     assert rank == 1 and piv[0] == 0 and np.all(T == 0)
 
 
+@pytest.mark.parametrize("tau", [1e-1, 1e-3, 1e-5, 1e-8])
+def test_qrcp_adaptive_rank_matches_lapack_diagonal(orc, tau):
+    # Sec. 2.1: the rank is the smallest s with sigma_{s+1} / sigma_1 < tau,
+    # the singular values estimated by the diagonal of the pivoted QR; the
+    # diagonal is LAPACK's (geqp3 through scipy) on a kernel block whose
+    # spectrum decays smoothly
+    rng = np.random.default_rng(11)
+    M = _kernel_block(rng, 200, 90, 0.45)
+    Q2, R2, P2 = sla.qr(M, pivoting=True, mode="economic")
+    dg = np.abs(np.diag(R2))
+    want = int(np.argmax(dg < tau * dg[0])) if np.any(dg < tau * dg[0]) else min(M.shape)
+    rank, piv, rd, T, R, tr = orc.qrcp(M, 80, tau)
+    assert rank == min(want, 80)
+    assert tr == (rank < 80)
+    assert list(piv[:rank]) == list(P2[:rank])
+    # the ID error is that of the truncated QR: ||M - M_skel P||_2 <= ||R22||_F;
+    # and with column pivoting every column of R22 is at most |R_ss| long, so
+    # sigma_{s+1}(M) <= ||R22||_2 <= sqrt(n - s) |R_ss|
+    P = np.zeros((rank, 90)); P[np.arange(rank), piv[:rank]] = 1.0; P[:, piv[rank:]] = T
+    err = np.linalg.norm(M - M[:, piv[:rank]] @ P, 2)
+    assert err <= np.linalg.norm(R2[rank:, rank:]) * (1 + 1e-8) + 1e-13 * np.linalg.norm(M)
+    sv = np.linalg.svd(M, compute_uv=False)
+    if rank < 80:
+        assert sv[rank] <= np.sqrt(90 - rank) * dg[rank] * (1 + 1e-8)
+
+
+def test_qrcp_adaptive_rank_zero_keeps_fixed_rank(orc):
+    rng = np.random.default_rng(12)
+    M = rng.standard_normal((50, 30))
+    a = orc.qrcp(M, 20)
+    b = orc.qrcp(M, 20, 0.0)
+    assert a[0] == b[0] == 20
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[3], b[3])
+
+
 def test_qrcp_ties_lowest_column(orc):
     # identical columns: the first pivot is the lowest position among maxima
     M = np.ones((6, 5)); M[:, 3] *= 2.0; M[:, 1] *= 2.0
