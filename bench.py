@@ -20,9 +20,8 @@ refinement); it is the headline only if that gate holds.
 The timed steps run without per-launch events.  Per-kernel times come from a
 separate pass of the same steps with HIP events around every launch
 (askit_profile_enable), and give the rooflines.  The oracle (plain C, OpenMP)
-is the CPU baseline: by default on a bounded sample of the workload, with
---cpu-full on the whole workload, where it also checks the GPU's tree,
-skeletons and FP64 solution.
+is the CPU baseline, timed on the whole workload (about 50 s on 16 cores);
+with --cpu-check it also checks the GPU's tree, skeletons and FP64 solution.
 """
 from __future__ import annotations
 
@@ -200,11 +199,12 @@ def main():
     ap.add_argument("--nrhs", type=int, default=64)
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision steps")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-full", action="store_true",
-                    help="run the oracle on the whole workload (several minutes on 16 cores) and check the GPU's "
-                         "tree, skeletons and FP64 solution against it")
-    ap.add_argument("--cpu-sample", type=int, default=262144,
-                    help="points of the oracle's bounded sample (without --cpu-full)")
+    ap.add_argument("--cpu-check", action="store_true",
+                    help="after the oracle's timed run on the whole workload, check the GPU's tree, skeletons and "
+                         "FP64 solution against it (about two minutes more on 16 cores)")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="time the oracle on the first CPU_SAMPLE points only, scaled by N log(N/m) (0: the "
+                         "whole workload)")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel profiled pass")
     ap.add_argument("--max-refine", type=int, default=60, help="GMRES-IR operator applications (mixed path)")
     ap.add_argument("--no-stable-check", action="store_true",
@@ -318,7 +318,7 @@ def main():
         f"{eps64:.2e}, refined {t_ref:.3f} s {info64}, min pivot ratio {pr64[0]:.2e}")
     ranks, cands = tree.skeleton_sizes()
     qrows = tree.qr_rows()
-    ids64, P64, sizes64 = tree.export_skeletons() if args.cpu_full else (None, None, None)
+    ids64, P64, sizes64 = tree.export_skeletons() if args.cpu_check else (None, None, None)
     f64.close()
 
     # --- per-kernel times: the same FP64 steps again, every launch between
@@ -398,10 +398,10 @@ def main():
         del xc, yc
 
     cpu = None
-    if args.cpu_full:
-        cpu = cpu_full_check(c, tree, ids64, P64, sizes64, x64, xref, args.cpu_rhs)
-    elif not args.no_cpu:
+    if args.cpu_sample:
         cpu = cpu_baseline(c, args.cpu_sample)
+    elif not args.no_cpu:
+        cpu = cpu_full_check(c, tree, ids64, P64, sizes64, x64, xref, args.cpu_rhs, args.cpu_check)
 
     out = {
         "metric": METRIC, "value": t_fac64, "unit": "s", "n_gpus": 1, "steps": args.steps,
@@ -538,7 +538,7 @@ def cpu_baseline(c, n_sample):
     sample of the workload: the first n_sample points of the mixture with the
     same d, m, s, h, lambda and sample count; its skeletonize + factorize time
     is scaled to N by the method's N log(N/m) work (Sec. 3, "Work").  The
-    whole workload takes several minutes on 16 cores (--cpu-full)."""
+    default run times the whole workload instead."""
     import oracle
     X = c["X"][:n_sample]
     m, s = c["m"], c["s"]
@@ -561,13 +561,14 @@ def cpu_baseline(c, n_sample):
                       f"{e - a:.2f} s measured, scaled by N log(N/m) to N={N} (depth {DN})"}
 
 
-def cpu_full_check(c, tree, ids, P, sizes, x64, xref, nrhs_check):
+def cpu_full_check(c, tree, ids, P, sizes, x64, xref, nrhs_check, check):
     """The oracle (plain C, OpenMP over the nodes of a level) on the whole
-    workload: its skeletonize + factorize time is the CPU baseline.  Then it
-    checks the GPU's results: the tree permutation bit for bit, the skeletons
-    node by node (pivots identical), and, factored on the GPU's own skeletons,
-    the GPU's FP64 direct and refined solutions of the first nrhs_check
-    right-hand sides against the oracle's solution and operator."""
+    workload: its skeletonize + factorize time is the CPU baseline.  With
+    `check` it then compares the GPU's results: the tree permutation bit for
+    bit, the skeletons node by node (pivots identical), and, factored on the
+    GPU's own skeletons, the GPU's FP64 direct and refined solutions of the
+    first nrhs_check right-hand sides against the oracle's solution and
+    operator."""
     import oracle
     X, B = c["X"], c["B"]
     N = X.shape[0]
@@ -586,6 +587,8 @@ def cpu_full_check(c, tree, ids, P, sizes, x64, xref, nrhs_check):
     out = {"value": g - b, "unit": "s", "cores": nth, "kind": "oracle",
            "sample": f"the whole workload (N={N}); skeletonize {e - b:.2f} s + factorize {g - e:.2f} s",
            "tree_s": b - a}
+    if not check:
+        return out
     check = {"perm_bit_exact": bool(np.array_equal(perm, tree.perm().cpu().numpy()))}
     # skeletons: identical pivot lists per node (internal nodes are compared
     # only where both children agree, since their candidates differ otherwise)
