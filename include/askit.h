@@ -260,6 +260,24 @@ askit_status askit_batch_solve(askit_batch b, const double *const *B, double *co
 askit_status askit_batch_factor(askit_batch b, int32_t i, askit_factor *f);
 void askit_batch_destroy(askit_batch b);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * permutation of askit_build_tree / askit_tree_perm (the same tree rules,
+ * the same kernels, bit-identical result) without building a tree handle.
+ * X: device, N x d row-major FP64 (finite; not checked here), perm: device,
+ * N int64 (perm[position] = original index).  Every temporary (node ranges,
+ * level partial sums, means, scatter matrices, axes, sort keys and their
+ * merge buffers) lives in one library-owned static device array of 64 MiB
+ * per device, kept until the process ends; no device memory is allocated or
+ * freed.  The temporaries of N points in d dimensions with leaf size m
+ * take about N (32 + 32 / m + 8 max(d, d (d + 1) / 2) / 256) bytes: N up to
+ * about 1.8M at d = 16, m = 512; larger inputs return ASKIT_ERR_ARG and
+ * enqueue nothing.
+ * Asynchronous on `stream`.  Calls that overlap on one device (other
+ * streams, other threads) race on the array: serialize them. */
+askit_status askit_tree_permutation_noalloc(const double *X, int64_t N, int32_t d, int32_t leaf_size,
+                                            int64_t *perm, void *stream);
+
 /* Per-phase timings (ms) and sizes of the last calls on a handle, as JSON. */
 askit_status askit_get_stats(askit_tree t, askit_factor f, char *json, size_t cap);
 

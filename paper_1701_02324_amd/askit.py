@@ -26,7 +26,7 @@ EXPORTED = [
     "askit_profile_report", "askit_tree_set_bandwidth", "askit_adjoint_scalars", "askit_skeletonize_batched",
     "askit_batch_create", "askit_batch_factorize", "askit_batch_check", "askit_batch_solve", "askit_batch_factor",
     "askit_batch_destroy", "askit_skeletonize_factorize", "askit_release_cached_memory",
-    "askit_factorize_batched", "askit_tree_qr_rows", "askit_tree_samples",
+    "askit_factorize_batched", "askit_tree_qr_rows", "askit_tree_samples", "askit_tree_permutation_noalloc",
 ]
 
 
@@ -67,6 +67,7 @@ def load(path: str = LIB_PATH):
     L.askit_tree_perm.argtypes = [_vp, _vp]
     L.askit_tree_qr_rows.argtypes = [_vp, _vp]
     L.askit_tree_samples.argtypes = [_vp, _vp]
+    L.askit_tree_permutation_noalloc.argtypes = [_vp, _i64, _i32, _i32, _vp, _vp]
     L.askit_skeletonize.argtypes = [_vp, _vp]
     L.askit_skeletons_export.argtypes = [_vp, _vp, _vp, _vp]
     L.askit_skeletons_import.argtypes = [_vp, _vp, _vp, _vp]
@@ -153,6 +154,20 @@ def askit_tree_perm(tree, N, device="cuda"):
     p = torch.empty(N, dtype=torch.int64, device=device)
     _check(load().askit_tree_perm(tree, _vp(p.data_ptr())))
     return p
+
+
+def askit_tree_permutation_noalloc(X, leaf_size, perm=None, stream=None):
+    """Tree permutation without any device allocation by the library (the
+    output buffer `perm`, int64 N on the device, may be passed in)."""
+    X = _dev64(X, "X")
+    if not X.is_contiguous():
+        raise ValueError("X must be contiguous")
+    N, d = X.shape
+    if perm is None:
+        perm = torch.empty(N, dtype=torch.int64, device=X.device)
+    _check(load().askit_tree_permutation_noalloc(_vp(X.data_ptr()), N, d, int(leaf_size), _vp(perm.data_ptr()),
+                                                 _stream(stream)))
+    return perm
 
 
 def askit_tree_qr_rows(tree, nnodes):

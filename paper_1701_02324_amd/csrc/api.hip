@@ -605,6 +605,88 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 
 }  // namespace
 
+// Temporaries of the tree build of N points in d dimensions at depth D, as
+// byte offsets into one arena (each array 256-byte aligned).
+struct TreeScratch {
+    size_t nb, ne, pa, pc, part, mu, S, axis, key, kid, key2, kid2, total;
+};
+static TreeScratch tree_scratch_layout(int64_t N, int d, int D) {
+    const int npair = d * (d + 1) / 2;
+    const int64_t nnodes = ((int64_t)2 << D) - 1;
+    int64_t part_max = 1;
+    for (int l = 0; l < D; l++) {
+        const int64_t cnt = (int64_t)1 << l, nmax = cdiv(N, cnt), maxch = cdiv(nmax, kTreeChunk);
+        part_max = std::max(part_max, cnt * maxch * std::max(d, npair));
+    }
+    const int64_t cnt_max = D > 0 ? ((int64_t)1 << (D - 1)) : 1;
+    TreeScratch L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    L.nb = take(sizeof(int64_t) * nnodes);
+    L.ne = take(sizeof(int64_t) * nnodes);
+    L.pa = take(sizeof(int16_t) * npair);
+    L.pc = take(sizeof(int16_t) * npair);
+    L.part = take(sizeof(double) * part_max);
+    L.mu = take(sizeof(double) * cnt_max * d);
+    L.S = take(sizeof(double) * cnt_max * d * d);
+    L.axis = take(sizeof(double) * cnt_max * d);
+    L.key = take(sizeof(double) * N);
+    L.kid = take(sizeof(int64_t) * N);
+    L.key2 = take(sizeof(double) * N);
+    L.kid2 = take(sizeof(int64_t) * N);
+    L.total = off;
+    return L;
+}
+
+// The levels of the tree build (Sec. 2.1, "Partitioning the matrix"): for
+// each level, chunk sums -> means -> scatter matrices -> principal axes ->
+// keys -> tile sort + merges -> the permutation reordered within every node.
+// perm holds the identity on entry and the tree order on exit; nb/ne are the
+// node ranges (heap order), pa/pc the index pairs of the scatter matrix; the
+// other pointers are temporaries sized as in tree_scratch_layout.
+static askit_status tree_levels(const double *X, int64_t N, int d, int D, int64_t *perm, const int64_t *nb,
+                                const int64_t *ne, const int16_t *pa, const int16_t *pc, double *part, double *mu,
+                                double *S, double *axis, double *key, int64_t *kid, double *key2, int64_t *kid2,
+                                hipStream_t st) {
+    const int npair = d * (d + 1) / 2;
+    for (int l = 0; l < D; l++) {
+        const int cnt = 1 << l;
+        const int64_t first = (((int64_t)1 << l) - 1), nmax = cdiv(N, cnt);
+        const int maxch = (int)cdiv(nmax, kTreeChunk);
+        hipLaunchKernelGGL(k_tree_chunk_mean, dim3(grid1((int64_t)cnt * maxch * d)), dim3(256), 0, st,
+                           X, perm, d, nb, ne, first, cnt, maxch, part);
+        hipLaunchKernelGGL(k_tree_mean, dim3(grid1((int64_t)cnt * d)), dim3(256), 0, st, nb, ne, first, cnt, maxch, d,
+                           part, mu);
+        hipLaunchKernelGGL(k_tree_chunk_scatter, dim3(grid1((int64_t)cnt * maxch * npair)), dim3(256), 0, st,
+                           X, perm, d, nb, ne, first, cnt, maxch, mu,
+                           pa, pc, npair, part);
+        hipLaunchKernelGGL(k_tree_scatter, dim3(grid1((int64_t)cnt * npair)), dim3(256), 0, st, nb, ne, first, cnt,
+                           maxch, d, pa, pc, npair, part, S);
+        hipLaunchKernelGGL(k_tree_axis, dim3(grid1(cnt, 64)), dim3(64), 0, st, cnt, d, S,
+                           axis);
+        const int bpn = (int)cdiv(nmax, 256);
+        hipLaunchKernelGGL(k_tree_keys, dim3(cnt * bpn), dim3(256), 0, st, X, perm, d,
+                           nb, ne, first, bpn, mu, axis, key, kid);
+        const int tpn = (int)cdiv(nmax, 1024);
+        hipLaunchKernelGGL(k_tree_sort_tiles, dim3(cnt * tpn), dim3(512), 0, st, nb, ne, first, tpn, key,
+                           kid);
+        double *ka = key, *kb2 = key2;
+        int64_t *ia = kid, *ib = kid2;
+        for (int64_t w = 1024; w < nmax; w *= 2) {
+            hipLaunchKernelGGL(k_tree_merge, dim3(cnt * bpn), dim3(256), 0, st, nb, ne, first, bpn, w, ka, ia, kb2, ib);
+            std::swap(ka, kb2);
+            std::swap(ia, ib);
+        }
+        hipLaunchKernelGGL(k_copy_ids, dim3(grid1(N)), dim3(256), 0, st, ia, perm, N);
+        HIP_TRY(hipGetLastError());
+    }
+    return ASKIT_OK;
+}
+
 // ---------------------------------------------------------------------------
 // handles
 // ---------------------------------------------------------------------------
@@ -811,38 +893,10 @@ askit_status askit_build_tree(const double *X, int64_t N, int32_t d, const askit
     HIP_TRY(hipMemsetAsync(bad.p, 0, sizeof(int32_t), st));
     hipLaunchKernelGGL(k_check_finite, dim3(grid1(N * d)), dim3(256), 0, st, t->X.as<double>(), N * d, bad.as<int32_t>());
     hipLaunchKernelGGL(k_iota, dim3(grid1(N)), dim3(256), 0, st, t->perm.as<int64_t>(), N);
-    const int64_t *nb = t->dnb.as<int64_t>(), *ne = t->dne.as<int64_t>();
-    for (int l = 0; l < t->D; l++) {
-        const int cnt = 1 << l;
-        const int64_t first = t->first(l), nmax = cdiv(N, cnt);
-        const int maxch = (int)cdiv(nmax, kTreeChunk);
-        hipLaunchKernelGGL(k_tree_chunk_mean, dim3(grid1((int64_t)cnt * maxch * d)), dim3(256), 0, st,
-                           t->X.as<double>(), t->perm.as<int64_t>(), d, nb, ne, first, cnt, maxch, part.as<double>());
-        hipLaunchKernelGGL(k_tree_mean, dim3(grid1((int64_t)cnt * d)), dim3(256), 0, st, nb, ne, first, cnt, maxch, d,
-                           part.as<double>(), mu.as<double>());
-        hipLaunchKernelGGL(k_tree_chunk_scatter, dim3(grid1((int64_t)cnt * maxch * npair)), dim3(256), 0, st,
-                           t->X.as<double>(), t->perm.as<int64_t>(), d, nb, ne, first, cnt, maxch, mu.as<double>(),
-                           dpa.as<int16_t>(), dpc.as<int16_t>(), npair, part.as<double>());
-        hipLaunchKernelGGL(k_tree_scatter, dim3(grid1((int64_t)cnt * npair)), dim3(256), 0, st, nb, ne, first, cnt,
-                           maxch, d, dpa.as<int16_t>(), dpc.as<int16_t>(), npair, part.as<double>(), S.as<double>());
-        hipLaunchKernelGGL(k_tree_axis, dim3(grid1(cnt, 64)), dim3(64), 0, st, cnt, d, S.as<double>(),
-                           axis.as<double>());
-        const int bpn = (int)cdiv(nmax, 256);
-        hipLaunchKernelGGL(k_tree_keys, dim3(cnt * bpn), dim3(256), 0, st, t->X.as<double>(), t->perm.as<int64_t>(), d,
-                           nb, ne, first, bpn, mu.as<double>(), axis.as<double>(), key.as<double>(), kid.as<int64_t>());
-        const int tpn = (int)cdiv(nmax, 1024);
-        hipLaunchKernelGGL(k_tree_sort_tiles, dim3(cnt * tpn), dim3(512), 0, st, nb, ne, first, tpn, key.as<double>(),
-                           kid.as<int64_t>());
-        double *ka = key.as<double>(), *kb2 = key2.as<double>();
-        int64_t *ia = kid.as<int64_t>(), *ib = kid2.as<int64_t>();
-        for (int64_t w = 1024; w < nmax; w *= 2) {
-            hipLaunchKernelGGL(k_tree_merge, dim3(cnt * bpn), dim3(256), 0, st, nb, ne, first, bpn, w, ka, ia, kb2, ib);
-            std::swap(ka, kb2);
-            std::swap(ia, ib);
-        }
-        hipLaunchKernelGGL(k_copy_ids, dim3(grid1(N)), dim3(256), 0, st, ia, t->perm.as<int64_t>(), N);
-        HIP_TRY(hipGetLastError());
-    }
+    ST_TRY(tree_levels(t->X.as<double>(), N, d, t->D, t->perm.as<int64_t>(), t->dnb.as<int64_t>(),
+                       t->dne.as<int64_t>(), dpa.as<int16_t>(), dpc.as<int16_t>(), part.as<double>(),
+                       mu.as<double>(), S.as<double>(), axis.as<double>(), key.as<double>(), kid.as<int64_t>(),
+                       key2.as<double>(), kid2.as<int64_t>(), st));
     hipLaunchKernelGGL(k_gather_points, dim3(grid1(N * d)), dim3(256), 0, st, t->X.as<double>(),
                        t->perm.as<int64_t>(), d, N, t->Xp.as<double>());
     ST_TRY(t->iperm.alloc(sizeof(int64_t) * N));
@@ -2672,3 +2726,60 @@ askit_status askit_get_stats(askit_tree t, askit_factor f, char *json, size_t ca
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free tree permutation.  Every temporary of the tree build lives
+// in this array: one copy per device, held until the process ends.  Host code
+// uses the device address hipGetSymbolAddress gives for the current device,
+// never the array's name.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<unsigned char *> g_scratch_ptr;  // per device ordinal
+
+askit_status scratch_of_current_device(unsigned char **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = (unsigned char *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return ASKIT_OK;
+}
+}  // namespace
+
+extern "C" askit_status askit_tree_permutation_noalloc(const double *X, int64_t N, int32_t d, int32_t leaf_size,
+                                                       int64_t *perm, void *stream) {
+    if (!X || !perm) return fail(ASKIT_ERR_ARG, "X or perm is NULL");
+    if (N < 1 || N >= (int64_t)1 << 31) return fail(ASKIT_ERR_ARG, "N must be in [1, 2^31)");
+    if (d < 1 || d > kMaxDim) return fail(ASKIT_ERR_ARG, "d must be in [1, 64]");
+    if (leaf_size < 2) return fail(ASKIT_ERR_ARG, "leaf_size must be >= 2");
+    int D = 0;
+    while ((int64_t)leaf_size * ((int64_t)1 << D) < N) D++;
+    const TreeScratch L = tree_scratch_layout(N, d, D);
+    if (L.total > kNoAllocScratchBytes)
+        return fail(ASKIT_ERR_ARG, "the tree build of " + std::to_string(N) + " points in " + std::to_string(d) +
+                                       "-D needs " + std::to_string(L.total) + " bytes of scratch; the allocation-free "
+                                       "entry point has " + std::to_string(kNoAllocScratchBytes));
+    unsigned char *w = nullptr;
+    ST_TRY(scratch_of_current_device(&w));
+    hipStream_t st = (hipStream_t)stream;
+    int64_t *nb = (int64_t *)(w + L.nb), *ne = (int64_t *)(w + L.ne);
+    int16_t *pa = (int16_t *)(w + L.pa), *pc = (int16_t *)(w + L.pc);
+    const int64_t nnodes = ((int64_t)2 << D) - 1;
+    const int npair = d * (d + 1) / 2;
+    hipLaunchKernelGGL(k_node_ranges, dim3(grid1(nnodes)), dim3(256), 0, st, nb, ne, N, D);
+    hipLaunchKernelGGL(k_pair_index, dim3(grid1(npair)), dim3(256), 0, st, pa, pc, d);
+    hipLaunchKernelGGL(k_iota, dim3(grid1(N)), dim3(256), 0, st, perm, N);
+    HIP_TRY(hipGetLastError());
+    return tree_levels(X, N, d, D, perm, nb, ne, pa, pc, (double *)(w + L.part), (double *)(w + L.mu),
+                       (double *)(w + L.S), (double *)(w + L.axis), (double *)(w + L.key), (int64_t *)(w + L.kid),
+                       (double *)(w + L.key2), (int64_t *)(w + L.kid2), st);
+}

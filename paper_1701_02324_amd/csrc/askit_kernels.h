@@ -26,6 +26,8 @@ __global__ void k_tree_merge(const int64_t *nb, const int64_t *ne, int64_t first
 __global__ void k_copy_ids(const int64_t *src, int64_t *dst, int64_t n);
 __global__ void k_gather_points(const double *X, const int64_t *perm, int d, int64_t N, double *Xp);
 __global__ void k_iota(int64_t *p, int64_t n);
+__global__ void k_node_ranges(int64_t *nb, int64_t *ne, int64_t N, int D);
+__global__ void k_pair_index(int16_t *pa, int16_t *pc, int d);
 __global__ void k_check_finite(const double *X, int64_t n, int32_t *bad);
 
 // skeletons (k_skel.hip)

@@ -253,6 +253,41 @@ __global__ void k_gather_points(const double *__restrict__ X, const int64_t *__r
     Xp[t] = X[perm[i] * d + k];
 }
 
+// node ranges of the complete tree of depth D over N positions (heap order):
+// from the root down, the left child takes floor(n / 2); one thread per node
+__global__ void k_node_ranges(int64_t *__restrict__ nb, int64_t *__restrict__ ne, int64_t N, int D) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= ((int64_t)2 << D) - 1) return;
+    int l = 0;
+    while ((((int64_t)2 << l) - 1) <= id) l++;
+    const int64_t j = id - (((int64_t)1 << l) - 1);
+    int64_t b = 0, n = N;
+    for (int k = l - 1; k >= 0; k--) {
+        if ((j >> k) & 1) {
+            b += n / 2;
+            n -= n / 2;
+        } else {
+            n /= 2;
+        }
+    }
+    nb[id] = b;
+    ne[id] = b + n;
+}
+
+// index pairs (a, c), a <= c, of the scatter matrix's upper triangle, row by
+// row: pair i -> (pa[i], pc[i])
+__global__ void k_pair_index(int16_t *__restrict__ pa, int16_t *__restrict__ pc, int d) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d * (d + 1) / 2) return;
+    int a = 0, first = 0;
+    while (first + (d - a) <= i) {
+        first += d - a;
+        a++;
+    }
+    pa[i] = (int16_t)a;
+    pc[i] = (int16_t)(a + (i - first));
+}
+
 __global__ void k_iota(int64_t *__restrict__ p, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = i;
