@@ -152,6 +152,25 @@ askit_status askit_skeletons_import(askit_tree t, const int32_t *ids, const doub
  * max|U_ii| of some block is below 1e-12. */
 askit_status askit_factorize(askit_tree t, double lambda, int32_t precision, void *stream, askit_factor *out);
 
+/* Hybrid solver (Sec. 2.3, "Fast hybrid solver"; Alg. HybridSolve, MatVecW,
+ * MatVecV) with the skeletonization frontier at tree level `level`
+ * (1 .. D): the frontier's nodes and their subtrees are factored as by
+ * askit_factorize (FP64); above the frontier nothing is compressed, so the
+ * matrix is lambda I + Ktilde with Ktilde_ab = P_{a a~} K_{a~ b} for any two
+ * frontier nodes a != b (level 1 gives askit_factorize's matrix, the root
+ * having no skeleton).  askit_solve on this factor runs HybridSolve:
+ * v = D^{-1} u up to the frontier, t = V v, the reduced system
+ * (I + V W) y = t of order sum_a s_a (at most 2^level * rank) by restarted
+ * GMRES with V (kernel summations) and W (the frontier's Phat) applied
+ * matrix-free, then x = v - W y.  askit_set_refinement sets that GMRES's
+ * iteration cap (default 2000; restarts every 1024) and relative residual target (default
+ * 1e-12); askit_last_solve_info reports it.  askit_matvec (which 0 and 1)
+ * applies the same restricted matrix; the transpose solve and which = 2 are
+ * not available (ASKIT_ERR_STATE).  Errors: ASKIT_ERR_STATE before
+ * askit_skeletonize, ASKIT_ERR_ARG for level outside [1, D] or a bad
+ * lambda; pivot ratios as for askit_factorize (frontier subtrees only). */
+askit_status askit_factorize_hybrid(askit_tree t, double lambda, int32_t level, void *stream, askit_factor *out);
+
 /* askit_skeletonize followed by askit_factorize (Alg. 1 then Alg. 2) as one
  * call, with the same results bit for bit.  The factorization of height h
  * needs only the skeletons of heights <= h, so it runs on a library-owned

@@ -63,6 +63,11 @@ def lib():
         L.orc_get_depth.argtypes = [ctypes.c_void_p]
         L.orc_set_h.argtypes = [ctypes.c_void_p, ctypes.c_double]
         L.orc_set_tol.argtypes = [ctypes.c_void_p, ctypes.c_double]
+        L.orc_set_level.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.orc_reduced_ratio.argtypes = [ctypes.c_void_p]
+        L.orc_reduced_ratio.restype = ctypes.c_double
+        L.orc_reduced_order.argtypes = [ctypes.c_void_p]
+        L.orc_reduced_order.restype = _i64
         L.orc_get_perm.argtypes = [ctypes.c_void_p, _lp]
         L.orc_node_range.argtypes = [ctypes.c_void_p, _i64, _lp, _lp]
         L.orc_skel_info.argtypes = [ctypes.c_void_p, _i64, _ip, _ip, _ip]
@@ -296,6 +301,20 @@ class Oracle:
             b, e = self.node_range(node)
             return np.arange(b, e, dtype=np.int64)
         return np.concatenate([self.skeleton(2 * node + 1)[0], self.skeleton(2 * node + 2)[0]])
+
+    # level restriction (hybrid solver, Sec. 2.3) ------------------------------
+    def set_level(self, L):
+        """Frontier at level L (0: the full method).  Above it nothing is
+        compressed; factorize() then factors the frontier's subtrees and the
+        reduced system I + V W, solve() runs HybridSolve, matvec() and
+        dense() apply that matrix."""
+        if lib().orc_set_level(self._h, int(L)):
+            raise ValueError("level must be in [0, D]")
+        self.level = int(L)
+
+    def reduced_system(self):
+        """(order of I + V W, its pivot ratio) after a factorization with a level restriction."""
+        return lib().orc_reduced_order(self._h), lib().orc_reduced_ratio(self._h)
 
     # factorization -----------------------------------------------------------
     def factorize(self, lam, variant=0):

@@ -69,6 +69,13 @@ typedef struct {
     int **piv;              /* row interchanges of the LU                  */
     double **Phat;          /* non-root: n_alpha x s_alpha row-major       */
     double *pivratio;       /* min|U_ii| / max|U_ii| per factored block    */
+    /* level restriction (hybrid solver): 0 = none; L >= 1 = frontier level */
+    int hybL;
+    int64_t hM;             /* order of the reduced system I + V W          */
+    int64_t *hoff;          /* row offset of each frontier node in it       */
+    double *hLU;            /* its LU (row-major) and pivots                */
+    int *hpiv;
+    double hratio;
 } orc_t;
 
 static int level_of(int64_t id) {
@@ -165,6 +172,8 @@ static void free_factor(orc_t *o) {
         free(o->LU[i]); free(o->piv[i]); free(o->Phat[i]);
         o->LU[i] = NULL; o->piv[i] = NULL; o->Phat[i] = NULL;
     }
+    free(o->hoff); free(o->hLU); free(o->hpiv);
+    o->hoff = NULL; o->hLU = NULL; o->hpiv = NULL;
     o->factored = 0;
 }
 
@@ -826,12 +835,49 @@ static int factor_internal(orc_t *o, int64_t id, int variant, int par) {
     return ORC_OK;
 }
 
+/* Reduced system of the hybrid solver (Sec. 2.3, "Fast hybrid solver").
+ * With the frontier A at level L, D = blockdiag(lambda I + Ktilde_aa),
+ * U = blockdiag(P_{a a~}) and V_{ab} = K_{a~ b} (a != b, zero on the
+ * diagonal), so that lambda I + Ktilde = D + U V = D (I + W V), W = D^{-1} U
+ * = blockdiag(Phat_a).  Z = I + V W has the blocks K_{a~ b} Phat_b (a != b)
+ * and the identity on the diagonal; the oracle assembles and LU-factors it
+ * (the method solves it iteratively). */
+static int factor_reduced(orc_t *o) {
+    int L = o->hybL;
+    int64_t f = first_at(L), cnt = (int64_t)1 << L;
+    o->hoff = (int64_t *)malloc(sizeof(int64_t) * (cnt + 1));
+    o->hoff[0] = 0;
+    for (int64_t j = 0; j < cnt; j++) o->hoff[j + 1] = o->hoff[j] + o->sr[f + j];
+    int64_t M = o->hM = o->hoff[cnt];
+    double *Z = (double *)calloc((size_t)M * M, sizeof(double));
+    for (int64_t i = 0; i < M; i++) Z[i * M + i] = 1.0;
+#pragma omp parallel for schedule(dynamic) collapse(2)
+    for (int64_t a = 0; a < cnt; a++)
+        for (int64_t b = 0; b < cnt; b++) {
+            if (a == b) continue;
+            int64_t ia = f + a, ib = f + b, nb = o->ne[ib] - o->nb[ib];
+            int sa = o->sr[ia], sb = o->sr[ib];
+            double *Kab = kblock_skel(o, ia, o->nb[ib], o->ne[ib], 0, 0);
+            double *blk = (double *)malloc(sizeof(double) * sa * sb);
+            mm(Kab, o->Phat[ib], blk, sa, nb, sb, 0);
+            for (int i = 0; i < sa; i++)
+                for (int k = 0; k < sb; k++) Z[(o->hoff[a] + i) * M + o->hoff[b] + k] = blk[(int64_t)i * sb + k];
+            free(Kab); free(blk);
+        }
+    o->hpiv = (int *)malloc(sizeof(int) * (M ? M : 1));
+    o->hratio = orc_lu(Z, (int)M, o->hpiv);
+    o->hLU = Z;
+    return ORC_OK;
+}
+
 int orc_factorize(orc_t *o, double lambda, int variant) {
     if (!o->skel_built) return ORC_ERR_STATE;
     if (!(lambda >= 0.0) || variant < 0 || variant > 2) return ORC_ERR_ARG;
     free_factor(o);
     o->lambda = lambda;
-    for (int l = o->D; l >= 0; l--) {
+    /* with a level restriction only the frontier's subtrees are factored */
+    int top = o->hybL > 0 ? o->hybL : 0;
+    for (int l = o->D; l >= top; l--) {
         int64_t f = first_at(l), cnt = (int64_t)1 << l;
         int inner = cnt < 8; /* few nodes: parallelise inside the node */
 #pragma omp parallel for schedule(dynamic) if (!inner)
@@ -840,9 +886,24 @@ int orc_factorize(orc_t *o, double lambda, int variant) {
             else factor_internal(o, f + j, variant, inner);
         }
     }
+    if (o->hybL > 0) factor_reduced(o);
     o->factored = 1;
     return ORC_OK;
 }
+
+/* Level restriction (Sec. 2.3): L = 0 keeps the full method; 1 <= L <= D
+ * puts the skeletonization frontier at level L.  Nodes above it are not
+ * compressed: for frontier nodes a != b, Ktilde_ab = P_{a a~} K_{a~ b}.
+ * L = 1 gives the full method's matrix (the root has no skeleton).  The
+ * factorization is dropped. */
+int orc_set_level(orc_t *o, int L) {
+    if (L < 0 || L > o->D || (L > 0 && o->D < 1)) return ORC_ERR_ARG;
+    free_factor(o);
+    o->hybL = L;
+    return ORC_OK;
+}
+double orc_reduced_ratio(const orc_t *o) { return o->hLU ? o->hratio : 1.0; }
+int64_t orc_reduced_order(const orc_t *o) { return o->hLU ? o->hM : 0; }
 
 void orc_get_phat(const orc_t *o, int64_t id, double *out) {
     memcpy(out, o->Phat[id], sizeof(double) * (o->ne[id] - o->nb[id]) * o->sr[id]);
@@ -871,15 +932,45 @@ static void from_pos(const orc_t *o, const double *u, double *Xo, int64_t ldx, i
 }
 
 /* x = (lambda I + Ktilde)^{-1} b: leaf LU solves, then one node step per
- * level from the leaves up (Alg. 3 with do_recur on the root, level by level) */
+ * level from the leaves up (Alg. 3 with do_recur on the root, level by level).
+ * With a level restriction (Alg. HybridSolve): v = D^{-1} u by the node
+ * steps up to the frontier, t = V v (MatVecV: t_a = sum_{b != a} K_{a~ b}
+ * v_b), y = Z^{-1} t, x = v - W y (MatVecW: x_b -= Phat_b y_b). */
 int orc_solve(const orc_t *o, const double *B, int64_t ldb, int nrhs, double *Xo, int64_t ldx) {
     if (!o->factored) return ORC_ERR_STATE;
     double *u = to_pos(o, B, ldb, nrhs);
-    for (int l = o->D; l >= 0; l--) {
+    int top = o->hybL > 0 ? o->hybL : 0;
+    for (int l = o->D; l >= top; l--) {
         int64_t f = first_at(l), cnt = (int64_t)1 << l;
         int inner = cnt < 8;
 #pragma omp parallel for schedule(dynamic) if (!inner)
         for (int64_t j = 0; j < cnt; j++) solve_node(o, f + j, u + o->nb[f + j] * nrhs, nrhs, 0, inner);
+    }
+    if (o->hybL > 0) {
+        int64_t f = first_at(o->hybL), cnt = (int64_t)1 << o->hybL, M = o->hM;
+        double *t = (double *)calloc((size_t)M * nrhs, sizeof(double));
+#pragma omp parallel for schedule(dynamic)
+        for (int64_t a = 0; a < cnt; a++)
+            for (int64_t b = 0; b < cnt; b++) {
+                if (a == b) continue;
+                int64_t ia = f + a, ib = f + b, nb = o->ne[ib] - o->nb[ib];
+                double *Kab = kblock_skel(o, ia, o->nb[ib], o->ne[ib], 0, 0);
+                double *tb = (double *)malloc(sizeof(double) * o->sr[ia] * nrhs);
+                mm(Kab, u + o->nb[ib] * nrhs, tb, o->sr[ia], nb, nrhs, 0);
+                for (int64_t i = 0; i < (int64_t)o->sr[ia] * nrhs; i++) t[o->hoff[a] * nrhs + i] += tb[i];
+                free(Kab); free(tb);
+            }
+        orc_lu_solve(o->hLU, o->hpiv, (int)M, t, nrhs);
+#pragma omp parallel for schedule(dynamic)
+        for (int64_t b = 0; b < cnt; b++) {
+            int64_t ib = f + b, nb = o->ne[ib] - o->nb[ib];
+            double *w = (double *)malloc(sizeof(double) * nb * nrhs);
+            mm(o->Phat[ib], t + o->hoff[b] * nrhs, w, nb, o->sr[ib], nrhs, 0);
+            double *ub = u + o->nb[ib] * nrhs;
+            for (int64_t i = 0; i < nb * nrhs; i++) ub[i] = ub[i] - w[i];
+            free(w);
+        }
+        free(t);
     }
     from_pos(o, u, Xo, ldx, nrhs);
     free(u);
@@ -891,7 +982,7 @@ int orc_solve(const orc_t *o, const double *B, int64_t ldb, int nrhs, double *Xo
  *   Ktilde_aa^{-T} = D^{-T} (I - V^T Z^{-T} W^T),
  * applied from the root down, then the transposed leaf solves. */
 int orc_solve_t(const orc_t *o, const double *B, int64_t ldb, int nrhs, double *Xo, int64_t ldx) {
-    if (!o->factored) return ORC_ERR_STATE;
+    if (!o->factored || o->hybL > 0) return ORC_ERR_STATE;
     double *g = to_pos(o, B, ldb, nrhs);
     for (int lv = 0; lv <= o->D; lv++) {
         int64_t f = first_at(lv), cnt = (int64_t)1 << lv;
@@ -943,7 +1034,9 @@ int orc_solve_t(const orc_t *o, const double *B, int64_t ldb, int nrhs, double *
 /*   push c down: [c_l~; c_r~] += P_c c_beta (telescoping, eq. (9));        */
 /*   leaves: y_a += P_{alpha~ alpha}^T c_a.                                  */
 /* which = 0: lambda I + Ktilde; which = 1: dKtilde/dh with the skeletons   */
-/* and projections held fixed (no lambda).                                   */
+/* and projections held fixed (no lambda).  With a level restriction at L   */
+/* (Sec. 2.3) the nodes above the frontier add no potentials; instead each  */
+/* frontier node a gets c_a = sum_{b != a} K_{a~ b} x_b, pushed down from L. */
 /* ------------------------------------------------------------------------ */
 
 int orc_matvec(const orc_t *o, int which, const double *Xin, int64_t ldx, int nrhs, double *Y, int64_t ldy) {
@@ -963,8 +1056,21 @@ int orc_matvec(const orc_t *o, int which, const double *Xin, int64_t ldx, int nr
                 for (int q = 0; q < nrhs; q++) y[i * nrhs + q] += a * x[k * nrhs + q];
             }
     }
-    /* skeleton potentials */
-    for (int lv = 0; lv < o->D; lv++) {
+    /* skeleton potentials (with a level restriction: below the frontier,
+     * plus every frontier node's potential from all other frontier nodes) */
+    int top = o->hybL > 0 ? o->hybL : 0;
+    if (top > 0) {
+        int64_t f = first_at(top), cnt = (int64_t)1 << top;
+#pragma omp parallel for schedule(dynamic)
+        for (int64_t a = 0; a < cnt; a++)
+            for (int k = 0; k < o->sr[f + a]; k++)
+                for (int64_t i = 0; i < o->N; i++) {
+                    if (i >= o->nb[f + a] && i < o->ne[f + a]) continue;
+                    double kv = kpos(o, o->skel[f + a][k], i, which);
+                    for (int q = 0; q < nrhs; q++) c[f + a][(int64_t)k * nrhs + q] += kv * x[i * nrhs + q];
+                }
+    }
+    for (int lv = top; lv < o->D; lv++) {
         int64_t f = first_at(lv), cnt = (int64_t)1 << lv;
 #pragma omp parallel for schedule(dynamic)
         for (int64_t j = 0; j < cnt; j++) {
@@ -982,7 +1088,7 @@ int orc_matvec(const orc_t *o, int which, const double *Xin, int64_t ldx, int nr
         }
     }
     /* push down through the internal projections */
-    for (int lv = 1; lv < o->D; lv++) {
+    for (int lv = top > 1 ? top : 1; lv < o->D; lv++) {
         int64_t f = first_at(lv), cnt = (int64_t)1 << lv;
 #pragma omp parallel for schedule(dynamic)
         for (int64_t j = 0; j < cnt; j++) {
@@ -1018,7 +1124,9 @@ int orc_matvec(const orc_t *o, int which, const double *Xin, int64_t ldx, int nr
  * lambda I + Ktilde (which = 0) or dKtilde/dh (which = 1), block by block:
  * leaf diagonal blocks exact; for every internal alpha the off-diagonal
  * blocks P_{l l~} K_{l~ r} and P_{r r~} K_{r~ l} of eq. (6), with the
- * telescoped projections of eq. (9). */
+ * telescoped projections of eq. (9).  With a level restriction at L, the
+ * internal nodes above the frontier are replaced by the blocks
+ * P_{a a~} K_{a~ b} between every two frontier nodes a != b. */
 int orc_dense(const orc_t *o, int which, double *A) {
     if (!o->skel_built) return ORC_ERR_STATE;
     int64_t N = o->N;
@@ -1030,7 +1138,24 @@ int orc_dense(const orc_t *o, int which, double *A) {
             for (int64_t k = b; k < e; k++)
                 A[o->perm[i] * N + o->perm[k]] = kpos(o, i, k, which) + ((i == k && !which) ? o->lambda : 0.0);
     }
-    for (int64_t id = 0; id < fl; id++) {
+    int top = o->hybL > 0 ? o->hybL : 0;
+    if (top > 0) { /* frontier pairs: P_{a a~} K_{a~ b} */
+        int64_t f = first_at(top), cnt = (int64_t)1 << top;
+        for (int64_t a = f; a < f + cnt; a++)
+            for (int64_t bb = f; bb < f + cnt; bb++) {
+                if (a == bb) continue;
+                int64_t na = o->ne[a] - o->nb[a], nbb = o->ne[bb] - o->nb[bb];
+                double *Pa = telescoped_P(o, a);
+                double *Kb = kblock_skel(o, a, o->nb[bb], o->ne[bb], which, 1);
+                double *blk = (double *)malloc(sizeof(double) * na * nbb);
+                mm(Pa, Kb, blk, na, o->sr[a], nbb, 1);
+                for (int64_t i = 0; i < na; i++)
+                    for (int64_t k = 0; k < nbb; k++)
+                        A[o->perm[o->nb[a] + i] * N + o->perm[o->nb[bb] + k]] = blk[i * nbb + k];
+                free(Pa); free(Kb); free(blk);
+            }
+    }
+    for (int64_t id = top > 0 ? first_at(top) : 0; id < fl; id++) {
         int64_t l = 2 * id + 1, r = 2 * id + 2;
         for (int side = 0; side < 2; side++) {
             int64_t a = side ? r : l, bb = side ? l : r; /* rows of a, columns of bb */

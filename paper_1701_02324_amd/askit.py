@@ -27,6 +27,7 @@ EXPORTED = [
     "askit_batch_create", "askit_batch_factorize", "askit_batch_check", "askit_batch_solve", "askit_batch_factor",
     "askit_batch_destroy", "askit_skeletonize_factorize", "askit_release_cached_memory",
     "askit_factorize_batched", "askit_tree_qr_rows", "askit_tree_samples", "askit_tree_permutation_noalloc",
+    "askit_factorize_hybrid",
 ]
 
 
@@ -73,6 +74,7 @@ def load(path: str = LIB_PATH):
     L.askit_skeletons_import.argtypes = [_vp, _vp, _vp, _vp]
     L.askit_factorize.argtypes = [_vp, ctypes.c_double, _i32, _vp, ctypes.POINTER(_vp)]
     L.askit_skeletonize_factorize.argtypes = [_vp, ctypes.c_double, _i32, _vp, ctypes.POINTER(_vp)]
+    L.askit_factorize_hybrid.argtypes = [_vp, ctypes.c_double, _i32, _vp, ctypes.POINTER(_vp)]
     for f in ("askit_solve", "askit_solve_transpose"):
         getattr(L, f).argtypes = [_vp, _vp, _i64, _i32, _vp, _i64, _vp]
     L.askit_matvec.argtypes = [_vp, _i32, _vp, _i64, _i32, _vp, _i64, _vp]
@@ -222,6 +224,13 @@ def askit_factorize(tree, lam, precision=ASKIT_FP64, stream=None):
 def askit_skeletonize_factorize(tree, lam, precision=ASKIT_FP64, stream=None):
     out = _vp()
     st = load().askit_skeletonize_factorize(tree, float(lam), int(precision), _stream(stream), ctypes.byref(out))
+    _check(st, allow_warn=True)
+    return out, st
+
+
+def askit_factorize_hybrid(tree, lam, level, stream=None):
+    out = _vp()
+    st = load().askit_factorize_hybrid(tree, float(lam), int(level), _stream(stream), ctypes.byref(out))
     _check(st, allow_warn=True)
     return out, st
 
@@ -381,6 +390,10 @@ class Tree:
         """skeletonize() then factorize(), pipelined over two streams."""
         return Factor(self, lam, precision, stream, fused=True)
 
+    def factorize_hybrid(self, lam, level, stream=None):
+        """Level-restricted factorization; solve() then runs the hybrid solver."""
+        return Factor(self, lam, ASKIT_FP64, stream, level=level)
+
     def set_bandwidth(self, h):
         """Bandwidth of subsequent factorizations (skeletons frozen)."""
         askit_tree_set_bandwidth(self.handle, h)
@@ -403,12 +416,16 @@ class Tree:
 class Factor:
     """Factorization of lambda I + Ktilde on a skeletonized tree."""
 
-    def __init__(self, tree, lam, precision=ASKIT_FP64, stream=None, fused=False):
+    def __init__(self, tree, lam, precision=ASKIT_FP64, stream=None, fused=False, level=0):
         self.tree = tree
         self.lam = float(lam)
         self.precision = precision
-        make = askit_skeletonize_factorize if fused else askit_factorize
-        self.handle, self.status = make(tree.handle, lam, precision, stream)
+        self.level = int(level)
+        if level:
+            self.handle, self.status = askit_factorize_hybrid(tree.handle, lam, level, stream)
+        else:
+            make = askit_skeletonize_factorize if fused else askit_factorize
+            self.handle, self.status = make(tree.handle, lam, precision, stream)
 
     def solve(self, B, stream=None):
         return askit_solve(self.handle, B, stream)

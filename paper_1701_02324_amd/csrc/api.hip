@@ -732,6 +732,14 @@ struct askit_factor_s {
     double min_ratio = 1.0;
     int min_node = -1;
     double t_factor = 0, t_solve = 0;
+    // level restriction (hybrid solver): frontier level L >= 1, or 0 for the
+    // full direct factorization.  The reduced system I + V W has order hM;
+    // frontier node j (heap id first(L) + j) owns its rows hoff[j] ..
+    int hyb = 0;
+    int64_t hM = 0;
+    std::vector<int64_t> hoff;
+    DBuf HZ, HT, HK, HR, HU, hws;  // N x cap scratch, reduced-system vectors, Krylov basis, V partials
+    std::unique_ptr<Plan> hv_w, hv_z, hw_store, hw_sub;
     void *ph(int level) const { return PH[level - 1]->p; }
     size_t elem() const { return prec == P64 ? 8 : 4; }
     double *lu_of(int64_t id) const {
@@ -1476,7 +1484,9 @@ static int factor_height_max(const std::vector<askit_factor> &fs) {
 }
 
 static askit_status factor_plan(const std::vector<askit_factor> &fs, Plan &P) {
-    for (int part = -1; part <= factor_height_max(fs); part++) ST_TRY(factor_plan_part(fs, P, part));
+    // with a level restriction only the frontier's subtrees are factored
+    const int top = (fs.size() == 1 && fs[0]->hyb) ? fs[0]->t->D - fs[0]->hyb : factor_height_max(fs);
+    for (int part = -1; part <= top; part++) ST_TRY(factor_plan_part(fs, P, part));
     return ASKIT_OK;
 }
 
@@ -1532,7 +1542,7 @@ static askit_status factor_ratio(askit_factor f, hipStream_t st) {
     HIP_TRY(hipStreamSynchronize(st));
     f->min_ratio = 1.0;
     f->min_node = -1;
-    for (int64_t id = 0; id < t->nnodes; id++) {
+    for (int64_t id = f->hyb ? t->first(f->hyb) : 0; id < t->nnodes; id++) {
         if (ratio[id] < f->min_ratio) {
             f->min_ratio = ratio[id];
             f->min_node = (int)id;
@@ -1676,6 +1686,38 @@ askit_status askit_factorize(askit_tree t, double lambda, int32_t precision, voi
     return st;
 }
 
+askit_status askit_factorize_hybrid(askit_tree t, double lambda, int32_t level, void *stream, askit_factor *out) {
+    if (!out) return fail(ASKIT_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!t) return fail(ASKIT_ERR_ARG, "NULL tree");
+    if (!t->skel_ok) return fail(ASKIT_ERR_STATE, "skeletonize first");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(ASKIT_ERR_ARG, "lambda must be finite and >= 0");
+    if (level < 1 || level > t->D) return fail(ASKIT_ERR_ARG, "level must be in [1, D]");
+    hipStream_t st = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    std::unique_ptr<askit_factor_s> f;
+    ST_TRY(factor_alloc(t, lambda, ASKIT_FP64, f));
+    f->hyb = level;
+    f->hoff.assign((size_t)1 << level, 0);
+    int64_t M = 0;
+    for (int64_t id = t->first(level); id < t->first(level + 1); id++) {
+        f->hoff[id - t->first(level)] = M;
+        M += t->hsr[id];
+    }
+    f->hM = M;
+    f->max_refine = 2000;
+    f->refine_tol = 1e-12;
+    Plan P;
+    P.tag = "factor";
+    ST_TRY(factor_plan({f.get()}, P));
+    HIP_TRY(P.run(st, t->s));
+    ST_TRY(factor_ratio(f.get(), st));
+    f->t_factor = ms_since(t0);
+    t->refs++;
+    *out = f.release();
+    return ratio_status(*out);
+}
+
 void askit_factor_destroy(askit_factor f) {
     if (!f) return;
     f->t->refs--;
@@ -1715,6 +1757,136 @@ static askit_status ensure_cap(askit_factor f, int nrhs) {
     f->mv_plan[0].reset();
     f->mv_plan[1].reset();
     f->mv_plan[2].reset();
+    f->hv_w.reset();
+    f->hv_z.reset();
+    f->hw_store.reset();
+    f->hw_sub.reset();
+    f->hws.release();
+    return ASKIT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Hybrid solver (Sec. 2.3, "Fast hybrid solver"; Alg. HybridSolve, MatVecW,
+// MatVecV).  The frontier A is the level L: its nodes and their subtrees are
+// skeletonized and factored as usual; above it nothing is compressed, so for
+// frontier nodes a != b, Ktilde_ab = P_{a a~} K_{a~ b}.  Then lambda I +
+// Ktilde = D (I + W V) with D = blockdiag(lambda I + Ktilde_aa), W =
+// blockdiag(Phat_a) and V_ab = K_{a~ b} (a != b), and
+//   x = v - W y,  v = D^{-1} u,  (I + V W) y = V v,
+// the reduced system of order sum_a s_a solved by GMRES with V and W applied
+// matrix-free (V: kernel summations from all other frontier nodes' points to
+// a's skeleton, W: the stored Phat of the frontier).
+// ---------------------------------------------------------------------------
+
+// partial-sum elements of the V contractions (each frontier node's two
+// ranges, split in chunks of kChunk points) for `cap` columns
+static int64_t hybrid_ws_elems(askit_factor f, int cap) {
+    askit_tree t = f->t;
+    int64_t worst = 0;
+    for (int half = 0; half < 2; half++) {
+        int64_t tot = 0;
+        for (int64_t id = t->first(f->hyb); id < t->first(f->hyb + 1); id++) {
+            const int64_t r0 = half ? t->ne[id] : 0, r1 = half ? t->N : t->nb[id];
+            const int64_t nch = cdiv(r1 - r0, kChunk);
+            if (nch > 1) tot += nch * (int64_t)t->hsr[id] * cap;
+        }
+        worst = std::max(worst, tot);
+    }
+    return worst;
+}
+
+// out rows of frontier node j (= first(L) + j) += or = sum_{b != j}
+// K(X_{j~}, X_b) src_b: src is N x cap row-major (tree order); out(j, r, c)
+// = cptr(j)[r * crs + c * ccs].  The range [0, b_j) is stored first, then
+// [e_j, N) added, in two launches (they write the same rows).
+template <class CP>
+static askit_status hybrid_v_commit(askit_factor f, Plan &P, const double *src, CP cptr, int64_t crs, int64_t ccs,
+                                    int which, bool add_first) {
+    askit_tree t = f->t;
+    const int s = t->s, cap = f->cap;
+    for (int half = 0; half < 2; half++) {
+        KmmBuild kb;
+        kb.tc = cap >= 128 ? 128 : (cap >= 64 ? 64 : 16);
+        int64_t wsoff = 0;
+        for (int64_t id = t->first(f->hyb); id < t->first(f->hyb + 1); id++) {
+            // the first non-empty range of a node stores (unless add_first), the second adds
+            const int64_t r0 = half ? t->ne[id] : 0, r1 = half ? t->N : t->nb[id];
+            if (r1 <= r0) continue;
+            const bool first_range = half == 0 || t->nb[id] == 0;
+            KmmTask k{};
+            k.X = t->Xp.as<double>();
+            k.R.idx = t->skel.as<int32_t>() + id * s;
+            k.R.n = t->hsr[id];
+            k.S.base = r0;
+            k.S.n = (int32_t)(r1 - r0);
+            k.B = src + r0 * cap;
+            k.ldb = cap;
+            k.C = cptr(id - t->first(f->hyb));
+            k.crs = crs;
+            k.ccs = ccs;
+            k.scale = -1.0 / (2.0 * f->h * f->h);
+            k.hinv = 1.0 / f->h;
+            k.which = which;
+            k.op = (first_range && !add_first) ? OP_STORE : OP_ADD;
+            k.rcap = t->hsr[id];
+            kmm_add(kb, k, k.S.n, cap, kChunk, 8, f->hws.as<char>(), wsoff);
+        }
+        if (wsoff * 8 > (int64_t)f->hws.bytes) return fail(ASKIT_ERR_STATE, "internal: hybrid workspace too small");
+        ST_TRY(kmm_commit(P, kb, P64, P64, t->d, s));
+    }
+    return ASKIT_OK;
+}
+
+// dst (N x cap row-major, tree order) op= W y: rows of frontier node b get
+// Phat_b y_b, y the reduced-system vector (hM x ncol column-major)
+static askit_status hybrid_w_commit(askit_factor f, Plan &P, const double *y, double *dst, int op) {
+    askit_tree t = f->t;
+    const int s = t->s, cap = f->cap, L = f->hyb;
+    GmmBuild gb;
+    gb.tc = cap >= 128 ? 128 : (cap >= 64 ? 64 : 16);
+    gb.elem = 8;
+    for (int64_t id = t->first(L); id < t->first(L + 1); id++) {
+        GmmTask g{};
+        g.A = (const double *)f->ph(L) + t->nb[id] * s;
+        g.ars = s;
+        g.acs = 1;
+        g.B = y + f->hoff[id - t->first(L)];
+        g.brs = 1;
+        g.bcs = f->hM;
+        g.C = dst + t->nb[id] * cap;
+        g.crs = cap;
+        g.ccs = 1;
+        g.rows = (int32_t)(t->ne[id] - t->nb[id]);
+        g.kdim = t->hsr[id];
+        g.op = op;
+        int64_t none = 0;
+        gmm_add(gb, g, cap, 1 << 30, nullptr, none);
+    }
+    return gmm_commit(P, gb, P64, 0);
+}
+
+static askit_status hybrid_plans(askit_factor f) {
+    const int64_t M = f->hM, cap = f->cap, N = f->t->N;
+    if (f->hv_w) return ASKIT_OK;
+    ST_TRY(f->hws.alloc(sizeof(double) * std::max<int64_t>(1, hybrid_ws_elems(f, (int)cap))));
+    ST_TRY(f->HZ.alloc(sizeof(double) * N * cap));
+    ST_TRY(f->HT.alloc(sizeof(double) * M * cap));
+    double *HT = f->HT.as<double>(), *HZ = f->HZ.as<double>(), *W = f->W.as<double>();
+    auto rows_of = [&](double *base) { return [=](int64_t j) { return (void *)(base + f->hoff[j]); }; };
+    f->hv_w.reset(new Plan());
+    f->hv_w->tag = "hybrid";
+    ST_TRY(hybrid_v_commit(f, *f->hv_w, W, rows_of(HT), 1, M, 0, false));
+    f->hw_sub.reset(new Plan());
+    f->hw_sub->tag = "hybrid";
+    ST_TRY(hybrid_w_commit(f, *f->hw_sub, HT, W, OP_SUB));
+    // operator: HZ = W y (y in HT), then out = V HZ; the caller adds y
+    f->hw_store.reset(new Plan());
+    f->hw_store->tag = "hybrid";
+    ST_TRY(hybrid_w_commit(f, *f->hw_store, HT, HZ, OP_STORE));
+    f->hv_z.reset(new Plan());
+    f->hv_z->tag = "hybrid";
+    ST_TRY(f->HU.alloc(sizeof(double) * M * cap));
+    ST_TRY(hybrid_v_commit(f, *f->hv_z, HZ, rows_of(f->HU.as<double>()), 1, M, 0, false));
     return ASKIT_OK;
 }
 
@@ -1745,6 +1917,8 @@ static askit_status solve_plan(const std::vector<askit_factor> &fs, Plan &P) {
         }
     }
     ST_TRY(getrs_commit(P, leaves, pr, false, 0));
+    // with a level restriction the node steps stop at the frontier (v = D^{-1} u)
+    if (fs.size() == 1 && fs[0]->hyb) Hmax = fs[0]->t->D - fs[0]->hyb;
     for (int hgt = 1; hgt <= Hmax; hgt++) {
         KmmBuild kb;
         kb.tc = cap >= 128 ? 128 : (cap >= 64 ? 64 : 16);
@@ -1946,8 +2120,16 @@ static askit_status matvec_plan(askit_factor f, int which, Plan &P) {
         }
     }
     if (D == 0) return ASKIT_OK;
+    // with a level restriction (Sec. 2.3) each frontier node a gets
+    // c_a = sum_{b != a} K_{a~ b} x_b, and the nodes above add nothing
+    if (f->hyb) {
+        if (!f->hws.p) ST_TRY(f->hws.alloc(sizeof(double) * std::max<int64_t>(1, hybrid_ws_elems(f, cap))));
+        ST_TRY(hybrid_v_commit(
+            f, P, WX, [=](int64_t j) { return (void *)(CB + (t->first(f->hyb) + j) * (int64_t)s * cap); }, cap, 1,
+            which, false));
+    }
     // skeleton potentials c_l = K_{l~ r} x_r, c_r = K_{r~ l} x_l, one launch per level
-    for (int l = 0; l < D; l++) {
+    for (int l = f->hyb; l < D; l++) {
         KmmBuild kl;
         kl.tc = cap >= 128 ? 128 : (cap >= 64 ? 64 : 16);
         int64_t wsoff = 0;
@@ -1976,8 +2158,9 @@ static askit_status matvec_plan(askit_factor f, int which, Plan &P) {
         }
         ST_TRY(kmm_commit(P, kl, P64, P64, d, s));
     }
-    // push down: [c_l; c_r] += P_c c_beta, levels 1 .. D-1 in order
-    for (int l = 1; l < D; l++) {
+    // push down: [c_l; c_r] += P_c c_beta, levels 1 .. D-1 in order (from
+    // the frontier down with a level restriction)
+    for (int l = std::max(1, f->hyb); l < D; l++) {
         GmmBuild gb;
         gb.tc = cap >= 128 ? 128 : (cap >= 64 ? 64 : 16);
         int64_t wsoff = 0;
@@ -2265,8 +2448,8 @@ static const int kRestart = 30;
 
 // out[j * nrhs + c] = <V_j(:, c), W(:, c)>, j < nv (device -> host)
 static askit_status mdot(askit_factor f, const double *V, const double *W, int nv, int nrhs, hipStream_t st,
-                         std::vector<double> &out) {
-    const int64_t N = f->t->N;
+                         std::vector<double> &out, int64_t len = -1) {
+    const int64_t N = len >= 0 ? len : f->t->N;
     const int64_t chunk = std::max<int64_t>(4096, cdiv(N, 256));
     const int nchunk = (int)cdiv(N, chunk);
     const int njc = nv * nrhs;
@@ -2331,8 +2514,10 @@ static askit_status gmres_refine(askit_factor f, const double *B, int64_t ldb, i
         res = 0.0;
         for (int c = 0; c < nrhs; c++) {
             rn[c] = std::sqrt(std::max(rn[c], 0.0));
-            res = std::max(res, rn[c] / bn[c]);
+            const double rc = rn[c] / bn[c];
+            if (!(rc <= res)) res = rc;  // a NaN residual propagates (and never converges)
         }
+        if (std::isnan(res)) break;
         if (res0 < 0) res0 = res;
         if (res <= f->refine_tol || it >= f->max_refine) break;
         // stagnation: a restart cycle that did not halve the true residual
@@ -2424,6 +2609,164 @@ static askit_status gmres_refine(askit_factor f, const double *B, int64_t ldb, i
     return ASKIT_OK;
 }
 
+
+// HybridSolve (Alg. HybridSolve): v = D^{-1} u by the node steps up to the
+// frontier; t = V v (MatVecV); (I + V W) y = t by GMRES (classical
+// Gram-Schmidt, twice; x0 = 0; the small Hessenberg systems on the host);
+// x = v - W y (MatVecW).  Reduced-system vectors are hM x nrhs column-major.
+static askit_status hybrid_solve(askit_factor f, const double *B, int64_t ldb, int nrhs, double *X, int64_t ldx,
+                                 hipStream_t st) {
+    askit_tree t = f->t;
+    ST_TRY(ensure_cap(f, nrhs));
+    if (!f->solve_plan) {
+        f->solve_plan.reset(new Plan());
+        f->solve_plan->tag = "solve";
+        ST_TRY(solve_plan({f}, *f->solve_plan));
+    }
+    ST_TRY(hybrid_plans(f));
+    const int64_t N = t->N, M = f->hM, MR = M * (int64_t)nrhs;
+    // restart length: the whole reduced system when its order is at most
+    // 1024 (GMRES then needs no restart), else 1024 basis vectors
+    const int m = (int)std::max<int64_t>(1, std::min<int64_t>(M, 1024));
+    const dim3 tg((unsigned)cdiv(N, 64), (unsigned)cdiv(nrhs, 64));
+    hipLaunchKernelGGL(k_gather_rhs_t<double>, tg, dim3(256), 0, st, B, ldb, t->iperm.as<int64_t>(), N, nrhs,
+                       f->W.as<double>(), (int64_t)f->cap);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(f->solve_plan->run(st, nrhs));  // W = v = D^{-1} u
+    HIP_TRY(f->hv_w->run(st, nrhs));        // HT = t = V v
+    // Krylov basis V_0 .. V_m, then t, y and a work vector: m + 4 slots
+    if (f->HK.bytes < sizeof(double) * (size_t)MR * (m + 4)) {
+        HIP_TRY(hipStreamSynchronize(st));
+        ST_TRY(f->HK.alloc(sizeof(double) * (size_t)MR * (m + 4)));
+    }
+    double *V = f->HK.as<double>(), *Bt = V + (size_t)(m + 1) * MR, *Y = Bt + MR, *R = Y + MR;
+    double *HT = f->HT.as<double>(), *HU = f->HU.as<double>();
+    HIP_TRY(hipMemcpyAsync(Bt, HT, sizeof(double) * MR, hipMemcpyDeviceToDevice, st));
+
+    hipLaunchKernelGGL(k_zero, dim3(grid1(MR)), dim3(256), 0, st, Y, MR);
+    HIP_TRY(hipGetLastError());
+    // out = (I + V W) in, in and out M x nrhs (out may be HU itself)
+    auto apply = [&](const double *in, double *outp) -> askit_status {
+        HIP_TRY(hipMemcpyAsync(HT, in, sizeof(double) * MR, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(f->hw_store->run(st, nrhs));
+        HIP_TRY(f->hv_z->run(st, nrhs));
+        hipLaunchKernelGGL(k_update, dim3(grid1(MR)), dim3(256), 0, st, HU, M, HT, M, M, nrhs);
+        HIP_TRY(hipGetLastError());
+        if (outp != HU) HIP_TRY(hipMemcpyAsync(outp, HU, sizeof(double) * MR, hipMemcpyDeviceToDevice, st));
+        return ASKIT_OK;
+    };
+    std::vector<double> bn, rn, h1, h2, hn, y;
+    ST_TRY(mdot(f, Bt, Bt, 1, nrhs, st, bn, M));
+    for (auto &v : bn) v = v > 0 ? std::sqrt(v) : 1.0;
+    std::vector<double> H((size_t)nrhs * (m + 1) * m), g((size_t)nrhs * (m + 1)), cs((size_t)nrhs * m),
+        sn((size_t)nrhs * m), sc(nrhs);
+    int it = 0;
+    double res = INFINITY, res0 = -1.0, prev = INFINITY;
+    bool first = true;
+    while (true) {
+        // r = t - (I + V W) y
+        if (first) {
+            HIP_TRY(hipMemcpyAsync(R, Bt, sizeof(double) * MR, hipMemcpyDeviceToDevice, st));
+        } else {
+            ST_TRY(apply(Y, R));
+            hipLaunchKernelGGL(k_sub_from, dim3(grid1(MR)), dim3(256), 0, st, Bt, M, R, M, nrhs);
+            HIP_TRY(hipGetLastError());
+        }
+        first = false;
+        ST_TRY(mdot(f, R, R, 1, nrhs, st, rn, M));
+        res = 0.0;
+        for (int c = 0; c < nrhs; c++) {
+            rn[c] = std::sqrt(std::max(rn[c], 0.0));
+            const double rc = rn[c] / bn[c];
+            if (!(rc <= res)) res = rc;  // a NaN residual propagates (and never converges)
+        }
+        if (std::isnan(res)) break;
+        if (res0 < 0) res0 = res;
+        if (res <= f->refine_tol || it >= f->max_refine) break;
+        if (res > 0.99 * prev) break;  // a whole restart cycle gained less than 1%
+        prev = res;
+        for (int c = 0; c < nrhs; c++) sc[c] = rn[c] > 0 ? 1.0 / rn[c] : 0.0;
+        ST_TRY(put_small(f, sc, st));
+        hipLaunchKernelGGL(k_scale_cols, dim3(grid1(MR)), dim3(256), 0, st, V, R, f->ksmall.as<double>(), M, nrhs);
+        std::fill(g.begin(), g.end(), 0.0);
+        for (int c = 0; c < nrhs; c++) g[(size_t)c * (m + 1)] = rn[c];
+        int used = 0;
+        for (int j = 0; j < m && it < f->max_refine; j++) {
+            double *Vj = V + (size_t)j * MR, *Wv = R;
+            ST_TRY(apply(Vj, Wv));
+            ST_TRY(mdot(f, V, Wv, j + 1, nrhs, st, h1, M));
+            ST_TRY(put_small(f, h1, st));
+            hipLaunchKernelGGL(k_maxpy, dim3(grid1(MR)), dim3(256), 0, st, Wv, V, f->ksmall.as<double>(), j + 1, M,
+                               nrhs);
+            ST_TRY(mdot(f, V, Wv, j + 1, nrhs, st, h2, M));
+            ST_TRY(put_small(f, h2, st));
+            hipLaunchKernelGGL(k_maxpy, dim3(grid1(MR)), dim3(256), 0, st, Wv, V, f->ksmall.as<double>(), j + 1, M,
+                               nrhs);
+            ST_TRY(mdot(f, Wv, Wv, 1, nrhs, st, hn, M));
+            for (int c = 0; c < nrhs; c++) {
+                hn[c] = std::sqrt(std::max(hn[c], 0.0));
+                sc[c] = hn[c] > 0 ? 1.0 / hn[c] : 0.0;
+            }
+            ST_TRY(put_small(f, sc, st));
+            hipLaunchKernelGGL(k_scale_cols, dim3(grid1(MR)), dim3(256), 0, st, V + (size_t)(j + 1) * MR, Wv,
+                               f->ksmall.as<double>(), M, nrhs);
+            HIP_TRY(hipGetLastError());
+            it++;
+            used = j + 1;
+            double worst = 0.0;
+            for (int c = 0; c < nrhs; c++) {
+                double *Hc = H.data() + (size_t)c * (m + 1) * m, *gc = g.data() + (size_t)c * (m + 1);
+                double *csc = cs.data() + (size_t)c * m, *snc = sn.data() + (size_t)c * m;
+                auto Hat = [&](int r, int k) -> double & { return Hc[(size_t)r * m + k]; };
+                for (int r = 0; r <= j; r++) Hat(r, j) = h1[(size_t)r * nrhs + c] + h2[(size_t)r * nrhs + c];
+                Hat(j + 1, j) = hn[c];
+                for (int r = 0; r < j; r++) {
+                    double a = Hat(r, j), b = Hat(r + 1, j);
+                    Hat(r, j) = csc[r] * a + snc[r] * b;
+                    Hat(r + 1, j) = -snc[r] * a + csc[r] * b;
+                }
+                double a = Hat(j, j), b = Hat(j + 1, j), rr = std::hypot(a, b);
+                csc[j] = rr > 0 ? a / rr : 1.0;
+                snc[j] = rr > 0 ? b / rr : 0.0;
+                Hat(j, j) = rr;
+                Hat(j + 1, j) = 0.0;
+                gc[j + 1] = -snc[j] * gc[j];
+                gc[j] = csc[j] * gc[j];
+                worst = std::max(worst, std::fabs(gc[j + 1]) / bn[c]);
+            }
+            if (worst <= 0.5 * f->refine_tol) break;
+        }
+        if (used == 0) break;
+        // y += V z, z from the triangular Hessenberg system
+        y.assign((size_t)used * nrhs, 0.0);
+        for (int c = 0; c < nrhs; c++) {
+            double *Hc = H.data() + (size_t)c * (m + 1) * m, *gc = g.data() + (size_t)c * (m + 1);
+            for (int r = used - 1; r >= 0; r--) {
+                double acc = gc[r];
+                for (int k = r + 1; k < used; k++) acc -= Hc[(size_t)r * m + k] * y[(size_t)k * nrhs + c];
+                double d = Hc[(size_t)r * m + r];
+                y[(size_t)r * nrhs + c] = d != 0.0 ? acc / d : 0.0;
+            }
+        }
+        ST_TRY(put_small(f, y, st));
+        hipLaunchKernelGGL(k_lincomb, dim3(grid1(MR)), dim3(256), 0, st, R, V, f->ksmall.as<double>(), used, M, nrhs);
+        hipLaunchKernelGGL(k_update, dim3(grid1(MR)), dim3(256), 0, st, Y, M, R, M, M, nrhs);
+        HIP_TRY(hipGetLastError());
+    }
+    // x = v - W y
+    HIP_TRY(hipMemcpyAsync(HT, Y, sizeof(double) * MR, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(f->hw_sub->run(st, nrhs));
+    hipLaunchKernelGGL(k_scatter_rhs_t<double>, tg, dim3(256), 0, st, f->W.as<double>(), (int64_t)f->cap,
+                       t->iperm.as<int64_t>(), N, nrhs, X, ldx, 0);
+    HIP_TRY(hipGetLastError());
+    f->info.iterations = it;
+    f->info.converged = res <= f->refine_tol;
+    f->info.initial_residual = res0;
+    f->info.residual = res;
+    HIP_TRY(hipStreamSynchronize(st));
+    return ASKIT_OK;
+}
+
 extern "C" {
 
 askit_status askit_solve(askit_factor f, const double *B, int64_t ldb, int32_t nrhs, double *X, int64_t ldx,
@@ -2434,6 +2777,7 @@ askit_status askit_solve(askit_factor f, const double *B, int64_t ldb, int32_t n
     f->info = askit_solve_info{};
     ST_TRY(with_device_arrays(f->t->N, nrhs, B, ldb, X, ldx, true, st,
                               [&](const double *Bd, int64_t lb, double *Xd, int64_t lx) {
+                                  if (f->hyb) return hybrid_solve(f, Bd, lb, nrhs, Xd, lx, st);
                                   if (f->max_refine == 0) return apply_inverse(f, Bd, lb, nrhs, Xd, lx, false, st);
                                   return gmres_refine(f, Bd, lb, nrhs, Xd, lx, false, st);
                               }));
@@ -2444,6 +2788,7 @@ askit_status askit_solve(askit_factor f, const double *B, int64_t ldb, int32_t n
 askit_status askit_solve_transpose(askit_factor f, const double *B, int64_t ldb, int32_t nrhs, double *X,
                                    int64_t ldx, void *stream) {
     ST_TRY(check_solve_args(f, B, ldb, nrhs, X, ldx));
+    if (f->hyb) return fail(ASKIT_ERR_STATE, "no transpose solve for a level-restricted (hybrid) factor");
     hipStream_t st = (hipStream_t)stream;
     f->info = askit_solve_info{};
     return with_device_arrays(f->t->N, nrhs, B, ldb, X, ldx, true, st,
@@ -2457,6 +2802,7 @@ askit_status askit_matvec(askit_factor f, int32_t which, const double *Xin, int6
                           int64_t ldy, void *stream) {
     ST_TRY(check_solve_args(f, Xin, ldx, nrhs, Y, ldy));
     if (which < 0 || which > 2) return fail(ASKIT_ERR_ARG, "which must be 0, 1 or 2");
+    if (which == 2 && f->hyb) return fail(ASKIT_ERR_STATE, "no transposed matvec for a level-restricted (hybrid) factor");
     hipStream_t st = (hipStream_t)stream;
     return with_device_arrays(f->t->N, nrhs, Xin, ldx, Y, ldy, true, st,
                               [&](const double *Xd, int64_t lxd, double *Yd, int64_t lyd) {

@@ -278,3 +278,61 @@ def test_instability_is_detected(orc):
     assert min(o.pivratio(n) for n in range(leaf0, o.nnodes)) < 1e-12
     o2 = _build(orc, X, 64, 8, 0.3, 1.0)
     assert min(o2.pivratio(n) for n in range(o2.nnodes)) > 1e-6
+
+
+# --- level restriction and the hybrid solver (Sec. 2.3) ---------------------
+
+def _hybrid_case(orc):
+    X, B = synth.small(2000, 3, 7, nrhs=3, kind="mixture", scale=2.0)
+    o = orc.Oracle(X, 64, 24, 0.6, seed=3)
+    o.build_tree()
+    o.skeletonize()
+    return o, B, 0.3
+
+
+def test_hybrid_level_one_is_the_full_method(orc):
+    # the root has no skeleton, so a frontier at level 1 leaves the matrix of
+    # the full method unchanged (only the root's Z changes hands: from a
+    # direct node step to the reduced system I + V W of order s_l + s_r)
+    o, B, lam = _hybrid_case(orc)
+    o.factorize(lam)
+    x0, A0, y0 = o.solve(B), o.dense(), o.matvec(B)
+    o.set_level(1)
+    o.factorize(lam)
+    assert np.array_equal(o.dense(), A0)
+    assert np.array_equal(o.matvec(B), y0)
+    assert _rel(o.solve(B), x0) < 1e-13
+
+
+@pytest.mark.parametrize("L", [2, 3, 5])
+def test_hybrid_solve_inverts_the_restricted_matrix(orc, L):
+    # HybridSolve against LAPACK on the assembled level-restricted
+    # lambda I + Ktilde; the reduced system has order sum_a s_a <= 2^L s
+    o, B, lam = _hybrid_case(orc)
+    o.set_level(L)
+    o.factorize(lam)
+    A = o.dense()
+    xd = sla.solve(A, B)
+    assert _rel(o.solve(B), xd) < 1e-11
+    assert _rel(o.matvec(B), A @ B) < 1e-13
+    M, ratio = o.reduced_system()
+    ranks = [o.skel_info(n)[0] for n in range((1 << L) - 1, (2 << L) - 1)]
+    assert M == sum(ranks) <= (1 << L) * 24
+    assert ratio > 1e-6
+    # nothing is compressed above the frontier: the blocks between two
+    # frontier nodes are P_{a a~} K_{a~ b}, one skeleton deep, so a frontier
+    # lower in the tree approximates K less and less (no error is added above)
+    K = orc.dense_kernel(o.X, o.h) + lam * np.eye(o.N)
+    errs = []
+    for LL in (1, L):
+        o.set_level(LL)
+        errs.append(np.linalg.norm(o.dense() - K))
+    assert errs[1] <= errs[0] * (1 + 1e-12)
+
+
+def test_hybrid_has_no_transpose_solve(orc):
+    o, B, lam = _hybrid_case(orc)
+    o.set_level(2)
+    o.factorize(lam)
+    with pytest.raises(RuntimeError):
+        o.solve_t(B)
