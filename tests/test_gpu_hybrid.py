@@ -75,7 +75,7 @@ def test_level_one_is_the_direct_solver(case, ak):
 
 
 @pytest.mark.parametrize("level", [2, 3, "D"])
-def test_hybrid_matches_oracle(case, ak, level):
+def test_hybrid_matches_oracle(case, ak, level, request):
     """Against the oracle's HybridSolve, which solves the reduced system
     exactly: the solution within 1e-9, or 10x the spread of the oracle's two
     FP64 orderings (paper telescoping and push-through) where the problem's
@@ -84,6 +84,8 @@ def test_hybrid_matches_oracle(case, ak, level):
     matvec (which 0 and 1) within 1e-12."""
     t, o, Bh, lam = case["t"], case["o"], case["B"], case["lam"]
     L = t.D if level == "D" else level
+    if L == t.D and t.N > 8192:
+        pytest.skip("the oracle's dense LU of a reduced system of order ~8000 takes minutes on the host")
     o.set_level(L)
     o.factorize(lam, 2)
     x2 = o.solve(Bh)
@@ -93,6 +95,9 @@ def test_hybrid_matches_oracle(case, ak, level):
     ro = float(np.max(np.linalg.norm(Bh - o.matvec(xo), axis=0) / np.linalg.norm(Bh, axis=0)))
     M, ratio = o.reduced_system()
     f = t.factorize_hybrid(lam, L)
+    # a reduced residual of 1e-11: the reduced systems here have condition
+    # numbers up to ~1e4, which puts their FP64 floor near 1e-12
+    f.set_refinement(4000, 1e-11)
     B = _cuda(Bh)
     x = f.solve(B)
     info = f.info()
