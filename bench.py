@@ -452,7 +452,32 @@ def forms_timings(ak, torch, dev, tree, lam, B):
     out["fp64_matvec_s"], _ = _timed(torch, lambda: f.matvec(B, 0))
     out["fp64_matvec_transpose_s"], _ = _timed(torch, lambda: f.matvec(B, 2))
     out["fp64_matvec_dh_s"], _ = _timed(torch, lambda: f.matvec(B, 1))
+    # hybrid solver (level restriction, Sec. 2.3) on the same tree, 4
+    # right-hand sides: level 1 keeps the matrix of the direct method (the
+    # root's reduced system solved by GMRES instead of its LU), level 3
+    # leaves the top three levels uncompressed
+    B4 = B[:, :4].contiguous()
+    x4 = f.solve(B4)
+    out["fp64_direct_residual_4rhs"] = float(((B4 - f.matvec(x4)).norm(dim=0) / B4.norm(dim=0)).max())
     f.close()
+    ranks, _ = tree.skeleton_sizes()
+    hyb = {}
+    for L in (1, 3):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        fh = tree.factorize_hybrid(lam, L)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        xh = fh.solve(B4)
+        torch.cuda.synchronize()
+        e = time.perf_counter()
+        info = fh.info()
+        res = float(((B4 - fh.matvec(xh)).norm(dim=0) / B4.norm(dim=0)).max())
+        hyb[f"level_{L}"] = {"factorize_s": b - a, "solve_s": e - b, "gmres": info, "residual": res,
+                             "reduced_order": int(ranks[(1 << L) - 1:(2 << L) - 1].sum())}
+        log(f"[bench] hybrid level {L}: factorize {b - a:.3f} s solve {e - b:.3f} s {info} residual {res:.2e}")
+        fh.close()
+    out["hybrid_4rhs"] = hyb
     # adjoint gradient
     c = synth.config(5)
     t5 = ak.Tree(torch.as_tensor(c["X"], device=dev), c["m"], c["s"], c["h"], seed=c["seed"])
