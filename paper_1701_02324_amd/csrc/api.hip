@@ -977,6 +977,7 @@ struct SkelRun {
     int nqr = 0, n1 = 0, nsp = 0, split_steps = 0;
     QrWork w{};
 
+
     // In the pipelined call the skeletonization of a level overlaps the
     // factorization below it; there a level with 2^kOneWgLevel nodes or more
     // does better with one workgroup per node than with one launch per pivot
@@ -1151,34 +1152,39 @@ struct SkelRun {
                 return hipGetLastError();
             }));
         }
-        if (nsp > 0) {
-            const SkelTask *tp = dsplit.as<SkelTask>();
-            const QrWork wk = w;
-            const unsigned g = (unsigned)(nsp * wk.slices);
-            const std::string hs = prof_height(hgt);
-            HIP_TRY(timed("skel:k_qs_rows" + hs, st, [&] {
-                hipLaunchKernelGGL(k_qs_rows, dim3(g), dim3(kQsThreads), 0, st, tp, wk, nsamp_max);
+        if (nsp > 0) ST_TRY(split_qr(hgt));
+        return ASKIT_OK;
+    }
+
+    // The pivoted QR of the split nodes: row norms, row map, compaction and
+    // initial norms, one launch per pivot step, then T and the outputs.
+    askit_status split_qr(int hgt) {
+        const SkelTask *tp = dsplit.as<SkelTask>();
+        const QrWork wk = w;
+        const unsigned g = (unsigned)(nsp * wk.slices);
+        const std::string hs = prof_height(hgt);
+        HIP_TRY(timed("skel:k_qs_rows" + hs, st, [&] {
+            hipLaunchKernelGGL(k_qs_rows, dim3(g), dim3(kQsThreads), 0, st, tp, wk, nsamp_max);
+            return hipGetLastError();
+        }));
+        HIP_TRY(timed("skel:k_qs_rowmap" + hs, st, [&] {
+            hipLaunchKernelGGL(k_qs_rowmap, dim3(nsp), dim3(512), 0, st, tp, wk);
+            return hipGetLastError();
+        }));
+        HIP_TRY(timed("skel:k_qs_init" + hs, st, [&] {
+            hipLaunchKernelGGL(k_qs_init, dim3(g), dim3(kQsThreads), 0, st, tp, wk, s, nsamp_max);
+            return hipGetLastError();
+        }));
+        for (int j = 0; j < split_steps; j++)
+            HIP_TRY(timed("skel:k_qs_step" + hs, st, [&] {
+                hipLaunchKernelGGL(k_qs_step, dim3(g), dim3(kQsThreads), 0, st, tp, wk, j, nsamp_max);
                 return hipGetLastError();
             }));
-            HIP_TRY(timed("skel:k_qs_rowmap" + hs, st, [&] {
-                hipLaunchKernelGGL(k_qs_rowmap, dim3(nsp), dim3(512), 0, st, tp, wk);
-                return hipGetLastError();
-            }));
-            HIP_TRY(timed("skel:k_qs_init" + hs, st, [&] {
-                hipLaunchKernelGGL(k_qs_init, dim3(g), dim3(kQsThreads), 0, st, tp, wk, s, nsamp_max);
-                return hipGetLastError();
-            }));
-            for (int j = 0; j < split_steps; j++)
-                HIP_TRY(timed("skel:k_qs_step" + hs, st, [&] {
-                    hipLaunchKernelGGL(k_qs_step, dim3(g), dim3(kQsThreads), 0, st, tp, wk, j, nsamp_max);
-                    return hipGetLastError();
-                }));
-            HIP_TRY(timed("skel:k_qs_finish" + hs, st, [&] {
-                hipLaunchKernelGGL(k_qs_finish, dim3(nsp, (unsigned)cdiv(wk.slices * kQsCols, kQsFinishCols)), dim3(512), 0,
-                                   st, tp, wk, s, nsamp_max);
-                return hipGetLastError();
-            }));
-        }
+        HIP_TRY(timed("skel:k_qs_finish" + hs, st, [&] {
+            hipLaunchKernelGGL(k_qs_finish, dim3(nsp, (unsigned)cdiv(wk.slices * kQsCols, kQsFinishCols)), dim3(512), 0,
+                               st, tp, wk, s, nsamp_max);
+            return hipGetLastError();
+        }));
         return ASKIT_OK;
     }
 

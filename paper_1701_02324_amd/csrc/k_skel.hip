@@ -913,97 +913,199 @@ __global__ __launch_bounds__(kQsThreads) void k_qs_init(const SkelTask *__restri
     }
 }
 
-// pivot step j: every workgroup of a node picks the same pivot (largest norm
-// over positions j .., lowest position on ties) and builds the same
-// reflector from the state of step j - 1 (buffers j % 2), then updates the
-// columns at its own positions > j into the other buffers
+// Pivot step j of a split node.  qs_pivot: every workgroup of a node picks the same
+// pivot (largest norm over positions j .., lowest position on ties) and
+// builds the same reflector from the state of step j - 1 (buffers j % 2);
+// wave 0 works, the result lands in LDS.  The writer workgroup records R_jj
+// or the stop.  qs_update: the workgroup updates the columns at the
+// positions > j of its column groups (s0, s0 + sstep, .. of kQsCols
+// positions each) into the other buffers; in the next pivot order positions
+// j and k are exchanged, and the column now at position q is updated and its
+// norm stored at q.
+struct QsPivot {
+    double tau;
+    int32_t k, p, stop;
+};
+
+// leading dimension of the split nodes' sampled blocks (the sample capacity)
+__device__ inline int ldm_of(const QrWork &w) { return w.rcap; }
+
+__device__ inline void qs_pivot(const SkelTask *tasks, const QrWork &w, int node, int j, bool writer, double *vh,
+                                QsPivot *sp) {
+    const GLB int32_t *st = glb(w.st) + kQsState * node;
+    const int rows = st[4], ncand = st[5];
+    GLB double *M = glb(tasks[node].M);
+    // |R_00| for the rank rule (meaningless, and unused, at step 0)
+    const double r00 = fabs(glb(w.diag)[(int64_t)node * w.cmax]);
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    if (wave != 0) return;
+    const GLB double *nin = glb(w.nrm) + (int64_t)node * 2 * w.cmax + (int64_t)(j & 1) * w.cmax;
+    const GLB int32_t *pin = glb(w.pos) + (int64_t)node * 2 * w.cmax + (int64_t)(j & 1) * w.cmax;
+    GLB double *Rjj = glb(w.diag) + (int64_t)node * w.cmax;
+    // each lane reads the norms and the columns of its positions (at most
+    // kQsScan: a split node has at most 2 s <= 2 kQrMaxRank candidates), all
+    // loads before the first comparison, so the pivot's column comes from
+    // the winning lane instead of another load
+    double nv[kQsScan];
+    int pc[kQsScan];
+#pragma unroll
+    for (int u = 0; u < kQsScan; u++) {
+        const int k = j + lane + u * kWave;
+        nv[u] = k < ncand ? nin[k] : -1.0;
+        pc[u] = k < ncand ? pin[k] : -1;
+    }
+    double bv = -1.0;
+    int bk = 0x7fffffff, bc = -1;
+#pragma unroll
+    for (int u = 0; u < kQsScan; u++) {
+        if (nv[u] > bv) {  // positions ascend within a lane: the first of equal norms stays
+            bv = nv[u];
+            bk = j + lane + u * kWave;
+            bc = pc[u];
+        }
+    }
+    const int kw = wave_argmax(bv, bk);
+    bk = kw == 0x7fffffff ? j : kw;  // no comparable norm (NaN): keep the order
+    const int p = kw == 0x7fffffff ? pin[j] : __builtin_amdgcn_readlane(bc, (kw - j) & (kWave - 1));
+    bool stop;
+    const Refl r = reflector_to_lds(M + (int64_t)p * ldm_of(w), j, rows, lane, j == 0 ? 0.0 : r00, tasks[node].tol, vh,
+                                    stop);
+    if (lane == 0) {
+        sp->stop = stop;
+        sp->k = bk;
+        sp->p = p;
+        sp->tau = r.tau;
+        vh[j] = 1.0;
+        if (writer) {
+            if (stop) {
+                GLB int32_t *stw = glb(w.st) + kQsState * node;
+                stw[0] = 1;
+                stw[1] = j;
+                stw[2] = (j == 0);
+            } else {
+                Rjj[j] = r.beta;
+            }
+        }
+    }
+}
+
+// the update of one workgroup's positions; columns of a wave are loaded
+// NC at a time before their products when rows - j <= 64 NT (the
+// per-column arithmetic is apply_col's, so the grouping changes no result)
+template <int NT, int NC>
+__device__ inline void qs_update_grouped(const QrWork &w, GLB double *M, int ldm, int node, int j, int rows,
+                                         int ncand, int s0, int sstep, const double *vh, const QsPivot &pv) {
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const GLB int32_t *pin = glb(w.pos) + (int64_t)node * 2 * w.cmax + (int64_t)(j & 1) * w.cmax;
+    GLB double *nout = glb(w.nrm) + (int64_t)node * 2 * w.cmax + (int64_t)((j + 1) & 1) * w.cmax;
+    GLB int32_t *pout = glb(w.pos) + (int64_t)node * 2 * w.cmax + (int64_t)((j + 1) & 1) * w.cmax;
+    // this workgroup's positions: group g of s0, s0 + sstep, ..; position
+    // i of the workgroup's list is q(i) = (s0 + (i / kQsCols) sstep) kQsCols + i % kQsCols
+    const int ngroups = (w.slices - s0 + sstep - 1) / sstep;
+    const int npos = ngroups * kQsCols;
+    auto qpos = [&](int i) { return (s0 + (i / kQsCols) * sstep) * kQsCols + i % kQsCols; };
+    const int pj = pin[j];
+    double vr[NT];
+#pragma unroll
+    for (int t = 0; t < NT; t++) {
+        const int i = j + lane + t * kWave;
+        vr[t] = i < rows ? vh[i] : 0.0;
+    }
+    for (int i0 = wave; i0 < npos; i0 += kQsWaves * NC) {
+        int q[NC], c[NC];
+        double a[NC][NT];
+#pragma unroll
+        for (int u = 0; u < NC; u++) {
+            const int i = i0 + u * kQsWaves;
+            q[u] = i < npos ? qpos(i) : ncand;
+            c[u] = -1;
+            if (q[u] < ncand) {
+                c[u] = q[u] == j ? pv.p : (q[u] == pv.k ? pj : pin[q[u]]);
+                if (lane == 0) pout[q[u]] = c[u];
+                if (q[u] <= j) c[u] = -1;  // placed, nothing to update
+            }
+#pragma unroll
+            for (int t = 0; t < NT; t++) {
+                const int r = j + lane + t * kWave;
+                a[u][t] = (c[u] >= 0 && r < rows) ? M[(int64_t)c[u] * ldm + r] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < NC; u++) {
+            if (c[u] < 0) continue;
+            double wsum = 0.0;
+#pragma unroll
+            for (int t = 0; t < NT; t++) wsum = fma(vr[t], a[u][t], wsum);
+            wsum = wave_sum(wsum) * pv.tau;
+            double n = 0.0;
+#pragma unroll
+            for (int t = 0; t < NT; t++) {
+                const int r = j + lane + t * kWave;
+                a[u][t] = fma(-vr[t], wsum, a[u][t]);
+                if (r > j && r < rows) n = fma(a[u][t], a[u][t], n);
+            }
+            GLB double *col = M + (int64_t)c[u] * ldm;
+#pragma unroll
+            for (int t = 0; t < NT; t++) {
+                const int r = j + lane + t * kWave;
+                if (r < rows) col[r] = a[u][t];
+            }
+            n = wave_sum(n);
+            if (lane == 0) nout[q[u]] = n;
+        }
+    }
+}
+
+// spans above 16 x 64 rows: one column at a time (apply_col)
+__device__ inline void qs_update_plain(const QrWork &w, GLB double *M, int ldm, int node, int j, int rows, int ncand,
+                                       int s0, int sstep, const double *vh, const QsPivot &pv) {
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const GLB int32_t *pin = glb(w.pos) + (int64_t)node * 2 * w.cmax + (int64_t)(j & 1) * w.cmax;
+    GLB double *nout = glb(w.nrm) + (int64_t)node * 2 * w.cmax + (int64_t)((j + 1) & 1) * w.cmax;
+    GLB int32_t *pout = glb(w.pos) + (int64_t)node * 2 * w.cmax + (int64_t)((j + 1) & 1) * w.cmax;
+    const int npos = ((w.slices - s0 + sstep - 1) / sstep) * kQsCols;
+    const int pj = pin[j];
+    for (int i = wave; i < npos; i += kQsWaves) {
+        const int q = (s0 + (i / kQsCols) * sstep) * kQsCols + i % kQsCols;
+        if (q >= ncand) continue;
+        const int c = q == j ? pv.p : (q == pv.k ? pj : pin[q]);
+        if (lane == 0) pout[q] = c;
+        if (q <= j) continue;
+        const double v = apply_col(M + (int64_t)c * ldm, vh, j, rows, pv.tau, lane);
+        if (lane == 0) nout[q] = v;
+    }
+}
+
+__device__ inline void qs_update(const SkelTask *tasks, const QrWork &w, int node, int j, int s0, int sstep,
+                                 const double *vh, const QsPivot &pv) {
+    const GLB int32_t *st = glb(w.st) + kQsState * node;
+    const int rows = st[4], ncand = st[5];
+    GLB double *M = glb(tasks[node].M);
+    const int ldm = ldm_of(w), span = rows - j;
+    if (span <= kWave) qs_update_grouped<1, 8>(w, M, ldm, node, j, rows, ncand, s0, sstep, vh, pv);
+    else if (span <= 2 * kWave) qs_update_grouped<2, 4>(w, M, ldm, node, j, rows, ncand, s0, sstep, vh, pv);
+    else if (span <= 4 * kWave) qs_update_grouped<4, 2>(w, M, ldm, node, j, rows, ncand, s0, sstep, vh, pv);
+    else if (span <= 8 * kWave) qs_update_grouped<8, 2>(w, M, ldm, node, j, rows, ncand, s0, sstep, vh, pv);
+    else if (span <= 16 * kWave) qs_update_grouped<16, 1>(w, M, ldm, node, j, rows, ncand, s0, sstep, vh, pv);
+    else qs_update_plain(w, M, ldm, node, j, rows, ncand, s0, sstep, vh, pv);
+}
+
+// one launch per pivot step: workgroup = (node, column group)
 __global__ __launch_bounds__(kQsThreads) void k_qs_step(const SkelTask *__restrict__ tasks, QrWork w, int j,
                                                          int ldm) {
     __shared__ double vh[kQrMaxRows];
-    __shared__ int32_t s_k, s_p, s_stop;
-    __shared__ double s_tau;
+    __shared__ QsPivot sp;
+    (void)ldm;
     const int node = blockIdx.x / w.slices, slice = blockIdx.x % w.slices;
     const GLB int32_t *st = glb(w.st) + kQsState * node;
-    const int stopped = st[0], steps = st[3], rows = st[4], ncand = st[5];
-    GLB double *M = glb(tasks[node].M);
-    // |R_00| for the rank guard, read with the node state (meaningless, and
-    // unused, at step 0)
-    const double r00 = fabs(glb(w.diag)[(int64_t)node * w.cmax]);
+    const int stopped = st[0], steps = st[3], ncand = st[5];
     if (stopped || j >= steps) return;
-    const int q0 = slice * kQsCols;
-    if (q0 >= ncand) return;
-    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
-    const GLB double *nin = glb(w.nrm) + (int64_t)node * 2 * w.cmax + (int64_t)(j & 1) * w.cmax;
-    GLB double *nout = glb(w.nrm) + (int64_t)node * 2 * w.cmax + (int64_t)((j + 1) & 1) * w.cmax;
-    const GLB int32_t *pin = glb(w.pos) + (int64_t)node * 2 * w.cmax + (int64_t)(j & 1) * w.cmax;
-    GLB int32_t *pout = glb(w.pos) + (int64_t)node * 2 * w.cmax + (int64_t)((j + 1) & 1) * w.cmax;
-    GLB double *Rjj = glb(w.diag) + (int64_t)node * w.cmax;
-    // this wave's positions and their columns (read early)
-    const int qa = q0 + 2 * wave, qb = qa + 1;
-    const int ca = qa < ncand ? pin[qa] : -1, cb = qb < ncand ? pin[qb] : -1;
-    if (wave == 0) {
-        // each lane reads the norms and the columns of its positions (at
-        // most kQsScan: a split node has at most 2 s <= 2 kQrMaxRank
-        // candidates), all loads before the first comparison, so the
-        // pivot's column comes from the winning lane instead of another load
-        double nv[kQsScan];
-        int pc[kQsScan];
-#pragma unroll
-        for (int u = 0; u < kQsScan; u++) {
-            const int k = j + lane + u * kWave;
-            nv[u] = k < ncand ? nin[k] : -1.0;
-            pc[u] = k < ncand ? pin[k] : -1;
-        }
-        double bv = -1.0;
-        int bk = 0x7fffffff, bc = -1;
-#pragma unroll
-        for (int u = 0; u < kQsScan; u++) {
-            if (nv[u] > bv) {  // positions ascend within a lane: the first of equal norms stays
-                bv = nv[u];
-                bk = j + lane + u * kWave;
-                bc = pc[u];
-            }
-        }
-        const int kw = wave_argmax(bv, bk);
-        bk = kw == 0x7fffffff ? j : kw;  // no comparable norm (NaN): keep the order
-        const int p = kw == 0x7fffffff ? pin[j] : __builtin_amdgcn_readlane(bc, (kw - j) & (kWave - 1));
-        bool stop;
-        const Refl r = reflector_to_lds(M + (int64_t)p * ldm, j, rows, lane, j == 0 ? 0.0 : r00, tasks[node].tol, vh,
-                                        stop);
-        if (lane == 0) {
-            s_stop = stop;
-            s_k = bk;
-            s_p = p;
-            s_tau = r.tau;
-            vh[j] = 1.0;
-            if (slice == 0) {
-                if (stop) {
-                    GLB int32_t *stw = glb(w.st) + kQsState * node;
-                    stw[0] = 1;
-                    stw[1] = j;
-                    stw[2] = (j == 0);
-                } else {
-                    Rjj[j] = r.beta;
-                }
-            }
-        }
-    }
+    if (slice * kQsCols >= ncand) return;
+    qs_pivot(tasks, w, node, j, slice == 0, vh, &sp);
     __syncthreads();
-    if (s_stop) return;
-    const int k = s_k, p = s_p;
-    const double tau = s_tau;
-    // the next pivot order at this wave's positions: positions j and k
-    // exchanged; the column now at position q > j is updated and its norm
-    // stored at q
-    for (int u = 0; u < 2; u++) {
-        const int q = u ? qb : qa;
-        if (q >= ncand) continue;
-        const int c = q == j ? p : (q == k ? pin[j] : (u ? cb : ca));
-        if (lane == 0) pout[q] = c;
-        if (q <= j) continue;
-        const double v = apply_col(M + (int64_t)c * ldm, vh, j, rows, tau, lane);
-        if (lane == 0) nout[q] = v;
-    }
+    const QsPivot pv = sp;
+    if (pv.stop) return;
+    qs_update(tasks, w, node, j, slice, w.slices, vh, pv);
 }
 
 // T = R11^{-1} R12 and the outputs; blockIdx.y takes the column groups
