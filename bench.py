@@ -63,13 +63,15 @@ def algorithmic_counts(N, d, m, s, D, nsamp, nrhs, ranks, qrows, split_levels, f
     dropped).  These are the counts the method needs, not what the kernels
     execute:
       skel:k_qrcp          nodes at levels > split_levels with c > s candidate
-                           columns and r factored rows: pivot step j costs
-                           6 (r-j)(c-j-1) (reflector dot 2, update 2, column
-                           norm 2 per trailing element), s_a steps; then
-                           T = R11^-1 R12: s_a^2 (c - s_a); plus (3d+1) r c
-                           for the kept rows it generates
+                           columns and r factored rows: pivot step j reads and
+                           writes the trailing block once, 16 (r-j)(c-j-1)
+                           bytes in FP64 (the block does not fit on chip, so
+                           the unblocked Householder QR streams it every step;
+                           its flops, 6 (r-j)(c-j-1), are 0.375 per byte), s_a
+                           steps; plus the r c generated entries written once
       skel:k_qs_step       the pivot steps of the nodes at levels 1..split_levels
-      skel:k_qs_finish     their s_a^2 (c - s_a)
+                           (bytes as above)
+      skel:k_qs_finish     T = R11^-1 R12: s_a^2 (c - s_a) flops
       skel:k_sample_rownorm (3d+1) flops per sampled kernel entry (difference,
                            fma, exp counted as one), nsamp' x c per node, one-
                            workgroup levels; skel:k_sample_block the same at
@@ -106,7 +108,7 @@ def algorithmic_counts(N, d, m, s, D, nsamp, nrhs, ranks, qrows, split_levels, f
                 rows_s = float(min(nsamp, N - n))
                 rows = float(qr[i])
                 k = int(r[i])
-                steps = sum(6.0 * (rows - j) * (cols - j - 1) for j in range(k))
+                steps = sum(16.0 * (rows - j) * (cols - j - 1) for j in range(k))
                 tsolve = k * k * (cols - k)
                 samp = rows_s * cols * (3.0 * d + 1)
                 if lvl <= split_levels:
@@ -114,7 +116,7 @@ def algorithmic_counts(N, d, m, s, D, nsamp, nrhs, ranks, qrows, split_levels, f
                     c["skel:k_qs_finish"] += tsolve
                     c["skel:k_sample_block"] += samp
                 else:
-                    c["skel:k_qrcp"] += steps + tsolve + rows * cols * (3.0 * d + 1)
+                    c["skel:k_qrcp"] += steps + 8.0 * rows * cols
                     c["skel:k_sample_rownorm"] += samp
         nlu = n if leaf else float(r[2 * i + 1] + r[2 * i + 2])
         c["factor:k_lu_nopiv" if leaf else "factor:k_lu"] += (2.0 / 3.0) * nlu ** 3
@@ -136,8 +138,8 @@ def algorithmic_counts(N, d, m, s, D, nsamp, nrhs, ranks, qrows, split_levels, f
 # FP64 vector and FP64 MFMA share one peak on MI355X (78.6 TFLOP/s); the
 # products of the mixed path would run FP32 MFMA, the timed FP64 path does not.
 ROOF_KIND = {
-    "skel:k_qrcp": ("alu", "fp64", "TFLOP/s"),
-    "skel:k_qs_step": ("alu", "fp64", "TFLOP/s"),
+    "skel:k_qrcp": ("hbm", None, "GB/s"),
+    "skel:k_qs_step": ("hbm", None, "GB/s"),
     "skel:k_qs_finish": ("alu", "fp64", "TFLOP/s"),
     "skel:k_sample_rownorm": ("alu", "fp64", "TFLOP/s"),
     "skel:k_sample_block": ("alu", "fp64", "TFLOP/s"),
@@ -156,7 +158,26 @@ ROOF_KIND = {
 # scaled by what the same counters read for a plain 1 GiB read + 1 GiB write
 # (torch.neg).  Valid only for the kernel source they were taken on (sha256 of
 # its files) and for this workload; otherwise "traffic" is null.
-TRAFFIC = {}
+TRAFFIC = {
+    "skel:k_qs_step": {
+        "source": ["k_skel.hip", "askit_dev.h"],
+        "src_sha256": "de4824c106d7466a92f70be94513050d7ca829a886799d07d14d11f773003882",
+        "workload": (1048576, 16, 512, 256, 1024),
+        "bytes_per_launch": (2357.4 * 2.0 + 3746.4) * 1024.0,
+    },
+    "skel:k_qrcp": {
+        "source": ["k_skel.hip", "askit_dev.h"],
+        "src_sha256": "de4824c106d7466a92f70be94513050d7ca829a886799d07d14d11f773003882",
+        "workload": (1048576, 16, 512, 256, 1024),
+        "bytes_per_launch": (1042740.5 * 2.0 + 1643313.1) * 1024.0,
+    },
+    "factor:k_lu_nopiv": {
+        "source": ["k_lu.hip", "askit_dev.h"],
+        "src_sha256": "c5e25716cb6a578a534550b417e0bd16064560ea4baaa7308903e0b89d91a7d6",
+        "workload": (1048576, 16, 512, 256, 1024),
+        "bytes_per_launch": (7701579.6 * 2.0 + 16277863.1) * 1024.0,
+    },
+}
 
 
 def kernel_source_sha(names):
@@ -376,11 +397,12 @@ def main():
     # the headline roofline is the kernel with the largest time in the step
     top = sorted(((k, v) for k, v in prof.items() if k != "@timeline"), key=lambda kv: -kv[1][0])
     dom = next((k for k, _ in top if k in rooflines), None)
+    for key, r in rooflines.items():
+        tr = TRAFFIC.get(key)
+        if tr is not None and tr["src_sha256"] == kernel_source_sha(tr["source"]) \
+                and tr["workload"] == (N, d, m, s, nsamp):
+            r["traffic"] = tr["bytes_per_launch"]
     roof = dict(rooflines[dom]) if dom else None
-    tr = TRAFFIC.get(dom) if dom else None
-    if roof is not None and tr is not None and tr["src_sha256"] == kernel_source_sha(tr["source"]) \
-            and tr["workload"] == (N, d, m, s, nsamp):
-        roof["traffic"] = tr["bytes_per_launch"]
 
     forms = None
     if not args.no_forms:
