@@ -100,6 +100,19 @@ def lib():
         L.orc_node_seed.restype = ctypes.c_uint64
         L.orc_sample.argtypes = [ctypes.c_uint64, _i64, _i64, _i64, _i64, _i64, ctypes.c_int, _lp]
         L.orc_sample.restype = _i64
+        L.orc_sample_prefix.argtypes = [ctypes.c_uint64, _i64, _i64, _i64, _i64, _i64, ctypes.c_int, _lp, _i64,
+                                        _lp]
+        L.orc_sample_prefix.restype = _i64
+        L.orc_set_knn.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.orc_set_knn.restype = ctypes.c_int
+        L.orc_get_knn.argtypes = [ctypes.c_void_p, _lp]
+        L.orc_node_nbr.argtypes = [ctypes.c_void_p, _i64, _lp, _lp]
+        L.orc_node_nbr.restype = _i64
+        L.orc_knn_rows.argtypes = [ctypes.c_void_p, _i64, _i64, ctypes.c_int, _lp]
+        L.orc_subtree_sample.argtypes = [ctypes.c_void_p, _i64, ctypes.c_int, _lp, _lp, _lp, _lp]
+        L.orc_subtree_sample.restype = _i64
+        L.orc_node_sample.argtypes = [ctypes.c_void_p, _i64, _lp]
+        L.orc_node_sample.restype = _i64
         L.orc_depth.argtypes = [_i64, ctypes.c_int]
         L.orc_num_threads.restype = ctypes.c_int
         _lib = L
@@ -200,6 +213,15 @@ def sample(seed, problem, node, N, b, e, nsamp):
     return q[:k].copy()
 
 
+def sample_prefix(seed, problem, node, N, b, e, nsamp, pre):
+    """S' of node [b,e) opened by the positions pre (distinct, outside the
+    node), filled by uniform draws."""
+    pre = np.ascontiguousarray(pre, dtype=np.int64)
+    q = np.zeros(max(nsamp, 1), dtype=np.int64)
+    k = lib().orc_sample_prefix(seed, problem, node, N, b, e, nsamp, _l(pre), pre.size, _l(q))
+    return q[:k].copy()
+
+
 def depth(N, m):
     return lib().orc_depth(N, m)
 
@@ -237,6 +259,7 @@ class Oracle:
             raise ValueError("tol must be in [0, 1)")
         self.D = lib().orc_get_depth(self._h)
         self.lam = None
+        self.kappa = 0
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -268,6 +291,50 @@ class Oracle:
     @property
     def nnodes(self):
         return (2 << self.D) - 1
+
+    # kappa-nearest-neighbour sampling --------------------------------------------
+    def set_knn(self, kappa):
+        """Neighbours of every point and the ranked neighbour list of every
+        node; the next skeletonize() samples each node's list first, then
+        uniform rows.  kappa = 0: uniform rows only."""
+        rc = lib().orc_set_knn(self._h, int(kappa))
+        if rc:
+            raise ValueError(f"set_knn failed ({rc})")
+        self.kappa = int(kappa)
+
+    def knn(self):
+        """N x kappa nearest positions of every position (tree order), -1 padded."""
+        out = np.zeros((self.N, self.kappa), dtype=np.int64)
+        lib().orc_get_knn(self._h, _l(out))
+        return out
+
+    def knn_rows(self, b, e, kappa):
+        """Neighbours of the positions [b, e) only (brute force against all N)."""
+        out = np.zeros((e - b, kappa), dtype=np.int64)
+        lib().orc_knn_rows(self._h, b, e, int(kappa), _l(out))
+        return out
+
+    def node_neighbors(self, node):
+        """(positions, weights) of a node's ranked neighbour list."""
+        pos = np.zeros(self.nsamp, dtype=np.int64); w = np.zeros(self.nsamp, dtype=np.int64)
+        n = lib().orc_node_nbr(self._h, node, _l(pos), _l(w))
+        return pos[:n].copy(), w[:n].copy()
+
+    def node_sample(self, node):
+        """The sampled rows S' the next skeletonize() uses for a node."""
+        q = np.zeros(self.nsamp, dtype=np.int64)
+        k = lib().orc_node_sample(self._h, node, _l(q))
+        return q[:k].copy()
+
+    def subtree_sample(self, node, kappa):
+        """(list positions, list weights, S') of a node computed from its
+        subtree alone: the same as set_knn(kappa) + node_neighbors/node_sample
+        at the cost of n_node x N distances."""
+        pos = np.zeros(self.nsamp, dtype=np.int64); w = np.zeros(self.nsamp, dtype=np.int64)
+        q = np.zeros(self.nsamp, dtype=np.int64); nl = np.zeros(1, dtype=np.int64)
+        k = lib().orc_subtree_sample(self._h, node, int(kappa), _l(pos), _l(w), _l(nl), _l(q))
+        n = int(nl[0])
+        return pos[:n].copy(), w[:n].copy(), q[:k].copy()
 
     # skeletons ---------------------------------------------------------------
     def skeletonize(self):

@@ -69,6 +69,11 @@ typedef struct {
     int **piv;              /* row interchanges of the LU                  */
     double **Phat;          /* non-root: n_alpha x s_alpha row-major       */
     double *pivratio;       /* min|U_ii| / max|U_ii| per factored block    */
+    /* kappa-nearest-neighbour sampling: 0 = uniform rows only            */
+    int kappa;
+    int64_t *knn;           /* N x kappa neighbour positions (-1 padded)   */
+    int64_t **nbr, **nbrw;  /* per node: ranked neighbour list, weights    */
+    int64_t *nnbr;          /* per node: its length (<= nsamp)             */
     /* level restriction (hybrid solver): 0 = none; L >= 1 = frontier level */
     int hybL;
     int64_t hM;             /* order of the reduced system I + V W          */
@@ -183,6 +188,9 @@ void orc_free(orc_t *o) {
     for (int64_t i = 0; i < o->nnodes; i++) { free(o->skel[i]); free(o->P[i]); }
     free(o->X); free(o->perm); free(o->nb); free(o->ne); free(o->sr); free(o->nc); free(o->trunc);
     free(o->skel); free(o->P); free(o->LU); free(o->piv); free(o->Phat); free(o->pivratio);
+    if (o->nbr)
+        for (int64_t i = 0; i < o->nnodes; i++) { free(o->nbr[i]); free(o->nbrw[i]); }
+    free(o->knn); free(o->nbr); free(o->nbrw); free(o->nnbr);
     free(o);
 }
 
@@ -321,7 +329,11 @@ static void split_node(orc_t *o, int64_t b, int64_t e) {
     free(part); free(mu); free(S); free(v); free(kv);
 }
 
+int orc_set_knn(orc_t *o, int kappa);
+
 int orc_build_tree(orc_t *o) {
+    o->tree_built = 0;
+    orc_set_knn(o, 0); /* neighbour lists belong to a tree */
     for (int64_t i = 0; i < o->N; i++) o->perm[i] = i;
     for (int l = 0; l < o->D; l++) {
         int64_t f = first_at(l), cnt = (int64_t)1 << l;
@@ -366,9 +378,13 @@ static uint64_t scale_draw(uint64_t u, uint64_t c) {
     return hh + (lh >> 32) + (hl >> 32) + (mid >> 32);
 }
 
-/* Sample positions for the node [b,e).  Returns the number written to q. */
-int64_t orc_sample(uint64_t seed, int64_t problem, int64_t id, int64_t N, int64_t b, int64_t e,
-                   int nsamp, int64_t *q) {
+/* Sample positions for the node [b,e), after the npre positions of pre[]
+ * (distinct, outside the node, npre <= nsamp), which open the list: draws
+ * that repeat any position already in the list are rejected.  When the
+ * complement has at most nsamp positions it is taken whole, in increasing
+ * order, and pre[] is not used.  Returns the number written to q. */
+int64_t orc_sample_prefix(uint64_t seed, int64_t problem, int64_t id, int64_t N, int64_t b, int64_t e,
+                          int nsamp, const int64_t *pre, int64_t npre, int64_t *q) {
     int64_t n = e - b, c = N - n;
     if (c <= 0) return 0;
     if (c <= nsamp) { /* the whole complement, increasing order */
@@ -377,8 +393,9 @@ int64_t orc_sample(uint64_t seed, int64_t problem, int64_t id, int64_t N, int64_
         for (int64_t i = e; i < N; i++) q[k++] = i;
         return k;
     }
-    uint64_t st = orc_node_seed(seed, problem, id);
     int64_t k = 0;
+    for (int64_t t = 0; t < npre && k < nsamp; t++) q[k++] = pre[t];
+    uint64_t st = orc_node_seed(seed, problem, id);
     while (k < nsamp) {
         int64_t r = (int64_t)scale_draw(orc_splitmix64(&st), (uint64_t)c);
         int64_t pos = r < b ? r : r + n;
@@ -388,6 +405,202 @@ int64_t orc_sample(uint64_t seed, int64_t problem, int64_t id, int64_t N, int64_
         if (!dup) q[k++] = pos;
     }
     return k;
+}
+
+/* uniform rows only */
+int64_t orc_sample(uint64_t seed, int64_t problem, int64_t id, int64_t N, int64_t b, int64_t e,
+                   int nsamp, int64_t *q) {
+    return orc_sample_prefix(seed, problem, id, N, b, e, nsamp, NULL, 0, q);
+}
+
+/* ------------------------------------------------------------------------ */
+/* kappa-nearest-neighbour importance sampling: the kappa of Sec. 4 (the    */
+/* number of nearest neighbours the skeletonization sampling uses, Table    */
+/* "speedup"), after the ASKIT library the paper builds on (Sec. 2.1 cites  */
+/* it for the sampling).  Reading: a row is important for a node when it is */
+/* among the kappa nearest neighbours of the node's points.                 */
+/*  * neighbours: the kappa points nearest to each point (itself excluded), */
+/*    ordered by (squared distance, position), the distance summed by       */
+/*    direct differences in increasing dimension (sqdist); -1 pads lists of */
+/*    N - 1 < kappa points;                                                 */
+/*  * a leaf's list: every neighbour of its points that lies outside it,    */
+/*    weighted by the number of its points that have it as a neighbour; an  */
+/*    internal node's list: its children's lists merged (weights of equal   */
+/*    positions added) with the positions inside the node dropped;          */
+/*    ranked by weight, largest first, lowest position on ties, and cut to  */
+/*    the sample size;                                                      */
+/*  * the sample S' of a node: its list first, in rank order, then uniform  */
+/*    draws (orc_sample_prefix) up to the sample size.                      */
+/* ------------------------------------------------------------------------ */
+
+/* (d2, pos) before (d2', pos') */
+static int nn_before(double da, int64_t pa, double db, int64_t pb) { return da < db || (da == db && pa < pb); }
+
+/* the kappa nearest positions of position i, by brute force over all N */
+static void knn_row(const orc_t *o, int64_t i, int kappa, int64_t *idx, double *dist) {
+    int cnt = 0;
+    const double *x = pt(o, i);
+    for (int64_t j = 0; j < o->N; j++) {
+        if (j == i) continue;
+        double r2 = sqdist(x, pt(o, j), o->d);
+        if (cnt == kappa && !nn_before(r2, j, dist[kappa - 1], idx[kappa - 1])) continue;
+        int p = cnt < kappa ? cnt++ : kappa - 1;
+        while (p > 0 && nn_before(r2, j, dist[p - 1], idx[p - 1])) {
+            dist[p] = dist[p - 1];
+            idx[p] = idx[p - 1];
+            p--;
+        }
+        dist[p] = r2;
+        idx[p] = j;
+    }
+    for (int t = cnt; t < kappa; t++) idx[t] = -1;
+}
+
+typedef struct { int64_t pos, w; } nbr_t;
+static int by_pos(const void *a, const void *b) {
+    int64_t x = ((const nbr_t *)a)->pos, y = ((const nbr_t *)b)->pos;
+    return x < y ? -1 : x > y;
+}
+static int by_rank(const void *a, const void *b) {
+    const nbr_t *x = (const nbr_t *)a, *y = (const nbr_t *)b;
+    if (x->w != y->w) return x->w > y->w ? -1 : 1;
+    return x->pos < y->pos ? -1 : x->pos > y->pos;
+}
+
+/* entries E[0..n) (overwritten): drop positions in [b,e), add the weights of
+ * equal positions, rank, keep the first cap; returns the length */
+static int64_t rank_entries(nbr_t *E, int64_t n, int64_t b, int64_t e, int64_t cap, int64_t **pos, int64_t **w) {
+    int64_t k = 0;
+    for (int64_t i = 0; i < n; i++)
+        if (E[i].pos < b || E[i].pos >= e) E[k++] = E[i];
+    qsort(E, (size_t)k, sizeof(nbr_t), by_pos);
+    int64_t u = 0;
+    for (int64_t i = 0; i < k;) {
+        int64_t j = i, acc = 0;
+        while (j < k && E[j].pos == E[i].pos) acc += E[j++].w;
+        E[u].pos = E[i].pos;
+        E[u].w = acc;
+        u++;
+        i = j;
+    }
+    qsort(E, (size_t)u, sizeof(nbr_t), by_rank);
+    int64_t len = u < cap ? u : cap;
+    *pos = (int64_t *)malloc(sizeof(int64_t) * (len > 0 ? len : 1));
+    *w = (int64_t *)malloc(sizeof(int64_t) * (len > 0 ? len : 1));
+    for (int64_t t = 0; t < len; t++) { (*pos)[t] = E[t].pos; (*w)[t] = E[t].w; }
+    return len;
+}
+
+/* lists of every node of the subtree of `top`, bottom-up; rows[i - nb[top]]
+ * holds the kappa neighbours of position i of that subtree */
+static void subtree_lists(orc_t *o, int64_t top, const int64_t *rows, int kappa, int64_t **pos, int64_t **w,
+                          int64_t *len) {
+    int ltop = level_of(top);
+    int64_t base = o->nb[top];
+    for (int l = o->D; l >= ltop; l--) {
+        int64_t span = (int64_t)1 << (l - ltop), f = first_at(l) + (top - first_at(ltop)) * span;
+#pragma omp parallel for schedule(dynamic)
+        for (int64_t j = 0; j < span; j++) {
+            int64_t id = f + j, b = o->nb[id], e = o->ne[id];
+            nbr_t *E;
+            int64_t n = 0;
+            if (l == o->D) {
+                E = (nbr_t *)malloc(sizeof(nbr_t) * ((e - b) * kappa + 1));
+                for (int64_t i = b; i < e; i++)
+                    for (int t = 0; t < kappa; t++) {
+                        int64_t q = rows[(i - base) * kappa + t];
+                        if (q >= 0) { E[n].pos = q; E[n].w = 1; n++; }
+                    }
+            } else {
+                int64_t cl = 2 * id + 1, cr = 2 * id + 2;
+                E = (nbr_t *)malloc(sizeof(nbr_t) * (len[cl] + len[cr] + 1));
+                for (int64_t t = 0; t < len[cl]; t++) { E[n].pos = pos[cl][t]; E[n].w = w[cl][t]; n++; }
+                for (int64_t t = 0; t < len[cr]; t++) { E[n].pos = pos[cr][t]; E[n].w = w[cr][t]; n++; }
+            }
+            free(pos[id]); free(w[id]);
+            len[id] = rank_entries(E, n, b, e, o->nsamp, &pos[id], &w[id]);
+            free(E);
+        }
+    }
+}
+
+/* Neighbours of every point and the ranked list of every node (kappa >= 1);
+ * kappa = 0 returns to uniform sampling.  Takes effect at the next
+ * skeletonization. */
+int orc_set_knn(orc_t *o, int kappa) {
+    if (kappa < 0) return ORC_ERR_ARG;
+    if (kappa > 0 && !o->tree_built) return ORC_ERR_STATE;
+    if (o->nbr)
+        for (int64_t i = 0; i < o->nnodes; i++) { free(o->nbr[i]); free(o->nbrw[i]); }
+    free(o->knn); free(o->nbr); free(o->nbrw); free(o->nnbr);
+    o->knn = NULL; o->nbr = NULL; o->nbrw = NULL; o->nnbr = NULL;
+    o->kappa = kappa;
+    if (kappa == 0) return ORC_OK;
+    o->knn = (int64_t *)malloc(sizeof(int64_t) * o->N * kappa);
+    o->nbr = (int64_t **)calloc(o->nnodes, sizeof(int64_t *));
+    o->nbrw = (int64_t **)calloc(o->nnodes, sizeof(int64_t *));
+    o->nnbr = (int64_t *)calloc(o->nnodes, sizeof(int64_t));
+    if (!o->knn || !o->nbr || !o->nbrw || !o->nnbr) return ORC_ERR_ALLOC;
+#pragma omp parallel
+    {
+        double *dist = (double *)malloc(sizeof(double) * kappa);
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < o->N; i++) knn_row(o, i, kappa, o->knn + i * kappa, dist);
+        free(dist);
+    }
+    subtree_lists(o, 0, o->knn, kappa, o->nbr, o->nbrw, o->nnbr);
+    return ORC_OK;
+}
+
+void orc_get_knn(const orc_t *o, int64_t *out) { memcpy(out, o->knn, sizeof(int64_t) * o->N * o->kappa); }
+
+/* a node's list: returns its length, copies positions and weights */
+int64_t orc_node_nbr(const orc_t *o, int64_t id, int64_t *pos, int64_t *w) {
+    if (!o->nbr) return 0;
+    memcpy(pos, o->nbr[id], sizeof(int64_t) * o->nnbr[id]);
+    memcpy(w, o->nbrw[id], sizeof(int64_t) * o->nnbr[id]);
+    return o->nnbr[id];
+}
+
+/* The neighbours of the positions [b, e) alone (brute force against all N),
+ * for checks on problems too large for orc_set_knn. */
+void orc_knn_rows(const orc_t *o, int64_t b, int64_t e, int kappa, int64_t *out) {
+#pragma omp parallel
+    {
+        double *dist = (double *)malloc(sizeof(double) * kappa);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = b; i < e; i++) knn_row(o, i, kappa, out + (i - b) * kappa, dist);
+        free(dist);
+    }
+}
+
+/* The list and sample of node `id` computed from its subtree only (the
+ * neighbours of its points by brute force, the lists of its descendants):
+ * what orc_set_knn and the sampler give that node, at a cost of
+ * n_id x N distances.  Returns the sample size; *nl = list length. */
+int64_t orc_subtree_sample(orc_t *o, int64_t id, int kappa, int64_t *lpos, int64_t *lw, int64_t *nl, int64_t *q) {
+    int64_t b = o->nb[id], e = o->ne[id];
+    int64_t *rows = (int64_t *)malloc(sizeof(int64_t) * (e - b) * kappa);
+    int64_t **pos = (int64_t **)calloc(o->nnodes, sizeof(int64_t *));
+    int64_t **w = (int64_t **)calloc(o->nnodes, sizeof(int64_t *));
+    int64_t *len = (int64_t *)calloc(o->nnodes, sizeof(int64_t));
+    orc_knn_rows(o, b, e, kappa, rows);
+    subtree_lists(o, id, rows, kappa, pos, w, len);
+    *nl = len[id];
+    memcpy(lpos, pos[id], sizeof(int64_t) * len[id]);
+    memcpy(lw, w[id], sizeof(int64_t) * len[id]);
+    int64_t ns = orc_sample_prefix(o->seed, o->problem, id, o->N, b, e, o->nsamp, pos[id], len[id], q);
+    for (int64_t i = 0; i < o->nnodes; i++) { free(pos[i]); free(w[i]); }
+    free(pos); free(w); free(len); free(rows);
+    return ns;
+}
+
+/* The sample S' the skeletonization uses for node id (uniform, or with the
+ * node's neighbour list first). */
+int64_t orc_node_sample(const orc_t *o, int64_t id, int64_t *q) {
+    const int64_t *pre = o->kappa > 0 ? o->nbr[id] : NULL;
+    int64_t npre = o->kappa > 0 ? o->nnbr[id] : 0;
+    return orc_sample_prefix(o->seed, o->problem, id, o->N, o->nb[id], o->ne[id], o->nsamp, pre, npre, q);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -525,7 +738,7 @@ static int skeletonize_node(orc_t *o, int64_t id) {
         return ORC_OK;
     }
     int64_t *q = (int64_t *)malloc(sizeof(int64_t) * o->nsamp);
-    int64_t ns = orc_sample(o->seed, o->problem, id, o->N, b, e, o->nsamp, q);
+    int64_t ns = orc_node_sample(o, id, q);
     double *M = (double *)malloc(sizeof(double) * ns * ncand);
     for (int c = 0; c < ncand; c++)
         for (int64_t i = 0; i < ns; i++) M[(int64_t)c * ns + i] = kpos(o, q[i], cand[c], 0);
