@@ -75,7 +75,19 @@ typedef struct askit_factor_s *askit_factor;
  * (0 -> L = D - 1, every internal level, in askit_skeletonize and
  * L = min(D - 1, 9), the levels with fewer than 1024 nodes, in
  * askit_skeletonize_factorize; -1 -> none).  Both shapes give bit-identical
- * skeletons. */
+ * skeletons.
+ * knn = kappa of the nearest-neighbour importance sampling (the number of
+ * neighbours the skeletonization sampling uses, Sec. 4, Table "speedup"); 0
+ * samples uniform rows only.  With kappa > 0 the tree build also finds the
+ * kappa nearest points of every point (exact, by squared distance summed
+ * as fma(t, t, r2) over t = x_k - y_k in increasing k, ties to the lower
+ * tree position) and ranks, for every node, the neighbours of its points
+ * that lie outside it: a leaf weighs each by the number of its points that
+ * have it as a neighbour, an internal node merges its children's lists
+ * (weights added) and drops its own points; largest weight first, lowest
+ * position on ties, cut to n_samples.  A node's sampled rows are its list,
+ * then uniform draws as with knn = 0 (repeats of listed rows rejected).
+ * In [0, 64] ([0, 32] for d > 32), knn * N < 2^31. */
 typedef struct {
     int32_t leaf_size;
     int32_t rank;
@@ -85,6 +97,8 @@ typedef struct {
     int64_t problem;
     double h;
     double tol;
+    int32_t knn;
+    int32_t reserved;  /* 0 */
 } askit_options;
 
 /* Tree build (Sec. 2.1, "Partitioning the matrix"): complete binary tree of
@@ -94,11 +108,23 @@ typedef struct {
  * Blocks until the tree is built.  Errors: ASKIT_ERR_ARG for N < 1 or
  * N >= 2^31, d < 1 or d > 64, m < 2, s < 1, h <= 0 or not finite, tol
  * outside [0, 1), non-finite coordinates, n_samples < 0 or > 4096,
- * qr_split_levels < -1, a largest leaf ceil(N / 2^D) above 512 points or
- * 2 s above 512 (the kernels hold a leaf block and a reduced system of order
- * s_l + s_r in one workgroup). */
+ * qr_split_levels < -1, knn outside its range, a largest leaf ceil(N / 2^D)
+ * above 512 points or 2 s above 512 (the kernels hold a leaf block and a
+ * reduced system of order s_l + s_r in one workgroup). */
 askit_status askit_build_tree(const double *X, int64_t N, int32_t d, const askit_options *opt, void *stream,
                               askit_tree *out);
+
+/* The kappa nearest neighbours of every point found by the tree build
+ * (knn > 0): idx[i * kappa + t] = tree position of the t-th nearest point
+ * of tree position i (t = 0 nearest; -1 where N - 1 < kappa).  idx: device
+ * or host, N x kappa int32.  Errors: ASKIT_ERR_STATE if knn = 0. */
+askit_status askit_tree_knn(askit_tree t, int32_t *idx);
+
+/* The ranked neighbour lists of the nodes (knn > 0; see askit_options):
+ * node id's list is pos[id * n_samples + k], weight[id * n_samples + k] for
+ * k < len[id] (the root's is empty).  pos, weight: nnodes x n_samples int32;
+ * len: nnodes int32; device or host.  Errors: ASKIT_ERR_STATE if knn = 0. */
+askit_status askit_tree_neighbor_lists(askit_tree t, int32_t *pos, int32_t *weight, int32_t *len);
 
 /* Tree depth D and the permutation (perm[position] = original index). */
 askit_status askit_tree_depth(askit_tree t, int32_t *D);

@@ -421,8 +421,8 @@ int64_t orc_sample(uint64_t seed, int64_t problem, int64_t id, int64_t N, int64_
 /* among the kappa nearest neighbours of the node's points.                 */
 /*  * neighbours: the kappa points nearest to each point (itself excluded), */
 /*    ordered by (squared distance, position), the distance summed by       */
-/*    direct differences in increasing dimension (sqdist); -1 pads lists of */
-/*    N - 1 < kappa points;                                                 */
+/*    direct differences in increasing dimension (nn_dist); -1 pads lists   */
+/*    of N - 1 < kappa points;                                              */
 /*  * a leaf's list: every neighbour of its points that lies outside it,    */
 /*    weighted by the number of its points that have it as a neighbour; an  */
 /*    internal node's list: its children's lists merged (weights of equal   */
@@ -433,6 +433,17 @@ int64_t orc_sample(uint64_t seed, int64_t problem, int64_t id, int64_t N, int64_
 /*    draws (orc_sample_prefix) up to the sample size.                      */
 /* ------------------------------------------------------------------------ */
 
+/* squared distance of the neighbour search: fma(t, t, r2) over
+ * t = x_k - y_k in increasing dimension (one rounding per term) */
+static double nn_dist(const double *x, const double *y, int d) {
+    double r2 = 0.0;
+    for (int k = 0; k < d; k++) {
+        double t = x[k] - y[k];
+        r2 = fma(t, t, r2);
+    }
+    return r2;
+}
+
 /* (d2, pos) before (d2', pos') */
 static int nn_before(double da, int64_t pa, double db, int64_t pb) { return da < db || (da == db && pa < pb); }
 
@@ -442,7 +453,7 @@ static void knn_row(const orc_t *o, int64_t i, int kappa, int64_t *idx, double *
     const double *x = pt(o, i);
     for (int64_t j = 0; j < o->N; j++) {
         if (j == i) continue;
-        double r2 = sqdist(x, pt(o, j), o->d);
+        double r2 = nn_dist(x, pt(o, j), o->d);
         if (cnt == kappa && !nn_before(r2, j, dist[kappa - 1], idx[kappa - 1])) continue;
         int p = cnt < kappa ? cnt++ : kappa - 1;
         while (p > 0 && nn_before(r2, j, dist[p - 1], idx[p - 1])) {

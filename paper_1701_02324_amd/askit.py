@@ -27,7 +27,7 @@ EXPORTED = [
     "askit_batch_create", "askit_batch_factorize", "askit_batch_check", "askit_batch_solve", "askit_batch_factor",
     "askit_batch_destroy", "askit_skeletonize_factorize", "askit_release_cached_memory",
     "askit_factorize_batched", "askit_tree_qr_rows", "askit_tree_samples", "askit_tree_permutation_noalloc",
-    "askit_factorize_hybrid",
+    "askit_factorize_hybrid", "askit_tree_knn", "askit_tree_neighbor_lists",
 ]
 
 
@@ -40,7 +40,8 @@ class AskitError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("leaf_size", ctypes.c_int32), ("rank", ctypes.c_int32), ("n_samples", ctypes.c_int32),
                 ("qr_split_levels", ctypes.c_int32), ("seed", ctypes.c_uint64), ("problem", ctypes.c_int64),
-                ("h", ctypes.c_double), ("tol", ctypes.c_double)]
+                ("h", ctypes.c_double), ("tol", ctypes.c_double), ("knn", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -68,6 +69,8 @@ def load(path: str = LIB_PATH):
     L.askit_tree_perm.argtypes = [_vp, _vp]
     L.askit_tree_qr_rows.argtypes = [_vp, _vp]
     L.askit_tree_samples.argtypes = [_vp, _vp]
+    L.askit_tree_knn.argtypes = [_vp, _vp]
+    L.askit_tree_neighbor_lists.argtypes = [_vp, _vp, _vp, _vp]
     L.askit_tree_permutation_noalloc.argtypes = [_vp, _i64, _i32, _i32, _vp, _vp]
     L.askit_skeletonize.argtypes = [_vp, _vp]
     L.askit_skeletons_export.argtypes = [_vp, _vp, _vp, _vp]
@@ -136,11 +139,11 @@ def _colmajor(B):
 # ---------------------------------------------------------------------------
 
 def askit_build_tree(X, leaf_size, rank, h, n_samples=0, seed=0, problem=0, stream=None, qr_split_levels=0,
-                     tol=0.0):
+                     tol=0.0, knn=0):
     X = _dev64(X, "X").contiguous()
     N, d = X.shape
     opt = Options(int(leaf_size), int(rank), int(n_samples), int(qr_split_levels), int(seed) & 0xFFFFFFFFFFFFFFFF,
-                  int(problem), float(h), float(tol))
+                  int(problem), float(h), float(tol), int(knn), 0)
     out = _vp()
     _check(load().askit_build_tree(_vp(X.data_ptr()), N, d, ctypes.byref(opt), _stream(stream), ctypes.byref(out)))
     return out
@@ -186,6 +189,24 @@ def askit_tree_samples(tree, nnodes, nsamp):
     out = np.zeros(nnodes * nsamp, dtype=np.int32)
     _check(load().askit_tree_samples(tree, out.ctypes.data))
     return out.reshape(nnodes, nsamp)
+
+
+def askit_tree_knn(tree, N, kappa):
+    """The kappa nearest tree positions of every tree position (numpy int32, N x kappa)."""
+    import numpy as np
+    out = np.zeros(N * kappa, dtype=np.int32)
+    _check(load().askit_tree_knn(tree, out.ctypes.data))
+    return out.reshape(N, kappa)
+
+
+def askit_tree_neighbor_lists(tree, nnodes, nsamp):
+    """(positions, weights, lengths) of every node's ranked neighbour list."""
+    import numpy as np
+    pos = np.zeros(nnodes * nsamp, dtype=np.int32)
+    w = np.zeros(nnodes * nsamp, dtype=np.int32)
+    n = np.zeros(nnodes, dtype=np.int32)
+    _check(load().askit_tree_neighbor_lists(tree, pos.ctypes.data, w.ctypes.data, n.ctypes.data))
+    return pos.reshape(nnodes, nsamp), w.reshape(nnodes, nsamp), n
 
 
 def askit_skeletonize(tree, stream=None):
@@ -344,13 +365,14 @@ class Tree:
     """Tree + skeletons of one problem (points X on the GPU, FP64)."""
 
     def __init__(self, X, leaf_size, rank, h, n_samples=0, seed=0, problem=0, stream=None, qr_split_levels=0,
-                 tol=0.0):
+                 tol=0.0, knn=0):
         self.N, self.d = X.shape
         self.m, self.s, self.h = int(leaf_size), int(rank), float(h)
         self.nsamp = int(n_samples) or 4 * self.s
         self.tol = float(tol)
+        self.knn = int(knn)
         self.handle = askit_build_tree(X, leaf_size, rank, h, n_samples, seed, problem, stream, qr_split_levels,
-                                       tol)
+                                       tol, knn)
         self.D = askit_tree_depth(self.handle)
         self.nnodes = (2 << self.D) - 1
         self.mmax = -(-self.N // (1 << self.D))
@@ -375,6 +397,14 @@ class Tree:
     def samples(self):
         """Sampled rows of each node's ID (nnodes x n_samples tree positions)."""
         return askit_tree_samples(self.handle, self.nnodes, self.nsamp)
+
+    def neighbors(self):
+        """kappa nearest tree positions of every tree position (knn > 0)."""
+        return askit_tree_knn(self.handle, self.N, self.knn)
+
+    def neighbor_lists(self):
+        """(positions, weights, lengths) of the nodes' ranked neighbour lists (knn > 0)."""
+        return askit_tree_neighbor_lists(self.handle, self.nnodes, self.nsamp)
 
     def qr_rows(self):
         """Rows of the sampled block each node's QR factored (0: no QR)."""

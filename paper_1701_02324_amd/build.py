@@ -22,9 +22,9 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INC, "-I
           # packed FP32 instructions are kept out of the generated code
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument"]
-# per-file extra flags: the tree build fixes the rounding of every operation
-EXTRA = {"k_tree.hip": ["-ffp-contract=off"]}
-SOURCES = ["api.hip", "k_tree.hip", "k_skel.hip", "k_lu.hip", "k_prod.hip", "k_misc.hip"]
+# per-file extra flags: the tree build and the neighbour search fix the rounding of every operation
+EXTRA = {"k_tree.hip": ["-ffp-contract=off"], "k_knn.hip": ["-ffp-contract=off"]}
+SOURCES = ["api.hip", "k_tree.hip", "k_skel.hip", "k_lu.hip", "k_prod.hip", "k_misc.hip", "k_knn.hip"]
 
 
 def hipcc() -> str:

@@ -702,6 +702,10 @@ struct askit_tree_s {
     double h = 1.0;      // bandwidth of the skeletonization
     double hfac = 1.0;   // bandwidth of the next factorization (skeletons frozen)
     double tol = 0.0;    // adaptive rank tolerance tau (0: fixed rank s)
+    int knn = 0;         // kappa of the neighbour sampling (0: uniform rows)
+    DBuf knnidx, nbpos, nbw, nblen;  // N x kappa neighbours; per node: ranked list (nsamp slots), length
+    std::vector<int32_t> hnn;        // host copy of the list lengths
+    double t_knn = 0;
     std::vector<int64_t> nb, ne;  // host node ranges
     DBuf X, Xp, perm, iperm, dnb, dne;  // iperm[original index] = tree position
     DBuf srank, trunc, skel, Pt, samp, qrows;
@@ -817,6 +821,79 @@ askit_status askit_profile_report(char *json, size_t cap) {
 // ---------------------------------------------------------------------------
 // tree
 // ---------------------------------------------------------------------------
+}  // extern "C"
+
+// Neighbours of every point (exact, k_knn) and the ranked neighbour list of
+// every non-root node, bottom-up (k_nbr_rank); list lengths copied to the host.
+template <int K>
+static void launch_knn(int dpad, const double *Xp, int64_t N, int d, const double *lo, const double *hi, int kappa,
+                       int32_t *out, hipStream_t st) {
+    const dim3 g((unsigned)cdiv(N, kWave)), b(kWave);
+    if (dpad == 16) hipLaunchKernelGGL((k_knn<K, 16>), g, b, 0, st, Xp, N, d, lo, hi, kappa, out);
+    else if (dpad == 32) hipLaunchKernelGGL((k_knn<K, 32>), g, b, 0, st, Xp, N, d, lo, hi, kappa, out);
+    else if constexpr (K <= 32) hipLaunchKernelGGL((k_knn<K, 64>), g, b, 0, st, Xp, N, d, lo, hi, kappa, out);
+}
+
+static askit_status build_neighbor_lists(askit_tree t, hipStream_t st) {
+    const int64_t N = t->N;
+    const int d = t->d, kappa = t->knn;
+    const int dpad = d <= 16 ? 16 : (d <= 32 ? 32 : 64);
+    const int64_t nrun = cdiv(N, 64);
+    DBuf lo, hi, scratch;
+    ST_TRY(lo.alloc(sizeof(double) * nrun * dpad));
+    ST_TRY(hi.alloc(sizeof(double) * nrun * dpad));
+    ST_TRY(t->knnidx.alloc(sizeof(int32_t) * N * kappa));
+    ST_TRY(t->nbpos.alloc(sizeof(int32_t) * t->nnodes * t->nsamp));
+    ST_TRY(t->nbw.alloc(sizeof(int32_t) * t->nnodes * t->nsamp));
+    ST_TRY(t->nblen.alloc(sizeof(int32_t) * t->nnodes));
+    HIP_TRY(hipMemsetAsync(t->nblen.p, 0, sizeof(int32_t) * t->nnodes, st));
+    HIP_TRY(timed("tree:k_knn_boxes", st, [&] {
+        hipLaunchKernelGGL(k_knn_boxes, dim3(grid1(nrun * dpad)), dim3(256), 0, st, t->Xp.as<double>(), N, d, dpad,
+                           lo.as<double>(), hi.as<double>());
+        return hipGetLastError();
+    }));
+    HIP_TRY(timed("tree:k_knn", st, [&] {
+        const double *Xp = t->Xp.as<double>();
+        int32_t *o = t->knnidx.as<int32_t>();
+        if (kappa <= 8) launch_knn<8>(dpad, Xp, N, d, lo.as<double>(), hi.as<double>(), kappa, o, st);
+        else if (kappa <= 16) launch_knn<16>(dpad, Xp, N, d, lo.as<double>(), hi.as<double>(), kappa, o, st);
+        else if (kappa <= 32) launch_knn<32>(dpad, Xp, N, d, lo.as<double>(), hi.as<double>(), kappa, o, st);
+        else launch_knn<64>(dpad, Xp, N, d, lo.as<double>(), hi.as<double>(), kappa, o, st);
+        return hipGetLastError();
+    }));
+    for (int l = t->D; l >= 1; l--) {
+        NbrTask nt{};
+        nt.nb = t->dnb.as<int64_t>();
+        nt.ne = t->dne.as<int64_t>();
+        nt.knn = t->knnidx.as<int32_t>();
+        nt.pos = t->nbpos.as<int32_t>();
+        nt.w = t->nbw.as<int32_t>();
+        nt.len = t->nblen.as<int32_t>();
+        nt.kappa = kappa;
+        nt.cap = t->nsamp;
+        nt.leaf = l == t->D;
+        const int64_t cnt = (int64_t)1 << l, nent = nt.leaf ? (int64_t)t->mmax * kappa : 2 * (int64_t)t->nsamp;
+        int64_t pmax = 2;
+        while (pmax < nent) pmax <<= 1;
+        if (pmax > kNbrLds) ST_TRY(scratch.alloc(sizeof(uint64_t) * cnt * 2 * pmax));
+        HIP_TRY(timed("tree:k_nbr_rank", st, [&] {
+            hipLaunchKernelGGL(k_nbr_rank, dim3((unsigned)cnt), dim3(kNbrThreads), 0, st, nt, t->first(l), pmax,
+                               pmax > kNbrLds ? scratch.as<uint64_t>() : nullptr);
+            return hipGetLastError();
+        }));
+        if (pmax > kNbrLds) {
+            HIP_TRY(hipStreamSynchronize(st));  // the scratch of this level is released next
+            scratch.release();
+        }
+    }
+    t->hnn.assign(t->nnodes, 0);
+    HIP_TRY(hipMemcpyAsync(t->hnn.data(), t->nblen.p, sizeof(int32_t) * t->nnodes, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return ASKIT_OK;
+}
+
+extern "C" {
+
 askit_status askit_build_tree(const double *X, int64_t N, int32_t d, const askit_options *opt, void *stream,
                               askit_tree *out) {
     if (!out) return fail(ASKIT_ERR_ARG, "out is NULL");
@@ -830,6 +907,9 @@ askit_status askit_build_tree(const double *X, int64_t N, int32_t d, const askit
     if (opt->n_samples < 0) return fail(ASKIT_ERR_ARG, "n_samples must be >= 0");
     if (opt->qr_split_levels < -1) return fail(ASKIT_ERR_ARG, "qr_split_levels must be >= -1");
     if (!(opt->tol >= 0.0 && opt->tol < 1.0)) return fail(ASKIT_ERR_ARG, "tol must be in [0, 1)");
+    if (opt->knn < 0 || opt->knn > kKnnMax || (d > 32 && opt->knn > 32))
+        return fail(ASKIT_ERR_ARG, "knn must be in [0, 64] (in [0, 32] for d > 32)");
+    if ((int64_t)opt->knn * N >= ((int64_t)1 << 31)) return fail(ASKIT_ERR_ARG, "knn * N must be below 2^31");
     hipStream_t st = (hipStream_t)stream;
     std::unique_ptr<askit_tree_s> t(new askit_tree_s());
     t->N = N;
@@ -843,6 +923,7 @@ askit_status askit_build_tree(const double *X, int64_t N, int32_t d, const askit
     t->h = opt->h;
     t->hfac = opt->h;
     t->tol = opt->tol;
+    t->knn = opt->knn;
     while ((int64_t)t->m * ((int64_t)1 << t->D) < N) t->D++;
     t->nnodes = ((int64_t)2 << t->D) - 1;
     // default: the split QR on every internal level (the pipelined call
@@ -927,7 +1008,29 @@ askit_status askit_build_tree(const double *X, int64_t N, int32_t d, const askit
     HIP_TRY(hipMemsetAsync(t->qrows.p, 0, sizeof(int32_t) * t->nnodes, st));
     HIP_TRY(hipStreamSynchronize(st));
     t->t_tree = ms_since(t0);
+    if (t->knn > 0) {
+        auto t1 = std::chrono::steady_clock::now();
+        ST_TRY(build_neighbor_lists(t.get(), st));
+        t->t_knn = ms_since(t1);
+    }
     *out = t.release();
+    return ASKIT_OK;
+}
+
+askit_status askit_tree_knn(askit_tree t, int32_t *idx) {
+    if (!t || !idx) return fail(ASKIT_ERR_ARG, "NULL argument");
+    if (t->knn <= 0) return fail(ASKIT_ERR_STATE, "the tree was built without neighbour sampling (knn = 0)");
+    HIP_TRY(hipMemcpy(idx, t->knnidx.p, sizeof(int32_t) * t->N * t->knn, hipMemcpyDefault));
+    return ASKIT_OK;
+}
+
+askit_status askit_tree_neighbor_lists(askit_tree t, int32_t *pos, int32_t *weight, int32_t *len) {
+    if (!t || !pos || !weight || !len) return fail(ASKIT_ERR_ARG, "NULL argument");
+    if (t->knn <= 0) return fail(ASKIT_ERR_STATE, "the tree was built without neighbour sampling (knn = 0)");
+    const size_t n = sizeof(int32_t) * t->nnodes * t->nsamp;
+    HIP_TRY(hipMemcpy(pos, t->nbpos.p, n, hipMemcpyDefault));
+    HIP_TRY(hipMemcpy(weight, t->nbw.p, n, hipMemcpyDefault));
+    HIP_TRY(hipMemcpy(len, t->nblen.p, sizeof(int32_t) * t->nnodes, hipMemcpyDefault));
     return ASKIT_OK;
 }
 
@@ -1065,6 +1168,10 @@ struct SkelRun {
                 a.N = t->N;
                 a.state = node_state(t->seed, t->problem, id);
                 a.out = t->samp.as<int32_t>() + id * t->nsamp;
+                if (t->knn > 0) {  // the node's neighbour list opens its sample
+                    a.pre = t->nbpos.as<int32_t>() + id * t->nsamp;
+                    a.npre = t->hnn[id];
+                }
                 k.q = a.out;
                 k.nq = (int32_t)std::min<int64_t>(t->nsamp, t->N - (a.e - a.b));
                 if (l <= split_of(t)) {
@@ -3066,10 +3173,12 @@ askit_status askit_get_stats(askit_tree t, askit_factor f, char *json, size_t ca
     char buf[1024];
     int n = snprintf(buf, sizeof buf,
                      "{\"N\": %lld, \"d\": %d, \"depth\": %d, \"leaf_size\": %d, \"rank\": %d, "
-                     "\"tree_ms\": %.3f, \"skeletonize_ms\": %.3f, \"factorize_ms\": %.3f, \"solve_ms\": %.3f, "
+                     "\"tree_ms\": %.3f, \"knn\": %d, \"knn_ms\": %.3f, \"skeletonize_ms\": %.3f, "
+                     "\"factorize_ms\": %.3f, \"solve_ms\": %.3f, "
                      "\"precision\": \"%s\", \"min_pivot_ratio\": %.3e, \"refine_iterations\": %d}",
                      t ? (long long)t->N : 0LL, t ? t->d : 0, t ? t->D : 0, t ? t->m : 0, t ? t->s : 0,
-                     t ? t->t_tree : 0.0, t ? t->t_skel : 0.0, f ? f->t_factor : 0.0, f ? f->t_solve : 0.0,
+                     t ? t->t_tree : 0.0, t ? t->knn : 0, t ? t->t_knn : 0.0, t ? t->t_skel : 0.0,
+                     f ? f->t_factor : 0.0, f ? f->t_solve : 0.0,
                      f ? (f->prec == P64 ? "fp64" : "mixed") : "none", f ? f->min_ratio : 0.0,
                      f ? f->info.iterations : 0);
     if (n < 0 || (size_t)n >= cap) return fail(ASKIT_ERR_ARG, "buffer too small");

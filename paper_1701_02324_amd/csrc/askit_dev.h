@@ -20,6 +20,9 @@ constexpr int kOneWgLevel = 10;  // pipelined call, by default: tree levels from
 constexpr int kLsThreads = 1024; // batched LU solves: 16 waves keep many block loads in flight
 constexpr int kLuFThreads = 512; // batched LU factorization
 constexpr int kXrDim = 16;       // kernel-block products keep row points in registers up to this dimension
+constexpr int kNbrThreads = 1024; // neighbour-list ranking: threads per node
+constexpr int kNbrLds = 4096;     // neighbour-list ranking: keys sorted in LDS (more go to a scratch slot)
+constexpr int kKnnMax = 64;       // largest kappa of the neighbour search (32 for d > 32)
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
@@ -183,11 +186,23 @@ struct LuTask {
     int32_t nrhs, pad;    // right-hand sides of this task (0: the launch's count)
 };
 
-// Sampling task (uniform rows outside a node, SplitMix64 stream).
+// Sampling task (rows outside a node): the npre positions of pre first (the
+// node's neighbour list), then uniform draws from its SplitMix64 stream.
 struct SampTask {
     int64_t b, e, N;
     uint64_t state;
     int32_t *out;
+    const int32_t *pre;
+    int32_t npre, pad;
+};
+
+// Ranked neighbour lists of the nodes of one level (kappa-NN sampling):
+// list of node id = pos/w[id * cap .. + len[id]).
+struct NbrTask {
+    const int64_t *nb, *ne;  // device node ranges
+    const int32_t *knn;      // N x kappa neighbour positions (-1: none)
+    int32_t *pos, *w, *len;
+    int32_t kappa, cap, leaf, pad;
 };
 
 // Sampled kernel block + QRCP task for one non-root node.

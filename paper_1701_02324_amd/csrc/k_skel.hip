@@ -23,7 +23,8 @@
 namespace askit {
 
 // ---------------------------------------------------------------------------
-// sampling: one wave per node.  Draw i (i = 1, 2, ..) of the node's stream is
+// sampling: one wave per node.  The node's neighbour list (kappa-NN
+// sampling), if any, opens the sample.  Draw i (i = 1, 2, ..) of the node's stream is
 // the SplitMix64 output of state + i * gamma, so the 64 lanes take 64
 // consecutive draws per round.  A draw is kept when its point was drawn
 // neither in an earlier round (open-addressing set in LDS) nor by a lower
@@ -51,9 +52,21 @@ __global__ __launch_bounds__(64) void k_sample(const SampTask *__restrict__ task
     }
     for (int i = lane; i < (1 << kSampHashBits); i += kWave) table[i] = 0;
     __syncthreads();
+    // the neighbour list opens the sample (distinct positions outside the
+    // node); its positions join the set, so draws that repeat them are
+    // rejected like repeated draws
+    const int npre = t.npre < nsamp ? t.npre : nsamp;
+    for (int i = lane; i < npre; i += kWave) {
+        const int32_t pos = t.pre[i];
+        t.out[i] = pos;
+        const uint32_t key = (uint32_t)pos + 1u;
+        for (uint32_t sl = (uint32_t)(((uint64_t)pos * kSplitMixGamma) >> (64 - kSampHashBits));; sl = (sl + 1) & mask)
+            if (atomicCAS(&table[sl], 0, (int32_t)key) == 0) break;
+    }
+    __syncthreads();
     // at most cap draws (a stream that cannot fill the sample is an error)
     const uint64_t cap = 64ULL * (uint64_t)(c + nsamp);
-    int k = 0;
+    int k = npre;
     for (uint64_t base = 0; k < nsamp; base += kWave) {
         const uint64_t i = base + (uint64_t)lane + 1;
         const bool valid = i <= cap;

@@ -32,7 +32,7 @@ def oracle_skeletons(o, rank, cmax):
 EPS = 2.0 ** -52
 
 
-def skeleton_parity(orc_mod, o, X, h, seed, ids, P, sizes, rank, cmax, problem=0, tau=0.0):
+def skeleton_parity(orc_mod, o, X, h, seed, ids, P, sizes, rank, cmax, problem=0, tau=0.0, sampler=None):
     """Node-by-node comparison of exported GPU skeletons with the oracle's,
     from the leaves up.  A node is compared when its candidates agree (a leaf,
     or an internal node whose children both matched).  On each such node the
@@ -48,6 +48,8 @@ def skeleton_parity(orc_mod, o, X, h, seed, ids, P, sizes, rank, cmax, problem=0
         1e-12 |M|_F of the oracle's pivot's, or the ranks differ at a
         diagonal entry that lies within 1e-12 |M|_F of the stopping
         threshold.
+    sampler(node), if given, returns the oracle's sampled rows of a node
+    (neighbour sampling); else the uniform sampler is used.
     Returns a report; failures lists the nodes that break these rules."""
     perm = o.perm()
     nn, D = o.nnodes, o.D
@@ -76,7 +78,7 @@ def skeleton_parity(orc_mod, o, X, h, seed, ids, P, sizes, rank, cmax, problem=0
                 rep["failures"].append((node, "identity skeleton differs"))
             continue
         b, e = o.node_range(node)
-        q = orc_mod.sample(seed, problem, node, o.N, b, e, o.nsamp)
+        q = sampler(node) if sampler else orc_mod.sample(seed, problem, node, o.N, b, e, o.nsamp)
         M = orc_mod.kernel_matrix(X, h, perm[q], perm[cand])
         nM = np.linalg.norm(M)
         rk, piv, rd, T, R, tr = orc_mod.qrcp(M, min(rank, nc), tau)

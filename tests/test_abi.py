@@ -50,6 +50,10 @@ def test_argument_validation_without_gpu(lib):
         (100, 3, A.Options(64, 300, 0, 0, 0, 0, 1.0)),  # 2 s above 512
         (100, 3, A.Options(64, 8, 0, 0, 0, 0, 1.0, -1e-3)),  # tol < 0
         (100, 3, A.Options(64, 8, 0, 0, 0, 0, 1.0, 1.0)),    # tol >= 1
+        (100, 3, A.Options(64, 8, 0, 0, 0, 0, 1.0, 0.0, -1)),  # knn < 0
+        (100, 3, A.Options(64, 8, 0, 0, 0, 0, 1.0, 0.0, 65)),  # knn > 64
+        (100, 40, A.Options(64, 8, 0, 0, 0, 0, 1.0, 0.0, 33)),  # knn > 32 for d > 32
+        (40_000_000, 3, A.Options(512, 8, 0, 0, 0, 0, 1.0, 0.0, 64)),  # knn N >= 2^31
     ]
     for N, d, opt in bad:
         st = lib.askit_build_tree(fake, N, d, ctypes.byref(opt), None, ctypes.byref(out))
@@ -58,6 +62,8 @@ def test_argument_validation_without_gpu(lib):
     assert lib.askit_build_tree(None, 10, 3, ctypes.byref(A.Options(4, 2, 0, 0, 0, 0, 1.0)), None,
                                 ctypes.byref(out)) == A.ASKIT_ERR_ARG
     # NULL handles
+    assert lib.askit_tree_knn(None, fake) == A.ASKIT_ERR_ARG
+    assert lib.askit_tree_neighbor_lists(None, fake, fake, fake) == A.ASKIT_ERR_ARG
     assert lib.askit_skeletonize(None, None) == A.ASKIT_ERR_ARG
     assert lib.askit_factorize(None, 1.0, 0, None, ctypes.byref(out)) == A.ASKIT_ERR_ARG
     assert lib.askit_solve(None, fake, 10, 1, fake, 10, None) == A.ASKIT_ERR_ARG
