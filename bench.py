@@ -407,6 +407,7 @@ def main():
     forms = None
     if not args.no_forms:
         forms = forms_timings(ak, torch, dev, tree, lam, B)
+        forms["knn_sampling"] = knn_sampling_form(ak, torch, dev, c, X, B, tree, lam)
     stable = None
     if not args.no_stable_check:
         stable = stable_config_check(ak, torch, dev, args.tol)
@@ -456,6 +457,79 @@ def _timed(torch, fn, reps=1):
         out = fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - a) / reps, out
+
+
+def knn_sampling_form(ak, torch, dev, c, X, B, tree, lam, kappa=32, rows=64):
+    """kappa-nearest-neighbour importance sampling on the 1M workload (kappa =
+    32) beside the headline's uniform rows: the neighbour search and list
+    ranking (part of the tree build), one FP64 pipelined skeletonize +
+    factorize, the ranks, the 4-RHS direct residual, and the approximation
+    error |Ktilde u - K u| / |K u| on 64 random rows (u ~ N(0,1), K u summed
+    exactly with torch) for both samplings.  k_knn is reported against the
+    FP64 vector peak on the points it actually compared (3 d flops per
+    pair: difference and fma), and against the brute-force pair count."""
+    N, d = X.shape
+    h, m, s, nsamp, seed = c["h"], c["m"], c["s"], c["nsamp"], c["seed"]
+    gen = torch.Generator().manual_seed(5)
+    ridx = torch.randperm(N, generator=gen)[:rows].to(dev)
+    u = B[:, :1].contiguous()
+    Xr = X[ridx]
+    Ku = torch.zeros(rows, 1, dtype=torch.float64, device=dev)
+    for j0 in range(0, N, 1 << 16):
+        d2 = torch.cdist(Xr, X[j0:j0 + (1 << 16)], compute_mode="donot_use_mm_for_euclid_dist") ** 2
+        Ku += torch.exp(-d2 / (2.0 * h * h)) @ u[j0:j0 + (1 << 16)]
+
+    def eps(f):
+        kt = f.matvec(u)[ridx] - lam * u[ridx]
+        return float((kt - Ku).norm() / Ku.norm())
+
+    ak.askit_profile_enable(True)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    tk = ak.Tree(X, m, s, h, n_samples=nsamp, seed=seed, knn=kappa)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - a
+    prof = ak.askit_profile_report()
+    ak.askit_profile_enable(False)
+    st = tk.stats()
+    f = tk.skeletonize_factorize(lam)
+    f.close()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    f = tk.skeletonize_factorize(lam)
+    torch.cuda.synchronize()
+    t_sf = time.perf_counter() - a
+    ranks, _ = tk.skeleton_sizes()
+    _, _, nlen = tk.neighbor_lists()
+    B4 = B[:, :4].contiguous()
+    res = float(((B4 - f.matvec(f.solve(B4))).norm(dim=0) / B4.norm(dim=0)).max())
+    e_knn = eps(f)
+    f.close()
+    fu = tree.factorize(lam, ak.ASKIT_FP64)
+    e_uni = eps(fu)
+    fu.close()
+    ranks_u, _ = tree.skeleton_sizes()
+    tk.close()
+    lv = lambda r: [round(float(r[(1 << l) - 1:(2 << l) - 1].mean()), 1) for l in range(1, len(r).bit_length())]
+    knn_ms = prof.get("tree:k_knn", (0.0, 1))[0]
+    pairs = float(st["knn_wave_points"]) * 64.0
+    out = {
+        "kappa": kappa, "tree_build_s": t_build, "neighbour_search_and_lists_s": st["knn_ms"] / 1e3,
+        "kernels_ms": {k: round(v[0], 3) for k, v in prof.items() if k.startswith("tree:k_knn") or
+                       k.startswith("tree:k_nbr")},
+        "k_knn_roofline": {"bound": "alu", "pairs_compared": pairs, "achieved": 3.0 * d * pairs / (knn_ms * 1e-3) / 1e12,
+                           "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                           "brute_force_pairs": float(N) * (N - 1),
+                           "brute_force_equivalent_tflops": 3.0 * d * N * (N - 1.0) / (knn_ms * 1e-3) / 1e12},
+        "mean_list_length_by_level": lv(nlen.astype(np.float64)),
+        "skeletonize_factorize_s": t_sf, "direct_residual_4rhs": res,
+        "mean_rank_by_level": {"knn": lv(ranks.astype(np.float64)), "uniform": lv(ranks_u.astype(np.float64))},
+        "approx_error_64_rows": {"knn": e_knn, "uniform": e_uni},
+    }
+    r = out["k_knn_roofline"]
+    r["frac"] = r["achieved"] / r["peak"]
+    log(f"[bench] knn sampling: {out}")
+    return out
 
 
 def forms_timings(ak, torch, dev, tree, lam, B):

@@ -706,6 +706,7 @@ struct askit_tree_s {
     DBuf knnidx, nbpos, nbw, nblen;  // N x kappa neighbours; per node: ranked list (nsamp slots), length
     std::vector<int32_t> hnn;        // host copy of the list lengths
     double t_knn = 0;
+    unsigned long long knn_points = 0;  // points the neighbour search compared, summed over its waves
     std::vector<int64_t> nb, ne;  // host node ranges
     DBuf X, Xp, perm, iperm, dnb, dne;  // iperm[original index] = tree position
     DBuf srank, trunc, skel, Pt, samp, qrows;
@@ -827,11 +828,12 @@ askit_status askit_profile_report(char *json, size_t cap) {
 // every non-root node, bottom-up (k_nbr_rank); list lengths copied to the host.
 template <int K>
 static void launch_knn(int dpad, const double *Xp, int64_t N, int d, const double *lo, const double *hi, int kappa,
-                       int32_t *out, hipStream_t st) {
+                       int32_t *out, unsigned long long *visits, hipStream_t st) {
     const dim3 g((unsigned)cdiv(N, kWave)), b(kWave);
-    if (dpad == 16) hipLaunchKernelGGL((k_knn<K, 16>), g, b, 0, st, Xp, N, d, lo, hi, kappa, out);
-    else if (dpad == 32) hipLaunchKernelGGL((k_knn<K, 32>), g, b, 0, st, Xp, N, d, lo, hi, kappa, out);
-    else if constexpr (K <= 32) hipLaunchKernelGGL((k_knn<K, 64>), g, b, 0, st, Xp, N, d, lo, hi, kappa, out);
+    if (dpad == 16) hipLaunchKernelGGL((k_knn<K, 16>), g, b, 0, st, Xp, N, d, lo, hi, kappa, out, visits);
+    else if (dpad == 32) hipLaunchKernelGGL((k_knn<K, 32>), g, b, 0, st, Xp, N, d, lo, hi, kappa, out, visits);
+    else if constexpr (K <= 32)
+        hipLaunchKernelGGL((k_knn<K, 64>), g, b, 0, st, Xp, N, d, lo, hi, kappa, out, visits);
 }
 
 static askit_status build_neighbor_lists(askit_tree t, hipStream_t st) {
@@ -839,7 +841,9 @@ static askit_status build_neighbor_lists(askit_tree t, hipStream_t st) {
     const int d = t->d, kappa = t->knn;
     const int dpad = d <= 16 ? 16 : (d <= 32 ? 32 : 64);
     const int64_t nrun = cdiv(N, 64);
-    DBuf lo, hi, scratch;
+    DBuf lo, hi, scratch, visits;
+    ST_TRY(visits.alloc(sizeof(unsigned long long)));
+    HIP_TRY(hipMemsetAsync(visits.p, 0, sizeof(unsigned long long), st));
     ST_TRY(lo.alloc(sizeof(double) * nrun * dpad));
     ST_TRY(hi.alloc(sizeof(double) * nrun * dpad));
     ST_TRY(t->knnidx.alloc(sizeof(int32_t) * N * kappa));
@@ -853,12 +857,13 @@ static askit_status build_neighbor_lists(askit_tree t, hipStream_t st) {
         return hipGetLastError();
     }));
     HIP_TRY(timed("tree:k_knn", st, [&] {
-        const double *Xp = t->Xp.as<double>();
+        const double *Xp = t->Xp.as<double>(), *L = lo.as<double>(), *H = hi.as<double>();
         int32_t *o = t->knnidx.as<int32_t>();
-        if (kappa <= 8) launch_knn<8>(dpad, Xp, N, d, lo.as<double>(), hi.as<double>(), kappa, o, st);
-        else if (kappa <= 16) launch_knn<16>(dpad, Xp, N, d, lo.as<double>(), hi.as<double>(), kappa, o, st);
-        else if (kappa <= 32) launch_knn<32>(dpad, Xp, N, d, lo.as<double>(), hi.as<double>(), kappa, o, st);
-        else launch_knn<64>(dpad, Xp, N, d, lo.as<double>(), hi.as<double>(), kappa, o, st);
+        unsigned long long *v = visits.as<unsigned long long>();
+        if (kappa <= 8) launch_knn<8>(dpad, Xp, N, d, L, H, kappa, o, v, st);
+        else if (kappa <= 16) launch_knn<16>(dpad, Xp, N, d, L, H, kappa, o, v, st);
+        else if (kappa <= 32) launch_knn<32>(dpad, Xp, N, d, L, H, kappa, o, v, st);
+        else launch_knn<64>(dpad, Xp, N, d, L, H, kappa, o, v, st);
         return hipGetLastError();
     }));
     for (int l = t->D; l >= 1; l--) {
@@ -888,6 +893,7 @@ static askit_status build_neighbor_lists(askit_tree t, hipStream_t st) {
     }
     t->hnn.assign(t->nnodes, 0);
     HIP_TRY(hipMemcpyAsync(t->hnn.data(), t->nblen.p, sizeof(int32_t) * t->nnodes, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&t->knn_points, visits.p, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     return ASKIT_OK;
 }
@@ -3173,11 +3179,12 @@ askit_status askit_get_stats(askit_tree t, askit_factor f, char *json, size_t ca
     char buf[1024];
     int n = snprintf(buf, sizeof buf,
                      "{\"N\": %lld, \"d\": %d, \"depth\": %d, \"leaf_size\": %d, \"rank\": %d, "
-                     "\"tree_ms\": %.3f, \"knn\": %d, \"knn_ms\": %.3f, \"skeletonize_ms\": %.3f, "
-                     "\"factorize_ms\": %.3f, \"solve_ms\": %.3f, "
+                     "\"tree_ms\": %.3f, \"knn\": %d, \"knn_ms\": %.3f, \"knn_wave_points\": %llu, "
+                     "\"skeletonize_ms\": %.3f, \"factorize_ms\": %.3f, \"solve_ms\": %.3f, "
                      "\"precision\": \"%s\", \"min_pivot_ratio\": %.3e, \"refine_iterations\": %d}",
                      t ? (long long)t->N : 0LL, t ? t->d : 0, t ? t->D : 0, t ? t->m : 0, t ? t->s : 0,
-                     t ? t->t_tree : 0.0, t ? t->knn : 0, t ? t->t_knn : 0.0, t ? t->t_skel : 0.0,
+                     t ? t->t_tree : 0.0, t ? t->knn : 0, t ? t->t_knn : 0.0, t ? t->knn_points : 0ULL,
+                     t ? t->t_skel : 0.0,
                      f ? f->t_factor : 0.0, f ? f->t_solve : 0.0,
                      f ? (f->prec == P64 ? "fp64" : "mixed") : "none", f ? f->min_ratio : 0.0,
                      f ? f->info.iterations : 0);

@@ -45,7 +45,7 @@ __global__ void k_qs_finish(const SkelTask *tasks, QrWork w, int s, int ldm);
 __global__ void k_knn_boxes(const double *Xp, int64_t N, int d, int dpad, double *lo, double *hi);
 template <int K, int DIM>
 __global__ void k_knn(const double *Xp, int64_t N, int d, const double *lo, const double *hi, int kappa,
-                      int32_t *out);
+                      int32_t *out, unsigned long long *visits);
 __global__ void k_nbr_rank(NbrTask t, int64_t first, int64_t pmax, uint64_t *scratch);
 
 // LU (k_lu.hip)
