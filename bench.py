@@ -421,10 +421,13 @@ def main():
         del xc, yc
 
     cpu = None
+    batched_sample = forms.pop("_batched_sample", None) if forms else None
     if args.cpu_sample:
         cpu = cpu_baseline(c, args.cpu_sample)
     elif not args.no_cpu:
         cpu = cpu_full_check(c, tree, ids64, P64, sizes64, x64, xref, args.cpu_rhs, args.cpu_check)
+    if cpu is not None and batched_sample:
+        cpu["batched_check"] = cpu_batched_check(batched_sample)
 
     out = {
         "metric": METRIC, "value": t_fac64, "unit": "s", "n_gpus": 1, "steps": args.steps,
@@ -607,6 +610,12 @@ def forms_timings(ak, torch, dev, tree, lam, B):
     t_fac, _ = _timed(torch, batch.factorize, reps=3)
     t_sol, _ = _timed(torch, lambda: batch.solve(Bs), reps=3)
     ratio, worst = batch.check()
+    # solutions of eight problems spread over the batch, for the oracle
+    # comparison of the CPU leg
+    xs = batch.solve(Bs)
+    torch.cuda.synchronize()
+    pick = list(range(0, len(probs), len(probs) // 8))[:8]
+    out["_batched_sample"] = [(probs[i], xs[i].cpu().numpy()) for i in pick]
     out["batched"] = {"problems": len(probs), "points": int(sum(len(p["X"]) for p in probs)),
                       "skeletonize_s": t_skel, "plan_and_capture_s": t_create, "factorize_graph_s": t_fac,
                       "solve_graph_s": t_sol, "factorizations_per_s": len(probs) / t_fac,
@@ -752,6 +761,36 @@ def cpu_full_check(c, tree, ids, P, sizes, x64, xref, nrhs_check, check):
     check["rhs_checked"] = k
     out["check"] = check
     log(f"[bench] cpu check: {check}")
+    return out
+
+
+def cpu_batched_check(sample):
+    """The batched workload's accuracy against the oracle, problem by
+    problem: for each sampled problem the oracle builds its own tree and
+    skeletons, factorizes and solves its 8 right-hand sides; the GPU's
+    batched FP64 solution (hipGraph replay) is compared with that solution
+    and its residual is taken under the oracle's operator."""
+    import oracle
+    rows = []
+    a = time.perf_counter()
+    for p, xg in sample:
+        o = oracle.Oracle(p["X"], p["m"], p["s"], p["h"], nsamp=p["nsamp"], seed=p["seed"], problem=p["problem"])
+        o.build_tree()
+        o.skeletonize()
+        o.factorize(p["lam"])
+        B = p["B"]
+        xo = o.solve(B)
+        nb = np.linalg.norm(B, axis=0)
+        rel = float((np.linalg.norm(xg - xo, axis=0) / np.linalg.norm(xo, axis=0)).max())
+        rg = float((np.linalg.norm(B - o.matvec(xg), axis=0) / nb).max())
+        ro = float((np.linalg.norm(B - o.matvec(xo), axis=0) / nb).max())
+        rows.append({"problem": p["problem"], "N": len(p["X"]), "lambda": p["lam"], "h": p["h"],
+                     "gpu_vs_oracle": rel, "gpu_residual": rg, "oracle_residual": ro})
+    out = {"problems": rows, "max_gpu_vs_oracle": max(r["gpu_vs_oracle"] for r in rows),
+           "max_gpu_residual": max(r["gpu_residual"] for r in rows),
+           "max_oracle_residual": max(r["oracle_residual"] for r in rows), "seconds": time.perf_counter() - a}
+    log(f"[bench] batched check: max GPU vs oracle {out['max_gpu_vs_oracle']:.2e}, residuals GPU "
+        f"{out['max_gpu_residual']:.2e} oracle {out['max_oracle_residual']:.2e}")
     return out
 
 
