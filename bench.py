@@ -17,7 +17,9 @@ FP64 LUs) is timed the same way and reported beside it with its accuracy gate
 (relative error to the refined FP64 solution <= 1e-6 with converged
 refinement); it is the headline only if that gate holds.
 
-The timed steps run without per-launch events.  Per-kernel times come from a
+Before the timed steps the tree's level-product tiles are autotuned once
+(askit_tune_factorization; --no-tune keeps the built-in choice); the tuning
+time is reported, not timed.  The timed steps run without per-launch events.  Per-kernel times come from a
 separate pass of the same steps with HIP events around every launch
 (askit_profile_enable), and give the rooflines.  The oracle (plain C, OpenMP)
 is the CPU baseline, timed on the whole workload (about 50 s on 16 cores);
@@ -237,6 +239,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB elementwise copy (reference for the HBM byte counters)")
     ap.add_argument("--tol", type=float, default=1e-11, help="target relative residual of the refined solves")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the built-in tile choices (skip askit_tune_factorization before the timed steps)")
     ap.add_argument("--qr-split-levels", type=int, default=0,
                     help="tree levels factored by the split pivoted QR (0: library default, -1: none)")
     ap.add_argument("--cpu-rhs", type=int, default=4, help="right-hand sides the oracle solves in its check")
@@ -265,6 +269,17 @@ def main():
     torch.cuda.synchronize()
     t_tree = time.perf_counter() - t0
     log(f"[bench] tree built in {t_tree:.3f} s (depth {tree.D})")
+    # tile autotuning of the factorization's level products, once, outside
+    # the timed steps (it needs skeletons: one skeletonization first)
+    tune = None
+    if not args.no_tune:
+        tree.skeletonize()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        table = tree.tune(lam)
+        torch.cuda.synchronize()
+        tune = {"seconds": time.perf_counter() - a, "kmm_columns_chunk_gmm_columns_by_height": table}
+        log(f"[bench] tuned tiles in {tune['seconds']:.2f} s: {table}")
 
     def step(prec, keep=False, fused=True, refine=0):
         # fused: askit_skeletonize_factorize (the two phases pipelined over
@@ -436,7 +451,7 @@ def main():
         "config": {"workload": f"gaussian-mixture N={N} d={d} m={m} s={s} h={h} lambda={lam} nrhs={args.nrhs}",
                    "N": N, "d": d, "leaf_size": m, "rank": s, "n_samples": nsamp, "nrhs": args.nrhs,
                    "precision": "fp64"},
-        "skeletonize_factorize_s": t_fac64, "separate_calls": two_call,
+        "skeletonize_factorize_s": t_fac64, "separate_calls": two_call, "tile_tuning": tune,
         "solve_s": t_sol64, "solves_per_s": args.nrhs / t_sol64, "one_rhs_solve_s": t_one,
         "fp64_direct_residual": eps64, "fp64_refined_solve_s": t_ref, "fp64_refinement": info64,
         "fp64_min_pivot_ratio": pr64[0], "tree_s": t_tree,

@@ -178,6 +178,21 @@ askit_status askit_skeletons_import(askit_tree t, const int32_t *ids, const doub
  * max|U_ii| of some block is below 1e-12. */
 askit_status askit_factorize(askit_tree t, double lambda, int32_t precision, void *stream, askit_factor *out);
 
+/* Tile autotuning of the level-batched factorization (the level schedule of
+ * Sec. 2.2 as one launch per kernel and tree height): times the FP64
+ * factorization's level products of t at every tree height -- the blocks
+ * K_{l~ r} Phat_r of the reduced systems Z (eq. (8)) and the telescoped
+ * Phat (eq. (10)) -- in each tile configuration: 64, 128 or 256 output
+ * columns per tile (at most twice the built-in choice for the rank) and
+ * contraction chunks of 2048, 4096 or 8192 points, and keeps the fastest
+ * per height in the tree.  Later factorizations of t (askit_factorize,
+ * askit_skeletonize_factorize; FP64, and mixed with tiles of at most 128
+ * columns) use it; the batched entry points keep the built-in choice.  The
+ * chunk changes the grouping of the split sums, so results change by
+ * rounding only.  Blocks until done.  Errors: ASKIT_ERR_STATE before
+ * askit_skeletonize, ASKIT_ERR_ARG for a bad lambda. */
+askit_status askit_tune_factorization(askit_tree t, double lambda, void *stream);
+
 /* Hybrid solver (Sec. 2.3, "Fast hybrid solver"; Alg. HybridSolve, MatVecW,
  * MatVecV) with the skeletonization frontier at tree level `level`
  * (1 .. D): the frontier's nodes and their subtrees are factored as by

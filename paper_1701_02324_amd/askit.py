@@ -27,7 +27,7 @@ EXPORTED = [
     "askit_batch_create", "askit_batch_factorize", "askit_batch_check", "askit_batch_solve", "askit_batch_factor",
     "askit_batch_destroy", "askit_skeletonize_factorize", "askit_release_cached_memory",
     "askit_factorize_batched", "askit_tree_qr_rows", "askit_tree_samples", "askit_tree_permutation_noalloc",
-    "askit_factorize_hybrid", "askit_tree_knn", "askit_tree_neighbor_lists",
+    "askit_factorize_hybrid", "askit_tree_knn", "askit_tree_neighbor_lists", "askit_tune_factorization",
 ]
 
 
@@ -70,6 +70,7 @@ def load(path: str = LIB_PATH):
     L.askit_tree_qr_rows.argtypes = [_vp, _vp]
     L.askit_tree_samples.argtypes = [_vp, _vp]
     L.askit_tree_knn.argtypes = [_vp, _vp]
+    L.askit_tune_factorization.argtypes = [_vp, ctypes.c_double, _vp]
     L.askit_tree_neighbor_lists.argtypes = [_vp, _vp, _vp, _vp]
     L.askit_tree_permutation_noalloc.argtypes = [_vp, _i64, _i32, _i32, _vp, _vp]
     L.askit_skeletonize.argtypes = [_vp, _vp]
@@ -207,6 +208,10 @@ def askit_tree_neighbor_lists(tree, nnodes, nsamp):
     n = np.zeros(nnodes, dtype=np.int32)
     _check(load().askit_tree_neighbor_lists(tree, pos.ctypes.data, w.ctypes.data, n.ctypes.data))
     return pos.reshape(nnodes, nsamp), w.reshape(nnodes, nsamp), n
+
+
+def askit_tune_factorization(tree, lam, stream=None):
+    _check(load().askit_tune_factorization(tree, float(lam), _stream(stream)))
 
 
 def askit_skeletonize(tree, stream=None):
@@ -415,6 +420,12 @@ class Tree:
 
     def factorize(self, lam, precision=ASKIT_FP64, stream=None):
         return Factor(self, lam, precision, stream)
+
+    def tune(self, lam, stream=None):
+        """Time the factorization's level products in each tile configuration
+        and keep the fastest per tree height (askit_tune_factorization)."""
+        askit_tune_factorization(self.handle, lam, stream)
+        return self.stats().get("tune")
 
     def skeletonize_factorize(self, lam, precision=ASKIT_FP64, stream=None):
         """skeletonize() then factorize(), pipelined over two streams."""

@@ -18,6 +18,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "askit.h"
@@ -434,6 +435,19 @@ void xcd_order(std::vector<TileItem> &items) {
 template <typename T, typename TB, typename TO>
 hipError_t launch_kmm(const KmmTask *tasks, const TileItem *items, int nitems, int ncol, int d, int tc,
                       hipStream_t st) {
+    constexpr bool f64 = std::is_same<T, double>::value && std::is_same<TB, double>::value &&
+                         std::is_same<TO, double>::value;
+    if constexpr (f64) {
+        if (tc == 256) {
+            if (d <= kXrDim)
+                hipLaunchKernelGGL((k_kmm<T, TB, TO, 256, true>), dim3(nitems), dim3(256), sizeof(T) * 16 * kXrDim, st,
+                                   tasks, items, ncol, d);
+            else
+                hipLaunchKernelGGL((k_kmm<T, TB, TO, 256, false>), dim3(nitems), dim3(256),
+                                   sizeof(T) * (64 * (d | 1) + 16 * d), st, tasks, items, ncol, d);
+            return hipGetLastError();
+        }
+    }
     if (d <= kXrDim) {  // row points in registers
         const size_t lds = sizeof(T) * 16 * kXrDim;
         if (tc == 128)
@@ -500,6 +514,7 @@ askit_status gmm_commit(Plan &P, GmmBuild &gb, Prec t, int rows_red_max) {
     const int nitems = (int)gb.items.size(), tc = gb.tc;
     P.add("k_gmm", [=](hipStream_t st, int ncol) -> hipError_t {
         if (t == P64) {
+            if (tc == 256) return launch_gmm<double, 256>(tp, ip, nitems, ncol, st);
             if (tc == 128) return launch_gmm<double, 128>(tp, ip, nitems, ncol, st);
             if (tc == 64) return launch_gmm<double, 64>(tp, ip, nitems, ncol, st);
             return launch_gmm<double, 16>(tp, ip, nitems, ncol, st);
@@ -694,6 +709,13 @@ static askit_status tree_levels(const double *X, int64_t N, int d, int D, int64_
 // node, one launch per pivot step) and the leaves, the widest level, one
 // workgroup per node.  Both give identical skeletons.
 
+// Tile configuration of the factorization's level products at one tree
+// height (0 fields: the built-in choice from the column count)
+struct Tune {
+    int kmm_tc = 0, gmm_tc = 0;  // output columns per tile of k_kmm / k_gmm
+    int64_t kmm_kc = 0;          // contraction points per split chunk of k_kmm
+};
+
 struct askit_tree_s {
     int64_t N = 0;
     int d = 0, m = 0, s = 0, nsamp = 0, D = 0, cmax = 0, mmax = 0;
@@ -707,6 +729,7 @@ struct askit_tree_s {
     std::vector<int32_t> hnn;        // host copy of the list lengths
     double t_knn = 0;
     unsigned long long knn_points = 0;  // points the neighbour search compared, summed over its waves
+    std::vector<Tune> tune;  // per tree height, from askit_tune_factorization (empty: built-in choices)
     std::vector<int64_t> nb, ne;  // host node ranges
     DBuf X, Xp, perm, iperm, dnb, dne;  // iperm[original index] = tree position
     DBuf srank, trunc, skel, Pt, samp, qrows;
@@ -1421,7 +1444,20 @@ static const int64_t kChunk = 4096;  // contraction chunk of the split products
 // lambda I + K_aa (they need no skeletons), part 0 = the leaves' Phat, part
 // h >= 1 = the internal nodes at height h.  Part h >= 0 reads the ranks and
 // skeletons of heights <= h only.
-static askit_status factor_plan_part(const std::vector<askit_factor> &fs, Plan &P, int part) {
+static int builtin_tc(int cols) { return cols >= 128 ? 128 : (cols >= 64 ? 64 : 16); }
+
+// smallest split chunk the factorization of t may use (sizes its workspace)
+static int64_t tree_kc_min(askit_tree t) {
+    int64_t kc = kChunk;
+    for (const Tune &u : t->tune)
+        if (u.kmm_kc > 0) kc = std::min(kc, u.kmm_kc);
+    return kc;
+}
+
+// force: the tile configuration of every height of this part (tuning runs);
+// else a single tree's tuned configuration, else the built-in choice
+static askit_status factor_plan_part(const std::vector<askit_factor> &fs, Plan &P, int part,
+                                     const Tune *force = nullptr) {
     askit_tree t0 = fs[0]->t;
     const int s = t0->s, d = t0->d, s2 = 2 * s;
     const Prec pr = fs[0]->prec;
@@ -1496,13 +1532,20 @@ static askit_status factor_plan_part(const std::vector<askit_factor> &fs, Plan &
     // heights 1 .. Hmax: internal nodes, bottom-up
     for (int hgt = std::max(part, 1); hgt <= std::min(part, Hmax); hgt++) {
         std::vector<IdTask> ident;
+        const Tune *tn = force;
+        if (!tn && fs.size() == 1 && (size_t)hgt < fs[0]->t->tune.size()) tn = &fs[0]->t->tune[hgt];
         KmmBuild kb;
-        kb.tc = s >= 128 ? 128 : (s >= 64 ? 64 : 16);
+        kb.tc = tn && tn->kmm_tc ? tn->kmm_tc : builtin_tc(s);
+        const int64_t kc = tn && tn->kmm_kc ? tn->kmm_kc : kChunk;
         kb.out_size = 8;
         std::vector<LuTask> lu, rs;
         std::vector<CopyTask> cp, cp32;
         GmmBuild gb;
-        gb.tc = kb.tc;
+        gb.tc = tn && tn->gmm_tc ? tn->gmm_tc : builtin_tc(s);
+        if (pr != P64) {  // 256-column tiles exist in FP64 only
+            kb.tc = std::min(kb.tc, 128);
+            gb.tc = std::min(gb.tc, 128);
+        }
         gb.elem = el;
         for (auto f : fs) {
             askit_tree t = f->t;
@@ -1534,7 +1577,7 @@ static askit_status factor_plan_part(const std::vector<askit_factor> &fs, Plan &
                     k.op = OP_STORE;
                     k.rcap = t->hsr[a];
                     k.ncol = t->hsr[o];
-                    kmm_add(kb, k, k.S.n, k.ncol, kChunk, el, f->ws.as<char>(), wsoff);
+                    kmm_add(kb, k, k.S.n, k.ncol, kc, el, f->ws.as<char>(), wsoff);
                 }
                 LuTask u{};
                 u.A = Z;
@@ -1649,7 +1692,7 @@ static askit_status factor_alloc(askit_tree t, double lambda, int precision, std
     const int64_t lvl_max = D >= 2 ? ((int64_t)1 << (D - 1)) : 1;  // nodes of the widest level with a telescoping step
     ST_TRY(f->Xc.alloc(sizeof(double) * lvl_max * s2 * s));
     if (f->prec == P32) ST_TRY(f->Xcf.alloc(sizeof(float) * lvl_max * s2 * s));
-    ST_TRY(f->ws.alloc(sizeof(double) * std::max<int64_t>(1, split_ws_elems(t, s, kChunk))));
+    ST_TRY(f->ws.alloc(sizeof(double) * std::max<int64_t>(1, split_ws_elems(t, s, tree_kc_min(t)))));
     return ASKIT_OK;
 }
 
@@ -1803,6 +1846,94 @@ askit_status askit_factorize(askit_tree t, double lambda, int32_t precision, voi
     askit_status st = factorize_impl(t, lambda, precision, (hipStream_t)stream, out);
     if (*out) (*out)->t_factor = ms_since(t0);
     return st;
+}
+
+askit_status askit_tune_factorization(askit_tree t, double lambda, void *stream) {
+    if (!t) return fail(ASKIT_ERR_ARG, "NULL tree");
+    if (!t->skel_ok) return fail(ASKIT_ERR_STATE, "skeletonize the tree first");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(ASKIT_ERR_ARG, "lambda must be >= 0 and finite");
+    hipStream_t st = (hipStream_t)stream;
+    const int D = t->D, s = t->s;
+    std::vector<int> tcs;
+    for (int tc : {64, 128, 256})
+        if (tc <= 2 * std::max(64, builtin_tc(s))) tcs.push_back(tc);
+    const int64_t kcs[] = {2048, 4096, 8192};
+    // workspace for the smallest chunk, then one factorization with the
+    // built-in choices: every height's inputs (the children's Phat) are valid
+    t->tune.assign(D + 1, Tune{0, 0, kcs[0]});
+    std::unique_ptr<askit_factor_s> f;
+    askit_status rc = factor_alloc(t, lambda, ASKIT_FP64, f);
+    t->tune.clear();
+    ST_TRY(rc);
+    {
+        Plan P;
+        P.tag = "tune";
+        ST_TRY(factor_plan({f.get()}, P));
+        HIP_TRY(P.run(st, s));
+    }
+    hipEvent_t ev[2];
+    HIP_TRY(hipEventCreate(&ev[0]));
+    if (hipEventCreate(&ev[1]) != hipSuccess) {
+        (void)hipEventDestroy(ev[0]);
+        return fail(ASKIT_ERR_HIP, "hipEventCreate failed");
+    }
+    // kernel time of the steps of one height whose names contain `what`
+    auto time_steps = [&](const Plan &P, float &kmm_ms, float &gmm_ms) -> hipError_t {
+        kmm_ms = gmm_ms = 0.f;
+        for (const auto &step : P.steps) {
+            const bool k = step.first.find("k_kmm") != std::string::npos ||
+                           step.first.find("k_reduce") != std::string::npos;
+            const bool g = step.first.find("k_gmm") != std::string::npos;
+            if (k || g) {
+                hipError_t e = hipEventRecord(ev[0], st);
+                if (e == hipSuccess) e = step.second(st, s);
+                if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+                if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+                if (e != hipSuccess) return e;
+                (k ? kmm_ms : gmm_ms) += ms;
+            } else {
+                hipError_t e = step.second(st, s);
+                if (e != hipSuccess) return e;
+            }
+        }
+        return hipSuccess;
+    };
+    std::vector<Tune> best(D + 1);
+    hipError_t err = hipSuccess;
+    askit_status ast = ASKIT_OK;
+    for (int hgt = 1; hgt <= D && err == hipSuccess && ast == ASKIT_OK; hgt++) {
+        float bk = INFINITY, bg = INFINITY;
+        for (int tc : tcs)
+            for (int64_t kc : kcs) {
+                Tune cand{tc, tc, kc};
+                Plan P;
+                P.tag = "tune";
+                ast = factor_plan_part({f.get()}, P, hgt, &cand);
+                if (ast != ASKIT_OK) break;
+                float km = 0.f, gm = 0.f, k2 = 0.f, g2 = 0.f;
+                err = time_steps(P, km, gm);  // first run warms the tile configuration
+                if (err == hipSuccess) err = time_steps(P, k2, g2);
+                if (err != hipSuccess) break;
+                if (k2 < bk) {
+                    bk = k2;
+                    best[hgt].kmm_tc = tc;
+                    best[hgt].kmm_kc = kc;
+                }
+                if (g2 < bg) {
+                    bg = g2;
+                    best[hgt].gmm_tc = tc;
+                }
+            }
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    ST_TRY(ast);
+    HIP_TRY(err);
+    HIP_TRY(hipStreamSynchronize(st));
+    t->tune = best;
+    return ASKIT_OK;
 }
 
 askit_status askit_factorize_hybrid(askit_tree t, double lambda, int32_t level, void *stream, askit_factor *out) {
@@ -3188,8 +3319,20 @@ askit_status askit_get_stats(askit_tree t, askit_factor f, char *json, size_t ca
                      f ? f->t_factor : 0.0, f ? f->t_solve : 0.0,
                      f ? (f->prec == P64 ? "fp64" : "mixed") : "none", f ? f->min_ratio : 0.0,
                      f ? f->info.iterations : 0);
-    if (n < 0 || (size_t)n >= cap) return fail(ASKIT_ERR_ARG, "buffer too small");
-    memcpy(json, buf, n + 1);
+    if (n < 0 || (size_t)n >= sizeof buf) return fail(ASKIT_ERR_ARG, "buffer too small");
+    std::string js(buf, (size_t)n);
+    if (t && !t->tune.empty()) {  // tuned tiles per height: [kmm columns, kmm chunk, gmm columns]
+        js.pop_back();
+        js += ", \"tune\": {";
+        for (size_t h = 1; h < t->tune.size(); h++) {
+            const Tune &u = t->tune[h];
+            js += (h > 1 ? ", \"" : "\"") + std::to_string(h) + "\": [" + std::to_string(u.kmm_tc) + ", " +
+                  std::to_string(u.kmm_kc) + ", " + std::to_string(u.gmm_tc) + "]";
+        }
+        js += "}}";
+    }
+    if (js.size() >= cap) return fail(ASKIT_ERR_ARG, "buffer too small");
+    memcpy(json, js.c_str(), js.size() + 1);
     return ASKIT_OK;
 }
 

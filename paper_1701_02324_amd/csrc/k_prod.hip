@@ -308,11 +308,12 @@ __global__ void k_reduce(const RedTask *__restrict__ tasks, int ncol, int blocks
     template __global__ void k_kmm<T, TB, TO, TC, true>(const KmmTask *, const TileItem *, int, int);
 #define KMM_ALL(T, TB, TO) KMM_INST(T, TB, TO, 16) KMM_INST(T, TB, TO, 64) KMM_INST(T, TB, TO, 128)
 KMM_ALL(double, double, double)
+KMM_INST(double, double, double, 256)
 KMM_ALL(float, float, float)
 KMM_ALL(float, float, double)
 KMM_ALL(double, float, double)
 #define GMM_INST(T, TC) template __global__ void k_gmm<T, TC>(const GmmTask *, const TileItem *, int, int);
-GMM_INST(double, 16) GMM_INST(double, 64) GMM_INST(double, 128)
+GMM_INST(double, 16) GMM_INST(double, 64) GMM_INST(double, 128) GMM_INST(double, 256)
 GMM_INST(float, 16) GMM_INST(float, 64) GMM_INST(float, 128)
 template __global__ void k_reduce<double, double>(const RedTask *, int, int);
 template __global__ void k_reduce<float, float>(const RedTask *, int, int);

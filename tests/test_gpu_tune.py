@@ -1,0 +1,69 @@
+"""The factorization's tile autotuner (level-batched execution, Sec. 2.2's
+level schedule): a tuned tree factorizes to the same solution up to the
+rounding of the regrouped split sums, through both entry points, in FP64
+and in mixed precision."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import colrel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ak():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1701_02324_amd as ak
+    ak.load()
+    return ak
+
+
+def _cuda(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def test_tuned_factorization_matches(ak):
+    X, B = synth.small(20000, 8, 41, nrhs=3, kind="mixture", scale=4.0)
+    lam = 0.5
+    print(f"[gpu tune] N=20000 m=256 s=128", file=sys.stderr, flush=True)
+    t = ak.Tree(_cuda(X), 256, 128, 1.5, seed=4)
+    t.skeletonize()
+    Bd = _cuda(B)
+    f = t.factorize(lam, ak.ASKIT_FP64)
+    x0 = f.solve(Bd).cpu().numpy()
+    r0 = float((np.linalg.norm(B - f.matvec(_cuda(x0)).cpu().numpy(), axis=0) / np.linalg.norm(B, axis=0)).max())
+    f.close()
+    table = t.tune(lam)
+    assert table and len(table) == t.D
+    for h, (ktc, kkc, gtc) in table.items():
+        assert ktc in (64, 128, 256) and gtc in (64, 128, 256) and kkc in (2048, 4096, 8192), (h, table)
+    f = t.factorize(lam, ak.ASKIT_FP64)
+    x1 = f.solve(Bd).cpu().numpy()
+    r1 = float((np.linalg.norm(B - f.matvec(_cuda(x1)).cpu().numpy(), axis=0) / np.linalg.norm(B, axis=0)).max())
+    f.close()
+    # a different split chunk regroups the partial sums of the Z blocks: the
+    # two solutions are two FP64 orderings of the same algebra, as close as
+    # the recursion's amplification of rounding allows (measured 1.4e-10
+    # here, with residuals of 2.0e-9 and 2.9e-9)
+    print(f"  tuned {table}; solutions differ by {colrel(x1, x0):.1e}, residuals {r0:.1e} {r1:.1e}",
+          file=sys.stderr, flush=True)
+    assert colrel(x1, x0) < 1e-8
+    assert r1 < 10 * max(r0, 1e-12)
+    # the pipelined call on the tuned tree gives the separate calls' factors
+    f = t.skeletonize_factorize(lam, ak.ASKIT_FP64)
+    x2 = f.solve(Bd).cpu().numpy()
+    f.close()
+    assert np.array_equal(x2, x1)
+    # mixed precision keeps tiles of at most 128 columns
+    f = t.factorize(lam, ak.ASKIT_MIXED)
+    f.set_refinement(50, 1e-11)
+    x3 = f.solve(Bd).cpu().numpy()
+    f.close()
+    assert colrel(x3, x0) < 1e-8
+    t.close()
