@@ -435,32 +435,39 @@ void xcd_order(std::vector<TileItem> &items) {
 template <typename T, typename TB, typename TO>
 hipError_t launch_kmm(const KmmTask *tasks, const TileItem *items, int nitems, int ncol, int d, int tc,
                       hipStream_t st) {
+    const size_t lds = d <= kXrDim ? sizeof(T) * 16 * kXrDim : sizeof(T) * (64 * (d | 1) + 16 * d);
     constexpr bool f64 = std::is_same<T, double>::value && std::is_same<TB, double>::value &&
                          std::is_same<TO, double>::value;
     if constexpr (f64) {
-        if (tc == 256) {
+        if (tc == 256) {  // two 128-column halves sharing the generated kernel tile
             if (d <= kXrDim)
-                hipLaunchKernelGGL((k_kmm<T, TB, TO, 256, true>), dim3(nitems), dim3(256), sizeof(T) * 16 * kXrDim, st,
-                                   tasks, items, ncol, d);
+                hipLaunchKernelGGL((k_kmm<T, TB, TO, 128, true, 2>), dim3(nitems), dim3(512), lds, st, tasks, items,
+                                   ncol, d);
             else
-                hipLaunchKernelGGL((k_kmm<T, TB, TO, 256, false>), dim3(nitems), dim3(256),
-                                   sizeof(T) * (64 * (d | 1) + 16 * d), st, tasks, items, ncol, d);
+                hipLaunchKernelGGL((k_kmm<T, TB, TO, 128, false, 2>), dim3(nitems), dim3(512), lds, st, tasks, items,
+                                   ncol, d);
             return hipGetLastError();
         }
     }
+    if (tc == 256) return hipErrorInvalidValue;  // 256-column tiles exist in FP64 only
     if (d <= kXrDim) {  // row points in registers
-        const size_t lds = sizeof(T) * 16 * kXrDim;
         if (tc == 128)
-            hipLaunchKernelGGL((k_kmm<T, TB, TO, 128, true>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
+            hipLaunchKernelGGL((k_kmm<T, TB, TO, 128, true, 1>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol,
+                               d);
         else if (tc == 64)
-            hipLaunchKernelGGL((k_kmm<T, TB, TO, 64, true>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
-        else hipLaunchKernelGGL((k_kmm<T, TB, TO, 16, true>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
+            hipLaunchKernelGGL((k_kmm<T, TB, TO, 64, true, 1>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol,
+                               d);
+        else
+            hipLaunchKernelGGL((k_kmm<T, TB, TO, 16, true, 1>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol,
+                               d);
         return hipGetLastError();
     }
-    const size_t lds = sizeof(T) * (64 * (d | 1) + 16 * d);
-    if (tc == 128) hipLaunchKernelGGL((k_kmm<T, TB, TO, 128, false>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
-    else if (tc == 64) hipLaunchKernelGGL((k_kmm<T, TB, TO, 64, false>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
-    else hipLaunchKernelGGL((k_kmm<T, TB, TO, 16, false>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
+    if (tc == 128)
+        hipLaunchKernelGGL((k_kmm<T, TB, TO, 128, false, 1>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
+    else if (tc == 64)
+        hipLaunchKernelGGL((k_kmm<T, TB, TO, 64, false, 1>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
+    else
+        hipLaunchKernelGGL((k_kmm<T, TB, TO, 16, false, 1>), dim3(nitems), dim3(256), lds, st, tasks, items, ncol, d);
     return hipGetLastError();
 }
 

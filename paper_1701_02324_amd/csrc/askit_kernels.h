@@ -56,7 +56,7 @@ template <typename T, int NR, bool TRANS>
 __global__ void k_lusolve(const LuTask *tasks, int ntask, int nrhs, int panels);
 
 // products (k_prod.hip)
-template <typename T, typename TB, typename TO, int TC, bool XR>
+template <typename T, typename TB, typename TO, int TC, bool XR, int CG>
 __global__ void k_kmm(const KmmTask *tasks, const TileItem *items, int ncol, int d);
 template <typename T, int TC> __global__ void k_gmm(const GmmTask *tasks, const TileItem *items, int ncol, int kchunk);
 template <typename T, typename TO> __global__ void k_reduce(const RedTask *tasks, int ncol, int blocks_per_task);

@@ -59,12 +59,17 @@ __device__ inline int64_t src_pos(const PtSrc &s, int i) { return s.idx ? (int64
 // points are staged in LDS at an odd stride (lanes read different rows: no
 // bank conflicts) and the contraction points at stride d (broadcast within a
 // wave).
-template <typename T, typename TB, typename TO, int TC, bool XR>
-__global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, const TileItem *__restrict__ items,
-                                             int ncol, int d) {
-    constexpr int NB = TC / 16;
+//
+// CG column groups of four waves each (256 CG threads) share one generated
+// kernel tile: the output tile is 64 x (CG TC), wave w owns rows
+// 16 (w % 4) .. + 15 of columns TC (w / 4) .. + TC - 1, so the exponentials
+// of a tile are computed once for CG TC columns.
+template <typename T, typename TB, typename TO, int TC, bool XR, int CG>
+__global__ __launch_bounds__(256 * CG) void k_kmm(const KmmTask *__restrict__ tasks,
+                                                  const TileItem *__restrict__ items, int ncol, int d) {
+    constexpr int NB = TC / 16, NT = 256 * CG;
     __shared__ T sA[kTR][kKS + 1];
-    __shared__ T sB[kKS][TC + 1];
+    __shared__ T sB[kKS][TC * CG + 1];
     // XR: 16 kXrDim elements of T; else 64 (d | 1) + 16 d
     extern __shared__ double dyn_lds[];
     const int dp = d | 1;
@@ -72,16 +77,16 @@ __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, 
     const TileItem it = items[blockIdx.x];
     if (it.task < 0) return;
     const KmmTask t = tasks[it.task];
-    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave, wr = wave % 4, wc = wave / 4;
     const int nrow = src_count(t.R);
     if (t.ncol > 0) ncol = min(ncol, t.ncol);
-    const int r0 = it.rt * kTR, c0 = it.ct * TC;
+    const int r0 = it.rt * kTR, c0 = it.ct * TC * CG;
     GLB TO *C = glb((TO *)t.C);
     const GLB double *X = glb(t.X);
     if (r0 >= nrow) {  // tile of padded rows: zero-fill on store
         if (t.op == OP_STORE)
-            for (int i = tid; i < kTR * TC; i += 256) {
-                int r = r0 + i / TC, c = c0 + i % TC;
+            for (int i = tid; i < kTR * TC * CG; i += NT) {
+                int r = r0 + i / (TC * CG), c = c0 + i % (TC * CG);
                 if (r < t.rcap && c < ncol) C[(int64_t)r * t.crs + (int64_t)c * t.ccs] = (TO)0;
             }
         return;
@@ -97,7 +102,7 @@ __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, 
 #pragma unroll
         for (int q = 0; q < kXrDim; q++) xr[q] = (live && q < d) ? (T)X[pr + q] : (T)0;
     } else {
-        for (int i = tid; i < kTR * d; i += 256) {
+        for (int i = tid; i < kTR * d; i += NT) {
             int r = i / d, k = i % d;
             sR[r * dp + k] = r0 + r < nrow ? (T)X[src_pos(t.R, r0 + r) * d + k] : (T)0;
         }
@@ -107,16 +112,17 @@ __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, 
     const GLB TB *B = glb((const TB *)t.B);
     // the next stage's contraction points and B rows are fetched into
     // registers while the current stage is generated and multiplied
-    constexpr int PS = (XR ? kKS * kXrDim : kKS * kMaxDim) / 256, PB = kKS * TC / 256;
+    constexpr int SS = XR ? kKS * kXrDim : kKS * kMaxDim;  // staged contraction values (max)
+    constexpr int PS = (SS + NT - 1) / NT, PB = kKS * TC * CG / NT;
     T pS[PS], pB[PB];
     auto fetch = [&](int ks) {
         const int kn = min(kKS, k1 - ks);
 #pragma unroll
         for (int u = 0; u < PS; u++) {
-            const int i = tid + u * 256;
+            const int i = tid + u * NT;
             if constexpr (XR) {
                 const int r = i / kXrDim, k = i % kXrDim;
-                pS[u] = (k < d && r < kn) ? (T)X[src_pos(t.S, ks + r) * d + k] : (T)0;
+                pS[u] = (i < SS && k < d && r < kn) ? (T)X[src_pos(t.S, ks + r) * d + k] : (T)0;
             } else {
                 const int r = i / d, k = i % d;
                 pS[u] = (i < kKS * d && r < kn) ? (T)X[src_pos(t.S, ks + r) * d + k] : (T)0;
@@ -124,7 +130,7 @@ __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, 
         }
 #pragma unroll
         for (int u = 0; u < PB; u++) {
-            const int i = tid + u * 256, k = i / TC, c = i % TC;
+            const int i = tid + u * NT, k = i / (TC * CG), c = i % (TC * CG);
             pB[u] = (k < kn && c0 + c < ncol) ? (T)B[(int64_t)(ks - t.k0 + k) * t.ldb + c0 + c] : (T)0;
         }
     };
@@ -134,22 +140,22 @@ __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, 
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < PS; u++) {
-            const int i = tid + u * 256;
-            if (XR || i < kKS * d) sS[i] = pS[u];
+            const int i = tid + u * NT;
+            if (XR ? i < SS : i < kKS * d) sS[i] = pS[u];
         }
 #pragma unroll
         for (int u = 0; u < PB; u++) {
-            const int i = tid + u * 256;
-            sB[i / TC][i % TC] = pB[u];
+            const int i = tid + u * NT;
+            sB[i / (TC * CG)][i % (TC * CG)] = pB[u];
         }
         __syncthreads();
         if (ks + kKS < k1) fetch(ks + kKS);
-        // generate the kernel tile: 64 x 16 entries, 4 per thread (thread
-        // tid: row tid % 64 = its lane, columns tid / 64 + 4 m)
+        // generate the kernel tile: 64 x 16 entries, 4 / CG per thread
+        // (thread tid: row tid % 64 = its lane, columns tid / 64 + 4 CG m)
         if constexpr (XR) {
 #pragma unroll
-            for (int m = 0; m < 4; m++) {
-                const int k = wave + 4 * m;
+            for (int m = 0; m < kKS / (4 * CG); m++) {
+                const int k = wave + 4 * CG * m;
                 T v = (T)0;
                 if (k < kn && r0 + lane < nrow) {
                     const T *y = sS + k * kXrDim;
@@ -165,7 +171,7 @@ __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, 
                 sA[lane][k] = v;
             }
         } else {
-            for (int i = tid; i < kTR * kKS; i += 256) {
+            for (int i = tid; i < kTR * kKS; i += NT) {
                 int r = i % kTR, k = i / kTR;
                 T v = (T)0;
                 if (k < kn && r0 + r < nrow) {
@@ -184,20 +190,20 @@ __global__ __launch_bounds__(256) void k_kmm(const KmmTask *__restrict__ tasks, 
         __syncthreads();
 #pragma unroll
         for (int k4 = 0; k4 < kKS; k4 += 4) {
-            T a = sA[wave * 16 + lane % 16][k4 + lane / 16];
+            T a = sA[wr * 16 + lane % 16][k4 + lane / 16];
 #pragma unroll
             for (int b = 0; b < NB; b++) {
-                T bb = sB[k4 + lane / 16][b * 16 + lane % 16];
+                T bb = sB[k4 + lane / 16][wc * TC + b * 16 + lane % 16];
                 acc[b] = Acc<T>::mma(a, bb, acc[b]);
             }
         }
     }
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        const int c = c0 + b * 16 + lane % 16;
+        const int c = c0 + wc * TC + b * 16 + lane % 16;
         if (c >= ncol) continue;
         for (int q = 0; q < 4; q++) {
-            const int r = r0 + wave * 16 + Acc<T>::row(lane, q);
+            const int r = r0 + wr * 16 + Acc<T>::row(lane, q);
             if (r < nrow) store_out(C, (int64_t)r * t.crs + (int64_t)c * t.ccs, (TO)acc[b][q], t.op);
             else if (r < t.rcap && t.op == OP_STORE) C[(int64_t)r * t.crs + (int64_t)c * t.ccs] = (TO)0;
         }
@@ -303,12 +309,12 @@ __global__ void k_reduce(const RedTask *__restrict__ tasks, int ncol, int blocks
     store_out(glb((TO *)t.dst), (int64_t)r * t.drs + (int64_t)c * t.dcs, (TO)acc, t.op);
 }
 
-#define KMM_INST(T, TB, TO, TC)                                                                    \
-    template __global__ void k_kmm<T, TB, TO, TC, false>(const KmmTask *, const TileItem *, int, int); \
-    template __global__ void k_kmm<T, TB, TO, TC, true>(const KmmTask *, const TileItem *, int, int);
-#define KMM_ALL(T, TB, TO) KMM_INST(T, TB, TO, 16) KMM_INST(T, TB, TO, 64) KMM_INST(T, TB, TO, 128)
+#define KMM_INST(T, TB, TO, TC, CG)                                                                    \
+    template __global__ void k_kmm<T, TB, TO, TC, false, CG>(const KmmTask *, const TileItem *, int, int); \
+    template __global__ void k_kmm<T, TB, TO, TC, true, CG>(const KmmTask *, const TileItem *, int, int);
+#define KMM_ALL(T, TB, TO) KMM_INST(T, TB, TO, 16, 1) KMM_INST(T, TB, TO, 64, 1) KMM_INST(T, TB, TO, 128, 1)
 KMM_ALL(double, double, double)
-KMM_INST(double, double, double, 256)
+KMM_INST(double, double, double, 128, 2)
 KMM_ALL(float, float, float)
 KMM_ALL(float, float, double)
 KMM_ALL(double, float, double)
