@@ -163,21 +163,21 @@ ROOF_KIND = {
 TRAFFIC = {
     "skel:k_qs_step": {
         "source": ["k_skel.hip", "askit_dev.h"],
-        "src_sha256": "de4824c106d7466a92f70be94513050d7ca829a886799d07d14d11f773003882",
+        "src_sha256": "0586e38bcae159acdd81463db7703b739763c032328ec820258bd67a5e0dbe14",
         "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": (2357.4 * 2.0 + 3746.4) * 1024.0,
+        "bytes_per_launch": (2356.9 * 2.0 + 3746.4) * 1024.0,
     },
     "skel:k_qrcp": {
         "source": ["k_skel.hip", "askit_dev.h"],
-        "src_sha256": "de4824c106d7466a92f70be94513050d7ca829a886799d07d14d11f773003882",
+        "src_sha256": "0586e38bcae159acdd81463db7703b739763c032328ec820258bd67a5e0dbe14",
         "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": (1042740.5 * 2.0 + 1643313.1) * 1024.0,
+        "bytes_per_launch": (1042445.0 * 2.0 + 1641988.0) * 1024.0,
     },
     "factor:k_lu_nopiv": {
         "source": ["k_lu.hip", "askit_dev.h"],
-        "src_sha256": "c5e25716cb6a578a534550b417e0bd16064560ea4baaa7308903e0b89d91a7d6",
+        "src_sha256": "9ac23dd4d35a11b11d1948683ec6c05201822bcfe71c133de2738afe3bfa6365",
         "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": (7701579.6 * 2.0 + 16277863.1) * 1024.0,
+        "bytes_per_launch": (7704740.9 * 2.0 + 16280838.5) * 1024.0,
     },
 }
 
