@@ -156,17 +156,23 @@ struct DBuf {
         return ASKIT_OK;
     }
     template <class T> T *as() const { return (T *)p; }
+    void swap(DBuf &o) {
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
+        std::swap(dev, o.dev);
+    }
 };
 
 // Host-to-device uploads of task lists are synchronous copies, except while
 // an upload stream is set (UploadOnStream): then they are queued on that
 // stream from host copies kept until the guard ends, so they neither wait
 // for nor delay the kernels queued on other streams.
-thread_local hipStream_t g_upload_stream = nullptr;  // per calling thread: calls on other handles may overlap
+thread_local bool g_upload_async = false;  // per calling thread: calls on other handles may overlap
+thread_local hipStream_t g_upload_stream = nullptr;  // may be the null stream
 thread_local std::vector<std::vector<char>> g_upload_keep;
 
 static askit_status copy_up(void *dst, const void *src, size_t bytes) {
-    if (g_upload_stream) {
+    if (g_upload_async) {
         g_upload_keep.emplace_back((const char *)src, (const char *)src + bytes);
         HIP_TRY(hipMemcpyAsync(dst, g_upload_keep.back().data(), bytes, hipMemcpyHostToDevice, g_upload_stream));
     } else {
@@ -179,8 +185,14 @@ static askit_status copy_up(void *dst, const void *src, size_t bytes) {
 // released at the end of the call that owns the guard (after it has
 // synchronized with `s`)
 struct UploadOnStream {
-    explicit UploadOnStream(hipStream_t s) { g_upload_stream = s; }
-    ~UploadOnStream() { g_upload_stream = nullptr; }
+    explicit UploadOnStream(hipStream_t s) {
+        g_upload_async = true;
+        g_upload_stream = s;
+    }
+    ~UploadOnStream() {
+        g_upload_async = false;
+        g_upload_stream = nullptr;
+    }
 };
 
 template <class T> askit_status upload(DBuf &b, const std::vector<T> &v) {
@@ -198,6 +210,23 @@ template <class T> askit_status upload_grow(DBuf &b, const std::vector<T> &v) {
 }
 static askit_status grow(DBuf &b, size_t n) {
     if (b.bytes < n) ST_TRY(b.alloc(n));
+    return ASKIT_OK;
+}
+
+// the same, with an outgrown buffer moved to `retired` instead of released
+// (a release synchronizes the device)
+static askit_status grow_keep(std::vector<std::unique_ptr<DBuf>> &retired, DBuf &b, size_t n) {
+    if (b.bytes >= n) return ASKIT_OK;
+    if (b.p) {
+        retired.emplace_back(new DBuf());
+        retired.back()->swap(b);
+    }
+    return b.alloc(n);
+}
+template <class T>
+askit_status upload_grow_keep(std::vector<std::unique_ptr<DBuf>> &retired, DBuf &b, const std::vector<T> &v) {
+    ST_TRY(grow_keep(retired, b, sizeof(T) * std::max<size_t>(v.size(), 1)));
+    if (!v.empty()) ST_TRY(copy_up(b.p, v.data(), sizeof(T) * v.size()));
     return ASKIT_OK;
 }
 
@@ -737,6 +766,10 @@ struct askit_tree_s {
     double t_knn = 0;
     unsigned long long knn_points = 0;  // points the neighbour search compared, summed over its waves
     std::vector<Tune> tune;  // per tree height, from askit_tune_factorization (empty: built-in choices)
+    int32_t *hsr_pinned = nullptr;  // pinned landing buffer of the rank reads (nnodes)
+    ~askit_tree_s() {
+        if (hsr_pinned) (void)hipHostFree(hsr_pinned);
+    }
     std::vector<int64_t> nb, ne;  // host node ranges
     DBuf X, Xp, perm, iperm, dnb, dne;  // iperm[original index] = tree position
     DBuf srank, trunc, skel, Pt, samp, qrows;
@@ -1112,6 +1145,11 @@ struct SkelRun {
     hipStream_t st = nullptr;
     DBuf M, err, dsamp, dsk, dqr, dsplit;
     DBuf wpart, wrmap, wrows, wnrm, wpos, wdiag, wst;
+    // Buffers outgrown by a later height are released when the run ends, not
+    // when they are replaced: a release synchronizes the device, which in the
+    // pipelined call would wait for the factorization queued on the other
+    // stream and stall the skeleton chain.
+    std::vector<std::unique_ptr<DBuf>> retired;
     // launch parameters of the prepared height
     int nqr = 0, n1 = 0, nsp = 0, split_steps = 0;
     QrWork w{};
@@ -1149,13 +1187,21 @@ struct SkelRun {
         return ASKIT_OK;
     }
 
-    // the ranks decided so far, on the host
+    // the ranks decided so far, on the host (through pinned memory: a copy
+    // to pageable memory goes through the runtime's staging path, which
+    // does not stay ordered on `st` alone)
     askit_status read_ranks() {
-        for (int i = 0; i < count; i++)
-            HIP_TRY(hipMemcpyAsync(trees[i]->hsr.data(), trees[i]->srank.p, sizeof(int32_t) * trees[i]->nnodes,
-                                   hipMemcpyDeviceToHost, st));
+        for (int i = 0; i < count; i++) {
+            askit_tree t = trees[i];
+            if (!t->hsr_pinned) HIP_TRY(hipHostMalloc((void **)&t->hsr_pinned, sizeof(int32_t) * t->nnodes));
+            HIP_TRY(hipMemcpyAsync(t->hsr_pinned, t->srank.p, sizeof(int32_t) * t->nnodes, hipMemcpyDeviceToHost,
+                                   st));
+        }
         HIP_TRY(hipStreamSynchronize(st));
-        for (int i = 0; i < count; i++) trees[i]->hsr[0] = 0;
+        for (int i = 0; i < count; i++) {
+            std::copy(trees[i]->hsr_pinned, trees[i]->hsr_pinned + trees[i]->nnodes, trees[i]->hsr.begin());
+            trees[i]->hsr[0] = 0;
+        }
         return ASKIT_OK;
     }
 
@@ -1165,6 +1211,12 @@ struct SkelRun {
         // and need neither samples nor a QR
         if (hgt > 0) ST_TRY(read_ranks());
         else HIP_TRY(hipStreamSynchronize(st));
+        // in the pipelined call the task lists are queued on the skeleton
+        // stream itself (host copies kept until the call ends): a synchronous
+        // copy would also wait for the factorization queued on the other
+        // stream, and stall the skeleton chain for as long
+        std::unique_ptr<UploadOnStream> on_stream;
+        if (pipelined) on_stream.reset(new UploadOnStream(st));
         std::vector<SampTask> samp_one, samp_split;
         std::vector<SkelTask> qr_one, qr_split, ident;
         int split_cols = 0;
@@ -1230,30 +1282,30 @@ struct SkelRun {
         nsp = (int)qr_split.size();
         const int none_ = (int)qr_one.size();
         const int64_t slot = (int64_t)nsamp_max * cmax;  // sampled block per node, column-major, ld nsamp_max
-        ST_TRY(grow(M, sizeof(double) * std::max(nqr, 1) * slot));
+        ST_TRY(grow_keep(retired, M, sizeof(double) * std::max(nqr, 1) * slot));
         for (int j = 0; j < nqr; j++) qr[j].M = M.as<double>() + (int64_t)j * slot;
         for (int j = 0; j < nsp; j++) qr_split[j].M = qr[none_ + j].M;
         std::vector<SkelTask> one(qr.begin(), qr.begin() + none_);
         one.insert(one.end(), ident.begin(), ident.end());
         n1 = (int)one.size();
         if (nqr > 0) {
-            ST_TRY(upload_grow(dsamp, samp));
-            ST_TRY(upload_grow(dsk, qr));
+            ST_TRY(upload_grow_keep(retired, dsamp, samp));
+            ST_TRY(upload_grow_keep(retired, dsk, qr));
         }
-        if (n1 > 0) ST_TRY(upload_grow(dqr, one));
+        if (n1 > 0) ST_TRY(upload_grow_keep(retired, dqr, one));
         if (nsp > 0) {
             w = QrWork{};
             w.cmax = cmax;
             w.rcap = nsamp_max;
             w.slices = (int)cdiv(split_cols, kQsCols);
-            ST_TRY(upload_grow(dsplit, qr_split));
-            ST_TRY(grow(wpart, sizeof(double) * (size_t)nsp * w.slices * w.rcap));
-            ST_TRY(grow(wrmap, sizeof(int32_t) * (size_t)nsp * w.rcap));
-            ST_TRY(grow(wrows, sizeof(int32_t) * (size_t)nsp));
-            ST_TRY(grow(wnrm, sizeof(double) * (size_t)nsp * 2 * cmax));
-            ST_TRY(grow(wpos, sizeof(int32_t) * (size_t)nsp * 2 * cmax));
-            ST_TRY(grow(wdiag, sizeof(double) * (size_t)nsp * cmax));
-            ST_TRY(grow(wst, sizeof(int32_t) * (size_t)nsp * kQsState));
+            ST_TRY(upload_grow_keep(retired, dsplit, qr_split));
+            ST_TRY(grow_keep(retired, wpart, sizeof(double) * (size_t)nsp * w.slices * w.rcap));
+            ST_TRY(grow_keep(retired, wrmap, sizeof(int32_t) * (size_t)nsp * w.rcap));
+            ST_TRY(grow_keep(retired, wrows, sizeof(int32_t) * (size_t)nsp));
+            ST_TRY(grow_keep(retired, wnrm, sizeof(double) * (size_t)nsp * 2 * cmax));
+            ST_TRY(grow_keep(retired, wpos, sizeof(int32_t) * (size_t)nsp * 2 * cmax));
+            ST_TRY(grow_keep(retired, wdiag, sizeof(double) * (size_t)nsp * cmax));
+            ST_TRY(grow_keep(retired, wst, sizeof(int32_t) * (size_t)nsp * kQsState));
             w.part = wpart.as<double>();
             w.rmap = wrmap.as<int32_t>();
             w.rows = wrows.as<int32_t>();
