@@ -890,13 +890,16 @@ askit_status askit_profile_report(char *json, size_t cap) {
 // Neighbours of every point (exact, k_knn) and the ranked neighbour list of
 // every non-root node, bottom-up (k_nbr_rank); list lengths copied to the host.
 template <int K>
-static void launch_knn(int dpad, const double *Xp, int64_t N, int d, const double *lo, const double *hi, int kappa,
-                       int32_t *out, unsigned long long *visits, hipStream_t st) {
+static void launch_knn(int dpad, const double *Xp, int64_t N, int d, const float *lo, const float *hi,
+                       const int64_t *levoff, int top, int kappa, int32_t *out, unsigned long long *visits,
+                       hipStream_t st) {
     const dim3 g((unsigned)cdiv(N, kWave)), b(kWave);
-    if (dpad == 16) hipLaunchKernelGGL((k_knn<K, 16>), g, b, 0, st, Xp, N, d, lo, hi, kappa, out, visits);
-    else if (dpad == 32) hipLaunchKernelGGL((k_knn<K, 32>), g, b, 0, st, Xp, N, d, lo, hi, kappa, out, visits);
+    if (dpad == 16)
+        hipLaunchKernelGGL((k_knn<K, 16>), g, b, 0, st, Xp, N, d, lo, hi, levoff, top, kappa, out, visits);
+    else if (dpad == 32)
+        hipLaunchKernelGGL((k_knn<K, 32>), g, b, 0, st, Xp, N, d, lo, hi, levoff, top, kappa, out, visits);
     else if constexpr (K <= 32)
-        hipLaunchKernelGGL((k_knn<K, 64>), g, b, 0, st, Xp, N, d, lo, hi, kappa, out, visits);
+        hipLaunchKernelGGL((k_knn<K, 64>), g, b, 0, st, Xp, N, d, lo, hi, levoff, top, kappa, out, visits);
 }
 
 static askit_status build_neighbor_lists(askit_tree t, hipStream_t st) {
@@ -904,11 +907,20 @@ static askit_status build_neighbor_lists(askit_tree t, hipStream_t st) {
     const int d = t->d, kappa = t->knn;
     const int dpad = d <= 16 ? 16 : (d <= 32 ? 32 : 64);
     const int64_t nrun = cdiv(N, 64);
-    DBuf lo, hi, scratch, visits;
+    // box tree over the runs: level 0 = the runs, each level half the one below
+    std::vector<int64_t> levoff{0};
+    for (int64_t n = nrun;; n = (n + 1) / 2) {
+        levoff.push_back(levoff.back() + n);
+        if (n == 1) break;
+    }
+    const int top = (int)levoff.size() - 2;
+    const int64_t nbox = levoff.back();
+    DBuf lo, hi, scratch, visits, dlev;
     ST_TRY(visits.alloc(sizeof(unsigned long long)));
     HIP_TRY(hipMemsetAsync(visits.p, 0, sizeof(unsigned long long), st));
-    ST_TRY(lo.alloc(sizeof(double) * nrun * dpad));
-    ST_TRY(hi.alloc(sizeof(double) * nrun * dpad));
+    ST_TRY(lo.alloc(sizeof(float) * nbox * dpad));
+    ST_TRY(hi.alloc(sizeof(float) * nbox * dpad));
+    ST_TRY(upload(dlev, levoff));
     ST_TRY(t->knnidx.alloc(sizeof(int32_t) * N * kappa));
     ST_TRY(t->nbpos.alloc(sizeof(int32_t) * t->nnodes * t->nsamp));
     ST_TRY(t->nbw.alloc(sizeof(int32_t) * t->nnodes * t->nsamp));
@@ -916,17 +928,24 @@ static askit_status build_neighbor_lists(askit_tree t, hipStream_t st) {
     HIP_TRY(hipMemsetAsync(t->nblen.p, 0, sizeof(int32_t) * t->nnodes, st));
     HIP_TRY(timed("tree:k_knn_boxes", st, [&] {
         hipLaunchKernelGGL(k_knn_boxes, dim3(grid1(nrun * dpad)), dim3(256), 0, st, t->Xp.as<double>(), N, d, dpad,
-                           lo.as<double>(), hi.as<double>());
+                           lo.as<float>(), hi.as<float>());
+        for (int l = 1; l <= top; l++) {
+            const int64_t nat = levoff[l + 1] - levoff[l];
+            hipLaunchKernelGGL(k_knn_box_up, dim3(grid1(nat * dpad)), dim3(256), 0, st, lo.as<float>(),
+                               hi.as<float>(), levoff[l - 1], levoff[l] - levoff[l - 1], levoff[l], nat, dpad);
+        }
         return hipGetLastError();
     }));
     HIP_TRY(timed("tree:k_knn", st, [&] {
-        const double *Xp = t->Xp.as<double>(), *L = lo.as<double>(), *H = hi.as<double>();
+        const double *Xp = t->Xp.as<double>();
+        const float *L = lo.as<float>(), *H = hi.as<float>();
+        const int64_t *lv = dlev.as<int64_t>();
         int32_t *o = t->knnidx.as<int32_t>();
         unsigned long long *v = visits.as<unsigned long long>();
-        if (kappa <= 8) launch_knn<8>(dpad, Xp, N, d, L, H, kappa, o, v, st);
-        else if (kappa <= 16) launch_knn<16>(dpad, Xp, N, d, L, H, kappa, o, v, st);
-        else if (kappa <= 32) launch_knn<32>(dpad, Xp, N, d, L, H, kappa, o, v, st);
-        else launch_knn<64>(dpad, Xp, N, d, L, H, kappa, o, v, st);
+        if (kappa <= 8) launch_knn<8>(dpad, Xp, N, d, L, H, lv, top, kappa, o, v, st);
+        else if (kappa <= 16) launch_knn<16>(dpad, Xp, N, d, L, H, lv, top, kappa, o, v, st);
+        else if (kappa <= 32) launch_knn<32>(dpad, Xp, N, d, L, H, lv, top, kappa, o, v, st);
+        else launch_knn<64>(dpad, Xp, N, d, L, H, lv, top, kappa, o, v, st);
         return hipGetLastError();
     }));
     for (int l = t->D; l >= 1; l--) {

@@ -42,10 +42,11 @@ __global__ void k_qs_step(const SkelTask *tasks, QrWork w, int j, int ldm);
 __global__ void k_qs_finish(const SkelTask *tasks, QrWork w, int s, int ldm);
 
 // kappa-NN sampling (k_knn.hip)
-__global__ void k_knn_boxes(const double *Xp, int64_t N, int d, int dpad, double *lo, double *hi);
+__global__ void k_knn_boxes(const double *Xp, int64_t N, int d, int dpad, float *lo, float *hi);
+__global__ void k_knn_box_up(float *lo, float *hi, int64_t below, int64_t nbelow, int64_t at, int64_t nat, int dpad);
 template <int K, int DIM>
-__global__ void k_knn(const double *Xp, int64_t N, int d, const double *lo, const double *hi, int kappa,
-                      int32_t *out, unsigned long long *visits);
+__global__ void k_knn(const double *Xp, int64_t N, int d, const float *lo, const float *hi, const int64_t *levoff,
+                      int top, int kappa, int32_t *out, unsigned long long *visits);
 __global__ void k_nbr_rank(NbrTask t, int64_t first, int64_t pmax, uint64_t *scratch);
 
 // LU (k_lu.hip)

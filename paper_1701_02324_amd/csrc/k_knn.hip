@@ -2,18 +2,19 @@
 // skeletonization (the kappa of the sampling in Sec. 4, Table "speedup":
 // the neighbours of a node's points that lie outside it are sampled first).
 //
-//  * k_knn_boxes: the bounding box of every run of kKnnRun consecutive tree
-//    positions (the tree keeps such runs spatially compact).
+//  * k_knn_boxes, k_knn_box_up: the bounding box of every run of kKnnRun
+//    consecutive tree positions (the tree keeps such runs spatially
+//    compact), and a binary tree of boxes over the runs.
 //  * k_knn: exact all-kappa-nearest neighbours, one wave per 64 query
-//    points.  The wave visits the runs outward from its own (own run, next,
-//    previous, ...); a run is skipped when, for every lane, the distance
-//    from its query to the run's box is above the lane's current kappa-th
-//    distance (with a 1e-12 relative margin that covers the rounding of
-//    both distances), otherwise its points are staged in LDS and compared
-//    one by one (the number of points compared, per wave, is counted in
-//    `visits`).  Each lane keeps its sorted
-//    list (squared distance, position) in registers and inserts by a fixed
-//    compare-exchange pass, so the result does not depend on the visiting
+//    points.  The wave walks the box tree depth first, nearer child first;
+//    a subtree is skipped when, for every lane, the distance from its query
+//    to the subtree's box is above the lane's current kappa-th distance
+//    (with a 1e-12 relative margin that covers the rounding of both
+//    distances); the points of the runs reached are staged in LDS and
+//    compared one by one (the number of points compared, per wave, is
+//    counted in `visits`).  Each lane keeps its sorted
+//    list (squared distance, position) in registers and inserts by a fixed,
+//    branch-free pass over it, so the result does not depend on the visiting
 //    order: the kappa smallest pairs in lexicographic order.  Distances are
 //    fma(t, t, r2) over t = x_k - y_k in increasing k; the padded
 //    coordinates (zero on both sides) add exact zeros.
@@ -35,11 +36,21 @@ namespace askit {
 
 constexpr int kKnnRun = 64;  // positions per bounding box
 
-__device__ inline bool nn_before(double da, int ia, double db, int ib) { return da < db || (da == db && ia < ib); }
+__device__ inline bool nn_before(double da, int ia, double db, int ib) { return (da < db) | ((da == db) & (ia < ib)); }
 
-// thread -> (run, dimension): min and max of the run's coordinates
-__global__ void k_knn_boxes(const double *__restrict__ Xp, int64_t N, int d, int dpad, double *__restrict__ lo,
-                            double *__restrict__ hi) {
+// thread -> (run, dimension): min and max of the run's coordinates, stored
+// in FP32 rounded outward (the box can only grow, so the distance bounds
+// stay lower bounds)
+__device__ inline float round_down_f(double v) {
+    float f = (float)v;
+    return (double)f > v ? nextafterf(f, -INFINITY) : f;
+}
+__device__ inline float round_up_f(double v) {
+    float f = (float)v;
+    return (double)f < v ? nextafterf(f, INFINITY) : f;
+}
+__global__ void k_knn_boxes(const double *__restrict__ Xp, int64_t N, int d, int dpad, float *__restrict__ lo,
+                            float *__restrict__ hi) {
     const int64_t nrun = (N + kKnnRun - 1) / kKnnRun;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= nrun * dpad) return;
@@ -55,35 +66,43 @@ __global__ void k_knn_boxes(const double *__restrict__ Xp, int64_t N, int d, int
             b = fmax(b, v);
         }
     }
-    lo[g] = a;
-    hi[g] = b;
+    lo[g] = round_down_f(a);
+    hi[g] = round_up_f(b);
+}
+
+// box of node i of a level of the box tree: the union of its children 2i
+// and 2i + 1 (when it exists) on the level below; boxes at stride dpad
+__global__ void k_knn_box_up(float *__restrict__ lo, float *__restrict__ hi, int64_t below, int64_t nbelow,
+                             int64_t at, int64_t nat, int dpad) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nat * dpad) return;
+    const int64_t i = g / dpad;
+    const int k = (int)(g % dpad);
+    const int64_t c0 = below + 2 * i, c1 = 2 * i + 1 < nbelow ? c0 + 1 : c0;
+    lo[(at + i) * dpad + k] = fmin(lo[c0 * dpad + k], lo[c1 * dpad + k]);
+    hi[(at + i) * dpad + k] = fmax(hi[c0 * dpad + k], hi[c1 * dpad + k]);
 }
 
 // K: list length kept in registers (>= kappa); DIM: coordinates per point
-// held (>= d, zero padded).  Points are read from Xp at stride d; boxes at
-// stride DIM.  The wave takes the runs in batches of kKnnBatch (in the
-// outward order): the batch's boxes are staged in LDS and tested against
-// every lane's query (a run is kept if any lane may find a neighbour in
-// it), then each kept run is tested again with the lanes' current
-// thresholds and, if still kept, its points are staged in LDS and compared.
-constexpr int kKnnBatch = 32;
+// held (>= d, zero padded).  Points are read from Xp at stride d.  The runs'
+// boxes form a binary tree (level 0: the runs; node i of level l covers runs
+// i 2^l .. (i + 1) 2^l - 1; boxes at stride DIM, level l from levoff[l]).
+// The wave walks it depth first from the root, the child nearer to its own
+// run first: a node is skipped when every lane's query is farther from its
+// box than the lane's current kappa-th distance (with the 1e-12 margin); a
+// run that is not skipped has its points staged in LDS and compared.  The
+// stack (node = level << 26 | index) lives in the lanes' registers.
 // points compared together (independent distance chains): four for short
-// lists of points of at most 16 coordinates; one otherwise, where the
-// registers leave no room for four (measured at 2^20 points in 16-D: kappa =
-// 8 168 against 185 ms, kappa = 32 246 against 366 ms)
+// lists of points of at most 16 coordinates; one otherwise, where four (or
+// two) leave one wave per SIMD or spill the list
 template <int K, int DIM> constexpr int knn_group() { return K <= 16 && DIM <= 16 ? 4 : 1; }
-__device__ inline int64_t knn_run_of(int64_t u, int64_t r0, int64_t nrun) {
-    // outward from the wave's own run: 0, +1, -1, +2, -2, ...
-    const int64_t r = r0 + ((u & 1) ? (u + 1) / 2 : -(u / 2));
-    return r < 0 ? r + nrun : (r >= nrun ? r - nrun : r);
-}
 
 template <int K, int DIM>
 __global__ __launch_bounds__(64) void k_knn(const double *__restrict__ Xp, int64_t N, int d,
-                                            const double *__restrict__ lo, const double *__restrict__ hi, int kappa,
+                                            const float *__restrict__ lo, const float *__restrict__ hi,
+                                            const int64_t *__restrict__ levoff, int top, int kappa,
                                             int32_t *__restrict__ out, unsigned long long *__restrict__ visits) {
-    __shared__ double sp[kKnnRun * DIM];          // points of the run being compared
-    __shared__ double sb[kKnnBatch * 2 * DIM];    // boxes of the batch: lo then hi per run
+    __shared__ double sp[kKnnRun * DIM];  // points of the run being compared
     const int lane = threadIdx.x;
     const int64_t q0 = (int64_t)blockIdx.x * kWave, q = q0 + lane;
     const bool live = q < N;
@@ -97,78 +116,88 @@ __global__ __launch_bounds__(64) void k_knn(const double *__restrict__ Xp, int64
         ld[t] = INFINITY;
         li[t] = 0x7fffffff;
     }
-    // lower bound of the squared distance from this lane's query to box i
-    // of the batch
-    auto bound = [&](int i) {
-        const double *bl = sb + i * 2 * DIM, *bh = bl + DIM;
+    const int64_t nrun = (N + kKnnRun - 1) / kKnnRun, r0 = q0 / kKnnRun;
+    constexpr int kIdxBits = 26;
+    int stk = 0, nst = 0;  // lane t holds stack entry t; nst is uniform
+    auto push = [&](int lvl, int64_t idx) {
+        if (lane == nst) stk = (lvl << kIdxBits) | (int)idx;
+        nst++;
+    };
+    push(top, 0);
+    while (nst > 0) {
+        nst--;
+        const int node = __builtin_amdgcn_readlane(stk, nst);
+        const int lvl = node >> kIdxBits;
+        const int64_t idx = node & ((1 << kIdxBits) - 1);
+        // lower bound of the squared distance from this lane's query to the box
+        const float *bl = lo + (levoff[lvl] + idx) * DIM, *bh = hi + (levoff[lvl] + idx) * DIM;
         double lb = 0.0;
 #pragma unroll
         for (int k = 0; k < DIM; k++) {
-            const double g = fmax(fmax(bl[k] - x[k], x[k] - bh[k]), 0.0);
+            const double g = fmax(fmax((double)bl[k] - x[k], x[k] - (double)bh[k]), 0.0);
             lb = fma(g, g, lb);
         }
-        return lb;
-    };
-    // a run may hold a neighbour of a lane unless its bound exceeds the
-    // lane's kappa-th distance by the 1e-12 margin
-    auto may = [&](double lb) { return live && !(lb * (1.0 - 1e-12) > ld[K - 1]); };
-    const int64_t nrun = (N + kKnnRun - 1) / kKnnRun, r0 = q0 / kKnnRun;
-    for (int64_t u0 = 0; u0 < nrun; u0 += kKnnBatch) {
-        const int nb = nrun - u0 < kKnnBatch ? (int)(nrun - u0) : kKnnBatch;
+        if (!__any(live && !(lb * (1.0 - 1e-12) > ld[K - 1]))) continue;
+        if (lvl > 0) {
+            // children on the level below: the one nearer to this wave's own
+            // run goes on top of the stack
+            const int64_t c0 = 2 * idx, c1 = 2 * idx + 1;
+            const int64_t nbelow = levoff[lvl] - levoff[lvl - 1];
+            const bool right_near = (r0 >> (lvl - 1)) > c0;
+            if (c1 < nbelow) {
+                if (right_near) {
+                    push(lvl - 1, c0);
+                    push(lvl - 1, c1);
+                } else {
+                    push(lvl - 1, c1);
+                    push(lvl - 1, c0);
+                }
+            } else {
+                push(lvl - 1, c0);
+            }
+            continue;
+        }
+        const int64_t j0 = idx * kKnnRun;
+        const int nj = nrun - 1 == idx ? (int)(N - j0) : kKnnRun;
         __syncthreads();
-        for (int e = lane; e < nb * 2 * DIM; e += kWave) {
-            const int i = e / (2 * DIM), k = e % (2 * DIM);
-            const int64_t r = knn_run_of(u0 + i, r0, nrun);
-            sb[e] = k < DIM ? lo[r * DIM + k] : hi[r * DIM + k - DIM];
+        if (lane < nj) {
+#pragma unroll
+            for (int k = 0; k < DIM; k++) sp[lane * DIM + k] = k < d ? Xp[(j0 + lane) * d + k] : 0.0;
         }
         __syncthreads();
-        uint64_t mask = 0;
-        for (int i = 0; i < nb; i++)
-            if (__any(may(bound(i)))) mask |= 1ull << i;
-        while (mask) {
-            const int i = __builtin_ctzll(mask);
-            mask &= mask - 1;
-            if (!__any(may(bound(i)))) continue;  // thresholds fell since the batch test
-            const int64_t r = knn_run_of(u0 + i, r0, nrun);
-            const int64_t j0 = r * kKnnRun;
-            const int nj = N - j0 < kKnnRun ? (int)(N - j0) : kKnnRun;
-            __syncthreads();
-            if (lane < nj) {
+        if (lane == 0) atomicAdd(visits, (unsigned long long)nj);  // points compared by this wave
+        constexpr int kKnnGroup = knn_group<K, DIM>();
+        for (int j4 = 0; j4 < nj; j4 += kKnnGroup) {
+            double r2[kKnnGroup];
 #pragma unroll
-                for (int k = 0; k < DIM; k++) sp[lane * DIM + k] = k < d ? Xp[(j0 + lane) * d + k] : 0.0;
-            }
-            __syncthreads();
-            if (lane == 0) atomicAdd(visits, (unsigned long long)nj);  // points compared by this wave
-            constexpr int kKnnGroup = knn_group<K, DIM>();
-            for (int j4 = 0; j4 < nj; j4 += kKnnGroup) {
-                double r2[kKnnGroup];
+            for (int p = 0; p < kKnnGroup; p++) r2[p] = 0.0;
 #pragma unroll
-                for (int p = 0; p < kKnnGroup; p++) r2[p] = 0.0;
-#pragma unroll
-                for (int k = 0; k < DIM; k++)
-#pragma unroll
-                    for (int p = 0; p < kKnnGroup; p++) {
-                        const double t = x[k] - sp[((j4 + p) & (kKnnRun - 1)) * DIM + k];
-                        r2[p] = fma(t, t, r2[p]);
-                    }
+            for (int k = 0; k < DIM; k++)
 #pragma unroll
                 for (int p = 0; p < kKnnGroup; p++) {
-                    const int j = (int)(j0 + j4 + p);
-                    if (live && j4 + p < nj && j != (int)q && nn_before(r2[p], j, ld[K - 1], li[K - 1])) {
-                        // fixed compare-exchange pass: the new pair sinks to its place
-                        double cd = r2[p];
-                        int ci = j;
+                    const double t = x[k] - sp[((j4 + p) & (kKnnRun - 1)) * DIM + k];
+                    r2[p] = fma(t, t, r2[p]);
+                }
 #pragma unroll
-                        for (int t = 0; t < K; t++) {
-                            const bool b = nn_before(cd, ci, ld[t], li[t]);
-                            const double td = ld[t];
-                            const int ti = li[t];
-                            ld[t] = b ? cd : td;
-                            li[t] = b ? ci : ti;
-                            cd = b ? td : cd;
-                            ci = b ? ti : ci;
-                        }
+            for (int p = 0; p < kKnnGroup; p++) {
+                const int j = (int)(j0 + j4 + p);
+                if (live && j4 + p < nj && j != (int)q && nn_before(r2[p], j, ld[K - 1], li[K - 1])) {
+                    // in place, from the end: entry t takes entry t - 1 when
+                    // the new pair goes before both, the new pair when it
+                    // goes before entry t only
+                    const double cd = r2[p];
+                    bool bt = true;
+#pragma unroll
+                    for (int t = K - 1; t > 0; t--) {
+                        const bool bp = nn_before(cd, j, ld[t - 1], li[t - 1]);
+                        const double nd = bp ? ld[t - 1] : cd;
+                        const int ni = bp ? li[t - 1] : j;
+                        ld[t] = bt ? nd : ld[t];
+                        li[t] = bt ? ni : li[t];
+                        bt = bp;
                     }
+                    ld[0] = bt ? cd : ld[0];
+                    li[0] = bt ? j : li[0];
                 }
             }
         }
@@ -180,28 +209,28 @@ __global__ __launch_bounds__(64) void k_knn(const double *__restrict__ Xp, int64
     }
 }
 
-template __global__ void k_knn<8, 16>(const double *, int64_t, int, const double *, const double *, int,
-                                             int32_t *, unsigned long long *);
-template __global__ void k_knn<16, 16>(const double *, int64_t, int, const double *, const double *, int,
-                                             int32_t *, unsigned long long *);
-template __global__ void k_knn<32, 16>(const double *, int64_t, int, const double *, const double *, int,
-                                             int32_t *, unsigned long long *);
-template __global__ void k_knn<64, 16>(const double *, int64_t, int, const double *, const double *, int,
-                                             int32_t *, unsigned long long *);
-template __global__ void k_knn<8, 32>(const double *, int64_t, int, const double *, const double *, int,
-                                             int32_t *, unsigned long long *);
-template __global__ void k_knn<16, 32>(const double *, int64_t, int, const double *, const double *, int,
-                                             int32_t *, unsigned long long *);
-template __global__ void k_knn<32, 32>(const double *, int64_t, int, const double *, const double *, int,
-                                             int32_t *, unsigned long long *);
-template __global__ void k_knn<64, 32>(const double *, int64_t, int, const double *, const double *, int,
-                                             int32_t *, unsigned long long *);
-template __global__ void k_knn<8, 64>(const double *, int64_t, int, const double *, const double *, int,
-                                             int32_t *, unsigned long long *);
-template __global__ void k_knn<16, 64>(const double *, int64_t, int, const double *, const double *, int,
-                                             int32_t *, unsigned long long *);
-template __global__ void k_knn<32, 64>(const double *, int64_t, int, const double *, const double *, int,
-                                             int32_t *, unsigned long long *);
+template __global__ void k_knn<8, 16>(const double *, int64_t, int, const float *, const float *,
+                                             const int64_t *, int, int, int32_t *, unsigned long long *);
+template __global__ void k_knn<16, 16>(const double *, int64_t, int, const float *, const float *,
+                                             const int64_t *, int, int, int32_t *, unsigned long long *);
+template __global__ void k_knn<32, 16>(const double *, int64_t, int, const float *, const float *,
+                                             const int64_t *, int, int, int32_t *, unsigned long long *);
+template __global__ void k_knn<64, 16>(const double *, int64_t, int, const float *, const float *,
+                                             const int64_t *, int, int, int32_t *, unsigned long long *);
+template __global__ void k_knn<8, 32>(const double *, int64_t, int, const float *, const float *,
+                                             const int64_t *, int, int, int32_t *, unsigned long long *);
+template __global__ void k_knn<16, 32>(const double *, int64_t, int, const float *, const float *,
+                                             const int64_t *, int, int, int32_t *, unsigned long long *);
+template __global__ void k_knn<32, 32>(const double *, int64_t, int, const float *, const float *,
+                                             const int64_t *, int, int, int32_t *, unsigned long long *);
+template __global__ void k_knn<64, 32>(const double *, int64_t, int, const float *, const float *,
+                                             const int64_t *, int, int, int32_t *, unsigned long long *);
+template __global__ void k_knn<8, 64>(const double *, int64_t, int, const float *, const float *,
+                                             const int64_t *, int, int, int32_t *, unsigned long long *);
+template __global__ void k_knn<16, 64>(const double *, int64_t, int, const float *, const float *,
+                                             const int64_t *, int, int, int32_t *, unsigned long long *);
+template __global__ void k_knn<32, 64>(const double *, int64_t, int, const float *, const float *,
+                                             const int64_t *, int, int, int32_t *, unsigned long long *);
 
 // ascending bitonic sort of the P keys at a (P a power of two), all threads
 template <typename PK>
