@@ -1521,7 +1521,9 @@ static const int64_t kChunk = 4096;  // contraction chunk of the split products
 // One part of the factorization plan: part -1 = the leaf LUs of
 // lambda I + K_aa (they need no skeletons), part 0 = the leaves' Phat, part
 // h >= 1 = the internal nodes at height h.  Part h >= 0 reads the ranks and
-// skeletons of heights <= h only.
+// skeletons of heights <= h only, and of a part h >= 1 the half `PartZ` (Z
+// and its LU) only those of heights <= h - 1; the half `PartPhat` (Xc =
+// Z^{-1} P_c and the telescoped Phat) needs the node's own skeleton.
 static int builtin_tc(int cols) { return cols >= 128 ? 128 : (cols >= 64 ? 64 : 16); }
 
 // smallest split chunk the factorization of t may use (sizes its workspace)
@@ -1534,8 +1536,10 @@ static int64_t tree_kc_min(askit_tree t) {
 
 // force: the tile configuration of every height of this part (tuning runs);
 // else a single tree's tuned configuration, else the built-in choice
+enum PartHalf { PartAll = 3, PartZ = 1, PartPhat = 2 };
+
 static askit_status factor_plan_part(const std::vector<askit_factor> &fs, Plan &P, int part,
-                                     const Tune *force = nullptr) {
+                                     const Tune *force = nullptr, int half = PartAll) {
     askit_tree t0 = fs[0]->t;
     const int s = t0->s, d = t0->d, s2 = 2 * s;
     const Prec pr = fs[0]->prec;
@@ -1637,8 +1641,8 @@ static askit_status factor_plan_part(const std::vector<askit_factor> &fs, Plan &
                 // column-major with leading dimension n (eq. (8))
                 const int sl = t->hsr[lc], sr = t->hsr[rc], n = sl + sr, sa = t->hsr[id];
                 double *Z = f->lu_of(id);
-                ident.push_back({Z, n, 0});
-                for (int side = 0; side < 2; side++) {
+                if (half & PartZ) ident.push_back({Z, n, 0});
+                for (int side = 0; side < 2 && (half & PartZ); side++) {
                     const int64_t a = side ? rc : lc, o = side ? lc : rc;  // skeleton of a vs points of o
                     KmmTask k{};
                     k.X = t->Xp.as<double>();
@@ -1664,8 +1668,8 @@ static askit_status factor_plan_part(const std::vector<askit_factor> &fs, Plan &
                 u.n = n;
                 u.lda = n;
                 u.ratio = f->ratio.as<double>() + id;
-                lu.push_back(u);
-                if (l >= 1) {
+                if (half & PartZ) lu.push_back(u);
+                if (l >= 1 && (half & PartPhat)) {
                     // Xc = Z^{-1} P_c with P_c = P_{alpha~ [l~ r~]}^T (n x s_alpha,
                     // row stride s), then Phat_alpha = blockdiag(Phat_l, Phat_r) Xc
                     double *xc = f->Xc.as<double>() + (id - f0) * (int64_t)s2 * s;
@@ -1865,10 +1869,10 @@ static askit_status skel_factor_impl(askit_tree t, double lambda, int precision,
     HIP_TRY(hipStreamWaitEvent(B.s, B.e, 0));
     HIP_TRY(P.run_from(B.s, t->s, 0));
     size_t done = P.steps.size();
-    auto factor_part = [&](int part) -> askit_status {
+    auto factor_part = [&](int part, int half) -> askit_status {
         {
             UploadOnStream g(U.s);
-            ST_TRY(factor_plan_part(fs, P, part));
+            ST_TRY(factor_plan_part(fs, P, part, nullptr, half));
         }
         HIP_TRY(hipEventRecord(U.e, U.s));
         HIP_TRY(hipStreamWaitEvent(B.s, U.e, 0));
@@ -1878,8 +1882,11 @@ static askit_status skel_factor_impl(askit_tree t, double lambda, int precision,
     };
     for (int hgt = 0; hgt <= R.Hmax; hgt++) {
         // wait for height hgt - 1 and read its ranks (the skeletonization
-        // uploads are made while the caller's stream is idle), launch height
-        // hgt, then build and queue the factorization of height hgt - 1
+        // uploads are made while the skeleton stream is idle), launch height
+        // hgt, then queue the rest of the factorization of height hgt - 1
+        // (Xc and Phat, which need its skeletons) and the Z blocks and LUs of
+        // height hgt (which need only those of its children), so that they
+        // run while height hgt is skeletonized
         if (hgt < R.Hmax) {
             ST_TRY(R.prepare(hgt));
             ST_TRY(R.launch(hgt));
@@ -1887,9 +1894,12 @@ static askit_status skel_factor_impl(askit_tree t, double lambda, int precision,
             ST_TRY(R.end());
             t_skel = ms_since(t0);
         }
-        if (hgt > 0) ST_TRY(factor_part(hgt - 1));
+        if (hgt > 0) {
+            ST_TRY(factor_part(hgt - 1, hgt - 1 == 0 ? PartAll : PartPhat));
+            ST_TRY(factor_part(hgt, PartZ));
+        }
     }
-    ST_TRY(factor_part(R.Hmax));
+    ST_TRY(factor_part(R.Hmax, PartPhat));  // empty at the root
     // the caller's stream continues after the factorization
     HIP_TRY(hipEventRecord(B.e, B.s));
     HIP_TRY(hipStreamWaitEvent(st, B.e, 0));
