@@ -193,6 +193,20 @@ askit_status askit_factorize(askit_tree t, double lambda, int32_t precision, voi
  * askit_skeletonize, ASKIT_ERR_ARG for a bad lambda. */
 askit_status askit_tune_factorization(askit_tree t, double lambda, void *stream);
 
+/* The factorization's tile configuration, set by the caller (to restore one
+ * that askit_tune_factorization chose earlier, e.g. from the "tune" entry of
+ * askit_get_stats, or to fix one).  table is a host array of 3 * heights
+ * int32 values; for tree height h = 1 .. heights, table[3 (h - 1)] is the
+ * output columns per k_kmm tile (64, 128 or 256), table[3 (h - 1) + 1] the
+ * contraction points per split chunk (2048, 4096 or 8192) and
+ * table[3 (h - 1) + 2] the output columns per k_gmm tile (64, 128 or 256).
+ * heights must equal the tree depth; heights = 0 (table may be NULL)
+ * returns to the built-in choice.  Applies to later factorizations as for
+ * askit_tune_factorization; the tile widths change no result, the chunk
+ * changes results by rounding only.  Errors: ASKIT_ERR_ARG for a NULL tree
+ * or table, a wrong height count or a size not listed. */
+askit_status askit_tree_set_tiling(askit_tree t, const int32_t *table, int32_t heights);
+
 /* Hybrid solver (Sec. 2.3, "Fast hybrid solver"; Alg. HybridSolve, MatVecW,
  * MatVecV) with the skeletonization frontier at tree level `level`
  * (1 .. D): the frontier's nodes and their subtrees are factored as by

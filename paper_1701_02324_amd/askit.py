@@ -28,6 +28,7 @@ EXPORTED = [
     "askit_batch_destroy", "askit_skeletonize_factorize", "askit_release_cached_memory",
     "askit_factorize_batched", "askit_tree_qr_rows", "askit_tree_samples", "askit_tree_permutation_noalloc",
     "askit_factorize_hybrid", "askit_tree_knn", "askit_tree_neighbor_lists", "askit_tune_factorization",
+    "askit_tree_set_tiling",
 ]
 
 
@@ -71,6 +72,7 @@ def load(path: str = LIB_PATH):
     L.askit_tree_samples.argtypes = [_vp, _vp]
     L.askit_tree_knn.argtypes = [_vp, _vp]
     L.askit_tune_factorization.argtypes = [_vp, ctypes.c_double, _vp]
+    L.askit_tree_set_tiling.argtypes = [_vp, _vp, _i32]
     L.askit_tree_neighbor_lists.argtypes = [_vp, _vp, _vp, _vp]
     L.askit_tree_permutation_noalloc.argtypes = [_vp, _i64, _i32, _i32, _vp, _vp]
     L.askit_skeletonize.argtypes = [_vp, _vp]
@@ -426,6 +428,19 @@ class Tree:
         and keep the fastest per tree height (askit_tune_factorization)."""
         askit_tune_factorization(self.handle, lam, stream)
         return self.stats().get("tune")
+
+    def set_tiling(self, table):
+        """Fix the factorization's tiles per height: {h: (kmm columns, kmm
+        chunk, gmm columns)} for h = 1 .. D (the form of tune()'s result),
+        or None for the built-in choice (askit_tree_set_tiling)."""
+        if table is None:
+            _check(load().askit_tree_set_tiling(self.handle, None, 0))
+            return
+        flat = []
+        for h in range(1, self.D + 1):
+            flat.extend(int(v) for v in (table[h] if h in table else table[str(h)]))
+        arr = (ctypes.c_int32 * len(flat))(*flat)
+        _check(load().askit_tree_set_tiling(self.handle, ctypes.cast(arr, _vp), len(table)))
 
     def skeletonize_factorize(self, lam, precision=ASKIT_FP64, stream=None):
         """skeletonize() then factorize(), pipelined over two streams."""

@@ -2024,6 +2024,27 @@ askit_status askit_tune_factorization(askit_tree t, double lambda, void *stream)
     return ASKIT_OK;
 }
 
+askit_status askit_tree_set_tiling(askit_tree t, const int32_t *table, int32_t heights) {
+    if (!t) return fail(ASKIT_ERR_ARG, "NULL tree");
+    if (heights == 0) {
+        t->tune.clear();
+        return ASKIT_OK;
+    }
+    if (!table) return fail(ASKIT_ERR_ARG, "table is NULL");
+    if (heights != t->D) return fail(ASKIT_ERR_ARG, "heights must equal the tree depth " + std::to_string(t->D));
+    std::vector<Tune> tn(t->D + 1);
+    auto width = [](int32_t v) { return v == 64 || v == 128 || v == 256; };
+    for (int h = 1; h <= t->D; h++) {
+        const int32_t *e = table + 3 * (h - 1);
+        if (!width(e[0]) || !width(e[2]) || !(e[1] == 2048 || e[1] == 4096 || e[1] == 8192))
+            return fail(ASKIT_ERR_ARG, "height " + std::to_string(h) + ": tile widths 64, 128 or 256 and chunks of "
+                                       "2048, 4096 or 8192 points");
+        tn[h] = Tune{e[0], e[2], e[1]};
+    }
+    t->tune = tn;
+    return ASKIT_OK;
+}
+
 askit_status askit_factorize_hybrid(askit_tree t, double lambda, int32_t level, void *stream, askit_factor *out) {
     if (!out) return fail(ASKIT_ERR_ARG, "out is NULL");
     *out = nullptr;

@@ -67,3 +67,38 @@ def test_tuned_factorization_matches(ak):
     f.close()
     assert colrel(x3, x0) < 1e-8
     t.close()
+
+
+@pytest.mark.parametrize("d", [8, 20])
+def test_tile_width_changes_no_result(ak, d):
+    """Every tile width sums the same products in the same order: 64-, 128-
+    and 256-column tiles (two 128-column wave groups sharing the generated
+    kernel tile; row points in registers for d <= 16, in LDS above) give the
+    same factors bit for bit, through both entry points; a table with sizes
+    the kernels do not have is refused."""
+    X, B = synth.small(12000, d, 43, nrhs=2, kind="mixture", scale=4.0)
+    lam = 0.5
+    print(f"[gpu tune] tile widths, N=12000 d={d} m=128 s=128", file=sys.stderr, flush=True)
+    t = ak.Tree(_cuda(X), 128, 128, 2.0, seed=5)
+    t.skeletonize()
+    Bd = _cuda(B)
+    xs = {}
+    for w in (64, 128, 256):
+        t.set_tiling({h: (w, 4096, w) for h in range(1, t.D + 1)})
+        f = t.factorize(lam, ak.ASKIT_FP64)
+        xs[w] = f.solve(Bd).cpu().numpy()
+        f.close()
+        assert t.stats()["tune"]["1"] == [w, 4096, w]
+    assert np.array_equal(xs[64], xs[128]) and np.array_equal(xs[128], xs[256])
+    f = t.skeletonize_factorize(lam, ak.ASKIT_FP64)  # still the 256-column tiles
+    assert np.array_equal(f.solve(Bd).cpu().numpy(), xs[256])
+    f.close()
+    t.set_tiling(None)
+    f = t.factorize(lam, ak.ASKIT_FP64)
+    assert np.array_equal(f.solve(Bd).cpu().numpy(), xs[128])  # built-in: 128 columns, 4096-point chunks
+    f.close()
+    with pytest.raises(ak.AskitError):
+        t.set_tiling({h: (96, 4096, 64) for h in range(1, t.D + 1)})
+    with pytest.raises(ak.AskitError):
+        t.set_tiling({h: (64, 1000, 64) for h in range(1, t.D + 1)})
+    t.close()
