@@ -576,8 +576,21 @@ askit_status gmm_commit(Plan &P, GmmBuild &gb, Prec t, int rows_red_max) {
 
 // spd: every matrix is symmetric positive definite (factored without row
 // exchanges)
-askit_status lu_commit(Plan &P, const std::vector<LuTask> &v, bool spd = false) {
-    if (v.empty()) return ASKIT_OK;
+// The matrices of one LU launch differ in order, and a launch lasts as long
+// as its slowest workgroups: the largest matrices go first (workgroups are
+// dispatched in index order), so that the small ones fill in beside them
+// instead of delaying a large one to the end.  Each task writes only its
+// own outputs, so the order changes no result.  (The solves keep the plan's
+// order: sorted, they measured slower.)
+static std::vector<LuTask> largest_first(const std::vector<LuTask> &v) {
+    std::vector<LuTask> o(v);
+    std::stable_sort(o.begin(), o.end(), [](const LuTask &a, const LuTask &b) { return a.n > b.n; });
+    return o;
+}
+
+askit_status lu_commit(Plan &P, const std::vector<LuTask> &v0, bool spd = false) {
+    if (v0.empty()) return ASKIT_OK;
+    const std::vector<LuTask> v = largest_first(v0);
     DBuf *b = P.own();
     ST_TRY(upload(*b, v));
     const LuTask *tp = b->as<LuTask>();
