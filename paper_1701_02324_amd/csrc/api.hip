@@ -258,6 +258,7 @@ typedef std::function<hipError_t(hipStream_t, int)> Launch;
 struct ProfRec {
     std::string name;
     hipEvent_t a, b;
+    int64_t launches;  // launches between the two events
 };
 struct Prof {
     bool on = false;
@@ -270,7 +271,9 @@ struct Prof {
 };
 Prof g_prof;
 
-template <class F> hipError_t timed(const std::string &name, hipStream_t st, F &&f) {
+// f issues `launches` launches (a chain of dependent launches is timed as
+// one interval, without events between its launches)
+template <class F> hipError_t timed(const std::string &name, hipStream_t st, F &&f, int64_t launches = 1) {
     if (!g_prof.on) return f();
     hipEvent_t a = nullptr, b = nullptr;
     hipError_t e = hipEventCreate(&a);
@@ -283,7 +286,7 @@ template <class F> hipError_t timed(const std::string &name, hipStream_t st, F &
     }
     e = f();
     const hipError_t e2 = hipEventRecord(b, st);
-    g_prof.pend.push_back({name, a, b});
+    g_prof.pend.push_back({name, a, b, launches});
     return e != hipSuccess ? e : e2;
 }
 
@@ -299,7 +302,7 @@ hipError_t prof_flush() {
         if (e != hipSuccess) return e;
         auto &v = g_prof.acc[r.name];
         v.first += ms;
-        v.second += 1;
+        v.second += r.launches;
         if (g_prof.timeline) {
             if (!g_prof.origin) {
                 g_prof.origin = r.a;  // kept until profiling is reset
@@ -1402,11 +1405,15 @@ struct SkelRun {
             hipLaunchKernelGGL(k_qs_init, dim3(g), dim3(kQsThreads), 0, st, tp, wk, s, nsamp_max);
             return hipGetLastError();
         }));
-        for (int j = 0; j < split_steps; j++)
-            HIP_TRY(timed("skel:k_qs_step" + hs, st, [&] {
-                hipLaunchKernelGGL(k_qs_step, dim3(g), dim3(kQsThreads), 0, st, tp, wk, j, nsamp_max);
+        // the pivot steps: one launch each, timed as one chain
+        HIP_TRY(timed(
+            "skel:k_qs_step" + hs, st,
+            [&] {
+                for (int j = 0; j < split_steps; j++)
+                    hipLaunchKernelGGL(k_qs_step, dim3(g), dim3(kQsThreads), 0, st, tp, wk, j, nsamp_max);
                 return hipGetLastError();
-            }));
+            },
+            split_steps));
         HIP_TRY(timed("skel:k_qs_finish" + hs, st, [&] {
             hipLaunchKernelGGL(k_qs_finish, dim3(nsp, (unsigned)cdiv(wk.slices * kQsCols, kQsFinishCols)), dim3(512), 0,
                                st, tp, wk, s, nsamp_max);
