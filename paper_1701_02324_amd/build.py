@@ -23,7 +23,10 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INC, "-I
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument"]
 # per-file extra flags: the tree build and the neighbour search fix the rounding of every operation
-EXTRA = {"k_tree.hip": ["-ffp-contract=off"], "k_knn.hip": ["-ffp-contract=off"]}
+EXTRA = {"k_tree.hip": ["-ffp-contract=off"], "k_knn.hip": ["-ffp-contract=off"],
+         # MFMA accumulators in VGPRs: in the AGPR form the compiler copies every
+         # accumulator to VGPRs and back around each stage of the product loops
+         "k_prod.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 SOURCES = ["api.hip", "k_tree.hip", "k_skel.hip", "k_lu.hip", "k_prod.hip", "k_misc.hip", "k_knn.hip"]
 
 

@@ -111,10 +111,23 @@ __global__ __launch_bounds__(256 * CG) void k_kmm(const KmmTask *__restrict__ ta
     for (int b = 0; b < NB; b++) acc[b] = typename Acc<T>::type{0, 0, 0, 0};
     const GLB TB *B = glb((const TB *)t.B);
     // the next stage's contraction points and B rows are fetched into
-    // registers while the current stage is generated and multiplied
+    // registers while the current stage is generated and multiplied.  Thread
+    // tid stages the same tile positions at every stage: the B addresses
+    // are set once and advance by one stage per fetch
     constexpr int SS = XR ? kKS * kXrDim : kKS * kMaxDim;  // staged contraction values (max)
     constexpr int PS = (SS + NT - 1) / NT, PB = kKS * TC * CG / NT;
     T pS[PS], pB[PB];
+    const GLB TB *qb[PB];
+    int kbb[PB];
+    bool okb[PB];
+#pragma unroll
+    for (int u = 0; u < PB; u++) {
+        const int i = tid + u * NT, k = i / (TC * CG), c = i % (TC * CG);
+        kbb[u] = k;
+        okb[u] = c0 + c < ncol;
+        qb[u] = B + (okb[u] ? (int64_t)k * t.ldb + c0 + c : 0);
+    }
+    const int64_t stepb = (int64_t)kKS * t.ldb;
     auto fetch = [&](int ks) {
         const int kn = min(kKS, k1 - ks);
 #pragma unroll
@@ -130,8 +143,8 @@ __global__ __launch_bounds__(256 * CG) void k_kmm(const KmmTask *__restrict__ ta
         }
 #pragma unroll
         for (int u = 0; u < PB; u++) {
-            const int i = tid + u * NT, k = i / (TC * CG), c = i % (TC * CG);
-            pB[u] = (k < kn && c0 + c < ncol) ? (T)B[(int64_t)(ks - t.k0 + k) * t.ldb + c0 + c] : (T)0;
+            pB[u] = (okb[u] && kbb[u] < kn) ? (T)*qb[u] : (T)0;
+            qb[u] += stepb;
         }
     };
     if (t.k0 < k1) fetch(t.k0);
@@ -230,47 +243,55 @@ __global__ __launch_bounds__(256) void k_gmm(const GmmTask *__restrict__ tasks, 
     typename Acc<T>::type acc[NB];
     for (int b = 0; b < NB; b++) acc[b] = typename Acc<T>::type{0, 0, 0, 0};
     // the next stage's A and B tiles are fetched into registers while the
-    // current stage is multiplied
+    // current stage is multiplied.  Thread tid stages the same tile
+    // positions at every stage: their coordinates, bounds and addresses are
+    // set once and the addresses advance by one stage per fetch (no
+    // per-element index arithmetic in the loop)
     constexpr int PA = kTR * kKS / 256, PB = kKS * TC / 256;
     T pA[PA], pB[PB];
+    const GLB T *qa[PA], *qb[PB];
+    int ia[PA], ib[PB];  // LDS offsets of the staged elements
+    int kaa[PA], kbb[PB];  // contraction index within the stage
+    bool oka[PA], okb[PB];
+#pragma unroll
+    for (int u = 0; u < PA; u++) {
+        const int i = tid + u * 256;
+        const int r = a_kfast ? i / kKS : i % kTR, k = a_kfast ? i % kKS : i / kTR;
+        kaa[u] = k;
+        oka[u] = r0 + r < t.rows;
+        ia[u] = r * (kKS + 1) + k;
+        qa[u] = A + (oka[u] ? (int64_t)(r0 + r) * t.ars + (int64_t)(kb + k) * t.acs : 0);
+    }
+#pragma unroll
+    for (int u = 0; u < PB; u++) {
+        const int i = tid + u * 256;
+        const int k = b_cfast ? i / TC : i % kKS, c = b_cfast ? i % TC : i / kKS;
+        kbb[u] = k;
+        okb[u] = c0 + c < ncol;
+        ib[u] = k * (TC + 1) + c;
+        qb[u] = B + (okb[u] ? (int64_t)(kb + k) * t.brs + (int64_t)(c0 + c) * t.bcs : 0);
+    }
+    const int64_t stepa = (int64_t)kKS * t.acs, stepb = (int64_t)kKS * t.brs;
     auto fetch = [&](int ks) {
         const int kn = min(kKS, ke - ks);
 #pragma unroll
         for (int u = 0; u < PA; u++) {
-            const int i = tid + u * 256;
-            int r, k;
-            if (a_kfast) { r = i / kKS; k = i % kKS; }
-            else { r = i % kTR; k = i / kTR; }
-            pA[u] = (k < kn && r0 + r < t.rows) ? A[(int64_t)(r0 + r) * t.ars + (int64_t)(ks + k) * t.acs] : (T)0;
+            pA[u] = (oka[u] && kaa[u] < kn) ? *qa[u] : (T)0;
+            qa[u] += stepa;
         }
 #pragma unroll
         for (int u = 0; u < PB; u++) {
-            const int i = tid + u * 256;
-            int k, c;
-            if (b_cfast) { k = i / TC; c = i % TC; }
-            else { k = i % kKS; c = i / kKS; }
-            pB[u] = (k < kn && c0 + c < ncol) ? B[(int64_t)(ks + k) * t.brs + (int64_t)(c0 + c) * t.bcs] : (T)0;
+            pB[u] = (okb[u] && kbb[u] < kn) ? *qb[u] : (T)0;
+            qb[u] += stepb;
         }
     };
     if (kb < ke) fetch(kb);
     for (int ks = kb; ks < ke; ks += kKS) {
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < PA; u++) {
-            const int i = tid + u * 256;
-            int r, k;
-            if (a_kfast) { r = i / kKS; k = i % kKS; }
-            else { r = i % kTR; k = i / kTR; }
-            sA[r][k] = pA[u];
-        }
+        for (int u = 0; u < PA; u++) (&sA[0][0])[ia[u]] = pA[u];
 #pragma unroll
-        for (int u = 0; u < PB; u++) {
-            const int i = tid + u * 256;
-            int k, c;
-            if (b_cfast) { k = i / TC; c = i % TC; }
-            else { k = i % kKS; c = i / kKS; }
-            sB[k][c] = pB[u];
-        }
+        for (int u = 0; u < PB; u++) (&sB[0][0])[ib[u]] = pB[u];
         __syncthreads();
         if (ks + kKS < ke) fetch(ks + kKS);
 #pragma unroll
