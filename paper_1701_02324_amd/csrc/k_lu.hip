@@ -420,19 +420,33 @@ __global__ __launch_bounds__(256) void k_lu_diaginv(const LuTask *__restrict__ t
 // finished with its precomputed diagonal inverse, then the remaining blocks
 // receive a rank-16 update, both on the FP64 matrix cores.
 // ---------------------------------------------------------------------------
+// The sweeps below load the operands of block step ib + 1 (its diagonal
+// inverse and its coupling blocks, which do not depend on the right-hand
+// sides) while step ib is applied, so that each step waits on LDS and the
+// matrix cores only.  A step's coupling jobs (J, column block) fit one
+// batch of kLsU jobs per wave: (nb - 1) CB <= 31 * 2 < 16 * 4.
+constexpr int kLsU = 4;
+static_assert((kLuMaxN / 16 - 1) * 2 <= (kLsThreads / kWave) * kLsU, "one batch of coupling jobs per step");
+
+// this lane's operand of the diagonal product: D'(row, k) for its k4 steps
+__device__ inline void load_diag(double (&dv)[4], const GLB double *D, bool transD, int lane, bool use) {
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+        const int row = lane % 16, kk = 4 * s + lane / 16;
+        dv[s] = use ? (transD ? D[kk + 16 * row] : D[row + 16 * kk]) : 0.0;
+    }
+}
+
 template <int NR>
-__device__ inline void diag_apply(double (*S)[NR + 1], int r0, const GLB double *D, bool transD, int lane, int wave) {
-    // S[r0:r0+16, :] = D' S[r0:r0+16, :] with D' = D or D^T (16 x 16, column-major)
+__device__ inline void diag_apply_reg(double (*S)[NR + 1], int r0, const double (&dv)[4], int lane, int wave) {
     constexpr int CB = NR / 16;
     dbl4 acc = {0, 0, 0, 0};
     const int cb = wave;
     if (cb < CB) {
 #pragma unroll
-        for (int k4 = 0; k4 < 16; k4 += 4) {
-            const int row = lane % 16, kk = k4 + lane / 16;
-            double a = transD ? D[kk + 16 * row] : D[row + 16 * kk];
-            double b = S[r0 + kk][cb * 16 + lane % 16];
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        for (int s = 0; s < 4; s++) {
+            const double b = S[r0 + 4 * s + lane / 16][cb * 16 + lane % 16];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(dv[s], b, acc, 0, 0, 0);
         }
     }
     __syncthreads();
@@ -441,41 +455,78 @@ __device__ inline void diag_apply(double (*S)[NR + 1], int r0, const GLB double 
     __syncthreads();
 }
 
-// S[J block] -= M(J, I) S[I block] for the blocks J in [jb0, jb1); element
-// (r, c) of the 16 x 16 coupling block is read through get(row, col) with
-// global row/column indices
-// Each wave takes the jobs wave, wave + 16, ... and loads the coupling blocks
-// of four jobs before their products, so that a workgroup keeps up to 64
-// block loads in flight.
+// this wave's coupling values of the jobs of one block step (blocks J in
+// [jb0, jb1) against rows i0 .. i0 + 15)
 template <int NR, typename G>
-__device__ inline void block_update(double (*S)[NR + 1], int i0, int jb0, int jb1, G get, int lane, int wave) {
-    constexpr int CB = NR / 16, NW = kLsThreads / kWave, U = 4;
+__device__ inline void load_coupling(double (&a)[kLsU][4], int i0, int jb0, int jb1, G get, int lane, int wave) {
+    constexpr int CB = NR / 16, NW = kLsThreads / kWave;
     const int njobs = (jb1 - jb0) * CB;
-    for (int base = wave; base < njobs; base += NW * U) {
-        double a[U][4];
 #pragma unroll
-        for (int u = 0; u < U; u++) {
-            const int job = base + u * NW;
-            const int J = jb0 + job / CB;
+    for (int u = 0; u < kLsU; u++) {
+        const int job = wave + u * NW;
+        const int J = jb0 + job / CB;
 #pragma unroll
-            for (int k4 = 0; k4 < 4; k4++)
-                a[u][k4] = job < njobs ? get(J * 16 + lane % 16, i0 + 4 * k4 + lane / 16) : 0.0;
+        for (int k4 = 0; k4 < 4; k4++) a[u][k4] = job < njobs ? get(J * 16 + lane % 16, i0 + 4 * k4 + lane / 16) : 0.0;
+    }
+}
+
+template <int NR>
+__device__ inline void block_update_reg(double (*S)[NR + 1], int i0, int jb0, int jb1, const double (&a)[kLsU][4],
+                                        int lane, int wave) {
+    constexpr int CB = NR / 16, NW = kLsThreads / kWave;
+    const int njobs = (jb1 - jb0) * CB;
+#pragma unroll
+    for (int u = 0; u < kLsU; u++) {
+        const int job = wave + u * NW;
+        if (job >= njobs) break;
+        const int J = jb0 + job / CB, cb = job % CB;
+        dbl4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int k4 = 0; k4 < 4; k4++) {
+            double b = S[i0 + 4 * k4 + lane / 16][cb * 16 + lane % 16];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][k4], b, acc, 0, 0, 0);
         }
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            const int job = base + u * NW;
-            if (job >= njobs) break;
-            const int J = jb0 + job / CB, cb = job % CB;
-            dbl4 acc = {0, 0, 0, 0};
-#pragma unroll
-            for (int k4 = 0; k4 < 4; k4++) {
-                double b = S[i0 + 4 * k4 + lane / 16][cb * 16 + lane % 16];
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][k4], b, acc, 0, 0, 0);
-            }
-            for (int q = 0; q < 4; q++) S[J * 16 + 4 * q + lane / 16][cb * 16 + lane % 16] -= acc[q];
-        }
+        for (int q = 0; q < 4; q++) S[J * 16 + 4 * q + lane / 16][cb * 16 + lane % 16] -= acc[q];
     }
     __syncthreads();
+}
+
+// one triangular sweep: forward (ib = 0 .. nb - 1, coupling blocks below)
+// or backward (ib = nb - 1 .. 0, coupling blocks above); D(ib) is the
+// diagonal inverse of step ib
+template <int NR, typename G, typename DP>
+__device__ inline void sweep(double (*S)[NR + 1], int nb, bool forward, DP dptr, bool transD, G get, int lane,
+                             int wave) {
+    constexpr int CB = NR / 16;
+    double dv[4], a[kLsU][4];
+    const int ib0 = forward ? 0 : nb - 1;
+    auto range = [&](int ib, int &j0, int &j1) {
+        j0 = forward ? ib + 1 : 0;
+        j1 = forward ? nb : ib;
+    };
+    int j0, j1;
+    range(ib0, j0, j1);
+    load_diag(dv, dptr(ib0), transD, lane, wave < CB);
+    load_coupling<NR>(a, ib0 * 16, j0, j1, get, lane, wave);
+    for (int t = 0; t < nb; t++) {
+        const int ib = forward ? t : nb - 1 - t;
+        double dc[4], ac[kLsU][4];
+#pragma unroll
+        for (int s2 = 0; s2 < 4; s2++) dc[s2] = dv[s2];
+#pragma unroll
+        for (int u = 0; u < kLsU; u++)
+#pragma unroll
+            for (int k4 = 0; k4 < 4; k4++) ac[u][k4] = a[u][k4];
+        if (t + 1 < nb) {  // the next step's operands, loaded while this one is applied
+            const int in = forward ? ib + 1 : ib - 1;
+            range(in, j0, j1);
+            load_diag(dv, dptr(in), transD, lane, wave < CB);
+            load_coupling<NR>(a, in * 16, j0, j1, get, lane, wave);
+        }
+        range(ib, j0, j1);
+        diag_apply_reg<NR>(S, ib * 16, dc, lane, wave);
+        block_update_reg<NR>(S, ib * 16, j0, j1, ac, lane, wave);
+    }
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
@@ -518,25 +569,15 @@ __global__ __launch_bounds__(kLsThreads) void k_lusolve(const LuTask *__restrict
                 }
             }
         __syncthreads();
-        for (int ib = 0; ib < nb; ib++) {  // L y = P b
-            diag_apply<NR>(S, ib * 16, dinv + (int64_t)(2 * ib) * 256, false, lane, wave);
-            block_update<NR>(S, ib * 16, ib + 1, nb, Lget, lane, wave);
-        }
-        for (int ib = nb - 1; ib >= 0; ib--) {  // U x = y
-            diag_apply<NR>(S, ib * 16, dinv + (int64_t)(2 * ib + 1) * 256, false, lane, wave);
-            block_update<NR>(S, ib * 16, 0, ib, Uget, lane, wave);
-        }
+        // L y = P b, then U x = y
+        sweep<NR>(S, nb, true, [&](int ib) { return dinv + (int64_t)(2 * ib) * 256; }, false, Lget, lane, wave);
+        sweep<NR>(S, nb, false, [&](int ib) { return dinv + (int64_t)(2 * ib + 1) * 256; }, false, Uget, lane, wave);
     } else {
         auto UTget = [&](int r, int c) -> double { return Uget(c, r); };
         auto LTget = [&](int r, int c) -> double { return Lget(c, r); };
-        for (int ib = 0; ib < nb; ib++) {  // U^T z = b
-            diag_apply<NR>(S, ib * 16, dinv + (int64_t)(2 * ib + 1) * 256, true, lane, wave);
-            block_update<NR>(S, ib * 16, ib + 1, nb, UTget, lane, wave);
-        }
-        for (int ib = nb - 1; ib >= 0; ib--) {  // L^T w = z
-            diag_apply<NR>(S, ib * 16, dinv + (int64_t)(2 * ib) * 256, true, lane, wave);
-            block_update<NR>(S, ib * 16, 0, ib, LTget, lane, wave);
-        }
+        // U^T z = b, then L^T w = z
+        sweep<NR>(S, nb, true, [&](int ib) { return dinv + (int64_t)(2 * ib + 1) * 256; }, true, UTget, lane, wave);
+        sweep<NR>(S, nb, false, [&](int ib) { return dinv + (int64_t)(2 * ib) * 256; }, true, LTget, lane, wave);
         if (tid < NR)
             for (int k = n - 1; k >= 0; k--) {
                 const int p = P[k];
