@@ -1362,7 +1362,7 @@ struct SkelRun {
             }));
             // the QR tasks hold the one-workgroup nodes first, then the split ones
             const int rt = (int)cdiv(nsamp_max, 64), ct = (int)cdiv(cmax, 64), none_ = nqr - nsp;
-            const size_t lds = sizeof(double) * (64 * (d | 1) + 64 * d);
+            const size_t lds = sizeof(double) * (64 * (d | 1) + 64 * std::max(d, kXrDim));
             if (none_ > 0)
                 HIP_TRY(timed("skel:k_sample_rownorm" + prof_height(hgt), st, [&] {
                     hipLaunchKernelGGL(k_sample_rownorm, dim3(none_ * rt * ct), dim3(256), lds, st,
@@ -1619,7 +1619,7 @@ static askit_status factor_plan_part(const std::vector<askit_factor> &fs, Plan &
             const int nl = (int)lt.size(), tl = (int)cdiv(mmax, 64);
             P.add("k_leaf_block", [=](hipStream_t st, int) -> hipError_t {
                 hipLaunchKernelGGL(k_leaf_block, dim3(nl * tl * tl), dim3(256),
-                                   sizeof(double) * (64 * (d | 1) + 64 * d), st, lp, tl, d);
+                                   sizeof(double) * (64 * (d | 1) + 64 * std::max(d, kXrDim)), st, lp, tl, d);
                 return hipGetLastError();
             });
             // lambda I + K_aa is symmetric positive definite for lambda > 0

@@ -99,9 +99,12 @@ template __global__ void k_scatter_multi<float>(const GatherTask *, double *cons
 // sets staged in LDS; grid = task * tiles^2 + tile
 __global__ __launch_bounds__(256) void k_leaf_block(const LeafTask *__restrict__ tasks, int tiles, int d) {
     // row points at an odd stride (lanes read different points: no bank
-    // conflicts), column points at stride d (one point per wave: broadcast)
-    extern __shared__ double dyn_lds[];  // 64 (d | 1) + 64 d doubles
-    const int dp = d | 1;
+    // conflicts), column points (one point per wave: broadcast) at stride d,
+    // or zero padded to kXrDim coordinates for d <= kXrDim, when each
+    // thread reads its row point into registers once (the padded terms add
+    // exact zeros: the same entries bit for bit)
+    extern __shared__ double dyn_lds[];  // 64 (d | 1) + 64 max(d, kXrDim) doubles
+    const int dp = d | 1, xw = d <= kXrDim ? kXrDim : d;
     double *ys = dyn_lds, *xs = dyn_lds + 64 * dp;
     const int per = tiles * tiles;
     const LeafTask t = tasks[blockIdx.x / per];
@@ -112,18 +115,32 @@ __global__ __launch_bounds__(256) void k_leaf_block(const LeafTask *__restrict__
     for (int i = threadIdx.x; i < 64 * d; i += blockDim.x) {
         const int a = i / d, k = i % d;
         ys[a * dp + k] = a < nr ? glb(t.X)[(t.b + r0 + a) * d + k] : 0.0;
-        xs[i] = a < nc ? glb(t.X)[(t.b + c0 + a) * d + k] : 0.0;
+    }
+    for (int i = threadIdx.x; i < 64 * xw; i += blockDim.x) {
+        const int a = i / xw, k = i % xw;
+        xs[i] = (a < nc && k < d) ? glb(t.X)[(t.b + c0 + a) * d + k] : 0.0;
     }
     __syncthreads();
     const int r = threadIdx.x % 64;
     if (r >= nr) return;
     const double *y = ys + r * dp;
+    double yr[kXrDim];
+#pragma unroll
+    for (int k = 0; k < kXrDim; k++) yr[k] = (d <= kXrDim && k < d) ? y[k] : 0.0;
     for (int c = threadIdx.x / 64; c < nc; c += 4) {
-        const double *x = xs + c * d;
+        const double *x = xs + c * xw;
         double r2 = 0.0;
-        for (int k = 0; k < d; k++) {
-            const double df = y[k] - x[k];
-            r2 = fma(df, df, r2);
+        if (d <= kXrDim) {
+#pragma unroll
+            for (int k = 0; k < kXrDim; k++) {
+                const double df = yr[k] - x[k];
+                r2 = fma(df, df, r2);
+            }
+        } else {
+            for (int k = 0; k < d; k++) {
+                const double df = y[k] - x[k];
+                r2 = fma(df, df, r2);
+            }
         }
         double v = exp(r2 * t.scale);
         if (r0 + r == c0 + c) v += t.lambda;

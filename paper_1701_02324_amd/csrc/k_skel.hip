@@ -125,15 +125,33 @@ __device__ inline double sqdist(const double *x, const double *y, int d) {
     return r2;
 }
 
+// the same sum over kXrDim coordinates, the row point y in registers and the
+// column point x in LDS, both zero padded beyond d (the padded terms add
+// exact zeros, so the value is sqdist's bit for bit)
+__device__ inline double sqdist_xr(const double *x, const double (&y)[kXrDim]) {
+    double r2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < kXrDim; k++) {
+        const double df = x[k] - y[k];
+        r2 = fma(df, df, r2);
+    }
+    return r2;
+}
+
+// tile staging of the sampled-block kernels: row points at an odd stride
+// (lanes read different points: no bank conflicts), column points at
+// stride xs_stride(d) (one point per wave: broadcast), zero padded to
+// kXrDim coordinates for d <= kXrDim, when the row point is then read into
+// registers once per thread
+__device__ inline int xs_stride(int d) { return d <= kXrDim ? kXrDim : d; }
+
 // block: 256 threads on a 64 x 64 tile (sampled rows x candidate columns);
 // both point sets are staged in LDS, each thread writes 16 entries of one
 // column (consecutive rows across lanes: coalesced column-major stores)
 __global__ __launch_bounds__(256) void k_sample_block(const SkelTask *__restrict__ tasks, int rowtiles, int ldm, int d,
                                                       int coltiles) {
-    // row points at an odd stride (lanes read different points: no bank
-    // conflicts), column points at stride d (one point per wave: broadcast)
-    extern __shared__ double dyn_lds[];  // 64 (d | 1) + 64 d doubles
-    const int dp = d | 1;
+    extern __shared__ double dyn_lds[];  // 64 (d | 1) + 64 xs_stride(d) doubles
+    const int dp = d | 1, xw = xs_stride(d);
     double *ys = dyn_lds, *xs = dyn_lds + 64 * dp;
     const int per = rowtiles * coltiles;
     const int task = blockIdx.x / per, rt = (blockIdx.x % per) % rowtiles, ct = (blockIdx.x % per) / rowtiles;
@@ -148,14 +166,25 @@ __global__ __launch_bounds__(256) void k_sample_block(const SkelTask *__restrict
     for (int i = threadIdx.x; i < 64 * d; i += blockDim.x) {
         const int a = i / d, k = i % d;
         ys[a * dp + k] = a < nr ? X[(int64_t)q[r0 + a] * d + k] : 0.0;
-        xs[i] = a < nc ? X[(int64_t)cand_pos(t, c0 + a, sl) * d + k] : 0.0;
+    }
+    for (int i = threadIdx.x; i < 64 * xw; i += blockDim.x) {
+        const int a = i / xw, k = i % xw;
+        xs[i] = (a < nc && k < d) ? X[(int64_t)cand_pos(t, c0 + a, sl) * d + k] : 0.0;
     }
     __syncthreads();
     const int r = threadIdx.x % 64;
     if (r >= nr) return;
     const double *y = ys + r * dp;
-    for (int c = threadIdx.x / 64; c < nc; c += 4)
-        glb(t.M)[(int64_t)(c0 + c) * ldm + r0 + r] = exp(sqdist(xs + c * d, y, d) * t.scale);
+    if (d <= kXrDim) {
+        double yr[kXrDim];
+#pragma unroll
+        for (int k = 0; k < kXrDim; k++) yr[k] = k < d ? y[k] : 0.0;
+        for (int c = threadIdx.x / 64; c < nc; c += 4)
+            glb(t.M)[(int64_t)(c0 + c) * ldm + r0 + r] = exp(sqdist_xr(xs + c * kXrDim, yr) * t.scale);
+    } else {
+        for (int c = threadIdx.x / 64; c < nc; c += 4)
+            glb(t.M)[(int64_t)(c0 + c) * ldm + r0 + r] = exp(sqdist(xs + c * d, y, d) * t.scale);
+    }
 }
 
 // The one-workgroup QR's input: instead of the block, the squared norm of
@@ -166,8 +195,8 @@ __global__ __launch_bounds__(256) void k_sample_block(const SkelTask *__restrict
 // is never stored: k_qrcp generates the rows that carry weight (gen_rows).
 __global__ __launch_bounds__(256) void k_sample_rownorm(const SkelTask *__restrict__ tasks, int rowtiles, int ldm,
                                                         int d, int coltiles) {
-    extern __shared__ double dyn_lds[];  // 64 (d | 1) + 64 d doubles
-    const int dp = d | 1;
+    extern __shared__ double dyn_lds[];  // 64 (d | 1) + 64 xs_stride(d) doubles
+    const int dp = d | 1, xw = xs_stride(d);
     double *ys = dyn_lds, *xs = dyn_lds + 64 * dp;
     const int per = rowtiles * coltiles;
     const int task = blockIdx.x / per, rt = (blockIdx.x % per) % rowtiles, ct = (blockIdx.x % per) / rowtiles;
@@ -182,16 +211,28 @@ __global__ __launch_bounds__(256) void k_sample_rownorm(const SkelTask *__restri
     for (int i = threadIdx.x; i < 64 * d; i += blockDim.x) {
         const int a = i / d, k = i % d;
         ys[a * dp + k] = a < nr ? X[(int64_t)q[r0 + a] * d + k] : 0.0;
-        xs[i] = a < nc ? X[(int64_t)cand_pos(t, c0 + a, sl) * d + k] : 0.0;
+    }
+    for (int i = threadIdx.x; i < 64 * xw; i += blockDim.x) {
+        const int a = i / xw, k = i % xw;
+        xs[i] = (a < nc && k < d) ? X[(int64_t)cand_pos(t, c0 + a, sl) * d + k] : 0.0;
     }
     __syncthreads();
     const int r = threadIdx.x % 64;
     if (r >= nr) return;
     const double *y = ys + r * dp;
+    double yr[kXrDim];
+#pragma unroll
+    for (int k = 0; k < kXrDim; k++) yr[k] = (d <= kXrDim && k < d) ? y[k] : 0.0;
     for (int cg = (threadIdx.x / 64) * kQsCols; cg < nc; cg += 4 * kQsCols) {
         double v[kQsCols];
+        if (d <= kXrDim) {
 #pragma unroll
-        for (int u = 0; u < kQsCols; u++) v[u] = cg + u < nc ? exp(sqdist(xs + (cg + u) * d, y, d) * t.scale) : 0.0;
+            for (int u = 0; u < kQsCols; u++)
+                v[u] = cg + u < nc ? exp(sqdist_xr(xs + (cg + u) * kXrDim, yr) * t.scale) : 0.0;
+        } else {
+#pragma unroll
+            for (int u = 0; u < kQsCols; u++) v[u] = cg + u < nc ? exp(sqdist(xs + (cg + u) * d, y, d) * t.scale) : 0.0;
+        }
         double p = 0.0;
 #pragma unroll
         for (int u = 0; u < kQsCols; u++)
