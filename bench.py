@@ -163,21 +163,21 @@ ROOF_KIND = {
 TRAFFIC = {
     "skel:k_qs_step": {
         "source": ["k_skel.hip", "askit_dev.h"],
-        "src_sha256": "0586e38bcae159acdd81463db7703b739763c032328ec820258bd67a5e0dbe14",
+        "src_sha256": "20cac8b03cedb8de9c67456a412bf3f86515bef69ff13bdc1c4a23ecee931649",
         "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": (2356.9 * 2.0 + 3746.4) * 1024.0,
+        "bytes_per_launch": (2346.7 * 2.0 + 3746.4) * 1024.0,
     },
     "skel:k_qrcp": {
         "source": ["k_skel.hip", "askit_dev.h"],
-        "src_sha256": "0586e38bcae159acdd81463db7703b739763c032328ec820258bd67a5e0dbe14",
+        "src_sha256": "20cac8b03cedb8de9c67456a412bf3f86515bef69ff13bdc1c4a23ecee931649",
         "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": (1042445.0 * 2.0 + 1641988.0) * 1024.0,
+        "bytes_per_launch": (1042779.6 * 2.0 + 1642575.5) * 1024.0,
     },
     "factor:k_lu_nopiv": {
         "source": ["k_lu.hip", "askit_dev.h"],
-        "src_sha256": "9ac23dd4d35a11b11d1948683ec6c05201822bcfe71c133de2738afe3bfa6365",
+        "src_sha256": "8e9c474b9dba921eec9b61e842a6430760b51f2d4bf8968df8c1c71027cd3b3b",
         "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": (7704740.9 * 2.0 + 16280838.5) * 1024.0,
+        "bytes_per_launch": (7706741.1 * 2.0 + 16270893.7) * 1024.0,
     },
 }
 
