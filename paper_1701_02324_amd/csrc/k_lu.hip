@@ -48,14 +48,29 @@ __device__ inline void trailing_update(GLB double *A, int lda, int kb, int r0, i
         double l[KP / 4];
 #pragma unroll
         for (int kk = 0; kk < KP / 4; kk++) l[kk] = ci < nr ? A[rb + (int64_t)(kb + 4 * kk + kq) * lda] : 0.0;
+        // element (q, r) of column block cbk is column c0 + 64 cbk + 16 q +
+        // 4 r + kq of this lane's row: one base pointer per stripe and
+        // strides instead of a 64-bit product per element, and no bounds
+        // tests in the blocks that lie inside the matrix
+        const bool live = ci < nr;
+        GLB double *rp = A + rb + (int64_t)(c0 + kq) * lda;
+        const int64_t l4 = 4 * (int64_t)lda, l16 = 16 * (int64_t)lda, l64 = 64 * (int64_t)lda;
         auto fetch = [&](int cbk, double (&c)[4][4]) {
+            GLB double *bp = rp + (int64_t)cbk * l64;
+            if (live && 64 * (cbk + 1) <= nc) {
 #pragma unroll
-            for (int q = 0; q < 4; q++)
+                for (int q = 0; q < 4; q++)
 #pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    const int cj = (4 * cbk + q) * 16 + 4 * r + kq;
-                    c[q][r] = (ci < nr && cj < nc) ? A[rb + (int64_t)(c0 + cj) * lda] : 0.0;
-                }
+                    for (int r = 0; r < 4; r++) c[q][r] = bp[q * l16 + r * l4];
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        const int cj = (4 * cbk + q) * 16 + 4 * r + kq;
+                        c[q][r] = (live && cj < nc) ? bp[q * l16 + r * l4] : 0.0;
+                    }
+            }
         };
         auto update = [&](int cbk, const double (&c)[4][4]) {
             const int cb0 = 4 * cbk;
@@ -77,13 +92,19 @@ __device__ inline void trailing_update(GLB double *A, int lda, int kb, int r0, i
                         acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[kk][q], l[4 * h + kk], acc[q], 0, 0, 0);
             }
             // acc[q][r] = entry (row st*16 + lane%16, column (cb0+q)*16 + 4r + lane/16)
-            if (ci < nr) {
+            GLB double *bp = rp + (int64_t)cbk * l64;
+            if (live && 64 * (cbk + 1) <= nc) {
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+#pragma unroll
+                    for (int r = 0; r < 4; r++) bp[q * l16 + r * l4] = c[q][r] - acc[q][r];
+            } else if (live) {
 #pragma unroll
                 for (int q = 0; q < 4; q++)
 #pragma unroll
                     for (int r = 0; r < 4; r++) {
                         const int cj = (cb0 + q) * 16 + 4 * r + kq;
-                        if (cj < nc) A[rb + (int64_t)(c0 + cj) * lda] = c[q][r] - acc[q][r];
+                        if (cj < nc) bp[q * l16 + r * l4] = c[q][r] - acc[q][r];
                     }
             }
         };
