@@ -458,21 +458,22 @@ __device__ inline void load_diag(double (&dv)[4], const GLB double *D, bool tran
     }
 }
 
+// S[r0:r0+16, :] = D' S[r0:r0+16, :]: wave cb < CB reads and rewrites the
+// 16 x 16 block of its own columns only, so no barrier separates its reads
+// from its writes; the barrier after them publishes the block to the update
 template <int NR>
 __device__ inline void diag_apply_reg(double (*S)[NR + 1], int r0, const double (&dv)[4], int lane, int wave) {
     constexpr int CB = NR / 16;
-    dbl4 acc = {0, 0, 0, 0};
     const int cb = wave;
     if (cb < CB) {
+        dbl4 acc = {0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < 4; s++) {
             const double b = S[r0 + 4 * s + lane / 16][cb * 16 + lane % 16];
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(dv[s], b, acc, 0, 0, 0);
         }
-    }
-    __syncthreads();
-    if (cb < CB)
         for (int q = 0; q < 4; q++) S[r0 + 4 * q + lane / 16][cb * 16 + lane % 16] = acc[q];
+    }
     __syncthreads();
 }
 
