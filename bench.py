@@ -171,13 +171,13 @@ TRAFFIC = {
         "source": ["k_skel.hip", "askit_dev.h"],
         "src_sha256": "20cac8b03cedb8de9c67456a412bf3f86515bef69ff13bdc1c4a23ecee931649",
         "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": (1042779.6 * 2.0 + 1642575.5) * 1024.0,
+        "bytes_per_launch": (1042606.6 * 2.0 + 1641072.5) * 1024.0,
     },
     "factor:k_lu_nopiv": {
         "source": ["k_lu.hip", "askit_dev.h"],
-        "src_sha256": "8e9c474b9dba921eec9b61e842a6430760b51f2d4bf8968df8c1c71027cd3b3b",
+        "src_sha256": "6d870d4f2a01d292c41259dc06e826a155cc42682aa0448bde42e733f05999bd",
         "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": (7706741.1 * 2.0 + 16270893.7) * 1024.0,
+        "bytes_per_launch": (7571613.1 * 2.0 + 16151911.8) * 1024.0,
     },
 }
 
