@@ -405,31 +405,46 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu_nopiv(const LuTask *__restri
 // One workgroup per matrix, one lane per block column.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_lu_diaginv(const LuTask *__restrict__ tasks) {
+    // the 16 x 16 diagonal blocks of a pass (eight: 32 jobs each) are staged
+    // in LDS once, completed by the identity beyond n, then read by the jobs
+    __shared__ double sT[8][256];
     const LuTask t = tasks[blockIdx.x];
     const int n = t.n, lda = t.lda, nb = (n + 15) / 16;
-    for (int job = threadIdx.x; job < nb * 32; job += blockDim.x) {
-        const int b = job / 32, j = job % 16, upper = (job % 32) / 16, b0 = b * 16;
-        double x[16];
-        GLB double *out = glb(t.dinv) + ((int64_t)(2 * b + upper)) * 256;
-        auto a = [&](int r, int c) -> double {
-            int gr = b0 + r, gc = b0 + c;
-            if (gr >= n || gc >= n) return r == c ? 1.0 : 0.0;
-            return glb((const double *)t.A)[gr + (int64_t)gc * lda];
-        };
-        if (!upper) {  // x = L^{-1} e_j, unit diagonal
-            for (int i = 0; i < 16; i++) {
-                double acc = (i == j) ? 1.0 : 0.0;
-                for (int k = 0; k < i; k++) acc = fma(-a(i, k), x[k], acc);
-                x[i] = acc;
-            }
-        } else {  // x = U^{-1} e_j
-            for (int i = 15; i >= 0; i--) {
-                double acc = (i == j) ? 1.0 : 0.0;
-                for (int k = i + 1; k < 16; k++) acc = fma(-a(i, k), x[k], acc);
-                x[i] = acc / a(i, i);
+    const int tid = threadIdx.x, tile = tid / 32;
+    for (int base = 0; base < nb * 32; base += 256) {
+        const int bs = base / 32 + tile;  // the block this thread stages and solves
+        if (bs < nb) {
+            const int b0 = bs * 16;
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int e = tid % 32 + 32 * u, r = e % 16, c = e / 16, gr = b0 + r, gc = b0 + c;
+                sT[tile][e] = (gr >= n || gc >= n) ? (r == c ? 1.0 : 0.0) : glb((const double *)t.A)[gr + (int64_t)gc * lda];
             }
         }
-        for (int i = 0; i < 16; i++) out[i + 16 * j] = x[i];
+        __syncthreads();
+        const int job = base + tid;
+        if (job < nb * 32) {
+            const int b = job / 32, j = job % 16, upper = (job % 32) / 16;
+            const double *T = sT[tile];
+            auto a = [&](int r, int c) -> double { return T[r + 16 * c]; };
+            double x[16];
+            GLB double *out = glb(t.dinv) + ((int64_t)(2 * b + upper)) * 256;
+            if (!upper) {  // x = L^{-1} e_j, unit diagonal
+                for (int i = 0; i < 16; i++) {
+                    double acc = (i == j) ? 1.0 : 0.0;
+                    for (int k = 0; k < i; k++) acc = fma(-a(i, k), x[k], acc);
+                    x[i] = acc;
+                }
+            } else {  // x = U^{-1} e_j
+                for (int i = 15; i >= 0; i--) {
+                    double acc = (i == j) ? 1.0 : 0.0;
+                    for (int k = i + 1; k < 16; k++) acc = fma(-a(i, k), x[k], acc);
+                    x[i] = acc / a(i, i);
+                }
+            }
+            for (int i = 0; i < 16; i++) out[i + 16 * j] = x[i];
+        }
+        __syncthreads();
     }
 }
 
