@@ -642,7 +642,8 @@ askit_status copy_commit(Plan &P, const std::vector<CopyTask> &v, Prec from, Pre
     ST_TRY(upload(*b, v));
     const CopyTask *tp = b->as<CopyTask>();
     const int n = (int)v.size();
-    const int rb = (int)cdiv((int64_t)rows_max * cols_max, 256);
+    const int rb = (int)cdiv((int64_t)rows_max, 4);  // four rows per 256-thread block
+    (void)cols_max;
     P.add("k_copy", [=](hipStream_t st, int) -> hipError_t {
         if (from == P64 && to == P64) hipLaunchKernelGGL((k_copy<double, double>), dim3(n * rb), dim3(256), 0, st, tp, rb);
         else if (from == P64) hipLaunchKernelGGL((k_copy<double, float>), dim3(n * rb), dim3(256), 0, st, tp, rb);
@@ -658,7 +659,7 @@ askit_status ident_commit(Plan &P, const std::vector<IdTask> &v, int n) {
     ST_TRY(upload(*b, v));
     const IdTask *tp = b->as<IdTask>();
     const int cnt = (int)v.size();
-    const int bpm = (int)cdiv((int64_t)n * n, 256);
+    const int bpm = (int)cdiv((int64_t)n, 4);  // four columns per 256-thread block
     P.add("k_identity", [=](hipStream_t st, int) -> hipError_t {
         hipLaunchKernelGGL(k_identity, dim3(cnt * bpm), dim3(256), 0, st, tp, bpm);
         return hipGetLastError();

@@ -148,22 +148,27 @@ __global__ __launch_bounds__(256) void k_leaf_block(const LeafTask *__restrict__
     }
 }
 
-// n x n identity blocks (column-major, ld = n); grid = task * blocks_per_matrix
+// n x n identity blocks (column-major, ld = n); grid = task * blocks_per_matrix,
+// one wave per column (block b: columns 4 b .. 4 b + 3), lanes over the rows
 __global__ void k_identity(const IdTask *__restrict__ tasks, int bpm) {
     const IdTask t = tasks[blockIdx.x / bpm];
-    const int64_t e = (int64_t)(blockIdx.x % bpm) * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)t.n * t.n) return;
-    glb(t.Z)[e] = (e % t.n == e / t.n) ? 1.0 : 0.0;
+    const int c = (blockIdx.x % bpm) * 4 + (int)threadIdx.x / kWave;
+    if (c >= t.n) return;
+    GLB double *col = glb(t.Z) + (int64_t)c * t.n;
+    for (int r = (int)threadIdx.x % kWave; r < t.n; r += kWave) col[r] = r == c ? 1.0 : 0.0;
 }
 
-// dst(r, c) = src(r, c) with precision conversion; grid = task * rowblocks + rb
+// dst(r, c) = src(r, c) with precision conversion; grid = task * rowblocks
 template <typename TS, typename TD>
 __global__ void k_copy(const CopyTask *__restrict__ tasks, int rowblocks) {
+    // one wave per row (block b of a task: rows 4 b .. 4 b + 3), lanes over
+    // the columns: no index division per element
     const CopyTask t = tasks[blockIdx.x / rowblocks];
-    const int64_t e = (int64_t)(blockIdx.x % rowblocks) * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)t.rows * t.cols) return;
-    const int64_t r = e / t.cols, c = e % t.cols;
-    glb((TD *)t.dst)[r * t.dld + c] = (TD)glb((const TS *)t.src)[r * t.sld + c];
+    const int r = (blockIdx.x % rowblocks) * 4 + (int)threadIdx.x / kWave;
+    if (r >= t.rows) return;
+    const GLB TS *src = glb((const TS *)t.src) + (int64_t)r * t.sld;
+    GLB TD *dst = glb((TD *)t.dst) + (int64_t)r * t.dld;
+    for (int c = (int)threadIdx.x % kWave; c < t.cols; c += kWave) dst[c] = (TD)src[c];
 }
 
 // Y(r, c) += a * X(r, c) over n rows x nrhs columns (row-major, stride ld)
