@@ -171,13 +171,13 @@ TRAFFIC = {
         "source": ["k_skel.hip", "askit_dev.h"],
         "src_sha256": "20cac8b03cedb8de9c67456a412bf3f86515bef69ff13bdc1c4a23ecee931649",
         "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": (1042606.6 * 2.0 + 1641072.5) * 1024.0,
+        "bytes_per_launch": (1042033.3 * 2.0 + 1643407.9) * 1024.0,
     },
     "factor:k_lu_nopiv": {
         "source": ["k_lu.hip", "askit_dev.h"],
-        "src_sha256": "6d870d4f2a01d292c41259dc06e826a155cc42682aa0448bde42e733f05999bd",
+        "src_sha256": "46de40707c0e508e7f58010e8fc9b2fdaee6a44ac3c34a2ecb09af2bdbc76ab1",
         "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": (7571613.1 * 2.0 + 16151911.8) * 1024.0,
+        "bytes_per_launch": (7568209.0 * 2.0 + 16151765.3) * 1024.0,
     },
 }
 
