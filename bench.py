@@ -216,8 +216,8 @@ def rooflines_of(prof, cnt, steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--N", type=int, default=1 << 20)
     ap.add_argument("--nrhs", type=int, default=64)
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision steps")
