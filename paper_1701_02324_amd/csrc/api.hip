@@ -1406,12 +1406,16 @@ struct SkelRun {
             hipLaunchKernelGGL(k_qs_init, dim3(g), dim3(kQsThreads), 0, st, tp, wk, s, nsamp_max);
             return hipGetLastError();
         }));
-        // the pivot steps: one launch each, timed as one chain
+        // the pivot steps: one launch each, timed as one chain; step j
+        // launches the slices from (j - 1) / kQsCols on (k_qs_step)
         HIP_TRY(timed(
             "skel:k_qs_step" + hs, st,
             [&] {
-                for (int j = 0; j < split_steps; j++)
-                    hipLaunchKernelGGL(k_qs_step, dim3(g), dim3(kQsThreads), 0, st, tp, wk, j, nsamp_max);
+                for (int j = 0; j < split_steps; j++) {
+                    const int s0 = j > 0 ? (j - 1) / kQsCols : 0;
+                    hipLaunchKernelGGL(k_qs_step, dim3((unsigned)(nsp * (wk.slices - s0))), dim3(kQsThreads), 0, st,
+                                       tp, wk, j, s0);
+                }
                 return hipGetLastError();
             },
             split_steps));

@@ -38,7 +38,7 @@ __global__ void k_qrcp(const SkelTask *tasks, int s, int ldm, int d);
 __global__ void k_qs_rows(const SkelTask *tasks, QrWork w, int ldm);
 __global__ void k_qs_rowmap(const SkelTask *tasks, QrWork w);
 __global__ void k_qs_init(const SkelTask *tasks, QrWork w, int s, int ldm);
-__global__ void k_qs_step(const SkelTask *tasks, QrWork w, int j, int ldm);
+__global__ void k_qs_step(const SkelTask *tasks, QrWork w, int j, int s0);
 __global__ void k_qs_finish(const SkelTask *tasks, QrWork w, int s, int ldm);
 
 // kappa-NN sampling (k_knn.hip)

@@ -1145,17 +1145,23 @@ __device__ inline void qs_update(const SkelTask *tasks, const QrWork &w, int nod
 }
 
 // one launch per pivot step: workgroup = (node, column group)
+// The launch covers the slices s0 .. w.slices - 1 of every node, s0 =
+// (j - 1) / kQsCols: a position placed at step p is copied into the other
+// buffer of the pivot order at step p + 1 and changes in neither after, so
+// the slices below s0, whose positions are all <= j - 2, have nothing left
+// to do.  The first launched slice records R_jj and the stop (a split node
+// has more than s candidates, so its positions reach past j).
 __global__ __launch_bounds__(kQsThreads) void k_qs_step(const SkelTask *__restrict__ tasks, QrWork w, int j,
-                                                         int ldm) {
+                                                         int s0) {
     __shared__ double vh[kQrMaxRows];
     __shared__ QsPivot sp;
-    (void)ldm;
-    const int node = blockIdx.x / w.slices, slice = blockIdx.x % w.slices;
+    const int nsl = w.slices - s0;
+    const int node = blockIdx.x / nsl, slice = s0 + blockIdx.x % nsl;
     const GLB int32_t *st = glb(w.st) + kQsState * node;
     const int stopped = st[0], steps = st[3], ncand = st[5];
     if (stopped || j >= steps) return;
     if (slice * kQsCols >= ncand) return;
-    qs_pivot(tasks, w, node, j, slice == 0, vh, &sp);
+    qs_pivot(tasks, w, node, j, slice == s0, vh, &sp);
     __syncthreads();
     const QsPivot pv = sp;
     if (pv.stop) return;
