@@ -163,21 +163,21 @@ ROOF_KIND = {
 TRAFFIC = {
     "skel:k_qs_step": {
         "source": ["k_skel.hip", "askit_dev.h"],
-        "src_sha256": "20cac8b03cedb8de9c67456a412bf3f86515bef69ff13bdc1c4a23ecee931649",
+        "src_sha256": "e516578fc87893b8790dbe66748ea9cf4b92ff723156b2388625139d35bea6b1",
         "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": (2346.7 * 2.0 + 3746.4) * 1024.0,
+        "bytes_per_launch": (2341.1 * 2.0 + 3744.1) * 1024.0,
     },
     "skel:k_qrcp": {
         "source": ["k_skel.hip", "askit_dev.h"],
-        "src_sha256": "20cac8b03cedb8de9c67456a412bf3f86515bef69ff13bdc1c4a23ecee931649",
+        "src_sha256": "e516578fc87893b8790dbe66748ea9cf4b92ff723156b2388625139d35bea6b1",
         "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": (1042033.3 * 2.0 + 1643407.9) * 1024.0,
+        "bytes_per_launch": (1042189.4 * 2.0 + 1642106.8) * 1024.0,
     },
     "factor:k_lu_nopiv": {
         "source": ["k_lu.hip", "askit_dev.h"],
         "src_sha256": "46de40707c0e508e7f58010e8fc9b2fdaee6a44ac3c34a2ecb09af2bdbc76ab1",
         "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": (7568209.0 * 2.0 + 16151765.3) * 1024.0,
+        "bytes_per_launch": (7567027.6 * 2.0 + 16155348.1) * 1024.0,
     },
 }
 
