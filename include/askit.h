@@ -207,6 +207,19 @@ askit_status askit_tune_factorization(askit_tree t, double lambda, void *stream)
  * or table, a wrong height count or a size not listed. */
 askit_status askit_tree_set_tiling(askit_tree t, const int32_t *table, int32_t heights);
 
+/* Launch shape of the factorization's LU with partial pivoting (Sec. 2.2:
+ * the reduced systems Z of eq. (8), and the leaf blocks when lambda = 0).
+ * A batch of LUs whose largest matrix has more than n rows runs one panel
+ * of 32 columns at a time over the whole batch: one workgroup per matrix
+ * factors the panel and its block row of U, then the trailing update is
+ * spread over one workgroup per 64 x 64 tile, so that a few large matrices
+ * occupy more than a few compute units.  Smaller batches keep one
+ * workgroup per matrix for the whole factorization.  Default 256; n >= 512
+ * never splits; n = 0 splits every batch.  The factors are the same bit
+ * for bit either way.  Applies to later factorizations of the tree.
+ * Errors: ASKIT_ERR_ARG for a NULL tree or n < 0. */
+askit_status askit_tree_set_lu_split(askit_tree t, int32_t n);
+
 /* Hybrid solver (Sec. 2.3, "Fast hybrid solver"; Alg. HybridSolve, MatVecW,
  * MatVecV) with the skeletonization frontier at tree level `level`
  * (1 .. D): the frontier's nodes and their subtrees are factored as by

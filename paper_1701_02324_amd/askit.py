@@ -29,6 +29,7 @@ EXPORTED = [
     "askit_factorize_batched", "askit_tree_qr_rows", "askit_tree_samples", "askit_tree_permutation_noalloc",
     "askit_factorize_hybrid", "askit_tree_knn", "askit_tree_neighbor_lists", "askit_tune_factorization",
     "askit_tree_set_tiling",
+    "askit_tree_set_lu_split",
 ]
 
 
@@ -73,6 +74,7 @@ def load(path: str = LIB_PATH):
     L.askit_tree_knn.argtypes = [_vp, _vp]
     L.askit_tune_factorization.argtypes = [_vp, ctypes.c_double, _vp]
     L.askit_tree_set_tiling.argtypes = [_vp, _vp, _i32]
+    L.askit_tree_set_lu_split.argtypes = [_vp, _i32]
     L.askit_tree_neighbor_lists.argtypes = [_vp, _vp, _vp, _vp]
     L.askit_tree_permutation_noalloc.argtypes = [_vp, _i64, _i32, _i32, _vp, _vp]
     L.askit_skeletonize.argtypes = [_vp, _vp]
@@ -441,6 +443,12 @@ class Tree:
             flat.extend(int(v) for v in (table[h] if h in table else table[str(h)]))
         arr = (ctypes.c_int32 * len(flat))(*flat)
         _check(load().askit_tree_set_tiling(self.handle, ctypes.cast(arr, _vp), len(table)))
+
+    def set_lu_split(self, n):
+        """LU batches whose largest matrix has more than n rows run panel by
+        panel over launches (askit_tree_set_lu_split; default 256, 512 never
+        splits, 0 always)."""
+        _check(load().askit_tree_set_lu_split(self.handle, int(n)))
 
     def skeletonize_factorize(self, lam, precision=ASKIT_FP64, stream=None):
         """skeletonize() then factorize(), pipelined over two streams."""

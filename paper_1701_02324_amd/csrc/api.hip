@@ -591,18 +591,59 @@ static std::vector<LuTask> largest_first(const std::vector<LuTask> &v) {
     return o;
 }
 
-askit_status lu_commit(Plan &P, const std::vector<LuTask> &v0, bool spd = false) {
+askit_status lu_commit(Plan &P, const std::vector<LuTask> &v0, bool spd, int32_t split_n) {
     if (v0.empty()) return ASKIT_OK;
     const std::vector<LuTask> v = largest_first(v0);
     DBuf *b = P.own();
     ST_TRY(upload(*b, v));
     const LuTask *tp = b->as<LuTask>();
-    const int n = (int)v.size();
-    P.add(spd ? "k_lu_nopiv" : "k_lu", [=](hipStream_t st, int) -> hipError_t {
-        if (spd) hipLaunchKernelGGL(k_lu_nopiv, dim3(n), dim3(kLuFThreads), 0, st, tp);
-        else hipLaunchKernelGGL(k_lu, dim3(n), dim3(kLuFThreads), 0, st, tp);
-        return hipGetLastError();
-    });
+    const int n = (int)v.size(), nmax = v[0].n;
+    if (!spd && nmax > split_n) {
+        // split over launches (k_lup_*): per panel, the tasks still
+        // factoring (a prefix, largest first) and the 64 x 64 tiles of their
+        // trailing matrices
+        DBuf *bw = P.own(), *bi = P.own();
+        const size_t prow_bytes = (size_t)n * kLuMaxN * sizeof(int32_t);
+        ST_TRY(bw->alloc(prow_bytes + (size_t)n * 2 * sizeof(double)));
+        const LuSplit w{bw->as<int32_t>(), (double *)((char *)bw->p + prow_bytes)};
+        std::vector<TileItem> items;
+        std::vector<int> active, off;
+        for (int kb = 0; kb < nmax; kb += kLuPanel) {
+            int act = 0;
+            std::vector<TileItem> pi;
+            for (int i = 0; i < n; i++) {
+                if (v[(size_t)i].n <= kb) break;
+                act++;
+                const int tt = (int)cdiv(v[(size_t)i].n - kb - kLuPanel, 64);
+                for (int rt = 0; rt < tt; rt++)
+                    for (int ct = 0; ct < tt; ct++) pi.push_back(TileItem{i, rt, ct, 0});
+            }
+            xcd_order(pi);
+            active.push_back(act);
+            off.push_back((int)items.size());
+            items.insert(items.end(), pi.begin(), pi.end());
+        }
+        off.push_back((int)items.size());
+        ST_TRY(upload(*bi, items));
+        const TileItem *ip = bi->as<TileItem>();
+        P.add("k_lu", [=](hipStream_t st, int) -> hipError_t {
+            for (size_t p = 0; p < active.size(); p++) {
+                const int kb = (int)p * kLuPanel;
+                hipLaunchKernelGGL(k_lup_panel, dim3(active[p]), dim3(kLuFThreads), 0, st, tp, w, kb);
+                if (off[p + 1] > off[p])
+                    hipLaunchKernelGGL(k_lup_update, dim3(off[p + 1] - off[p]), dim3(kLupThreads), 0, st, tp, w,
+                                       ip + off[p], kb);
+            }
+            hipLaunchKernelGGL(k_lup_finish, dim3(n), dim3(kLuFThreads), 0, st, tp, w);
+            return hipGetLastError();
+        });
+    } else {
+        P.add(spd ? "k_lu_nopiv" : "k_lu", [=](hipStream_t st, int) -> hipError_t {
+            if (spd) hipLaunchKernelGGL(k_lu_nopiv, dim3(n), dim3(kLuFThreads), 0, st, tp);
+            else hipLaunchKernelGGL(k_lu, dim3(n), dim3(kLuFThreads), 0, st, tp);
+            return hipGetLastError();
+        });
+    }
     P.add("k_lu_diaginv", [=](hipStream_t st, int) -> hipError_t {
         hipLaunchKernelGGL(k_lu_diaginv, dim3(n), dim3(256), 0, st, tp);
         return hipGetLastError();
@@ -783,6 +824,7 @@ struct askit_tree_s {
     double t_knn = 0;
     unsigned long long knn_points = 0;  // points the neighbour search compared, summed over its waves
     std::vector<Tune> tune;  // per tree height, from askit_tune_factorization (empty: built-in choices)
+    int32_t lu_split = kLuSplitN;  // LU batches with a larger matrix are split over launches (askit_tree_set_lu_split)
     int32_t *hsr_pinned = nullptr;  // pinned landing buffer of the rank reads (nnodes)
     ~askit_tree_s() {
         if (hsr_pinned) (void)hipHostFree(hsr_pinned);
@@ -1563,6 +1605,13 @@ static int64_t tree_kc_min(askit_tree t) {
 // else a single tree's tuned configuration, else the built-in choice
 enum PartHalf { PartAll = 3, PartZ = 1, PartPhat = 2 };
 
+// the smallest split size of the trees factored together
+static int32_t lu_split_of(const std::vector<askit_factor> &fs) {
+    int32_t n = kLuSplitN;
+    for (size_t i = 0; i < fs.size(); i++) n = i ? std::min(n, fs[i]->t->lu_split) : fs[i]->t->lu_split;
+    return n;
+}
+
 static askit_status factor_plan_part(const std::vector<askit_factor> &fs, Plan &P, int part,
                                      const Tune *force = nullptr, int half = PartAll) {
     askit_tree t0 = fs[0]->t;
@@ -1630,7 +1679,7 @@ static askit_status factor_plan_part(const std::vector<askit_factor> &fs, Plan &
             // lambda I + K_aa is symmetric positive definite for lambda > 0
             bool spd = true;
             for (auto f : fs) spd = spd && f->lambda > 0.0;
-            ST_TRY(lu_commit(P, lu, spd));
+            ST_TRY(lu_commit(P, lu, spd, lu_split_of(fs)));
         } else {
             ST_TRY(copy_commit(P, cp, P64, pr, mmax, s));
             ST_TRY(getrs_commit(P, rs, pr, false, s));
@@ -1736,7 +1785,7 @@ static askit_status factor_plan_part(const std::vector<askit_factor> &fs, Plan &
         }
         ST_TRY(ident_commit(P, ident, s2));
         ST_TRY(kmm_commit(P, kb, pr, P64, d, s));
-        ST_TRY(lu_commit(P, lu));
+        ST_TRY(lu_commit(P, lu, false, lu_split_of(fs)));
         ST_TRY(copy_commit(P, cp, P64, P64, s2, s));
         ST_TRY(getrs_commit(P, rs, P64, false, s));
         if (pr == P32) ST_TRY(copy_commit(P, cp32, P64, P32, s2, s));
@@ -2067,6 +2116,13 @@ askit_status askit_tree_set_tiling(askit_tree t, const int32_t *table, int32_t h
         tn[h] = Tune{e[0], e[2], e[1]};
     }
     t->tune = tn;
+    return ASKIT_OK;
+}
+
+askit_status askit_tree_set_lu_split(askit_tree t, int32_t n) {
+    if (!t) return fail(ASKIT_ERR_ARG, "NULL tree");
+    if (n < 0) return fail(ASKIT_ERR_ARG, "n must be >= 0");
+    t->lu_split = n;
     return ASKIT_OK;
 }
 

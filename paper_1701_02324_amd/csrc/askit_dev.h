@@ -19,6 +19,10 @@ constexpr int kQsState = 8;      // ints of per-node state of the split QRCP
 constexpr int kOneWgLevel = 10;  // pipelined call, by default: tree levels from here (>= 1024 nodes) use one workgroup per node
 constexpr int kLsThreads = 1024; // batched LU solves: 16 waves keep many block loads in flight
 constexpr int kLuFThreads = 512; // batched LU factorization
+constexpr int kLuMaxN = 512;     // largest matrix of the batched LU
+constexpr int kLuPanel = 32;     // panel width of the blocked LU
+constexpr int kLupThreads = 256; // LU split over launches: threads of a trailing-update tile
+constexpr int kLuSplitN = 256;   // LU batches whose largest matrix is larger are split over launches
 constexpr int kXrDim = 16;       // kernel-block products keep row points in registers up to this dimension
 constexpr int kNbrThreads = 1024; // neighbour-list ranking: threads per node
 constexpr int kNbrLds = 4096;     // neighbour-list ranking: keys sorted in LDS (more go to a scratch slot)
@@ -184,6 +188,14 @@ struct LuTask {
     double *ratio;        // pivot ratio output (factor)
     double *dinv;         // inverses of the 16 x 16 diagonal blocks of L and U
     int32_t nrhs, pad;    // right-hand sides of this task (0: the launch's count)
+};
+
+// State of the LU split over launches (one slot per task of the launch):
+// the physical row of each logical row, and the smallest and largest
+// |pivot| so far.
+struct LuSplit {
+    int32_t *prow;        // tasks x kLuMaxN
+    double *smm;          // tasks x 2
 };
 
 // Sampling task (rows outside a node): the npre positions of pre first (the

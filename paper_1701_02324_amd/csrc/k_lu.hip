@@ -14,9 +14,8 @@
 
 namespace askit {
 
-constexpr int kPanel = 32;
+constexpr int kPanel = kLuPanel;
 static_assert(kLuFThreads % kWave == 0, "whole waves");
-constexpr int kLuMaxN = 512;
 static_assert(kLuFThreads >= kLuMaxN, "one thread per row of the largest matrix");
 
 // ---------------------------------------------------------------------------
@@ -121,134 +120,135 @@ __device__ inline void trailing_update(GLB double *A, int lda, int kb, int r0, i
     }
 }
 
-__global__ __launch_bounds__(kLuFThreads) void k_lu(const LuTask *__restrict__ tasks) {
-    constexpr int NT = kLuFThreads, NW = NT / kWave;
-    // W: the U block row (row-major, ld = nt rounded up to 64), then staging
-    // of the final row pass; L11: the unit lower panel triangle; prb: the
-    // pivot row
-    __shared__ double W[kPanel * kLuMaxN];
-    __shared__ double L11[kPanel * kPanel];
-    __shared__ double redv[NW];
-    __shared__ int redk[NW];
-    __shared__ double prb[kPanel];
-    __shared__ int32_t sp[kPanel];
-    // logical row i of the matrix is stored in physical row prow[i]: row
-    // exchanges only swap entries here; one pass at the end puts every row
-    // in place
-    __shared__ int32_t prow[kLuMaxN];
-    const LuTask t = tasks[blockIdx.x];
-    const int n = t.n, lda = t.lda, tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
-    GLB double *A = glb(t.A);
-    // smallest and largest |pivot| (every thread sees every pivot)
-    double s_min = INFINITY, s_max = 0.0;
-    for (int i = tid; i < n; i += NT) prow[i] = i;
-    __syncthreads();
-    for (int kb = 0; kb < n; kb += kPanel) {
-        const int nb = n - kb < kPanel ? n - kb : kPanel, m = n - kb;
-        // ---- panel (columns kb .. kb+nb-1, rows kb .. n-1): thread r < m
-        // holds panel row r in registers.  Rows do not move: each keeps its
-        // logical position lp and an exchange only swaps two positions, so a
-        // column step is one pivot search over the rows not chosen yet, one
-        // broadcast of the pivot row through LDS and a local rank-1 update.
-        {
-            const bool own = tid < m;
-            const int32_t arow = own ? prow[kb + tid] : 0;
-            double rw[kPanel];
+// Shared memory of one panel of the blocked LU: L11 the unit lower panel
+// triangle; redv / redk the per-wave pivot candidates; prb the pivot row;
+// sp the panel's pivot rows.
+struct LuPanelLds {
+    double L11[kPanel * kPanel];
+    double redv[kLuFThreads / kWave];
+    int redk[kLuFThreads / kWave];
+    double prb[kPanel];
+    int32_t sp[kPanel];
+};
+
+// Panel kb of the blocked LU (columns kb .. kb+nb-1, rows kb .. n-1) and the
+// U block row right of it, by one workgroup of kLuFThreads threads.
+// Logical row i of the matrix is stored in physical row prow[i] (LDS): row
+// exchanges only swap entries there.  With STAGE the U block row is also
+// left in W (row-major, ld = trailing columns rounded up to 64) for the
+// trailing update.  Ends with a barrier.  Returns the
+// number of trailing columns n - kb - nb.
+template <bool STAGE>
+__device__ inline int lu_panel(GLB double *A, GLB int32_t *piv, int n, int lda, int kb, int32_t *prow,
+                               LuPanelLds &S, double *W, double &s_min, double &s_max, int tid, int lane, int wave) {
+    constexpr int NW = kLuFThreads / kWave;
+    const int nb = n - kb < kPanel ? n - kb : kPanel, m = n - kb;
+    // ---- panel: thread r < m holds panel row r in registers.  Rows do not
+    // move: each keeps its logical position lp and an exchange only swaps two
+    // positions, so a column step is one pivot search over the rows not
+    // chosen yet, one broadcast of the pivot row through LDS and a local
+    // rank-1 update.
+    {
+        const bool own = tid < m;
+        const int32_t arow = own ? prow[kb + tid] : 0;
+        double rw[kPanel];
 #pragma unroll
-            for (int j = 0; j < kPanel; j++) rw[j] = (own && j < nb) ? A[arow + (int64_t)(kb + j) * lda] : 0.0;
-            int lp = tid;
-            bool done = !own;
+        for (int j = 0; j < kPanel; j++) rw[j] = (own && j < nb) ? A[arow + (int64_t)(kb + j) * lda] : 0.0;
+        int lp = tid;
+        bool done = !own;
 #pragma unroll
-            for (int k = 0; k < kPanel; k++) {
-                if (k < nb) {
-                    // largest |a| of column k over the remaining rows (a NaN
-                    // counts as infinite), ties to the lowest position: the
-                    // maximum first, then the smallest key = position * 1024
-                    // + row among the rows holding it
-                    const double a = rw[k];
-                    const double v = done ? -1.0 : (a != a ? INFINITY : fabs(a));
-                    const double wm = wave_max_d(v);
-                    const int wk = wave_min_i(v == wm ? ((lp << 10) | tid) : 0x7fffffff);
-                    if (lane == 0) {
-                        redv[wave] = wm;
-                        redk[wave] = wk;
-                    }
-                    __syncthreads();
-                    double bv = redv[0];
+        for (int k = 0; k < kPanel; k++) {
+            if (k < nb) {
+                // largest |a| of column k over the remaining rows (a NaN
+                // counts as infinite), ties to the lowest position: the
+                // maximum first, then the smallest key = position * 1024
+                // + row among the rows holding it
+                const double a = rw[k];
+                const double v = done ? -1.0 : (a != a ? INFINITY : fabs(a));
+                const double wm = wave_max_d(v);
+                const int wk = wave_min_i(v == wm ? ((lp << 10) | tid) : 0x7fffffff);
+                if (lane == 0) {
+                    S.redv[wave] = wm;
+                    S.redk[wave] = wk;
+                }
+                __syncthreads();
+                double bv = S.redv[0];
 #pragma unroll
-                    for (int w = 1; w < NW; w++) bv = fmax(bv, redv[w]);
-                    int bk = 0x7fffffff;
+                for (int w = 1; w < NW; w++) bv = fmax(bv, S.redv[w]);
+                int bk = 0x7fffffff;
 #pragma unroll
-                    for (int w = 0; w < NW; w++) bk = redv[w] == bv ? min(bk, redk[w]) : bk;
-                    const int P = bk & 1023, p = bk >> 10;
-                    if (tid == P) {
+                for (int w = 0; w < NW; w++) bk = S.redv[w] == bv ? min(bk, S.redk[w]) : bk;
+                const int P = bk & 1023, p = bk >> 10;
+                if (tid == P) {
 #pragma unroll
-                        for (int j = 0; j < kPanel; j++) prb[j] = rw[j];
-                        done = true;
-                    }
-                    if (tid == 0) sp[k] = kb + p;
-                    if (lp == k) lp = p;  // the row at position k moves to p
-                    if (tid == P) lp = k;
-                    __syncthreads();
-                    const double ukk = prb[k];
-                    const double au = fabs(ukk);
-                    s_min = au == au ? fmin(s_min, au) : 0.0;
-                    s_max = fmax(s_max, au);
-                    if (!done && ukk != 0.0) {
-                        const double l = rw[k] / ukk;
-                        rw[k] = l;
+                    for (int j = 0; j < kPanel; j++) S.prb[j] = rw[j];
+                    done = true;
+                }
+                if (tid == 0) S.sp[k] = kb + p;
+                if (lp == k) lp = p;  // the row at position k moves to p
+                if (tid == P) lp = k;
+                __syncthreads();
+                const double ukk = S.prb[k];
+                const double au = fabs(ukk);
+                s_min = au == au ? fmin(s_min, au) : 0.0;
+                s_max = fmax(s_max, au);
+                if (!done && ukk != 0.0) {
+                    const double l = rw[k] / ukk;
+                    rw[k] = l;
 #pragma unroll
-                        for (int j = k + 1; j < kPanel; j++) rw[j] = fma(-l, prb[j], rw[j]);
-                    }
+                    for (int j = k + 1; j < kPanel; j++) rw[j] = fma(-l, S.prb[j], rw[j]);
                 }
             }
-            // rows stay where they are in A; their positions go into prow
-            if (own) {
+        }
+        // rows stay where they are in A; their positions go into prow
+        if (own) {
 #pragma unroll
-                for (int j = 0; j < kPanel; j++)
-                    if (j < nb) A[arow + (int64_t)(kb + j) * lda] = rw[j];
-                if (lp < nb) {
+            for (int j = 0; j < kPanel; j++)
+                if (j < nb) A[arow + (int64_t)(kb + j) * lda] = rw[j];
+            if (lp < nb) {
 #pragma unroll
-                    for (int c = 0; c < kPanel; c++)
-                        if (c < nb) L11[lp + c * kPanel] = rw[c];
-                }
-                prow[kb + lp] = arow;
+                for (int c = 0; c < kPanel; c++)
+                    if (c < nb) S.L11[lp + c * kPanel] = rw[c];
             }
-            if (tid < nb) glb(t.piv)[kb + tid] = sp[tid];
-            __syncthreads();
+            prow[kb + lp] = arow;
         }
-        const int j0 = kb + nb, nt = n - j0;
-        if (nt <= 0) continue;  // only the last panel can be narrower than kPanel
-        // ---- U block row: A[kb:kb+32, j0:n] = L11^{-1} A[kb:kb+32, j0:n],
-        // thread j solves column j0 + j in registers (the same operations,
-        // in the same order, as row-by-row substitution); the rows are also
-        // staged in W for the trailing update, zero-padded to ldw columns
-        const int ldw = (nt + 63) & ~63;
-        if (tid >= nt && tid < ldw) {
-#pragma unroll
-            for (int r = 0; r < kPanel; r++) W[r * ldw + tid] = 0.0;
-        }
-        if (tid < nt) {
-            const int64_t col = (int64_t)(j0 + tid) * lda;
-            double u[kPanel];
-#pragma unroll
-            for (int r = 0; r < kPanel; r++) u[r] = A[prow[kb + r] + col];
-#pragma unroll
-            for (int c = 0; c < kPanel; c++)
-#pragma unroll
-                for (int r = c + 1; r < kPanel; r++) u[r] = fma(-L11[r + c * kPanel], u[c], u[r]);
-#pragma unroll
-            for (int r = 0; r < kPanel; r++) {
-                A[prow[kb + r] + col] = u[r];
-                W[r * ldw + tid] = u[r];
-            }
-        }
-        __syncthreads();
-        trailing_update<NW, kPanel>(A, lda, kb, j0, nt, j0, nt, W, ldw, [&](int i) -> int64_t { return prow[i]; }, wave,
-                                    lane);
+        if (tid < nb) piv[kb + tid] = S.sp[tid];
         __syncthreads();
     }
-    // rows in place: column batches of kPanel staged in W
+    const int j0 = kb + nb, nt = n - j0;
+    if (nt <= 0) return nt;  // only the last panel can be narrower than kPanel
+    // ---- U block row: A[kb:kb+32, j0:n] = L11^{-1} A[kb:kb+32, j0:n],
+    // thread j solves column j0 + j in registers (the same operations, in
+    // the same order, as row-by-row substitution); with STAGE the rows are
+    // also staged in W, zero-padded to ldw columns
+    const int ldw = (nt + 63) & ~63;
+    if (STAGE && tid >= nt && tid < ldw) {
+#pragma unroll
+        for (int r = 0; r < kPanel; r++) W[r * ldw + tid] = 0.0;
+    }
+    if (tid < nt) {
+        const int64_t col = (int64_t)(j0 + tid) * lda;
+        double u[kPanel];
+#pragma unroll
+        for (int r = 0; r < kPanel; r++) u[r] = A[prow[kb + r] + col];
+#pragma unroll
+        for (int c = 0; c < kPanel; c++)
+#pragma unroll
+            for (int r = c + 1; r < kPanel; r++) u[r] = fma(-S.L11[r + c * kPanel], u[c], u[r]);
+#pragma unroll
+        for (int r = 0; r < kPanel; r++) {
+            A[prow[kb + r] + col] = u[r];
+            if (STAGE) W[r * ldw + tid] = u[r];
+        }
+    }
+    __syncthreads();
+    return nt;
+}
+
+// Rows in place (physical row prow[i] becomes row i): column batches of
+// kPanel staged in W.
+__device__ inline void lu_rows_in_place(GLB double *A, int n, int lda, const int32_t *prow, double *W, int tid) {
+    constexpr int NT = kLuFThreads;
     for (int cb = 0; cb < n; cb += kPanel) {
         const int nc = n - cb < kPanel ? n - cb : kPanel;
         for (int e = tid; e < n * nc; e += NT) {
@@ -262,7 +262,106 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu(const LuTask *__restrict__ t
         }
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(kLuFThreads) void k_lu(const LuTask *__restrict__ tasks) {
+    constexpr int NT = kLuFThreads, NW = NT / kWave;
+    // W: the U block row, then staging of the final row pass
+    __shared__ double W[kPanel * kLuMaxN];
+    __shared__ LuPanelLds S;
+    __shared__ int32_t prow[kLuMaxN];
+    const LuTask t = tasks[blockIdx.x];
+    const int n = t.n, lda = t.lda, tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    GLB double *A = glb(t.A);
+    // smallest and largest |pivot| (every thread sees every pivot)
+    double s_min = INFINITY, s_max = 0.0;
+    for (int i = tid; i < n; i += NT) prow[i] = i;
+    __syncthreads();
+    for (int kb = 0; kb < n; kb += kPanel) {
+        const int nt = lu_panel<true>(A, glb(t.piv), n, lda, kb, prow, S, W, s_min, s_max, tid, lane, wave);
+        if (nt <= 0) continue;
+        const int j0 = n - nt, ldw = (nt + 63) & ~63;
+        trailing_update<NW, kPanel>(A, lda, kb, j0, nt, j0, nt, W, ldw, [&](int i) -> int64_t { return prow[i]; },
+                                    wave, lane);
+        __syncthreads();
+    }
+    lu_rows_in_place(A, n, lda, prow, W, tid);
     if (tid == 0 && t.ratio) *glb(t.ratio) = n ? (s_max > 0.0 ? s_min / s_max : 0.0) : 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// The same factorization split over launches, for batches whose largest
+// matrices leave most compute units idle under one workgroup per matrix:
+// per panel, k_lup_panel factors the panel and solves the U block row (one
+// workgroup per matrix, the code of k_lu), then k_lup_update applies the
+// trailing update in 64 x 64 tiles, one workgroup each (the trailing update
+// of k_lu restricted to the tile: the same products in the same order, so
+// the factors are bit for bit those of k_lu); k_lup_finish puts the rows in
+// place.  Between launches each matrix's row positions and pivot extremes
+// live in LuSplit.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kLuFThreads) void k_lup_panel(const LuTask *__restrict__ tasks, LuSplit w, int kb) {
+    constexpr int NT = kLuFThreads;
+    __shared__ LuPanelLds S;
+    __shared__ int32_t prow[kLuMaxN];
+    const LuTask t = tasks[blockIdx.x];
+    const int n = t.n, lda = t.lda, tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    if (kb >= n) return;
+    GLB int32_t *gp = glb(w.prow) + (int64_t)blockIdx.x * kLuMaxN;
+    GLB double *gs = glb(w.smm) + 2 * (int64_t)blockIdx.x;
+    double s_min = INFINITY, s_max = 0.0;
+    if (kb == 0) {
+        for (int i = tid; i < n; i += NT) prow[i] = i;
+    } else {
+        for (int i = tid; i < n; i += NT) prow[i] = gp[i];
+        s_min = gs[0];
+        s_max = gs[1];
+    }
+    __syncthreads();
+    lu_panel<false>(glb(t.A), glb(t.piv), n, lda, kb, prow, S, nullptr, s_min, s_max, tid, lane, wave);
+    // the panel moved positions kb .. n-1 only
+    for (int i = kb + tid; i < n; i += NT) gp[i] = prow[i];
+    if (tid == 0) {
+        gs[0] = s_min;
+        gs[1] = s_max;
+    }
+}
+
+__global__ __launch_bounds__(kLupThreads) void k_lup_update(const LuTask *__restrict__ tasks, LuSplit w,
+                                                             const TileItem *__restrict__ items, int kb) {
+    __shared__ double W[kPanel * 64];
+    const TileItem it = items[blockIdx.x];
+    if (it.task < 0) return;  // padding of the compute-die order
+    const LuTask t = tasks[it.task];
+    const int n = t.n, lda = t.lda, tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    const int j0 = kb + kPanel, r0 = j0 + 64 * it.rt, c0 = j0 + 64 * it.ct;
+    const int nr = min(64, n - r0), nc = min(64, n - c0);
+    GLB double *A = glb(t.A);
+    const GLB int32_t *gp = glb(w.prow) + (int64_t)it.task * kLuMaxN;
+    // the tile's columns of the U block row, zero past nc
+    for (int e = tid; e < kPanel * 64; e += kLupThreads) {
+        const int k = e / 64, cj = e % 64;
+        W[e] = cj < nc ? A[gp[kb + k] + (int64_t)(c0 + cj) * lda] : 0.0;
+    }
+    __syncthreads();
+    trailing_update<kLupThreads / kWave, kPanel>(A, lda, kb, r0, nr, c0, nc, W, 64,
+                                                 [&](int i) -> int64_t { return gp[i]; }, wave, lane);
+}
+
+__global__ __launch_bounds__(kLuFThreads) void k_lup_finish(const LuTask *__restrict__ tasks, LuSplit w) {
+    constexpr int NT = kLuFThreads;
+    __shared__ double W[kPanel * kLuMaxN];
+    __shared__ int32_t prow[kLuMaxN];
+    const LuTask t = tasks[blockIdx.x];
+    const int n = t.n, lda = t.lda, tid = threadIdx.x;
+    const GLB int32_t *gp = glb(w.prow) + (int64_t)blockIdx.x * kLuMaxN;
+    for (int i = tid; i < n; i += NT) prow[i] = gp[i];
+    __syncthreads();
+    lu_rows_in_place(glb(t.A), n, lda, prow, W, tid);
+    if (tid == 0 && t.ratio) {
+        const GLB double *gs = glb(w.smm) + 2 * (int64_t)blockIdx.x;
+        *glb(t.ratio) = n ? (gs[1] > 0.0 ? gs[0] / gs[1] : 0.0) : 1.0;
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -65,6 +65,7 @@ def test_argument_validation_without_gpu(lib):
     assert lib.askit_tree_knn(None, fake) == A.ASKIT_ERR_ARG
     assert lib.askit_tune_factorization(None, 1.0, None) == A.ASKIT_ERR_ARG
     assert lib.askit_tree_set_tiling(None, None, 0) == A.ASKIT_ERR_ARG
+    assert lib.askit_tree_set_lu_split(None, 256) == A.ASKIT_ERR_ARG
     assert lib.askit_tree_neighbor_lists(None, fake, fake, fake) == A.ASKIT_ERR_ARG
     assert lib.askit_skeletonize(None, None) == A.ASKIT_ERR_ARG
     assert lib.askit_factorize(None, 1.0, 0, None, ctypes.byref(out)) == A.ASKIT_ERR_ARG

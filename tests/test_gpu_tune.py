@@ -1,7 +1,8 @@
-"""The factorization's tile autotuner (level-batched execution, Sec. 2.2's
+"""The factorization's launch shapes (level-batched execution, Sec. 2.2's
 level schedule): a tuned tree factorizes to the same solution up to the
 rounding of the regrouped split sums, through both entry points, in FP64
-and in mixed precision."""
+and in mixed precision; tile widths and the LU split over launches change
+no result."""
 import sys
 
 import numpy as np
@@ -101,4 +102,40 @@ def test_tile_width_changes_no_result(ak, d):
         t.set_tiling({h: (96, 4096, 64) for h in range(1, t.D + 1)})
     with pytest.raises(ak.AskitError):
         t.set_tiling({h: (64, 1000, 64) for h in range(1, t.D + 1)})
+    t.close()
+
+
+@pytest.mark.parametrize("lam", [0.5, 0.0])
+def test_lu_split_changes_no_result(ak, lam):
+    """The LU with partial pivoting split over launches (a 32-column panel
+    per launch over the batch, the trailing update in 64 x 64 tiles) gives
+    the factors of the one-workgroup LU bit for bit: reduced systems Z of up
+    to 2s = 320 rows (split from 257 rows by default), and with lambda = 0
+    the leaf blocks (up to 256 rows, factored with pivoting) too when every
+    batch is split; through both entry points."""
+    X, B = synth.small(12000, 8, 47, nrhs=2, kind="mixture", scale=4.0)
+    print(f"[gpu tune] LU split, N=12000 d=8 m=256 s=160 lambda={lam}", file=sys.stderr, flush=True)
+    t = ak.Tree(_cuda(X), 256, 160, 2.0, seed=5)
+    t.skeletonize()
+    r = t.skeleton_sizes()[0]
+    zmax = max(int(r[2 * i + 1] + r[2 * i + 2]) for i in range((len(r) - 1) // 2))
+    assert zmax > 256  # the default splits the upper heights
+    Bd = _cuda(B)
+    xs, ratios = {}, {}
+    for n in (512, 256, 0):
+        t.set_lu_split(n)
+        f = t.factorize(lam, ak.ASKIT_FP64)
+        xs[n] = f.solve(Bd).cpu().numpy()
+        ratios[n] = f.pivot_ratio()
+        f.close()
+    assert np.array_equal(xs[512], xs[256], equal_nan=True) and np.array_equal(xs[512], xs[0], equal_nan=True)
+    assert ratios[512] == ratios[256] == ratios[0]
+    if lam > 0:
+        assert np.all(np.isfinite(xs[0]))
+    t.set_lu_split(0)
+    f = t.skeletonize_factorize(lam, ak.ASKIT_FP64)
+    assert np.array_equal(f.solve(Bd).cpu().numpy(), xs[512], equal_nan=True)
+    f.close()
+    with pytest.raises(ak.AskitError):
+        t.set_lu_split(-1)
     t.close()
