@@ -624,6 +624,12 @@ askit_status lu_commit(Plan &P, const std::vector<LuTask> &v0, bool spd, int32_t
             items.insert(items.end(), pi.begin(), pi.end());
         }
         off.push_back((int)items.size());
+        // the final row pass: kLupFinCols columns per workgroup; a task of
+        // order 0 still gets one (its pivot ratio)
+        for (int i = 0; i < n; i++)
+            for (int cg = 0; cg < std::max<int64_t>(1, cdiv(v[(size_t)i].n, kLupFinCols)); cg++)
+                items.push_back(TileItem{i, cg, 0, 0});
+        const int nfin = (int)items.size() - off.back();
         ST_TRY(upload(*bi, items));
         const TileItem *ip = bi->as<TileItem>();
         P.add("k_lu", [=](hipStream_t st, int) -> hipError_t {
@@ -634,7 +640,7 @@ askit_status lu_commit(Plan &P, const std::vector<LuTask> &v0, bool spd, int32_t
                     hipLaunchKernelGGL(k_lup_update, dim3(off[p + 1] - off[p]), dim3(kLupThreads), 0, st, tp, w,
                                        ip + off[p], kb);
             }
-            hipLaunchKernelGGL(k_lup_finish, dim3(n), dim3(kLuFThreads), 0, st, tp, w);
+            hipLaunchKernelGGL(k_lup_finish, dim3(nfin), dim3(kLupThreads), 0, st, tp, w, ip + off.back());
             return hipGetLastError();
         });
     } else {

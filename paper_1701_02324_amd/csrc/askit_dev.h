@@ -22,6 +22,7 @@ constexpr int kLuFThreads = 512; // batched LU factorization
 constexpr int kLuMaxN = 512;     // largest matrix of the batched LU
 constexpr int kLuPanel = 32;     // panel width of the blocked LU
 constexpr int kLupThreads = 256; // LU split over launches: threads of a trailing-update tile
+constexpr int kLupFinCols = 8;   // LU split over launches: columns per workgroup of the final row pass
 constexpr int kLuSplitN = 256;   // LU batches whose largest matrix is larger are split over launches
 constexpr int kXrDim = 16;       // kernel-block products keep row points in registers up to this dimension
 constexpr int kNbrThreads = 1024; // neighbour-list ranking: threads per node

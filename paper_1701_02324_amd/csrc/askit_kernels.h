@@ -53,7 +53,7 @@ __global__ void k_nbr_rank(NbrTask t, int64_t first, int64_t pmax, uint64_t *scr
 __global__ void k_lu(const LuTask *tasks);
 __global__ void k_lup_panel(const LuTask *tasks, LuSplit w, int kb);
 __global__ void k_lup_update(const LuTask *tasks, LuSplit w, const TileItem *items, int kb);
-__global__ void k_lup_finish(const LuTask *tasks, LuSplit w);
+__global__ void k_lup_finish(const LuTask *tasks, LuSplit w, const TileItem *items);
 __global__ void k_lu_nopiv(const LuTask *tasks);
 __global__ void k_lu_diaginv(const LuTask *tasks);
 template <typename T, int NR, bool TRANS>

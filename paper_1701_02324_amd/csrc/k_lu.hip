@@ -297,7 +297,7 @@ __global__ __launch_bounds__(kLuFThreads) void k_lu(const LuTask *__restrict__ t
 // trailing update in 64 x 64 tiles, one workgroup each (the trailing update
 // of k_lu restricted to the tile: the same products in the same order, so
 // the factors are bit for bit those of k_lu); k_lup_finish puts the rows in
-// place.  Between launches each matrix's row positions and pivot extremes
+// place, a few columns per workgroup.  Between launches each matrix's row positions and pivot extremes
 // live in LuSplit.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kLuFThreads) void k_lup_panel(const LuTask *__restrict__ tasks, LuSplit w, int kb) {
@@ -348,18 +348,35 @@ __global__ __launch_bounds__(kLupThreads) void k_lup_update(const LuTask *__rest
                                                  [&](int i) -> int64_t { return gp[i]; }, wave, lane);
 }
 
-__global__ __launch_bounds__(kLuFThreads) void k_lup_finish(const LuTask *__restrict__ tasks, LuSplit w) {
-    constexpr int NT = kLuFThreads;
-    __shared__ double W[kPanel * kLuMaxN];
-    __shared__ int32_t prow[kLuMaxN];
-    const LuTask t = tasks[blockIdx.x];
+// Rows in place, kLupFinCols columns per workgroup (the columns are
+// independent): lanes 32 c .. 32 c + 31 move column c0 + c, each lane every
+// 32nd row, through registers; the barrier separates the reads of the
+// workgroup's columns from its writes.
+__global__ __launch_bounds__(kLupThreads) void k_lup_finish(const LuTask *__restrict__ tasks, LuSplit w,
+                                                             const TileItem *__restrict__ items) {
+    static_assert(kLupThreads == 32 * kLupFinCols, "32 lanes per column");
+    constexpr int RPL = kLuMaxN / 32;  // rows per lane
+    const TileItem it = items[blockIdx.x];
+    const LuTask t = tasks[it.task];
     const int n = t.n, lda = t.lda, tid = threadIdx.x;
-    const GLB int32_t *gp = glb(w.prow) + (int64_t)blockIdx.x * kLuMaxN;
-    for (int i = tid; i < n; i += NT) prow[i] = gp[i];
+    const int c = it.rt * kLupFinCols + tid / 32, r0 = tid % 32;
+    const bool live = c < n;
+    GLB double *col = glb(t.A) + (int64_t)c * lda;
+    const GLB int32_t *gp = glb(w.prow) + (int64_t)it.task * kLuMaxN;
+    double v[RPL];
+#pragma unroll
+    for (int i = 0; i < RPL; i++) {
+        const int r = r0 + 32 * i;
+        v[i] = live && r < n ? col[gp[r]] : 0.0;
+    }
     __syncthreads();
-    lu_rows_in_place(glb(t.A), n, lda, prow, W, tid);
-    if (tid == 0 && t.ratio) {
-        const GLB double *gs = glb(w.smm) + 2 * (int64_t)blockIdx.x;
+#pragma unroll
+    for (int i = 0; i < RPL; i++) {
+        const int r = r0 + 32 * i;
+        if (live && r < n) col[r] = v[i];
+    }
+    if (it.rt == 0 && tid == 0 && t.ratio) {
+        const GLB double *gs = glb(w.smm) + 2 * (int64_t)it.task;
         *glb(t.ratio) = n ? (gs[1] > 0.0 ? gs[0] / gs[1] : 0.0) : 1.0;
     }
 }
