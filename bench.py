@@ -163,21 +163,21 @@ ROOF_KIND = {
 TRAFFIC = {
     "skel:k_qs_step": {
         "source": ["k_skel.hip", "askit_dev.h"],
-        "src_sha256": "e516578fc87893b8790dbe66748ea9cf4b92ff723156b2388625139d35bea6b1",
+        "src_sha256": "2ee4b4dd202670b7a795b1ebadde224b6563daf510b0b3dd40f37f9e1cadeeac",
         "workload": (1048576, 16, 512, 256, 1024),
         "bytes_per_launch": (2341.1 * 2.0 + 3744.1) * 1024.0,
     },
     "skel:k_qrcp": {
         "source": ["k_skel.hip", "askit_dev.h"],
-        "src_sha256": "e516578fc87893b8790dbe66748ea9cf4b92ff723156b2388625139d35bea6b1",
+        "src_sha256": "2ee4b4dd202670b7a795b1ebadde224b6563daf510b0b3dd40f37f9e1cadeeac",
         "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": (1042189.4 * 2.0 + 1642106.8) * 1024.0,
+        "bytes_per_launch": (1041292.5 * 2.0 + 1642088.7) * 1024.0,
     },
     "factor:k_lu_nopiv": {
         "source": ["k_lu.hip", "askit_dev.h"],
-        "src_sha256": "46de40707c0e508e7f58010e8fc9b2fdaee6a44ac3c34a2ecb09af2bdbc76ab1",
+        "src_sha256": "f6104c39adc9229c98bea4e249a3bc3daf7ab6903b1648d6d8ac8d035d3d29de",
         "workload": (1048576, 16, 512, 256, 1024),
-        "bytes_per_launch": (7567027.6 * 2.0 + 16155348.1) * 1024.0,
+        "bytes_per_launch": (7562807.0 * 2.0 + 16138858.1) * 1024.0,
     },
 }
 
