@@ -115,3 +115,47 @@ def test_batched_mixed_precision(ak):
         assert errr <= 1e-6
     b64.close()
     b32.close()
+
+
+def test_batched_lu_split_graph_replays(ak):
+    """The LU with partial pivoting split over launches inside the batch's
+    captured graph: reduced systems of up to 320 rows (s = 160), a batch
+    with every LU split over launches against one with none; three replays
+    of each graph, with eager work between them, give the same solutions bit
+    for bit, and the two batches agree bit for bit."""
+    import torch
+    probs = synth.batched_problems(count=4, nrhs=3, nmin=2000, nmax=6000)
+    for p in probs:
+        p["m"], p["s"], p["nsamp"] = 128, 160, 320
+        p["lam"] = max(p["lam"], 0.1)
+    say(f"[gpu batch] LU split in the graph, N = {[len(p['X']) for p in probs]}")
+    trees = [ak.Tree(torch.as_tensor(p["X"], device="cuda"), p["m"], p["s"], p["h"], n_samples=p["nsamp"],
+                     seed=p["seed"], problem=p["problem"]) for p in probs]
+    ak.askit_skeletonize_batched(trees)
+    zmax = 0
+    for t in trees:
+        r = t.skeleton_sizes()[0]
+        zmax = max([zmax] + [int(r[2 * i + 1] + r[2 * i + 2]) for i in range((len(r) - 1) // 2)])
+    assert zmax > 256
+    Bs = [torch.as_tensor(p["B"], device="cuda") for p in probs]
+    out = {}
+    for n in (512, 0):
+        for t in trees:
+            t.set_lu_split(n)
+        batch = ak.Batch(trees, [p["lam"] for p in probs], ak.ASKIT_FP64, nrhs=3)
+        runs = []
+        for rep in range(3):
+            batch.factorize()
+            runs.append([x.cpu().numpy() for x in batch.solve(Bs)])
+            torch.cuda.synchronize()
+            assert torch.randn(4096, device="cuda").abs().sum().item() > 0  # eager work between replays
+        for rep in (1, 2):
+            assert all(np.array_equal(a, b) for a, b in zip(runs[0], runs[rep])), (n, rep)
+        assert all(np.all(np.isfinite(x)) for x in runs[0])
+        ratio, _ = batch.check()
+        assert ratio > 1e-12
+        out[n] = runs[0]
+        batch.close()
+    assert all(np.array_equal(a, b) for a, b in zip(out[512], out[0]))
+    for t in trees:
+        t.close()
