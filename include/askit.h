@@ -216,8 +216,9 @@ askit_status askit_tree_set_tiling(askit_tree t, const int32_t *table, int32_t h
  * occupy more than a few compute units.  Smaller batches keep one
  * workgroup per matrix for the whole factorization.  Default 256; n >= 512
  * never splits; n = 0 splits every batch.  The factors are the same bit
- * for bit either way.  Applies to later factorizations of the tree.
- * Errors: ASKIT_ERR_ARG for a NULL tree or n < 0. */
+ * for bit either way.  Applies to later factorizations of the tree; a
+ * batch (askit_batch_create, askit_factorize_batched) takes the smallest n
+ * of its trees.  Errors: ASKIT_ERR_ARG for a NULL tree or n < 0. */
 askit_status askit_tree_set_lu_split(askit_tree t, int32_t n);
 
 /* Hybrid solver (Sec. 2.3, "Fast hybrid solver"; Alg. HybridSolve, MatVecW,
