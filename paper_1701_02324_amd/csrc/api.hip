@@ -614,7 +614,8 @@ askit_status lu_commit(Plan &P, const std::vector<LuTask> &v0, bool spd, int32_t
             for (int i = 0; i < n; i++) {
                 if (v[(size_t)i].n <= kb) break;
                 act++;
-                const int tt = (int)cdiv(v[(size_t)i].n - kb - kLuPanel, 64);
+                const int rest = v[(size_t)i].n - kb - kLuPanel;  // trailing order after this panel
+                const int tt = rest > 0 ? (int)cdiv(rest, 64) : 0;
                 for (int rt = 0; rt < tt; rt++)
                     for (int ct = 0; ct < tt; ct++) pi.push_back(TileItem{i, rt, ct, 0});
             }
